@@ -1,0 +1,144 @@
+"""The Wave-ADR cycle (Algorithm 1) and the problem container.
+
+Test infrastructure only (see the package docstring).
+
+Readings of the paper used here (each also listed in the design notes):
+* levels: l = 1 finest ... L coarsest, n_l = n / 2^(l-1); coarse operators are
+  re-discretised with h_l = 2^(l-1)/n and injected n^2 and damping;
+* smoothers: one damped Jacobi sweep before and after on level 1 (weight w[0]);
+  Chebyshev(5) before and after on levels 2 and 4..L-1 (parameter alpha_l = w[l-1]);
+  Chebyshev(10) on level L and return; level 3 has no smoothing (the text's
+  "no iterations on the third level"; the literal post-smoother of Algorithm 1
+  is available with level3_literal=True);
+* the branch order of Algorithm 1 is kept (l == 1, then l == L, then l == 3);
+* after the level-2 post-smoother, adr_steps ADR corrections (r, demodulate,
+  ADR V-cycle, modulate-add) are applied; only the correction repeats.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .adr import adr_coefficients, adr_step
+from .grid import apply_A, damping_rho, inject, kappa_level, level_size, prolong_bilinear, restrict_fw
+from .smooth import (alpha_median_rule, chebyshev, default_jacobi_weight, jacobi, lambda_gershgorin)
+
+F64 = torch.float64
+C128 = torch.complex128
+
+
+class Problem:
+    """Discrete damped Helmholtz problem and the parameters of the Wave-ADR cycle.
+
+    velocity: (n, n) array c(x) > 0 (n^2 = 1/c^2 on the fine grid).
+    weights:  length-L vector, w[0] = Jacobi weight, w[l-1] = Chebyshev alpha_l.
+    phi:      fine-grid phase (n, n); may be a tensor that requires grad."""
+
+    def __init__(self, velocity, k: float, levels: int, damping_cells: int = 16,
+                 damping_strength: float = 0.5, sigma: int = 1, adr_steps: int = 8,
+                 cheb_pre: int = 5, cheb_post: int = 5, cheb_coarse: int = 10,
+                 gmres_m: int = 3, gmres_coarse_m: int = 10, level3_literal: bool = False,
+                 weights=None, phi=None):
+        vel = torch.as_tensor(np.asarray(velocity, dtype=np.float64))
+        self.n = int(vel.shape[0])
+        if self.n & (self.n - 1) or self.n < 8:
+            raise ValueError("n must be a power of two >= 8")
+        if not 2 <= levels <= int(np.log2(self.n)) - 1:
+            raise ValueError("bad number of levels")
+        self.k = float(k)
+        self.L = int(levels)
+        self.W = int(damping_cells)
+        self.strength = float(damping_strength)
+        self.sigma = int(sigma)
+        self.adr_steps = int(adr_steps)
+        self.cheb_pre, self.cheb_post, self.cheb_coarse = cheb_pre, cheb_post, cheb_coarse
+        self.gmres_m, self.gmres_coarse_m = gmres_m, gmres_coarse_m
+        self.level3_literal = bool(level3_literal)
+        self.n2_fine = 1.0 / (vel * vel)
+        self.h, self.n2, self.rho, self.kappa, self.lam = {}, {}, {}, {}, {}
+        for l in range(1, self.L + 1):
+            nl = level_size(self.n, l)
+            self.h[l] = 1.0 / nl
+            self.n2[l] = inject(self.n2_fine, l)
+            self.rho[l] = damping_rho(self.n, l, self.W)
+            self.kappa[l] = kappa_level(self.n2[l], self.rho[l], self.k, self.strength, self.sigma)
+            self.lam[l] = lambda_gershgorin(self.kappa[l], self.h[l])
+        self.weights = self.default_weights() if weights is None else torch.as_tensor(weights, dtype=F64)
+        self.adr = {}
+        if phi is not None:
+            self.set_phase(phi)
+
+    def default_weights(self) -> torch.Tensor:
+        """w[0] = (4-K)/(5-K) with K = k^2 max(n^2) h_1^2; w[l-1] = alpha_l by the
+        median rule (lower end of the Chebyshev interval at the median of the
+        constant-coefficient spectrum of A^*A with the level's mean n^2)."""
+        w = np.zeros(self.L)
+        w[0] = default_jacobi_weight(self.k, float(self.n2[1][1:, 1:].max()), self.h[1])
+        for l in range(2, self.L + 1):
+            nl = level_size(self.n, l)
+            w[l - 1] = alpha_median_rule(self.k, float(self.n2[l][1:, 1:].mean()), nl, self.lam[l])
+        return torch.as_tensor(w, dtype=F64)
+
+    def set_weights(self, w):
+        self.weights = w if isinstance(w, torch.Tensor) else torch.as_tensor(np.asarray(w, dtype=np.float64))
+
+    def set_phase(self, phi):
+        """Inject phi to the ADR levels 2..L, build their coefficients, and the
+        level-2 carrier e^{+- i sigma k phi_2}."""
+        phi = phi if isinstance(phi, torch.Tensor) else torch.as_tensor(np.asarray(phi))
+        phi = phi.to(F64)
+        self.adr = {}
+        for l in range(2, self.L + 1):
+            self.adr[l] = adr_coefficients(inject(phi, l), self.n2[l], self.rho[l], self.k,
+                                           self.strength, self.sigma, self.h[l])
+        phi2 = inject(phi, 2)
+        arg = (self.sigma * self.k) * phi2
+        self.carrier = torch.complex(torch.cos(arg), torch.sin(arg))
+        self.carrier_conj = torch.complex(torch.cos(arg), -torch.sin(arg))
+
+    # convenience
+    def A(self, u, level: int = 1):
+        return apply_A(u, self.kappa[level], self.h[level])
+
+    def zeros(self, level: int = 1):
+        nl = level_size(self.n, level)
+        return torch.zeros((nl, nl), dtype=C128)
+
+
+def wave_adr_cycle(P: Problem, level: int, g: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """One Wave-ADR cycle on level ``level`` (Algorithm 1)."""
+    kap, h, w = P.kappa[level], P.h[level], P.weights
+    L = P.L
+    # pre-smoothing
+    if level == 1:
+        u = jacobi(u, g, kap, h, w[0])
+    elif level == L:
+        return chebyshev(u, g, kap, h, w[L - 1], P.cheb_coarse, P.lam[L])
+    elif level == 3:
+        pass
+    else:
+        u = chebyshev(u, g, kap, h, w[level - 1], P.cheb_pre, P.lam[level])
+    # coarse-grid correction with zero initial guess
+    rc = restrict_fw(g - apply_A(u, kap, h))
+    ec = wave_adr_cycle(P, level + 1, rc, torch.zeros_like(rc))
+    u = u + prolong_bilinear(ec)
+    # post-smoothing
+    if level == 1:
+        u = jacobi(u, g, kap, h, w[0])
+    elif level == 2:
+        u = chebyshev(u, g, kap, h, w[1], P.cheb_post, P.lam[2])
+        if P.adr_steps > 0 and L >= 3:
+            if not P.adr:
+                raise RuntimeError("phase not set")
+            for _ in range(P.adr_steps):
+                u = adr_step(P, g, u)
+    elif level == 3 and not P.level3_literal:
+        pass
+    else:
+        u = chebyshev(u, g, kap, h, w[level - 1], P.cheb_post, P.lam[level])
+    return u
+
+
+def cycle(P: Problem, g: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """C(u, g): one cycle from the fine-grid iterate u."""
+    return wave_adr_cycle(P, 1, g, u)
