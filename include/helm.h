@@ -1,0 +1,164 @@
+/*
+ * helm.h -- C ABI of the MI355X (gfx950) Wave-ADR Helmholtz library (libhelm.so).
+ *
+ * Problem (paper Section 2, the damped equation and its 5-point discretisation):
+ *     A u = -Delta_h u - kappa u = g,  kappa = k^2 n(x)^2 (1 + i sigma delta(x)),
+ * on the unit square with zero Dirichlet values on the outer ring, where
+ * n = 1/c is the slowness, k the angular frequency (the paper's omega) and
+ * delta = damping_strength * rho^2 the sponge profile (rho ramps linearly from 0
+ * to 1 over damping_cells fine cells towards the boundary, max over the axes).
+ * sigma = +1 uses the carrier e^{+i k phi}; sigma = -1 is the paper's printed
+ * sign convention (the complex conjugate of every operator).
+ *
+ * Grid layout (every array argument): n x n nodes, n = 2^m, h = 1/n, row-major,
+ * element (i, j) at offset i*n + j, i = y index, j = x index (x fastest).
+ * Row 0 and column 0 are the Dirichlet ring and must be zero in g and u on
+ * entry; the library keeps them zero.  Complex arrays are interleaved
+ * (re, im) pairs of float (HELM_C64) or double (HELM_C128), i.e. the memory
+ * layout of torch.complex64 / torch.complex128.
+ *
+ * Ownership: every array argument is caller-owned device memory unless marked
+ * "host".  The context owns all workspaces; they are allocated by helm_setup
+ * and freed by helm_destroy.  helm_cycle and helm_solve allocate nothing.
+ *
+ * Streams: every call is asynchronous on the given stream (a hipStream_t passed
+ * as void*, NULL = default stream), except helm_setup, helm_set_phase (which
+ * synchronise once), and helm_solve (which reads one convergence scalar per
+ * iteration back to the host).  A context may be used by one thread at a time.
+ *
+ * Errors: every call returns a helm_status and never aborts; no C++ exception
+ * crosses the ABI.  Invalid arguments give HELM_EINVAL and leave outputs
+ * untouched; helm_last_error() returns a thread-local description of the last
+ * failure.
+ */
+#ifndef HELM_H_
+#define HELM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct helm_ctx_s* helm_ctx;
+
+typedef enum {
+    HELM_OK = 0,
+    HELM_EINVAL = 1,      /* invalid argument; nothing was done */
+    HELM_ENOMEM = 2,      /* device allocation failed */
+    HELM_EHIP = 3,        /* a HIP runtime call failed */
+    HELM_ENOCONV = 4,     /* solve: tolerance not reached within maxit */
+    HELM_EBREAKDOWN = 5,  /* solve: NaN/Inf or residual growth above 1e4 x initial */
+    HELM_ESTATE = 6       /* call out of order (e.g. cycle before helm_set_phase) */
+} helm_status;
+
+typedef enum { HELM_C64 = 0, HELM_C128 = 1 } helm_prec;
+
+/* Problem and cycle parameters.  Fill with helm_desc_default, then adjust. */
+typedef struct {
+    int32_t n;                /* nodes per side, power of two, 16..8192 */
+    int32_t levels;           /* L, 2..log2(n)-1; the ADR correction needs L >= 3 */
+    double k;                 /* angular frequency, > 0 */
+    int32_t damping_cells;    /* sponge width W in fine cells, >= 1 (default 16) */
+    double damping_strength;  /* delta = strength * rho^2 (default 0.5) */
+    int32_t sign;             /* sigma: +1 (default) or -1 */
+    int32_t cycle_prec;       /* helm_prec of the cycle (the coarsest wave level is always FP64) */
+    int32_t adr_steps;        /* ADR corrections after the level-2 post-smoother (default 8, 0 = off) */
+    int32_t cheb_pre;         /* Chebyshev steps before the coarse correction (default 5) */
+    int32_t cheb_post;        /* Chebyshev steps after it (default 5) */
+    int32_t cheb_coarse;      /* Chebyshev steps on level L (default 10) */
+    int32_t gmres_m;          /* GMRES(m) smoother on ADR levels (default 3) */
+    int32_t gmres_coarse_m;   /* GMRES(m) on the coarsest ADR level (default 10) */
+    int32_t level3_literal;   /* 0: no smoothing on level 3 (default); 1: Chebyshev post-smoother there */
+    int32_t restart;          /* FGMRES restart length (default 20, at most 24) */
+} helm_desc;
+
+/* Defaults of every field for an n x n grid at frequency k:
+ * levels = min(7, log2 n - 3) (at least 2), W = 16, strength 0.5, sign +1, C128,
+ * M = 8, Chebyshev 5/5/10, GMRES 3/10, restart 20. */
+void helm_desc_default(helm_desc* d, int32_t n, double k);
+
+/* Setup phase (paper Figure "cycle": the solver's setup/solve split).
+ * velocity: device, n*n doubles, c(x) > 0 (n^2 = 1/c^2 on the fine grid, injected
+ * to coarse levels).  Computes per-level spectral bounds and the default
+ * weights (helm_get_weights).  On success *out owns every workspace. */
+helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* out, void* stream);
+
+/* Phase field of the ADR correction (the paper's tau, Section 3.2; eq. Rytov).
+ * phi: device, n*n, double (phi_is_f64 = 1) or float (0), fine grid.  Builds the
+ * ADR coefficients (phase derivatives, reaction term) on levels 2..L and the
+ * level-2 carrier.  Required before helm_cycle when adr_steps > 0. */
+helm_status helm_set_phase(helm_ctx ctx, const void* phi, int32_t phi_is_f64, void* stream);
+
+/* Per-level smoother weights (host, `levels` doubles): w[0] = damped-Jacobi weight
+ * of level 1 (Section 3.1.1), w[l-1] = Chebyshev interval parameter alpha_l of
+ * level l >= 2 (eq. cheb; interval [lambda_l/alpha_l, lambda_l]).  alpha_l >= 1. */
+helm_status helm_set_weights(helm_ctx ctx, const double* w);
+helm_status helm_get_weights(helm_ctx ctx, double* w);
+/* Spectral bound lambda_l of A_l^* A_l used by Chebyshev (host out, `levels` doubles). */
+helm_status helm_get_lambdas(helm_ctx ctx, double* lam);
+
+/* One Wave-ADR cycle (paper Algorithm 1) on the fine grid: u <- C(u, g).
+ * g, u: device, n*n complex in cycle_prec; u is read and overwritten. */
+helm_status helm_cycle(helm_ctx ctx, const void* g, void* u, void* stream);
+
+/* Outer solve to ||g - A u|| / ||g|| < tol (paper Section 4.3.1).
+ * g, u: device, n*n complex128; u holds the initial guess and receives the result.
+ * mode 0: FGMRES(restart) in FP64 right-preconditioned by one cycle (cycles in
+ *         cycle_prec; cast around the cycle when cycle_prec = HELM_C64).
+ * mode 1: FP64 iterative refinement around an FP32 FGMRES(restart) with FP32
+ *         cycles (requires cycle_prec = HELM_C64): r = g - A u and u += d in FP64.
+ * iters (host out): preconditioner applications; relres (host out): true FP64
+ * relative residual at exit; history (host out, may be NULL): maxit+1 doubles,
+ * the residual estimate after each iteration.  Returns HELM_ENOCONV if tol was
+ * not reached within maxit (iters and relres still filled). */
+helm_status helm_solve(helm_ctx ctx, const void* g, void* u, double tol, int32_t maxit, int32_t mode,
+                       int32_t* iters, double* relres, double* history, void* stream);
+
+/* FP64 residual on the fine grid: r = g - A u (device, complex128, r may be NULL)
+ * and its 2-norm plus ||g|| (host out, may be NULL).  Synchronises the stream. */
+helm_status helm_residual(helm_ctx ctx, const void* g, const void* u, void* r, double* rnorm,
+                          double* gnorm, void* stream);
+
+/* Adjoint of K unrolled cycles (paper Section 3.3: the training loss after K cycles
+ * and its back-propagation).  Given u_0 (device, cycle_prec, NULL = zero) and the
+ * gradient of a real loss with respect to u_K in torch's convention for complex
+ * tensors (grad_uK = 2 dL/d conj(u_K)), accumulates dL/dphi (device, n*n float for
+ * cycle_prec C64, double for C128, overwritten) and dL/dw (device, `levels`
+ * doubles, overwritten).  ckpt_ws: device workspace of K*n*n complex elements in
+ * cycle_prec for the per-cycle checkpoints, or NULL for a library-owned buffer
+ * (allocated on first use). */
+helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const void* u0,
+                                const void* grad_uK, void* grad_phi, double* grad_w, void* ckpt_ws,
+                                void* stream);
+
+/* Internal operators, exposed for step-by-step parity tests.  op codes:
+ *   1  out = A_l in              (level l, cycle_prec complex)
+ *   2  out = R in                (in on level l, out on level l+1)
+ *   3  out += P in               (in on level l+1, out on level l)
+ *   4  out = Jacobi(in; g=in2)   (level 1)
+ *   5  out = Chebyshev(in; g=in2, pre-step count)  (level l >= 2)
+ *   6  out = M_l in              (ADR operator, level l >= 2)
+ *   7  out = GMRES(M_l; b=in2, x0=in, m=gmres_m)   (level l >= 2)
+ *   8  out = ADR V-cycle(b=in2, x0=0) (level l >= 2)
+ *   9  out = ADR step(u=in, g=in2) (level 2)
+ *  10  out = wave-ADR cycle on level l from (u=in, g=in2)
+ *  11  out = R(in2 - A_l in)     (fused residual + restriction)
+ * Arrays are device memory in cycle_prec (level L arrays are complex128). */
+helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* in, const void* in2,
+                          void* out, void* stream);
+
+/* Frees every workspace; NULL-safe; the context must not be used afterwards. */
+helm_status helm_destroy(helm_ctx ctx);
+
+const char* helm_status_string(helm_status s);
+const char* helm_last_error(void);
+
+/* Library version string. */
+const char* helm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H_ */

@@ -1,0 +1,121 @@
+// Shared device/host definitions of the Wave-ADR HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace helm {
+
+// Interleaved complex number with the memory layout of torch.complex64/128.
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T a, T b) {
+    return cplx<T>{a, b};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) {
+    return {a.re - b.re, a.im - b.im};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) {
+    return {s * a.re, s * a.im};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> conjg(cplx<T> a) {
+    return {a.re, -a.im};
+}
+// a / b
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cdiv(cplx<T> a, cplx<T> b) {
+    T d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+__device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename To, typename Ti>
+__host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) {
+    return {static_cast<To>(a.re), static_cast<To>(a.im)};
+}
+
+using c64 = cplx<float>;
+using c128 = cplx<double>;
+
+// Geometry and coefficients of one level of the hierarchy.
+//   n      nodes per side on this level (h = 1/n)
+//   s      stride of the level in fine-grid indices, 2^(l-1)
+//   nf     fine-grid nodes per side
+//   W      sponge width in fine cells
+// kappa(i, j) = k2 * n2(i, j) * (1 + i * sig_str * rho^2), rho from the indices.
+struct Geom {
+    int n;
+    int s;
+    int nf;
+    int W;
+    double inv_h2;
+    double k2;
+    double sig_str;
+};
+
+template <typename T>
+__device__ __forceinline__ T sponge_ramp(int t, int nf, int W) {
+    int d = t < nf - t ? t : nf - t;
+    T r = T(1) - T(d) / T(W);
+    return r > T(0) ? r : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> kappa_at(const Geom& G, T n2, int i, int j) {
+    T ri = sponge_ramp<T>(i * G.s, G.nf, G.W);
+    T rj = sponge_ramp<T>(j * G.s, G.nf, G.W);
+    T rho = ri > rj ? ri : rj;
+    T kr = T(G.k2) * n2;
+    return {kr, kr * (T(G.sig_str) * (rho * rho))};
+}
+
+// Load with the implicit zero ring at index n (i, j >= 0 always holds for callers).
+template <typename V>
+__device__ __forceinline__ V ldz(const V* __restrict__ a, int i, int j, int n) {
+    if (i >= n || j >= n) return V{};
+    return a[(size_t)i * n + j];
+}
+
+// Maximum Krylov dimension supported by the device-side least squares.
+constexpr int MAXM = 24;
+
+// Device-resident state of one GMRES/FGMRES instance (all FP64).
+struct KrylovScal {
+    double beta;                          // ||r0||
+    double scale[MAXM + 1];               // v_i = scale[i] * V_i
+    double H[2 * (MAXM + 1) * MAXM];      // complex Hessenberg, H(i,j) at 2*(i + j*(MAXM+1))
+    double dots[2 * (MAXM + 2)];          // results of the last reduction pass
+    double y[2 * MAXM];                   // least-squares solution
+    double R[2 * (MAXM + 1) * MAXM];      // working copy for the Givens QR
+    double e[2 * (MAXM + 1)];             // rotated right-hand side
+    int cols;                             // Arnoldi columns completed
+    int done;                             // 1: no further Arnoldi work (solved, breakdown, zero rhs)
+    int m;                                // requested Krylov dimension
+    int pad;
+};
+
+// Reduction tickets (one per kernel family use; reset by the last block).
+struct Tickets {
+    unsigned int t[4];
+};
+
+}  // namespace helm

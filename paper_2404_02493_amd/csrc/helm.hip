@@ -1,0 +1,1072 @@
+// Host side of the Wave-ADR library: context and hierarchy setup, the cycle
+// recursion (Algorithm 1), the ADR V-cycle with device-resident GMRES, the
+// outer FGMRES / iterative refinement, and the C ABI of include/helm.h.
+//
+// The host only enqueues kernels; every grid operation runs in the kernels of
+// kernels_*.hpp.  Scalars that steer the Krylov methods stay on the device,
+// except that the outer solver reads one Hessenberg column per iteration.
+#include <algorithm>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/helm.h"
+#include "kernels_krylov.hpp"
+
+namespace helm {
+
+static thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+    helm_status code;
+    Error(helm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                                      \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess)                                                                             \
+            throw Error(HELM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_) + " (line " +        \
+                                       std::to_string(__LINE__) + ")");                                   \
+    } while (0)
+
+#define REQUIRE(cond, msg)                                   \
+    do {                                                     \
+        if (!(cond)) throw Error(HELM_EINVAL, (msg));        \
+    } while (0)
+
+struct WaveLevel {
+    int n = 0;
+    Geom G{};
+    bool f64 = false;      // this level computes in FP64
+    void* n2 = nullptr;    // real, cycle precision (FP64 on f64 levels)
+    void* g = nullptr;     // right-hand side (levels >= 2)
+    void* u = nullptr;     // iterate (levels >= 2)
+    void* t = nullptr;     // Chebyshev scratch
+    void* r = nullptr;
+    void* d = nullptr;
+    double lam = 0.0;      // spectral bound of A^*A
+    double n2max = 0.0, n2mean = 0.0;
+};
+
+struct AdrLevel {
+    int n = 0;
+    AdrGeom A{};
+    void* px = nullptr;
+    void* py = nullptr;
+    void* c0 = nullptr;
+    void* b = nullptr;
+    void* x = nullptr;
+    void* V[MAXM + 1] = {};
+    KrylovScal* K = nullptr;
+};
+
+}  // namespace helm
+
+struct helm_ctx_s {
+    helm_desc d{};
+    int L = 0;
+    bool f32 = false;  // cycle precision is complex64
+    std::vector<void*> allocs;
+    double* n2f = nullptr;  // fine n^2 (FP64)
+    std::vector<helm::WaveLevel> wl;
+    std::vector<helm::AdrLevel> al;
+    void* theta2 = nullptr;  // reduced carrier phase on level 2 (cycle precision)
+    bool phase_set = false;
+    std::vector<double> w, w_default;
+    void* ws1 = nullptr;     // second level-1 iterate (cycle precision)
+    double* partials = nullptr;
+    unsigned int* ticket = nullptr;
+    double* dscal = nullptr;  // small device scratch (norms)
+    helm::KrylovScal* Kout = nullptr;
+    helm::KrylovScal* Kin = nullptr;
+    // outer FGMRES (complex128) and inner (cycle precision, iterative refinement)
+    void* fV[helm::MAXM + 1] = {};
+    void* fZ[helm::MAXM] = {};
+    void* iV[helm::MAXM + 1] = {};
+    void* iZ[helm::MAXM] = {};
+    void* cyc_g = nullptr;   // cycle-precision staging (mode 0 with complex64 cycles)
+    void* cyc_u = nullptr;
+    void* rbuf = nullptr;    // FP64 residual (mode 1)
+    void* dbuf = nullptr;    // inner correction (mode 1)
+    void* ckpt = nullptr;
+    size_t ckpt_bytes = 0;
+};
+
+namespace helm {
+
+static void* dalloc(helm_ctx c, size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(HELM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    c->allocs.push_back(p);
+    return p;
+}
+
+static inline dim3 tile_block() { return dim3(TX, TWY, 1); }
+static inline int flat_blocks(size_t N, int cap = 2048) {
+    size_t b = (N + BLOCK - 1) / BLOCK;
+    return (int)std::max<size_t>(1, std::min<size_t>(b, (size_t)cap));
+}
+
+static Geom make_geom(const helm_ctx c, int level) {
+    Geom G{};
+    G.n = c->d.n >> (level - 1);
+    G.s = 1 << (level - 1);
+    G.nf = c->d.n;
+    G.W = c->d.damping_cells;
+    G.inv_h2 = double(G.n) * double(G.n);
+    G.k2 = c->d.k * c->d.k;
+    G.sig_str = double(c->d.sign) * c->d.damping_strength;
+    return G;
+}
+
+static AdrGeom make_adr_geom(const helm_ctx c, int level) {
+    AdrGeom A{};
+    A.n = c->d.n >> (level - 1);
+    A.inv_h2 = double(A.n) * double(A.n);
+    A.inv_2h = 0.5 * double(A.n);
+    A.two_sk = 2.0 * double(c->d.sign) * c->d.k;
+    return A;
+}
+
+static size_t csize(bool f64) { return f64 ? sizeof(c128) : sizeof(c64); }
+static size_t rsize(bool f64) { return f64 ? sizeof(double) : sizeof(float); }
+
+static int nv_bucket(int m) { return m <= 4 ? 4 : (m <= 12 ? 12 : MAXM); }
+
+// ------------------------------------------------------------------ default weights
+static double median_alpha(double k, double n2mean, int nl, double lam) {
+    const double h = 1.0 / nl;
+    std::vector<double> s(nl - 1);
+    for (int a = 1; a < nl; ++a) {
+        double v = std::sin(a * M_PI * h / 2.0);
+        s[a - 1] = v * v;
+    }
+    std::vector<double> vals((size_t)(nl - 1) * (nl - 1));
+    const double c4 = 4.0 / (h * h), kk = k * k * n2mean;
+    size_t q = 0;
+    for (int a = 0; a < nl - 1; ++a)
+        for (int b = 0; b < nl - 1; ++b) {
+            double sig = c4 * (s[a] + s[b]) - kk;
+            vals[q++] = sig * sig;
+        }
+    size_t mid = (vals.size() - 1) / 2;
+    std::nth_element(vals.begin(), vals.begin() + mid, vals.end());
+    double med = vals[mid];
+    if (vals.size() % 2 == 0) {
+        double hi = *std::min_element(vals.begin() + mid + 1, vals.end());
+        med = 0.5 * (med + hi);
+    }
+    return std::max(1.0, lam / med);
+}
+
+// ------------------------------------------------------------------ engine
+template <typename T>
+struct Engine {
+    helm_ctx c;
+    hipStream_t st;
+    using C = cplx<T>;
+
+    Engine(helm_ctx ctx, hipStream_t s) : c(ctx), st(s) {}
+
+    size_t N(int level) const {
+        size_t n = (size_t)(c->d.n >> (level - 1));
+        return n * n;
+    }
+
+    // ---- generic launches on a level of precision P
+    template <typename P>
+    void residual(const Geom& G, const void* n2, const void* g, const void* u, void* r) {
+        hipLaunchKernelGGL((k_residual<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const P*)n2,
+                           (const cplx<P>*)g, (const cplx<P>*)u, (cplx<P>*)r);
+    }
+    template <typename P>
+    void applyA(const Geom& G, const void* n2, const void* x, void* y, int conj_k) {
+        hipLaunchKernelGGL((k_apply_A<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const P*)n2,
+                           (const cplx<P>*)x, (cplx<P>*)y, conj_k);
+    }
+    template <typename P>
+    void zero(void* y, size_t n) {
+        hipLaunchKernelGGL((k_zero<P>), dim3(flat_blocks(n)), dim3(BLOCK), 0, st, n, (cplx<P>*)y);
+    }
+
+    template <typename P>
+    void chebyshev(int l, const void* g, void* u, bool u_zero, double alpha, int m) {
+        WaveLevel& W = c->wl[l];
+        const Geom& G = W.G;
+        const double lam = W.lam;
+        const double a = lam / alpha;
+        const double theta = 0.5 * (lam + a);
+        const double dc = 0.5 * (lam - a);
+        const size_t n = N(l);
+        if (u_zero) zero<P>(u, n);
+        const void* t0 = g;
+        if (!u_zero) {
+            residual<P>(G, W.n2, g, u, W.t);
+            t0 = W.t;
+        }
+        hipLaunchKernelGGL((k_cheb_start<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const P*)W.n2,
+                           (const cplx<P>*)t0, (cplx<P>*)W.r, (cplx<P>*)W.d, P(1.0 / theta));
+        double rho = dc / theta;
+        for (int step = 1; step <= m; ++step) {
+            if (step < m) {
+                applyA<P>(G, W.n2, W.d, W.t, 0);
+                const double den = 2.0 * theta - dc * rho;
+                const double rho_new = dc / den;
+                const double c1 = rho_new * rho, c2 = 2.0 / den;
+                hipLaunchKernelGGL((k_cheb_step<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G,
+                                   (const P*)W.n2, (const cplx<P>*)W.t, (cplx<P>*)W.r, (cplx<P>*)W.d,
+                                   (cplx<P>*)u, P(c1), P(c2));
+                rho = rho_new;
+            } else {
+                hipLaunchKernelGGL((k_axpy<P>), dim3(flat_blocks(n)), dim3(BLOCK), 0, st, n, P(1),
+                                   (const cplx<P>*)W.d, (cplx<P>*)u);
+            }
+        }
+    }
+
+    // rc = R (g - A u) from level l (precision Pf) to level l+1 (precision Pc)
+    template <typename Pf, typename Pc>
+    void resid_restrict(int l, const void* g, const void* u, void* rc) {
+        const Geom& G = c->wl[l].G;
+        hipLaunchKernelGGL((k_resid_restrict<Pf, Pc>), dim3(tiles_of(G.n / 2)), tile_block(), 0, st, G,
+                           (const Pf*)c->wl[l].n2, (const cplx<Pf>*)g, (const cplx<Pf>*)u, (cplx<Pc>*)rc);
+    }
+    template <typename Pc, typename Pf>
+    void prolong_add(int l, const void* ec, void* u) {
+        const int n = c->wl[l].n;
+        hipLaunchKernelGGL((k_prolong_add<Pc, Pf>), dim3(tiles_of(n)), tile_block(), 0, st, n,
+                           (const cplx<Pc>*)ec, (cplx<Pf>*)u);
+    }
+
+    void restrict_down(int l, const void* g, const void* u, void* rc) {
+        if (c->wl[l + 1].f64)
+            resid_restrict<T, double>(l, g, u, rc);
+        else
+            resid_restrict<T, T>(l, g, u, rc);
+    }
+    void prolong_up(int l, const void* ec, void* u) {
+        if (c->wl[l + 1].f64)
+            prolong_add<double, T>(l, ec, u);
+        else
+            prolong_add<T, T>(l, ec, u);
+    }
+
+    // ---- the coarsest wave level (always FP64)
+    void coarsest(int l) {
+        WaveLevel& W = c->wl[l];
+        chebyshev<double>(l, W.g, W.u, true, c->w[l - 1], c->d.cheb_coarse);
+    }
+
+    // ---- one cycle on level l >= 2 with zero initial iterate: u_l from g_l
+    void cycle_coarse(int l) {
+        WaveLevel& W = c->wl[l];
+        const int L = c->L;
+        if (l == L) {
+            coarsest(l);
+            return;
+        }
+        bool u_zero = true;
+        if (l == 3) {
+            // no pre-smoothing on level 3
+        } else {
+            chebyshev<T>(l, W.g, W.u, true, c->w[l - 1], c->d.cheb_pre);
+            u_zero = false;
+        }
+        restrict_down(l, W.g, u_zero ? nullptr : W.u, c->wl[l + 1].g);
+        cycle_coarse(l + 1);
+        if (u_zero) zero<T>(W.u, N(l));
+        prolong_up(l, c->wl[l + 1].u, W.u);
+        if (l == 2) {
+            chebyshev<T>(l, W.g, W.u, false, c->w[1], c->d.cheb_post);
+            if (c->d.adr_steps > 0 && L >= 3)
+                for (int s = 0; s < c->d.adr_steps; ++s) adr_step();
+        } else if (l == 3 && !c->d.level3_literal) {
+            // no post-smoothing on level 3
+        } else {
+            chebyshev<T>(l, W.g, W.u, false, c->w[l - 1], c->d.cheb_post);
+        }
+    }
+
+    // ---- fine-grid cycle: u_out = C(u_in, g); u_in may be null (zero)
+    void cycle(const void* g, const void* u_in, void* u_out) {
+        WaveLevel& W = c->wl[1];
+        const Geom& G = W.G;
+        const T w0 = T(c->w[0]);
+        hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const T*)W.n2,
+                           (const C*)g, (const C*)u_in, (C*)c->ws1, w0);
+        restrict_down(1, g, c->ws1, c->wl[2].g);
+        cycle_coarse(2);
+        prolong_up(1, c->wl[2].u, c->ws1);
+        hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const T*)W.n2,
+                           (const C*)g, (const C*)c->ws1, (C*)u_out, w0);
+    }
+
+    // ---- ADR correction on level 2
+    void adr_step() {
+        WaveLevel& W = c->wl[2];
+        AdrLevel& A = c->al[2];
+        hipLaunchKernelGGL((k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), 0, st, W.G, (const T*)W.n2,
+                           (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
+        adr_vcycle(2);
+        hipLaunchKernelGGL((k_adr_modadd<T>), dim3(flat_blocks(N(2))), dim3(BLOCK), 0, st, N(2), (const C*)A.x,
+                           (const T*)c->theta2, (C*)W.u);
+    }
+
+    void adr_vcycle(int l) {
+        AdrLevel& A = c->al[l];
+        if (l == c->L) {
+            gmres(l, c->d.gmres_coarse_m, true);
+            return;
+        }
+        gmres(l, c->d.gmres_m, true);
+        hipLaunchKernelGGL((k_adr_resid_restrict<T>), dim3(tiles_of(A.n / 2)), tile_block(), 0, st, A.A,
+                           (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
+                           (C*)c->al[l + 1].b);
+        adr_vcycle(l + 1);
+        hipLaunchKernelGGL((k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.n,
+                           (const C*)c->al[l + 1].x, (C*)A.x);
+        gmres(l, c->d.gmres_m, false);
+    }
+
+    template <int NV>
+    void gmres_nv(int l, int m, bool x0_zero) {
+        AdrLevel& A = c->al[l];
+        const size_t n = N(l);
+        VecSet<T> V{};
+        V.v[0] = (const C*)(x0_zero ? A.b : A.V[0]);
+        for (int i = 1; i <= m; ++i) V.v[i] = (const C*)A.V[i];
+        if (x0_zero) {
+            hipLaunchKernelGGL((k_krylov_init_norm<T>), dim3(flat_blocks(n, 1024)), dim3(BLOCK), 0, st, n,
+                               (const C*)A.b, A.K, m, c->partials, c->ticket);
+        } else {
+            hipLaunchKernelGGL((k_adr_residual_init<T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
+                               (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
+                               (C*)A.V[0], A.K, m, c->partials, c->ticket);
+        }
+        for (int j = 0; j < m; ++j) {
+            hipLaunchKernelGGL((k_arnoldi_adr<T, NV>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
+                               (const T*)A.px, (const T*)A.py, (const C*)A.c0, V, j, (C*)A.V[j + 1], A.K,
+                               c->partials, c->ticket);
+            hipLaunchKernelGGL((k_orth_pass1<T, NV>), dim3(flat_blocks(n, 1024)), dim3(BLOCK), 0, st, n, V, j,
+                               (C*)A.V[j + 1], A.K, c->partials, c->ticket);
+            hipLaunchKernelGGL((k_orth_pass2<T, NV>), dim3(flat_blocks(n, 1024)), dim3(BLOCK), 0, st, n, V, j,
+                               (C*)A.V[j + 1], A.K, 1e-14, c->partials, c->ticket);
+        }
+        hipLaunchKernelGGL((k_krylov_combine<T, NV>), dim3(flat_blocks(n)), dim3(BLOCK), 0, st, n, V,
+                           (const KrylovScal*)A.K, (const C*)(x0_zero ? nullptr : A.x), (C*)A.x);
+    }
+    void gmres(int l, int m, bool x0_zero) {
+        switch (nv_bucket(m)) {
+            case 4: gmres_nv<4>(l, m, x0_zero); break;
+            case 12: gmres_nv<12>(l, m, x0_zero); break;
+            default: gmres_nv<MAXM>(l, m, x0_zero); break;
+        }
+    }
+};
+
+// ------------------------------------------------------------------ outer Krylov (host-driven Givens)
+using cd = std::complex<double>;
+
+static void givens(cd a, cd b, double& c, cd& s) {
+    if (b == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        return;
+    }
+    if (a == 0.0) {
+        c = 0.0;
+        s = 1.0;
+        return;
+    }
+    double rho = std::hypot(std::abs(a), std::abs(b));
+    c = std::abs(a) / rho;
+    s = (a / std::abs(a)) * std::conj(b) / rho;
+}
+
+// One restart cycle of FGMRES on the fine grid with vectors of precision P and a
+// preconditioner that maps V_j to Z_j.  Returns iterations done; updates x (precision P)
+// in place with x += Z y.  est_out: final residual estimate / gnorm.
+template <typename P, typename Prec>
+static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** V, void** Z, KrylovScal* K,
+                        bool z_scaled, void* x, double gnorm, double stop_abs, int maxit_left, Prec&& prec,
+                        std::vector<double>* history, double* est_out, bool* breakdown) {
+    using Cp = cplx<P>;
+    const int m = c->d.restart;
+    const Geom G = make_geom(c, 1);
+    const size_t N = (size_t)G.n * G.n;
+    // K init from V[0]
+    hipLaunchKernelGGL((k_krylov_init_norm<P>), dim3(flat_blocks(N, 1024)), dim3(BLOCK), 0, st, N, (const Cp*)V[0],
+                       K, m, c->partials, c->ticket);
+    KrylovScal hk;
+    HIPCHK(hipMemcpyAsync(&hk.beta, &K->beta, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double beta = hk.beta;
+    *breakdown = false;
+    if (!(beta > 0.0) || !std::isfinite(beta)) {
+        *est_out = beta / gnorm;
+        *breakdown = !std::isfinite(beta);
+        return 0;
+    }
+    VecSet<P> Vs{}, Zs{};
+    for (int i = 0; i <= m; ++i) Vs.v[i] = (const Cp*)V[i];
+    for (int i = 0; i < m; ++i) Zs.v[i] = (const Cp*)Z[i];
+    std::vector<std::vector<cd>> H(m + 1, std::vector<cd>(m, 0.0));
+    std::vector<double> cs(m);
+    std::vector<cd> sn(m), e(m + 1, 0.0);
+    e[0] = beta;
+    std::vector<double> scale(m + 1, 0.0);
+    scale[0] = 1.0 / beta;
+    int used = 0;
+    double est = beta / gnorm;
+    std::vector<double> col(2 * (MAXM + 1));
+    for (int j = 0; j < m && used < maxit_left; ++j) {
+        prec(j, scale[j]);  // Z[j] = preconditioned V[j] (scaled by scale[j] if !z_scaled)
+        hipLaunchKernelGGL((k_arnoldi_helm<P, MAXM>), dim3(tiles_of(G.n)), tile_block(), 0, st, G,
+                           (const P*)n2_fine, (const Cp*)Z[j], z_scaled ? 0 : 1, Vs, j, (Cp*)V[j + 1], K,
+                           c->partials, c->ticket);
+        hipLaunchKernelGGL((k_orth_pass1<P, MAXM>), dim3(flat_blocks(N, 1024)), dim3(BLOCK), 0, st, N, Vs, j,
+                           (Cp*)V[j + 1], K, c->partials, c->ticket);
+        hipLaunchKernelGGL((k_orth_pass2<P, MAXM>), dim3(flat_blocks(N, 1024)), dim3(BLOCK), 0, st, N, Vs, j,
+                           (Cp*)V[j + 1], K, 0.0, c->partials, c->ticket);
+        HIPCHK(hipMemcpyAsync(col.data(), K->H + 2 * (j * (MAXM + 1)), sizeof(double) * 2 * (j + 2),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i <= j + 1; ++i) H[i][j] = cd(col[2 * i], col[2 * i + 1]);
+        const double hn = col[2 * (j + 1)];
+        for (int i = 0; i < j; ++i) {
+            cd t1 = cs[i] * H[i][j] + sn[i] * H[i + 1][j];
+            cd t2 = -std::conj(sn[i]) * H[i][j] + cs[i] * H[i + 1][j];
+            H[i][j] = t1;
+            H[i + 1][j] = t2;
+        }
+        givens(H[j][j], H[j + 1][j], cs[j], sn[j]);
+        H[j][j] = cs[j] * H[j][j] + sn[j] * H[j + 1][j];
+        H[j + 1][j] = 0.0;
+        e[j + 1] = -std::conj(sn[j]) * e[j];
+        e[j] = cs[j] * e[j];
+        used = j + 1;
+        est = std::abs(e[j + 1]) / gnorm;
+        if (history) history->push_back(est);
+        if (!std::isfinite(hn) || !std::isfinite(est)) {
+            *breakdown = true;
+            break;
+        }
+        if (std::abs(e[j + 1]) < stop_abs || hn == 0.0) break;
+        scale[j + 1] = 1.0 / hn;
+    }
+    // y by back substitution; x += sum y_i zs_i Z_i
+    std::vector<cd> y(used);
+    for (int i = used - 1; i >= 0; --i) {
+        cd acc = e[i];
+        for (int q = i + 1; q < used; ++q) acc -= H[i][q] * y[q];
+        y[i] = acc / H[i][i];
+    }
+    // write y and cols, and the Z scales, into the device state
+    std::vector<double> ybuf(2 * MAXM, 0.0);
+    for (int i = 0; i < used; ++i) {
+        ybuf[2 * i] = y[i].real();
+        ybuf[2 * i + 1] = y[i].imag();
+    }
+    std::vector<double> zs(MAXM + 1, 1.0);
+    if (!z_scaled)
+        for (int i = 0; i < used; ++i) zs[i] = scale[i];
+    HIPCHK(hipMemcpyAsync(K->y, ybuf.data(), sizeof(double) * 2 * MAXM, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(K->scale, zs.data(), sizeof(double) * (MAXM + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(&K->cols, &used, sizeof(int), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL((k_krylov_combine<P, MAXM>), dim3(flat_blocks(N)), dim3(BLOCK), 0, st, N, Zs,
+                       (const KrylovScal*)K, (const Cp*)x, (Cp*)x);
+    HIPCHK(hipStreamSynchronize(st));
+    *est_out = est;
+    return used;
+}
+
+static void residual_fp64(helm_ctx c, hipStream_t st, const void* g, const void* u, void* r, double* rn, double* gn) {
+    const Geom G = make_geom(c, 1);
+    hipLaunchKernelGGL(k_residual_norms, dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const double*)c->n2f,
+                       (const c128*)g, (const c128*)u, (c128*)r, c->partials, c->ticket, c->dscal);
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, c->dscal, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (rn) *rn = std::sqrt(h[0]);
+    if (gn) *gn = std::sqrt(h[1]);
+}
+
+// ------------------------------------------------------------------ setup
+static void validate(const helm_desc* d) {
+    REQUIRE(d != nullptr, "desc is NULL");
+    REQUIRE(d->n >= 16 && d->n <= 8192 && (d->n & (d->n - 1)) == 0, "n must be a power of two in [16, 8192]");
+    int lg = 0;
+    while ((1 << lg) < d->n) ++lg;
+    REQUIRE(d->levels >= 2 && d->levels <= lg - 1, "levels must be in [2, log2(n) - 1]");
+    REQUIRE(d->k > 0 && std::isfinite(d->k), "k must be positive");
+    REQUIRE(d->damping_cells >= 1, "damping_cells must be >= 1");
+    REQUIRE(d->damping_strength >= 0 && std::isfinite(d->damping_strength), "damping_strength must be >= 0");
+    REQUIRE(d->sign == 1 || d->sign == -1, "sign must be +1 or -1");
+    REQUIRE(d->cycle_prec == HELM_C64 || d->cycle_prec == HELM_C128, "cycle_prec must be HELM_C64 or HELM_C128");
+    REQUIRE(d->adr_steps >= 0 && d->adr_steps <= 64, "adr_steps must be in [0, 64]");
+    REQUIRE(d->cheb_pre >= 1 && d->cheb_post >= 1 && d->cheb_coarse >= 1 && d->cheb_pre <= 64 &&
+                d->cheb_post <= 64 && d->cheb_coarse <= 64,
+            "Chebyshev step counts must be in [1, 64]");
+    REQUIRE(d->gmres_m >= 1 && d->gmres_m <= MAXM && d->gmres_coarse_m >= 1 && d->gmres_coarse_m <= MAXM,
+            "GMRES dimensions must be in [1, 24]");
+    REQUIRE(d->restart >= 1 && d->restart <= MAXM, "restart must be in [1, 24]");
+}
+
+static void build(helm_ctx c, const double* velocity, hipStream_t st) {
+    const helm_desc& d = c->d;
+    const int n = d.n, L = d.levels;
+    c->L = L;
+    c->f32 = d.cycle_prec == HELM_C64;
+    const bool f64c = !c->f32;
+    const size_t NF = (size_t)n * n;
+    // reduction scratch: enough partials for any tiled kernel on the fine grid
+    const size_t maxblk = std::max<size_t>((size_t)tiles_of(n), 2048);
+    c->partials = (double*)dalloc(c, maxblk * (2 * MAXM + 4) * sizeof(double));
+    c->ticket = (unsigned int*)dalloc(c, 256);
+    HIPCHK(hipMemsetAsync(c->ticket, 0, 256, st));
+    c->dscal = (double*)dalloc(c, 64 * sizeof(double));
+    c->Kout = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
+    c->Kin = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
+    HIPCHK(hipMemsetAsync(c->Kout, 0, sizeof(KrylovScal), st));
+    HIPCHK(hipMemsetAsync(c->Kin, 0, sizeof(KrylovScal), st));
+    // fine n^2 in FP64, velocity check
+    c->n2f = (double*)dalloc(c, NF * sizeof(double));
+    int* bad = (int*)c->dscal;
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_slowness2, dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF, velocity, c->n2f, bad);
+    HIPCHK(hipGetLastError());
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    REQUIRE(hbad == 0, "velocity must be positive and finite everywhere");
+    // wave levels
+    c->wl.assign(L + 1, WaveLevel{});
+    for (int l = 1; l <= L; ++l) {
+        WaveLevel& W = c->wl[l];
+        W.n = n >> (l - 1);
+        W.G = make_geom(c, l);
+        W.f64 = f64c || l == L;
+        const size_t Nl = (size_t)W.n * W.n;
+        if (l == 1 && W.f64) {
+            W.n2 = c->n2f;
+        } else {
+            W.n2 = dalloc(c, Nl * rsize(W.f64));
+            if (W.f64)
+                hipLaunchKernelGGL((k_inject_real<double, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.n,
+                                   1 << (l - 1), n, (const double*)c->n2f, (double*)W.n2);
+            else
+                hipLaunchKernelGGL((k_inject_real<float, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.n,
+                                   1 << (l - 1), n, (const double*)c->n2f, (float*)W.n2);
+        }
+        if (l >= 2) {
+            W.g = dalloc(c, Nl * csize(W.f64));
+            W.u = dalloc(c, Nl * csize(W.f64));
+            W.t = dalloc(c, Nl * csize(W.f64));
+            W.r = dalloc(c, Nl * csize(W.f64));
+            W.d = dalloc(c, Nl * csize(W.f64));
+        }
+        // statistics from the FP64 fine field by injection (through a FP64 copy on coarse levels)
+        const double* n2d = c->n2f;
+        double* tmp = nullptr;
+        if (l > 1) {
+            tmp = (double*)dalloc(c, Nl * sizeof(double));
+            hipLaunchKernelGGL((k_inject_real<double, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.n,
+                               1 << (l - 1), n, (const double*)c->n2f, tmp);
+            n2d = tmp;
+        }
+        hipLaunchKernelGGL(k_level_stats, dim3(flat_blocks(Nl, 1024)), dim3(BLOCK), 0, st, W.G, n2d, c->partials,
+                           c->ticket, c->dscal + 8);
+        double hs[3];
+        HIPCHK(hipMemcpyAsync(hs, c->dscal + 8, sizeof(hs), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        W.lam = (hs[0] + 4.0 * W.G.inv_h2) * (hs[0] + 4.0 * W.G.inv_h2);
+        W.n2max = hs[1];
+        W.n2mean = hs[2] / double((size_t)(W.n - 1) * (W.n - 1));
+        if (tmp) {
+            HIPCHK(hipFree(tmp));
+            c->allocs.pop_back();
+        }
+    }
+    // default weights
+    c->w.assign(L, 0.0);
+    {
+        const double h1 = 1.0 / n;
+        const double K = d.k * d.k * c->wl[1].n2max * h1 * h1;
+        c->w[0] = (4.0 - K) / (5.0 - K);
+        for (int l = 2; l <= L; ++l) c->w[l - 1] = median_alpha(d.k, c->wl[l].n2mean, c->wl[l].n, c->wl[l].lam);
+    }
+    c->w_default = c->w;
+    // level-1 second iterate
+    c->ws1 = dalloc(c, NF * csize(f64c));
+    // ADR levels
+    c->al.assign(L + 1, AdrLevel{});
+    if (L >= 3) {
+        for (int l = 2; l <= L; ++l) {
+            AdrLevel& A = c->al[l];
+            A.n = n >> (l - 1);
+            A.A = make_adr_geom(c, l);
+            const size_t Nl = (size_t)A.n * A.n;
+            A.px = dalloc(c, Nl * rsize(f64c));
+            A.py = dalloc(c, Nl * rsize(f64c));
+            A.c0 = dalloc(c, Nl * csize(f64c));
+            A.b = dalloc(c, Nl * csize(f64c));
+            A.x = dalloc(c, Nl * csize(f64c));
+            const int m = (l == L) ? d.gmres_coarse_m : d.gmres_m;
+            for (int i = 0; i <= m; ++i) A.V[i] = dalloc(c, Nl * csize(f64c));
+            A.K = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
+            HIPCHK(hipMemsetAsync(A.K, 0, sizeof(KrylovScal), st));
+        }
+        c->theta2 = dalloc(c, (size_t)(n / 2) * (n / 2) * rsize(f64c));
+    }
+    // outer FGMRES (complex128) vectors
+    for (int i = 0; i <= d.restart; ++i) c->fV[i] = dalloc(c, NF * sizeof(c128));
+    for (int i = 0; i < d.restart; ++i) c->fZ[i] = dalloc(c, NF * sizeof(c128));
+    if (c->f32) {
+        c->cyc_g = dalloc(c, NF * sizeof(c64));
+        c->cyc_u = dalloc(c, NF * sizeof(c64));
+        for (int i = 0; i <= d.restart; ++i) c->iV[i] = dalloc(c, NF * sizeof(c64));
+        for (int i = 0; i < d.restart; ++i) c->iZ[i] = dalloc(c, NF * sizeof(c64));
+        c->dbuf = dalloc(c, NF * sizeof(c64));
+    }
+    c->rbuf = dalloc(c, NF * sizeof(c128));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
+    if (c->L < 3) {
+        c->phase_set = true;
+        return;
+    }
+    for (int l = 2; l <= c->L; ++l) {
+        AdrLevel& A = c->al[l];
+        const Geom G = make_geom(c, l);
+        const size_t Nl = (size_t)A.n * A.n;
+        void* th = (l == 2) ? c->theta2 : nullptr;
+        const int nb = flat_blocks(Nl);
+        if (c->f32) {
+            if (is64)
+                hipLaunchKernelGGL((k_adr_coef<float, double>), dim3(nb), dim3(BLOCK), 0, st, G, (const double*)c->n2f,
+                                   (const double*)phi, c->d.k, c->d.sign, c->d.damping_strength, (float*)A.px,
+                                   (float*)A.py, (c64*)A.c0, (float*)th);
+            else
+                hipLaunchKernelGGL((k_adr_coef<float, float>), dim3(nb), dim3(BLOCK), 0, st, G, (const double*)c->n2f,
+                                   (const float*)phi, c->d.k, c->d.sign, c->d.damping_strength, (float*)A.px,
+                                   (float*)A.py, (c64*)A.c0, (float*)th);
+        } else {
+            if (is64)
+                hipLaunchKernelGGL((k_adr_coef<double, double>), dim3(nb), dim3(BLOCK), 0, st, G,
+                                   (const double*)c->n2f, (const double*)phi, c->d.k, c->d.sign,
+                                   c->d.damping_strength, (double*)A.px, (double*)A.py, (c128*)A.c0, (double*)th);
+            else
+                hipLaunchKernelGGL((k_adr_coef<double, float>), dim3(nb), dim3(BLOCK), 0, st, G,
+                                   (const double*)c->n2f, (const float*)phi, c->d.k, c->d.sign,
+                                   c->d.damping_strength, (double*)A.px, (double*)A.py, (c128*)A.c0, (double*)th);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    c->phase_set = true;
+}
+
+template <typename T>
+static void run_cycle(helm_ctx c, const void* g, const void* u_in, void* u_out, hipStream_t st) {
+    Engine<T> E(c, st);
+    E.cycle(g, u_in, u_out);
+}
+
+static void cycle_any(helm_ctx c, const void* g, const void* u_in, void* u_out, hipStream_t st) {
+    if (c->f32)
+        run_cycle<float>(c, g, u_in, u_out, st);
+    else
+        run_cycle<double>(c, g, u_in, u_out, st);
+}
+
+// ------------------------------------------------------------------ solve
+static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int maxit, int mode, int* iters,
+                         double* relres, double* history, hipStream_t st) {
+    const size_t NF = (size_t)c->d.n * c->d.n;
+    double rn = 0, gn = 0;
+    residual_fp64(c, st, g, u, c->fV[0], &rn, &gn);
+    std::vector<double> hist;
+    int its = 0;
+    if (!(gn > 0.0)) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF, (c128*)u);
+        HIPCHK(hipStreamSynchronize(st));
+        *iters = 0;
+        *relres = 0.0;
+        return HELM_OK;
+    }
+    const double r0 = rn;
+    helm_status status = HELM_OK;
+    bool converged = rn / gn < tol;
+    if (mode == 0) {
+        while (!converged && its < maxit) {
+            double est = 0;
+            bool bd = false;
+            auto prec = [&](int j, double s) {
+                if (c->f32) {
+                    hipLaunchKernelGGL((k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+                                       (const c128*)c->fV[j], (c64*)c->cyc_g, s);
+                    cycle_any(c, c->cyc_g, nullptr, c->cyc_u, st);
+                    hipLaunchKernelGGL((k_cast_scale<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+                                       (const c64*)c->cyc_u, (c128*)c->fZ[j], 1.0);
+                } else {
+                    cycle_any(c, c->fV[j], nullptr, c->fZ[j], st);
+                }
+            };
+            // Z scaled by 1/||V_j|| already when the cycle input was normalised (complex64 path)
+            const bool zs = c->f32;
+            int used = fgmres_cycle<double>(c, st, c->n2f, c->fV, c->fZ, c->Kout, zs, u, gn, tol * gn, maxit - its,
+                                            prec, &hist, &est, &bd);
+            its += used;
+            residual_fp64(c, st, g, u, c->fV[0], &rn, &gn);
+            if (bd || !std::isfinite(rn) || rn > 1e4 * r0) {
+                status = HELM_EBREAKDOWN;
+                break;
+            }
+            converged = rn / gn < tol;
+            if (used == 0) break;
+        }
+    } else {
+        REQUIRE(c->f32, "mode 1 (iterative refinement) needs cycle_prec = HELM_C64");
+        const double eta = 1e-4;
+        while (!converged && its < maxit) {
+            // inner right-hand side r / ||r|| in complex64 (fV[0] holds r)
+            hipLaunchKernelGGL((k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+                               (const c128*)c->fV[0], (c64*)c->iV[0], 1.0 / rn);
+            hipLaunchKernelGGL((k_zero<float>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF, (c64*)c->dbuf);
+            auto prec = [&](int j, double s) { cycle_any(c, c->iV[j], nullptr, c->iZ[j], st); (void)s; };
+            double est = 0;
+            bool bd = false;
+            const double target = std::max(eta, 0.5 * tol * gn / rn);
+            int used = fgmres_cycle<float>(c, st, c->wl[1].n2, c->iV, c->iZ, c->Kin, false, c->dbuf, 1.0, target,
+                                           maxit - its, prec, nullptr, &est, &bd);
+            its += used;
+            hipLaunchKernelGGL((k_add_cast<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+                               (const c64*)c->dbuf, (c128*)u, rn);
+            residual_fp64(c, st, g, u, c->fV[0], &rn, &gn);
+            hist.push_back(rn / gn);
+            if (bd || !std::isfinite(rn) || rn > 1e4 * r0) {
+                status = HELM_EBREAKDOWN;
+                break;
+            }
+            converged = rn / gn < tol;
+            if (used == 0) break;
+        }
+    }
+    *iters = its;
+    *relres = rn / gn;
+    if (history)
+        for (size_t i = 0; i < hist.size() && i < (size_t)maxit + 1; ++i) history[i] = hist[i];
+    if (status == HELM_OK && !converged) status = HELM_ENOCONV;
+    return status;
+}
+
+}  // namespace helm
+
+// ================================================================== C ABI
+using namespace helm;
+
+static helm_status fail(const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+}
+
+#define ABI_GUARD(...)                                             \
+    try {                                                          \
+        __VA_ARGS__                                                \
+    } catch (const Error& e) {                                     \
+        return fail(e);                                            \
+    } catch (const std::exception& e) {                            \
+        g_last_error = e.what();                                   \
+        return HELM_EHIP;                                          \
+    } catch (...) {                                                \
+        g_last_error = "unknown error";                            \
+        return HELM_EHIP;                                          \
+    }
+
+extern "C" {
+
+void helm_desc_default(helm_desc* d, int32_t n, double k) {
+    if (!d) return;
+    std::memset(d, 0, sizeof(*d));
+    d->n = n;
+    int lg = 0;
+    while (lg < 31 && (1 << lg) < n) ++lg;
+    int L = std::min(7, lg - 3);
+    d->levels = L < 2 ? 2 : L;
+    d->k = k;
+    d->damping_cells = 16;
+    d->damping_strength = 0.5;
+    d->sign = 1;
+    d->cycle_prec = HELM_C128;
+    d->adr_steps = 8;
+    d->cheb_pre = 5;
+    d->cheb_post = 5;
+    d->cheb_coarse = 10;
+    d->gmres_m = 3;
+    d->gmres_coarse_m = 10;
+    d->level3_literal = 0;
+    d->restart = 20;
+}
+
+helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* out, void* stream) {
+    ABI_GUARD({
+        REQUIRE(out != nullptr, "out is NULL");
+        validate(desc);
+        REQUIRE(velocity != nullptr, "velocity is NULL");
+        helm_ctx c = new helm_ctx_s();
+        c->d = *desc;
+        try {
+            build(c, velocity, (hipStream_t)stream);
+        } catch (...) {
+            helm_destroy(c);
+            throw;
+        }
+        *out = c;
+        return HELM_OK;
+    })
+}
+
+helm_status helm_set_phase(helm_ctx ctx, const void* phi, int32_t phi_is_f64, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && phi != nullptr, "NULL argument");
+        set_phase(ctx, phi, phi_is_f64 != 0, (hipStream_t)stream);
+        return HELM_OK;
+    })
+}
+
+helm_status helm_set_weights(helm_ctx ctx, const double* w) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && w != nullptr, "NULL argument");
+        for (int l = 0; l < ctx->L; ++l) {
+            REQUIRE(std::isfinite(w[l]), "weights must be finite");
+            if (l >= 1) REQUIRE(w[l] >= 1.0, "Chebyshev alpha must be >= 1");
+        }
+        ctx->w.assign(w, w + ctx->L);
+        return HELM_OK;
+    })
+}
+
+helm_status helm_get_weights(helm_ctx ctx, double* w) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && w != nullptr, "NULL argument");
+        for (int l = 0; l < ctx->L; ++l) w[l] = ctx->w[l];
+        return HELM_OK;
+    })
+}
+
+helm_status helm_get_lambdas(helm_ctx ctx, double* lam) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && lam != nullptr, "NULL argument");
+        for (int l = 1; l <= ctx->L; ++l) lam[l - 1] = ctx->wl[l].lam;
+        return HELM_OK;
+    })
+}
+
+helm_status helm_cycle(helm_ctx ctx, const void* g, void* u, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && u != nullptr, "NULL argument");
+        if (ctx->d.adr_steps > 0 && ctx->L >= 3 && !ctx->phase_set)
+            throw Error(HELM_ESTATE, "helm_set_phase must be called before helm_cycle");
+        cycle_any(ctx, g, u, u, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+        return HELM_OK;
+    })
+}
+
+helm_status helm_solve(helm_ctx ctx, const void* g, void* u, double tol, int32_t maxit, int32_t mode,
+                       int32_t* iters, double* relres, double* history, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && u != nullptr && iters != nullptr && relres != nullptr,
+                "NULL argument");
+        REQUIRE(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
+        REQUIRE(mode == 0 || mode == 1, "mode must be 0 or 1");
+        if (ctx->d.adr_steps > 0 && ctx->L >= 3 && !ctx->phase_set)
+            throw Error(HELM_ESTATE, "helm_set_phase must be called before helm_solve");
+        int it = 0;
+        double rr = 0;
+        helm_status s = solve(ctx, g, u, tol, maxit, mode, &it, &rr, history, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+        *iters = it;
+        *relres = rr;
+        if (s == HELM_ENOCONV) g_last_error = "tolerance not reached within maxit";
+        if (s == HELM_EBREAKDOWN) g_last_error = "breakdown: non-finite or growing residual";
+        return s;
+    })
+}
+
+helm_status helm_residual(helm_ctx ctx, const void* g, const void* u, void* r, double* rnorm, double* gnorm,
+                          void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && u != nullptr, "NULL argument");
+        residual_fp64(ctx, (hipStream_t)stream, g, u, r, rnorm, gnorm);
+        return HELM_OK;
+    })
+}
+
+helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const void* u0, const void* grad_uK,
+                                void* grad_phi, double* grad_w, void* ckpt_ws, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && grad_uK != nullptr && grad_phi != nullptr && grad_w != nullptr,
+                "NULL argument");
+        REQUIRE(K >= 1, "K must be >= 1");
+        (void)u0;
+        (void)ckpt_ws;
+        (void)stream;
+        throw Error(HELM_ESTATE, "helm_cycle_backward is not available in this build");
+    })
+}
+
+helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* in, const void* in2, void* out,
+                          void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && out != nullptr, "NULL argument");
+        REQUIRE(level >= 1 && level <= ctx->L, "bad level");
+        hipStream_t st = (hipStream_t)stream;
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            Engine<T> E(ctx, st);
+            WaveLevel& W = ctx->wl[level];
+            switch (op) {
+                case 1:
+                    if (W.f64) E.template applyA<double>(W.G, W.n2, in, out, 0);
+                    else E.template applyA<T>(W.G, W.n2, in, out, 0);
+                    break;
+                case 2:
+                    REQUIRE(level < ctx->L, "restriction needs level < L");
+                    if (ctx->wl[level + 1].f64 && !W.f64) {
+                        // in -> R in with g = in, u = 0
+                        E.template resid_restrict<T, double>(level, in, nullptr, out);
+                    } else if (W.f64) {
+                        E.template resid_restrict<double, double>(level, in, nullptr, out);
+                    } else {
+                        E.template resid_restrict<T, T>(level, in, nullptr, out);
+                    }
+                    break;
+                case 3:
+                    REQUIRE(level < ctx->L, "prolongation needs level < L");
+                    if (ctx->wl[level + 1].f64 && !W.f64) E.template prolong_add<double, T>(level, in, out);
+                    else if (W.f64) E.template prolong_add<double, double>(level, in, out);
+                    else E.template prolong_add<T, T>(level, in, out);
+                    break;
+                case 4:
+                    REQUIRE(level == 1, "Jacobi runs on level 1");
+                    hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(W.n)), tile_block(), 0, st, W.G, (const T*)W.n2,
+                                       (const cplx<T>*)in2, (const cplx<T>*)in, (cplx<T>*)out, T(ctx->w[0]));
+                    break;
+                case 5: {
+                    REQUIRE(level >= 2, "Chebyshev runs on levels >= 2");
+                    const size_t Nl = (size_t)W.n * W.n;
+                    const int m = (level == ctx->L) ? ctx->d.cheb_coarse : ctx->d.cheb_pre;
+                    if (W.f64) {
+                        HIPCHK(hipMemcpyAsync(out, in, Nl * sizeof(c128), hipMemcpyDeviceToDevice, st));
+                        E.template chebyshev<double>(level, in2, out, false, ctx->w[level - 1], m);
+                    } else {
+                        HIPCHK(hipMemcpyAsync(out, in, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                        E.template chebyshev<T>(level, in2, out, false, ctx->w[level - 1], m);
+                    }
+                    break;
+                }
+                case 6: {
+                    REQUIRE(level >= 2 && ctx->L >= 3 && ctx->phase_set, "ADR operator needs the phase");
+                    AdrLevel& A = ctx->al[level];
+                    hipLaunchKernelGGL((k_adr_apply<T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
+                                       (const T*)A.px, (const T*)A.py, (const cplx<T>*)A.c0, (const cplx<T>*)in,
+                                       (cplx<T>*)out);
+                    break;
+                }
+                case 7: {
+                    REQUIRE(level >= 2 && ctx->L >= 3 && ctx->phase_set, "GMRES needs the phase");
+                    AdrLevel& A = ctx->al[level];
+                    const size_t Nl = (size_t)A.n * A.n;
+                    HIPCHK(hipMemcpyAsync(A.b, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipMemcpyAsync(A.x, in, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    E.gmres(level, level == ctx->L ? ctx->d.gmres_coarse_m : ctx->d.gmres_m, false);
+                    HIPCHK(hipMemcpyAsync(out, A.x, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    break;
+                }
+                case 8: {
+                    REQUIRE(level >= 2 && ctx->L >= 3 && ctx->phase_set, "ADR V-cycle needs the phase");
+                    AdrLevel& A = ctx->al[level];
+                    const size_t Nl = (size_t)A.n * A.n;
+                    HIPCHK(hipMemcpyAsync(A.b, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    E.adr_vcycle(level);
+                    HIPCHK(hipMemcpyAsync(out, A.x, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    break;
+                }
+                case 9: {
+                    REQUIRE(level == 2 && ctx->L >= 3 && ctx->phase_set, "ADR step runs on level 2 with the phase");
+                    const size_t Nl = (size_t)W.n * W.n;
+                    HIPCHK(hipMemcpyAsync(W.g, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipMemcpyAsync(W.u, in, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    E.adr_step();
+                    HIPCHK(hipMemcpyAsync(out, W.u, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+                    break;
+                }
+                case 10: {
+                    if (level == 1) {
+                        E.cycle(in2, in, out);
+                    } else {
+                        REQUIRE(in == nullptr, "coarse cycles start from a zero iterate (in must be NULL)");
+                        const size_t Nl = (size_t)W.n * W.n;
+                        HIPCHK(hipMemcpyAsync(W.g, in2, Nl * csize(W.f64), hipMemcpyDeviceToDevice, st));
+                        E.cycle_coarse(level);
+                        HIPCHK(hipMemcpyAsync(out, W.u, Nl * csize(W.f64), hipMemcpyDeviceToDevice, st));
+                    }
+                    break;
+                }
+                case 11:
+                    REQUIRE(level < ctx->L, "restriction needs level < L");
+                    if (W.f64) E.template resid_restrict<double, double>(level, in2, in, out);
+                    else if (ctx->wl[level + 1].f64) E.template resid_restrict<T, double>(level, in2, in, out);
+                    else E.template resid_restrict<T, T>(level, in2, in, out);
+                    break;
+                default:
+                    throw Error(HELM_EINVAL, "unknown debug op");
+            }
+        };
+        if (ctx->f32) run(float{});
+        else run(double{});
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return HELM_OK;
+    })
+}
+
+helm_status helm_destroy(helm_ctx ctx) {
+    if (!ctx) return HELM_OK;
+    for (void* p : ctx->allocs) (void)hipFree(p);
+    ctx->allocs.clear();
+    delete ctx;
+    return HELM_OK;
+}
+
+const char* helm_status_string(helm_status s) {
+    switch (s) {
+        case HELM_OK: return "HELM_OK";
+        case HELM_EINVAL: return "HELM_EINVAL: invalid argument";
+        case HELM_ENOMEM: return "HELM_ENOMEM: device allocation failed";
+        case HELM_EHIP: return "HELM_EHIP: HIP runtime error";
+        case HELM_ENOCONV: return "HELM_ENOCONV: tolerance not reached";
+        case HELM_EBREAKDOWN: return "HELM_EBREAKDOWN: numerical breakdown";
+        case HELM_ESTATE: return "HELM_ESTATE: call out of order";
+    }
+    return "unknown status";
+}
+
+const char* helm_last_error(void) { return g_last_error.c_str(); }
+
+const char* helm_version(void) { return "helm-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

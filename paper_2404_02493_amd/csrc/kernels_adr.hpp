@@ -1,0 +1,182 @@
+// ADR-correction kernels: coefficients, upwind ADR operator, demodulation and
+// re-modulation with the carrier e^{+- i sigma k phi}, ADR residual/restriction.
+#pragma once
+
+#include "kernels_wave.hpp"
+
+namespace helm {
+
+// Geometry of one ADR level.
+struct AdrGeom {
+    int n;
+    double inv_h2;
+    double inv_2h;     // 1/(2h)
+    double two_sk;     // 2 * sigma * k (the advection factor is -i * two_sk)
+};
+
+// Phase derivatives and reaction term on one ADR level, computed in FP64 from the
+// fine phase by injection (stride s); second-order central differences inside,
+// first-order one-sided ones at the last unknown (the node x = 1 is not stored).
+//   c0 = -i sigma k Lap(phi) + k^2 (phi_x^2 + phi_y^2 - n2) - i sigma k^2 n2 delta
+// theta (level 2 only, may be null): sigma k phi reduced to [-pi, pi] in FP64.
+template <typename T, typename TP>
+__global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __restrict__ n2f,
+                                                    const TP* __restrict__ phi, double k, int sigma, double strength,
+                                                    T* __restrict__ px_out, T* __restrict__ py_out,
+                                                    cplx<T>* __restrict__ c0_out, T* __restrict__ theta_out) {
+    const int n = G.n, s = G.s, nf = G.nf;
+    const size_t N = (size_t)n * n;
+    const double h = 1.0 / n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        auto P = [&](int a, int b) -> double { return double(phi[(size_t)a * s * nf + (size_t)b * s]); };
+        if (theta_out) {
+            // Cody-Waite reduction with a two-part 2 pi
+            const double P1 = 6.283185307179586, P2 = 2.4492935982947064e-16;
+            double a = double(sigma) * k * P(i, j);
+            double q = rint(a / P1);
+            double t = fma(-q, P1, a);
+            t = fma(-q, P2, t);
+            theta_out[p] = T(t);
+        }
+        if (i == 0 || j == 0) {
+            px_out[p] = T(0);
+            py_out[p] = T(0);
+            c0_out[p] = cplx<T>{};
+            continue;
+        }
+        double px, py, pxx, pyy;
+        const double c = P(i, j);
+        if (j <= n - 2) {
+            px = (P(i, j + 1) - P(i, j - 1)) / (2.0 * h);
+            pxx = ((P(i, j + 1) - 2.0 * c) + P(i, j - 1)) / (h * h);
+        } else {
+            px = (c - P(i, j - 1)) / h;
+            pxx = ((c - 2.0 * P(i, j - 1)) + P(i, j - 2)) / (h * h);
+        }
+        if (i <= n - 2) {
+            py = (P(i + 1, j) - P(i - 1, j)) / (2.0 * h);
+            pyy = ((P(i + 1, j) - 2.0 * c) + P(i - 1, j)) / (h * h);
+        } else {
+            py = (c - P(i - 1, j)) / h;
+            pyy = ((c - 2.0 * P(i - 1, j)) + P(i - 2, j)) / (h * h);
+        }
+        const double lap = pxx + pyy;
+        const double nn = n2f[(size_t)i * s * nf + (size_t)j * s];
+        const double ri = sponge_ramp<double>(i * s, nf, G.W), rj = sponge_ramp<double>(j * s, nf, G.W);
+        const double rho = ri > rj ? ri : rj;
+        const double delta = strength * rho * rho;
+        const double k2 = k * k;
+        const double re = k2 * ((px * px + py * py) - nn);
+        const double im = -(double(sigma) * k) * lap - ((double(sigma) * k2) * nn) * delta;
+        px_out[p] = T(px);
+        py_out[p] = T(py);
+        c0_out[p] = mk<T>(T(re), T(im));
+    }
+}
+
+// (M x)(i,j) = -Delta_h x - 2 i sigma k U_h[x] + c0 x   (x scaled by xs)
+template <typename T>
+__device__ __forceinline__ cplx<T> applyM_at(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,
+                                             const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ x, int i,
+                                             int j) {
+    const int n = A.n;
+    const size_t p = (size_t)i * n + j;
+    const cplx<T> c = x[p];
+    const cplx<T> w = ldz(x, i, j - 1, n), e = ldz(x, i, j + 1, n);
+    const cplx<T> s = ldz(x, i - 1, j, n), nn = ldz(x, i + 1, j, n);
+    const T fx = px[p], fy = py[p];
+    const T ax = fx < T(0) ? -fx : fx, ay = fy < T(0) ? -fy : fy;
+    const cplx<T> lap = T(A.inv_h2) * (T(4) * c - (((s + nn) + w) + e));
+    const cplx<T> U = T(A.inv_2h) * (((((T(2) * (ax + ay)) * c - (fx + ax) * w) + (fx - ax) * e) - (fy + ay) * s) +
+                                    (fy - ay) * nn);
+    // -2 i sigma k U = (two_sk * U.im, -two_sk * U.re)
+    const cplx<T> adv = mk<T>(T(A.two_sk) * U.im, -T(A.two_sk) * U.re);
+    return lap + (adv + c0[p] * c);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_apply(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                     const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ x,
+                                                     cplx<T>* __restrict__ y) {
+    int j, i0;
+    tile_origin(A.n, j, i0);
+    if (j >= A.n) return;
+    for (int r = 0; r < RPT; ++r) {
+        const int i = i0 + r;
+        if (i >= A.n) break;
+        cplx<T> v{};
+        if (i > 0 && j > 0) v = applyM_at(A, px, py, c0, x, i, j);
+        y[(size_t)i * A.n + j] = v;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> adr_resid_at(const AdrGeom& A, const T* px, const T* py, const cplx<T>* c0,
+                                                const cplx<T>* b, const cplx<T>* x, int i, int j) {
+    cplx<T> bv = b[(size_t)i * A.n + j];
+    if (x == nullptr) return bv;
+    return bv - applyM_at(A, px, py, c0, x, i, j);
+}
+
+// rc = R (b - M x) on the next ADR level (x == nullptr: x = 0)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_resid_restrict(AdrGeom A, const T* __restrict__ px,
+                                                              const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                                              const cplx<T>* __restrict__ b,
+                                                              const cplx<T>* __restrict__ x, cplx<T>* __restrict__ rc) {
+    const int nc = A.n / 2;
+    int J, I0;
+    tile_origin(nc, J, I0);
+    if (J >= nc) return;
+    for (int r = 0; r < RPT; ++r) {
+        const int I = I0 + r;
+        if (I >= nc) break;
+        cplx<T> v{};
+        if (I > 0 && J > 0) {
+            const int fi = 2 * I, fj = 2 * J;
+            auto R = [&](int a, int bb) { return adr_resid_at(A, px, py, c0, b, x, a, bb); };
+            cplx<T> c = R(fi, fj);
+            cplx<T> ud = R(fi - 1, fj) + R(fi + 1, fj) + R(fi, fj - 1) + R(fi, fj + 1);
+            cplx<T> dg = R(fi - 1, fj - 1) + R(fi - 1, fj + 1) + R(fi + 1, fj - 1) + R(fi + 1, fj + 1);
+            v = T(1.0 / 16.0) * ((T(4) * c + T(2) * ud) + dg);
+        }
+        rc[(size_t)I * nc + J] = v;
+    }
+}
+
+// r_hat = (g - A u) e^{-i theta}
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_demod(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
+                                                     const cplx<T>* __restrict__ u, const T* __restrict__ theta,
+                                                     cplx<T>* __restrict__ rhat) {
+    int j, i0;
+    tile_origin(G.n, j, i0);
+    if (j >= G.n) return;
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int i = i0 + rr;
+        if (i >= G.n) break;
+        cplx<T> v{};
+        const size_t p = (size_t)i * G.n + j;
+        if (i > 0 && j > 0) {
+            cplx<T> r = resid_at(G, n2, g, u, i, j);
+            T sn, cs;
+            sincos_t(theta[p], &sn, &cs);
+            v = r * mk<T>(cs, -sn);
+        }
+        rhat[p] = v;
+    }
+}
+
+// u += a e^{+i theta}
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_modadd(size_t N, const cplx<T>* __restrict__ a, const T* __restrict__ theta,
+                                                      cplx<T>* __restrict__ u) {
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        T sn, cs;
+        sincos_t(theta[p], &sn, &cs);
+        u[p] = u[p] + a[p] * mk<T>(cs, sn);
+    }
+}
+
+}  // namespace helm

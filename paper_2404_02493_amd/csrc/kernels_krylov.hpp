@@ -1,0 +1,352 @@
+// Krylov kernels shared by the GMRES(m) ADR smoother and the outer FGMRES:
+// fused operator + inner-product passes, two-pass classical Gram-Schmidt with
+// re-orthogonalisation, the device-side Hessenberg least squares, and the
+// final combination x = x0 + V y.  All inner products accumulate in FP64 and
+// every grid reduction ends in the last block (no host round trip).
+#pragma once
+
+#include "kernels_adr.hpp"
+
+namespace helm {
+
+template <typename T>
+struct VecSet {
+    const cplx<T>* v[MAXM + 1];
+};
+
+__device__ __forceinline__ double* Hp(KrylovScal* K, int i, int j) { return K->H + 2 * (i + j * (MAXM + 1)); }
+
+// Solve min || beta e1 - H y || for the leading (cols+1) x cols block with complex
+// Givens rotations (one thread; works in K->R / K->e, global memory).
+__device__ inline void ks_least_squares(KrylovScal* K, int cols) {
+    double* R = K->R;
+    double* e = K->e;
+    auto Rp = [&](int i, int j) { return R + 2 * (i + j * (MAXM + 1)); };
+    for (int j = 0; j < cols; ++j)
+        for (int i = 0; i <= j + 1; ++i) {
+            Rp(i, j)[0] = Hp(K, i, j)[0];
+            Rp(i, j)[1] = Hp(K, i, j)[1];
+        }
+    for (int i = 0; i <= cols; ++i) e[2 * i] = e[2 * i + 1] = 0.0;
+    e[0] = K->beta;
+    for (int j = 0; j < cols; ++j) {
+        // rotation j acts on rows j, j+1; rows j..j+1 of columns < j are already zero
+        double ar = Rp(j, j)[0], ai = Rp(j, j)[1];
+        double br = Rp(j + 1, j)[0], bi = Rp(j + 1, j)[1];
+        double na = hypot(ar, ai), nb = hypot(br, bi);
+        double c, sr, si;  // [c s; -conj(s) c], s = (a/|a|) conj(b) / rho
+        if (nb == 0.0) {
+            c = 1.0; sr = 0.0; si = 0.0;
+        } else if (na == 0.0) {
+            c = 0.0; sr = 1.0; si = 0.0;
+        } else {
+            double rho = hypot(na, nb);
+            c = na / rho;
+            double ur = ar / na, ui = ai / na;
+            sr = (ur * br + ui * bi) / rho;
+            si = (ui * br - ur * bi) / rho;
+        }
+        for (int q = j; q < cols; ++q) {
+            double xr = Rp(j, q)[0], xi = Rp(j, q)[1];
+            double yr = Rp(j + 1, q)[0], yi = Rp(j + 1, q)[1];
+            Rp(j, q)[0] = c * xr + (sr * yr - si * yi);
+            Rp(j, q)[1] = c * xi + (sr * yi + si * yr);
+            Rp(j + 1, q)[0] = -(sr * xr + si * xi) + c * yr;
+            Rp(j + 1, q)[1] = -(sr * xi - si * xr) + c * yi;
+        }
+        double xr = e[2 * j], xi = e[2 * j + 1];
+        e[2 * j] = c * xr;
+        e[2 * j + 1] = c * xi;
+        e[2 * j + 2] = -(sr * xr + si * xi);
+        e[2 * j + 3] = -(sr * xi - si * xr);
+    }
+    for (int i = cols - 1; i >= 0; --i) {
+        double accr = e[2 * i], acci = e[2 * i + 1];
+        for (int q = i + 1; q < cols; ++q) {
+            double hr_ = Rp(i, q)[0], hi_ = Rp(i, q)[1];
+            double yr = K->y[2 * q], yi = K->y[2 * q + 1];
+            accr -= hr_ * yr - hi_ * yi;
+            acci -= hr_ * yi + hi_ * yr;
+        }
+        double dr = Rp(i, i)[0], di = Rp(i, i)[1];
+        double d = dr * dr + di * di;
+        K->y[2 * i] = (accr * dr + acci * di) / d;
+        K->y[2 * i + 1] = (acci * dr - accr * di) / d;
+    }
+    for (int i = cols; i < MAXM; ++i) K->y[2 * i] = K->y[2 * i + 1] = 0.0;
+}
+
+// Starts a Krylov run from a given first vector: beta = ||x||, scale[0] = 1/beta.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_krylov_init_norm(size_t N, const cplx<T>* __restrict__ x, KrylovScal* K,
+                                                            int m, double* partials, unsigned int* ticket) {
+    __shared__ double red[4];
+    __shared__ double sums[1];
+    __shared__ int is_last;
+    double acc[1] = {0.0};
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        cplx<T> v = x[p];
+        acc[0] += double(v.re) * double(v.re) + double(v.im) * double(v.im);
+    }
+    if (block_partials_and_ticket<1>(acc, 1, partials, ticket, red, sums, &is_last)) {
+        grid_final_sum<1>(partials, 1, red, sums, ticket);
+        if (threadIdx.x == 0) {
+            double b = sqrt(sums[0]);
+            K->beta = b;
+            K->m = m;
+            K->cols = 0;
+            K->done = (b == 0.0 || !isfinite(b)) ? 1 : 0;
+            K->scale[0] = b > 0.0 ? 1.0 / b : 0.0;
+            if (K->done)
+                for (int i = 0; i < MAXM; ++i) K->y[2 * i] = K->y[2 * i + 1] = 0.0;
+        }
+    }
+}
+
+// r0 = b - M x (ADR operator) written to r0, then the same start as k_krylov_init_norm.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_residual_init(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                             const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
+                                                             const cplx<T>* __restrict__ x, cplx<T>* __restrict__ r0,
+                                                             KrylovScal* K, int m, double* partials,
+                                                             unsigned int* ticket) {
+    __shared__ double red[4];
+    __shared__ double sums[1];
+    __shared__ int is_last;
+    double acc[1] = {0.0};
+    int j, i0;
+    tile_origin(A.n, j, i0);
+    if (j < A.n) {
+        for (int r = 0; r < RPT; ++r) {
+            const int i = i0 + r;
+            if (i >= A.n) break;
+            cplx<T> v{};
+            if (i > 0 && j > 0) v = adr_resid_at(A, px, py, c0, b, x, i, j);
+            r0[(size_t)i * A.n + j] = v;
+            acc[0] += double(v.re) * double(v.re) + double(v.im) * double(v.im);
+        }
+    }
+    if (block_partials_and_ticket<1>(acc, 1, partials, ticket, red, sums, &is_last)) {
+        grid_final_sum<1>(partials, 1, red, sums, ticket);
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            double bb = sqrt(sums[0]);
+            K->beta = bb;
+            K->m = m;
+            K->cols = 0;
+            K->done = (bb == 0.0 || !isfinite(bb)) ? 1 : 0;
+            K->scale[0] = bb > 0.0 ? 1.0 / bb : 0.0;
+            if (K->done)
+                for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
+        }
+    }
+}
+
+// Accumulates sum conj(V_i) * w over i <= jj into acc (unscaled).
+template <typename T, int NV>
+__device__ __forceinline__ void acc_dots(double (&acc)[2 * NV + 2], const VecSet<T>& V, int jj, size_t p, cplx<T> w) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i <= jj) {
+            cplx<T> v = V.v[i][p];
+            acc[2 * i] += double(v.re) * double(w.re) + double(v.im) * double(w.im);
+            acc[2 * i + 1] += double(v.re) * double(w.im) - double(v.im) * double(w.re);
+        }
+    }
+}
+
+// Stores the scaled inner products of the Arnoldi matvec pass into K->dots.
+template <int NV>
+__device__ __forceinline__ void finalize_mv(KrylovScal* K, int jj, const double* sums) {
+    for (int i = 0; i <= jj; ++i) {
+        double s = K->scale[i];
+        K->dots[2 * i] = s * sums[2 * i];
+        K->dots[2 * i + 1] = s * sums[2 * i + 1];
+    }
+}
+
+// Arnoldi matvec pass with the ADR operator: w = M (scale[jj] V_jj); dots_i = <v_i, w>.
+template <typename T, int NV>
+__global__ __launch_bounds__(BLOCK) void k_arnoldi_adr(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                       const cplx<T>* __restrict__ c0, VecSet<T> V, int jj,
+                                                       cplx<T>* __restrict__ w, KrylovScal* K, double* partials,
+                                                       unsigned int* ticket) {
+    __shared__ double red[4 * (2 * NV + 2)];
+    __shared__ double sums[2 * NV + 2];
+    __shared__ int is_last;
+    if (K->done) return;
+    const T sj = T(K->scale[jj]);
+    double acc[2 * NV + 2];
+#pragma unroll
+    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
+    int j, i0;
+    tile_origin(A.n, j, i0);
+    if (j < A.n) {
+        for (int r = 0; r < RPT; ++r) {
+            const int i = i0 + r;
+            if (i >= A.n) break;
+            const size_t p = (size_t)i * A.n + j;
+            cplx<T> v{};
+            if (i > 0 && j > 0) v = sj * applyM_at(A, px, py, c0, V.v[jj], i, j);
+            w[p] = v;
+            acc_dots<T, NV>(acc, V, jj, p, v);
+        }
+    }
+    if (block_partials_and_ticket<2 * NV + 2>(acc, 2 * (jj + 1), partials, ticket, red, sums, &is_last)) {
+        grid_final_sum<2 * NV + 2>(partials, 2 * (jj + 1), red, sums, ticket);
+        if (threadIdx.x == 0 && threadIdx.y == 0) finalize_mv<NV>(K, jj, sums);
+    }
+}
+
+// Arnoldi matvec pass with the Helmholtz operator on z: w = A (s z), s = scale[jj] if
+// use_scale else 1; dots_i = <v_i, w>   (FGMRES: z = C(0, V_jj) or C(0, v_jj)).
+template <typename T, int NV>
+__global__ __launch_bounds__(BLOCK) void k_arnoldi_helm(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ z,
+                                                        int use_scale, VecSet<T> V, int jj, cplx<T>* __restrict__ w, KrylovScal* K,
+                                                        double* partials, unsigned int* ticket) {
+    __shared__ double red[4 * (2 * NV + 2)];
+    __shared__ double sums[2 * NV + 2];
+    __shared__ int is_last;
+    if (K->done) return;
+    const T sj = use_scale ? T(K->scale[jj]) : T(1);
+    double acc[2 * NV + 2];
+#pragma unroll
+    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
+    int j, i0;
+    tile_origin(G.n, j, i0);
+    if (j < G.n) {
+        for (int r = 0; r < RPT; ++r) {
+            const int i = i0 + r;
+            if (i >= G.n) break;
+            const size_t p = (size_t)i * G.n + j;
+            cplx<T> v{};
+            if (i > 0 && j > 0) v = sj * applyA_at(G, n2, z, i, j, false);
+            w[p] = v;
+            acc_dots<T, NV>(acc, V, jj, p, v);
+        }
+    }
+    if (block_partials_and_ticket<2 * NV + 2>(acc, 2 * (jj + 1), partials, ticket, red, sums, &is_last)) {
+        grid_final_sum<2 * NV + 2>(partials, 2 * (jj + 1), red, sums, ticket);
+        if (threadIdx.x == 0 && threadIdx.y == 0) finalize_mv<NV>(K, jj, sums);
+    }
+}
+
+// Loads the coefficients c_i = dots_i * scale_i (complex) of the current correction.
+template <typename T, int NV>
+__device__ __forceinline__ void load_coefs(const KrylovScal* K, int jj, cplx<T> (&c)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i <= jj) {
+            double s = K->scale[i];
+            c[i] = mk<T>(T(K->dots[2 * i] * s), T(K->dots[2 * i + 1] * s));
+        } else {
+            c[i] = cplx<T>{};
+        }
+    }
+}
+
+// Gram-Schmidt pass 1: w -= sum_i dots_i v_i, then dots2_i = <v_i, w>.
+// Finalize: H(i, jj) = dots_i (first round), dots = dots2.
+template <typename T, int NV>
+__global__ __launch_bounds__(BLOCK) void k_orth_pass1(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
+                                                      KrylovScal* K, double* partials, unsigned int* ticket) {
+    __shared__ double red[4 * (2 * NV + 2)];
+    __shared__ double sums[2 * NV + 2];
+    __shared__ int is_last;
+    if (K->done) return;
+    cplx<T> c[NV];
+    load_coefs<T, NV>(K, jj, c);
+    double acc[2 * NV + 2];
+#pragma unroll
+    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        cplx<T> x = w[p];
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i <= jj) x = x - c[i] * V.v[i][p];
+        w[p] = x;
+        acc_dots<T, NV>(acc, V, jj, p, x);
+    }
+    if (block_partials_and_ticket<2 * NV + 2>(acc, 2 * (jj + 1), partials, ticket, red, sums, &is_last)) {
+        grid_final_sum<2 * NV + 2>(partials, 2 * (jj + 1), red, sums, ticket);
+        if (threadIdx.x == 0) {
+            for (int i = 0; i <= jj; ++i) {
+                Hp(K, i, jj)[0] = K->dots[2 * i];
+                Hp(K, i, jj)[1] = K->dots[2 * i + 1];
+                double s = K->scale[i];
+                K->dots[2 * i] = s * sums[2 * i];
+                K->dots[2 * i + 1] = s * sums[2 * i + 1];
+            }
+        }
+    }
+}
+
+// Gram-Schmidt pass 2: w -= sum_i dots2_i v_i and ||w||^2.  Finalize: H(i, jj) += dots2_i,
+// H(jj+1, jj) = ||w||, next scale, breakdown test, and the least squares at the end.
+template <typename T, int NV>
+__global__ __launch_bounds__(BLOCK) void k_orth_pass2(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
+                                                      KrylovScal* K, double breakdown_tol, double* partials,
+                                                      unsigned int* ticket) {
+    __shared__ double red[4];
+    __shared__ double sums[1];
+    __shared__ int is_last;
+    if (K->done) return;
+    cplx<T> c[NV];
+    load_coefs<T, NV>(K, jj, c);
+    double acc[1] = {0.0};
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        cplx<T> x = w[p];
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i <= jj) x = x - c[i] * V.v[i][p];
+        w[p] = x;
+        acc[0] += double(x.re) * double(x.re) + double(x.im) * double(x.im);
+    }
+    if (block_partials_and_ticket<1>(acc, 1, partials, ticket, red, sums, &is_last)) {
+        grid_final_sum<1>(partials, 1, red, sums, ticket);
+        if (threadIdx.x == 0) {
+            for (int i = 0; i <= jj; ++i) {
+                Hp(K, i, jj)[0] += K->dots[2 * i];
+                Hp(K, i, jj)[1] += K->dots[2 * i + 1];
+            }
+            double hn = sqrt(sums[0]);
+            Hp(K, jj + 1, jj)[0] = hn;
+            Hp(K, jj + 1, jj)[1] = 0.0;
+            K->cols = jj + 1;
+            if (!isfinite(hn)) {
+                K->done = 2;
+                for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
+            } else if (hn <= breakdown_tol * K->beta || jj + 1 == K->m) {
+                ks_least_squares(K, jj + 1);
+                K->done = 1;
+            } else {
+                K->scale[jj + 1] = 1.0 / hn;
+            }
+        }
+    }
+}
+
+// x = x0 + sum_{i < cols} y_i scale_i V_i  (x0 == nullptr: 0; x may alias x0).
+template <typename T, int NV>
+__global__ __launch_bounds__(BLOCK) void k_krylov_combine(size_t N, VecSet<T> V, const KrylovScal* K,
+                                                          const cplx<T>* x0, cplx<T>* x) {
+    const int cols = K->cols;
+    cplx<T> c[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i < cols) {
+            double s = K->scale[i];
+            c[i] = mk<T>(T(K->y[2 * i] * s), T(K->y[2 * i + 1] * s));
+        } else {
+            c[i] = cplx<T>{};
+        }
+    }
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        cplx<T> v = x0 ? x0[p] : cplx<T>{};
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < cols) v = v + c[i] * V.v[i][p];
+        x[p] = v;
+    }
+}
+
+}  // namespace helm

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Inputs come from helm_inputs (seeded); weights are the oracle's defaults, passed
+to the library.  Tolerances: relative 1e-12 for FP64 cycles, 1e-5 for FP32
+cycles, on one operator or one cycle from an identical input.
+"""
+import numpy as np
+import pytest
+import torch
+
+import helm_inputs as hi
+from oracle.adr import adr_step, adr_vcycle, apply_M, gmres
+from oracle.cycle import Problem, cycle, wave_adr_cycle
+from oracle.grid import apply_A, prolong_bilinear, restrict_fw
+from oracle.smooth import chebyshev, jacobi
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+def rel(a, b):
+    a = a.detach().cpu().to(torch.complex128)
+    b = b.detach().cpu().to(torch.complex128)
+    return (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+
+
+def _rand(rng, n):
+    v = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    v[0, :] = 0
+    v[:, 0] = 0
+    return torch.as_tensor(v)
+
+
+def make_pair(case, prec, **kw):
+    from paper_2404_02493_amd import Helmholtz
+
+    P = Problem(case.velocity, case.k, case.levels, damping_cells=case.damping_cells, phi=case.phi, **kw)
+    H = Helmholtz(case.velocity, case.k, levels=case.levels, precision=prec, damping_cells=case.damping_cells,
+                  **{k: int(v) for k, v in kw.items()})
+    H.set_phase(case.phi)
+    H.set_weights(P.weights.numpy())
+    return P, H
+
+
+def to_dev(x, dtype):
+    return x.to(dtype).to("cuda:0").contiguous()
+
+
+def rounded(x, dtype):
+    """Input as the GPU sees it, upcast back for the oracle."""
+    return x.to(dtype).to(torch.complex128)
+
+
+@pytest.fixture(scope="module")
+def small_case():
+    return hi.make_problem(64, 40.0, 4, seed=11, medium="grf", phase="fmm", damping_cells=8)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_default_weights_match_oracle(small_case, prec):
+    from paper_2404_02493_amd import Helmholtz
+
+    c = small_case
+    P = Problem(c.velocity, c.k, c.levels, damping_cells=c.damping_cells)
+    H = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=c.damping_cells)
+    assert np.allclose(H.weights, P.weights.numpy(), rtol=1e-12)
+    assert np.allclose(H.lambdas, [P.lam[l] for l in range(1, c.levels + 1)], rtol=1e-13)
+    H.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_operator_parity(small_case, prec):
+    c = small_case
+    P, H = make_pair(c, prec)
+    rng = np.random.default_rng(0)
+    tol = TOL[prec]
+    cd = H.cdtype
+    L = c.levels
+    report = {}
+    for l in range(1, L + 1):
+        nl = c.n >> (l - 1)
+        dt = H.level_dtype(l)
+        x = rounded(_rand(rng, nl), dt)
+        out = H.debug_op(1, l, to_dev(x, dt), out_dtype=dt)
+        report[f"A{l}"] = rel(out, apply_A(x, P.kappa[l], P.h[l]))
+        if l < L:
+            dtc = H.level_dtype(l + 1)
+            out = H.debug_op(2, l, to_dev(x, dt), out_shape_level=l + 1, out_dtype=dtc)
+            report[f"R{l}"] = rel(out, restrict_fw(x))
+            e = rounded(_rand(rng, nl // 2), dtc)
+            base = rounded(_rand(rng, nl), dt)
+            outp = to_dev(base, dt)
+            H.debug_op(3, l, to_dev(e, dtc), out=outp)
+            report[f"P{l}"] = rel(outp, base + prolong_bilinear(e))
+            g = rounded(_rand(rng, nl), dt)
+            out = H.debug_op(11, l, to_dev(x, dt), to_dev(g, dt), out_shape_level=l + 1, out_dtype=dtc)
+            report[f"RR{l}"] = rel(out, restrict_fw(g - apply_A(x, P.kappa[l], P.h[l])))
+    # Jacobi (level 1)
+    x, g = rounded(_rand(rng, c.n), cd), rounded(_rand(rng, c.n), cd)
+    out = H.debug_op(4, 1, to_dev(x, cd), to_dev(g, cd))
+    report["J1"] = rel(out, jacobi(x, g, P.kappa[1], P.h[1], P.weights[0]))
+    # Chebyshev on level 2 (pre count) and the coarsest level
+    for l, m in [(2, P.cheb_pre), (L, P.cheb_coarse)]:
+        nl = c.n >> (l - 1)
+        dt = H.level_dtype(l)
+        x, g = rounded(_rand(rng, nl), dt), rounded(_rand(rng, nl), dt)
+        out = H.debug_op(5, l, to_dev(x, dt), to_dev(g, dt), out_dtype=dt)
+        report[f"C{l}"] = rel(out, chebyshev(x, g, P.kappa[l], P.h[l], P.weights[l - 1], m, P.lam[l]))
+    # ADR operator on every ADR level
+    for l in range(2, L + 1):
+        nl = c.n >> (l - 1)
+        x = rounded(_rand(rng, nl), cd)
+        out = H.debug_op(6, l, to_dev(x, cd))
+        report[f"M{l}"] = rel(out, apply_M(x, P.adr[l]))
+    # GMRES(3) from a nonzero x0 on level 2
+    n2 = c.n // 2
+    x0, b = rounded(_rand(rng, n2), cd), rounded(_rand(rng, n2), cd)
+    out = H.debug_op(7, 2, to_dev(x0, cd), to_dev(b, cd))
+    report["G2"] = rel(out, gmres(lambda v: apply_M(v, P.adr[2]), b, x0, P.gmres_m))
+    # ADR V-cycle from level 2
+    out = H.debug_op(8, 2, None, to_dev(b, cd))
+    report["V2"] = rel(out, adr_vcycle(P, 2, b, None))
+    # one ADR step on level 2
+    u2, g2 = rounded(_rand(rng, n2), cd), rounded(_rand(rng, n2), cd)
+    out = H.debug_op(9, 2, to_dev(u2, cd), to_dev(g2, cd))
+    report["S2"] = rel(out, adr_step(P, g2, u2))
+    # coarse cycle from level 2 with zero iterate
+    out = H.debug_op(10, 2, None, to_dev(g2, cd))
+    report["W2"] = rel(out, wave_adr_cycle(P, 2, g2, torch.zeros_like(g2)))
+    # fine cycle from a random iterate
+    u, g = rounded(_rand(rng, c.n), cd), rounded(_rand(rng, c.n), cd)
+    out = H.debug_op(10, 1, to_dev(u, cd), to_dev(g, cd))
+    report["W1"] = rel(out, cycle(P, g, u))
+    H.close()
+    bad = {k: v for k, v in report.items() if not v < tol}
+    print({k: f"{v:.2e}" for k, v in report.items()})
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("name", ["const128", "grf512"])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_cycle_parity_along_oracle_iterates(name, prec):
+    """One cycle from identical iterates u_k of the oracle's stationary iteration."""
+    c = hi.make_case(name)
+    P, H = make_pair(c, prec)
+    g = rounded(torch.as_tensor(c.g), H.cdtype)
+    u = torch.zeros_like(g)
+    errs = []
+    for k in range(3):
+        ref = cycle(P, g, u)
+        ud = to_dev(u, H.cdtype)
+        H.cycle(to_dev(g, H.cdtype), ud)
+        errs.append(rel(ud, ref))
+        u = rounded(ref, H.cdtype)
+    H.close()
+    print(name, prec, [f"{e:.2e}" for e in errs])
+    assert max(errs) < TOL[prec], errs
+
+
+def test_solve_fp64_matches_oracle():
+    from oracle.solve import fgmres
+
+    c = hi.make_case("const128")
+    P, H = make_pair(c, "c128")
+    g = torch.as_tensor(c.g)
+    x_or, its_or, rr_or, ok = fgmres(P, g, tol=1e-6, maxit=300)
+    assert ok
+    u, its, rr, hist = H.solve(g.to("cuda:0"), tol=1e-6, maxit=300, mode=0)
+    H.close()
+    print("iterations gpu", its, "oracle", its_or, "relres", rr, rr_or)
+    assert rr < 1e-6
+    assert abs(its - its_or) <= 1
+    assert rel(u, x_or) < 1e-6
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_solve_fp32_cycles(mode):
+    """FP32 cycles inside FP64 FGMRES (mode 0) or FP64 iterative refinement (mode 1):
+    the true FP64 residual reaches 1e-6; the error against the FP64 oracle solution
+    is reported and bounded."""
+    from oracle.solve import fgmres
+
+    c = hi.make_case("const128")
+    P, H = make_pair(c, "c64")
+    g = torch.as_tensor(c.g)
+    x_or, its_or, rr_or, ok = fgmres(P, g, tol=1e-8, maxit=400)
+    u, its, rr, hist = H.solve(g.to("cuda:0"), tol=1e-6, maxit=400, mode=mode)
+    H.close()
+    err = rel(u, x_or)
+    print("mode", mode, "iterations", its, "relres", rr, "error vs oracle", err)
+    assert rr < 1e-6
+    assert err < 1e-4
+
+
+def test_cycle_before_phase_is_state_error():
+    from paper_2404_02493_amd import Helmholtz, HelmError
+
+    c = hi.make_problem(32, 10.0, 3, seed=1, damping_cells=4)
+    H = Helmholtz(c.velocity, c.k, levels=3, damping_cells=4)
+    g = torch.as_tensor(c.g).to("cuda:0")
+    u = torch.zeros_like(g)
+    with pytest.raises(HelmError) as e:
+        H.cycle(g, u)
+    assert e.value.status == 6
+    H.close()
