@@ -1,0 +1,200 @@
+"""Benchmark: time to a 1e-6 relative residual on the 4096 x 4096, k = 2100 layered
+medium (8 layers + 20 elliptical inclusions, fast-marching phase, 7 levels), FP32
+cycles inside FP64 iterative refinement, with the plain FP64 GPU solve beside it.
+
+One "step" is one full solve from a zero initial guess (all parts of the path:
+cycles, Krylov, FP64 residual and refinement), inputs resident in HBM.  Prints
+one JSON line.  Extra fields: the FP64 solve, the per-kernel profile from HIP
+events (with the algorithmic bytes of each launch), the roofline of the
+dominant kernel, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(case, iterations: int, budget_s: float = 30.0):
+    """The FP64 CPU oracle on a bounded sample of the same workload: one FGMRES
+    iteration (one cycle from a zero iterate, A z and one Arnoldi step) at full
+    size, extrapolated to the iteration count of the FP64 GPU solve."""
+    import torch
+
+    from oracle.cycle import Problem, cycle
+    from oracle.grid import apply_A, cdot, cnorm
+
+    threads = os.cpu_count() or 1
+    torch.set_num_threads(threads)
+    P = Problem(case.velocity, case.k, case.levels, damping_cells=case.damping_cells, phi=case.phi)
+    g = torch.as_tensor(case.g)
+    t0 = time.perf_counter()
+    v = g / cnorm(g)
+    z = cycle(P, v, torch.zeros_like(v))
+    w = apply_A(z, P.kappa[1], P.h[1])
+    h = cdot(v, w)
+    w = w - h * v
+    _ = cnorm(w)
+    t_iter = time.perf_counter() - t0
+    return {"value": t_iter * iterations, "unit": "s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"one FP64 FGMRES iteration (cycle + A z + Arnoldi step) at {case.n}x{case.n}, "
+                      f"{t_iter:.2f} s, times {iterations} iterations of the FP64 solve",
+            "sample_seconds": t_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="layered4096")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--maxit", type=int, default=3000)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: the solver has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import helm_inputs as hi
+    from paper_2404_02493_amd import Helmholtz
+
+    dev = "cuda:0"
+    log(f"generating workload {args.workload} seed {args.seed}")
+    t = time.perf_counter()
+    case = hi.make_case(args.workload, seed=args.seed)
+    log(f"inputs ready in {time.perf_counter() - t:.1f} s (n={case.n}, k={case.k}, L={case.levels})")
+    g = torch.as_tensor(case.g).to(dev)
+
+    log("setup FP32-cycle context")
+    H32 = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells)
+    H32.set_phase(case.phi)
+
+    def run32():
+        u = torch.zeros_like(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, its, rr, _ = H32.solve(g, u, tol=args.tol, maxit=args.maxit, mode=1)
+        torch.cuda.synchronize()
+        return u, its, rr, time.perf_counter() - t0
+
+    for w in range(args.warmup):
+        _, its, rr, dt = run32()
+        log(f"warmup {w}: FP32+refinement {its} iterations, relres {rr:.2e}, {dt:.3f} s")
+    times, iters = [], []
+    torch.cuda.synchronize()
+    for s in range(args.steps):
+        u32, its, rr32, dt = run32()
+        times.append(dt)
+        iters.append(its)
+        log(f"step {s}: FP32+refinement {its} iterations, relres {rr32:.2e}, {dt:.3f} s")
+    t32 = float(np.mean(times))
+
+    prof32 = None
+    if not args.no_profile:
+        H32.profile_begin()
+        _, its_p, _, dtp = run32()
+        prof32 = H32.profile_end()
+        log(f"profiled FP32 step: {dtp:.3f} s")
+
+    fp64 = None
+    prof64 = None
+    if not args.no_fp64:
+        log("setup FP64 context")
+        H64 = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c128",
+                        damping_cells=case.damping_cells)
+        H64.set_phase(case.phi)
+        u64 = torch.zeros_like(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u64, its64, rr64, _ = H64.solve(g, u64, tol=args.tol, maxit=args.maxit, mode=0)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        diff = (torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)).item()
+        log(f"FP64 solve: {its64} iterations, relres {rr64:.2e}, {t64:.3f} s; |u32-u64|/|u64| = {diff:.2e}")
+        fp64 = {"seconds": t64, "iterations": its64, "relres": rr64, "rel_diff_fp32_vs_fp64": diff}
+        if not args.no_profile:
+            H64.profile_begin()
+            u64b = torch.zeros_like(g)
+            H64.solve(g, u64b, tol=args.tol, maxit=args.maxit, mode=0)
+            prof64 = H64.profile_end()
+        H64.close()
+
+    roofline = None
+    summary = {}
+    if prof32:
+        ks = prof32["kernels"]
+        tot_ms = sum(k["ms"] for k in ks)
+        tot_bytes = sum(k["bytes"] for k in ks)
+        top = ks[0]
+        achieved = top["bytes"] / (top["ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": top["name"], "launches": top["launches"],
+                    "avg_launch_us": round(1e3 * top["ms"] / top["launches"], 2),
+                    "bytes_per_launch": top["bytes"] / top["launches"]}
+        summary = {"kernel_ms_total": round(tot_ms, 3), "algorithmic_GB": round(tot_bytes / 1e9, 3),
+                   "effective_GBs_in_kernels": round(tot_bytes / (tot_ms * 1e-3) / 1e9, 1),
+                   "top_kernels": [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),
+                                    "GBs": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)} for k in ks[:8]]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on one FP64 FGMRES iteration")
+        cpu = cpu_baseline(case, fp64["iterations"] if fp64 else int(np.mean(iters)))
+        log(f"CPU oracle sample {cpu['sample_seconds']:.1f} s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "time to 1e-6 rel. residual + HBM GB/s, 4096^2 k~2100, FP32+refine vs FP64",
+        "value": round(t32, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t32, 2),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": case.n, "k": case.k, "levels": case.levels,
+                   "seed": args.seed, "medium": case.meta["medium"], "phase": "first-order fast marching",
+                   "solver": "FP64 iterative refinement around FP32 FGMRES(20), FP32 Wave-ADR cycles (coarsest FP64)",
+                   "adr_steps": 8, "tol": args.tol},
+        "iterations": int(np.mean(iters)),
+        "relres": rr32,
+        "fp64": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "profile_fp32": summary,
+    }
+    if prof64:
+        ks = prof64["kernels"]
+        out["profile_fp64"] = {"kernel_ms_total": round(sum(k["ms"] for k in ks), 3),
+                               "top_kernels": [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),
+                                                "GBs": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)}
+                                               for k in ks[:5]]}
+    print(json.dumps(out), flush=True)
+    H32.close()
+
+
+if __name__ == "__main__":
+    main()

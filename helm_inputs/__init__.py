@@ -101,10 +101,12 @@ def grf_velocity(rng: np.random.Generator, n: int, corr_len: float = 0.1,
 
 
 def layered_velocity(rng: np.random.Generator, n: int, nlayers: int = 8, nellipses: int = 20,
-                     cmin: float = 1.5, cmax: float = 4.5, contrast: float = 0.3) -> np.ndarray:
+                     cmin: float = 1.5, cmax: float = 4.5, contrast: float = 0.3,
+                     smooth: float = 0.0) -> np.ndarray:
     """Horizontal layers (sorted uniform interface depths, per-layer speed
     U[cmin, cmax]) plus elliptical inclusions multiplying the speed by
-    (1 +/- contrast), applied in order; no smoothing."""
+    (1 +/- contrast), applied in order; then, if smooth > 0, a Gaussian filter of
+    standard deviation ``smooth`` (physical units, nearest-value boundaries)."""
     h = 1.0 / n
     depths = np.sort(rng.uniform(0.0, 1.0, size=nlayers - 1))
     speeds = rng.uniform(cmin, cmax, size=nlayers)
@@ -122,6 +124,10 @@ def layered_velocity(rng: np.random.Generator, n: int, nlayers: int = 8, nellips
         v = -dx * np.sin(th) + dy * np.cos(th)
         inside = (u / a) ** 2 + (v / b) ** 2 <= 1.0
         c = np.where(inside, c * (1.0 + sign * contrast), c)
+    if smooth > 0.0:
+        from scipy.ndimage import gaussian_filter
+
+        c = gaussian_filter(c, smooth * n, mode="nearest")
     return c
 
 
@@ -176,27 +182,39 @@ CONFIGS = {
     "grf512": dict(n=512, k=320.0, levels=6, medium="grf", nsrc=(1, 1), phase="fmm"),
     # differentiation workload, 1024 x 1024, k = 640, float32 phase
     "grf1024": dict(n=1024, k=640.0, levels=7, medium="grf", nsrc=(1, 1), phase="fmm32"),
-    # layered + inclusions, 4096 x 4096, k = 2100
-    "layered4096": dict(n=4096, k=2100.0, levels=7, medium="layered", nsrc=(1, 1), phase="fmm"),
+    # layered + inclusions smoothed over about one wavelength, 4096 x 4096, k = 2100
+    "layered4096": dict(n=4096, k=2100.0, levels=7, medium="layered", nsrc=(1, 1), phase="fmm", smooth=0.01),
+    # the same model without smoothing (sharp interfaces)
+    "layered4096_sharp": dict(n=4096, k=2100.0, levels=7, medium="layered", nsrc=(1, 1), phase="fmm"),
 }
 
 
+def sponge_cells(n: int, k: float, cmax: float, minimum: int = 16) -> int:
+    """Sponge width in fine cells: one wavelength 2 pi c_max / k at the largest wave
+    speed of the medium (the usual thickness of the damping layer), at least 16."""
+    return int(max(minimum, int(np.ceil(2.0 * np.pi * cmax * n / k))))
+
+
 def make_problem(n: int, k: float, levels: int, seed: int, medium: str = "const",
-                 nsrc=(1, 1), phase: str = "analytic", damping_cells: int = 16,
-                 name: str = "custom") -> Case:
+                 nsrc=(1, 1), phase: str = "analytic", damping_cells=None,
+                 name: str = "custom", smooth: float = 0.0) -> Case:
     """Build one seeded problem.  medium in {const, grf, layered};
-    phase in {analytic, fmm, fmm32}; nsrc = (min, max) number of sources."""
+    phase in {analytic, fmm, fmm32}; nsrc = (min, max) number of sources;
+    damping_cells None = one wavelength at the top speed, at least 16."""
     rng = _rng(seed)
     count = int(rng.integers(nsrc[0], nsrc[1] + 1))
-    xy = _source_positions(rng, n, count, damping_cells + 4)
     if medium == "const":
         vel = np.ones((n, n))
     elif medium == "grf":
         vel = grf_velocity(rng, n)
     elif medium == "layered":
-        vel = layered_velocity(rng, n)
+        vel = layered_velocity(rng, n, smooth=smooth)
     else:
         raise ValueError(medium)
+    if damping_cells is None:
+        damping_cells = sponge_cells(n, k, float(vel.max()))
+    # sources at least 4 cells inside the sponge-free region
+    xy = _source_positions(rng, n, count, damping_cells + 4)
     g = gaussian_sources(n, xy)
     if phase == "analytic":
         if medium != "const":
@@ -210,7 +228,7 @@ def make_problem(n: int, k: float, levels: int, seed: int, medium: str = "const"
         raise ValueError(phase)
     return Case(name=name, n=n, k=float(k), levels=int(levels), damping_cells=damping_cells,
                 velocity=np.ascontiguousarray(vel, dtype=np.float64), g=g, phi=phi, sources=xy,
-                meta=dict(seed=seed, medium=medium, phase=phase))
+                meta=dict(seed=seed, medium=medium, phase=phase, smooth=smooth))
 
 
 def make_case(name: str, seed: int = 0) -> Case:

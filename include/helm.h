@@ -71,11 +71,15 @@ typedef struct {
     int32_t gmres_coarse_m;   /* GMRES(m) on the coarsest ADR level (default 10) */
     int32_t level3_literal;   /* 0: no smoothing on level 3 (default); 1: Chebyshev post-smoother there */
     int32_t restart;          /* FGMRES restart length (default 20, at most 24) */
+    int32_t gmres_arnoldi;    /* 0 (default): GMRES(m <= 4) smoother in s-step form (Krylov basis
+                                 rebuilt on tiles, Gram least squares); 1: always Arnoldi */
+    int32_t use_graphs;       /* 1 (default): each cycle is captured once per (g, u) pointer pair as a
+                                 HIP graph and replayed; 0: kernels are launched one by one */
 } helm_desc;
 
 /* Defaults of every field for an n x n grid at frequency k:
  * levels = min(7, log2 n - 3) (at least 2), W = 16, strength 0.5, sign +1, C128,
- * M = 8, Chebyshev 5/5/10, GMRES 3/10, restart 20. */
+ * M = 8, Chebyshev 5/5/10, GMRES 3/10 (s-step form), restart 20, graphs on. */
 void helm_desc_default(helm_desc* d, int32_t n, double k);
 
 /* Setup phase (paper Figure "cycle": the solver's setup/solve split).
@@ -147,6 +151,16 @@ helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const vo
  * Arrays are device memory in cycle_prec (level L arrays are complex128). */
 helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* in, const void* in2,
                           void* out, void* stream);
+
+/* Per-launch kernel timing for measurement (not for use under graph capture).
+ * helm_profile_begin starts recording a HIP event pair around every kernel launch
+ * of the cycle and solve paths; helm_profile_end synchronises, stops recording and
+ * writes a JSON summary into json (host, cap bytes):
+ *   {"kernels": [{"name", "launches", "ms" (summed event time), "bytes"
+ *                 (algorithmic bytes: each input read once, each output written once)}]}
+ * sorted by time.  Returns HELM_EINVAL if cap is too small. */
+helm_status helm_profile_begin(helm_ctx ctx);
+helm_status helm_profile_end(helm_ctx ctx, char* json, int64_t cap);
 
 /* Frees every workspace; NULL-safe; the context must not be used afterwards. */
 helm_status helm_destroy(helm_ctx ctx);

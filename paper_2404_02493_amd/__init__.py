@@ -163,6 +163,16 @@ class Helmholtz:
         check(lib().helm_debug_op(self._ctx, int(op), int(level), _ptr(x), _ptr(x2), _ptr(out), _stream_ptr(stream)))
         return out
 
+    def profile_begin(self):
+        check(lib().helm_profile_begin(self._ctx))
+
+    def profile_end(self) -> dict:
+        import json
+
+        buf = ctypes.create_string_buffer(1 << 20)
+        check(lib().helm_profile_end(self._ctx, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
     def level_dtype(self, level: int):
         torch = _torch()
         if level == self.levels:

@@ -16,7 +16,7 @@ STATUS = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP", 4: "
 # every symbol declared in include/helm.h
 EXPORTS = ["helm_desc_default", "helm_setup", "helm_set_phase", "helm_set_weights", "helm_get_weights",
            "helm_get_lambdas", "helm_cycle", "helm_solve", "helm_residual", "helm_cycle_backward",
-           "helm_debug_op", "helm_destroy", "helm_status_string", "helm_last_error", "helm_version"]
+           "helm_debug_op", "helm_profile_begin", "helm_profile_end", "helm_destroy", "helm_status_string", "helm_last_error", "helm_version"]
 
 
 class HelmDesc(ctypes.Structure):
@@ -36,6 +36,8 @@ class HelmDesc(ctypes.Structure):
         ("gmres_coarse_m", ctypes.c_int32),
         ("level3_literal", ctypes.c_int32),
         ("restart", ctypes.c_int32),
+        ("gmres_arnoldi", ctypes.c_int32),
+        ("use_graphs", ctypes.c_int32),
     ]
 
 
@@ -85,6 +87,10 @@ def lib():
     L.helm_cycle_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.helm_debug_op.restype = i32
     L.helm_debug_op.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.helm_profile_begin.restype = i32
+    L.helm_profile_begin.argtypes = [vp]
+    L.helm_profile_end.restype = i32
+    L.helm_profile_end.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
     L.helm_destroy.restype = i32
     L.helm_destroy.argtypes = [vp]
     L.helm_status_string.restype = ctypes.c_char_p

@@ -113,9 +113,5 @@ struct KrylovScal {
     int pad;
 };
 
-// Reduction tickets (one per kernel family use; reset by the last block).
-struct Tickets {
-    unsigned int t[4];
-};
 
 }  // namespace helm

@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "../../include/helm.h"
-#include "kernels_krylov.hpp"
+#include "kernels_sstep.hpp"
 
 namespace helm {
 
@@ -60,6 +60,7 @@ struct AdrLevel {
     void* c0 = nullptr;
     void* b = nullptr;
     void* x = nullptr;
+    void* xalt = nullptr;  // second iterate for out-of-place s-step updates
     void* V[MAXM + 1] = {};
     KrylovScal* K = nullptr;
 };
@@ -79,7 +80,6 @@ struct helm_ctx_s {
     std::vector<double> w, w_default;
     void* ws1 = nullptr;     // second level-1 iterate (cycle precision)
     double* partials = nullptr;
-    unsigned int* ticket = nullptr;
     double* dscal = nullptr;  // small device scratch (norms)
     helm::KrylovScal* Kout = nullptr;
     helm::KrylovScal* Kin = nullptr;
@@ -94,7 +94,51 @@ struct helm_ctx_s {
     void* dbuf = nullptr;    // inner correction (mode 1)
     void* ckpt = nullptr;
     size_t ckpt_bytes = 0;
+    // captured cycles, keyed by the (g, u_in, u_out) pointers they were captured with
+    struct GraphEntry {
+        const void* g;
+        const void* uin;
+        void* uout;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;  // library-owned stream used only for capture
+    // per-launch timing with HIP events and the algorithmic bytes of each launch
+    struct Prof {
+        struct Rec {
+            const char* name;
+            int grid;
+            double bytes;
+            hipEvent_t e0, e1;
+        };
+        bool on = false;
+        std::vector<Rec> recs;
+        std::vector<hipEvent_t> pool;
+        size_t used = 0;
+        hipEvent_t next(hipStream_t st) {
+            if (used == pool.size()) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return nullptr;
+                pool.push_back(e);
+            }
+            hipEvent_t e = pool[used++];
+            (void)hipEventRecord(e, st);
+            return e;
+        }
+    } prof;
 };
+
+// Launch with optional per-launch event timing (name = kernel expression).
+#define LAUNCH(CTX, BYTES, KERN, GRID, BLK, ST, ...)                                    \
+    do {                                                                                \
+        hipEvent_t e0_ = nullptr;                                                       \
+        if ((CTX)->prof.on) e0_ = (CTX)->prof.next(ST);                                 \
+        hipLaunchKernelGGL(KERN, GRID, BLK, 0, ST, __VA_ARGS__);                        \
+        if ((CTX)->prof.on && e0_) {                                                    \
+            hipEvent_t e1_ = (CTX)->prof.next(ST);                                      \
+            (CTX)->prof.recs.push_back({#KERN, (int)dim3(GRID).x, (double)(BYTES), e0_, e1_}); \
+        }                                                                               \
+    } while (0)
 
 namespace helm {
 
@@ -137,6 +181,8 @@ static AdrGeom make_adr_geom(const helm_ctx c, int level) {
     return A;
 }
 
+static inline double NN(int n) { return double(n) * double(n); }
+
 static size_t csize(bool f64) { return f64 ? sizeof(c128) : sizeof(c64); }
 static size_t rsize(bool f64) { return f64 ? sizeof(double) : sizeof(float); }
 
@@ -168,6 +214,18 @@ static double median_alpha(double k, double n2mean, int nl, double lam) {
     return std::max(1.0, lam / med);
 }
 
+// ------------------------------------------------------------------ Krylov finalize helper
+template <int NV>
+static void krylov_fin(helm_ctx c, hipStream_t st, int nblk, int op, int jj, int m, KrylovScal* K, double tol) {
+    if (op == FIN_INIT || op == FIN_ORTH2) {
+        LAUNCH(c, 8.0 * nblk, (k_krylov_finalize<2>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nblk, op,
+               jj, m, K, tol);
+    } else {
+        LAUNCH(c, 16.0 * nblk * (jj + 1), (k_krylov_finalize<2 * NV + 2>), dim3(1), dim3(FBLOCK), st,
+               (const double*)c->partials, nblk, op, jj, m, K, tol);
+    }
+}
+
 // ------------------------------------------------------------------ engine
 template <typename T>
 struct Engine {
@@ -185,17 +243,17 @@ struct Engine {
     // ---- generic launches on a level of precision P
     template <typename P>
     void residual(const Geom& G, const void* n2, const void* g, const void* u, void* r) {
-        hipLaunchKernelGGL((k_residual<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const P*)n2,
+        LAUNCH(c, ((u ? 3 : 2) * sizeof(cplx<P>) + (u ? sizeof(P) : 0)) * NN(G.n), (k_residual<P>), dim3(tiles_of(G.n)), tile_block(), st, G, (const P*)n2,
                            (const cplx<P>*)g, (const cplx<P>*)u, (cplx<P>*)r);
     }
     template <typename P>
     void applyA(const Geom& G, const void* n2, const void* x, void* y, int conj_k) {
-        hipLaunchKernelGGL((k_apply_A<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const P*)n2,
+        LAUNCH(c, (2 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_apply_A<P>), dim3(tiles_of(G.n)), tile_block(), st, G, (const P*)n2,
                            (const cplx<P>*)x, (cplx<P>*)y, conj_k);
     }
     template <typename P>
     void zero(void* y, size_t n) {
-        hipLaunchKernelGGL((k_zero<P>), dim3(flat_blocks(n)), dim3(BLOCK), 0, st, n, (cplx<P>*)y);
+        LAUNCH(c, sizeof(cplx<P>) * double(n), (k_zero<P>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, (cplx<P>*)y);
     }
 
     template <typename P>
@@ -213,7 +271,7 @@ struct Engine {
             residual<P>(G, W.n2, g, u, W.t);
             t0 = W.t;
         }
-        hipLaunchKernelGGL((k_cheb_start<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const P*)W.n2,
+        LAUNCH(c, (3 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start<P>), dim3(tiles_of(G.n)), tile_block(), st, G, (const P*)W.n2,
                            (const cplx<P>*)t0, (cplx<P>*)W.r, (cplx<P>*)W.d, P(1.0 / theta));
         double rho = dc / theta;
         for (int step = 1; step <= m; ++step) {
@@ -222,12 +280,12 @@ struct Engine {
                 const double den = 2.0 * theta - dc * rho;
                 const double rho_new = dc / den;
                 const double c1 = rho_new * rho, c2 = 2.0 / den;
-                hipLaunchKernelGGL((k_cheb_step<P>), dim3(tiles_of(G.n)), tile_block(), 0, st, G,
+                LAUNCH(c, (7 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_step<P>), dim3(tiles_of(G.n)), tile_block(), st, G,
                                    (const P*)W.n2, (const cplx<P>*)W.t, (cplx<P>*)W.r, (cplx<P>*)W.d,
                                    (cplx<P>*)u, P(c1), P(c2));
                 rho = rho_new;
             } else {
-                hipLaunchKernelGGL((k_axpy<P>), dim3(flat_blocks(n)), dim3(BLOCK), 0, st, n, P(1),
+                LAUNCH(c, 3 * sizeof(cplx<P>) * double(n), (k_axpy<P>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, P(1),
                                    (const cplx<P>*)W.d, (cplx<P>*)u);
             }
         }
@@ -237,13 +295,13 @@ struct Engine {
     template <typename Pf, typename Pc>
     void resid_restrict(int l, const void* g, const void* u, void* rc) {
         const Geom& G = c->wl[l].G;
-        hipLaunchKernelGGL((k_resid_restrict<Pf, Pc>), dim3(tiles_of(G.n / 2)), tile_block(), 0, st, G,
+        LAUNCH(c, (u ? 2 * sizeof(cplx<Pf>) + sizeof(Pf) : sizeof(cplx<Pf>)) * NN(G.n) + sizeof(cplx<Pc>) * NN(G.n / 2), (k_resid_restrict<Pf, Pc>), dim3(tiles_of(G.n / 2)), tile_block(), st, G,
                            (const Pf*)c->wl[l].n2, (const cplx<Pf>*)g, (const cplx<Pf>*)u, (cplx<Pc>*)rc);
     }
     template <typename Pc, typename Pf>
     void prolong_add(int l, const void* ec, void* u) {
         const int n = c->wl[l].n;
-        hipLaunchKernelGGL((k_prolong_add<Pc, Pf>), dim3(tiles_of(n)), tile_block(), 0, st, n,
+        LAUNCH(c, 2 * sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * NN(n / 2), (k_prolong_add<Pc, Pf>), dim3(tiles_of(n)), tile_block(), st, n,
                            (const cplx<Pc>*)ec, (cplx<Pf>*)u);
     }
 
@@ -301,12 +359,12 @@ struct Engine {
         WaveLevel& W = c->wl[1];
         const Geom& G = W.G;
         const T w0 = T(c->w[0]);
-        hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const T*)W.n2,
+        LAUNCH(c, ((u_in ? 3 : 2) * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2,
                            (const C*)g, (const C*)u_in, (C*)c->ws1, w0);
         restrict_down(1, g, c->ws1, c->wl[2].g);
         cycle_coarse(2);
         prolong_up(1, c->wl[2].u, c->ws1);
-        hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const T*)W.n2,
+        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2,
                            (const C*)g, (const C*)c->ws1, (C*)u_out, w0);
     }
 
@@ -314,10 +372,10 @@ struct Engine {
     void adr_step() {
         WaveLevel& W = c->wl[2];
         AdrLevel& A = c->al[2];
-        hipLaunchKernelGGL((k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), 0, st, W.G, (const T*)W.n2,
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st, W.G, (const T*)W.n2,
                            (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
         adr_vcycle(2);
-        hipLaunchKernelGGL((k_adr_modadd<T>), dim3(flat_blocks(N(2))), dim3(BLOCK), 0, st, N(2), (const C*)A.x,
+        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))), dim3(BLOCK), st, N(2), (const C*)A.x,
                            (const T*)c->theta2, (C*)W.u);
     }
 
@@ -328,11 +386,11 @@ struct Engine {
             return;
         }
         gmres(l, c->d.gmres_m, true);
-        hipLaunchKernelGGL((k_adr_resid_restrict<T>), dim3(tiles_of(A.n / 2)), tile_block(), 0, st, A.A,
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>), dim3(tiles_of(A.n / 2)), tile_block(), st, A.A,
                            (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
                            (C*)c->al[l + 1].b);
         adr_vcycle(l + 1);
-        hipLaunchKernelGGL((k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.n,
+        LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), st, A.n,
                            (const C*)c->al[l + 1].x, (C*)A.x);
         gmres(l, c->d.gmres_m, false);
     }
@@ -344,27 +402,70 @@ struct Engine {
         VecSet<T> V{};
         V.v[0] = (const C*)(x0_zero ? A.b : A.V[0]);
         for (int i = 1; i <= m; ++i) V.v[i] = (const C*)A.V[i];
+        const int nbf = flat_blocks(n, MAXRED), nbt = red_blocks(A.n);
         if (x0_zero) {
-            hipLaunchKernelGGL((k_krylov_init_norm<T>), dim3(flat_blocks(n, 1024)), dim3(BLOCK), 0, st, n,
-                               (const C*)A.b, A.K, m, c->partials, c->ticket);
+            LAUNCH(c, sizeof(C) * double(n), (k_krylov_init_norm<T>), dim3(nbf), dim3(BLOCK), st, n, (const C*)A.b,
+                   c->partials);
+            krylov_fin<NV>(c, st, nbf, FIN_INIT, 0, m, A.K, 0.0);
         } else {
-            hipLaunchKernelGGL((k_adr_residual_init<T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
-                               (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
-                               (C*)A.V[0], A.K, m, c->partials, c->ticket);
+            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_adr_residual_init<T>), dim3(nbt), tile_block(), st,
+                   A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x, (C*)A.V[0],
+                   c->partials);
+            krylov_fin<NV>(c, st, nbt, FIN_INIT, 0, m, A.K, 0.0);
         }
         for (int j = 0; j < m; ++j) {
-            hipLaunchKernelGGL((k_arnoldi_adr<T, NV>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
-                               (const T*)A.px, (const T*)A.py, (const C*)A.c0, V, j, (C*)A.V[j + 1], A.K,
-                               c->partials, c->ticket);
-            hipLaunchKernelGGL((k_orth_pass1<T, NV>), dim3(flat_blocks(n, 1024)), dim3(BLOCK), 0, st, n, V, j,
-                               (C*)A.V[j + 1], A.K, c->partials, c->ticket);
-            hipLaunchKernelGGL((k_orth_pass2<T, NV>), dim3(flat_blocks(n, 1024)), dim3(BLOCK), 0, st, n, V, j,
-                               (C*)A.V[j + 1], A.K, 1e-14, c->partials, c->ticket);
+            LAUNCH(c, ((j + 3) * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_arnoldi_adr<T, NV>), dim3(nbt), tile_block(),
+                   st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, V, j, (C*)A.V[j + 1],
+                   (const KrylovScal*)A.K, c->partials);
+            krylov_fin<NV>(c, st, nbt, FIN_MV, j, m, A.K, 0.0);
+            LAUNCH(c, (j + 3) * sizeof(C) * double(n), (k_orth_pass1<T, NV>), dim3(nbf), dim3(BLOCK), st, n, V, j,
+                   (C*)A.V[j + 1], (const KrylovScal*)A.K, c->partials);
+            krylov_fin<NV>(c, st, nbf, FIN_ORTH1, j, m, A.K, 0.0);
+            LAUNCH(c, (j + 3) * sizeof(C) * double(n), (k_orth_pass2<T, NV>), dim3(nbf), dim3(BLOCK), st, n, V, j,
+                   (C*)A.V[j + 1], (const KrylovScal*)A.K, c->partials);
+            krylov_fin<NV>(c, st, nbf, FIN_ORTH2, j, m, A.K, 1e-14);
         }
-        hipLaunchKernelGGL((k_krylov_combine<T, NV>), dim3(flat_blocks(n)), dim3(BLOCK), 0, st, n, V,
+        LAUNCH(c, (m + 1 + (x0_zero ? 0 : 1)) * sizeof(C) * double(n), (k_krylov_combine<T, NV>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, V,
                            (const KrylovScal*)A.K, (const C*)(x0_zero ? nullptr : A.x), (C*)A.x);
     }
+    template <int MM>
+    void gmres_sstep(int l, bool x0_zero) {
+        AdrLevel& A = c->al[l];
+        const int nb = tiles_of(A.n), nbr = red_blocks(A.n);
+        constexpr int NG = (MM + 1) * (MM + 1);
+        const double bx = x0_zero ? 0.0 : 1.0;
+        if (x0_zero) {
+            LAUNCH(c, (sizeof(C) + 2 * sizeof(T) + sizeof(C)) * NN(A.n), (k_sstep_gram<T, MM, false>), dim3(nbr),
+                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)nullptr, c->partials);
+        } else {
+            LAUNCH(c, ((2 + bx) * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_gram<T, MM, true>), dim3(nbr),
+                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)A.x, c->partials);
+        }
+        LAUNCH(c, 8.0 * NG * nbr, (k_sstep_solve<MM>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nbr,
+               A.K, 1e-12);
+        if (x0_zero) {
+            LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false>), dim3(nb),
+                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)nullptr, (const KrylovScal*)A.K, (C*)A.x);
+        } else {
+            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true>), dim3(nb),
+                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)A.x, (const KrylovScal*)A.K, (C*)A.xalt);
+            std::swap(A.x, A.xalt);
+        }
+    }
+
     void gmres(int l, int m, bool x0_zero) {
+        if (l < c->L && m <= 4 && !c->d.gmres_arnoldi) {
+            switch (m) {
+                case 1: gmres_sstep<1>(l, x0_zero); return;
+                case 2: gmres_sstep<2>(l, x0_zero); return;
+                case 3: gmres_sstep<3>(l, x0_zero); return;
+                default: gmres_sstep<4>(l, x0_zero); return;
+            }
+        }
         switch (nv_bucket(m)) {
             case 4: gmres_nv<4>(l, m, x0_zero); break;
             case 12: gmres_nv<12>(l, m, x0_zero); break;
@@ -404,8 +505,10 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     const Geom G = make_geom(c, 1);
     const size_t N = (size_t)G.n * G.n;
     // K init from V[0]
-    hipLaunchKernelGGL((k_krylov_init_norm<P>), dim3(flat_blocks(N, 1024)), dim3(BLOCK), 0, st, N, (const Cp*)V[0],
-                       K, m, c->partials, c->ticket);
+    const int nbf = flat_blocks(N, MAXRED), nbt = red_blocks(G.n);
+    LAUNCH(c, sizeof(Cp) * double(N), (k_krylov_init_norm<P>), dim3(nbf), dim3(BLOCK), st, N, (const Cp*)V[0],
+           c->partials);
+    krylov_fin<MAXM>(c, st, nbf, FIN_INIT, 0, m, K, 0.0);
     KrylovScal hk;
     HIPCHK(hipMemcpyAsync(&hk.beta, &K->beta, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -430,13 +533,16 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     std::vector<double> col(2 * (MAXM + 1));
     for (int j = 0; j < m && used < maxit_left; ++j) {
         prec(j, scale[j]);  // Z[j] = preconditioned V[j] (scaled by scale[j] if !z_scaled)
-        hipLaunchKernelGGL((k_arnoldi_helm<P, MAXM>), dim3(tiles_of(G.n)), tile_block(), 0, st, G,
-                           (const P*)n2_fine, (const Cp*)Z[j], z_scaled ? 0 : 1, Vs, j, (Cp*)V[j + 1], K,
-                           c->partials, c->ticket);
-        hipLaunchKernelGGL((k_orth_pass1<P, MAXM>), dim3(flat_blocks(N, 1024)), dim3(BLOCK), 0, st, N, Vs, j,
-                           (Cp*)V[j + 1], K, c->partials, c->ticket);
-        hipLaunchKernelGGL((k_orth_pass2<P, MAXM>), dim3(flat_blocks(N, 1024)), dim3(BLOCK), 0, st, N, Vs, j,
-                           (Cp*)V[j + 1], K, 0.0, c->partials, c->ticket);
+        LAUNCH(c, ((j + 3) * sizeof(Cp) + sizeof(P)) * double(N), (k_arnoldi_helm<P, MAXM>), dim3(nbt), tile_block(),
+               st, G, (const P*)n2_fine, (const Cp*)Z[j], z_scaled ? 0 : 1, Vs, j, (Cp*)V[j + 1],
+               (const KrylovScal*)K, c->partials);
+        krylov_fin<MAXM>(c, st, nbt, FIN_MV, j, m, K, 0.0);
+        LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass1<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,
+               (Cp*)V[j + 1], (const KrylovScal*)K, c->partials);
+        krylov_fin<MAXM>(c, st, nbf, FIN_ORTH1, j, m, K, 0.0);
+        LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass2<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,
+               (Cp*)V[j + 1], (const KrylovScal*)K, c->partials);
+        krylov_fin<MAXM>(c, st, nbf, FIN_ORTH2, j, m, K, 0.0);
         HIPCHK(hipMemcpyAsync(col.data(), K->H + 2 * (j * (MAXM + 1)), sizeof(double) * 2 * (j + 2),
                               hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -482,7 +588,7 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     HIPCHK(hipMemcpyAsync(K->y, ybuf.data(), sizeof(double) * 2 * MAXM, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(K->scale, zs.data(), sizeof(double) * (MAXM + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(&K->cols, &used, sizeof(int), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL((k_krylov_combine<P, MAXM>), dim3(flat_blocks(N)), dim3(BLOCK), 0, st, N, Zs,
+    LAUNCH(c, (used + 2) * sizeof(Cp) * double(N), (k_krylov_combine<P, MAXM>), dim3(flat_blocks(N)), dim3(BLOCK), st, N, Zs,
                        (const KrylovScal*)K, (const Cp*)x, (Cp*)x);
     HIPCHK(hipStreamSynchronize(st));
     *est_out = est;
@@ -491,8 +597,11 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
 
 static void residual_fp64(helm_ctx c, hipStream_t st, const void* g, const void* u, void* r, double* rn, double* gn) {
     const Geom G = make_geom(c, 1);
-    hipLaunchKernelGGL(k_residual_norms, dim3(tiles_of(G.n)), tile_block(), 0, st, G, (const double*)c->n2f,
-                       (const c128*)g, (const c128*)u, (c128*)r, c->partials, c->ticket, c->dscal);
+    const int nbt = red_blocks(G.n);
+    LAUNCH(c, (3 * 16.0 + 8.0 + (r ? 16.0 : 0.0)) * NN(G.n), k_residual_norms, dim3(nbt), tile_block(), st, G,
+           (const double*)c->n2f, (const c128*)g, (const c128*)u, (c128*)r, c->partials);
+    LAUNCH(c, 16.0 * nbt, (k_finalize_sums<2>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nbt, 2,
+           c->dscal);
     double h[2];
     HIPCHK(hipMemcpyAsync(h, c->dscal, sizeof(h), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -519,6 +628,8 @@ static void validate(const helm_desc* d) {
     REQUIRE(d->gmres_m >= 1 && d->gmres_m <= MAXM && d->gmres_coarse_m >= 1 && d->gmres_coarse_m <= MAXM,
             "GMRES dimensions must be in [1, 24]");
     REQUIRE(d->restart >= 1 && d->restart <= MAXM, "restart must be in [1, 24]");
+    REQUIRE(d->gmres_arnoldi == 0 || d->gmres_arnoldi == 1, "gmres_arnoldi must be 0 or 1");
+    REQUIRE(d->use_graphs == 0 || d->use_graphs == 1, "use_graphs must be 0 or 1");
 }
 
 static void build(helm_ctx c, const double* velocity, hipStream_t st) {
@@ -531,8 +642,6 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     // reduction scratch: enough partials for any tiled kernel on the fine grid
     const size_t maxblk = std::max<size_t>((size_t)tiles_of(n), 2048);
     c->partials = (double*)dalloc(c, maxblk * (2 * MAXM + 4) * sizeof(double));
-    c->ticket = (unsigned int*)dalloc(c, 256);
-    HIPCHK(hipMemsetAsync(c->ticket, 0, 256, st));
     c->dscal = (double*)dalloc(c, 64 * sizeof(double));
     c->Kout = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
     c->Kin = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
@@ -583,11 +692,17 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
                                1 << (l - 1), n, (const double*)c->n2f, tmp);
             n2d = tmp;
         }
-        hipLaunchKernelGGL(k_level_stats, dim3(flat_blocks(Nl, 1024)), dim3(BLOCK), 0, st, W.G, n2d, c->partials,
-                           c->ticket, c->dscal + 8);
-        double hs[3];
-        HIPCHK(hipMemcpyAsync(hs, c->dscal + 8, sizeof(hs), hipMemcpyDeviceToHost, st));
+        const int nbs = flat_blocks(Nl, 1024);
+        hipLaunchKernelGGL(k_level_stats, dim3(nbs), dim3(BLOCK), 0, st, W.G, n2d, c->partials);
+        std::vector<double> ps(3 * (size_t)nbs);
+        HIPCHK(hipMemcpyAsync(ps.data(), c->partials, ps.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        double hs[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < nbs; ++q) {
+            hs[0] = std::max(hs[0], ps[3 * q]);
+            hs[1] = std::max(hs[1], ps[3 * q + 1]);
+            hs[2] += ps[3 * q + 2];
+        }
         W.lam = (hs[0] + 4.0 * W.G.inv_h2) * (hs[0] + 4.0 * W.G.inv_h2);
         W.n2max = hs[1];
         W.n2mean = hs[2] / double((size_t)(W.n - 1) * (W.n - 1));
@@ -620,6 +735,7 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
             A.c0 = dalloc(c, Nl * csize(f64c));
             A.b = dalloc(c, Nl * csize(f64c));
             A.x = dalloc(c, Nl * csize(f64c));
+            A.xalt = dalloc(c, Nl * csize(f64c));
             const int m = (l == L) ? d.gmres_coarse_m : d.gmres_m;
             for (int i = 0; i <= m; ++i) A.V[i] = dalloc(c, Nl * csize(f64c));
             A.K = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
@@ -684,11 +800,51 @@ static void run_cycle(helm_ctx c, const void* g, const void* u_in, void* u_out, 
     E.cycle(g, u_in, u_out);
 }
 
-static void cycle_any(helm_ctx c, const void* g, const void* u_in, void* u_out, hipStream_t st) {
+static void cycle_eager(helm_ctx c, const void* g, const void* u_in, void* u_out, hipStream_t st) {
     if (c->f32)
         run_cycle<float>(c, g, u_in, u_out, st);
     else
         run_cycle<double>(c, g, u_in, u_out, st);
+}
+
+static void drop_graphs(helm_ctx c) {
+    for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
+    c->graphs.clear();
+}
+
+// One cycle: replays the graph captured for these pointers (capturing it on first
+// use), or launches eagerly when graphs are off or per-launch profiling is on.
+// The cycle's kernel arguments depend only on the pointers and the weights, so a
+// graph stays valid until the weights change (drop_graphs).
+static void cycle_any(helm_ctx c, const void* g, const void* u_in, void* u_out, hipStream_t st) {
+    if (!c->d.use_graphs || c->prof.on) {
+        cycle_eager(c, g, u_in, u_out, st);
+        return;
+    }
+    for (auto& e : c->graphs) {
+        if (e.g == g && e.uin == u_in && e.uout == u_out) {
+            HIPCHK(hipGraphLaunch(e.exec, st));
+            return;
+        }
+    }
+    if (c->graphs.size() >= 64) drop_graphs(c);
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        cycle_eager(c, g, u_in, u_out, c->cap_stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(c->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+    c->graphs.push_back({g, u_in, u_out, exec});
+    HIPCHK(hipGraphLaunch(exec, st));
 }
 
 // ------------------------------------------------------------------ solve
@@ -700,7 +856,7 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
     std::vector<double> hist;
     int its = 0;
     if (!(gn > 0.0)) {
-        hipLaunchKernelGGL((k_zero<double>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF, (c128*)u);
+        LAUNCH(c, 16.0 * double(NF), (k_zero<double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF, (c128*)u);
         HIPCHK(hipStreamSynchronize(st));
         *iters = 0;
         *relres = 0.0;
@@ -715,10 +871,10 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
             bool bd = false;
             auto prec = [&](int j, double s) {
                 if (c->f32) {
-                    hipLaunchKernelGGL((k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+                    LAUNCH(c, 24.0 * double(NF), (k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
                                        (const c128*)c->fV[j], (c64*)c->cyc_g, s);
                     cycle_any(c, c->cyc_g, nullptr, c->cyc_u, st);
-                    hipLaunchKernelGGL((k_cast_scale<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+                    LAUNCH(c, 24.0 * double(NF), (k_cast_scale<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
                                        (const c64*)c->cyc_u, (c128*)c->fZ[j], 1.0);
                 } else {
                     cycle_any(c, c->fV[j], nullptr, c->fZ[j], st);
@@ -742,9 +898,9 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
         const double eta = 1e-4;
         while (!converged && its < maxit) {
             // inner right-hand side r / ||r|| in complex64 (fV[0] holds r)
-            hipLaunchKernelGGL((k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+            LAUNCH(c, 24.0 * double(NF), (k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
                                (const c128*)c->fV[0], (c64*)c->iV[0], 1.0 / rn);
-            hipLaunchKernelGGL((k_zero<float>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF, (c64*)c->dbuf);
+            LAUNCH(c, 8.0 * double(NF), (k_zero<float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF, (c64*)c->dbuf);
             auto prec = [&](int j, double s) { cycle_any(c, c->iV[j], nullptr, c->iZ[j], st); (void)s; };
             double est = 0;
             bool bd = false;
@@ -752,7 +908,7 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
             int used = fgmres_cycle<float>(c, st, c->wl[1].n2, c->iV, c->iZ, c->Kin, false, c->dbuf, 1.0, target,
                                            maxit - its, prec, nullptr, &est, &bd);
             its += used;
-            hipLaunchKernelGGL((k_add_cast<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF,
+            LAUNCH(c, 40.0 * double(NF), (k_add_cast<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
                                (const c64*)c->dbuf, (c128*)u, rn);
             residual_fp64(c, st, g, u, c->fV[0], &rn, &gn);
             hist.push_back(rn / gn);
@@ -818,6 +974,8 @@ void helm_desc_default(helm_desc* d, int32_t n, double k) {
     d->gmres_coarse_m = 10;
     d->level3_literal = 0;
     d->restart = 20;
+    d->gmres_arnoldi = 0;
+    d->use_graphs = 1;
 }
 
 helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* out, void* stream) {
@@ -854,6 +1012,7 @@ helm_status helm_set_weights(helm_ctx ctx, const double* w) {
             if (l >= 1) REQUIRE(w[l] >= 1.0, "Chebyshev alpha must be >= 1");
         }
         ctx->w.assign(w, w + ctx->L);
+        drop_graphs(ctx);
         return HELM_OK;
     })
 }
@@ -1044,8 +1203,67 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
     })
 }
 
+helm_status helm_profile_begin(helm_ctx ctx) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr, "NULL argument");
+        ctx->prof.recs.clear();
+        ctx->prof.used = 0;
+        ctx->prof.on = true;
+        return HELM_OK;
+    })
+}
+
+helm_status helm_profile_end(helm_ctx ctx, char* json, int64_t cap) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && json != nullptr && cap > 0, "NULL argument");
+        auto& P = ctx->prof;
+        P.on = false;
+        if (!P.recs.empty()) HIPCHK(hipEventSynchronize(P.recs.back().e1));
+        struct Agg {
+            std::string name;
+            long launches = 0;
+            double ms = 0, bytes = 0;
+        };
+        std::vector<Agg> agg;
+        for (auto& r : P.recs) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+            std::string key = std::string(r.name) + " [" + std::to_string(r.grid) + " blocks]";
+            auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg& a) { return a.name == key; });
+            if (it == agg.end()) {
+                agg.push_back(Agg{key});
+                it = agg.end() - 1;
+            }
+            it->launches += 1;
+            it->ms += ms;
+            it->bytes += r.bytes;
+        }
+        std::sort(agg.begin(), agg.end(), [](const Agg& a, const Agg& b) { return a.ms > b.ms; });
+        std::string out = "{\"kernels\": [";
+        for (size_t i = 0; i < agg.size(); ++i) {
+            char buf[512];
+            std::string nm = agg[i].name;
+            for (auto& ch : nm)
+                if (ch == '"') ch = '\'';
+            std::snprintf(buf, sizeof(buf), "%s{\"name\": \"%s\", \"launches\": %ld, \"ms\": %.6f, \"bytes\": %.6e}",
+                          i ? ", " : "", nm.c_str(), agg[i].launches, agg[i].ms, agg[i].bytes);
+            out += buf;
+        }
+        out += "]}";
+        P.recs.clear();
+        P.used = 0;
+        REQUIRE((int64_t)out.size() < cap, "profile buffer too small");
+        std::memcpy(json, out.c_str(), out.size() + 1);
+        return HELM_OK;
+    })
+}
+
 helm_status helm_destroy(helm_ctx ctx) {
     if (!ctx) return HELM_OK;
+    drop_graphs(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+    ctx->prof.pool.clear();
     for (void* p : ctx->allocs) (void)hipFree(p);
     ctx->allocs.clear();
     delete ctx;

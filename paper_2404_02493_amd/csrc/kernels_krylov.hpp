@@ -76,47 +76,35 @@ __device__ inline void ks_least_squares(KrylovScal* K, int cols) {
     for (int i = cols; i < MAXM; ++i) K->y[2 * i] = K->y[2 * i + 1] = 0.0;
 }
 
-// Starts a Krylov run from a given first vector: beta = ||x||, scale[0] = 1/beta.
+// Partial ||x||^2 of a Krylov start vector (finalize with FIN_INIT).
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_krylov_init_norm(size_t N, const cplx<T>* __restrict__ x, KrylovScal* K,
-                                                            int m, double* partials, unsigned int* ticket) {
+__global__ __launch_bounds__(BLOCK) void k_krylov_init_norm(size_t N, const cplx<T>* __restrict__ x, double* partials) {
     __shared__ double red[4];
     __shared__ double sums[1];
-    __shared__ int is_last;
     double acc[1] = {0.0};
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         cplx<T> v = x[p];
         acc[0] += double(v.re) * double(v.re) + double(v.im) * double(v.im);
     }
-    if (block_partials_and_ticket<1>(acc, 1, partials, ticket, red, sums, &is_last)) {
-        grid_final_sum<1>(partials, 1, red, sums, ticket);
-        if (threadIdx.x == 0) {
-            double b = sqrt(sums[0]);
-            K->beta = b;
-            K->m = m;
-            K->cols = 0;
-            K->done = (b == 0.0 || !isfinite(b)) ? 1 : 0;
-            K->scale[0] = b > 0.0 ? 1.0 / b : 0.0;
-            if (K->done)
-                for (int i = 0; i < MAXM; ++i) K->y[2 * i] = K->y[2 * i + 1] = 0.0;
-        }
-    }
+    block_sum<1, 4>(acc, 1, red, sums);
+    store_partials(sums, 1, partials);
 }
 
-// r0 = b - M x (ADR operator) written to r0, then the same start as k_krylov_init_norm.
+// r0 = b - M x (ADR operator) written to r0, partial ||r0||^2 (finalize with FIN_INIT).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_residual_init(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                              const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
                                                              const cplx<T>* __restrict__ x, cplx<T>* __restrict__ r0,
-                                                             KrylovScal* K, int m, double* partials,
-                                                             unsigned int* ticket) {
+                                                             double* partials) {
     __shared__ double red[4];
     __shared__ double sums[1];
-    __shared__ int is_last;
     double acc[1] = {0.0};
-    int j, i0;
-    tile_origin(A.n, j, i0);
-    if (j < A.n) {
+    int t0, t1;
+    tile_chunk(A.n, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        int j, i0;
+        tile_xy(A.n, t, j, i0);
+        if (j >= A.n) continue;
         for (int r = 0; r < RPT; ++r) {
             const int i = i0 + r;
             if (i >= A.n) break;
@@ -126,19 +114,8 @@ __global__ __launch_bounds__(BLOCK) void k_adr_residual_init(AdrGeom A, const T*
             acc[0] += double(v.re) * double(v.re) + double(v.im) * double(v.im);
         }
     }
-    if (block_partials_and_ticket<1>(acc, 1, partials, ticket, red, sums, &is_last)) {
-        grid_final_sum<1>(partials, 1, red, sums, ticket);
-        if (threadIdx.x == 0 && threadIdx.y == 0) {
-            double bb = sqrt(sums[0]);
-            K->beta = bb;
-            K->m = m;
-            K->cols = 0;
-            K->done = (bb == 0.0 || !isfinite(bb)) ? 1 : 0;
-            K->scale[0] = bb > 0.0 ? 1.0 / bb : 0.0;
-            if (K->done)
-                for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
-        }
-    }
+    block_sum<1, 4>(acc, 1, red, sums);
+    store_partials(sums, 1, partials);
 }
 
 // Accumulates sum conj(V_i) * w over i <= jj into acc (unscaled).
@@ -154,33 +131,25 @@ __device__ __forceinline__ void acc_dots(double (&acc)[2 * NV + 2], const VecSet
     }
 }
 
-// Stores the scaled inner products of the Arnoldi matvec pass into K->dots.
-template <int NV>
-__device__ __forceinline__ void finalize_mv(KrylovScal* K, int jj, const double* sums) {
-    for (int i = 0; i <= jj; ++i) {
-        double s = K->scale[i];
-        K->dots[2 * i] = s * sums[2 * i];
-        K->dots[2 * i + 1] = s * sums[2 * i + 1];
-    }
-}
-
-// Arnoldi matvec pass with the ADR operator: w = M (scale[jj] V_jj); dots_i = <v_i, w>.
+// Arnoldi matvec pass with the ADR operator: w = M (scale[jj] V_jj); partial sums of
+// conj(V_i) w, i <= jj (finalize with FIN_MV).
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_arnoldi_adr(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                        const cplx<T>* __restrict__ c0, VecSet<T> V, int jj,
-                                                       cplx<T>* __restrict__ w, KrylovScal* K, double* partials,
-                                                       unsigned int* ticket) {
+                                                       cplx<T>* __restrict__ w, const KrylovScal* K, double* partials) {
     __shared__ double red[4 * (2 * NV + 2)];
     __shared__ double sums[2 * NV + 2];
-    __shared__ int is_last;
     if (K->done) return;
     const T sj = T(K->scale[jj]);
     double acc[2 * NV + 2];
 #pragma unroll
     for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
-    int j, i0;
-    tile_origin(A.n, j, i0);
-    if (j < A.n) {
+    int t0, t1;
+    tile_chunk(A.n, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        int j, i0;
+        tile_xy(A.n, t, j, i0);
+        if (j >= A.n) continue;
         for (int r = 0; r < RPT; ++r) {
             const int i = i0 + r;
             if (i >= A.n) break;
@@ -191,29 +160,29 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_adr(AdrGeom A, const T* __res
             acc_dots<T, NV>(acc, V, jj, p, v);
         }
     }
-    if (block_partials_and_ticket<2 * NV + 2>(acc, 2 * (jj + 1), partials, ticket, red, sums, &is_last)) {
-        grid_final_sum<2 * NV + 2>(partials, 2 * (jj + 1), red, sums, ticket);
-        if (threadIdx.x == 0 && threadIdx.y == 0) finalize_mv<NV>(K, jj, sums);
-    }
+    block_sum<2 * NV + 2, 4>(acc, 2 * (jj + 1), red, sums);
+    store_partials(sums, 2 * (jj + 1), partials);
 }
 
 // Arnoldi matvec pass with the Helmholtz operator on z: w = A (s z), s = scale[jj] if
-// use_scale else 1; dots_i = <v_i, w>   (FGMRES: z = C(0, V_jj) or C(0, v_jj)).
+// use_scale else 1; partial sums of conj(V_i) w  (FGMRES: z = C(0, V_jj) or C(0, v_jj)).
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ z,
-                                                        int use_scale, VecSet<T> V, int jj, cplx<T>* __restrict__ w, KrylovScal* K,
-                                                        double* partials, unsigned int* ticket) {
+                                                        int use_scale, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
+                                                        const KrylovScal* K, double* partials) {
     __shared__ double red[4 * (2 * NV + 2)];
     __shared__ double sums[2 * NV + 2];
-    __shared__ int is_last;
     if (K->done) return;
     const T sj = use_scale ? T(K->scale[jj]) : T(1);
     double acc[2 * NV + 2];
 #pragma unroll
     for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
-    int j, i0;
-    tile_origin(G.n, j, i0);
-    if (j < G.n) {
+    int t0, t1;
+    tile_chunk(G.n, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        int j, i0;
+        tile_xy(G.n, t, j, i0);
+        if (j >= G.n) continue;
         for (int r = 0; r < RPT; ++r) {
             const int i = i0 + r;
             if (i >= G.n) break;
@@ -224,10 +193,8 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm(Geom G, const T* __restr
             acc_dots<T, NV>(acc, V, jj, p, v);
         }
     }
-    if (block_partials_and_ticket<2 * NV + 2>(acc, 2 * (jj + 1), partials, ticket, red, sums, &is_last)) {
-        grid_final_sum<2 * NV + 2>(partials, 2 * (jj + 1), red, sums, ticket);
-        if (threadIdx.x == 0 && threadIdx.y == 0) finalize_mv<NV>(K, jj, sums);
-    }
+    block_sum<2 * NV + 2, 4>(acc, 2 * (jj + 1), red, sums);
+    store_partials(sums, 2 * (jj + 1), partials);
 }
 
 // Loads the coefficients c_i = dots_i * scale_i (complex) of the current correction.
@@ -244,14 +211,12 @@ __device__ __forceinline__ void load_coefs(const KrylovScal* K, int jj, cplx<T> 
     }
 }
 
-// Gram-Schmidt pass 1: w -= sum_i dots_i v_i, then dots2_i = <v_i, w>.
-// Finalize: H(i, jj) = dots_i (first round), dots = dots2.
+// Gram-Schmidt pass 1: w -= sum_i dots_i v_i, partial sums of conj(V_i) w (FIN_ORTH1).
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_orth_pass1(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
-                                                      KrylovScal* K, double* partials, unsigned int* ticket) {
+                                                      const KrylovScal* K, double* partials) {
     __shared__ double red[4 * (2 * NV + 2)];
     __shared__ double sums[2 * NV + 2];
-    __shared__ int is_last;
     if (K->done) return;
     cplx<T> c[NV];
     load_coefs<T, NV>(K, jj, c);
@@ -266,29 +231,16 @@ __global__ __launch_bounds__(BLOCK) void k_orth_pass1(size_t N, VecSet<T> V, int
         w[p] = x;
         acc_dots<T, NV>(acc, V, jj, p, x);
     }
-    if (block_partials_and_ticket<2 * NV + 2>(acc, 2 * (jj + 1), partials, ticket, red, sums, &is_last)) {
-        grid_final_sum<2 * NV + 2>(partials, 2 * (jj + 1), red, sums, ticket);
-        if (threadIdx.x == 0) {
-            for (int i = 0; i <= jj; ++i) {
-                Hp(K, i, jj)[0] = K->dots[2 * i];
-                Hp(K, i, jj)[1] = K->dots[2 * i + 1];
-                double s = K->scale[i];
-                K->dots[2 * i] = s * sums[2 * i];
-                K->dots[2 * i + 1] = s * sums[2 * i + 1];
-            }
-        }
-    }
+    block_sum<2 * NV + 2, 4>(acc, 2 * (jj + 1), red, sums);
+    store_partials(sums, 2 * (jj + 1), partials);
 }
 
-// Gram-Schmidt pass 2: w -= sum_i dots2_i v_i and ||w||^2.  Finalize: H(i, jj) += dots2_i,
-// H(jj+1, jj) = ||w||, next scale, breakdown test, and the least squares at the end.
+// Gram-Schmidt pass 2: w -= sum_i dots2_i v_i, partial ||w||^2 (FIN_ORTH2).
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_orth_pass2(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
-                                                      KrylovScal* K, double breakdown_tol, double* partials,
-                                                      unsigned int* ticket) {
+                                                      const KrylovScal* K, double* partials) {
     __shared__ double red[4];
     __shared__ double sums[1];
-    __shared__ int is_last;
     if (K->done) return;
     cplx<T> c[NV];
     load_coefs<T, NV>(K, jj, c);
@@ -301,26 +253,67 @@ __global__ __launch_bounds__(BLOCK) void k_orth_pass2(size_t N, VecSet<T> V, int
         w[p] = x;
         acc[0] += double(x.re) * double(x.re) + double(x.im) * double(x.im);
     }
-    if (block_partials_and_ticket<1>(acc, 1, partials, ticket, red, sums, &is_last)) {
-        grid_final_sum<1>(partials, 1, red, sums, ticket);
-        if (threadIdx.x == 0) {
-            for (int i = 0; i <= jj; ++i) {
-                Hp(K, i, jj)[0] += K->dots[2 * i];
-                Hp(K, i, jj)[1] += K->dots[2 * i + 1];
-            }
-            double hn = sqrt(sums[0]);
-            Hp(K, jj + 1, jj)[0] = hn;
-            Hp(K, jj + 1, jj)[1] = 0.0;
-            K->cols = jj + 1;
-            if (!isfinite(hn)) {
-                K->done = 2;
-                for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
-            } else if (hn <= breakdown_tol * K->beta || jj + 1 == K->m) {
-                ks_least_squares(K, jj + 1);
-                K->done = 1;
-            } else {
-                K->scale[jj + 1] = 1.0 / hn;
-            }
+    block_sum<1, 4>(acc, 1, red, sums);
+    store_partials(sums, 1, partials);
+}
+
+enum FinOp { FIN_INIT = 0, FIN_MV = 1, FIN_ORTH1 = 2, FIN_ORTH2 = 3 };
+
+// One block: sums the partials of the previous Krylov pass and updates the state.
+//   FIN_INIT : beta = ||r0||, scale[0] = 1/beta, cols = 0, done if beta == 0
+//   FIN_MV   : dots_i = scale_i * sum conj(V_i) w
+//   FIN_ORTH1: H(i, jj) = dots_i (first round), dots_i = second-round products
+//   FIN_ORTH2: H(i, jj) += dots_i, H(jj+1, jj) = ||w||, next scale; on breakdown
+//              (||w|| <= tol beta) or at jj + 1 == m the Hessenberg least squares.
+template <int KV>
+__global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __restrict__ partials, int nblk, int op,
+                                                            int jj, int m, KrylovScal* K, double tol) {
+    __shared__ double red[(FBLOCK / 64) * KV];
+    __shared__ double sums[KV];
+    if (op != FIN_INIT && K->done) return;
+    const int kcount = (op == FIN_MV || op == FIN_ORTH1) ? 2 * (jj + 1) : 1;
+    final_sum<KV>(partials, nblk, kcount, red, sums);
+    if (threadIdx.x != 0) return;
+    if (op == FIN_INIT) {
+        double b = sqrt(sums[0]);
+        K->beta = b;
+        K->m = m;
+        K->cols = 0;
+        K->done = (b == 0.0 || !isfinite(b)) ? 1 : 0;
+        K->scale[0] = b > 0.0 ? 1.0 / b : 0.0;
+        if (K->done)
+            for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
+    } else if (op == FIN_MV) {
+        for (int i = 0; i <= jj; ++i) {
+            double s = K->scale[i];
+            K->dots[2 * i] = s * sums[2 * i];
+            K->dots[2 * i + 1] = s * sums[2 * i + 1];
+        }
+    } else if (op == FIN_ORTH1) {
+        for (int i = 0; i <= jj; ++i) {
+            Hp(K, i, jj)[0] = K->dots[2 * i];
+            Hp(K, i, jj)[1] = K->dots[2 * i + 1];
+            double s = K->scale[i];
+            K->dots[2 * i] = s * sums[2 * i];
+            K->dots[2 * i + 1] = s * sums[2 * i + 1];
+        }
+    } else {
+        for (int i = 0; i <= jj; ++i) {
+            Hp(K, i, jj)[0] += K->dots[2 * i];
+            Hp(K, i, jj)[1] += K->dots[2 * i + 1];
+        }
+        double hn = sqrt(sums[0]);
+        Hp(K, jj + 1, jj)[0] = hn;
+        Hp(K, jj + 1, jj)[1] = 0.0;
+        K->cols = jj + 1;
+        if (!isfinite(hn)) {
+            K->done = 2;
+            for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
+        } else if (hn <= tol * K->beta || jj + 1 == K->m) {
+            ks_least_squares(K, jj + 1);
+            K->done = 1;
+        } else {
+            K->scale[jj + 1] = 1.0 / hn;
         }
     }
 }

@@ -30,6 +30,26 @@ __device__ __forceinline__ void tile_origin(int n, int& j, int& i0) {
     i0 = ty * TY + threadIdx.y * RPT;
 }
 
+// Reduction kernels run at most MAXRED blocks; each block owns a contiguous chunk
+// of tiles [t0, t1) (XCD-aware block order as above).
+__host__ __device__ inline int red_blocks(int n) { return tiles_of(n) < MAXRED ? tiles_of(n) : MAXRED; }
+
+__device__ __forceinline__ void tile_chunk(int n, int& t0, int& t1) {
+    const int nt = tiles_of(n);
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int per = (nt + nb - 1) / nb;
+    t0 = b * per;
+    t1 = t0 + per < nt ? t0 + per : nt;
+}
+
+__device__ __forceinline__ void tile_xy(int n, int t, int& j, int& i0) {
+    const int ntx = (n + TX - 1) / TX;
+    j = (t % ntx) * TX + threadIdx.x;
+    i0 = (t / ntx) * TY + threadIdx.y * RPT;
+}
+
 template <typename T>
 __device__ __forceinline__ cplx<T> lap_at(const cplx<T>* __restrict__ u, int i, int j, int n, T inv_h2) {
     cplx<T> c = u[(size_t)i * n + j];
@@ -87,18 +107,20 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom G, const T* __restrict_
     }
 }
 
-// Fine-grid FP64 residual with ||r||^2 and ||g||^2 (grid reduction into out[0..1]).
+// Fine-grid FP64 residual with per-block partial sums of ||r||^2 and ||g||^2
+// (finalized by k_finalize_sums).
 __global__ __launch_bounds__(BLOCK) void k_residual_norms(Geom G, const double* __restrict__ n2,
                                                           const c128* __restrict__ g, const c128* __restrict__ u,
-                                                          c128* __restrict__ r, double* partials,
-                                                          unsigned int* ticket, double* out) {
+                                                          c128* __restrict__ r, double* partials) {
     __shared__ double red[4 * 2];
     __shared__ double sums[2];
-    __shared__ int is_last;
-    int j, i0;
-    tile_origin(G.n, j, i0);
     double acc[2] = {0.0, 0.0};
-    if (j < G.n) {
+    int t0, t1;
+    tile_chunk(G.n, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        int j, i0;
+        tile_xy(G.n, t, j, i0);
+        if (j >= G.n) continue;
         for (int rr = 0; rr < RPT; ++rr) {
             const int i = i0 + rr;
             if (i >= G.n) break;
@@ -112,13 +134,18 @@ __global__ __launch_bounds__(BLOCK) void k_residual_norms(Geom G, const double* 
             if (r) r[(size_t)i * G.n + j] = v;
         }
     }
-    if (block_partials_and_ticket<2>(acc, 2, partials, ticket, red, sums, &is_last)) {
-        grid_final_sum<2>(partials, 2, red, sums, ticket);
-        if (threadIdx.x == 0 && threadIdx.y == 0) {
-            out[0] = sums[0];
-            out[1] = sums[1];
-        }
-    }
+    block_sum<2, 4>(acc, 2, red, sums);
+    store_partials(sums, 2, partials);
+}
+
+// out[v] = sum over blocks of partials (one block of FBLOCK threads).
+template <int K>
+__global__ __launch_bounds__(FBLOCK) void k_finalize_sums(const double* __restrict__ partials, int nblk, int kcount,
+                                                          double* out) {
+    __shared__ double red[(FBLOCK / 64) * K];
+    __shared__ double sums[K];
+    final_sum<K>(partials, nblk, kcount, red, sums);
+    if ((int)threadIdx.x < kcount) out[threadIdx.x] = sums[threadIdx.x];
 }
 
 // Full weighting of one fine value set around fine node (2I, 2J).
@@ -305,13 +332,10 @@ __global__ __launch_bounds__(BLOCK) void k_slowness2(size_t N, const double* __r
     }
 }
 
-// Per-level statistics over the unknowns (1 <= i, j <= n-1): max |4/h^2 - kappa|,
-// max n2, sum n2.  Grid reduction into out[0..2] (max via partial maxima).
-__global__ __launch_bounds__(BLOCK) void k_level_stats(Geom G, const double* __restrict__ n2, double* partials,
-                                                       unsigned int* ticket, double* out) {
+// Per-level statistics over the unknowns (1 <= i, j <= n-1): per-block max |4/h^2 - kappa|,
+// max n2 and sum n2, stored as partials[3 * block + {0,1,2}] (combined on the host).
+__global__ __launch_bounds__(BLOCK) void k_level_stats(Geom G, const double* __restrict__ n2, double* partials) {
     __shared__ double red[4 * 3];
-    __shared__ double sums[3];
-    __shared__ int is_last;
     const int n = G.n;
     const size_t N = (size_t)n * n;
     double mx = 0.0, mn2 = 0.0, sn2 = 0.0;
@@ -325,7 +349,6 @@ __global__ __launch_bounds__(BLOCK) void k_level_stats(Geom G, const double* __r
         mn2 = v > mn2 ? v : mn2;
         sn2 += v;
     }
-    // block max/sum
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     for (int off = 32; off > 0; off >>= 1) {
@@ -347,28 +370,9 @@ __global__ __launch_bounds__(BLOCK) void k_level_stats(Geom G, const double* __r
             b = red[w * 3 + 1] > b ? red[w * 3 + 1] : b;
             c += red[w * 3 + 2];
         }
-        const int blk = blockIdx.x;
-        partials[blk * 3 + 0] = a;
-        partials[blk * 3 + 1] = b;
-        partials[blk * 3 + 2] = c;
-        __threadfence();
-        unsigned int t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (is_last && tid == 0) {
-        __threadfence();
-        double a = 0, b = 0, c = 0;
-        for (int q = 0; q < (int)gridDim.x; ++q) {
-            const volatile double* pp = partials + q * 3;
-            a = pp[0] > a ? pp[0] : a;
-            b = pp[1] > b ? pp[1] : b;
-            c += pp[2];
-        }
-        out[0] = a;
-        out[1] = b;
-        out[2] = c;
-        *ticket = 0u;
+        partials[blockIdx.x * 3 + 0] = a;
+        partials[blockIdx.x * 3 + 1] = b;
+        partials[blockIdx.x * 3 + 2] = c;
     }
 }
 

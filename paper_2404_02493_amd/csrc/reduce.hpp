@@ -1,11 +1,16 @@
-// Block reductions and the deterministic "last block finishes" grid reduction.
+// Block reductions.  Grid reductions are two-kernel: every block stores its
+// partial sums (plain stores, layout partials[v * nblk + block]) and a one-block
+// finalize kernel sums them in a fixed order.  There is no cross-block
+// synchronisation inside a kernel.
 #pragma once
 
 #include "common.hpp"
 
 namespace helm {
 
-constexpr int BLOCK = 256;  // threads per block of every kernel (4 wavefronts of 64)
+constexpr int BLOCK = 256;     // threads per block of the grid kernels (4 wavefronts of 64)
+constexpr int FBLOCK = 1024;   // threads of the one-block finalize kernels
+constexpr int MAXRED = 2048;   // at most this many blocks in a kernel that produces partials
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -13,9 +18,10 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Reduce K per-thread accumulators over the block; thread 0 receives the sums in out[].
-// red: LDS scratch of at least 4*K doubles.
-template <int K>
+// Reduce K per-thread accumulators over the block (any size up to 1024 threads);
+// thread 0 receives the sums in out[] (LDS).  red: LDS scratch of NW*K doubles,
+// NW = number of wavefronts of the block.
+template <int K, int NW>
 __device__ __forceinline__ void block_sum(const double (&acc)[K], int kcount, double* red, double* out) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -27,53 +33,37 @@ __device__ __forceinline__ void block_sum(const double (&acc)[K], int kcount, do
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        for (int v = 0; v < kcount; ++v) out[v] = red[v] + red[K + v] + red[2 * K + v] + red[3 * K + v];
+    if (tid < kcount) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += red[w * K + tid];
+        out[tid] = s;
     }
     __syncthreads();
 }
 
-// Writes this block's K sums to partials[block*kcount + v] and takes a ticket.
-// Returns true in every thread of the last block to finish; that block then sees
-// every partial (release/acquire at device scope).  Deterministic: the final sum
-// is formed by grid_final_sum in a fixed order.
-template <int K>
-__device__ __forceinline__ bool block_partials_and_ticket(const double (&acc)[K], int kcount, double* partials,
-                                                          unsigned int* ticket, double* red, double* sums,
-                                                          int* is_last) {
-    block_sum<K>(acc, kcount, red, sums);
+// Stores this block's kcount sums (after block_sum) to partials[v * nblk + block].
+__device__ __forceinline__ void store_partials(const double* sums, int kcount, double* partials) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int nblk = gridDim.x * gridDim.y;
-    const int blk = blockIdx.x + blockIdx.y * gridDim.x;
-    if (tid == 0) {
-        for (int v = 0; v < kcount; ++v) partials[(size_t)blk * kcount + v] = sums[v];
-        __threadfence();
-        unsigned int t = atomicAdd(ticket, 1u);
-        *is_last = (t == (unsigned)(nblk - 1));
-    }
-    __syncthreads();
-    bool last = *is_last != 0;
-    if (last) __threadfence();
-    return last;
+    const int nblk = gridDim.x;
+    if (tid < kcount) partials[(size_t)tid * nblk + blockIdx.x] = sums[tid];
 }
 
-// Called by every thread of the last block: sums[v] = sum over blocks of partials (fixed order).
+// In a one-block finalize kernel of FBLOCK threads: sums[v] = sum over blocks of
+// partials[v * nblk + b], v < kcount, fixed order; result in LDS sums[] for all threads.
 template <int K>
-__device__ __forceinline__ void grid_final_sum(const double* partials, int kcount, double* red, double* sums,
-                                               unsigned int* ticket) {
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int nblk = gridDim.x * gridDim.y;
+__device__ __forceinline__ void final_sum(const double* __restrict__ partials, int nblk, int kcount, double* red,
+                                          double* sums) {
     double acc[K];
 #pragma unroll
     for (int v = 0; v < K; ++v) acc[v] = 0.0;
-    for (int b = tid; b < nblk; b += BLOCK) {
-        const volatile double* p = partials + (size_t)b * kcount;
+    const int tid = threadIdx.x;
+    for (int b = tid; b < nblk; b += FBLOCK) {
 #pragma unroll
         for (int v = 0; v < K; ++v)
-            if (v < kcount) acc[v] += p[v];
+            if (v < kcount) acc[v] += partials[(size_t)v * nblk + b];
     }
-    block_sum<K>(acc, kcount, red, sums);
-    if (tid == 0) *ticket = 0u;
+    block_sum<K, FBLOCK / 64>(acc, kcount, red, sums);
 }
 
 }  // namespace helm

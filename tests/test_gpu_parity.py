@@ -32,12 +32,12 @@ def _rand(rng, n):
     return torch.as_tensor(v)
 
 
-def make_pair(case, prec, **kw):
+def make_pair(case, prec, gmres_arnoldi=0, **kw):
     from paper_2404_02493_amd import Helmholtz
 
     P = Problem(case.velocity, case.k, case.levels, damping_cells=case.damping_cells, phi=case.phi, **kw)
     H = Helmholtz(case.velocity, case.k, levels=case.levels, precision=prec, damping_cells=case.damping_cells,
-                  **{k: int(v) for k, v in kw.items()})
+                  gmres_arnoldi=gmres_arnoldi, **{k: int(v) for k, v in kw.items()})
     H.set_phase(case.phi)
     H.set_weights(P.weights.numpy())
     return P, H
@@ -69,10 +69,13 @@ def test_default_weights_match_oracle(small_case, prec):
     H.close()
 
 
+@pytest.mark.parametrize("arnoldi", [0, 1])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_operator_parity(small_case, prec):
+def test_operator_parity(small_case, prec, arnoldi):
+    """Every internal operator on identical inputs; arnoldi=1 forces the Arnoldi
+    form of the GMRES smoother, 0 uses the s-step form on levels < L."""
     c = small_case
-    P, H = make_pair(c, prec)
+    P, H = make_pair(c, prec, gmres_arnoldi=arnoldi)
     rng = np.random.default_rng(0)
     tol = TOL[prec]
     cd = H.cdtype
@@ -204,3 +207,33 @@ def test_cycle_before_phase_is_state_error():
         H.cycle(g, u)
     assert e.value.status == 6
     H.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_graph_replays_match_eager(small_case, prec):
+    """Cycles replayed from a captured HIP graph equal eager launches bit for bit,
+    over several replays with eager work and synchronisations in between."""
+    c = small_case
+    P, Hg = make_pair(c, prec)
+    _, He = make_pair(c, prec, use_graphs=0) if False else (None, None)
+    from paper_2404_02493_amd import Helmholtz
+
+    He = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=c.damping_cells, use_graphs=0)
+    He.set_phase(c.phi)
+    He.set_weights(P.weights.numpy())
+    rng = np.random.default_rng(7)
+    g = to_dev(_rand(rng, c.n), Hg.cdtype)
+    ug = torch.zeros_like(g)
+    ue = torch.zeros_like(g)
+    for rep in range(4):
+        Hg.cycle(g, ug)
+        He.cycle(g, ue)
+        torch.cuda.synchronize()
+        assert torch.equal(ug, ue), rep
+        # eager work on the graph context between replays
+        x = to_dev(_rand(rng, c.n), Hg.cdtype)
+        Hg.debug_op(1, 1, x)
+        _ = (x * 2).sum().item()
+        torch.cuda.synchronize()
+    Hg.close()
+    He.close()
