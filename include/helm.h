@@ -68,18 +68,22 @@ typedef struct {
     int32_t cheb_post;        /* Chebyshev steps after it (default 5) */
     int32_t cheb_coarse;      /* Chebyshev steps on level L (default 10) */
     int32_t gmres_m;          /* GMRES(m) smoother on ADR levels (default 3) */
-    int32_t gmres_coarse_m;   /* GMRES(m) on the coarsest ADR level (default 10) */
+    int32_t gmres_coarse_m;   /* GMRES(m) on the coarsest ADR level (default 3) */
     int32_t level3_literal;   /* 0: no smoothing on level 3 (default); 1: Chebyshev post-smoother there */
     int32_t restart;          /* FGMRES restart length (default 20, at most 24) */
     int32_t gmres_arnoldi;    /* 0 (default): GMRES(m <= 4) smoother in s-step form (Krylov basis
                                  rebuilt on tiles, Gram least squares); 1: always Arnoldi */
     int32_t use_graphs;       /* 1 (default): each cycle is captured once per (g, u) pointer pair as a
                                  HIP graph and replayed; 0: kernels are launched one by one */
+    int32_t adr_levels;       /* levels of the ADR V-cycle, from level 2 down (default 3; 0 = all, L - 1) */
+    int32_t tail_n;           /* a coarsest ADR level with at most tail_n nodes per side (and at most
+                                 4096 nodes) runs its GMRES in one workgroup (default 64; 0 = never) */
 } helm_desc;
 
 /* Defaults of every field for an n x n grid at frequency k:
  * levels = min(7, log2 n - 3) (at least 2), W = 16, strength 0.5, sign +1, C128,
- * M = 8, Chebyshev 5/5/10, GMRES 3/10 (s-step form), restart 20, graphs on. */
+ * M = 8, Chebyshev 5/5/10, GMRES(3) on a 3-level ADR V-cycle (s-step form), restart 20,
+ * graphs on. */
 void helm_desc_default(helm_desc* d, int32_t n, double k);
 
 /* Setup phase (paper Figure "cycle": the solver's setup/solve split).

@@ -119,12 +119,12 @@ def gmres(op, b: torch.Tensor, x0, m: int, breakdown_tol: float = 1e-14):
 
 
 def adr_vcycle(P, level: int, b: torch.Tensor, x):
-    """One V-cycle for M on ADR levels level..L (Section 3.2.2: one V-cycle with
-    GMRES(3) pre- and post-smoothing).  Reading: on the coarsest level L the
+    """One V-cycle for M on ADR levels level..LA (Section 3.2.2: one V-cycle with
+    GMRES(3) pre- and post-smoothing).  Reading: on the coarsest ADR level LA the
     cycle applies GMRES(gmres_coarse_m) and returns."""
     coef = P.adr[level]
     op = lambda v: apply_M(v, coef)
-    if level == P.L:
+    if level == P.LA:
         return gmres(op, b, x, P.gmres_coarse_m)
     x = gmres(op, b, x, P.gmres_m)
     rc = restrict_fw(b - op(x))

@@ -12,7 +12,9 @@ Readings of the paper used here (each also listed in the design notes):
   is available with level3_literal=True);
 * the branch order of Algorithm 1 is kept (l == 1, then l == L, then l == 3);
 * after the level-2 post-smoother, adr_steps ADR corrections (r, demodulate,
-  ADR V-cycle, modulate-add) are applied; only the correction repeats.
+  ADR V-cycle, modulate-add) are applied; only the correction repeats;
+* the ADR V-cycle spans adr_levels levels from level 2 down (default 3) with
+  GMRES(3) smoothing on each, also the coarsest (gmres_coarse_m = 3).
 """
 from __future__ import annotations
 
@@ -37,8 +39,8 @@ class Problem:
     def __init__(self, velocity, k: float, levels: int, damping_cells: int = 16,
                  damping_strength: float = 0.5, sigma: int = 1, adr_steps: int = 8,
                  cheb_pre: int = 5, cheb_post: int = 5, cheb_coarse: int = 10,
-                 gmres_m: int = 3, gmres_coarse_m: int = 10, level3_literal: bool = False,
-                 weights=None, phi=None):
+                 gmres_m: int = 3, gmres_coarse_m: int = 3, level3_literal: bool = False,
+                 weights=None, phi=None, adr_levels=3):
         vel = torch.as_tensor(np.asarray(velocity, dtype=np.float64))
         self.n = int(vel.shape[0])
         if self.n & (self.n - 1) or self.n < 8:
@@ -54,6 +56,10 @@ class Problem:
         self.cheb_pre, self.cheb_post, self.cheb_coarse = cheb_pre, cheb_post, cheb_coarse
         self.gmres_m, self.gmres_coarse_m = gmres_m, gmres_coarse_m
         self.level3_literal = bool(level3_literal)
+        # ADR V-cycle on levels 2..LA (LA = L unless fewer ADR levels are requested)
+        self.LA = self.L if adr_levels is None else min(self.L, 1 + int(adr_levels))
+        if self.L >= 3 and self.LA < 2:
+            raise ValueError("adr_levels must be >= 1")
         self.n2_fine = 1.0 / (vel * vel)
         self.h, self.n2, self.rho, self.kappa, self.lam = {}, {}, {}, {}, {}
         for l in range(1, self.L + 1):
@@ -88,7 +94,7 @@ class Problem:
         phi = phi if isinstance(phi, torch.Tensor) else torch.as_tensor(np.asarray(phi))
         phi = phi.to(F64)
         self.adr = {}
-        for l in range(2, self.L + 1):
+        for l in range(2, self.LA + 1):
             self.adr[l] = adr_coefficients(inject(phi, l), self.n2[l], self.rho[l], self.k,
                                            self.strength, self.sigma, self.h[l])
         phi2 = inject(phi, 2)

@@ -38,6 +38,8 @@ class HelmDesc(ctypes.Structure):
         ("restart", ctypes.c_int32),
         ("gmres_arnoldi", ctypes.c_int32),
         ("use_graphs", ctypes.c_int32),
+        ("adr_levels", ctypes.c_int32),
+        ("tail_n", ctypes.c_int32),
     ]
 
 

@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "../../include/helm.h"
-#include "kernels_sstep.hpp"
+#include "kernels_tail.hpp"
 
 namespace helm {
 
@@ -70,6 +70,7 @@ struct AdrLevel {
 struct helm_ctx_s {
     helm_desc d{};
     int L = 0;
+    int LA = 0;  // coarsest level of the ADR V-cycle
     bool f32 = false;  // cycle precision is complex64
     std::vector<void*> allocs;
     double* n2f = nullptr;  // fine n^2 (FP64)
@@ -379,9 +380,30 @@ struct Engine {
                            (const T*)c->theta2, (C*)W.u);
     }
 
+    // GMRES on a small level in one workgroup (the coarsest ADR level), if it fits.
+    bool gmres_block(int l, int m, bool x0_zero) {
+        AdrLevel& A = c->al[l];
+        if (A.n > c->d.tail_n || (size_t)A.n * A.n > 4 * 1024 || m > 12) return false;
+        BlockLevel<T> t{};
+        t.A = A.A;
+        t.px = (const T*)A.px;
+        t.py = (const T*)A.py;
+        t.c0 = (const C*)A.c0;
+        t.b = (const C*)A.b;
+        t.x = (C*)A.x;
+        t.V = (C*)A.V[0];
+        t.m = m;
+        const double bytes = (3.0 * m + 4.0) * sizeof(C) * NN(A.n);
+        if (m <= 4)
+            LAUNCH(c, bytes, (k_gmres_block<T, 1024, 4, 4096>), dim3(1), dim3(1024), st, t, x0_zero ? 1 : 0, 1e-14);
+        else
+            LAUNCH(c, bytes, (k_gmres_block<T, 512, 12, 4096>), dim3(1), dim3(512), st, t, x0_zero ? 1 : 0, 1e-14);
+        return true;
+    }
+
     void adr_vcycle(int l) {
         AdrLevel& A = c->al[l];
-        if (l == c->L) {
+        if (l == c->LA) {
             gmres(l, c->d.gmres_coarse_m, true);
             return;
         }
@@ -458,7 +480,9 @@ struct Engine {
     }
 
     void gmres(int l, int m, bool x0_zero) {
-        if (l < c->L && m <= 4 && !c->d.gmres_arnoldi) {
+        // one workgroup on the coarsest level, s-step form on the larger ones
+        if (l == c->LA && gmres_block(l, m, x0_zero)) return;
+        if (m <= 4 && !c->d.gmres_arnoldi) {
             switch (m) {
                 case 1: gmres_sstep<1>(l, x0_zero); return;
                 case 2: gmres_sstep<2>(l, x0_zero); return;
@@ -630,12 +654,15 @@ static void validate(const helm_desc* d) {
     REQUIRE(d->restart >= 1 && d->restart <= MAXM, "restart must be in [1, 24]");
     REQUIRE(d->gmres_arnoldi == 0 || d->gmres_arnoldi == 1, "gmres_arnoldi must be 0 or 1");
     REQUIRE(d->use_graphs == 0 || d->use_graphs == 1, "use_graphs must be 0 or 1");
+    REQUIRE(d->tail_n >= 0, "tail_n must be >= 0");
+    REQUIRE(d->adr_levels >= 0, "adr_levels must be >= 0");
 }
 
 static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     const helm_desc& d = c->d;
     const int n = d.n, L = d.levels;
     c->L = L;
+    c->LA = d.adr_levels > 0 ? std::min(L, 1 + d.adr_levels) : L;
     c->f32 = d.cycle_prec == HELM_C64;
     const bool f64c = !c->f32;
     const size_t NF = (size_t)n * n;
@@ -725,7 +752,7 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     // ADR levels
     c->al.assign(L + 1, AdrLevel{});
     if (L >= 3) {
-        for (int l = 2; l <= L; ++l) {
+        for (int l = 2; l <= c->LA; ++l) {
             AdrLevel& A = c->al[l];
             A.n = n >> (l - 1);
             A.A = make_adr_geom(c, l);
@@ -736,8 +763,9 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
             A.b = dalloc(c, Nl * csize(f64c));
             A.x = dalloc(c, Nl * csize(f64c));
             A.xalt = dalloc(c, Nl * csize(f64c));
-            const int m = (l == L) ? d.gmres_coarse_m : d.gmres_m;
-            for (int i = 0; i <= m; ++i) A.V[i] = dalloc(c, Nl * csize(f64c));
+            const int m = (l == c->LA) ? d.gmres_coarse_m : d.gmres_m;
+            char* vb = (char*)dalloc(c, (size_t)(m + 1) * Nl * csize(f64c));  // V_0..V_m contiguous
+            for (int i = 0; i <= m; ++i) A.V[i] = vb + (size_t)i * Nl * csize(f64c);
             A.K = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
             HIPCHK(hipMemsetAsync(A.K, 0, sizeof(KrylovScal), st));
         }
@@ -763,7 +791,7 @@ static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
         c->phase_set = true;
         return;
     }
-    for (int l = 2; l <= c->L; ++l) {
+    for (int l = 2; l <= c->LA; ++l) {
         AdrLevel& A = c->al[l];
         const Geom G = make_geom(c, l);
         const size_t Nl = (size_t)A.n * A.n;
@@ -971,11 +999,13 @@ void helm_desc_default(helm_desc* d, int32_t n, double k) {
     d->cheb_post = 5;
     d->cheb_coarse = 10;
     d->gmres_m = 3;
-    d->gmres_coarse_m = 10;
+    d->gmres_coarse_m = 3;
     d->level3_literal = 0;
     d->restart = 20;
     d->gmres_arnoldi = 0;
     d->use_graphs = 1;
+    d->tail_n = 64;
+    d->adr_levels = 3;
 }
 
 helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* out, void* stream) {
@@ -1138,7 +1168,8 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                     break;
                 }
                 case 6: {
-                    REQUIRE(level >= 2 && ctx->L >= 3 && ctx->phase_set, "ADR operator needs the phase");
+                    REQUIRE(level >= 2 && level <= ctx->LA && ctx->L >= 3 && ctx->phase_set,
+                            "ADR operator needs the phase and an ADR level");
                     AdrLevel& A = ctx->al[level];
                     hipLaunchKernelGGL((k_adr_apply<T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
                                        (const T*)A.px, (const T*)A.py, (const cplx<T>*)A.c0, (const cplx<T>*)in,
@@ -1151,7 +1182,8 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                     const size_t Nl = (size_t)A.n * A.n;
                     HIPCHK(hipMemcpyAsync(A.b, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     HIPCHK(hipMemcpyAsync(A.x, in, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
-                    E.gmres(level, level == ctx->L ? ctx->d.gmres_coarse_m : ctx->d.gmres_m, false);
+                    REQUIRE(level <= ctx->LA, "level beyond the ADR hierarchy");
+                    E.gmres(level, level == ctx->LA ? ctx->d.gmres_coarse_m : ctx->d.gmres_m, false);
                     HIPCHK(hipMemcpyAsync(out, A.x, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     break;
                 }

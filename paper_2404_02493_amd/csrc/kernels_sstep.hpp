@@ -173,13 +173,19 @@ __global__ __launch_bounds__(FBLOCK) void k_sstep_solve(const double* __restrict
     __shared__ double sums[NG];
     final_sum<NG>(partials, nblk, NG, red, sums);
     if (threadIdx.x != 0) return;
-    // Hermitian G(i,j), i,j = 0..M
+    // Hermitian G(i,j), i,j = 0..M; every loop below has compile-time bounds so that
+    // the small arrays stay in registers.
     double gr[M + 1][M + 1], gi[M + 1][M + 1];
+#pragma unroll
+    for (int i = 0; i <= M; ++i) {
+        gr[i][i] = sums[i];
+        gi[i][i] = 0.0;
+    }
     {
         int o = M + 1;
-        for (int i = 0; i <= M; ++i) {
-            gr[i][i] = sums[i];
-            gi[i][i] = 0.0;
+#pragma unroll
+        for (int i = 0; i <= M; ++i)
+#pragma unroll
             for (int j = i + 1; j <= M; ++j) {
                 gr[i][j] = sums[o];
                 gi[i][j] = sums[o + 1];
@@ -187,79 +193,89 @@ __global__ __launch_bounds__(FBLOCK) void k_sstep_solve(const double* __restrict
                 gi[j][i] = -sums[o + 1];
                 o += 2;
             }
-        }
     }
     const double beta = sqrt(gr[0][0]);
-    K->beta = beta;
-    for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
-    if (!(beta > 0.0) || !isfinite(beta)) {
-        K->cols = 0;
-        K->done = isfinite(beta) ? 1 : 2;
-        return;
-    }
-    double d[M + 1];
-    for (int i = 0; i <= M; ++i) d[i] = sqrt(gr[i][i]);
-    // normalised normal equations N c' = r, N(i,j) = G(i,j)/(d_i d_j), r(i) = G(i,0)/(d_i d_0), i,j = 1..M
-    double Lr[M][M], Li[M][M];
-    int cols = M;
-    for (int i = 0; i < M; ++i)
-        for (int j = 0; j < M; ++j) {
-            const double s = (d[i + 1] > 0 && d[j + 1] > 0) ? 1.0 / (d[i + 1] * d[j + 1]) : 0.0;
-            Lr[i][j] = gr[i + 1][j + 1] * s;
-            Li[i][j] = gi[i + 1][j + 1] * s;
-        }
-    // Cholesky N = L L^H (lower), stop at the first negligible pivot
-    for (int j = 0; j < M; ++j) {
-        double p = Lr[j][j];
-        for (int q = 0; q < j; ++q) p -= Lr[j][q] * Lr[j][q] + Li[j][q] * Li[j][q];
-        if (!(p > breakdown_tol * breakdown_tol)) {
-            cols = j;
-            break;
-        }
-        const double lj = sqrt(p);
-        Lr[j][j] = lj;
-        Li[j][j] = 0.0;
-        for (int i = j + 1; i < M; ++i) {
-            double sr = Lr[i][j], si = Li[i][j];
-            for (int q = 0; q < j; ++q) {  // L(i,q) conj(L(j,q))
-                sr -= Lr[i][q] * Lr[j][q] + Li[i][q] * Li[j][q];
-                si -= Li[i][q] * Lr[j][q] - Lr[i][q] * Li[j][q];
+    double yr[M], yi[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) yr[i] = yi[i] = 0.0;
+    int cols = 0;
+    if (beta > 0.0 && isfinite(beta)) {
+        double d[M + 1];
+#pragma unroll
+        for (int i = 0; i <= M; ++i) d[i] = sqrt(gr[i][i]);
+        // normalised normal equations N c' = r, N(i,j) = G(i,j)/(d_i d_j), r(i) = G(i,0)/(d_i d_0)
+        double Lr[M][M], Li[M][M];
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double s = (d[i + 1] > 0 && d[j + 1] > 0) ? 1.0 / (d[i + 1] * d[j + 1]) : 0.0;
+                Lr[i][j] = gr[i + 1][j + 1] * s;
+                Li[i][j] = gi[i + 1][j + 1] * s;
             }
-            Lr[i][j] = sr / lj;
-            Li[i][j] = si / lj;
+        // Cholesky N = L L^H; columns after the first negligible pivot are dropped
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double p = Lr[j][j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) p -= Lr[j][q] * Lr[j][q] + Li[j][q] * Li[j][q];
+            ok = ok && (p > breakdown_tol * breakdown_tol);
+            if (ok) cols = j + 1;
+            const double lj = ok ? sqrt(p) : 1.0;
+            Lr[j][j] = lj;
+            Li[j][j] = 0.0;
+#pragma unroll
+            for (int i = j + 1; i < M; ++i) {
+                double sr = Lr[i][j], si = Li[i][j];
+#pragma unroll
+                for (int q = 0; q < j; ++q) {
+                    sr -= Lr[i][q] * Lr[j][q] + Li[i][q] * Li[j][q];
+                    si -= Li[i][q] * Lr[j][q] - Lr[i][q] * Li[j][q];
+                }
+                Lr[i][j] = sr / lj;
+                Li[i][j] = si / lj;
+            }
+        }
+        double zr[M], zi[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {  // L z = r  (rows >= cols give zero)
+            const double s = 1.0 / (d[i + 1] * d[0]);
+            double sr = gr[i + 1][0] * s, si = gi[i + 1][0] * s;
+#pragma unroll
+            for (int q = 0; q < i; ++q) {
+                sr -= Lr[i][q] * zr[q] - Li[i][q] * zi[q];
+                si -= Lr[i][q] * zi[q] + Li[i][q] * zr[q];
+            }
+            zr[i] = i < cols ? sr / Lr[i][i] : 0.0;
+            zi[i] = i < cols ? si / Lr[i][i] : 0.0;
+        }
+#pragma unroll
+        for (int i = M - 1; i >= 0; --i) {  // L^H c' = z
+            double sr = zr[i], si = zi[i];
+#pragma unroll
+            for (int q = i + 1; q < M; ++q) {
+                sr -= Lr[q][i] * zr[q] + Li[q][i] * zi[q];
+                si -= Lr[q][i] * zi[q] - Li[q][i] * zr[q];
+            }
+            zr[i] = i < cols ? sr / Lr[i][i] : 0.0;
+            zi[i] = i < cols ? si / Lr[i][i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) {  // c_j = c'_j d_0 / d_j
+            const double s = i < cols ? d[0] / d[i + 1] : 0.0;
+            yr[i] = zr[i] * s;
+            yi[i] = zi[i] * s;
         }
     }
-    double rr[M], ri[M], zr[M], zi[M];
-    for (int i = 0; i < cols; ++i) {
-        const double s = 1.0 / (d[i + 1] * d[0]);
-        rr[i] = gr[i + 1][0] * s;
-        ri[i] = gi[i + 1][0] * s;
-    }
-    for (int i = 0; i < cols; ++i) {  // L z = r
-        double sr = rr[i], si = ri[i];
-        for (int q = 0; q < i; ++q) {
-            sr -= Lr[i][q] * zr[q] - Li[i][q] * zi[q];
-            si -= Lr[i][q] * zi[q] + Li[i][q] * zr[q];
-        }
-        zr[i] = sr / Lr[i][i];
-        zi[i] = si / Lr[i][i];
-    }
-    for (int i = cols - 1; i >= 0; --i) {  // L^H c' = z
-        double sr = zr[i], si = zi[i];
-        for (int q = i + 1; q < cols; ++q) {  // conj(L(q,i)) c'_q
-            sr -= Lr[q][i] * zr[q] + Li[q][i] * zi[q];
-            si -= Lr[q][i] * zi[q] - Li[q][i] * zr[q];
-        }
-        zr[i] = sr / Lr[i][i];
-        zi[i] = si / Lr[i][i];
-    }
-    for (int i = 0; i < cols; ++i) {  // c_j = c'_j d_0 / d_j
-        const double s = d[0] / d[i + 1];
-        K->y[2 * i] = zr[i] * s;
-        K->y[2 * i + 1] = zi[i] * s;
+    K->beta = beta;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        K->y[2 * i] = yr[i];
+        K->y[2 * i + 1] = yi[i];
     }
     K->cols = cols;
-    K->done = 1;
+    K->done = isfinite(beta) ? 1 : 2;
 }
 
 // Pass 2: x_out = x0 + sum_{j=1..cols} c_j K_{j-1} on the tile interior.

@@ -32,12 +32,12 @@ def _rand(rng, n):
     return torch.as_tensor(v)
 
 
-def make_pair(case, prec, gmres_arnoldi=0, **kw):
+def make_pair(case, prec, gmres_arnoldi=0, tail_n=64, **kw):
     from paper_2404_02493_amd import Helmholtz
 
     P = Problem(case.velocity, case.k, case.levels, damping_cells=case.damping_cells, phi=case.phi, **kw)
     H = Helmholtz(case.velocity, case.k, levels=case.levels, precision=prec, damping_cells=case.damping_cells,
-                  gmres_arnoldi=gmres_arnoldi, **{k: int(v) for k, v in kw.items()})
+                  gmres_arnoldi=gmres_arnoldi, tail_n=tail_n, **{k: int(v) for k, v in kw.items()})
     H.set_phase(case.phi)
     H.set_weights(P.weights.numpy())
     return P, H
@@ -69,13 +69,16 @@ def test_default_weights_match_oracle(small_case, prec):
     H.close()
 
 
-@pytest.mark.parametrize("arnoldi", [0, 1])
+@pytest.mark.parametrize("form", ["sstep", "arnoldi", "tail"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_operator_parity(small_case, prec, arnoldi):
-    """Every internal operator on identical inputs; arnoldi=1 forces the Arnoldi
-    form of the GMRES smoother, 0 uses the s-step form on levels < L."""
+def test_operator_parity(small_case, prec, form):
+    """Every internal operator on identical inputs, for each form of the ADR
+    smoother: s-step GMRES on separate kernels ("sstep"), Arnoldi GMRES on
+    separate kernels ("arnoldi"), and the default: s-step GMRES with the coarsest
+    ADR level's GMRES in one workgroup ("tail")."""
     c = small_case
-    P, H = make_pair(c, prec, gmres_arnoldi=arnoldi)
+    arnoldi, tail_n = {"sstep": (0, 0), "arnoldi": (1, 0), "tail": (0, 64)}[form]
+    P, H = make_pair(c, prec, gmres_arnoldi=arnoldi, tail_n=tail_n)
     rng = np.random.default_rng(0)
     tol = TOL[prec]
     cd = H.cdtype
