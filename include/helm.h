@@ -128,17 +128,35 @@ helm_status helm_solve(helm_ctx ctx, const void* g, void* u, double tol, int32_t
 helm_status helm_residual(helm_ctx ctx, const void* g, const void* u, void* r, double* rnorm,
                           double* gnorm, void* stream);
 
-/* Adjoint of K unrolled cycles (paper Section 3.3: the training loss after K cycles
- * and its back-propagation).  Given u_0 (device, cycle_prec, NULL = zero) and the
- * gradient of a real loss with respect to u_K in torch's convention for complex
- * tensors (grad_uK = 2 dL/d conj(u_K)), accumulates dL/dphi (device, n*n float for
- * cycle_prec C64, double for C128, overwritten) and dL/dw (device, `levels`
- * doubles, overwritten).  ckpt_ws: device workspace of K*n*n complex elements in
- * cycle_prec for the per-cycle checkpoints, or NULL for a library-owned buffer
- * (allocated on first use). */
+/* Adjoint of K unrolled cycles (Section 3.3: the training loss after K cycles,
+ * eq. loss, and its back-propagation; Algorithm 1 reversed).
+ *   u_{k+1} = C(u_k, g), k = 0..K-1, from u_0 (device, cycle_prec, NULL = zero).
+ *   grad_uK  (device, cycle_prec, n*n complex): the cotangent of u_K in torch's
+ *            convention for complex tensors, dL/dRe(u_K) + i dL/dIm(u_K).
+ *   grad_phi (device, n*n, overwritten): dL/dphi for the fine phase last passed to
+ *            helm_set_phase; float for cycle_prec HELM_C64, double for HELM_C128.
+ *            The phase enters only through its injection to the ADR levels, so the
+ *            entries off the level-2 lattice (odd fine indices) are zero.
+ *   grad_w   (device, `levels` doubles, overwritten): dL/dw for the weights of
+ *            helm_set_weights (w[0] Jacobi, w[l-1] Chebyshev alpha of level l).
+ *   ckpt_ws  device workspace of K*n*n complex elements in cycle_prec for the
+ *            per-cycle checkpoints, or NULL for a library-owned buffer.
+ * The call re-runs the K cycles (checkpointing u_0..u_{K-1}), then reverses them
+ * one at a time, re-recording each cycle's intermediates on a library-owned tape
+ * (allocated on the first call, about 4 + 4*adr_steps fine-grid vectors).
+ * Requires gmres_m, gmres_coarse_m <= 6 (HELM_EINVAL otherwise) and the phase
+ * (HELM_ESTATE otherwise).  Asynchronous on `stream`. */
 helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const void* u0,
                                 const void* grad_uK, void* grad_phi, double* grad_w, void* ckpt_ws,
                                 void* stream);
+
+/* Loss of the unrolled cycles (Section 3.3, eq. loss, without the normalisation by
+ * ||g||^2): *loss = ||g - A u||^2 accumulated in FP64 from g, u (device, cycle_prec);
+ * if grad_u (device, cycle_prec) is not NULL it receives the cotangent
+ * -2 A^H (g - A u) in the convention of helm_cycle_backward.  Synchronises the
+ * stream (the loss is returned on the host). */
+helm_status helm_loss(helm_ctx ctx, const void* g, const void* u, double* loss, void* grad_u,
+                      void* stream);
 
 /* Internal operators, exposed for step-by-step parity tests.  op codes:
  *   1  out = A_l in              (level l, cycle_prec complex)

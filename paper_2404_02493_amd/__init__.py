@@ -152,6 +152,38 @@ class Helmholtz:
                                   _stream_ptr(stream)))
         return r, rn.value, gn.value
 
+    # ------------------------------------------------------------------ unrolled cycles and their adjoint
+    def loss(self, g, u, grad: bool = False, stream=None):
+        """L = ||g - A u||^2 (FP64) for cycle-dtype device grids g, u; with grad=True also
+        dL/du in torch's complex convention.  Returns (L, grad_u or None)."""
+        torch = _torch()
+        gu = torch.empty_like(u) if grad else None
+        val = ctypes.c_double()
+        check(lib().helm_loss(self._ctx, _ptr(g), _ptr(u), ctypes.byref(val), _ptr(gu), _stream_ptr(stream)))
+        return val.value, gu
+
+    def cycle_backward(self, K: int, g, grad_uK, u0=None, ckpt=None, stream=None):
+        """Cotangents of the phase and of the weights for u_K = C^K(u_0, g), given the
+        cotangent of u_K.  Returns (grad_phi (n, n) device tensor, grad_w (levels,)
+        float64 device tensor)."""
+        torch = _torch()
+        pdt = torch.float32 if self.cdtype == torch.complex64 else torch.float64
+        gphi = torch.empty((self.n, self.n), dtype=pdt, device=self.device)
+        gw = torch.empty((self.levels,), dtype=torch.float64, device=self.device)
+        check(lib().helm_cycle_backward(self._ctx, int(K), _ptr(g), _ptr(u0), _ptr(grad_uK), _ptr(gphi), _ptr(gw),
+                                        _ptr(ckpt), _stream_ptr(stream)))
+        return gphi, gw
+
+    def unrolled(self, phi, w, g, K: int):
+        """u_K after K cycles from u_0 = 0 as a differentiable function of the phase phi
+        (n x n tensor) and the weights w (levels float64 tensor); g is a cycle-dtype
+        device grid.  Gradients come from the hand-written adjoint (helm_cycle_backward)."""
+        return _Unrolled.apply(phi, w, g, self, int(K))
+
+    def residual_loss(self, g, u):
+        """Differentiable L = ||g - A u||^2 (float64 device scalar) of a cycle-dtype grid u."""
+        return _Loss.apply(u, g, self)
+
     def debug_op(self, op: int, level: int, x=None, x2=None, out=None, out_shape_level=None, out_dtype=None,
                  stream=None):
         """Runs one internal operator (see helm_debug_op in include/helm.h)."""
@@ -178,3 +210,58 @@ class Helmholtz:
         if level == self.levels:
             return torch.complex128
         return self.cdtype
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class Unrolled(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, phi, w, g, helm, K):
+            helm.set_phase(phi.detach())
+            helm.set_weights([float(x) for x in w.detach().cpu().tolist()])
+            u = torch.zeros_like(g)
+            for _ in range(K):
+                helm.cycle(g, u)
+            ctx.helm, ctx.K = helm, K
+            ctx.phi_meta = (phi.dtype, phi.device)
+            ctx.w_meta = (w.dtype, w.device)
+            ctx.save_for_backward(g)
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            (g,) = ctx.saved_tensors
+            helm = ctx.helm
+            gphi, gw = helm.cycle_backward(ctx.K, g, grad_u.contiguous().to(g.dtype))
+            return (gphi.to(dtype=ctx.phi_meta[0], device=ctx.phi_meta[1]),
+                    gw.to(dtype=ctx.w_meta[0], device=ctx.w_meta[1]), None, None, None)
+
+    class Loss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, u, g, helm):
+            val, gu = helm.loss(g, u.contiguous(), grad=True)
+            ctx.save_for_backward(gu)
+            return torch.tensor(val, dtype=torch.float64, device=u.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (gu,) = ctx.saved_tensors
+            return gu * grad_out.to(gu.real.dtype), None, None
+
+    return Unrolled, Loss
+
+
+class _Lazy:
+    def __init__(self, idx):
+        self.idx = idx
+        self.cls = None
+
+    def apply(self, *args):
+        if self.cls is None:
+            self.cls = _autograd_function()[self.idx]
+        return self.cls.apply(*args)
+
+
+_Unrolled = _Lazy(0)
+_Loss = _Lazy(1)

@@ -15,7 +15,7 @@ STATUS = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP", 4: "
 
 # every symbol declared in include/helm.h
 EXPORTS = ["helm_desc_default", "helm_setup", "helm_set_phase", "helm_set_weights", "helm_get_weights",
-           "helm_get_lambdas", "helm_cycle", "helm_solve", "helm_residual", "helm_cycle_backward",
+           "helm_get_lambdas", "helm_cycle", "helm_solve", "helm_residual", "helm_cycle_backward", "helm_loss",
            "helm_debug_op", "helm_profile_begin", "helm_profile_end", "helm_destroy", "helm_status_string", "helm_last_error", "helm_version"]
 
 
@@ -87,6 +87,8 @@ def lib():
     L.helm_residual.argtypes = [vp, vp, vp, vp, P(dbl), P(dbl), vp]
     L.helm_cycle_backward.restype = i32
     L.helm_cycle_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.helm_loss.restype = i32
+    L.helm_loss.argtypes = [vp, vp, vp, P(dbl), vp, vp]
     L.helm_debug_op.restype = i32
     L.helm_debug_op.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.helm_profile_begin.restype = i32

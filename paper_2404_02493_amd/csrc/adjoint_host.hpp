@@ -1,0 +1,523 @@
+// Host side of the adjoint of K unrolled cycles (Section 3.3: the loss after K
+// cycles and its back-propagation to the phase and to the smoother weights).
+//
+// Strategy: the K forward cycles are re-run from u_0 and every iterate u_k is
+// kept (one checkpoint per cycle).  Then, for k = K-1 .. 0, cycle k is run once
+// more from u_k while a tape records what its reverse needs (the inputs of the
+// smoothers, the ADR right-hand sides and iterates, and for every GMRES call the
+// monomial Krylov basis and its least-squares coefficients), and the cycle is
+// reversed from the tape: u_k's cotangent from u_{k+1}'s, with the cotangents of
+// the weights, of the ADR coefficients phi_x, phi_y, c0 and of the carrier phase
+// accumulated on the way.  At the end those are pulled back to the fine phase.
+//
+// Included from helm.hip inside namespace helm (uses its context, LAUNCH, Engine).
+#pragma once
+
+struct AdrTape {  // one GMRES-smoothed ADR level inside one ADR step
+    void* b = nullptr;
+    void* x1 = nullptr;
+    void* x2 = nullptr;
+    void* xo = nullptr;
+    void* kpre[GMAX + 1] = {};
+    void* kpost[GMAX + 1] = {};
+    GRec* rpre = nullptr;
+    GRec* rpost = nullptr;
+};
+
+struct AdjState {
+    bool ready = false;
+    int M = 0;
+    void* uB = nullptr;                      // level 1: input of the post-Jacobi sweep
+    void* fb[2] = {};                        // level-1 cotangents
+    std::vector<void*> g, ub;                // wave levels: right-hand side, input of the post-smoother
+    std::vector<void*> lub, lgb;             // cotangent of the level's output / of its right-hand side
+    std::vector<std::array<void*, 9>> cs;    // Chebyshev reverse scratch
+    std::vector<std::vector<AdrTape>> adr;   // [step][level]
+    std::vector<void*> axb, axb2, abb, acc0, acc1;  // ADR cotangents per level
+    std::vector<double*> pxb, pyb;
+    std::vector<c128*> c0b;
+    double* thb = nullptr;                   // carrier phase cotangent (level 2)
+    double* phib2 = nullptr;                 // phase cotangent on the level-2 lattice
+    void* rbar2 = nullptr;
+    double* wacc = nullptr;                  // weight cotangents (FP64, device)
+    void* ckpt = nullptr;                    // library-owned checkpoints
+    size_t ckpt_bytes = 0;
+};
+
+static void dfree(helm_ctx c, void* p) {
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+static int gm_of(helm_ctx c, int l) { return l == c->LA ? c->d.gmres_coarse_m : c->d.gmres_m; }
+
+static void adj_alloc(helm_ctx c, hipStream_t st) {
+    AdjState& S = *c->adj;
+    if (S.ready) return;
+    const int n = c->d.n, L = c->L;
+    const bool f64c = !c->f32;
+    const size_t NF = (size_t)n * n;
+    const bool adr_on = c->d.adr_steps > 0 && L >= 3;
+    S.M = adr_on ? c->d.adr_steps : 0;
+    S.uB = dalloc(c, NF * csize(f64c));
+    S.fb[0] = dalloc(c, NF * csize(f64c));
+    S.fb[1] = dalloc(c, NF * csize(f64c));
+    S.g.assign(L + 1, nullptr);
+    S.ub.assign(L + 1, nullptr);
+    S.lub.assign(L + 1, nullptr);
+    S.lgb.assign(L + 1, nullptr);
+    S.cs.assign(L + 1, {});
+    for (int l = 2; l <= L; ++l) {
+        const size_t Nl = (size_t)(n >> (l - 1)) * (n >> (l - 1));
+        const size_t cb = Nl * csize(c->wl[l].f64);
+        S.g[l] = dalloc(c, cb);
+        if (l < L) S.ub[l] = dalloc(c, cb);
+        S.lub[l] = dalloc(c, cb);
+        S.lgb[l] = dalloc(c, cb);
+        for (int q = 0; q < 9; ++q) S.cs[l][q] = dalloc(c, cb);
+    }
+    S.wacc = (double*)dalloc(c, 64 * sizeof(double));
+    if (adr_on) {
+        S.adr.assign(S.M, std::vector<AdrTape>(c->LA + 1));
+        S.axb.assign(c->LA + 1, nullptr);
+        S.axb2.assign(c->LA + 1, nullptr);
+        S.abb.assign(c->LA + 1, nullptr);
+        S.acc0.assign(c->LA + 1, nullptr);
+        S.acc1.assign(c->LA + 1, nullptr);
+        S.pxb.assign(c->LA + 1, nullptr);
+        S.pyb.assign(c->LA + 1, nullptr);
+        S.c0b.assign(c->LA + 1, nullptr);
+        const int nrec = S.M * c->LA * 2;
+        GRec* recs = (GRec*)dalloc(c, (size_t)nrec * sizeof(GRec));
+        std::vector<GRec> hrec(nrec);
+        std::memset(hrec.data(), 0, hrec.size() * sizeof(GRec));
+        int ri = 0;
+        for (int l = 2; l <= c->LA; ++l) {
+            const size_t Nl = (size_t)(n >> (l - 1)) * (n >> (l - 1));
+            const size_t cb = Nl * csize(f64c);
+            S.axb[l] = dalloc(c, cb);
+            S.axb2[l] = dalloc(c, cb);
+            S.abb[l] = dalloc(c, cb);
+            S.acc0[l] = dalloc(c, cb);
+            S.acc1[l] = dalloc(c, cb);
+            S.pxb[l] = (double*)dalloc(c, Nl * sizeof(double));
+            S.pyb[l] = (double*)dalloc(c, Nl * sizeof(double));
+            S.c0b[l] = (c128*)dalloc(c, Nl * sizeof(c128));
+            const int m = gm_of(c, l);
+            for (int s = 0; s < S.M; ++s) {
+                AdrTape& T = S.adr[s][l];
+                T.b = dalloc(c, cb);
+                T.xo = dalloc(c, cb);
+                for (int q = 0; q <= m; ++q) T.kpre[q] = dalloc(c, cb);
+                hrec[ri].m = m;
+                T.rpre = recs + ri++;
+                if (l < c->LA) {
+                    T.x1 = dalloc(c, cb);
+                    T.x2 = dalloc(c, cb);
+                    for (int q = 0; q <= m; ++q) T.kpost[q] = dalloc(c, cb);
+                    hrec[ri].m = m;
+                    T.rpost = recs + ri++;
+                }
+            }
+        }
+        HIPCHK(hipMemcpyAsync(recs, hrec.data(), hrec.size() * sizeof(GRec), hipMemcpyHostToDevice, st));
+        const size_t N2 = (size_t)(n / 2) * (n / 2);
+        S.thb = (double*)dalloc(c, N2 * sizeof(double));
+        S.phib2 = (double*)dalloc(c, N2 * sizeof(double));
+        S.rbar2 = dalloc(c, N2 * csize(f64c));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    S.ready = true;
+}
+
+template <typename T>
+struct AdjEngine {
+    helm_ctx c;
+    hipStream_t st;
+    Engine<T> E;
+    AdjState& S;
+    using C = cplx<T>;
+
+    AdjEngine(helm_ctx ctx, hipStream_t s) : c(ctx), st(s), E(ctx, s), S(*ctx->adj) {}
+
+    size_t N(int l) const { return E.N(l); }
+    int fb(size_t n) const { return flat_blocks(n); }
+    double tau(int l) const { return 8.0 * c->al[l].A.inv_h2; }
+
+    template <typename F>
+    void prec(int l, F&& f) {
+        if (c->wl[l].f64) f(double{});
+        else f(T{});
+    }
+    void copy(void* dst, const void* src, size_t bytes) {
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+    }
+    void fin_add(int nblk, int slot) {
+        LAUNCH(c, 8.0 * nblk, (k_finalize_add<1>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nblk, 1, 1.0,
+               S.wacc + slot);
+    }
+
+    // ------------------------------------------------------------ record (forward with tape)
+    void rec_cycle(const void* g, const void* u0) {
+        WaveLevel& W = c->wl[1];
+        const Geom& G = W.G;
+        LAUNCH(c, ((u0 ? 3 : 2) * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(),
+               st, G, (const T*)W.n2, (const C*)g, (const C*)u0, (C*)S.uB, T(c->w[0]));
+        E.restrict_down(1, g, S.uB, S.g[2]);
+        rec_level(2);
+        E.prolong_up(1, c->wl[2].u, S.uB);
+    }
+
+    void rec_level(int l) {
+        WaveLevel& W = c->wl[l];
+        const int L = c->L;
+        const size_t cb = N(l) * csize(W.f64);
+        if (l == L) {
+            E.template chebyshev<double>(l, S.g[l], W.u, true, c->w[l - 1], c->d.cheb_coarse);
+            return;
+        }
+        if (l == 3) {
+            E.restrict_down(l, S.g[l], nullptr, S.g[l + 1]);
+        } else {
+            E.template chebyshev<T>(l, S.g[l], W.u, true, c->w[l - 1], c->d.cheb_pre);
+            E.restrict_down(l, S.g[l], W.u, S.g[l + 1]);
+        }
+        rec_level(l + 1);
+        if (l == 3) E.template zero<T>(W.u, N(l));
+        E.prolong_up(l, c->wl[l + 1].u, W.u);
+        if (l != 3 || c->d.level3_literal) {
+            copy(S.ub[l], W.u, cb);
+            E.template chebyshev<T>(l, S.g[l], W.u, false, c->w[l - 1], c->d.cheb_post);
+        }
+        if (l == 2)
+            for (int s = 0; s < S.M; ++s) rec_adr_step(s);
+    }
+
+    void rec_adr_step(int s) {
+        WaveLevel& W = c->wl[2];
+        AdrTape& Tp = S.adr[s][2];
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st,
+               W.G, (const T*)W.n2, (const C*)S.g[2], (const C*)W.u, (const T*)c->theta2, (C*)Tp.b);
+        rec_adrv(s, 2);
+        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
+               (const C*)Tp.xo, (const T*)c->theta2, (C*)W.u);
+    }
+
+    void rec_adrv(int s, int l) {
+        AdrTape& Tp = S.adr[s][l];
+        AdrLevel& A = c->al[l];
+        if (l == c->LA) {
+            rec_gmres(l, Tp.b, nullptr, gm_of(c, l), Tp.kpre, Tp.rpre, Tp.xo);
+            return;
+        }
+        const int m = gm_of(c, l);
+        rec_gmres(l, Tp.b, nullptr, m, Tp.kpre, Tp.rpre, Tp.x1);
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_adr_resid_restrict<T>), dim3(tiles_of(A.n / 2)),
+               tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)Tp.b,
+               (const C*)Tp.x1, (C*)S.adr[s][l + 1].b);
+        rec_adrv(s, l + 1);
+        copy(Tp.x2, Tp.x1, N(l) * sizeof(C));
+        LAUNCH(c, 3 * sizeof(C) * NN(A.n), (k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), st, A.n,
+               (const C*)S.adr[s][l + 1].xo, (C*)Tp.x2);
+        rec_gmres(l, Tp.b, Tp.x2, m, Tp.kpost, Tp.rpost, Tp.xo);
+    }
+
+    void rec_gmres(int l, const void* b, const void* x0, int m, void* const* kv, GRec* R, void* xout) {
+        AdrLevel& A = c->al[l];
+        const size_t n = N(l);
+        const int nb = fb(n);
+        VecSet<T> K{};
+        for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
+        LAUNCH(c, (x0 ? 4.0 : 2.0) * sizeof(C) * n, (k_gr_r0<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
+               (const T*)A.py, (const C*)A.c0, (const C*)b, (const C*)x0, (C*)kv[0], c->partials);
+        double* gram = R->gram;  // device address arithmetic only
+        LAUNCH(c, 16.0 * nb, (k_finalize_sums<2>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, 2, gram);
+        for (int jj = 1; jj <= m; ++jj) {
+            LAUNCH(c, (jj + 2.0) * sizeof(C) * n, (k_gr_chain<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
+                   (const T*)A.py, (const C*)A.c0, K, jj, 1.0 / tau(l), (C*)kv[jj], c->partials);
+            LAUNCH(c, 16.0 * nb * (jj + 1), (k_finalize_sums<2 * (GMAX + 1)>), dim3(1), dim3(FBLOCK), st,
+                   (const double*)c->partials, nb, 2 * (jj + 1), gram + 2 * (jj * (jj + 1) / 2));
+        }
+        LAUNCH(c, 0.0, k_gr_solve, dim3(1), dim3(64), st, R, tau(l));
+        LAUNCH(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n, K, m,
+               (const GRec*)R, (const C*)x0, (C*)xout);
+    }
+
+    // ------------------------------------------------------------ reverse
+    // fb[0] holds the cotangent of u_{k+1} on entry and that of u_k on exit.
+    void rev_cycle(const void* g, const void* u0) {
+        WaveLevel& W = c->wl[1];
+        const Geom& G = W.G;
+        const size_t NF = N(1);
+        const int nb = fb(NF);
+        LAUNCH(c, (5.0 * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G, (const T*)W.n2,
+               (const C*)g, (const C*)S.uB, (const C*)S.fb[0], (C*)S.fb[1], T(c->w[0]), c->partials);
+        fin_add(nb, 0);
+        restrict_adj(1, S.fb[1], S.lub[2]);
+        rev_level(2);
+        prolong_adj(1, S.lgb[2], S.fb[1], nullptr);
+        LAUNCH(c, ((u0 ? 5.0 : 4.0) * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G,
+               (const T*)W.n2, (const C*)g, (const C*)u0, (const C*)S.fb[1], (C*)S.fb[0], T(c->w[0]), c->partials);
+        fin_add(nb, 0);
+    }
+
+    // out (level l+1) = 4 R x (level l): the cotangent of a coarse correction.
+    void restrict_adj(int l, const void* x, void* out) {
+        const int n = c->wl[l].n;
+        const size_t nc = N(l + 1);
+        auto go = [&](auto tf, auto tc) {
+            using Pf = decltype(tf);
+            using Pc = decltype(tc);
+            LAUNCH(c, sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * double(nc), (k_restrict_scale<Pf, Pc>),
+                   dim3(fb(nc)), dim3(BLOCK), st, n, (const cplx<Pf>*)x, (cplx<Pc>*)out, 4.0);
+        };
+        if (c->wl[l].f64) go(double{}, double{});
+        else if (c->wl[l + 1].f64) go(T{}, double{});
+        else go(T{}, T{});
+    }
+    // reverse of rc = R (g - A u) on level l: gbar += P rcbar/4, ubar -= A^H P rcbar/4
+    void prolong_adj(int l, const void* rcbar, void* ubar, void* gbar) {
+        WaveLevel& W = c->wl[l];
+        const size_t n = N(l);
+        auto go = [&](auto tf, auto tc) {
+            using Pf = decltype(tf);
+            using Pc = decltype(tc);
+            LAUNCH(c, (3.0 * sizeof(cplx<Pf>) + sizeof(Pf)) * n + sizeof(cplx<Pc>) * double(N(l + 1)),
+                   (k_prolong_adj<Pc, Pf>), dim3(fb(n)), dim3(BLOCK), st, W.G, (const Pf*)W.n2,
+                   (const cplx<Pc>*)rcbar, (cplx<Pf>*)ubar, (cplx<Pf>*)gbar);
+        };
+        if (W.f64) go(double{}, double{});
+        else if (c->wl[l + 1].f64) go(T{}, double{});
+        else go(T{}, T{});
+    }
+
+    // Reverse of m Chebyshev steps u' = u + q(N) A^H (g - A u) on level l (u == null:
+    // from zero).  ubar holds u''s cotangent on entry and u's on exit; gbar += A q(N) ubar';
+    // wacc[l-1] += Re <q_alpha(N) ubar', A^H (g - A u)>.
+    template <typename P>
+    void cheb_adj(int l, const void* g, const void* u, void* ubar, void* gbar, double alpha, int m) {
+        using Cp = cplx<P>;
+        WaveLevel& W = c->wl[l];
+        const Geom& G = W.G;
+        const size_t n = N(l);
+        const int nb = fb(n);
+        auto& B = S.cs[l];
+        Cp *r = (Cp*)B[0], *rt = (Cp*)B[1], *d = (Cp*)B[2], *dt = (Cp*)B[3], *s = (Cp*)B[4], *stt = (Cp*)B[5];
+        Cp *t1 = (Cp*)B[6], *t2 = (Cp*)B[7], *res = (Cp*)B[8];
+        const double lam = W.lam;
+        const double a = lam / alpha;
+        const double th = 0.5 * (lam + a), dc = 0.5 * (lam - a);
+        const double th_t = -lam / (2.0 * alpha * alpha), dc_t = lam / (2.0 * alpha * alpha);
+        double rho = dc / th, rho_t = (dc_t * th - dc * th_t) / (th * th);
+        LAUNCH(c, 7.0 * sizeof(Cp) * n, (k_chebadj_start<P>), dim3(nb), dim3(BLOCK), st, n, (const Cp*)ubar, r, rt, d,
+               dt, s, stt, P(1.0 / th), P(-th_t / (th * th)));
+        for (int t = 1; t < m; ++t) {
+            LAUNCH(c, (4.0 * sizeof(Cp) + sizeof(P)) * n, (k_apply_A2<P>), dim3(nb), dim3(BLOCK), st, G,
+                   (const P*)W.n2, (const Cp*)d, (const Cp*)dt, t1, t2);
+            const double den = 2.0 * th - dc * rho;
+            const double den_t = 2.0 * th_t - dc_t * rho - dc * rho_t;
+            const double rn = dc / den, rn_t = (dc_t * den - dc * den_t) / (den * den);
+            const double c1 = rn * rho, c1t = rn_t * rho + rn * rho_t;
+            const double c2 = 2.0 / den, c2t = -2.0 * den_t / (den * den);
+            LAUNCH(c, (14.0 * sizeof(Cp) + sizeof(P)) * n, (k_chebadj_step<P>), dim3(nb), dim3(BLOCK), st, G,
+                   (const P*)W.n2, (const Cp*)t1, (const Cp*)t2, r, rt, d, dt, s, stt, P(c1), P(c2), P(c1t), P(c2t));
+            rho = rn;
+            rho_t = rn_t;
+        }
+        E.template residual<P>(G, W.n2, g, u, res);
+        LAUNCH(c, (2.0 * sizeof(Cp) + sizeof(P)) * n, (k_dot_ah<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,
+               (const Cp*)stt, (const Cp*)res, c->partials);
+        fin_add(nb, l - 1);
+        E.template applyA<P>(G, W.n2, s, t1, 0);
+        LAUNCH(c, (5.0 * sizeof(Cp) + sizeof(P)) * n, (k_adj_ahsub<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,
+               (const Cp*)t1, (Cp*)(u ? ubar : nullptr), (Cp*)gbar);
+    }
+
+    void rev_level(int l) {
+        WaveLevel& W = c->wl[l];
+        const int L = c->L;
+        const size_t n = N(l);
+        prec(l, [&](auto tag) {
+            using P = decltype(tag);
+            E.template zero<P>(S.lgb[l], n);
+        });
+        if (l == L) {
+            cheb_adj<double>(l, S.g[l], nullptr, S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_coarse);
+            return;
+        }
+        if (l == 2)
+            for (int s = S.M - 1; s >= 0; --s) rev_adr_step(s);
+        if (l != 3 || c->d.level3_literal)
+            cheb_adj<T>(l, S.g[l], S.ub[l], S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_post);
+        restrict_adj(l, S.lub[l], S.lub[l + 1]);
+        rev_level(l + 1);
+        prolong_adj(l, S.lgb[l + 1], l == 3 ? nullptr : S.lub[l], S.lgb[l]);
+        if (l != 3) cheb_adj<T>(l, S.g[l], nullptr, S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_pre);
+        (void)W;
+    }
+
+    void rev_adr_step(int s) {
+        WaveLevel& W = c->wl[2];
+        AdrTape& Tp = S.adr[s][2];
+        const size_t n = N(2);
+        LAUNCH(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_modadd_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
+               (const C*)S.lub[2], (const C*)Tp.xo, (const T*)c->theta2, (C*)S.axb[2], S.thb);
+        rev_adrv(s, 2);
+        LAUNCH(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_demod_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
+               (const C*)S.abb[2], (const C*)Tp.b, (const T*)c->theta2, (C*)S.rbar2, S.thb);
+        LAUNCH(c, (5.0 * sizeof(C) + sizeof(T)) * n, (k_adj_ahsub<T>), dim3(fb(n)), dim3(BLOCK), st, W.G,
+               (const T*)W.n2, (const C*)S.rbar2, (C*)S.lub[2], (C*)S.lgb[2]);
+    }
+
+    void rev_adrv(int s, int l) {
+        AdrTape& Tp = S.adr[s][l];
+        AdrLevel& A = c->al[l];
+        const int m = gm_of(c, l);
+        if (l == c->LA) {
+            rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb[l], S.abb[l], true, nullptr);
+            return;
+        }
+        rev_gmres(l, Tp.x2, m, Tp.kpost, Tp.rpost, S.axb[l], S.abb[l], true, S.axb2[l]);
+        const size_t nc = N(l + 1);
+        LAUNCH(c, sizeof(C) * (double(N(l)) + nc), (k_restrict_scale<T, T>), dim3(fb(nc)), dim3(BLOCK), st, A.n,
+               (const C*)S.axb2[l], (C*)S.axb[l + 1], 4.0);
+        rev_adrv(s, l + 1);
+        LAUNCH(c, (6.0 * sizeof(C) + 2 * sizeof(T) + 32.0 * 2) * NN(A.n), (k_adr_rr_adj<T>), dim3(fb(N(l))),
+               dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)S.abb[l + 1],
+               (const C*)Tp.x1, (C*)S.axb2[l], (C*)S.abb[l], S.pxb[l], S.pyb[l], S.c0b[l]);
+        rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb2[l], S.abb[l], false, nullptr);
+    }
+
+    // Reverse of x = GMRES(M_l; b, x0, m) from the recorded basis kv and record R:
+    // bbar (=|+=) the cotangent of b; xbar0 (if x0) = that of x0.
+    void rev_gmres(int l, const void* x0, int m, void* const* kv, GRec* R, const void* xbar, void* bbar, bool bset,
+                   void* xbar0) {
+        AdrLevel& A = c->al[l];
+        const size_t n = N(l);
+        const int nb = fb(n);
+        VecSet<T> K{};
+        for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
+        LAUNCH(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
+               c->partials);
+        LAUNCH(c, 16.0 * nb * m, (k_finalize_sums<2 * GMAX>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb,
+               2 * m, (double*)R->cbar);
+        LAUNCH(c, 0.0, k_ga_prep, dim3(1), dim3(64), st, R, tau(l));
+        VecSet<T> V{};
+        V.v[0] = (const C*)xbar;
+        for (int q = 0; q <= m; ++q) V.v[q + 1] = (const C*)kv[q];
+        const int nv = m + 2;
+        C* acc = (C*)S.acc0[l];
+        C* nxt = (C*)S.acc1[l];
+        const double* coef = R->coef;
+        const double gbytes = 32.0 * 2 + sizeof(C);  // coefficient cotangents (read-modify-write) and a
+        LAUNCH(c, (nv + 1.0) * sizeof(C) * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
+               (const T*)A.py, (const C*)A.c0, V, nv, coef + m * GCOEF_STRIDE, (const C*)nullptr, 0.0,
+               (const C*)nullptr, acc, S.pxb[l], S.pyb[l], S.c0b[l]);
+        for (int j = m + 1; j >= 2; --j) {
+            LAUNCH(c, ((nv + 2.0) * sizeof(C) + 2 * sizeof(T)) * n + gbytes * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK),
+                   st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, V, nv, coef + (j - 2) * GCOEF_STRIDE,
+                   (const C*)acc, 1.0 / tau(l), (const C*)kv[j - 2], nxt, S.pxb[l], S.pyb[l], S.c0b[l]);
+            std::swap(acc, nxt);
+        }
+        if (bset) copy(bbar, acc, n * sizeof(C));
+        else LAUNCH(c, 3.0 * sizeof(C) * n, (k_axpy<T>), dim3(nb), dim3(BLOCK), st, n, T(1), (const C*)acc, (C*)bbar);
+        if (x0) {
+            VecSet<T> V1{};
+            V1.v[0] = (const C*)xbar;
+            LAUNCH(c, (4.0 * sizeof(C) + 2 * sizeof(T)) * n + gbytes * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK), st,
+                   A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, V1, 1, (const double*)R->one, (const C*)acc,
+                   -1.0, (const C*)x0, (C*)xbar0, S.pxb[l], S.pyb[l], S.c0b[l]);
+        }
+    }
+
+    // Cotangent of the fine phase from the accumulated coefficient cotangents.
+    template <typename TO>
+    void phase_out(void* grad_phi) {
+        const int n = c->d.n;
+        const size_t NF = N(1);
+        if (S.M > 0) {
+            for (int l = 2; l <= c->LA; ++l) {
+                const int nl = n >> (l - 1);
+                LAUNCH(c, (2.0 * sizeof(T) + 32.0 + 16.0) * NN(nl), (k_phi_adj<T>), dim3(fb(N(l))), dim3(BLOCK), st, nl,
+                       1 << (l - 2), n / 2, c->d.k, c->d.sign, (const T*)c->al[l].px, (const T*)c->al[l].py,
+                       (const double*)S.pxb[l], (const double*)S.pyb[l], (const c128*)S.c0b[l],
+                       (const double*)(l == 2 ? S.thb : nullptr), S.phib2);
+            }
+            LAUNCH(c, (sizeof(TO) + 2.0) * NF, (k_phi_out<TO>), dim3(fb(NF)), dim3(BLOCK), st, n,
+                   (const double*)S.phib2, (TO*)grad_phi);
+        } else {
+            HIPCHK(hipMemsetAsync(grad_phi, 0, NF * sizeof(TO), st));
+        }
+    }
+};
+
+// Checkpointed forward, then the reverse sweep over the K cycles.
+template <typename T>
+static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, const void* grad_uK, void* grad_phi,
+                           double* grad_w, void* ckpt_ws, hipStream_t st) {
+    if (!c->adj) c->adj = new AdjState();
+    adj_alloc(c, st);
+    AdjState& S = *c->adj;
+    const size_t NF = (size_t)c->d.n * c->d.n;
+    const size_t vb = NF * sizeof(cplx<T>);
+    char* ck = (char*)ckpt_ws;
+    if (!ck) {
+        if (S.ckpt_bytes < (size_t)K * vb) {
+            dfree(c, S.ckpt);
+            S.ckpt = nullptr;
+            S.ckpt_bytes = 0;
+            S.ckpt = dalloc(c, (size_t)K * vb);
+            S.ckpt_bytes = (size_t)K * vb;
+        }
+        ck = (char*)S.ckpt;
+    }
+    // zero the accumulators
+    HIPCHK(hipMemsetAsync(S.wacc, 0, 64 * sizeof(double), st));
+    if (S.M > 0) {
+        for (int l = 2; l <= c->LA; ++l) {
+            const size_t Nl = (size_t)(c->d.n >> (l - 1)) * (c->d.n >> (l - 1));
+            HIPCHK(hipMemsetAsync(S.pxb[l], 0, Nl * sizeof(double), st));
+            HIPCHK(hipMemsetAsync(S.pyb[l], 0, Nl * sizeof(double), st));
+            HIPCHK(hipMemsetAsync(S.c0b[l], 0, Nl * sizeof(c128), st));
+        }
+        const size_t N2 = (size_t)(c->d.n / 2) * (c->d.n / 2);
+        HIPCHK(hipMemsetAsync(S.thb, 0, N2 * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(S.phib2, 0, N2 * sizeof(double), st));
+    }
+    // u_0 .. u_{K-1}
+    if (u0) HIPCHK(hipMemcpyAsync(ck, u0, vb, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(hipMemsetAsync(ck, 0, vb, st));
+    for (int k = 0; k + 1 < K; ++k) cycle_any(c, g, ck + (size_t)k * vb, ck + (size_t)(k + 1) * vb, st);
+    // reverse sweep
+    AdjEngine<T> R(c, st);
+    HIPCHK(hipMemcpyAsync(S.fb[0], grad_uK, vb, hipMemcpyDeviceToDevice, st));
+    for (int k = K - 1; k >= 0; --k) {
+        const void* uk = ck + (size_t)k * vb;
+        R.rec_cycle(g, uk);
+        R.rev_cycle(g, uk);
+    }
+    if (c->f32) R.template phase_out<float>(grad_phi);
+    else R.template phase_out<double>(grad_phi);
+    HIPCHK(hipMemcpyAsync(grad_w, S.wacc, c->L * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipGetLastError());
+}
+
+// L = ||g - A u||^2 (FP64) and, if grad_u, its cotangent -2 A^H (g - A u) in cycle precision.
+template <typename T>
+static double loss_grad(helm_ctx c, const void* g, const void* u, void* grad_u, hipStream_t st) {
+    const Geom G = make_geom(c, 1);
+    const size_t NF = (size_t)G.n * G.n;
+    const int nb = flat_blocks(NF);
+    LAUNCH(c, (2.0 * sizeof(cplx<T>) + 8.0 + 16.0) * NF, (k_loss_resid<T>), dim3(nb), dim3(BLOCK), st, G,
+           (const double*)c->n2f, (const cplx<T>*)g, (const cplx<T>*)u, (c128*)c->rbuf, c->partials);
+    LAUNCH(c, 8.0 * nb, (k_finalize_sums<1>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, 1, c->dscal);
+    if (grad_u)
+        LAUNCH(c, (16.0 + 8.0 + sizeof(cplx<T>)) * NF, (k_loss_grad<T>), dim3(nb), dim3(BLOCK), st, G,
+               (const double*)c->n2f, (const c128*)c->rbuf, (cplx<T>*)grad_u);
+    double h = 0.0;
+    HIPCHK(hipMemcpyAsync(&h, c->dscal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return h;
+}

@@ -6,6 +6,7 @@
 // kernels_*.hpp.  Scalars that steer the Krylov methods stay on the device,
 // except that the outer solver reads one Hessenberg column per iteration.
 #include <algorithm>
+#include <array>
 #include <complex>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,7 @@
 
 #include "../../include/helm.h"
 #include "kernels_tail.hpp"
+#include "kernels_adjoint.hpp"
 
 namespace helm {
 
@@ -65,6 +67,8 @@ struct AdrLevel {
     KrylovScal* K = nullptr;
 };
 
+struct AdjState;
+
 }  // namespace helm
 
 struct helm_ctx_s {
@@ -93,8 +97,7 @@ struct helm_ctx_s {
     void* cyc_u = nullptr;
     void* rbuf = nullptr;    // FP64 residual (mode 1)
     void* dbuf = nullptr;    // inner correction (mode 1)
-    void* ckpt = nullptr;
-    size_t ckpt_bytes = 0;
+    helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
     // captured cycles, keyed by the (g, u_in, u_out) pointers they were captured with
     struct GraphEntry {
         const void* g;
@@ -956,6 +959,8 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
     return status;
 }
 
+#include "adjoint_host.hpp"
+
 }  // namespace helm
 
 // ================================================================== C ABI
@@ -1109,11 +1114,26 @@ helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const vo
     ABI_GUARD({
         REQUIRE(ctx != nullptr && g != nullptr && grad_uK != nullptr && grad_phi != nullptr && grad_w != nullptr,
                 "NULL argument");
-        REQUIRE(K >= 1, "K must be >= 1");
-        (void)u0;
-        (void)ckpt_ws;
-        (void)stream;
-        throw Error(HELM_ESTATE, "helm_cycle_backward is not available in this build");
+        REQUIRE(K >= 1 && K <= 100000, "K must be in [1, 100000]");
+        if (ctx->d.adr_steps > 0 && ctx->L >= 3 && !ctx->phase_set)
+            throw Error(HELM_ESTATE, "helm_set_phase must be called before helm_cycle_backward");
+        REQUIRE(ctx->d.gmres_m <= GMAX && ctx->d.gmres_coarse_m <= GMAX,
+                "the adjoint supports GMRES dimensions up to 6");
+        hipStream_t st = (hipStream_t)stream;
+        if (ctx->f32) cycle_backward<float>(ctx, K, g, u0, grad_uK, grad_phi, grad_w, ckpt_ws, st);
+        else cycle_backward<double>(ctx, K, g, u0, grad_uK, grad_phi, grad_w, ckpt_ws, st);
+        HIPCHK(hipGetLastError());
+        return HELM_OK;
+    })
+}
+
+helm_status helm_loss(helm_ctx ctx, const void* g, const void* u, double* loss, void* grad_u, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && u != nullptr && loss != nullptr, "NULL argument");
+        hipStream_t st = (hipStream_t)stream;
+        *loss = ctx->f32 ? loss_grad<float>(ctx, g, u, grad_u, st) : loss_grad<double>(ctx, g, u, grad_u, st);
+        HIPCHK(hipGetLastError());
+        return HELM_OK;
     })
 }
 
@@ -1293,6 +1313,8 @@ helm_status helm_profile_end(helm_ctx ctx, char* json, int64_t cap) {
 helm_status helm_destroy(helm_ctx ctx) {
     if (!ctx) return HELM_OK;
     drop_graphs(ctx);
+    delete ctx->adj;
+    ctx->adj = nullptr;
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     ctx->prof.pool.clear();

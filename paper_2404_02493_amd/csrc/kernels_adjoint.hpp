@@ -1,0 +1,797 @@
+// Reverse-mode kernels of the unrolled Wave-ADR cycle: the back-propagation of
+// the training loss of Section 3.3 (eq. loss) through K cycles of Algorithm 1.
+//
+// Convention: for a real loss L the cotangent of a complex array x is
+// xbar = dL/dRe(x) + i dL/dIm(x) (torch's convention), so a complex-linear map
+// y = B x pulls back as xbar = B^H ybar, and a real parameter p that enters y
+// receives Re <ybar, dy/dp>, with <a, b> = sum conj(a) b.
+//
+// The operators involved and their adjoints:
+//   A   = -Delta_h - diag(kappa)        A^H = -Delta_h - diag(conj kappa)
+//   R   full weighting                  R^T = P / 4  (P bilinear, P = 4 R^T)
+//   M   upwind ADR operator (eq. ADR, eq. upwind); M^H gathers the conjugated
+//       coefficients of the neighbouring rows (the stencil is not symmetric).
+// Every kernel keeps the ring i = 0 or j = 0 at zero, as the forward kernels do.
+#pragma once
+
+#include "kernels_krylov.hpp"
+
+namespace helm {
+
+constexpr int GMAX = 6;  // largest GMRES dimension the adjoint supports
+
+// State of one GMRES(m) call of the ADR smoother, recorded in the monomial Krylov
+// basis k_1 = r0, k_{j+1} = M k_j / tau (tau only scales the basis), so that
+// x = x0 + sum_j c_j k_j with c the least-squares solution of the normal equations
+// (W^H W) c = W^H r0, W = tau [k_2 .. k_{m+1}].  All FP64.
+struct GRec {
+    double gram[(GMAX + 1) * (GMAX + 2)];  // column c (1-based): <k_i, k_c>, i <= c, at 2*(c(c-1)/2 + i-1)
+    double c[2 * GMAX];
+    double Lf[2 * GMAX * GMAX];            // Cholesky factor of the normalised W^H W (lower, row-major)
+    double dsc[GMAX];                      // normalisation 1/sqrt(diag(W^H W))
+    double cbar[2 * GMAX];                 // <k_j, xbar>
+    double z[2 * GMAX];                    // (W^H W)^{-1} cbar
+    double coef[2 * (GMAX + 1) * (GMAX + 2)];  // row r (0-based, kbar_{r+1}) over (xbar, k_1..k_{m+1})
+    double one[2];                         // the coefficient row (1, 0): xbar alone
+    int m;                                 // requested dimension
+    int rank;                              // columns used (< m when the Krylov space is invariant)
+    int zero;                              // r0 == 0: x = x0
+    int pad;
+};
+constexpr int GCOEF_STRIDE = 2 * (GMAX + 2);
+
+__device__ __forceinline__ int gram_off(int i, int c) { return 2 * (c * (c - 1) / 2 + i - 1); }
+
+template <typename T>
+__device__ __forceinline__ cplx<T> ldc(const cplx<T>* __restrict__ a, int i, int j, int n) {
+    if (i <= 0 || j <= 0 || i >= n || j >= n) return cplx<T>{};
+    return a[(size_t)i * n + j];
+}
+
+// Per-block sums of K accumulators into partials[v * nblk + block] (256 threads).
+template <int K>
+__device__ __forceinline__ void reduce_store(const double (&acc)[K], int kcount, double* partials) {
+    __shared__ double red[4 * K];
+    __shared__ double sums[K];
+    block_sum<K, 4>(acc, kcount, red, sums);
+    store_partials(sums, kcount, partials);
+}
+
+// out[v] += sum over blocks (one block of FBLOCK threads), v < kcount; scale s.
+template <int K>
+__global__ __launch_bounds__(FBLOCK) void k_finalize_add(const double* __restrict__ partials, int nblk, int kcount,
+                                                         double s, double* out) {
+    __shared__ double red[(FBLOCK / 64) * K];
+    __shared__ double sums[K];
+    final_sum<K>(partials, nblk, kcount, red, sums);
+    if ((int)threadIdx.x < kcount) out[threadIdx.x] += s * sums[threadIdx.x];
+}
+
+// ------------------------------------------------------------------ wave levels
+
+// Jacobi sweep y = u + w D^{-1} (g - A u), D = 4/h^2 - kappa (eq. sjac), reversed:
+//   ubar_out = ybar - w A^H (D^{-H} ybar),   wbar += Re <ybar, D^{-1} (g - A u)>.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_jacobi_adj(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
+                                                      const cplx<T>* __restrict__ u, const cplx<T>* __restrict__ yb,
+                                                      cplx<T>* __restrict__ ub, T w, double* partials) {
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    double acc[1] = {0.0};
+    auto dinv_h = [&](int a, int b) -> cplx<T> {  // ybar(a,b) / conj(D(a,b)), zero off the unknowns
+        if (a <= 0 || b <= 0 || a >= n || b >= n) return cplx<T>{};
+        const size_t q = (size_t)a * n + b;
+        cplx<T> kap = kappa_at<T>(G, n2[q], a, b);
+        cplx<T> dh = mk<T>(T(4) * T(G.inv_h2) - kap.re, kap.im);  // conj(D)
+        return cdiv(yb[q], dh);
+    };
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        cplx<T> out{};
+        if (i > 0 && j > 0) {
+            cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
+            cplx<T> d = mk<T>(T(4) * T(G.inv_h2) - kap.re, -kap.im);
+            cplx<T> res = resid_at(G, n2, g, u, i, j);
+            cplx<T> q = cdiv(res, d);
+            cplx<T> y = yb[p];
+            acc[0] += double(y.re) * double(q.re) + double(y.im) * double(q.im);
+            cplx<T> qc = dinv_h(i, j);
+            cplx<T> nb = ((dinv_h(i - 1, j) + dinv_h(i + 1, j)) + dinv_h(i, j - 1)) + dinv_h(i, j + 1);
+            cplx<T> ahq = T(G.inv_h2) * (T(4) * qc - nb) - conjg(kap) * qc;
+            out = y - w * ahq;
+        }
+        ub[p] = out;
+    }
+    reduce_store<1>(acc, 1, partials);
+}
+
+// xc = s * R x (full weighting from the fine level with n nodes per side).
+template <typename Tf, typename Tc>
+__global__ __launch_bounds__(BLOCK) void k_restrict_scale(int n, const cplx<Tf>* __restrict__ x,
+                                                          cplx<Tc>* __restrict__ xc, double s) {
+    const int nc = n / 2;
+    const size_t N = (size_t)nc * nc;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int I = (int)(p / nc), J = (int)(p % nc);
+        cplx<Tc> out{};
+        if (I > 0 && J > 0) {
+            const int fi = 2 * I, fj = 2 * J;
+            auto X = [&](int a, int b) { return ccast<double>(ldc(x, a, b, n)); };
+            c128 c = X(fi, fj);
+            c128 e = ((X(fi - 1, fj) + X(fi + 1, fj)) + X(fi, fj - 1)) + X(fi, fj + 1);
+            c128 dg = ((X(fi - 1, fj - 1) + X(fi - 1, fj + 1)) + X(fi + 1, fj - 1)) + X(fi + 1, fj + 1);
+            c128 v = (s / 16.0) * ((4.0 * c + 2.0 * e) + dg);
+            out = ccast<Tc>(v);
+        }
+        xc[p] = out;
+    }
+}
+
+// Reverse of rc = R (g - A u) given rcbar on the coarse level: with t = P rcbar / 4,
+//   gbar += t  (if gbar),   ubar -= A^H t  (if ubar).  In place on gbar and ubar.
+template <typename Tc, typename Tf>
+__global__ __launch_bounds__(BLOCK) void k_prolong_adj(Geom G, const Tf* __restrict__ n2,
+                                                       const cplx<Tc>* __restrict__ rcbar, cplx<Tf>* __restrict__ ubar,
+                                                       cplx<Tf>* __restrict__ gbar) {
+    const int n = G.n, nc = n / 2;
+    const size_t N = (size_t)n * n;
+    auto tq = [&](int a, int b) -> cplx<Tf> {
+        if (a <= 0 || b <= 0 || a >= n || b >= n) return cplx<Tf>{};
+        return Tf(0.25) * prolong_at<Tc, Tf>(rcbar, nc, a, b);
+    };
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        if (i == 0 || j == 0) continue;
+        const cplx<Tf> t = tq(i, j);
+        if (gbar) gbar[p] = gbar[p] + t;
+        if (ubar) {
+            cplx<Tf> kap = kappa_at<Tf>(G, n2[p], i, j);
+            cplx<Tf> nb = ((tq(i - 1, j) + tq(i + 1, j)) + tq(i, j - 1)) + tq(i, j + 1);
+            cplx<Tf> aht = Tf(G.inv_h2) * (Tf(4) * t - nb) - conjg(kap) * t;
+            ubar[p] = ubar[p] - aht;
+        }
+    }
+}
+
+// gbar += t (if gbar);  ubar -= A^H t (if ubar).  In place.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adj_ahsub(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ t,
+                                                     cplx<T>* __restrict__ ubar, cplx<T>* __restrict__ gbar) {
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        if (i == 0 || j == 0) continue;
+        if (gbar) gbar[p] = gbar[p] + t[p];
+        if (ubar) ubar[p] = ubar[p] - applyA_at(G, n2, t, i, j, true);
+    }
+}
+
+// Chebyshev reverse, start of the primal + alpha-tangent recurrences on v:
+//   r = v, rt = 0, d = v / theta, dt = v * dt0, s = d, st = dt.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_chebadj_start(size_t N, const cplx<T>* __restrict__ v, cplx<T>* __restrict__ r,
+                                                         cplx<T>* __restrict__ rt, cplx<T>* __restrict__ d,
+                                                         cplx<T>* __restrict__ dt, cplx<T>* __restrict__ s,
+                                                         cplx<T>* __restrict__ st, T inv_theta, T dt0) {
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const cplx<T> x = v[p];
+        const cplx<T> dd = inv_theta * x, ddt = dt0 * x;
+        r[p] = x;
+        rt[p] = cplx<T>{};
+        d[p] = dd;
+        dt[p] = ddt;
+        s[p] = dd;
+        st[p] = ddt;
+    }
+}
+
+// t1 = A d, t2 = A dt
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_apply_A2(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ d,
+                                                    const cplx<T>* __restrict__ dt, cplx<T>* __restrict__ t1,
+                                                    cplx<T>* __restrict__ t2) {
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        cplx<T> a{}, b{};
+        if (i > 0 && j > 0) {
+            a = applyA_at(G, n2, d, i, j, false);
+            b = applyA_at(G, n2, dt, i, j, false);
+        }
+        t1[p] = a;
+        t2[p] = b;
+    }
+}
+
+// One step of both recurrences (t1 = A d, t2 = A dt):
+//   r -= A^H t1; rt -= A^H t2; d' = c1 d + c2 r; dt' = c1t d + c1 dt + c2t r + c2 rt;
+//   s += d'; st += dt'.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_chebadj_step(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ t1,
+                                                        const cplx<T>* __restrict__ t2, cplx<T>* __restrict__ r,
+                                                        cplx<T>* __restrict__ rt, cplx<T>* __restrict__ d,
+                                                        cplx<T>* __restrict__ dt, cplx<T>* __restrict__ s,
+                                                        cplx<T>* __restrict__ st, T c1, T c2, T c1t, T c2t) {
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        if (i == 0 || j == 0) continue;
+        const cplx<T> rv = r[p] - applyA_at(G, n2, t1, i, j, true);
+        const cplx<T> rtv = rt[p] - applyA_at(G, n2, t2, i, j, true);
+        const cplx<T> dv = d[p], dtv = dt[p];
+        const cplx<T> dn = c1 * dv + c2 * rv;
+        const cplx<T> dtn = ((c1t * dv + c1 * dtv) + c2t * rv) + c2 * rtv;
+        r[p] = rv;
+        rt[p] = rtv;
+        d[p] = dn;
+        dt[p] = dtn;
+        s[p] = s[p] + dn;
+        st[p] = st[p] + dtn;
+    }
+}
+
+// partial Re <a, A^H b>
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_dot_ah(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ a,
+                                                  const cplx<T>* __restrict__ b, double* partials) {
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    double acc[1] = {0.0};
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        if (i == 0 || j == 0) continue;
+        const cplx<T> v = applyA_at(G, n2, b, i, j, true);
+        const cplx<T> x = a[p];
+        acc[0] += double(x.re) * double(v.re) + double(x.im) * double(v.im);
+    }
+    reduce_store<1>(acc, 1, partials);
+}
+
+// ------------------------------------------------------------------ ADR correction (level 2)
+
+// Reverse of u' = u + a e^{i theta}:  abar = e^{-i theta} ubar',
+// thbar += Re <ubar', i a e^{i theta}> = -Im(conj(ubar') a e^{i theta}).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* __restrict__ ub, const cplx<T>* __restrict__ a,
+                                                      const T* __restrict__ theta, cplx<T>* __restrict__ abar,
+                                                      double* __restrict__ thbar) {
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        T sn, cs;
+        sincos_t(theta[p], &sn, &cs);
+        const cplx<T> e = mk<T>(cs, sn);
+        const cplx<T> y = ub[p];
+        abar[p] = conjg(e) * y;
+        const cplx<T> ae = a[p] * e;
+        // Im(conj(y) * ae)
+        thbar[p] -= double(y.re) * double(ae.im) - double(y.im) * double(ae.re);
+    }
+}
+
+// Reverse of b = r e^{-i theta}:  rbar = e^{i theta} bbar,  thbar += Im(conj(bbar) b).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_demod_adj(size_t N, const cplx<T>* __restrict__ bbar, const cplx<T>* __restrict__ b,
+                                                     const T* __restrict__ theta, cplx<T>* __restrict__ rbar,
+                                                     double* __restrict__ thbar) {
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        T sn, cs;
+        sincos_t(theta[p], &sn, &cs);
+        const cplx<T> e = mk<T>(cs, sn);
+        const cplx<T> y = bbar[p], bv = b[p];
+        rbar[p] = e * y;
+        thbar[p] += double(y.re) * double(bv.im) - double(y.im) * double(bv.re);
+    }
+}
+
+// ------------------------------------------------------------------ ADR operator adjoint
+
+// Row coefficients of M at an unknown (fx = phi_x, fy = phi_y): with g = 2 sigma k / (2h),
+//   centre 4/h^2 + c0 - i g 2(|fx|+|fy|), west -1/h^2 + i g (fx+|fx|), east -1/h^2 - i g (fx-|fx|),
+//   south -1/h^2 + i g (fy+|fy|), north -1/h^2 - i g (fy-|fy|).
+// (M^H y)(i,j) = conj(centre_ij) y_ij + conj(west_{i,j+1}) y_{i,j+1} + conj(east_{i,j-1}) y_{i,j-1}
+//              + conj(south_{i+1,j}) y_{i+1,j} + conj(north_{i-1,j}) y_{i-1,j}.
+template <typename T>
+__device__ __forceinline__ cplx<T> applyMH_at(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,
+                                              const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ y, int i,
+                                              int j) {
+    const int n = A.n;
+    const T g = T(A.two_sk * A.inv_2h), ih2 = T(A.inv_h2);
+    const size_t p = (size_t)i * n + j;
+    const T fx = px[p], fy = py[p];
+    const T ax = fx < T(0) ? -fx : fx, ay = fy < T(0) ? -fy : fy;
+    const cplx<T> cc = c0[p];
+    // conj(centre) = (4/h^2 + c0.re, -c0.im + g 2(|fx|+|fy|))
+    cplx<T> out = mk<T>(T(4) * ih2 + cc.re, -cc.im + g * (T(2) * (ax + ay))) * y[p];
+    if (j + 1 < n) {  // row (i, j+1), its west coefficient; conj: (-1/h^2, -g (fx+|fx|))
+        const size_t q = p + 1;
+        const T f = px[q], a = f < T(0) ? -f : f;
+        out = out + mk<T>(-ih2, -g * (f + a)) * y[q];
+    }
+    if (j - 1 >= 1) {  // row (i, j-1), its east coefficient; conj: (-1/h^2, +g (fx-|fx|))
+        const size_t q = p - 1;
+        const T f = px[q], a = f < T(0) ? -f : f;
+        out = out + mk<T>(-ih2, g * (f - a)) * y[q];
+    }
+    if (i + 1 < n) {  // row (i+1, j), its south coefficient
+        const size_t q = p + n;
+        const T f = py[q], a = f < T(0) ? -f : f;
+        out = out + mk<T>(-ih2, -g * (f + a)) * y[q];
+    }
+    if (i - 1 >= 1) {  // row (i-1, j), its north coefficient
+        const size_t q = p - n;
+        const T f = py[q], a = f < T(0) ? -f : f;
+        out = out + mk<T>(-ih2, g * (f - a)) * y[q];
+    }
+    return out;
+}
+
+// Coefficient cotangents at row (i,j) for y = M a with output cotangent yb:
+//   pxbar += 2 sigma k Im(conj(yb) dU/dfx), dU/dfx = (2 sx a_c - (1+sx) a_w + (1-sx) a_e) / (2h),
+//   likewise pybar with (s, n) neighbours; c0bar += conj(a_c) yb.  d|f|/df = sign(f), 0 at 0.
+template <typename T>
+__device__ __forceinline__ void coef_grad_at(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,
+                                             const cplx<T>* __restrict__ a, cplx<T> yb, int i, int j,
+                                             double* __restrict__ pxb, double* __restrict__ pyb,
+                                             c128* __restrict__ c0b) {
+    const int n = A.n;
+    const size_t p = (size_t)i * n + j;
+    const T fx = px[p], fy = py[p];
+    const T sx = fx > T(0) ? T(1) : (fx < T(0) ? T(-1) : T(0));
+    const T sy = fy > T(0) ? T(1) : (fy < T(0) ? T(-1) : T(0));
+    const cplx<T> ac = a[p];
+    const cplx<T> aw = ldz(a, i, j - 1, n), ae = ldz(a, i, j + 1, n);
+    const cplx<T> as = ldz(a, i - 1, j, n), an = ldz(a, i + 1, j, n);
+    const cplx<T> dux = T(A.inv_2h) * (((T(2) * sx) * ac - (T(1) + sx) * aw) + (T(1) - sx) * ae);
+    const cplx<T> duy = T(A.inv_2h) * (((T(2) * sy) * ac - (T(1) + sy) * as) + (T(1) - sy) * an);
+    const double ybr = double(yb.re), ybi = double(yb.im);
+    pxb[p] += A.two_sk * (ybr * double(dux.im) - ybi * double(dux.re));
+    pyb[p] += A.two_sk * (ybr * double(duy.im) - ybi * double(duy.re));
+    c128 cb = c0b[p];
+    cb.re += double(ac.re) * ybr + double(ac.im) * ybi;
+    cb.im += double(ac.re) * ybi - double(ac.im) * ybr;
+    c0b[p] = cb;
+}
+
+// ------------------------------------------------------------------ GMRES record
+
+// k1 = b - M x0 (x0 may be null); partial ||k1||^2.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gr_r0(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                 const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
+                                                 const cplx<T>* __restrict__ x0, cplx<T>* __restrict__ k1,
+                                                 double* partials) {
+    const int n = A.n;
+    const size_t N = (size_t)n * n;
+    double acc[2] = {0.0, 0.0};
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        cplx<T> v{};
+        if (i > 0 && j > 0) {
+            v = b[p];
+            if (x0) v = v - applyM_at(A, px, py, c0, x0, i, j);
+            acc[0] += double(v.re) * double(v.re) + double(v.im) * double(v.im);
+        }
+        k1[p] = v;
+    }
+    reduce_store<2>(acc, 2, partials);
+}
+
+// k_{jj+1} = M k_jj / tau (1-based jj), and partial <k_i, k_{jj+1}> for i = 1..jj+1.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gr_chain(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                    const cplx<T>* __restrict__ c0, VecSet<T> Kv, int jj, double inv_tau,
+                                                    cplx<T>* __restrict__ kout, double* partials) {
+    const int n = A.n;
+    const size_t N = (size_t)n * n;
+    double acc[2 * (GMAX + 1)];
+#pragma unroll
+    for (int v = 0; v < 2 * (GMAX + 1); ++v) acc[v] = 0.0;
+    const cplx<T>* __restrict__ kin = Kv.v[jj - 1];
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        cplx<T> v{};
+        if (i > 0 && j > 0) {
+            v = T(inv_tau) * applyM_at(A, px, py, c0, kin, i, j);
+#pragma unroll
+            for (int q = 0; q < GMAX + 1; ++q) {
+                if (q < jj) {
+                    const cplx<T> kq = Kv.v[q][p];
+                    acc[2 * q] += double(kq.re) * double(v.re) + double(kq.im) * double(v.im);
+                    acc[2 * q + 1] += double(kq.re) * double(v.im) - double(kq.im) * double(v.re);
+                } else if (q == jj) {
+                    acc[2 * q] += double(v.re) * double(v.re) + double(v.im) * double(v.im);
+                }
+            }
+        }
+        kout[p] = v;
+    }
+    reduce_store<2 * (GMAX + 1)>(acc, 2 * (jj + 1), partials);
+}
+
+// Least squares of one GMRES call from the Gram matrix of k_1..k_{m+1} (one thread):
+// normalised Cholesky of W^H W; columns whose pivot falls below 1e-14 (an invariant
+// Krylov space) are dropped, which reproduces the early exit of Arnoldi.
+__global__ void k_gr_solve(GRec* __restrict__ R, double tau) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int m = R->m;
+    auto Gc = [&](int i, int j) -> c128 {  // <k_i, k_j>, 1-based
+        if (i <= j) return c128{R->gram[gram_off(i, j)], R->gram[gram_off(i, j) + 1]};
+        return c128{R->gram[gram_off(j, i)], -R->gram[gram_off(j, i) + 1]};
+    };
+    for (int a = 0; a < 2 * GMAX; ++a) {
+        R->c[a] = 0.0;
+        R->z[a] = 0.0;
+    }
+    const double b2 = Gc(1, 1).re;
+    R->zero = !(b2 > 0.0) || !isfinite(b2);
+    R->rank = 0;
+    if (R->zero) return;
+    double s[GMAX];
+    for (int a = 0; a < m; ++a) {
+        const double dg = tau * tau * Gc(a + 2, a + 2).re;
+        s[a] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
+        R->dsc[a] = s[a];
+    }
+    // normalised matrix G^_ab = s_a s_b tau^2 <k_{a+2}, k_{b+2}>, Cholesky row by row
+    int rank = 0;
+    for (int a = 0; a < m; ++a) {
+        if (s[a] == 0.0) break;
+        for (int b = 0; b <= a; ++b) {
+            c128 g = Gc(a + 2, b + 2);
+            double gr = s[a] * s[b] * tau * tau * g.re, gi = s[a] * s[b] * tau * tau * g.im;
+            for (int q = 0; q < b; ++q) {  // - L_aq conj(L_bq)
+                const double lr = R->Lf[2 * (a * GMAX + q)], li = R->Lf[2 * (a * GMAX + q) + 1];
+                const double mr = R->Lf[2 * (b * GMAX + q)], mi = R->Lf[2 * (b * GMAX + q) + 1];
+                gr -= lr * mr + li * mi;
+                gi -= li * mr - lr * mi;
+            }
+            if (b < a) {
+                const double d = R->Lf[2 * (b * GMAX + b)];
+                R->Lf[2 * (a * GMAX + b)] = gr / d;
+                R->Lf[2 * (a * GMAX + b) + 1] = gi / d;
+            } else {
+                if (!(gr > 1e-14)) goto done;
+                R->Lf[2 * (a * GMAX + a)] = sqrt(gr);
+                R->Lf[2 * (a * GMAX + a) + 1] = 0.0;
+            }
+        }
+        rank = a + 1;
+    }
+done:
+    R->rank = rank;
+    {
+        // rhs_a = s_a tau <k_{a+2}, k_1>;  L L^H y = rhs;  c_a = s_a y_a
+        double yr[GMAX], yi[GMAX];
+        for (int a = 0; a < rank; ++a) {
+            c128 g = Gc(a + 2, 1);
+            double rr = s[a] * tau * g.re, ri = s[a] * tau * g.im;
+            for (int q = 0; q < a; ++q) {
+                const double lr = R->Lf[2 * (a * GMAX + q)], li = R->Lf[2 * (a * GMAX + q) + 1];
+                rr -= lr * yr[q] - li * yi[q];
+                ri -= lr * yi[q] + li * yr[q];
+            }
+            const double d = R->Lf[2 * (a * GMAX + a)];
+            yr[a] = rr / d;
+            yi[a] = ri / d;
+        }
+        for (int a = rank - 1; a >= 0; --a) {
+            double rr = yr[a], ri = yi[a];
+            for (int q = a + 1; q < rank; ++q) {  // - conj(L_qa) y_q
+                const double lr = R->Lf[2 * (q * GMAX + a)], li = R->Lf[2 * (q * GMAX + a) + 1];
+                rr -= lr * yr[q] + li * yi[q];
+                ri -= lr * yi[q] - li * yr[q];
+            }
+            const double d = R->Lf[2 * (a * GMAX + a)];
+            yr[a] = rr / d;
+            yi[a] = ri / d;
+        }
+        for (int a = 0; a < rank; ++a) {
+            R->c[2 * a] = s[a] * yr[a];
+            R->c[2 * a + 1] = s[a] * yi[a];
+        }
+    }
+}
+
+// x = x0 + sum_{j=1..m} c_j k_j  (x0 may be null; may alias x).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gr_combine(size_t N, VecSet<T> Kv, int m, const GRec* __restrict__ R,
+                                                      const cplx<T>* x0, cplx<T>* x) {
+    __shared__ T cf[2 * GMAX];
+    if (threadIdx.x < 2 * GMAX) cf[threadIdx.x] = T(R->c[threadIdx.x]);
+    __syncthreads();
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        cplx<T> v = x0 ? x0[p] : cplx<T>{};
+        for (int q = 0; q < m; ++q) v = v + mk<T>(cf[2 * q], cf[2 * q + 1]) * Kv.v[q][p];
+        x[p] = v;
+    }
+}
+
+// ------------------------------------------------------------------ GMRES reverse
+
+// partial <k_j, xbar>, j = 1..m
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_ga_dots(size_t N, VecSet<T> Kv, int m, const cplx<T>* __restrict__ xb,
+                                                   double* partials) {
+    double acc[2 * GMAX];
+#pragma unroll
+    for (int v = 0; v < 2 * GMAX; ++v) acc[v] = 0.0;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const cplx<T> y = xb[p];
+#pragma unroll
+        for (int q = 0; q < GMAX; ++q) {
+            if (q < m) {
+                const cplx<T> k = Kv.v[q][p];
+                acc[2 * q] += double(k.re) * double(y.re) + double(k.im) * double(y.im);
+                acc[2 * q + 1] += double(k.re) * double(y.im) - double(k.im) * double(y.re);
+            }
+        }
+    }
+    reduce_store<2 * GMAX>(acc, 2 * m, partials);
+}
+
+// z = (W^H W)^{-1} cbar and the coefficients of kbar_1..kbar_{m+1} over (xbar, k_1..k_{m+1}):
+//   rho = r0 - W c = k_1 - tau sum c_j k_{j+1},   Wz = tau sum z_j k_{j+1},
+//   kbar_1 = conj(c_1) xbar + Wz,
+//   kbar_{j+1} = [j < m] conj(c_{j+1}) xbar + tau (conj(z_j) rho - conj(c_j) Wz),  j = 1..m
+// (differential of the normal equations: dc = (W^H W)^{-1} (dW^H rho + W^H (dr0 - dW c))).
+__global__ void k_ga_prep(GRec* __restrict__ R, double tau) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int m = R->m, rank = R->rank;
+    for (int q = 0; q < 2 * (GMAX + 1) * (GMAX + 2); ++q) R->coef[q] = 0.0;
+    R->one[0] = 1.0;
+    R->one[1] = 0.0;
+    if (R->zero) return;
+    double s[GMAX];
+    for (int a = 0; a < rank; ++a) s[a] = R->dsc[a];
+    double yr[GMAX], yi[GMAX];
+    for (int a = 0; a < rank; ++a) {
+        double rr = s[a] * R->cbar[2 * a], ri = s[a] * R->cbar[2 * a + 1];
+        for (int q = 0; q < a; ++q) {
+            const double lr = R->Lf[2 * (a * GMAX + q)], li = R->Lf[2 * (a * GMAX + q) + 1];
+            rr -= lr * yr[q] - li * yi[q];
+            ri -= lr * yi[q] + li * yr[q];
+        }
+        const double d = R->Lf[2 * (a * GMAX + a)];
+        yr[a] = rr / d;
+        yi[a] = ri / d;
+    }
+    for (int a = rank - 1; a >= 0; --a) {
+        double rr = yr[a], ri = yi[a];
+        for (int q = a + 1; q < rank; ++q) {
+            const double lr = R->Lf[2 * (q * GMAX + a)], li = R->Lf[2 * (q * GMAX + a) + 1];
+            rr -= lr * yr[q] + li * yi[q];
+            ri -= lr * yi[q] - li * yr[q];
+        }
+        const double d = R->Lf[2 * (a * GMAX + a)];
+        yr[a] = rr / d;
+        yi[a] = ri / d;
+    }
+    for (int a = 0; a < 2 * GMAX; ++a) R->z[a] = 0.0;
+    for (int a = 0; a < rank; ++a) {
+        R->z[2 * a] = s[a] * yr[a];
+        R->z[2 * a + 1] = s[a] * yi[a];
+    }
+    // vectors over (xbar, k_1, ..., k_{m+1}) as complex coefficient lists
+    c128 rho[GMAX + 2], wz[GMAX + 2];
+    for (int q = 0; q < m + 2; ++q) rho[q] = wz[q] = c128{0.0, 0.0};
+    rho[1] = c128{1.0, 0.0};
+    for (int j = 1; j <= m; ++j) {
+        rho[j + 1] = c128{-tau * R->c[2 * (j - 1)], -tau * R->c[2 * (j - 1) + 1]};
+        wz[j + 1] = c128{tau * R->z[2 * (j - 1)], tau * R->z[2 * (j - 1) + 1]};
+    }
+    auto row = [&](int r) { return R->coef + r * GCOEF_STRIDE; };
+    // kbar_1
+    {
+        double* o = row(0);
+        o[0] = R->c[0];
+        o[1] = -R->c[1];
+        for (int q = 1; q < m + 2; ++q) {
+            o[2 * q] += wz[q].re;
+            o[2 * q + 1] += wz[q].im;
+        }
+    }
+    for (int j = 1; j <= m; ++j) {
+        double* o = row(j);
+        if (j < m) {
+            o[0] = R->c[2 * j];
+            o[1] = -R->c[2 * j + 1];
+        }
+        const c128 zc = c128{tau * R->z[2 * (j - 1)], -tau * R->z[2 * (j - 1) + 1]};   // tau conj(z_j)
+        const c128 cc = c128{tau * R->c[2 * (j - 1)], -tau * R->c[2 * (j - 1) + 1]};   // tau conj(c_j)
+        for (int q = 1; q < m + 2; ++q) {
+            const c128 a = zc * rho[q], b = cc * wz[q];
+            o[2 * q] += a.re - b.re;
+            o[2 * q + 1] += a.im - b.im;
+        }
+    }
+}
+
+// out = sum_q coef_q V_q + mu M^H accin   (accin may be null), and, when a is given,
+// the coefficient cotangents of y = M a with ybar = mu accin.  V_0 = xbar, V_q = k_q.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_ga_step(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                   const cplx<T>* __restrict__ c0, VecSet<T> V, int nv,
+                                                   const double* __restrict__ coef, const cplx<T>* __restrict__ accin,
+                                                   double mu, const cplx<T>* __restrict__ a, cplx<T>* __restrict__ out,
+                                                   double* __restrict__ pxb, double* __restrict__ pyb,
+                                                   c128* __restrict__ c0b) {
+    __shared__ T cf[2 * (GMAX + 2)];
+    if (threadIdx.x < 2 * (GMAX + 2)) cf[threadIdx.x] = threadIdx.x < 2 * nv ? T(coef[threadIdx.x]) : T(0);
+    __syncthreads();
+    const int n = A.n;
+    const size_t N = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        cplx<T> v{};
+        if (i > 0 && j > 0) {
+            for (int q = 0; q < nv; ++q) v = v + mk<T>(cf[2 * q], cf[2 * q + 1]) * V.v[q][p];
+            if (accin) {
+                v = v + T(mu) * applyMH_at(A, px, py, c0, accin, i, j);
+                if (a) coef_grad_at(A, px, py, a, T(mu) * accin[p], i, j, pxb, pyb, c0b);
+            }
+        }
+        out[p] = v;
+    }
+}
+
+// Reverse of bc = R (b - M x1) given bcbar (coarse): with t = P bcbar / 4,
+//   bbar += t, xbar -= M^H t, coefficient cotangents with ybar = -t, a = x1.  In place.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                      const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ bcbar,
+                                                      const cplx<T>* __restrict__ x1, cplx<T>* __restrict__ xbar,
+                                                      cplx<T>* __restrict__ bbar, double* __restrict__ pxb,
+                                                      double* __restrict__ pyb, c128* __restrict__ c0b) {
+    const int n = A.n, nc = n / 2;
+    const size_t N = (size_t)n * n;
+    const T g = T(A.two_sk * A.inv_2h), ih2 = T(A.inv_h2);
+    auto tq = [&](int a, int b) -> cplx<T> {
+        if (a <= 0 || b <= 0 || a >= n || b >= n) return cplx<T>{};
+        return T(0.25) * prolong_at<T, T>(bcbar, nc, a, b);
+    };
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        if (i == 0 || j == 0) continue;
+        const cplx<T> t = tq(i, j);
+        bbar[p] = bbar[p] + t;
+        // M^H t with t evaluated at the neighbours (same gather as applyMH_at)
+        const T fx = px[p], fy = py[p];
+        const T ax = fx < T(0) ? -fx : fx, ay = fy < T(0) ? -fy : fy;
+        const cplx<T> cc = c0[p];
+        cplx<T> mh = mk<T>(T(4) * ih2 + cc.re, -cc.im + g * (T(2) * (ax + ay))) * t;
+        if (j + 1 < n) {
+            const T f = px[p + 1], af = f < T(0) ? -f : f;
+            mh = mh + mk<T>(-ih2, -g * (f + af)) * tq(i, j + 1);
+        }
+        if (j - 1 >= 1) {
+            const T f = px[p - 1], af = f < T(0) ? -f : f;
+            mh = mh + mk<T>(-ih2, g * (f - af)) * tq(i, j - 1);
+        }
+        if (i + 1 < n) {
+            const T f = py[p + n], af = f < T(0) ? -f : f;
+            mh = mh + mk<T>(-ih2, -g * (f + af)) * tq(i + 1, j);
+        }
+        if (i - 1 >= 1) {
+            const T f = py[p - n], af = f < T(0) ? -f : f;
+            mh = mh + mk<T>(-ih2, g * (f - af)) * tq(i - 1, j);
+        }
+        xbar[p] = xbar[p] - mh;
+        coef_grad_at(A, px, py, x1, T(-1) * t, i, j, pxb, pyb, c0b);
+    }
+}
+
+// ------------------------------------------------------------------ phase cotangent
+
+// Cotangent of the fine phase from the cotangents of phi_x, phi_y, c0 on one ADR
+// level (and of the carrier phase theta on level 2), added to the level-2 array
+// phib2 (level node (i,j) -> level-2 node (i*s2, j*s2)).  Reverse of k_adr_coef:
+//   Px = pxbar + 2 k^2 phi_x Re(c0bar), Py likewise, Lap-bar = -sigma k Im(c0bar),
+// pulled back through the central / one-sided differences of the coefficients.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_phi_adj(int n, int s2, int n2side, double k, int sigma,
+                                                   const T* __restrict__ px, const T* __restrict__ py,
+                                                   const double* __restrict__ pxb, const double* __restrict__ pyb,
+                                                   const c128* __restrict__ c0b, const double* __restrict__ thb,
+                                                   double* __restrict__ phib2) {
+    const size_t N = (size_t)n * n;
+    const double h = 1.0 / n, i2h = 0.5 * n, ih = double(n), ih2 = double(n) * double(n);
+    const double k2 = k * k, sk = double(sigma) * k;
+    auto PX = [&](int a, int b) -> double {
+        if (a <= 0 || b <= 0 || a >= n || b >= n) return 0.0;
+        const size_t q = (size_t)a * n + b;
+        return pxb[q] + 2.0 * k2 * double(px[q]) * c0b[q].re;
+    };
+    auto PY = [&](int a, int b) -> double {
+        if (a <= 0 || b <= 0 || a >= n || b >= n) return 0.0;
+        const size_t q = (size_t)a * n + b;
+        return pyb[q] + 2.0 * k2 * double(py[q]) * c0b[q].re;
+    };
+    auto LB = [&](int a, int b) -> double {
+        if (a <= 0 || b <= 0 || a >= n || b >= n) return 0.0;
+        return -sk * c0b[(size_t)a * n + b].im;
+    };
+    (void)h;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        double v = 0.0;
+        // along x (rows i >= 1): derivative index q = j-1, j, j+1 and the edge q = n-1
+        if (i >= 1) {
+            if (j - 1 >= 1 && j - 1 <= n - 2) v += PX(i, j - 1) * i2h + LB(i, j - 1) * ih2;
+            if (j + 1 >= 1 && j + 1 <= n - 2) v += -PX(i, j + 1) * i2h + LB(i, j + 1) * ih2;
+            if (j >= 1 && j <= n - 2) v += -2.0 * LB(i, j) * ih2;
+            if (j == n - 1) v += PX(i, n - 1) * ih + LB(i, n - 1) * ih2;
+            if (j == n - 2) v += -PX(i, n - 1) * ih - 2.0 * LB(i, n - 1) * ih2;
+            if (j == n - 3) v += LB(i, n - 1) * ih2;
+        }
+        // along y (columns j >= 1)
+        if (j >= 1) {
+            if (i - 1 >= 1 && i - 1 <= n - 2) v += PY(i - 1, j) * i2h + LB(i - 1, j) * ih2;
+            if (i + 1 >= 1 && i + 1 <= n - 2) v += -PY(i + 1, j) * i2h + LB(i + 1, j) * ih2;
+            if (i >= 1 && i <= n - 2) v += -2.0 * LB(i, j) * ih2;
+            if (i == n - 1) v += PY(n - 1, j) * ih + LB(n - 1, j) * ih2;
+            if (i == n - 2) v += -PY(n - 1, j) * ih - 2.0 * LB(n - 1, j) * ih2;
+            if (i == n - 3) v += LB(n - 1, j) * ih2;
+        }
+        if (thb) v += sk * thb[p];
+        phib2[(size_t)i * s2 * n2side + (size_t)j * s2] += v;
+    }
+}
+
+// Fine-grid phase cotangent: the level-2 lattice (even fine indices) carries phib2,
+// every other node 0 (the phase enters only through its injection).
+template <typename TO>
+__global__ __launch_bounds__(BLOCK) void k_phi_out(int nf, const double* __restrict__ phib2, TO* __restrict__ out) {
+    const size_t N = (size_t)nf * nf;
+    const int n2 = nf / 2;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / nf), j = (int)(p % nf);
+        double v = 0.0;
+        if (!(i & 1) && !(j & 1)) v = phib2[(size_t)(i >> 1) * n2 + (j >> 1)];
+        out[p] = TO(v);
+    }
+}
+
+// ------------------------------------------------------------------ loss
+
+// r = g - A u in FP64 on the fine grid (g, u in precision T), partial ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_loss_resid(Geom G, const double* __restrict__ n2, const cplx<T>* __restrict__ g,
+                                                      const cplx<T>* __restrict__ u, c128* __restrict__ r,
+                                                      double* partials) {
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    double acc[1] = {0.0};
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        c128 v{};
+        if (i > 0 && j > 0) {
+            auto U = [&](int a, int b) { return ccast<double>(ldz(u, a, b, n)); };
+            const c128 c = U(i, j);
+            const c128 nb = ((U(i - 1, j) + U(i + 1, j)) + U(i, j - 1)) + U(i, j + 1);
+            const c128 kap = kappa_at<double>(G, n2[p], i, j);
+            const c128 au = G.inv_h2 * (4.0 * c - nb) - kap * c;
+            v = ccast<double>(g[p]) - au;
+            acc[0] += v.re * v.re + v.im * v.im;
+        }
+        r[p] = v;
+    }
+    reduce_store<1>(acc, 1, partials);
+}
+
+// gu = -2 A^H r  (the cotangent of u for L = ||g - A u||^2), cast to T.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_loss_grad(Geom G, const double* __restrict__ n2, const c128* __restrict__ r,
+                                                     cplx<T>* __restrict__ gu) {
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        cplx<T> v{};
+        if (i > 0 && j > 0) v = ccast<T>(-2.0 * applyA_at(G, n2, r, i, j, true));
+        gu[p] = v;
+    }
+}
+
+}  // namespace helm

@@ -66,6 +66,8 @@ def test_null_arguments_are_rejected():
     assert L.helm_setup(None, None, ctypes.byref(ctx), None) == 1
     assert L.helm_cycle(None, None, None, None) == 1
     assert L.helm_solve(None, None, None, 1e-6, 10, 0, None, None, None, None) == 1
+    assert L.helm_cycle_backward(None, 1, None, None, None, None, None, None, None) == 1
+    assert L.helm_loss(None, None, None, None, None, None) == 1
     assert L.helm_destroy(None) == 0
 
 
