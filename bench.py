@@ -53,6 +53,103 @@ def cpu_baseline(case, iterations: int, budget_s: float = 30.0):
             "sample_seconds": t_iter}
 
 
+def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):
+    """The adjoint of K unrolled FP32 cycles on the 1024^2, k = 640 random medium
+    (7 levels, fast-marching phase in float32): wall time of one helm_cycle_backward
+    (which re-runs the K forward cycles for its checkpoints) against K forward cycles."""
+    import numpy as np
+    import torch
+
+    import helm_inputs as hi
+    from paper_2404_02493_amd import Helmholtz
+
+    case = hi.make_case("grf1024", seed=seed)
+    H = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells)
+    H.set_phase(case.phi)
+    g = torch.as_tensor(case.g).to(H.cdtype).to("cuda:0")
+
+    def forward():
+        u = torch.zeros_like(g)
+        for _ in range(K):
+            H.cycle(g, u)
+        return u
+
+    u = forward()
+    _, gu = H.loss(g, u, grad=True)
+    H.cycle_backward(K, g, gu)  # first call allocates the tape
+    torch.cuda.synchronize()
+    tf, tb = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        u = forward()
+        torch.cuda.synchronize()
+        tf.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        H.cycle_backward(K, g, gu)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+    H.close()
+    f, b = float(np.median(tf)), float(np.median(tb))
+    return {"workload": "grf1024 (n=1024, k=640, L=7), K=10 FP32 cycles from zero", "forward_ms": round(1e3 * f, 3),
+            "backward_ms": round(1e3 * b, 3), "backward_over_forward": round(b / f, 2),
+            "note": "backward includes re-running the K forward cycles for the checkpoints and the per-cycle "
+                    "re-recording of the tape"}
+
+
+def bench_batch(args):
+    """Mixed batch: 64 problems with n drawn from {256, 512, 1024}, k = 0.625 n, own random
+    medium, 1-4 sources with a multi-source fast-marching phase; every problem solved to
+    tol with FP32 cycles inside FP64 refinement.  value = problems per second."""
+    import numpy as np
+    import torch
+
+    import helm_inputs as hi
+    from paper_2404_02493_amd import HelmholtzBatch
+
+    t = time.perf_counter()
+    cases = hi.make_batch(args.seed)
+    log(f"batch inputs ready in {time.perf_counter() - t:.1f} s")
+    probs = [dict(velocity=c.velocity, k=c.k, levels=c.levels, damping_cells=c.damping_cells, phi=c.phi)
+             for c in cases]
+    gs = [torch.as_tensor(c.g).to("cuda:0") for c in cases]
+    res = {}
+    for lanes in (args.lanes, 1):
+        t = time.perf_counter()
+        B = HelmholtzBatch(probs, precision="c64", lanes=lanes)
+        torch.cuda.synchronize()
+        log(f"lanes={lanes}: setup of {len(cases)} contexts in {time.perf_counter() - t:.1f} s")
+        for w in range(args.warmup):
+            B.solve(gs, tol=args.tol, maxit=args.maxit, mode=1)
+        torch.cuda.synchronize()
+        times = []
+        for s in range(args.steps):
+            t0 = time.perf_counter()
+            us, its, rr, st = B.solve(gs, tol=args.tol, maxit=args.maxit, mode=1)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            log(f"lanes={lanes} step {s}: {times[-1]:.3f} s, iterations {int(its.sum())}, "
+                f"max relres {rr.max():.2e}, statuses {sorted(set(st.tolist()))}")
+        res[lanes] = (float(np.mean(times)), its, rr, st)
+        B.close()
+    tb, its, rr, st = res[args.lanes]
+    t1 = res[1][0]
+    npts = sum(c.n * c.n for c in cases)
+    out = {
+        "metric": "problems/s, 64-problem mixed batch (n in {256,512,1024}, k=0.625n), FP32+refine to 1e-6",
+        "value": round(len(cases) / tb, 3), "unit": "problems/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * tb, 2), "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "problems": len(cases), "fine_points": npts, "lanes": args.lanes,
+                   "sizes": {str(n): sum(1 for c in cases if c.n == n) for n in (256, 512, 1024)},
+                   "seed": args.seed, "tol": args.tol},
+        "all_converged": bool(np.all(st == 0)), "total_iterations": int(its.sum()),
+        "max_relres": float(rr.max()),
+        "one_lane": {"seconds": round(t1, 3), "problems_per_s": round(len(cases) / t1, 3),
+                     "speedup_of_lanes": round(t1 / tb, 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,11 +162,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--lanes", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the solver has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
 
     import numpy as np
     import torch
@@ -156,6 +259,12 @@ def main():
                    "top_kernels": [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),
                                     "GBs": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)} for k in ks[:8]]}
 
+    adjoint = None
+    if not args.no_adjoint:
+        log("timing the adjoint of 10 unrolled cycles at 1024^2")
+        adjoint = bench_adjoint()
+        log(f"adjoint: {adjoint}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one FP64 FGMRES iteration")
@@ -185,6 +294,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "profile_fp32": summary,
+        "adjoint": adjoint,
     }
     if prof64:
         ks = prof64["kernels"]

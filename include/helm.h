@@ -19,7 +19,9 @@
  *
  * Ownership: every array argument is caller-owned device memory unless marked
  * "host".  The context owns all workspaces; they are allocated by helm_setup
- * and freed by helm_destroy.  helm_cycle and helm_solve allocate nothing.
+ * and freed by helm_destroy, except the Krylov bases of helm_solve (allocated by
+ * the first solve in each mode) and the adjoint tape and checkpoints (allocated
+ * by the first helm_cycle_backward).  helm_cycle allocates nothing.
  *
  * Streams: every call is asynchronous on the given stream (a hipStream_t passed
  * as void*, NULL = default stream), except helm_setup, helm_set_phase (which
@@ -41,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct helm_ctx_s* helm_ctx;
+typedef struct helm_batch_s* helm_batch;
 
 typedef enum {
     HELM_OK = 0,
@@ -157,6 +160,28 @@ helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const vo
  * stream (the loss is returned on the host). */
 helm_status helm_loss(helm_ctx ctx, const void* g, const void* u, double* loss, void* grad_u,
                       void* stream);
+
+/* Batched solves: nprob independent problems of mixed sizes (the batch dimension of
+ * Sections 1 and 4).  desc: host array of nprob descriptors; velocity, phi: host
+ * arrays of nprob device pointers (phi may be NULL, or phi[p] NULL, to set the phase
+ * later through helm_batch_get + helm_set_phase; phi_is_f64 as in helm_set_phase).
+ * lanes: problems in flight at once (0 = 4), each on its own stream and host thread.
+ * The contexts are built concurrently; the call returns when all are ready. */
+helm_status helm_batch_setup(int32_t nprob, const helm_desc* desc, const double* const* velocity,
+                             const void* const* phi, int32_t phi_is_f64, int32_t lanes,
+                             helm_batch* out, void* stream);
+/* The context of problem p (owned by the batch; valid until helm_batch_destroy). */
+helm_status helm_batch_get(helm_batch b, int32_t p, helm_ctx* out);
+/* helm_solve of every problem: g, u host arrays of nprob device pointers (complex128
+ * n_p*n_p); iters, relres, status: host arrays of nprob outputs.  Problems are taken
+ * longest first (n^2) by the lanes; each runs exactly the single-problem solve, so
+ * results equal helm_solve on the same context bit for bit.  Work already queued on
+ * `stream` is waited for; the call returns when every problem is done.  Returns
+ * HELM_OK if all converged, otherwise the most severe per-problem status. */
+helm_status helm_batch_solve(helm_batch b, const void* const* g, void* const* u, double tol,
+                             int32_t maxit, int32_t mode, int32_t* iters, double* relres,
+                             int32_t* status, void* stream);
+helm_status helm_batch_destroy(helm_batch b); /* NULL-safe */
 
 /* Internal operators, exposed for step-by-step parity tests.  op codes:
  *   1  out = A_l in              (level l, cycle_prec complex)

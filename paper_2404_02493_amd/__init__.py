@@ -14,7 +14,7 @@ import numpy as np
 
 from ._abi import HELM_C64, HELM_C128, HelmDesc, HelmError, lib, lib_path, check
 
-__all__ = ["Helmholtz", "HelmDesc", "HelmError", "HELM_C64", "HELM_C128", "lib", "lib_path", "default_desc"]
+__all__ = ["Helmholtz", "HelmholtzBatch", "HelmDesc", "HelmError", "HELM_C64", "HELM_C128", "lib", "lib_path", "default_desc"]
 
 
 def _torch():
@@ -210,6 +210,91 @@ class Helmholtz:
         if level == self.levels:
             return torch.complex128
         return self.cdtype
+
+
+class _Borrowed(Helmholtz):
+    """A problem context owned by a batch (not destroyed by this object)."""
+
+    def __init__(self, ctx, n, levels, cdtype, device):
+        self._ctx = ctx
+        self.n, self.levels, self.cdtype, self.device = n, levels, cdtype, device
+
+    def close(self):
+        self._ctx = ctypes.c_void_p()
+
+
+class HelmholtzBatch:
+    """Independent problems of mixed sizes solved together (helm_batch_* in include/helm.h).
+
+    problems: list of dicts with keys velocity (n x n), k, and optionally levels, phi,
+    damping_cells and any other helm_desc field.  lanes: problems in flight at once."""
+
+    def __init__(self, problems, precision: str = "c64", lanes: int = 4, device: str = "cuda:0", stream=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.cdtype = torch.complex64 if precision == "c64" else torch.complex128
+        descs = (HelmDesc * len(problems))()
+        vels, phis, keep = [], [], []
+        self.sizes = []
+        for p, prob in enumerate(problems):
+            vel = torch.as_tensor(np.asarray(prob["velocity"], dtype=np.float64)).to(self.device).contiguous()
+            n = int(vel.shape[0])
+            d = default_desc(n, float(prob["k"]))
+            d.cycle_prec = HELM_C64 if precision == "c64" else HELM_C128
+            for key, val in prob.items():
+                if key in ("velocity", "k", "phi"):
+                    continue
+                if not hasattr(d, key):
+                    raise TypeError(f"unknown field {key}")
+                setattr(d, key, val)
+            descs[p] = d
+            phi = prob.get("phi")
+            pt = None
+            if phi is not None:
+                pt = torch.as_tensor(np.asarray(phi, dtype=np.float64)).to(self.device).contiguous()
+            keep += [vel, pt]
+            vels.append(vel.data_ptr())
+            phis.append(pt.data_ptr() if pt is not None else None)
+            self.sizes.append((n, int(d.levels)))
+        VA = ctypes.c_void_p * len(problems)
+        self._b = ctypes.c_void_p()
+        check(lib().helm_batch_setup(len(problems), descs, VA(*vels), VA(*phis), 1, int(lanes),
+                                     ctypes.byref(self._b), _stream_ptr(stream)))
+        self.nprob = len(problems)
+
+    def problem(self, p: int) -> Helmholtz:
+        """The single-problem view of problem p (for set_weights, cycle, ...)."""
+        ctx = ctypes.c_void_p()
+        check(lib().helm_batch_get(self._b, int(p), ctypes.byref(ctx)))
+        n, L = self.sizes[p]
+        return _Borrowed(ctx, n, L, self.cdtype, self.device)
+
+    def solve(self, gs, us=None, tol: float = 1e-6, maxit: int = 1000, mode: int = 1, stream=None):
+        """Solves every problem; gs, us: lists of complex128 device grids.  Returns
+        (us, iters, relres, status) with numpy arrays of per-problem results."""
+        torch = _torch()
+        gs = [g.to(device=self.device, dtype=torch.complex128).contiguous() for g in gs]
+        us = [torch.zeros_like(g) for g in gs] if us is None else us
+        VA = ctypes.c_void_p * self.nprob
+        its = (ctypes.c_int32 * self.nprob)()
+        rr = (ctypes.c_double * self.nprob)()
+        st = (ctypes.c_int32 * self.nprob)()
+        code = lib().helm_batch_solve(self._b, VA(*[g.data_ptr() for g in gs]), VA(*[u.data_ptr() for u in us]),
+                                      float(tol), int(maxit), int(mode), its, rr, st, _stream_ptr(stream))
+        if code not in (0, 4):
+            check(code)
+        return us, np.array(its[:]), np.array(rr[:]), np.array(st[:])
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            lib().helm_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _autograd_function():

@@ -16,6 +16,7 @@ STATUS = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP", 4: "
 # every symbol declared in include/helm.h
 EXPORTS = ["helm_desc_default", "helm_setup", "helm_set_phase", "helm_set_weights", "helm_get_weights",
            "helm_get_lambdas", "helm_cycle", "helm_solve", "helm_residual", "helm_cycle_backward", "helm_loss",
+           "helm_batch_setup", "helm_batch_get", "helm_batch_solve", "helm_batch_destroy",
            "helm_debug_op", "helm_profile_begin", "helm_profile_end", "helm_destroy", "helm_status_string", "helm_last_error", "helm_version"]
 
 
@@ -88,6 +89,14 @@ def lib():
     L.helm_cycle_backward.restype = i32
     L.helm_cycle_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.helm_loss.restype = i32
+    L.helm_batch_setup.restype = i32
+    L.helm_batch_setup.argtypes = [i32, vp, P(vp), P(vp), i32, i32, P(vp), vp]
+    L.helm_batch_get.restype = i32
+    L.helm_batch_get.argtypes = [vp, i32, P(vp)]
+    L.helm_batch_solve.restype = i32
+    L.helm_batch_solve.argtypes = [vp, P(vp), P(vp), dbl, i32, i32, P(i32), P(dbl), P(i32), vp]
+    L.helm_batch_destroy.restype = i32
+    L.helm_batch_destroy.argtypes = [vp]
     L.helm_loss.argtypes = [vp, vp, vp, P(dbl), vp, vp]
     L.helm_debug_op.restype = i32
     L.helm_debug_op.argtypes = [vp, i32, i32, vp, vp, vp, vp]

@@ -7,11 +7,13 @@
 // except that the outer solver reads one Hessenberg column per iteration.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <complex>
 #include <cstdio>
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/helm.h"
@@ -130,6 +132,17 @@ struct helm_ctx_s {
             return e;
         }
     } prof;
+};
+
+// A batch of independent problems (see batch.hpp): one context per problem and
+// one stream + host thread per lane.
+struct helm_batch_s {
+    std::vector<helm_ctx> ctx;
+    int lanes = 0;
+    int device = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;  // one per lane
+    hipEvent_t ev_in = nullptr;
 };
 
 // Launch with optional per-launch event timing (name = kernel expression).
@@ -774,16 +787,9 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
         }
         c->theta2 = dalloc(c, (size_t)(n / 2) * (n / 2) * rsize(f64c));
     }
-    // outer FGMRES (complex128) vectors
-    for (int i = 0; i <= d.restart; ++i) c->fV[i] = dalloc(c, NF * sizeof(c128));
-    for (int i = 0; i < d.restart; ++i) c->fZ[i] = dalloc(c, NF * sizeof(c128));
-    if (c->f32) {
-        c->cyc_g = dalloc(c, NF * sizeof(c64));
-        c->cyc_u = dalloc(c, NF * sizeof(c64));
-        for (int i = 0; i <= d.restart; ++i) c->iV[i] = dalloc(c, NF * sizeof(c64));
-        for (int i = 0; i < d.restart; ++i) c->iZ[i] = dalloc(c, NF * sizeof(c64));
-        c->dbuf = dalloc(c, NF * sizeof(c64));
-    }
+    // FP64 residual vectors; the Krylov bases of the outer solvers are allocated by
+    // the first solve in each mode (ensure_solver_ws)
+    c->fV[0] = dalloc(c, NF * sizeof(c128));
     c->rbuf = dalloc(c, NF * sizeof(c128));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
@@ -879,9 +885,32 @@ static void cycle_any(helm_ctx c, const void* g, const void* u_in, void* u_out, 
 }
 
 // ------------------------------------------------------------------ solve
+// Krylov bases of the outer solver of `mode` (first use only): mode 0 keeps
+// restart+1 V and restart Z vectors in complex128 (plus complex64 staging for
+// complex64 cycles), mode 1 the complex64 inner bases and correction.
+static void ensure_solver_ws(helm_ctx c, int mode) {
+    const size_t NF = (size_t)c->d.n * c->d.n;
+    const int m = c->d.restart;
+    if (mode == 0 && !c->fZ[0]) {
+        for (int i = 1; i <= m; ++i) c->fV[i] = dalloc(c, NF * sizeof(c128));
+        for (int i = 0; i < m; ++i) c->fZ[i] = dalloc(c, NF * sizeof(c128));
+        if (c->f32) {
+            c->cyc_g = dalloc(c, NF * sizeof(c64));
+            c->cyc_u = dalloc(c, NF * sizeof(c64));
+        }
+    }
+    if (mode == 1 && !c->iV[0]) {
+        for (int i = 0; i <= m; ++i) c->iV[i] = dalloc(c, NF * sizeof(c64));
+        for (int i = 0; i < m; ++i) c->iZ[i] = dalloc(c, NF * sizeof(c64));
+        c->dbuf = dalloc(c, NF * sizeof(c64));
+    }
+}
+
 static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int maxit, int mode, int* iters,
                          double* relres, double* history, hipStream_t st) {
     const size_t NF = (size_t)c->d.n * c->d.n;
+    if (mode == 1) REQUIRE(c->f32, "mode 1 (iterative refinement) needs cycle_prec = HELM_C64");
+    ensure_solver_ws(c, mode);
     double rn = 0, gn = 0;
     residual_fp64(c, st, g, u, c->fV[0], &rn, &gn);
     std::vector<double> hist;
@@ -960,6 +989,7 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
 }
 
 #include "adjoint_host.hpp"
+#include "batch.hpp"
 
 }  // namespace helm
 
@@ -1135,6 +1165,102 @@ helm_status helm_loss(helm_ctx ctx, const void* g, const void* u, double* loss, 
         HIPCHK(hipGetLastError());
         return HELM_OK;
     })
+}
+
+helm_status helm_batch_setup(int32_t nprob, const helm_desc* desc, const double* const* velocity,
+                             const void* const* phi, int32_t phi_is_f64, int32_t lanes, helm_batch* out,
+                             void* stream) {
+    ABI_GUARD({
+        REQUIRE(out != nullptr && desc != nullptr && velocity != nullptr, "NULL argument");
+        REQUIRE(nprob >= 1 && nprob <= 4096, "nprob must be in [1, 4096]");
+        REQUIRE(lanes >= 0 && lanes <= 64, "lanes must be in [0, 64]");
+        for (int p = 0; p < nprob; ++p) {
+            validate(&desc[p]);
+            REQUIRE(velocity[p] != nullptr, "velocity[" + std::to_string(p) + "] is NULL");
+        }
+        helm_batch b = new helm_batch_s();
+        try {
+            HIPCHK(hipGetDevice(&b->device));
+            b->lanes = std::min(nprob, lanes > 0 ? lanes : 4);
+            b->ctx.assign(nprob, nullptr);
+            for (int l = 0; l < b->lanes; ++l) {
+                hipStream_t s = nullptr;
+                HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+                b->streams.push_back(s);
+                hipEvent_t e = nullptr;
+                HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                b->events.push_back(e);
+            }
+            HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+            lanes_after(b, (hipStream_t)stream);
+            std::vector<helm_status> st(nprob, HELM_OK);
+            std::vector<std::string> msg(nprob);
+            run_lanes(b, longest_first_desc(desc, nprob), [&](int p, int lane) {
+                helm_ctx c = new helm_ctx_s();
+                c->d = desc[p];
+                b->ctx[p] = c;
+                build(c, velocity[p], b->streams[lane]);
+                if (phi && phi[p]) set_phase(c, phi[p], phi_is_f64 != 0, b->streams[lane]);
+                return HELM_OK;
+            }, st, msg);
+            helm_status s = first_error(st, msg);
+            if (s != HELM_OK) throw Error(s, g_last_error);
+            caller_after(b, (hipStream_t)stream);
+        } catch (...) {
+            batch_free(b);
+            throw;
+        }
+        *out = b;
+        return HELM_OK;
+    })
+}
+
+helm_status helm_batch_get(helm_batch b, int32_t p, helm_ctx* out) {
+    ABI_GUARD({
+        REQUIRE(b != nullptr && out != nullptr, "NULL argument");
+        REQUIRE(p >= 0 && p < (int)b->ctx.size(), "problem index out of range");
+        *out = b->ctx[p];
+        return HELM_OK;
+    })
+}
+
+helm_status helm_batch_solve(helm_batch b, const void* const* g, void* const* u, double tol, int32_t maxit,
+                             int32_t mode, int32_t* iters, double* relres, int32_t* status, void* stream) {
+    ABI_GUARD({
+        REQUIRE(b != nullptr && g != nullptr && u != nullptr && iters != nullptr && relres != nullptr &&
+                    status != nullptr,
+                "NULL argument");
+        REQUIRE(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
+        REQUIRE(mode == 0 || mode == 1, "mode must be 0 or 1");
+        const int np = (int)b->ctx.size();
+        for (int p = 0; p < np; ++p) {
+            REQUIRE(g[p] != nullptr && u[p] != nullptr, "g[p] and u[p] must not be NULL");
+            helm_ctx c = b->ctx[p];
+            if (c->d.adr_steps > 0 && c->L >= 3 && !c->phase_set)
+                throw Error(HELM_ESTATE, "problem " + std::to_string(p) + ": phase not set");
+            if (mode == 1) REQUIRE(c->f32, "mode 1 needs cycle_prec = HELM_C64 for every problem");
+        }
+        lanes_after(b, (hipStream_t)stream);
+        std::vector<helm_status> st(np, HELM_OK);
+        std::vector<std::string> msg(np);
+        run_lanes(b, longest_first(b), [&](int p, int lane) {
+            int it = 0;
+            double rr = 0.0;
+            helm_status s = solve(b->ctx[p], g[p], u[p], tol, maxit, mode, &it, &rr, nullptr, b->streams[lane]);
+            HIPCHK(hipGetLastError());
+            iters[p] = it;
+            relres[p] = rr;
+            return s;
+        }, st, msg);
+        for (int p = 0; p < np; ++p) status[p] = st[p];
+        caller_after(b, (hipStream_t)stream);
+        return first_error(st, msg);
+    })
+}
+
+helm_status helm_batch_destroy(helm_batch b) {
+    batch_free(b);
+    return HELM_OK;
 }
 
 helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* in, const void* in2, void* out,
