@@ -545,7 +545,7 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     const Geom G = make_geom(c, 1);
     const size_t N = (size_t)G.n * G.n;
     // K init from V[0]
-    const int nbf = flat_blocks(N, MAXRED), nbt = red_blocks(G.n);
+    const int nbf = flat_blocks(N, MAXRED);
     LAUNCH(c, sizeof(Cp) * double(N), (k_krylov_init_norm<P>), dim3(nbf), dim3(BLOCK), st, N, (const Cp*)V[0],
            c->partials);
     krylov_fin<MAXM>(c, st, nbf, FIN_INIT, 0, m, K, 0.0);
@@ -573,11 +573,11 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     std::vector<double> col(2 * (MAXM + 1));
     for (int j = 0; j < m && used < maxit_left; ++j) {
         prec(j, scale[j]);  // Z[j] = preconditioned V[j] (scaled by scale[j] if !z_scaled)
-        LAUNCH(c, ((j + 3) * sizeof(Cp) + sizeof(P)) * double(N), (k_arnoldi_helm<P, MAXM>), dim3(nbt), tile_block(),
-               st, G, (const P*)n2_fine, (const Cp*)Z[j], z_scaled ? 0 : 1, Vs, j, (Cp*)V[j + 1],
+        LAUNCH(c, ((j + 3) * sizeof(Cp) + sizeof(P)) * double(N), (k_arnoldi_helm_ws<P, MAXM>), dim3(nbf),
+               dim3(BLOCK), st, G, (const P*)n2_fine, (const Cp*)Z[j], z_scaled ? 0 : 1, Vs, j, (Cp*)V[j + 1],
                (const KrylovScal*)K, c->partials);
-        krylov_fin<MAXM>(c, st, nbt, FIN_MV, j, m, K, 0.0);
-        LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass1<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,
+        krylov_fin<MAXM>(c, st, nbf, FIN_MV, j, m, K, 0.0);
+        LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass1_ws<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,
                (Cp*)V[j + 1], (const KrylovScal*)K, c->partials);
         krylov_fin<MAXM>(c, st, nbf, FIN_ORTH1, j, m, K, 0.0);
         LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass2<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,

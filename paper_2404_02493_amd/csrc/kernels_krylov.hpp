@@ -118,17 +118,25 @@ __global__ __launch_bounds__(BLOCK) void k_adr_residual_init(AdrGeom A, const T*
     store_partials(sums, 1, partials);
 }
 
-// Accumulates sum conj(V_i) * w over i <= jj into acc (unscaled).
-template <typename T, int NV>
-__device__ __forceinline__ void acc_dots(double (&acc)[2 * NV + 2], const VecSet<T>& V, int jj, size_t p, cplx<T> w) {
+// Accumulates sum conj(V_i) * w over i <= jj into acc (unscaled).  Per-thread partial
+// sums run in the working precision A (a thread sums a few dozen products); the
+// block and grid reductions are FP64.
+template <typename T, int NV, typename A = double>
+__device__ __forceinline__ void acc_dots(A (&acc)[2 * NV + 2], const VecSet<T>& V, int jj, size_t p, cplx<T> w) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         if (i <= jj) {
             cplx<T> v = V.v[i][p];
-            acc[2 * i] += double(v.re) * double(w.re) + double(v.im) * double(w.im);
-            acc[2 * i + 1] += double(v.re) * double(w.im) - double(v.im) * double(w.re);
+            acc[2 * i] += A(v.re) * A(w.re) + A(v.im) * A(w.im);
+            acc[2 * i + 1] += A(v.re) * A(w.im) - A(v.im) * A(w.re);
         }
     }
+}
+
+template <int K, typename A>
+__device__ __forceinline__ void to_double(const A (&a)[K], double (&d)[K]) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) d[q] = double(a[q]);
 }
 
 // Arnoldi matvec pass with the ADR operator: w = M (scale[jj] V_jj); partial sums of
@@ -174,9 +182,9 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm(Geom G, const T* __restr
     __shared__ double sums[2 * NV + 2];
     if (K->done) return;
     const T sj = use_scale ? T(K->scale[jj]) : T(1);
-    double acc[2 * NV + 2];
+    T acc[2 * NV + 2];
 #pragma unroll
-    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = T(0);
     int t0, t1;
     tile_chunk(G.n, t0, t1);
     for (int t = t0; t < t1; ++t) {
@@ -190,10 +198,12 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm(Geom G, const T* __restr
             cplx<T> v{};
             if (i > 0 && j > 0) v = sj * applyA_at(G, n2, z, i, j, false);
             w[p] = v;
-            acc_dots<T, NV>(acc, V, jj, p, v);
+            acc_dots<T, NV, T>(acc, V, jj, p, v);
         }
     }
-    block_sum<2 * NV + 2, 4>(acc, 2 * (jj + 1), red, sums);
+    double accd[2 * NV + 2];
+    to_double(acc, accd);
+    block_sum<2 * NV + 2, 4>(accd, 2 * (jj + 1), red, sums);
     store_partials(sums, 2 * (jj + 1), partials);
 }
 
@@ -217,21 +227,27 @@ __global__ __launch_bounds__(BLOCK) void k_orth_pass1(size_t N, VecSet<T> V, int
                                                       const KrylovScal* K, double* partials) {
     __shared__ double red[4 * (2 * NV + 2)];
     __shared__ double sums[2 * NV + 2];
+    __shared__ cplx<T> c[NV];
     if (K->done) return;
-    cplx<T> c[NV];
-    load_coefs<T, NV>(K, jj, c);
-    double acc[2 * NV + 2];
+    if ((int)threadIdx.x < NV) {
+        const int i = threadIdx.x;
+        c[i] = i <= jj ? mk<T>(T(K->dots[2 * i] * K->scale[i]), T(K->dots[2 * i + 1] * K->scale[i])) : cplx<T>{};
+    }
+    __syncthreads();
+    T acc[2 * NV + 2];
 #pragma unroll
-    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = T(0);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         cplx<T> x = w[p];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
             if (i <= jj) x = x - c[i] * V.v[i][p];
         w[p] = x;
-        acc_dots<T, NV>(acc, V, jj, p, x);
+        acc_dots<T, NV, T>(acc, V, jj, p, x);
     }
-    block_sum<2 * NV + 2, 4>(acc, 2 * (jj + 1), red, sums);
+    double accd[2 * NV + 2];
+    to_double(acc, accd);
+    block_sum<2 * NV + 2, 4>(accd, 2 * (jj + 1), red, sums);
     store_partials(sums, 2 * (jj + 1), partials);
 }
 
@@ -255,6 +271,160 @@ __global__ __launch_bounds__(BLOCK) void k_orth_pass2(size_t N, VecSet<T> V, int
     }
     block_sum<1, 4>(acc, 1, red, sums);
     store_partials(sums, 1, partials);
+}
+
+// ---- wave-split passes for the outer FGMRES (up to MAXM + 1 basis vectors)
+// The 4 wavefronts of a block walk the same elements, 64 * E at a time; wave w owns
+// the basis vectors i = w, w + 4, ...: it loads them once per element, adds its
+// share of the projection (exchanged through LDS) and accumulates their inner
+// products with the updated vector.  Each vector is read once per pass and a thread
+// holds the accumulators of a quarter of the basis only.
+constexpr int WS_WAVES = 4;
+
+template <typename T>
+struct WsShape {
+    static constexpr int E = sizeof(T) == 4 ? 4 : 2;  // elements per lane per step
+    static constexpr int STEP = 64 * E;
+};
+
+// Contiguous element range of this block, a multiple of the step.
+template <typename T>
+__device__ __forceinline__ void ws_range(size_t N, size_t& b0, size_t& b1) {
+    const size_t step = WsShape<T>::STEP;
+    const size_t per = ((N + gridDim.x - 1) / gridDim.x + step - 1) / step * step;
+    b0 = (size_t)blockIdx.x * per;
+    b1 = b0 + per < N ? b0 + per : N;
+}
+
+// Per-wave accumulators (vectors i = wave + 4k) -> partials[(2i + c) * nblk + block].
+template <typename T, int NPW>
+__device__ __forceinline__ void ws_store(const T (&acc)[2 * NPW], int jj, double* sums, double* partials) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+        const int i = wave + WS_WAVES * k;
+        if (i <= jj) {
+            const double re = wave_sum(double(acc[2 * k])), im = wave_sum(double(acc[2 * k + 1]));
+            if (lane == 0) {
+                sums[2 * i] = re;
+                sums[2 * i + 1] = im;
+            }
+        }
+    }
+    __syncthreads();
+    store_partials(sums, 2 * (jj + 1), partials);
+}
+
+// w = A (s z) on the fine grid and partial conj(V_i) w, i <= jj (finalize with FIN_MV).
+template <typename T, int NV>
+__global__ __launch_bounds__(BLOCK) void k_arnoldi_helm_ws(Geom G, const T* __restrict__ n2,
+                                                           const cplx<T>* __restrict__ z, int use_scale, VecSet<T> V,
+                                                           int jj, cplx<T>* __restrict__ w, const KrylovScal* K,
+                                                           double* partials) {
+    constexpr int NPW = (NV + WS_WAVES - 1) / WS_WAVES;
+    constexpr int E = WsShape<T>::E;
+    __shared__ double sums[2 * NV + 2];
+    if (K->done) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const T sj = use_scale ? T(K->scale[jj]) : T(1);
+    const size_t N = (size_t)G.n * G.n;
+    T acc[2 * NPW];
+#pragma unroll
+    for (int q = 0; q < 2 * NPW; ++q) acc[q] = T(0);
+    size_t b0, b1;
+    ws_range<T>(N, b0, b1);
+    for (size_t base = b0; base < b1; base += WsShape<T>::STEP) {
+        cplx<T> x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const size_t p = base + (size_t)e * 64 + lane;
+            x[e] = cplx<T>{};
+            if (p < b1) {
+                const int i = (int)(p / G.n), j = (int)(p % G.n);
+                if (i > 0 && j > 0) x[e] = sj * applyA_at(G, n2, z, i, j, false);
+                if (wave == 0) w[p] = x[e];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NPW; ++k) {
+            const int iv = wave + WS_WAVES * k;
+            if (iv <= jj) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const size_t p = base + (size_t)e * 64 + lane;
+                    if (p < b1) {
+                        const cplx<T> v = V.v[iv][p];
+                        acc[2 * k] += v.re * x[e].re + v.im * x[e].im;
+                        acc[2 * k + 1] += v.re * x[e].im - v.im * x[e].re;
+                    }
+                }
+            }
+        }
+    }
+    ws_store<T, NPW>(acc, jj, sums, partials);
+}
+
+// Gram-Schmidt pass 1: w -= sum_i dots_i v_i; partial conj(V_i) w (FIN_ORTH1).
+template <typename T, int NV>
+__global__ __launch_bounds__(BLOCK) void k_orth_pass1_ws(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
+                                                         const KrylovScal* K, double* partials) {
+    constexpr int NPW = (NV + WS_WAVES - 1) / WS_WAVES;
+    constexpr int E = WsShape<T>::E;
+    __shared__ cplx<T> cs[NV];
+    __shared__ cplx<T> part[WS_WAVES][E][64];
+    __shared__ double sums[2 * NV + 2];
+    if (K->done) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if ((int)threadIdx.x < NV) {
+        const int i = threadIdx.x;
+        cs[i] = i <= jj ? mk<T>(T(K->dots[2 * i] * K->scale[i]), T(K->dots[2 * i + 1] * K->scale[i])) : cplx<T>{};
+    }
+    __syncthreads();
+    T acc[2 * NPW];
+#pragma unroll
+    for (int q = 0; q < 2 * NPW; ++q) acc[q] = T(0);
+    size_t b0, b1;
+    ws_range<T>(N, b0, b1);
+    for (size_t base = b0; base < b1; base += WsShape<T>::STEP) {
+        cplx<T> v[NPW][E];
+        cplx<T> px[E], wv[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            // every wave reads w before the barrier; wave 0 overwrites it after
+            const size_t p = base + (size_t)e * 64 + lane;
+            px[e] = cplx<T>{};
+            wv[e] = p < b1 ? w[p] : cplx<T>{};
+        }
+#pragma unroll
+        for (int k = 0; k < NPW; ++k) {
+            const int iv = wave + WS_WAVES * k;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const size_t p = base + (size_t)e * 64 + lane;
+                v[k][e] = (iv <= jj && p < b1) ? V.v[iv][p] : cplx<T>{};
+                px[e] = px[e] + cs[iv <= jj ? iv : 0] * v[k][e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) part[wave][e][lane] = px[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const size_t p = base + (size_t)e * 64 + lane;
+            cplx<T> x{};
+            if (p < b1) {
+                x = wv[e] - ((part[0][e][lane] + part[1][e][lane]) + (part[2][e][lane] + part[3][e][lane]));
+                if (wave == 0) w[p] = x;
+            }
+#pragma unroll
+            for (int k = 0; k < NPW; ++k) {
+                acc[2 * k] += v[k][e].re * x.re + v[k][e].im * x.im;
+                acc[2 * k + 1] += v[k][e].re * x.im - v[k][e].im * x.re;
+            }
+        }
+        __syncthreads();
+    }
+    ws_store<T, NPW>(acc, jj, sums, partials);
 }
 
 enum FinOp { FIN_INIT = 0, FIN_MV = 1, FIN_ORTH1 = 2, FIN_ORTH2 = 3 };
