@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2404_02493_amd", "tuning.json"),
+                    help="JSON cache of measured launch shapes ('none' = built-in defaults)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the solver has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -190,6 +192,12 @@ def main():
     log("setup FP32-cycle context")
     H32 = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells)
     H32.set_phase(case.phi)
+    tuning = None
+    if args.tune_cache != "none":
+        t = time.perf_counter()
+        tuning = H32.tune(cache=args.tune_cache)
+        log(f"tuning ({time.perf_counter() - t:.1f} s): sstep_blocks {tuning['sstep_blocks']}, "
+            f"fgmres_blocks {tuning['fgmres_blocks']}")
 
     def run32():
         u = torch.zeros_like(g)
@@ -225,6 +233,8 @@ def main():
         H64 = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c128",
                         damping_cells=case.damping_cells)
         H64.set_phase(case.phi)
+        if args.tune_cache != "none":
+            H64.tune(cache=args.tune_cache)
         u64 = torch.zeros_like(g)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -295,6 +305,7 @@ def main():
         "cpu_baseline": cpu,
         "profile_fp32": summary,
         "adjoint": adjoint,
+        "tuning": {k: v for k, v in tuning.items() if k != "timings_ms"} if tuning else None,
     }
     if prof64:
         ks = prof64["kernels"]

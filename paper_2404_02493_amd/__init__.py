@@ -195,6 +195,53 @@ class Helmholtz:
         check(lib().helm_debug_op(self._ctx, int(op), int(level), _ptr(x), _ptr(x2), _ptr(out), _stream_ptr(stream)))
         return out
 
+    # ------------------------------------------------------------------ autotuning
+    def tuning_key(self) -> str:
+        torch = _torch()
+        d = self.desc
+        name = torch.cuda.get_device_name(self.device)
+        return (f"{name}|n={self.n}|L={self.levels}|{'c64' if self.cdtype == torch.complex64 else 'c128'}"
+                f"|m={d.gmres_m}/{d.gmres_coarse_m}|adr={d.adr_levels}|tail={d.tail_n}|arnoldi={d.gmres_arnoldi}"
+                f"|restart={d.restart}")
+
+    def tune(self, cache: str | None = None, stream=None) -> dict:
+        """Chooses launch shapes by measurement (helm_tune) and applies them.  With a
+        cache path (JSON file), a stored choice for the same device / size / precision /
+        solver shape is applied instead of measuring, and new measurements are stored."""
+        import json
+
+        key = self.tuning_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tuning(table[key])
+                return table[key]
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(lib().helm_tune(self._ctx, buf, len(buf), _stream_ptr(stream)))
+        res = json.loads(buf.value.decode())
+        if cache:
+            table[key] = res
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return res
+
+    def set_tuning(self, tuning):
+        import json
+
+        text = tuning if isinstance(tuning, str) else json.dumps(tuning)
+        check(lib().helm_set_tuning(self._ctx, text.encode()))
+
+    def get_tuning(self) -> dict:
+        import json
+
+        buf = ctypes.create_string_buffer(1 << 12)
+        check(lib().helm_get_tuning(self._ctx, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
     def profile_begin(self):
         check(lib().helm_profile_begin(self._ctx))
 

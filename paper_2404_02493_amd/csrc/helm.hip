@@ -7,6 +7,7 @@
 // except that the outer solver reads one Hessenberg column per iteration.
 #include <algorithm>
 #include <array>
+#include <cctype>
 #include <atomic>
 #include <complex>
 #include <cstdio>
@@ -100,6 +101,11 @@ struct helm_ctx_s {
     void* rbuf = nullptr;    // FP64 residual (mode 1)
     void* dbuf = nullptr;    // inner correction (mode 1)
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
+    // launch shapes chosen by the autotuner (0 = built-in default)
+    struct Tuning {
+        int sstep_blocks[16] = {};  // blocks of the s-step Gram pass on ADR level l
+        int fgmres_blocks = 0;      // blocks of the outer FGMRES passes on the fine grid
+    } tn;
     // captured cycles, keyed by the (g, u_in, u_out) pointers they were captured with
     struct GraphEntry {
         const void* g;
@@ -391,7 +397,7 @@ struct Engine {
         AdrLevel& A = c->al[2];
         LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st, W.G, (const T*)W.n2,
                            (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
-        adr_vcycle(2);
+        if (adr_vcycle(2, true)) return;
         LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))), dim3(BLOCK), st, N(2), (const C*)A.x,
                            (const T*)c->theta2, (C*)W.u);
     }
@@ -417,12 +423,12 @@ struct Engine {
         return true;
     }
 
-    void adr_vcycle(int l) {
+    // One ADR V-cycle from x = 0 on levels l..LA.  top: the caller is the ADR step on
+    // level 2 and accepts the re-modulated update of u folded into the last smoother
+    // (returns whether that happened; otherwise the result is in A.x).
+    bool adr_vcycle(int l, bool top = false) {
         AdrLevel& A = c->al[l];
-        if (l == c->LA) {
-            gmres(l, c->d.gmres_coarse_m, true);
-            return;
-        }
+        if (l == c->LA) return gmres(l, c->d.gmres_coarse_m, true, top);
         gmres(l, c->d.gmres_m, true);
         LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>), dim3(tiles_of(A.n / 2)), tile_block(), st, A.A,
                            (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
@@ -430,7 +436,7 @@ struct Engine {
         adr_vcycle(l + 1);
         LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), st, A.n,
                            (const C*)c->al[l + 1].x, (C*)A.x);
-        gmres(l, c->d.gmres_m, false);
+        return gmres(l, c->d.gmres_m, false, top);
     }
 
     template <int NV>
@@ -466,10 +472,13 @@ struct Engine {
         LAUNCH(c, (m + 1 + (x0_zero ? 0 : 1)) * sizeof(C) * double(n), (k_krylov_combine<T, NV>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, V,
                            (const KrylovScal*)A.K, (const C*)(x0_zero ? nullptr : A.x), (C*)A.x);
     }
+    // s-step GMRES(MM) on ADR level l.  mod: the result is not stored but added,
+    // re-modulated, to the level-2 iterate (the end of an ADR step).
     template <int MM>
-    void gmres_sstep(int l, bool x0_zero) {
+    void gmres_sstep(int l, bool x0_zero, bool mod = false) {
         AdrLevel& A = c->al[l];
-        const int nb = tiles_of(A.n), nbr = red_blocks(A.n);
+        const int nb = tiles_of(A.n);
+        const int nbr = c->tn.sstep_blocks[l] > 0 ? std::min(c->tn.sstep_blocks[l], red_blocks(A.n)) : red_blocks(A.n);
         constexpr int NG = (MM + 1) * (MM + 1);
         const double bx = x0_zero ? 0.0 : 1.0;
         if (x0_zero) {
@@ -481,36 +490,55 @@ struct Engine {
                    tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                    (const C*)A.x, c->partials);
         }
-        LAUNCH(c, 8.0 * NG * nbr, (k_sstep_solve<MM>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nbr,
-               A.K, 1e-12);
+        double* gsum = A.K->R;  // device scratch inside the Krylov state
+        LAUNCH(c, 8.0 * NG * nbr, k_sstep_reduce, dim3(NG), dim3(BLOCK), st, (const double*)c->partials, nbr, gsum);
+        const double tolb = 1e-12;
+        const T* th = (const T*)c->theta2;
+        C* u2 = (C*)c->wl[2].u;
         if (x0_zero) {
-            LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false>), dim3(nb),
-                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                   (const C*)nullptr, (const KrylovScal*)A.K, (C*)A.x);
+            if (mod)
+                LAUNCH(c, (4 * sizeof(C) + 3 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false, true>), dim3(nb),
+                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                       (const C*)nullptr, (const double*)gsum, tolb, A.K, (C*)nullptr, th, u2);
+            else
+                LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false, false>), dim3(nb),
+                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                       (const C*)nullptr, (const double*)gsum, tolb, A.K, (C*)A.x, th, (C*)nullptr);
         } else {
-            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true>), dim3(nb),
-                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                   (const C*)A.x, (const KrylovScal*)A.K, (C*)A.xalt);
-            std::swap(A.x, A.xalt);
+            if (mod) {
+                LAUNCH(c, (5 * sizeof(C) + 3 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true, true>), dim3(nb),
+                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                       (const C*)A.x, (const double*)gsum, tolb, A.K, (C*)nullptr, th, u2);
+            } else {
+                LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true, false>), dim3(nb),
+                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                       (const C*)A.x, (const double*)gsum, tolb, A.K, (C*)A.xalt, th, (C*)nullptr);
+                std::swap(A.x, A.xalt);
+            }
         }
     }
 
-    void gmres(int l, int m, bool x0_zero) {
+    // GMRES(m) smoother on ADR level l (x = A.x, b = A.b).  mod: for the last smoother
+    // of an ADR step on level 2, fold the re-modulated update of u into the kernel when
+    // the s-step form runs; returns whether it did.
+    bool gmres(int l, int m, bool x0_zero, bool mod = false) {
         // one workgroup on the coarsest level, s-step form on the larger ones
-        if (l == c->LA && gmres_block(l, m, x0_zero)) return;
+        if (l == c->LA && gmres_block(l, m, x0_zero)) return false;
         if (m <= 4 && !c->d.gmres_arnoldi) {
             switch (m) {
-                case 1: gmres_sstep<1>(l, x0_zero); return;
-                case 2: gmres_sstep<2>(l, x0_zero); return;
-                case 3: gmres_sstep<3>(l, x0_zero); return;
-                default: gmres_sstep<4>(l, x0_zero); return;
+                case 1: gmres_sstep<1>(l, x0_zero, mod); break;
+                case 2: gmres_sstep<2>(l, x0_zero, mod); break;
+                case 3: gmres_sstep<3>(l, x0_zero, mod); break;
+                default: gmres_sstep<4>(l, x0_zero, mod); break;
             }
+            return mod;
         }
         switch (nv_bucket(m)) {
             case 4: gmres_nv<4>(l, m, x0_zero); break;
             case 12: gmres_nv<12>(l, m, x0_zero); break;
             default: gmres_nv<MAXM>(l, m, x0_zero); break;
         }
+        return false;
     }
 };
 
@@ -545,7 +573,7 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     const Geom G = make_geom(c, 1);
     const size_t N = (size_t)G.n * G.n;
     // K init from V[0]
-    const int nbf = flat_blocks(N, MAXRED);
+    const int nbf = c->tn.fgmres_blocks > 0 ? std::min(c->tn.fgmres_blocks, MAXRED) : flat_blocks(N, MAXRED);
     LAUNCH(c, sizeof(Cp) * double(N), (k_krylov_init_norm<P>), dim3(nbf), dim3(BLOCK), st, N, (const Cp*)V[0],
            c->partials);
     krylov_fin<MAXM>(c, st, nbf, FIN_INIT, 0, m, K, 0.0);
@@ -990,6 +1018,7 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
 
 #include "adjoint_host.hpp"
 #include "batch.hpp"
+#include "tune.hpp"
 
 }  // namespace helm
 
@@ -1261,6 +1290,37 @@ helm_status helm_batch_solve(helm_batch b, const void* const* g, void* const* u,
 helm_status helm_batch_destroy(helm_batch b) {
     batch_free(b);
     return HELM_OK;
+}
+
+helm_status helm_tune(helm_ctx ctx, char* json, int64_t cap, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr, "NULL argument");
+        hipStream_t st = (hipStream_t)stream;
+        std::string out = ctx->f32 ? tune_ctx<float>(ctx, st) : tune_ctx<double>(ctx, st);
+        if (json) {
+            REQUIRE((int64_t)out.size() < cap, "tuning buffer too small");
+            std::memcpy(json, out.c_str(), out.size() + 1);
+        }
+        return HELM_OK;
+    })
+}
+
+helm_status helm_set_tuning(helm_ctx ctx, const char* json) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && json != nullptr, "NULL argument");
+        apply_tuning(ctx, json);
+        return HELM_OK;
+    })
+}
+
+helm_status helm_get_tuning(helm_ctx ctx, char* json, int64_t cap) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && json != nullptr && cap > 0, "NULL argument");
+        std::string out = tuning_json(ctx, "");
+        REQUIRE((int64_t)out.size() < cap, "tuning buffer too small");
+        std::memcpy(json, out.c_str(), out.size() + 1);
+        return HELM_OK;
+    })
 }
 
 helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* in, const void* in2, void* out,

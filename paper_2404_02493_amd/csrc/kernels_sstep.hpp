@@ -6,7 +6,8 @@
 // The Krylov vectors are never stored: each pass rebuilds them on a 64 x 16 tile
 // plus a halo of one node per operator application, staged through LDS.
 //   pass 1 (k_sstep_gram):    K_0..K_m on the tile, Gram matrix G = K^H K (FP64)
-//   solve  (k_sstep_solve):   one block: G -> normalised Cholesky -> c
+//   reduce (k_sstep_reduce):  the Gram partials summed, one block per entry
+//   (the normalised Cholesky solve for c runs at the start of every combine block)
 //   pass 2 (k_sstep_combine): K_0..K_{m-1} again, x_out = x0 + sum c_j K_{j-1}
 // The normalised monomial basis of the ADR operator is well conditioned for
 // m <= 4 (condition numbers of 5-40 measured on the workloads), so the normal
@@ -163,16 +164,12 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_gram(AdrGeom A, const T* __rest
     store_partials(sums, S::NG, partials);
 }
 
-// One block: G = sum of the partials, normalised Cholesky solve of the normal
-// equations, c_j stored in K->y (complex), K->cols = number of columns kept.
+// Normalised Cholesky solve of the normal equations from the Gram sums (layout of
+// k_sstep_gram); one thread.  yr, yi: coefficients c_j of K_{j-1}; cols: columns kept
+// (columns after the first negligible pivot are dropped); beta = ||K_0||.
 template <int M>
-__global__ __launch_bounds__(FBLOCK) void k_sstep_solve(const double* __restrict__ partials, int nblk, KrylovScal* K,
-                                                        double breakdown_tol) {
-    constexpr int NG = (M + 1) * (M + 1);
-    __shared__ double red[(FBLOCK / 64) * NG];
-    __shared__ double sums[NG];
-    final_sum<NG>(partials, nblk, NG, red, sums);
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sums, double breakdown_tol,
+                                                  double (&yr)[M], double (&yi)[M], int& cols, double& beta) {
     // Hermitian G(i,j), i,j = 0..M; every loop below has compile-time bounds so that
     // the small arrays stay in registers.
     double gr[M + 1][M + 1], gi[M + 1][M + 1];
@@ -194,11 +191,10 @@ __global__ __launch_bounds__(FBLOCK) void k_sstep_solve(const double* __restrict
                 o += 2;
             }
     }
-    const double beta = sqrt(gr[0][0]);
-    double yr[M], yi[M];
+    beta = sqrt(gr[0][0]);
 #pragma unroll
     for (int i = 0; i < M; ++i) yr[i] = yi[i] = 0.0;
-    int cols = 0;
+    cols = 0;
     if (beta > 0.0 && isfinite(beta)) {
         double d[M + 1];
 #pragma unroll
@@ -268,24 +264,35 @@ __global__ __launch_bounds__(FBLOCK) void k_sstep_solve(const double* __restrict
             yi[i] = zi[i] * s;
         }
     }
-    K->beta = beta;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        K->y[2 * i] = yr[i];
-        K->y[2 * i + 1] = yi[i];
-    }
-    K->cols = cols;
-    K->done = isfinite(beta) ? 1 : 2;
 }
 
-// Pass 2: x_out = x0 + sum_{j=1..cols} c_j K_{j-1} on the tile interior.
-template <typename T, int M, bool X0>
+// Grid reduction of the Gram partials: block v sums partials[v * nblk + b] over b
+// (fixed order) into gsum[v]; NG blocks of BLOCK threads.
+__global__ __launch_bounds__(BLOCK) void k_sstep_reduce(const double* __restrict__ partials, int nblk,
+                                                        double* __restrict__ gsum) {
+    __shared__ double red[4];
+    __shared__ double sums[1];
+    const int v = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += BLOCK) acc[0] += partials[(size_t)v * nblk + b];
+    block_sum<1, 4>(acc, 1, red, sums);
+    if (threadIdx.x == 0) gsum[v] = sums[0];
+}
+
+// Pass 2: x_out = x0 + sum_{j=1..cols} c_j K_{j-1} on the tile interior, with the
+// coefficients solved per block from the Gram sums gsum (thread 0, overlapped with
+// the other threads' tile loads); block 0 also records them in K.  MOD: instead of
+// writing x_out, adds x_out e^{i theta} to u (the re-modulation of the ADR step).
+template <typename T, int M, bool X0, bool MOD = false>
 __global__ __launch_bounds__(BLOCK) void k_sstep_combine(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                          const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
-                                                         const cplx<T>* __restrict__ x0, const KrylovScal* K,
-                                                         cplx<T>* __restrict__ xout) {
+                                                         const cplx<T>* __restrict__ x0,
+                                                         const double* __restrict__ gsum, double breakdown_tol,
+                                                         KrylovScal* K, cplx<T>* __restrict__ xout,
+                                                         const T* __restrict__ theta, cplx<T>* __restrict__ u) {
     using S = SStep<M, X0>;
     __shared__ cplx<T> buf[S::NB][S::PN];
+    __shared__ cplx<T> cs[M];
     int j0, i0;
     {
         int jj, ii;
@@ -293,14 +300,30 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine(AdrGeom A, const T* __r
         j0 = jj - (int)threadIdx.x;
         i0 = ii - (int)threadIdx.y * RPT;
     }
-    const int cols = K->cols;
-    cplx<T> c[M];
+    const int tid = threadIdx.x + threadIdx.y * TX;
+    if (tid == 0) {
+        double yr[M], yi[M], beta;
+        int cols;
+        sstep_small_solve<M>(gsum, breakdown_tol, yr, yi, cols, beta);
 #pragma unroll
-    for (int j = 0; j < M; ++j) c[j] = j < cols ? mk<T>(T(K->y[2 * j]), T(K->y[2 * j + 1])) : cplx<T>{};
-    // K_0 needs halo M-1 here
+        for (int j = 0; j < M; ++j) cs[j] = mk<T>(T(yr[j]), T(yi[j]));
+        if (blockIdx.x == 0) {
+            K->beta = beta;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                K->y[2 * j] = yr[j];
+                K->y[2 * j + 1] = yi[j];
+            }
+            K->cols = cols;
+            K->done = isfinite(beta) ? 1 : 2;
+        }
+    }
+    // K_0 needs halo M-1 here (the loads end with a barrier, which also publishes cs)
     sstep_load<T, M, X0>(A, px, py, c0, b, x0, buf[1], buf[0], M - 1, i0, j0);
     for (int j = 1; j < M; ++j) sstep_stage<T, M, X0>(A, px, py, c0, buf[j - 1], buf[j], M - 1 - j, i0, j0);
-    const int tid = threadIdx.x + threadIdx.y * TX;
+    cplx<T> c[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) c[j] = cs[j];
     for (int q = tid; q < TX * TY; q += BLOCK) {
         const int ri = q / TX, rj = q - ri * TX;
         const int gi = i0 + ri, gj = j0 + rj;
@@ -313,7 +336,13 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine(AdrGeom A, const T* __r
 #pragma unroll
             for (int j = 0; j < M; ++j) v = v + c[j] * buf[j][li * S::PW + lj];
         }
-        xout[p] = v;
+        if (MOD) {
+            T sn, cn;
+            sincos_t(theta[p], &sn, &cn);
+            u[p] = u[p] + v * mk<T>(cn, sn);
+        } else {
+            xout[p] = v;
+        }
     }
 }
 

@@ -1,0 +1,211 @@
+// Autotuner of launch shapes, measured on the context's own hierarchy.
+//
+// Knobs (each changes only how a reduction is split over blocks, hence only the
+// summation order of FP64 partial sums):
+//   sstep_blocks[l]  blocks of the s-step GMRES Gram pass on ADR level l: fewer
+//                    blocks shorten the one-block solve that sums their partials,
+//                    more blocks expose more parallelism in the Gram pass;
+//   fgmres_blocks    blocks of the outer FGMRES passes on the fine grid.
+// Every candidate runs the real kernels on the level's buffers filled with
+// hashed data; the fastest (HIP-event time over a few repetitions) is kept.  The
+// result is a small JSON text that helm_set_tuning applies again later, so a
+// caller can cache it per (device, problem size, precision).
+//
+// Included from helm.hip inside namespace helm.
+#pragma once
+
+// x = hashed values in [-1, 1] + i [-1, 1] on the unknowns, 0 on the ring.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_fill_hash(int n, uint32_t seed, cplx<T>* __restrict__ x) {
+    const size_t N = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        uint64_t h = (uint64_t)p * 0x9E3779B97F4A7C15ull + seed;
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 29;
+        const double a = double(h & 0xFFFFFF) / double(0x800000) - 1.0;
+        const double b = double((h >> 24) & 0xFFFFFF) / double(0x800000) - 1.0;
+        x[p] = (i == 0 || j == 0) ? cplx<T>{} : mk<T>(T(a), T(b));
+    }
+}
+
+// A Krylov state that lets the FGMRES passes run with every coefficient zero.
+__global__ void k_tune_kstate(KrylovScal* K) {
+    if (threadIdx.x != 0) return;
+    K->done = 0;
+    K->beta = 1.0;
+    for (int i = 0; i <= MAXM; ++i) K->scale[i] = 1.0;
+    for (int i = 0; i < 2 * (MAXM + 2); ++i) K->dots[i] = 0.0;
+}
+
+template <typename F>
+static double time_ms(hipStream_t st, int reps, F&& f) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    f();  // warm
+    HIPCHK(hipEventRecord(a, st));
+    for (int r = 0; r < reps; ++r) f();
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return double(ms) / reps;
+}
+
+static std::string tuning_json(helm_ctx c, const std::string& timings) {
+    std::string out = "{\"n\": " + std::to_string(c->d.n) + ", \"levels\": " + std::to_string(c->L) +
+                      ", \"prec\": \"" + (c->f32 ? "c64" : "c128") + "\", \"sstep_blocks\": {";
+    bool first = true;
+    for (int l = 2; l <= c->LA && l < 16; ++l) {
+        if (c->tn.sstep_blocks[l] <= 0) continue;
+        out += std::string(first ? "" : ", ") + "\"" + std::to_string(l) + "\": " + std::to_string(c->tn.sstep_blocks[l]);
+        first = false;
+    }
+    out += "}, \"fgmres_blocks\": " + std::to_string(c->tn.fgmres_blocks);
+    if (!timings.empty()) out += ", \"timings_ms\": {" + timings + "}";
+    return out + "}";
+}
+
+template <typename T>
+static std::string tune_ctx(helm_ctx c, hipStream_t st) {
+    Engine<T> E(c, st);
+    char buf[128];
+    std::string tim;
+    auto note = [&](const std::string& key, double ms) {
+        std::snprintf(buf, sizeof(buf), "%s\"%s\": %.5f", tim.empty() ? "" : ", ", key.c_str(), ms);
+        tim += buf;
+    };
+    const int reps = 5;
+    // ADR levels that run the s-step form
+    if (c->L >= 3 && c->d.adr_steps > 0 && !c->d.gmres_arnoldi) {
+        for (int l = 2; l <= c->LA && l < 16; ++l) {
+            AdrLevel& A = c->al[l];
+            const int m = l == c->LA ? c->d.gmres_coarse_m : c->d.gmres_m;
+            if (m > 4) continue;
+            if (l == c->LA && A.n <= c->d.tail_n && (size_t)A.n * A.n <= 4096) continue;  // one-workgroup form
+            const int nb = flat_blocks((size_t)A.n * A.n);
+            hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.n, 17u + l, (cplx<T>*)A.b);
+            hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.n, 91u + l, (cplx<T>*)A.x);
+            HIPCHK(hipGetLastError());
+            int best = 0;
+            double tbest = 1e30;
+            for (int cand = 64; cand <= MAXRED; cand *= 2) {
+                if (cand > red_blocks(A.n)) break;
+                c->tn.sstep_blocks[l] = cand;
+                const double t = time_ms(st, reps, [&] {
+                    E.gmres(l, m, true);
+                    E.gmres(l, m, false);
+                });
+                note("sstep_l" + std::to_string(l) + "_" + std::to_string(cand), t);
+                if (t < tbest) {
+                    tbest = t;
+                    best = cand;
+                }
+            }
+            c->tn.sstep_blocks[l] = best;
+        }
+    }
+    // outer FGMRES passes on the fine grid (basis of the inner solver for complex64
+    // cycles, of the FP64 solver otherwise), at the middle of a restart cycle
+    {
+        const int mode = c->f32 ? 1 : 0;
+        ensure_solver_ws(c, mode);
+        const Geom G = make_geom(c, 1);
+        const size_t NF = (size_t)G.n * G.n;
+        const int jj = std::max(0, c->d.restart / 2);
+        void** Vp = c->f32 ? c->iV : c->fV;
+        void** Zp = c->f32 ? c->iZ : c->fZ;
+        const void* n2 = c->f32 ? c->wl[1].n2 : (const void*)c->n2f;
+        for (int i = 0; i <= jj + 1; ++i)
+            hipLaunchKernelGGL((k_fill_hash<T>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, G.n, 1000u + i,
+                               (cplx<T>*)Vp[i]);
+        hipLaunchKernelGGL((k_fill_hash<T>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, G.n, 7u, (cplx<T>*)Zp[0]);
+        hipLaunchKernelGGL(k_tune_kstate, dim3(1), dim3(64), 0, st, c->Kin);
+        HIPCHK(hipGetLastError());
+        VecSet<T> Vs{};
+        for (int i = 0; i <= c->d.restart; ++i) Vs.v[i] = (const cplx<T>*)Vp[i];
+        int best = 0;
+        double tbest = 1e30;
+        for (int cand = 256; cand <= MAXRED; cand *= 2) {
+            const double t = time_ms(st, reps, [&] {
+                hipLaunchKernelGGL((k_arnoldi_helm_ws<T, MAXM>), dim3(cand), dim3(BLOCK), 0, st, G, (const T*)n2,
+                                   (const cplx<T>*)Zp[0], 0, Vs, jj, (cplx<T>*)Vp[jj + 1], (const KrylovScal*)c->Kin,
+                                   c->partials);
+                hipLaunchKernelGGL((k_orth_pass1_ws<T, MAXM>), dim3(cand), dim3(BLOCK), 0, st, NF, Vs, jj,
+                                   (cplx<T>*)Vp[jj + 1], (const KrylovScal*)c->Kin, c->partials);
+                hipLaunchKernelGGL((k_orth_pass2<T, MAXM>), dim3(cand), dim3(BLOCK), 0, st, NF, Vs, jj,
+                                   (cplx<T>*)Vp[jj + 1], (const KrylovScal*)c->Kin, c->partials);
+            });
+            HIPCHK(hipGetLastError());
+            note("fgmres_" + std::to_string(cand), t);
+            if (t < tbest) {
+                tbest = t;
+                best = cand;
+            }
+        }
+        c->tn.fgmres_blocks = best;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    drop_graphs(c);
+    return tuning_json(c, tim);
+}
+
+// Applies {"sstep_blocks": {"l": blocks, ...}, "fgmres_blocks": blocks} (other keys ignored).
+static void apply_tuning(helm_ctx c, const char* json) {
+    const std::string s(json);
+    helm_ctx_s::Tuning t = c->tn;
+    auto skip_ws = [&](size_t& i) {
+        while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\t' || s[i] == '\r')) ++i;
+    };
+    auto read_int = [&](size_t& i) -> long {
+        skip_ws(i);
+        REQUIRE(i < s.size() && (std::isdigit((unsigned char)s[i]) || s[i] == '-'), "tuning: integer expected");
+        size_t used = 0;
+        long v = std::stol(s.substr(i), &used);
+        i += used;
+        return v;
+    };
+    size_t k = s.find("\"sstep_blocks\"");
+    if (k != std::string::npos) {
+        size_t i = s.find('{', k);
+        REQUIRE(i != std::string::npos, "tuning: sstep_blocks must be an object");
+        ++i;
+        for (int l = 0; l < 16; ++l) t.sstep_blocks[l] = 0;
+        for (;;) {
+            skip_ws(i);
+            REQUIRE(i < s.size(), "tuning: unterminated sstep_blocks");
+            if (s[i] == '}') break;
+            if (s[i] == ',') {
+                ++i;
+                continue;
+            }
+            REQUIRE(s[i] == '"', "tuning: level key expected");
+            ++i;
+            const long l = read_int(i);
+            REQUIRE(i < s.size() && s[i] == '"', "tuning: level key expected");
+            ++i;
+            skip_ws(i);
+            REQUIRE(i < s.size() && s[i] == ':', "tuning: ':' expected");
+            ++i;
+            const long v = read_int(i);
+            REQUIRE(l >= 2 && l <= c->LA && l < 16, "tuning: level out of range");
+            REQUIRE(v >= 0 && v <= MAXRED, "tuning: block count out of range");
+            t.sstep_blocks[l] = (int)v;
+        }
+    }
+    k = s.find("\"fgmres_blocks\"");
+    if (k != std::string::npos) {
+        size_t i = s.find(':', k);
+        REQUIRE(i != std::string::npos, "tuning: fgmres_blocks value expected");
+        ++i;
+        const long v = read_int(i);
+        REQUIRE(v >= 0 && v <= MAXRED, "tuning: block count out of range");
+        t.fgmres_blocks = (int)v;
+    }
+    c->tn = t;
+    drop_graphs(c);
+}

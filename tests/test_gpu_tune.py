@@ -1,0 +1,70 @@
+"""GPU: the launch-shape autotuner (helm_tune / helm_set_tuning).
+
+The tuner only changes how FP64 partial sums are split over blocks, so a tuned
+context must keep the oracle parity of an untuned one (relative 1e-12 for FP64
+cycles, 1e-5 for FP32 cycles), and a cached tuning must apply exactly."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import helm_inputs as hi
+from oracle.cycle import Problem, cycle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-12), ("c64", 1e-5)])
+def test_tuned_cycle_keeps_parity(prec, tol, tmp_path):
+    from paper_2404_02493_amd import Helmholtz
+
+    c = hi.make_problem(256, 160.0, 5, seed=4, medium="grf", phase="fmm", damping_cells=16)
+    P = Problem(c.velocity, c.k, c.levels, damping_cells=16, phi=c.phi)
+    H = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=16)
+    H.set_phase(c.phi)
+    H.set_weights(P.weights.numpy())
+    cache = str(tmp_path / "tune.json")
+    res = H.tune(cache=cache)
+    print(json.dumps(res), flush=True)
+    assert res["fgmres_blocks"] in (256, 512, 1024, 2048)
+    for l, nb in res["sstep_blocks"].items():
+        assert 2 <= int(l) <= c.levels and 64 <= nb <= 2048
+    assert H.get_tuning()["sstep_blocks"] == res["sstep_blocks"]
+    rng = np.random.default_rng(1)
+    u0 = rng.standard_normal((256, 256)) + 1j * rng.standard_normal((256, 256))
+    u0[0, :] = 0
+    u0[:, 0] = 0
+    g = torch.as_tensor(c.g)
+    ref = cycle(P, g.to(torch.complex128), torch.as_tensor(u0))
+    dt = H.cdtype
+    gd = g.to(dt).to("cuda:0")
+    ud = torch.as_tensor(u0).to(dt).to("cuda:0")
+    if prec == "c64":  # the oracle sees the rounded inputs
+        ref = cycle(P, g.to(dt).to(torch.complex128), torch.as_tensor(u0).to(dt).to(torch.complex128))
+    H.cycle(gd, ud)
+    err = (torch.linalg.norm(ud.cpu().to(torch.complex128) - ref) / torch.linalg.norm(ref)).item()
+    assert err < tol, err
+    # a second context takes the cached choice without measuring
+    H2 = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=16)
+    res2 = H2.tune(cache=cache)
+    assert res2 == res
+    assert H2.get_tuning()["fgmres_blocks"] == res["fgmres_blocks"]
+    H.close()
+    H2.close()
+
+
+def test_set_tuning_rejects_bad_input():
+    from paper_2404_02493_amd import Helmholtz, HelmError
+
+    c = hi.make_problem(128, 80.0, 4, seed=1, medium="const", phase="analytic", damping_cells=16)
+    H = Helmholtz(c.velocity, c.k, levels=c.levels, damping_cells=16)
+    before = H.get_tuning()
+    for bad in ['{"sstep_blocks": {"9": 64}}', '{"fgmres_blocks": 99999}', '{"sstep_blocks": {"2": x}}']:
+        with pytest.raises(HelmError):
+            H.set_tuning(bad)
+        assert H.get_tuning() == before
+    H.set_tuning('{"sstep_blocks": {"2": 128}, "fgmres_blocks": 512}')
+    t = H.get_tuning()
+    assert t["sstep_blocks"] == {"2": 128} and t["fgmres_blocks"] == 512
+    H.close()
