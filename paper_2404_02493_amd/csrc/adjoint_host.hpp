@@ -214,8 +214,8 @@ struct AdjEngine {
         }
         const int m = gm_of(c, l);
         rec_gmres(l, Tp.b, nullptr, m, Tp.kpre, Tp.rpre, Tp.x1);
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_adr_resid_restrict<T>), dim3(tiles_of(A.n / 2)),
-               tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)Tp.b,
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.n)),
+               dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)Tp.b,
                (const C*)Tp.x1, (C*)S.adr[s][l + 1].b);
         rec_adrv(s, l + 1);
         copy(Tp.x2, Tp.x1, N(l) * sizeof(C));

@@ -318,7 +318,7 @@ struct Engine {
     template <typename Pf, typename Pc>
     void resid_restrict(int l, const void* g, const void* u, void* rc) {
         const Geom& G = c->wl[l].G;
-        LAUNCH(c, (u ? 2 * sizeof(cplx<Pf>) + sizeof(Pf) : sizeof(cplx<Pf>)) * NN(G.n) + sizeof(cplx<Pc>) * NN(G.n / 2), (k_resid_restrict<Pf, Pc>), dim3(tiles_of(G.n / 2)), tile_block(), st, G,
+        LAUNCH(c, (u ? 2 * sizeof(cplx<Pf>) + sizeof(Pf) : sizeof(cplx<Pf>)) * NN(G.n) + sizeof(cplx<Pc>) * NN(G.n / 2), (k_resid_restrict<Pf, Pc>), dim3(rr_blocks(G.n)), dim3(BLOCK), st, G,
                            (const Pf*)c->wl[l].n2, (const cplx<Pf>*)g, (const cplx<Pf>*)u, (cplx<Pc>*)rc);
     }
     template <typename Pc, typename Pf>
@@ -397,7 +397,9 @@ struct Engine {
         AdrLevel& A = c->al[2];
         LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st, W.G, (const T*)W.n2,
                            (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
-        if (adr_vcycle(2, true)) return;
+        // the re-modulation stays a separate streaming pass: folded into the last
+        // smoother's combine kernel (adr_vcycle(2, true)) it ran slower on gfx950
+        adr_vcycle(2);
         LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))), dim3(BLOCK), st, N(2), (const C*)A.x,
                            (const T*)c->theta2, (C*)W.u);
     }
@@ -430,7 +432,7 @@ struct Engine {
         AdrLevel& A = c->al[l];
         if (l == c->LA) return gmres(l, c->d.gmres_coarse_m, true, top);
         gmres(l, c->d.gmres_m, true);
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>), dim3(tiles_of(A.n / 2)), tile_block(), st, A.A,
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.n)), dim3(BLOCK), st, A.A,
                            (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
                            (C*)c->al[l + 1].b);
         adr_vcycle(l + 1);

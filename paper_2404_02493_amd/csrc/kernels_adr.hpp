@@ -119,30 +119,24 @@ __device__ __forceinline__ cplx<T> adr_resid_at(const AdrGeom& A, const T* px, c
     return bv - applyM_at(A, px, py, c0, x, i, j);
 }
 
-// rc = R (b - M x) on the next ADR level (x == nullptr: x = 0)
+template <typename T>
+struct AdrRes {
+    AdrGeom A;
+    const T* px;
+    const T* py;
+    const cplx<T>* c0;
+    const cplx<T>* b;
+    const cplx<T>* x;
+    __device__ cplx<T> operator()(int i, int j) const { return adr_resid_at(A, px, py, c0, b, x, i, j); }
+};
+
+// rc = R (b - M x) on the next ADR level (x == nullptr: x = 0); rr_blocks(A.n) blocks.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_resid_restrict(AdrGeom A, const T* __restrict__ px,
                                                               const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                                               const cplx<T>* __restrict__ b,
                                                               const cplx<T>* __restrict__ x, cplx<T>* __restrict__ rc) {
-    const int nc = A.n / 2;
-    int J, I0;
-    tile_origin(nc, J, I0);
-    if (J >= nc) return;
-    for (int r = 0; r < RPT; ++r) {
-        const int I = I0 + r;
-        if (I >= nc) break;
-        cplx<T> v{};
-        if (I > 0 && J > 0) {
-            const int fi = 2 * I, fj = 2 * J;
-            auto R = [&](int a, int bb) { return adr_resid_at(A, px, py, c0, b, x, a, bb); };
-            cplx<T> c = R(fi, fj);
-            cplx<T> ud = R(fi - 1, fj) + R(fi + 1, fj) + R(fi, fj - 1) + R(fi, fj + 1);
-            cplx<T> dg = R(fi - 1, fj - 1) + R(fi - 1, fj + 1) + R(fi + 1, fj - 1) + R(fi + 1, fj + 1);
-            v = T(1.0 / 16.0) * ((T(4) * c + T(2) * ud) + dg);
-        }
-        rc[(size_t)I * nc + J] = v;
-    }
+    restrict_tile<T, T>(A.n, AdrRes<T>{A, px, py, c0, b, x}, rc);
 }
 
 // r_hat = (g - A u) e^{-i theta}

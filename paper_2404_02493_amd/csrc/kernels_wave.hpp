@@ -148,35 +148,68 @@ __global__ __launch_bounds__(FBLOCK) void k_finalize_sums(const double* __restri
     if ((int)threadIdx.x < kcount) out[threadIdx.x] = sums[threadIdx.x];
 }
 
-// Full weighting of one fine value set around fine node (2I, 2J).
-template <typename Tf>
-__device__ __forceinline__ cplx<Tf> fw_resid(const Geom& G, const Tf* __restrict__ n2, const cplx<Tf>* __restrict__ g,
-                                             const cplx<Tf>* __restrict__ u, int I, int J) {
-    const int fi = 2 * I, fj = 2 * J;
-    cplx<Tf> c = resid_at(G, n2, g, u, fi, fj);
-    cplx<Tf> ud = resid_at(G, n2, g, u, fi - 1, fj) + resid_at(G, n2, g, u, fi + 1, fj) +
-                  resid_at(G, n2, g, u, fi, fj - 1) + resid_at(G, n2, g, u, fi, fj + 1);
-    cplx<Tf> dg = resid_at(G, n2, g, u, fi - 1, fj - 1) + resid_at(G, n2, g, u, fi - 1, fj + 1) +
-                  resid_at(G, n2, g, u, fi + 1, fj - 1) + resid_at(G, n2, g, u, fi + 1, fj + 1);
-    return Tf(1.0 / 16.0) * ((Tf(4) * c + Tf(2) * ud) + dg);
+// ------------------------------------------------------------------ residual + full weighting
+// A block owns a coarse tile of RCX x RCY nodes: it evaluates the fine residual once
+// on the (2 RCX + 1) x (2 RCY + 1) fine nodes around it into LDS, then applies the
+// 9-point full weighting from LDS (each fine residual is computed about once
+// instead of 2.25 times).  Coarse tiles are assigned XCD-aware as in tile_origin.
+constexpr int RCX = 32, RCY = 16;
+
+__host__ __device__ inline int rr_blocks(int n) {
+    const int nc = n / 2;
+    return ((nc + RCX - 1) / RCX) * ((nc + RCY - 1) / RCY);
 }
 
-// rc = R (g - A u) on the coarse grid of size G.n/2 (u == nullptr: u = 0).
+template <typename Tf, typename Tc, typename Res>
+__device__ __forceinline__ void restrict_tile(int n, const Res& res, cplx<Tc>* __restrict__ rc) {
+    constexpr int FW = 2 * RCX + 1, FH = 2 * RCY + 1;
+    __shared__ cplx<Tf> r[FH * FW];
+    const int nc = n / 2;
+    const int ntx = (nc + RCX - 1) / RCX;
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int I0 = (b / ntx) * RCY, J0 = (b % ntx) * RCX;
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;
+    for (int q = threadIdx.x; q < FH * FW; q += BLOCK) {
+        const int ri = q / FW, rj = q - ri * FW;
+        const int fi = fi0 + ri, fj = fj0 + rj;
+        cplx<Tf> v{};
+        if (fi >= 1 && fj >= 1 && fi < n && fj < n) v = res(fi, fj);
+        r[q] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < RCX * RCY; q += BLOCK) {
+        const int ci = q / RCX, cj = q - ci * RCX;
+        const int I = I0 + ci, J = J0 + cj;
+        if (I >= nc || J >= nc) continue;
+        cplx<Tf> v{};
+        if (I > 0 && J > 0) {
+            const int l = (2 * ci + 1) * FW + 2 * cj + 1;
+            const cplx<Tf> c = r[l];
+            const cplx<Tf> ud = ((r[l - FW] + r[l + FW]) + r[l - 1]) + r[l + 1];
+            const cplx<Tf> dg = ((r[l - FW - 1] + r[l - FW + 1]) + r[l + FW - 1]) + r[l + FW + 1];
+            v = Tf(1.0 / 16.0) * ((Tf(4) * c + Tf(2) * ud) + dg);
+        }
+        rc[(size_t)I * nc + J] = ccast<Tc>(v);
+    }
+}
+
+template <typename Tf>
+struct HelmRes {
+    Geom G;
+    const Tf* n2;
+    const cplx<Tf>* g;
+    const cplx<Tf>* u;
+    __device__ cplx<Tf> operator()(int i, int j) const { return resid_at(G, n2, g, u, i, j); }
+};
+
+// rc = R (g - A u) on the coarse grid of size G.n/2 (u == nullptr: u = 0); rr_blocks(G.n) blocks.
 template <typename Tf, typename Tc>
 __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Geom G, const Tf* __restrict__ n2,
                                                           const cplx<Tf>* __restrict__ g,
                                                           const cplx<Tf>* __restrict__ u, cplx<Tc>* __restrict__ rc) {
-    const int nc = G.n / 2;
-    int J, I0;
-    tile_origin(nc, J, I0);
-    if (J >= nc) return;
-    for (int r = 0; r < RPT; ++r) {
-        const int I = I0 + r;
-        if (I >= nc) break;
-        cplx<Tf> v{};
-        if (I > 0 && J > 0) v = fw_resid(G, n2, g, u, I, J);
-        rc[(size_t)I * nc + J] = ccast<Tc>(v);
-    }
+    restrict_tile<Tf, Tc>(G.n, HelmRes<Tf>{G, n2, g, u}, rc);
 }
 
 // u += P ec (bilinear interpolation, P = 4 R^T); ec has nc = n/2 nodes per side.
