@@ -397,8 +397,6 @@ struct Engine {
         AdrLevel& A = c->al[2];
         LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st, W.G, (const T*)W.n2,
                            (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
-        // the re-modulation stays a separate streaming pass: folded into the last
-        // smoother's combine kernel (adr_vcycle(2, true)) it ran slower on gfx950
         adr_vcycle(2);
         LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))), dim3(BLOCK), st, N(2), (const C*)A.x,
                            (const T*)c->theta2, (C*)W.u);
@@ -425,12 +423,13 @@ struct Engine {
         return true;
     }
 
-    // One ADR V-cycle from x = 0 on levels l..LA.  top: the caller is the ADR step on
-    // level 2 and accepts the re-modulated update of u folded into the last smoother
-    // (returns whether that happened; otherwise the result is in A.x).
-    bool adr_vcycle(int l, bool top = false) {
+    // One ADR V-cycle from x = 0 on levels l..LA (result in A.x).
+    void adr_vcycle(int l) {
         AdrLevel& A = c->al[l];
-        if (l == c->LA) return gmres(l, c->d.gmres_coarse_m, true, top);
+        if (l == c->LA) {
+            gmres(l, c->d.gmres_coarse_m, true);
+            return;
+        }
         gmres(l, c->d.gmres_m, true);
         LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.n)), dim3(BLOCK), st, A.A,
                            (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
@@ -438,7 +437,7 @@ struct Engine {
         adr_vcycle(l + 1);
         LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), st, A.n,
                            (const C*)c->al[l + 1].x, (C*)A.x);
-        return gmres(l, c->d.gmres_m, false, top);
+        gmres(l, c->d.gmres_m, false);
     }
 
     template <int NV>
@@ -474,10 +473,9 @@ struct Engine {
         LAUNCH(c, (m + 1 + (x0_zero ? 0 : 1)) * sizeof(C) * double(n), (k_krylov_combine<T, NV>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, V,
                            (const KrylovScal*)A.K, (const C*)(x0_zero ? nullptr : A.x), (C*)A.x);
     }
-    // s-step GMRES(MM) on ADR level l.  mod: the result is not stored but added,
-    // re-modulated, to the level-2 iterate (the end of an ADR step).
+    // s-step GMRES(MM) on ADR level l.
     template <int MM>
-    void gmres_sstep(int l, bool x0_zero, bool mod = false) {
+    void gmres_sstep(int l, bool x0_zero) {
         AdrLevel& A = c->al[l];
         const int nb = tiles_of(A.n);
         const int nbr = c->tn.sstep_blocks[l] > 0 ? std::min(c->tn.sstep_blocks[l], red_blocks(A.n)) : red_blocks(A.n);
@@ -495,52 +493,36 @@ struct Engine {
         double* gsum = A.K->R;  // device scratch inside the Krylov state
         LAUNCH(c, 8.0 * NG * nbr, k_sstep_reduce, dim3(NG), dim3(BLOCK), st, (const double*)c->partials, nbr, gsum);
         const double tolb = 1e-12;
-        const T* th = (const T*)c->theta2;
-        C* u2 = (C*)c->wl[2].u;
         if (x0_zero) {
-            if (mod)
-                LAUNCH(c, (4 * sizeof(C) + 3 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false, true>), dim3(nb),
-                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                       (const C*)nullptr, (const double*)gsum, tolb, A.K, (C*)nullptr, th, u2);
-            else
-                LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false, false>), dim3(nb),
-                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                       (const C*)nullptr, (const double*)gsum, tolb, A.K, (C*)A.x, th, (C*)nullptr);
+            LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false>), dim3(nb),
+                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)nullptr, (const double*)gsum, tolb, A.K, (C*)A.x);
         } else {
-            if (mod) {
-                LAUNCH(c, (5 * sizeof(C) + 3 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true, true>), dim3(nb),
-                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                       (const C*)A.x, (const double*)gsum, tolb, A.K, (C*)nullptr, th, u2);
-            } else {
-                LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true, false>), dim3(nb),
-                       tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                       (const C*)A.x, (const double*)gsum, tolb, A.K, (C*)A.xalt, th, (C*)nullptr);
-                std::swap(A.x, A.xalt);
-            }
+            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true>), dim3(nb),
+                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)A.x, (const double*)gsum, tolb, A.K, (C*)A.xalt);
+            std::swap(A.x, A.xalt);
         }
     }
 
-    // GMRES(m) smoother on ADR level l (x = A.x, b = A.b).  mod: for the last smoother
-    // of an ADR step on level 2, fold the re-modulated update of u into the kernel when
-    // the s-step form runs; returns whether it did.
-    bool gmres(int l, int m, bool x0_zero, bool mod = false) {
+    // GMRES(m) smoother on ADR level l (x = A.x, b = A.b).
+    void gmres(int l, int m, bool x0_zero) {
         // one workgroup on the coarsest level, s-step form on the larger ones
-        if (l == c->LA && gmres_block(l, m, x0_zero)) return false;
+        if (l == c->LA && gmres_block(l, m, x0_zero)) return;
         if (m <= 4 && !c->d.gmres_arnoldi) {
             switch (m) {
-                case 1: gmres_sstep<1>(l, x0_zero, mod); break;
-                case 2: gmres_sstep<2>(l, x0_zero, mod); break;
-                case 3: gmres_sstep<3>(l, x0_zero, mod); break;
-                default: gmres_sstep<4>(l, x0_zero, mod); break;
+                case 1: gmres_sstep<1>(l, x0_zero); break;
+                case 2: gmres_sstep<2>(l, x0_zero); break;
+                case 3: gmres_sstep<3>(l, x0_zero); break;
+                default: gmres_sstep<4>(l, x0_zero); break;
             }
-            return mod;
+            return;
         }
         switch (nv_bucket(m)) {
             case 4: gmres_nv<4>(l, m, x0_zero); break;
             case 12: gmres_nv<12>(l, m, x0_zero); break;
             default: gmres_nv<MAXM>(l, m, x0_zero); break;
         }
-        return false;
     }
 };
 

@@ -24,7 +24,6 @@ struct SStep {
     static constexpr int PW = TX + 2 * HMAX;
     static constexpr int PH = TY + 2 * HMAX;
     static constexpr int PN = PW * PH;
-    static constexpr int NB = (M >= 2 ? M : 2);  // LDS buffers
     static constexpr int NG = (M + 1) * (M + 1);  // doubles of the Gram (diag real + upper complex)
 };
 
@@ -112,16 +111,33 @@ __device__ __forceinline__ void sstep_load(const AdrGeom& A, const T* __restrict
     __syncthreads();
 }
 
+// Interior points of a tile per thread, and the interior values of a buffer copied
+// to registers (point q = tid + e * BLOCK of the tile).
+constexpr int IPT = TX * TY / BLOCK;
+
+template <typename T, int PW, int HMAX>
+__device__ __forceinline__ void sstep_keep(const cplx<T>* __restrict__ buf, cplx<T> (&k)[IPT], int tid) {
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const int q = tid + e * BLOCK;
+        const int ri = q / TX, rj = q - ri * TX;
+        k[e] = buf[(HMAX + ri) * PW + HMAX + rj];
+    }
+}
+
 // Pass 1: K_0..K_M on the tile and the Gram matrix; per-block sums to partials[blk * NG].
 // Layout of the NG doubles: G(i,i) real for i = 0..M, then G(i,j), i < j, as (re, im).
+// Two LDS buffers alternate between the stages; the interior values of every K_j
+// are kept in registers as soon as the stage has produced them.
 template <typename T, int M, bool X0>
 __global__ __launch_bounds__(BLOCK) void k_sstep_gram(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                       const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
                                                       const cplx<T>* __restrict__ x0, double* __restrict__ partials) {
     using S = SStep<M, X0>;
-    __shared__ cplx<T> buf[S::NB][S::PN];
+    __shared__ cplx<T> bufA[S::PN], bufB[S::PN];
     __shared__ double red[4 * S::NG];
     __shared__ double sums[S::NG];
+    // FP64 products: the unscaled powers M^j K_0 span many decades (|M| ~ 8/h^2)
     double acc[S::NG];
 #pragma unroll
     for (int q = 0; q < S::NG; ++q) acc[q] = 0.0;
@@ -129,36 +145,46 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_gram(AdrGeom A, const T* __rest
     int t0, t1;
     tile_chunk(A.n, t0, t1);
     for (int t = t0; t < t1; ++t) {
-    int j0, i0;
-    sstep_tile(A.n, t, j0, i0);
-    __syncthreads();
-    // K_0 lives in buf[0]; K_j in buf[j] (j < M); x0 staging uses buf[1] before K_1 is formed
-    sstep_load<T, M, X0>(A, px, py, c0, b, x0, buf[1], buf[0], M, i0, j0);
-    for (int j = 1; j < M; ++j) sstep_stage<T, M, X0>(A, px, py, c0, buf[j - 1], buf[j], M - j, i0, j0);
-    for (int q = tid; q < TX * TY; q += BLOCK) {
-        const int ri = q / TX, rj = q - ri * TX;
-        const int gi = i0 + ri, gj = j0 + rj;
-        if (gi < 1 || gj < 1 || gi >= A.n || gj >= A.n) continue;
-        const int li = S::HMAX + ri, lj = S::HMAX + rj;
-        const size_t p = (size_t)gi * A.n + gj;
-        cplx<T> k[M + 1];
+        int j0, i0;
+        sstep_tile(A.n, t, j0, i0);
+        __syncthreads();
+        // x0 staging in bufB, K_0 in bufA, then K_j alternating
+        sstep_load<T, M, X0>(A, px, py, c0, b, x0, bufB, bufA, M, i0, j0);
+        cplx<T> k[M + 1][IPT];
+        sstep_keep<T, S::PW, S::HMAX>(bufA, k[0], tid);
+        cplx<T>* src = bufA;
+        cplx<T>* dst = bufB;
 #pragma unroll
-        for (int j = 0; j < M; ++j) k[j] = buf[j][li * S::PW + lj];
-        k[M] = applyM_lds<T, S::PW>(A, buf[M - 1], li, lj, px[p], py[p], c0[p]);
-        int o = M + 1;
+        for (int j = 1; j < M; ++j) {
+            sstep_stage<T, M, X0>(A, px, py, c0, src, dst, M - j, i0, j0);
+            sstep_keep<T, S::PW, S::HMAX>(dst, k[j], tid);
+            cplx<T>* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
 #pragma unroll
-        for (int i = 0; i <= M; ++i) {
-            const double ar = double(k[i].re), ai = double(k[i].im);
-            acc[i] += ar * ar + ai * ai;
+        for (int e = 0; e < IPT; ++e) {
+            const int q = tid + e * BLOCK;
+            const int ri = q / TX, rj = q - ri * TX;
+            const int gi = i0 + ri, gj = j0 + rj;
+            if (gi < 1 || gj < 1 || gi >= A.n || gj >= A.n) continue;
+            const int li = S::HMAX + ri, lj = S::HMAX + rj;
+            const size_t p = (size_t)gi * A.n + gj;
+            k[M][e] = applyM_lds<T, S::PW>(A, src, li, lj, px[p], py[p], c0[p]);
+            int o = M + 1;
 #pragma unroll
-            for (int j = i + 1; j <= M; ++j) {
-                const double br = double(k[j].re), bi = double(k[j].im);
-                acc[o] += ar * br + ai * bi;
-                acc[o + 1] += ar * bi - ai * br;
-                o += 2;
+            for (int i = 0; i <= M; ++i) {
+                const double ar = double(k[i][e].re), ai = double(k[i][e].im);
+                acc[i] += ar * ar + ai * ai;
+#pragma unroll
+                for (int jv = i + 1; jv <= M; ++jv) {
+                    const double br = double(k[jv][e].re), bi = double(k[jv][e].im);
+                    acc[o] += ar * br + ai * bi;
+                    acc[o + 1] += ar * bi - ai * br;
+                    o += 2;
+                }
             }
         }
-    }
     }
     block_sum<S::NG, 4>(acc, S::NG, red, sums);
     store_partials(sums, S::NG, partials);
@@ -281,17 +307,15 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_reduce(const double* __restrict
 
 // Pass 2: x_out = x0 + sum_{j=1..cols} c_j K_{j-1} on the tile interior, with the
 // coefficients solved per block from the Gram sums gsum (thread 0, overlapped with
-// the other threads' tile loads); block 0 also records them in K.  MOD: instead of
-// writing x_out, adds x_out e^{i theta} to u (the re-modulation of the ADR step).
-template <typename T, int M, bool X0, bool MOD = false>
+// the other threads' tile loads); block 0 also records them in K.
+template <typename T, int M, bool X0>
 __global__ __launch_bounds__(BLOCK) void k_sstep_combine(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                          const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
                                                          const cplx<T>* __restrict__ x0,
                                                          const double* __restrict__ gsum, double breakdown_tol,
-                                                         KrylovScal* K, cplx<T>* __restrict__ xout,
-                                                         const T* __restrict__ theta, cplx<T>* __restrict__ u) {
+                                                         KrylovScal* K, cplx<T>* __restrict__ xout) {
     using S = SStep<M, X0>;
-    __shared__ cplx<T> buf[S::NB][S::PN];
+    __shared__ cplx<T> bufA[S::PN], bufB[S::PN];
     __shared__ cplx<T> cs[M];
     int j0, i0;
     {
@@ -319,30 +343,36 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine(AdrGeom A, const T* __r
         }
     }
     // K_0 needs halo M-1 here (the loads end with a barrier, which also publishes cs)
-    sstep_load<T, M, X0>(A, px, py, c0, b, x0, buf[1], buf[0], M - 1, i0, j0);
-    for (int j = 1; j < M; ++j) sstep_stage<T, M, X0>(A, px, py, c0, buf[j - 1], buf[j], M - 1 - j, i0, j0);
+    sstep_load<T, M, X0>(A, px, py, c0, b, x0, bufB, bufA, M - 1, i0, j0);
+    cplx<T> k[M][IPT];
+    sstep_keep<T, S::PW, S::HMAX>(bufA, k[0], tid);
+    cplx<T>* src = bufA;
+    cplx<T>* dst = bufB;
+#pragma unroll
+    for (int j = 1; j < M; ++j) {
+        sstep_stage<T, M, X0>(A, px, py, c0, src, dst, M - 1 - j, i0, j0);
+        sstep_keep<T, S::PW, S::HMAX>(dst, k[j], tid);
+        cplx<T>* tmp = src;
+        src = dst;
+        dst = tmp;
+    }
     cplx<T> c[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) c[j] = cs[j];
-    for (int q = tid; q < TX * TY; q += BLOCK) {
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const int q = tid + e * BLOCK;
         const int ri = q / TX, rj = q - ri * TX;
         const int gi = i0 + ri, gj = j0 + rj;
         if (gi >= A.n || gj >= A.n) continue;
         const size_t p = (size_t)gi * A.n + gj;
         cplx<T> v{};
         if (gi >= 1 && gj >= 1) {
-            const int li = S::HMAX + ri, lj = S::HMAX + rj;
             v = X0 ? x0[p] : cplx<T>{};
 #pragma unroll
-            for (int j = 0; j < M; ++j) v = v + c[j] * buf[j][li * S::PW + lj];
+            for (int j = 0; j < M; ++j) v = v + c[j] * k[j][e];
         }
-        if (MOD) {
-            T sn, cn;
-            sincos_t(theta[p], &sn, &cn);
-            u[p] = u[p] + v * mk<T>(cn, sn);
-        } else {
-            xout[p] = v;
-        }
+        xout[p] = v;
     }
 }
 
