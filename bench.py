@@ -96,6 +96,25 @@ def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):
                     "re-recording of the tape"}
 
 
+def copy_probe(reps: int = 5):
+    """A plain device copy of 4096^2 complex64 values (128 MiB read + 128 MiB written per
+    dispatch), the known-size reference for the FETCH_SIZE / WRITE_SIZE counters."""
+    import numpy as np
+    import torch
+
+    from paper_2404_02493_amd import Helmholtz
+
+    n = 4096
+    H = Helmholtz(np.ones((n, n)), 100.0, levels=3, precision="c64", adr_steps=0)
+    x = torch.ones((n, n), dtype=torch.complex64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        H.debug_op(12, 1, x, None, y)
+    torch.cuda.synchronize()
+    log(f"copy probe: {reps} dispatches of {n * n * 8 / 2**20:.0f} MiB read + written")
+    H.close()
+
+
 def bench_batch(args):
     """Mixed batch: 64 problems with n drawn from {256, 512, 1024}, k = 0.625 n, own random
     medium, 1-4 sources with a multi-source fast-marching phase; every problem solved to
@@ -164,6 +183,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain copy kernel of known size (reference for memory counters)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2404_02493_amd", "tuning.json"),
                     help="JSON cache of measured launch shapes ('none' = built-in defaults)")
     args = ap.parse_args()
@@ -174,6 +195,9 @@ def main():
 
     if args.workload == "batch64":
         bench_batch(args)
+        return
+    if args.copy_probe:
+        copy_probe()
         return
 
     import numpy as np

@@ -210,6 +210,8 @@ helm_status helm_get_tuning(helm_ctx ctx, char* json, int64_t cap);
  *   9  out = ADR step(u=in, g=in2) (level 2)
  *  10  out = wave-ADR cycle on level l from (u=in, g=in2)
  *  11  out = R(in2 - A_l in)     (fused residual + restriction)
+ *  12  out = in                  (plain copy of a level array: a probe of known
+ *                                 size for hardware memory counters)
  * Arrays are device memory in cycle_prec (level L arrays are complex128). */
 helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* in, const void* in2,
                           void* out, void* stream);

@@ -1413,6 +1413,18 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                     else if (ctx->wl[level + 1].f64) E.template resid_restrict<T, double>(level, in2, in, out);
                     else E.template resid_restrict<T, T>(level, in2, in, out);
                     break;
+                case 12: {
+                    // plain copy of one level's complex array (a known-size probe for
+                    // hardware memory counters)
+                    const size_t Nl = (size_t)W.n * W.n;
+                    if (W.f64)
+                        LAUNCH(ctx, 32.0 * Nl, (k_copy<double>), dim3(flat_blocks(Nl, 8192)), dim3(BLOCK), st, Nl,
+                               (const c128*)in, (c128*)out);
+                    else
+                        LAUNCH(ctx, 2.0 * sizeof(cplx<T>) * Nl, (k_copy<T>), dim3(flat_blocks(Nl, 8192)), dim3(BLOCK),
+                               st, Nl, (const cplx<T>*)in, (cplx<T>*)out);
+                    break;
+                }
                 default:
                     throw Error(HELM_EINVAL, "unknown debug op");
             }

@@ -316,6 +316,8 @@ __device__ __forceinline__ void ws_store(const T (&acc)[2 * NPW], int jj, double
 }
 
 // w = A (s z) on the fine grid and partial conj(V_i) w, i <= jj (finalize with FIN_MV).
+// Wave e of the block evaluates the stencil for slice e of the step (E slices of 64
+// elements, E = 4 waves for complex64) and shares it through LDS, so z is read once.
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm_ws(Geom G, const T* __restrict__ n2,
                                                            const cplx<T>* __restrict__ z, int use_scale, VecSet<T> V,
@@ -324,6 +326,7 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm_ws(Geom G, const T* __re
     constexpr int NPW = (NV + WS_WAVES - 1) / WS_WAVES;
     constexpr int E = WsShape<T>::E;
     __shared__ double sums[2 * NV + 2];
+    __shared__ cplx<T> xs[E][64];
     if (K->done) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const T sj = use_scale ? T(K->scale[jj]) : T(1);
@@ -334,17 +337,21 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm_ws(Geom G, const T* __re
     size_t b0, b1;
     ws_range<T>(N, b0, b1);
     for (size_t base = b0; base < b1; base += WsShape<T>::STEP) {
-        cplx<T> x[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
+        // stencil slices: wave w computes slices w, w + 4, ... (E <= 4: one or none)
+        for (int e = wave; e < E; e += WS_WAVES) {
             const size_t p = base + (size_t)e * 64 + lane;
-            x[e] = cplx<T>{};
+            cplx<T> v{};
             if (p < b1) {
                 const int i = (int)(p / G.n), j = (int)(p % G.n);
-                if (i > 0 && j > 0) x[e] = sj * applyA_at(G, n2, z, i, j, false);
-                if (wave == 0) w[p] = x[e];
+                if (i > 0 && j > 0) v = sj * applyA_at(G, n2, z, i, j, false);
+                w[p] = v;
             }
+            xs[e][lane] = v;
         }
+        __syncthreads();
+        cplx<T> x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = xs[e][lane];
 #pragma unroll
         for (int k = 0; k < NPW; ++k) {
             const int iv = wave + WS_WAVES * k;
@@ -360,6 +367,7 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_helm_ws(Geom G, const T* __re
                 }
             }
         }
+        __syncthreads();
     }
     ws_store<T, NPW>(acc, jj, sums, partials);
 }

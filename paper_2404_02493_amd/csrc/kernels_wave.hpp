@@ -337,6 +337,11 @@ __global__ __launch_bounds__(BLOCK) void k_add_cast(size_t N, const cplx<Ti>* __
 }
 
 template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_copy(size_t N, const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y) {
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) y[p] = x[p];
+}
+
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_zero(size_t N, cplx<T>* __restrict__ y) {
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) y[p] = cplx<T>{};
 }
