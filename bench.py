@@ -283,8 +283,12 @@ def main():
         tot_bytes = sum(k["bytes"] for k in ks)
         top = ks[0]
         achieved = top["bytes"] / (top["ms"] * 1e-3) / 1e9
+        from paper_2404_02493_amd.traffic import load as load_traffic
+
+        traffic = load_traffic(os.path.join(ROOT, "profiles", "traffic_sstep_gram_x0_level2_layered4096.json"),
+                               top["name"])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": top["name"], "launches": top["launches"],
                     "avg_launch_us": round(1e3 * top["ms"] / top["launches"], 2),
                     "bytes_per_launch": top["bytes"] / top["launches"]}

@@ -99,6 +99,8 @@ struct helm_ctx_s {
     void* cyc_g = nullptr;   // cycle-precision staging (mode 0 with complex64 cycles)
     void* cyc_u = nullptr;
     void* rbuf = nullptr;    // FP64 residual (mode 1)
+    double* hcol = nullptr;  // pinned host copies of the outer Hessenberg columns
+    hipEvent_t col_ev[helm::MAXM] = {};
     void* dbuf = nullptr;    // inner correction (mode 1)
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
     // launch shapes chosen by the autotuner (0 = built-in default)
@@ -582,9 +584,14 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     scale[0] = 1.0 / beta;
     int used = 0;
     double est = beta / gnorm;
-    std::vector<double> col(2 * (MAXM + 1));
-    for (int j = 0; j < m && used < maxit_left; ++j) {
-        prec(j, scale[j]);  // Z[j] = preconditioned V[j] (scaled by scale[j] if !z_scaled)
+    // Iteration j + 1 is queued before the host reads the Hessenberg column of
+    // iteration j, so the device never waits for the host's Givens update.  When the
+    // host stops at column j, the queued iteration only touches state that the next
+    // restart rewrites (its kernels exit early once the device marks a breakdown).
+    const int jmax = std::min(m, maxit_left);
+    const size_t cstride = 2 * (MAXM + 1);
+    auto enqueue = [&](int j) {
+        prec(j, K->scale + j);  // Z[j] = preconditioned V[j] (scaled by scale[j] if !z_scaled)
         LAUNCH(c, ((j + 3) * sizeof(Cp) + sizeof(P)) * double(N), (k_arnoldi_helm_ws<P, MAXM>), dim3(nbf),
                dim3(BLOCK), st, G, (const P*)n2_fine, (const Cp*)Z[j], z_scaled ? 0 : 1, Vs, j, (Cp*)V[j + 1],
                (const KrylovScal*)K, c->partials);
@@ -595,9 +602,15 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
         LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass2<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,
                (Cp*)V[j + 1], (const KrylovScal*)K, c->partials);
         krylov_fin<MAXM>(c, st, nbf, FIN_ORTH2, j, m, K, 0.0);
-        HIPCHK(hipMemcpyAsync(col.data(), K->H + 2 * (j * (MAXM + 1)), sizeof(double) * 2 * (j + 2),
+        HIPCHK(hipMemcpyAsync(c->hcol + j * cstride, K->H + 2 * (j * (MAXM + 1)), sizeof(double) * 2 * (j + 2),
                               hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipEventRecord(c->col_ev[j], st));
+    };
+    if (jmax > 0) enqueue(0);
+    for (int j = 0; j < jmax; ++j) {
+        if (j + 1 < jmax) enqueue(j + 1);
+        HIPCHK(hipEventSynchronize(c->col_ev[j]));
+        const double* col = c->hcol + j * cstride;
         for (int i = 0; i <= j + 1; ++i) H[i][j] = cd(col[2 * i], col[2 * i + 1]);
         const double hn = col[2 * (j + 1)];
         for (int i = 0; i < j; ++i) {
@@ -903,6 +916,10 @@ static void cycle_any(helm_ctx c, const void* g, const void* u_in, void* u_out, 
 static void ensure_solver_ws(helm_ctx c, int mode) {
     const size_t NF = (size_t)c->d.n * c->d.n;
     const int m = c->d.restart;
+    if (!c->hcol) {
+        HIPCHK(hipHostMalloc((void**)&c->hcol, sizeof(double) * MAXM * 2 * (MAXM + 1), hipHostMallocDefault));
+        for (int i = 0; i < MAXM; ++i) HIPCHK(hipEventCreateWithFlags(&c->col_ev[i], hipEventDisableTiming));
+    }
     if (mode == 0 && !c->fZ[0]) {
         for (int i = 1; i <= m; ++i) c->fV[i] = dalloc(c, NF * sizeof(c128));
         for (int i = 0; i < m; ++i) c->fZ[i] = dalloc(c, NF * sizeof(c128));
@@ -941,10 +958,10 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
         while (!converged && its < maxit) {
             double est = 0;
             bool bd = false;
-            auto prec = [&](int j, double s) {
+            auto prec = [&](int j, const double* ds) {
                 if (c->f32) {
-                    LAUNCH(c, 24.0 * double(NF), (k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
-                                       (const c128*)c->fV[j], (c64*)c->cyc_g, s);
+                    LAUNCH(c, 24.0 * double(NF), (k_cast_scale_dev<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK),
+                           st, NF, (const c128*)c->fV[j], (c64*)c->cyc_g, ds);
                     cycle_any(c, c->cyc_g, nullptr, c->cyc_u, st);
                     LAUNCH(c, 24.0 * double(NF), (k_cast_scale<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
                                        (const c64*)c->cyc_u, (c128*)c->fZ[j], 1.0);
@@ -973,7 +990,7 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
             LAUNCH(c, 24.0 * double(NF), (k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
                                (const c128*)c->fV[0], (c64*)c->iV[0], 1.0 / rn);
             LAUNCH(c, 8.0 * double(NF), (k_zero<float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF, (c64*)c->dbuf);
-            auto prec = [&](int j, double s) { cycle_any(c, c->iV[j], nullptr, c->iZ[j], st); (void)s; };
+            auto prec = [&](int j, const double*) { cycle_any(c, c->iV[j], nullptr, c->iZ[j], st); };
             double est = 0;
             bool bd = false;
             const double target = std::max(eta, 0.5 * tol * gn / rn);
@@ -1499,6 +1516,9 @@ helm_status helm_destroy(helm_ctx ctx) {
     ctx->adj = nullptr;
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->col_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->hcol) (void)hipHostFree(ctx->hcol);
     ctx->prof.pool.clear();
     for (void* p : ctx->allocs) (void)hipFree(p);
     ctx->allocs.clear();

@@ -325,6 +325,17 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scale(size_t N, const cplx<Ti>* 
     }
 }
 
+// y = (*s) cast(x) with the scale read from device memory
+template <typename To, typename Ti>
+__global__ __launch_bounds__(BLOCK) void k_cast_scale_dev(size_t N, const cplx<Ti>* __restrict__ x,
+                                                          cplx<To>* __restrict__ y, const double* __restrict__ s) {
+    const double sc = *s;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        cplx<Ti> v = x[p];
+        y[p] = mk<To>(To(sc * double(v.re)), To(sc * double(v.im)));
+    }
+}
+
 // y += s * cast(x)
 template <typename To, typename Ti>
 __global__ __launch_bounds__(BLOCK) void k_add_cast(size_t N, const cplx<Ti>* __restrict__ x, cplx<To>* __restrict__ y,
