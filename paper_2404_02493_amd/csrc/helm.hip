@@ -299,19 +299,21 @@ struct Engine {
         LAUNCH(c, (3 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start<P>), dim3(tiles_of(G.n)), tile_block(), st, G, (const P*)W.n2,
                            (const cplx<P>*)t0, (cplx<P>*)W.r, (cplx<P>*)W.d, P(1.0 / theta));
         double rho = dc / theta;
+        void* dcur = W.d;  // d alternates between W.d and W.t
+        void* dnext = W.t;
         for (int step = 1; step <= m; ++step) {
             if (step < m) {
-                applyA<P>(G, W.n2, W.d, W.t, 0);
                 const double den = 2.0 * theta - dc * rho;
                 const double rho_new = dc / den;
                 const double c1 = rho_new * rho, c2 = 2.0 / den;
-                LAUNCH(c, (7 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_step<P>), dim3(tiles_of(G.n)), tile_block(), st, G,
-                                   (const P*)W.n2, (const cplx<P>*)W.t, (cplx<P>*)W.r, (cplx<P>*)W.d,
-                                   (cplx<P>*)u, P(c1), P(c2));
+                LAUNCH(c, (7 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_fused<P>), dim3(tiles_of(G.n)),
+                       tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)dcur, (cplx<P>*)dnext, (cplx<P>*)W.r,
+                       (cplx<P>*)u, P(c1), P(c2));
+                std::swap(dcur, dnext);
                 rho = rho_new;
             } else {
                 LAUNCH(c, 3 * sizeof(cplx<P>) * double(n), (k_axpy<P>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, P(1),
-                                   (const cplx<P>*)W.d, (cplx<P>*)u);
+                                   (const cplx<P>*)dcur, (cplx<P>*)u);
             }
         }
     }

@@ -289,24 +289,46 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start(Geom G, const T* __restric
     }
 }
 
-// Chebyshev step: u += d; r -= A^* t; d = c1 d + c2 r    (t = A d)
+// Fused Chebyshev step on a 64 x 16 tile: t = A d_in on the tile and a halo of one
+// (in LDS), then at the tile's nodes  u += d_in;  r -= A^* t;  d_out = c1 d_in + c2 r.
+// d_in and d_out are different arrays (neighbouring tiles still read d_in).
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_cheb_step(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ t,
-                                                     cplx<T>* __restrict__ r, cplx<T>* __restrict__ d,
-                                                     cplx<T>* __restrict__ u, T c1, T c2) {
+__global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restrict__ n2,
+                                                      const cplx<T>* __restrict__ d_in, cplx<T>* __restrict__ d_out,
+                                                      cplx<T>* __restrict__ r, cplx<T>* __restrict__ u, T c1, T c2) {
+    constexpr int HW = TX + 2, HH = TY + 2;
+    __shared__ cplx<T> ts[HH * HW];
     int j, i0;
     tile_origin(G.n, j, i0);
+    const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
+    const int tid = threadIdx.x + threadIdx.y * TX;
+    for (int q = tid; q < HH * HW; q += BLOCK) {
+        const int ri = q / HW, rj = q - ri * HW;
+        const int gi = it - 1 + ri, gj = jt - 1 + rj;
+        cplx<T> v{};
+        if (gi >= 1 && gj >= 1 && gi < G.n && gj < G.n) v = applyA_at(G, n2, d_in, gi, gj, false);
+        ts[q] = v;
+    }
+    __syncthreads();
     if (j >= G.n) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
         if (i >= G.n) break;
-        if (i == 0 || j == 0) continue;
         const size_t p = (size_t)i * G.n + j;
-        cplx<T> dv = d[p];
+        if (i == 0 || j == 0) {  // keep the ring of the alternate d buffer zero
+            d_out[p] = cplx<T>{};
+            continue;
+        }
+        const int l = (i - it + 1) * HW + (j - jt + 1);
+        cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
+        kap.im = -kap.im;
+        const cplx<T> tc = ts[l];
+        const cplx<T> aht = T(G.inv_h2) * (T(4) * tc - (((ts[l - HW] + ts[l + HW]) + ts[l - 1]) + ts[l + 1])) - kap * tc;
+        const cplx<T> dv = d_in[p];
+        const cplx<T> rv = r[p] - aht;
         u[p] = u[p] + dv;
-        cplx<T> rv = r[p] - applyA_at(G, n2, t, i, j, true);
         r[p] = rv;
-        d[p] = c1 * dv + c2 * rv;
+        d_out[p] = c1 * dv + c2 * rv;
     }
 }
 
