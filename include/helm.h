@@ -81,6 +81,8 @@ typedef struct {
     int32_t adr_levels;       /* levels of the ADR V-cycle, from level 2 down (default 3; 0 = all, L - 1) */
     int32_t tail_n;           /* a coarsest ADR level with at most tail_n nodes per side (and at most
                                  4096 nodes) runs its GMRES in one workgroup (default 64; 0 = never) */
+    int32_t wave_tail_n;      /* the wave levels >= 3 with at most wave_tail_n nodes per side run in
+                                 one workgroup, all of them in a single launch (default 32; 0 = never) */
 } helm_desc;
 
 /* Defaults of every field for an n x n grid at frequency k:

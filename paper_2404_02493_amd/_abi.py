@@ -42,6 +42,7 @@ class HelmDesc(ctypes.Structure):
         ("use_graphs", ctypes.c_int32),
         ("adr_levels", ctypes.c_int32),
         ("tail_n", ctypes.c_int32),
+        ("wave_tail_n", ctypes.c_int32),
     ]
 
 

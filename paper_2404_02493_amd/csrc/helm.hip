@@ -20,6 +20,7 @@
 #include "../../include/helm.h"
 #include "kernels_tail.hpp"
 #include "kernels_adjoint.hpp"
+#include "kernels_wtail.hpp"
 
 namespace helm {
 
@@ -78,6 +79,7 @@ struct helm_ctx_s {
     helm_desc d{};
     int L = 0;
     int LA = 0;  // coarsest level of the ADR V-cycle
+    int LT = 0;  // first wave level run by the one-workgroup tail kernel (0 = none)
     bool f32 = false;  // cycle precision is complex64
     std::vector<void*> allocs;
     double* n2f = nullptr;  // fine n^2 (FP64)
@@ -351,10 +353,42 @@ struct Engine {
         chebyshev<double>(l, W.g, W.u, true, c->w[l - 1], c->d.cheb_coarse);
     }
 
+    // ---- levels LT..L in one workgroup (u_LT from g_LT, zero initial iterate)
+    void wave_tail(int l0) {
+        TailWaveArgs a{};
+        for (int l = l0; l <= c->L; ++l) {
+            WaveLevel& W = c->wl[l];
+            TailWaveLevel& t = a.lv[l];
+            t.G = W.G;
+            t.f64 = W.f64 ? 1 : 0;
+            t.n2 = W.n2;
+            t.g = W.g;
+            t.u = W.u;
+            t.r = W.r;
+            t.d = W.d;
+            t.t = W.t;
+            t.lam = W.lam;
+            t.alpha = c->w[l - 1];
+        }
+        a.l0 = l0;
+        a.L = c->L;
+        a.cheb_pre = c->d.cheb_pre;
+        a.cheb_post = c->d.cheb_post;
+        a.cheb_coarse = c->d.cheb_coarse;
+        a.level3_literal = c->d.level3_literal;
+        double bytes = 0.0;
+        for (int l = l0; l <= c->L; ++l) bytes += 8.0 * csize(c->wl[l].f64) * NN(c->wl[l].n);
+        LAUNCH(c, bytes, (k_wave_tail<T>), dim3(1), dim3(WT_THREADS), st, a);
+    }
+
     // ---- one cycle on level l >= 2 with zero initial iterate: u_l from g_l
     void cycle_coarse(int l) {
         WaveLevel& W = c->wl[l];
         const int L = c->L;
+        if (c->LT > 0 && l >= c->LT) {
+            wave_tail(l);
+            return;
+        }
         if (l == L) {
             coarsest(l);
             return;
@@ -698,6 +732,7 @@ static void validate(const helm_desc* d) {
     REQUIRE(d->gmres_arnoldi == 0 || d->gmres_arnoldi == 1, "gmres_arnoldi must be 0 or 1");
     REQUIRE(d->use_graphs == 0 || d->use_graphs == 1, "use_graphs must be 0 or 1");
     REQUIRE(d->tail_n >= 0, "tail_n must be >= 0");
+    REQUIRE(d->wave_tail_n >= 0, "wave_tail_n must be >= 0");
     REQUIRE(d->adr_levels >= 0, "adr_levels must be >= 0");
 }
 
@@ -781,6 +816,13 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
             c->allocs.pop_back();
         }
     }
+    // first level (>= 3) small enough for the one-workgroup tail of the wave cycle
+    c->LT = 0;
+    for (int l = 3; l <= L && l <= WT_MAXL; ++l)
+        if (c->wl[l].n <= d.wave_tail_n) {
+            c->LT = l;
+            break;
+        }
     // default weights
     c->w.assign(L, 0.0);
     {
@@ -1072,6 +1114,7 @@ void helm_desc_default(helm_desc* d, int32_t n, double k) {
     d->gmres_arnoldi = 0;
     d->use_graphs = 1;
     d->tail_n = 64;
+    d->wave_tail_n = 32;
     d->adr_levels = 3;
 }
 

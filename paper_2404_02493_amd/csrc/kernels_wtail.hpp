@@ -1,0 +1,173 @@
+// The small levels of the wave cycle in one workgroup.
+//
+// Below a few hundred nodes per side every operation of the cycle is a handful
+// of microseconds of work, so separate launches are dominated by their latency.
+// k_wave_tail runs the whole coarse part of Algorithm 1 from a given level down
+// (Chebyshev pre-smoothing, residual + full weighting, the coarser cycle,
+// bilinear prolongation, post-smoothing, and the coarsest level's Chebyshev
+// iteration) in one workgroup of 1024 threads, with the level arrays in global
+// memory and a workgroup barrier between dependent sweeps.  It computes the
+// same operations in the same precision as the per-level kernels.
+#pragma once
+
+#include "kernels_wave.hpp"
+
+namespace helm {
+
+constexpr int WT_THREADS = 1024;
+constexpr int WT_MAXL = 14;
+
+struct TailWaveLevel {
+    Geom G;
+    int f64;           // arrays of this level are complex128 / double
+    const void* n2;
+    void* g;
+    void* u;
+    void* r;
+    void* d;
+    void* t;
+    double lam;        // spectral bound of A^* A
+    double alpha;      // Chebyshev interval parameter
+};
+
+struct TailWaveArgs {
+    TailWaveLevel lv[WT_MAXL + 1];  // indexed by level
+    int l0;                         // first level handled here (>= 3)
+    int L;
+    int cheb_pre, cheb_post, cheb_coarse;
+    int level3_literal;
+};
+
+// r = A^* (g - A u) (u == nullptr: A^* g), d = r / theta; t holds g - A u.
+template <typename P>
+__device__ void wt_cheb(const TailWaveLevel& W, bool u_zero, int m) {
+    const Geom& G = W.G;
+    const int n = G.n;
+    const int N = n * n;
+    const P* n2 = (const P*)W.n2;
+    cplx<P>* g = (cplx<P>*)W.g;
+    cplx<P>* u = (cplx<P>*)W.u;
+    cplx<P>* r = (cplx<P>*)W.r;
+    cplx<P>* d = (cplx<P>*)W.d;
+    cplx<P>* t = (cplx<P>*)W.t;
+    const double lam = W.lam, a = lam / W.alpha;
+    const double theta = 0.5 * (lam + a), dc = 0.5 * (lam - a);
+    // t = g - A u (or g)
+    for (int p = threadIdx.x; p < N; p += WT_THREADS) {
+        const int i = p / n, j = p - i * n;
+        cplx<P> v{};
+        if (i > 0 && j > 0) v = resid_at(G, n2, g, u_zero ? (const cplx<P>*)nullptr : (const cplx<P>*)u, i, j);
+        t[p] = v;
+        if (u_zero) u[p] = cplx<P>{};
+    }
+    __syncthreads();
+    const P inv_theta = P(1.0 / theta);
+    for (int p = threadIdx.x; p < N; p += WT_THREADS) {
+        const int i = p / n, j = p - i * n;
+        cplx<P> v{};
+        if (i > 0 && j > 0) v = applyA_at(G, n2, t, i, j, true);
+        r[p] = v;
+        d[p] = inv_theta * v;
+    }
+    __syncthreads();
+    double rho = dc / theta;
+    for (int step = 1; step <= m; ++step) {
+        if (step < m) {
+            for (int p = threadIdx.x; p < N; p += WT_THREADS) {  // t = A d
+                const int i = p / n, j = p - i * n;
+                cplx<P> v{};
+                if (i > 0 && j > 0) v = applyA_at(G, n2, d, i, j, false);
+                t[p] = v;
+            }
+            __syncthreads();
+            const double den = 2.0 * theta - dc * rho;
+            const double rho_new = dc / den;
+            const P c1 = P(rho_new * rho), c2 = P(2.0 / den);
+            for (int p = threadIdx.x; p < N; p += WT_THREADS) {  // u += d; r -= A^* t; d = c1 d + c2 r
+                const int i = p / n, j = p - i * n;
+                if (i == 0 || j == 0) continue;
+                const cplx<P> dv = d[p];
+                const cplx<P> rv = r[p] - applyA_at(G, n2, t, i, j, true);
+                u[p] = u[p] + dv;
+                r[p] = rv;
+                d[p] = c1 * dv + c2 * rv;
+            }
+            __syncthreads();
+            rho = rho_new;
+        } else {
+            for (int p = threadIdx.x; p < N; p += WT_THREADS) u[p] = u[p] + d[p];
+            __syncthreads();
+        }
+    }
+}
+
+// gc = R (g - A u) from level l (precision Pf) to level l + 1 (precision Pc); u may be zero.
+template <typename Pf, typename Pc>
+__device__ void wt_restrict(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero) {
+    const Geom& G = F.G;
+    const int n = G.n, nc = n / 2;
+    const Pf* n2 = (const Pf*)F.n2;
+    const cplx<Pf>* g = (const cplx<Pf>*)F.g;
+    const cplx<Pf>* u = u_zero ? nullptr : (const cplx<Pf>*)F.u;
+    cplx<Pc>* gc = (cplx<Pc>*)Cl.g;
+    for (int q = threadIdx.x; q < nc * nc; q += WT_THREADS) {
+        const int I = q / nc, J = q - I * nc;
+        cplx<Pf> v{};
+        if (I > 0 && J > 0) {
+            const int fi = 2 * I, fj = 2 * J;
+            auto R = [&](int a, int b) { return resid_at(G, n2, g, u, a, b); };
+            const cplx<Pf> c = R(fi, fj);
+            const cplx<Pf> ud = ((R(fi - 1, fj) + R(fi + 1, fj)) + R(fi, fj - 1)) + R(fi, fj + 1);
+            const cplx<Pf> dg = ((R(fi - 1, fj - 1) + R(fi - 1, fj + 1)) + R(fi + 1, fj - 1)) + R(fi + 1, fj + 1);
+            v = Pf(1.0 / 16.0) * ((Pf(4) * c + Pf(2) * ud) + dg);
+        }
+        gc[q] = ccast<Pc>(v);
+    }
+    __syncthreads();
+}
+
+// u (level l, precision Pf) += P e (level l + 1, precision Pc); u_zero: u = P e.
+template <typename Pc, typename Pf>
+__device__ void wt_prolong(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero) {
+    const int n = F.G.n, nc = n / 2;
+    cplx<Pf>* u = (cplx<Pf>*)F.u;
+    const cplx<Pc>* ec = (const cplx<Pc>*)Cl.u;
+    for (int p = threadIdx.x; p < n * n; p += WT_THREADS) {
+        const int i = p / n, j = p - i * n;
+        cplx<Pf> v{};
+        if (i > 0 && j > 0) v = prolong_at<Pc, Pf>(ec, nc, i, j);
+        u[p] = u_zero ? v : u[p] + v;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void wt_transfer_down(const TailWaveArgs& a, int l, bool u_zero) {
+    if (a.lv[l + 1].f64) wt_restrict<T, double>(a.lv[l], a.lv[l + 1], u_zero);
+    else wt_restrict<T, T>(a.lv[l], a.lv[l + 1], u_zero);
+}
+template <typename T>
+__device__ void wt_transfer_up(const TailWaveArgs& a, int l, bool u_zero) {
+    if (a.lv[l + 1].f64) wt_prolong<double, T>(a.lv[l], a.lv[l + 1], u_zero);
+    else wt_prolong<T, T>(a.lv[l], a.lv[l + 1], u_zero);
+}
+
+// The cycle on levels l0..L from a zero iterate, as the per-level host recursion runs
+// it (no ADR correction here: l0 >= 3).  Levels below L are in precision T (or FP64
+// when the whole cycle is FP64); level L is FP64.
+template <typename T>
+__global__ __launch_bounds__(WT_THREADS) void k_wave_tail(TailWaveArgs a) {
+    for (int l = a.l0; l < a.L; ++l) {  // descend: pre-smoothing and restriction
+        const bool smooth = l != 3;
+        if (smooth) wt_cheb<T>(a.lv[l], true, a.cheb_pre);
+        wt_transfer_down<T>(a, l, !smooth);
+    }
+    wt_cheb<double>(a.lv[a.L], true, a.cheb_coarse);
+    for (int l = a.L - 1; l >= a.l0; --l) {  // ascend: prolongation and post-smoothing
+        const bool pre = l != 3;
+        wt_transfer_up<T>(a, l, !pre);
+        if (l != 3 || a.level3_literal) wt_cheb<T>(a.lv[l], false, a.cheb_post);
+    }
+}
+
+}  // namespace helm

@@ -33,7 +33,7 @@ def test_desc_defaults():
     d = default_desc(4096, 2100.0)
     assert (d.n, d.levels, d.damping_cells, d.sign, d.adr_steps) == (4096, 7, 16, 1, 8)
     assert (d.cheb_pre, d.cheb_post, d.cheb_coarse, d.gmres_m, d.gmres_coarse_m, d.restart) == (5, 5, 10, 3, 3, 20)
-    assert (d.adr_levels, d.gmres_arnoldi, d.use_graphs, d.tail_n) == (3, 0, 1, 64)
+    assert (d.adr_levels, d.gmres_arnoldi, d.use_graphs, d.tail_n, d.wave_tail_n) == (3, 0, 1, 64, 32)
     assert d.damping_strength == 0.5 and d.k == 2100.0
     assert default_desc(128, 80.0).levels == 4
 
@@ -42,7 +42,7 @@ def test_desc_defaults():
                                          ("damping_cells", 0), ("sign", 0), ("cycle_prec", 5),
                                          ("gmres_m", 0), ("gmres_m", 25), ("restart", 30), ("cheb_pre", 0),
                                          ("adr_levels", -1), ("use_graphs", 2), ("gmres_arnoldi", 3),
-                                         ("tail_n", -5)])
+                                         ("tail_n", -5), ("wave_tail_n", -1)])
 def test_setup_rejects_invalid_descriptors(field, value):
     from paper_2404_02493_amd import default_desc
 

@@ -240,3 +240,27 @@ def test_graph_replays_match_eager(small_case, prec):
         torch.cuda.synchronize()
     Hg.close()
     He.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-13), ("c64", 1e-5)])
+@pytest.mark.parametrize("literal", [0, 1])
+def test_wave_tail_matches_per_level_kernels(prec, tol, literal):
+    """The one-workgroup kernel for the small wave levels gives the cycle of the
+    per-level kernels (wave_tail_n = 0), including the literal level-3 smoother,
+    to the per-cycle tolerance of the precision (FP32: 1e-5 relative)."""
+    from paper_2404_02493_amd import Helmholtz
+
+    c = hi.make_problem(256, 160.0, 5, seed=8, medium="grf", phase="fmm", damping_cells=16)
+    rng = np.random.default_rng(3)
+    u0 = _rand(rng, 256)
+    outs = []
+    for wt in (0, 128):
+        H = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=16, wave_tail_n=wt,
+                      level3_literal=literal)
+        H.set_phase(c.phi)
+        g = to_dev(torch.as_tensor(c.g), H.cdtype)
+        u = to_dev(u0, H.cdtype)
+        H.cycle(g, u)
+        outs.append(u.cpu())
+        H.close()
+    assert rel(outs[1], outs[0]) < tol
