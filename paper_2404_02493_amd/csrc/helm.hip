@@ -133,8 +133,10 @@ struct helm_ctx_s {
         size_t used = 0;
         hipEvent_t next(hipStream_t st) {
             if (used == pool.size()) {
+                // timing-only events: no system-scope fence, so recording one does not
+                // write back and invalidate the caches between the timed launches
                 hipEvent_t e;
-                if (hipEventCreate(&e) != hipSuccess) return nullptr;
+                if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
                 pool.push_back(e);
             }
             hipEvent_t e = pool[used++];
@@ -1515,24 +1517,53 @@ helm_status helm_profile_end(helm_ctx ctx, char* json, int64_t cap) {
         auto& P = ctx->prof;
         P.on = false;
         if (!P.recs.empty()) HIPCHK(hipEventSynchronize(P.recs.back().e1));
+        // Launches are grouped by kernel and grid; a group whose launches move one of at
+        // most three distinct byte counts (the same kernel on different levels with the
+        // same grid) is split by byte count, one whose byte count varies from launch to
+        // launch (a Krylov pass over a growing basis) stays whole.
         struct Agg {
             std::string name;
             long launches = 0;
             double ms = 0, bytes = 0;
         };
-        std::vector<Agg> agg;
+        struct Sub {
+            std::string base;
+            double bpl;
+            long launches = 0;
+            double ms = 0, bytes = 0;
+        };
+        std::vector<Sub> subs;
         for (auto& r : P.recs) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
-            std::string key = std::string(r.name) + " [" + std::to_string(r.grid) + " blocks]";
+            std::string base = std::string(r.name) + " [" + std::to_string(r.grid) + " blocks";
+            auto it = std::find_if(subs.begin(), subs.end(),
+                                   [&](const Sub& a) { return a.base == base && a.bpl == r.bytes; });
+            if (it == subs.end()) {
+                subs.push_back(Sub{base, r.bytes});
+                it = subs.end() - 1;
+            }
+            it->launches += 1;
+            it->ms += ms;
+            it->bytes += r.bytes;
+        }
+        std::vector<Agg> agg;
+        for (auto& sb : subs) {
+            const long distinct = std::count_if(subs.begin(), subs.end(), [&](const Sub& a) { return a.base == sb.base; });
+            std::string key = sb.base + "]";
+            if (distinct <= 3) {
+                char mb[48];
+                std::snprintf(mb, sizeof(mb), ", %.1f MB", sb.bpl / 1e6);
+                key = sb.base + mb + "]";
+            }
             auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg& a) { return a.name == key; });
             if (it == agg.end()) {
                 agg.push_back(Agg{key});
                 it = agg.end() - 1;
             }
-            it->launches += 1;
-            it->ms += ms;
-            it->bytes += r.bytes;
+            it->launches += sb.launches;
+            it->ms += sb.ms;
+            it->bytes += sb.bytes;
         }
         std::sort(agg.begin(), agg.end(), [](const Agg& a, const Agg& b) { return a.ms > b.ms; });
         std::string out = "{\"kernels\": [";
