@@ -220,7 +220,7 @@ def main():
     if args.tune_cache != "none":
         t = time.perf_counter()
         tuning = H32.tune(cache=args.tune_cache)
-        log(f"tuning ({time.perf_counter() - t:.1f} s): sstep_blocks {tuning['sstep_blocks']}, "
+        log(f"tuning ({time.perf_counter() - t:.1f} s): sstep_rows {tuning['sstep_rows']}, "
             f"fgmres_blocks {tuning['fgmres_blocks']}")
 
     def run32():
@@ -283,15 +283,19 @@ def main():
         tot_bytes = sum(k["bytes"] for k in ks)
         top = ks[0]
         achieved = top["bytes"] / (top["ms"] * 1e-3) / 1e9
-        from paper_2404_02493_amd.traffic import load as load_traffic
+        from paper_2404_02493_amd.traffic import find as find_traffic
 
-        traffic = load_traffic(os.path.join(ROOT, "profiles", "traffic_sstep_gram_x0_level2_layered4096.json"),
-                               top["name"])
+        # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE counter runs, scaled by a
+        # plain copy of known size), as a rate over the same average launch time
+        tbytes = find_traffic(os.path.join(ROOT, "profiles"), top["name"])
+        avg_s = 1e-3 * top["ms"] / top["launches"]
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": round(tbytes / avg_s / 1e9, 1) if tbytes else None,
                     "kernel": top["name"], "launches": top["launches"],
-                    "avg_launch_us": round(1e3 * top["ms"] / top["launches"], 2),
-                    "bytes_per_launch": top["bytes"] / top["launches"]}
+                    "avg_launch_us": round(1e6 * avg_s, 2),
+                    "bytes_per_launch": top["bytes"] / top["launches"],
+                    "traffic_bytes_per_launch": tbytes}
         summary = {"kernel_ms_total": round(tot_ms, 3), "algorithmic_GB": round(tot_bytes / 1e9, 3),
                    "effective_GBs_in_kernels": round(tot_bytes / (tot_ms * 1e-3) / 1e9, 1),
                    "top_kernels": [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),

@@ -102,6 +102,7 @@ constexpr int MAXM = 24;
 struct KrylovScal {
     double beta;                          // ||r0||
     double scale[MAXM + 1];               // v_i = scale[i] * V_i
+    double zscale[MAXM + 1];              // FGMRES: factor of V_j in the preconditioner input of z_j
     double H[2 * (MAXM + 1) * MAXM];      // complex Hessenberg, H(i,j) at 2*(i + j*(MAXM+1))
     double dots[2 * (MAXM + 2)];          // results of the last reduction pass
     double y[2 * MAXM];                   // least-squares solution
@@ -110,7 +111,7 @@ struct KrylovScal {
     int cols;                             // Arnoldi columns completed
     int done;                             // 1: no further Arnoldi work (solved, breakdown, zero rhs)
     int m;                                // requested Krylov dimension
-    int pad;
+    unsigned ticket;                      // arrivals at a last-block reduction (0 between launches)
 };
 
 

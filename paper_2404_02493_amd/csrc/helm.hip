@@ -51,6 +51,7 @@ struct WaveLevel {
     void* n2 = nullptr;    // real, cycle precision (FP64 on f64 levels)
     void* g = nullptr;     // right-hand side (levels >= 2)
     void* u = nullptr;     // iterate (levels >= 2)
+    void* ualt = nullptr;  // second iterate of the fused ADR steps (level 2)
     void* t = nullptr;     // Chebyshev scratch
     void* r = nullptr;
     void* d = nullptr;
@@ -65,6 +66,7 @@ struct AdrLevel {
     void* py = nullptr;
     void* c0 = nullptr;
     void* b = nullptr;
+    void* balt = nullptr;  // second right-hand side of the fused ADR steps (level 2)
     void* x = nullptr;
     void* xalt = nullptr;  // second iterate for out-of-place s-step updates
     void* V[MAXM + 1] = {};
@@ -90,6 +92,7 @@ struct helm_ctx_s {
     std::vector<double> w, w_default;
     void* ws1 = nullptr;     // second level-1 iterate (cycle precision)
     double* partials = nullptr;
+    size_t partials_cap = 0;  // doubles
     double* dscal = nullptr;  // small device scratch (norms)
     helm::KrylovScal* Kout = nullptr;
     helm::KrylovScal* Kin = nullptr;
@@ -107,7 +110,7 @@ struct helm_ctx_s {
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
     // launch shapes chosen by the autotuner (0 = built-in default)
     struct Tuning {
-        int sstep_blocks[16] = {};  // blocks of the s-step Gram pass on ADR level l
+        int sstep_rows[16] = {};    // rows per marching segment of the s-step passes on ADR level l
         int fgmres_blocks = 0;      // blocks of the outer FGMRES passes on the fine grid
     } tn;
     // captured cycles, keyed by the (g, u_in, u_out) pointers they were captured with
@@ -241,6 +244,17 @@ static double median_alpha(double k, double n2mean, int nl, double lam) {
         med = 0.5 * (med + hi);
     }
     return std::max(1.0, lam / med);
+}
+
+// f(std::integral_constant<int, J>{}) for the runtime value j = J in [0, N).
+template <int N, int J = 0, typename F>
+static void static_for_host(int j, F&& f) {
+    if constexpr (J < N) {
+        if (j == J)
+            f(std::integral_constant<int, J>{});
+        else
+            static_for_host<N, J + 1>(j, f);
+    }
 }
 
 // ------------------------------------------------------------------ Krylov finalize helper
@@ -408,8 +422,7 @@ struct Engine {
         prolong_up(l, c->wl[l + 1].u, W.u);
         if (l == 2) {
             chebyshev<T>(l, W.g, W.u, false, c->w[1], c->d.cheb_post);
-            if (c->d.adr_steps > 0 && L >= 3)
-                for (int s = 0; s < c->d.adr_steps; ++s) adr_step();
+            if (c->d.adr_steps > 0 && L >= 3) adr_steps(c->d.adr_steps);
         } else if (l == 3 && !c->d.level3_literal) {
             // no post-smoothing on level 3
         } else {
@@ -431,15 +444,56 @@ struct Engine {
                            (const C*)g, (const C*)c->ws1, (C*)u_out, w0);
     }
 
-    // ---- ADR correction on level 2
-    void adr_step() {
+    // ---- ADR corrections on level 2 (M = adr_steps of them)
+    // Each step: r = g - A u, demodulate, one ADR V-cycle, u += a e^{i theta}.  When the
+    // post-smoother of level 2 runs in s-step form, its second pass also re-modulates
+    // and adds the correction and demodulates the next step's right-hand side (the
+    // last step only adds), writing the other buffer of u and b; the pointers end on
+    // the buffers they started on.
+    bool adr_fused() const {
+        const int m = c->d.gmres_m;
+        return c->LA > 2 && m <= 3 && !c->d.gmres_arnoldi && c->wl[2].ualt && c->al[2].balt;
+    }
+    ModArgs<T> mod_args(void* uout, void* bout) {
+        WaveLevel& W = c->wl[2];
+        ModArgs<T> a{};
+        a.G = W.G;
+        a.theta = (const T*)c->theta2;
+        a.n2 = (const T*)W.n2;
+        a.g = (const C*)W.g;
+        a.u = (const C*)W.u;
+        a.uout = (C*)uout;
+        a.bout = (C*)bout;
+        return a;
+    }
+    void adr_steps(int M) {
         WaveLevel& W = c->wl[2];
         AdrLevel& A = c->al[2];
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st, W.G, (const T*)W.n2,
-                           (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
-        adr_vcycle(2);
-        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))), dim3(BLOCK), st, N(2), (const C*)A.x,
-                           (const T*)c->theta2, (C*)W.u);
+        void* const u_home = W.u;
+        void* const b_home = A.b;
+        const bool fused = adr_fused();
+        for (int s = 0; s < M; ++s) {
+            if (s == 0 || !fused)
+                LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(),
+                       st, W.G, (const T*)W.n2, (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
+            if (!fused) {
+                adr_vcycle(2);
+                LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))),
+                       dim3(BLOCK), st, N(2), (const C*)A.x, (const T*)c->theta2, (C*)W.u);
+                continue;
+            }
+            if (s + 1 < M) {
+                const ModArgs<T> ma = mod_args(W.u == u_home ? W.ualt : u_home, A.b == b_home ? A.balt : b_home);
+                adr_vcycle(2, EPI_MODRD, &ma);
+                std::swap(W.u, W.ualt);
+                std::swap(A.b, A.balt);
+            } else {
+                const ModArgs<T> ma = mod_args(u_home, nullptr);
+                adr_vcycle(2, EPI_MOD, &ma);
+                if (W.u != u_home) std::swap(W.u, W.ualt);
+            }
+        }
+        if (A.b != b_home) std::swap(A.b, A.balt);
     }
 
     // GMRES on a small level in one workgroup (the coarsest ADR level), if it fits.
@@ -463,8 +517,9 @@ struct Engine {
         return true;
     }
 
-    // One ADR V-cycle from x = 0 on levels l..LA (result in A.x).
-    void adr_vcycle(int l) {
+    // One ADR V-cycle from x = 0 on levels l..LA (result in A.x, or handed to the
+    // epilogue epi of the last smoother of level l).
+    void adr_vcycle(int l, int epi = EPI_X, const ModArgs<T>* ma = nullptr) {
         AdrLevel& A = c->al[l];
         if (l == c->LA) {
             gmres(l, c->d.gmres_coarse_m, true);
@@ -477,7 +532,7 @@ struct Engine {
         adr_vcycle(l + 1);
         LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), st, A.n,
                            (const C*)c->al[l + 1].x, (C*)A.x);
-        gmres(l, c->d.gmres_m, false);
+        gmres(l, c->d.gmres_m, false, epi, ma);
     }
 
     template <int NV>
@@ -513,51 +568,83 @@ struct Engine {
         LAUNCH(c, (m + 1 + (x0_zero ? 0 : 1)) * sizeof(C) * double(n), (k_krylov_combine<T, NV>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, V,
                            (const KrylovScal*)A.K, (const C*)(x0_zero ? nullptr : A.x), (C*)A.x);
     }
+    // Steps per unit of the marching s-step passes on ADR level l (a multiple of 8; a
+    // unit covers that many rows minus twice its halo): the tuned value, else the
+    // shortest (24..128) that keeps the Gram pass at 2048 wavefronts or fewer.
+    int sstep_steps(int l) const {
+        if (c->tn.sstep_rows[l] > 0) return c->tn.sstep_rows[l];
+        const int n = c->al[l].n;
+        int S = 24;
+        while (S < 128 && March<3, true, true>::units(n, S) > 2048) S += 8;
+        return S;
+    }
+
     // s-step GMRES(MM) on ADR level l.
     template <int MM>
-    void gmres_sstep(int l, bool x0_zero) {
+    void gmres_sstep(int l, bool x0_zero, int epi, const ModArgs<T>* ma) {
         AdrLevel& A = c->al[l];
-        const int nb = tiles_of(A.n);
-        const int nbr = c->tn.sstep_blocks[l] > 0 ? std::min(c->tn.sstep_blocks[l], red_blocks(A.n)) : red_blocks(A.n);
+        const int S = sstep_steps(l);
         constexpr int NG = (MM + 1) * (MM + 1);
-        const double bx = x0_zero ? 0.0 : 1.0;
-        if (x0_zero) {
-            LAUNCH(c, (sizeof(C) + 2 * sizeof(T) + sizeof(C)) * NN(A.n), (k_sstep_gram<T, MM, false>), dim3(nbr),
-                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                   (const C*)nullptr, c->partials);
-        } else {
-            LAUNCH(c, ((2 + bx) * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_gram<T, MM, true>), dim3(nbr),
-                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                   (const C*)A.x, c->partials);
-        }
-        double* gsum = A.K->R;  // device scratch inside the Krylov state
-        LAUNCH(c, 8.0 * NG * nbr, k_sstep_reduce, dim3(NG), dim3(BLOCK), st, (const double*)c->partials, nbr, gsum);
         const double tolb = 1e-12;
+        const double nn = NN(A.n);
+        double* gsum = A.K->R;  // device scratch inside the Krylov state
+        const ModArgs<T> none{};
         if (x0_zero) {
-            LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, false>), dim3(nb),
-                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                   (const C*)nullptr, (const double*)gsum, tolb, A.K, (C*)A.x);
-        } else {
-            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_sstep_combine<T, MM, true>), dim3(nb),
-                   tile_block(), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
-                   (const C*)A.x, (const double*)gsum, tolb, A.K, (C*)A.xalt);
+            REQUIRE(epi == EPI_X, "fused ADR epilogue on a pre-smoother");
+            const int ng = March<MM, false, true>::units(A.n, S), nc = March<MM, false, false>::units(A.n, S);
+            REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many segments for the reduction scratch");
+            LAUNCH(c, (2 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_gram<T, MM, false>), dim3(ng), dim3(64), st,
+                   A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)nullptr,
+                   c->partials);
+            LAUNCH(c, 8.0 * NG * ng, (k_sstep_solve<MM>), dim3(NG), dim3(BLOCK), st, (const double*)c->partials, ng,
+                   tolb, gsum, A.K);
+            LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, false, EPI_X>), dim3(nc), dim3(64),
+                   st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)nullptr,
+                   (const KrylovScal*)A.K, (C*)A.x, none);
+            return;
+        }
+        const int ng = March<MM, true, true>::units(A.n, S);
+        REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many segments for the reduction scratch");
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_gram<T, MM, true>), dim3(ng), dim3(64), st, A.A,
+               S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x, c->partials);
+        LAUNCH(c, 8.0 * NG * ng, (k_sstep_solve<MM>), dim3(NG), dim3(BLOCK), st, (const double*)c->partials, ng, tolb,
+               gsum, A.K);
+        if (epi == EPI_X) {
+            const int nc = March<MM, true, false>::units(A.n, S);
+            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_X>), dim3(nc), dim3(64),
+                   st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
+                   (const KrylovScal*)A.K, (C*)A.xalt, none);
             std::swap(A.x, A.xalt);
+        } else if (epi == EPI_MOD) {
+            const int nc = March<MM, true, false>::units(A.n, S);
+            LAUNCH(c, (5 * sizeof(C) + 3 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MOD>), dim3(nc),
+                   dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
+        } else if constexpr (MM <= 3) {
+            const int nc = March<MM, true, false, 1>::units(A.n, S);
+            LAUNCH(c, (7 * sizeof(C) + 4 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MODRD>), dim3(nc),
+                   dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
+        } else {
+            throw Error(HELM_EINVAL, "fused ADR epilogue needs gmres_m <= 3");
         }
     }
 
-    // GMRES(m) smoother on ADR level l (x = A.x, b = A.b).
-    void gmres(int l, int m, bool x0_zero) {
+    // GMRES(m) smoother on ADR level l (x = A.x, b = A.b); epi != EPI_X (s-step form,
+    // x0 != 0 only) hands the result to that epilogue instead of A.x.
+    void gmres(int l, int m, bool x0_zero, int epi = EPI_X, const ModArgs<T>* ma = nullptr) {
         // one workgroup on the coarsest level, s-step form on the larger ones
         if (l == c->LA && gmres_block(l, m, x0_zero)) return;
         if (m <= 4 && !c->d.gmres_arnoldi) {
             switch (m) {
-                case 1: gmres_sstep<1>(l, x0_zero); break;
-                case 2: gmres_sstep<2>(l, x0_zero); break;
-                case 3: gmres_sstep<3>(l, x0_zero); break;
-                default: gmres_sstep<4>(l, x0_zero); break;
+                case 1: gmres_sstep<1>(l, x0_zero, epi, ma); break;
+                case 2: gmres_sstep<2>(l, x0_zero, epi, ma); break;
+                case 3: gmres_sstep<3>(l, x0_zero, epi, ma); break;
+                default: gmres_sstep<4>(l, x0_zero, epi, ma); break;
             }
             return;
         }
+        REQUIRE(epi == EPI_X, "fused ADR epilogue without the s-step smoother");
         switch (nv_bucket(m)) {
             case 4: gmres_nv<4>(l, m, x0_zero); break;
             case 12: gmres_nv<12>(l, m, x0_zero); break;
@@ -618,8 +705,6 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     std::vector<double> cs(m);
     std::vector<cd> sn(m), e(m + 1, 0.0);
     e[0] = beta;
-    std::vector<double> scale(m + 1, 0.0);
-    scale[0] = 1.0 / beta;
     int used = 0;
     double est = beta / gnorm;
     // Iteration j + 1 is queued before the host reads the Hessenberg column of
@@ -628,18 +713,25 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     // restart rewrites (its kernels exit early once the device marks a breakdown).
     const int jmax = std::min(m, maxit_left);
     const size_t cstride = 2 * (MAXM + 1);
+    // Classical Gram-Schmidt twice with the second round lagging one pass: V[j] enters
+    // iteration j after one round (V[0] = r0 needs none), z_j is the preconditioned
+    // V[j], and the Arnoldi pass of iteration j applies the second round to V[j]
+    // while it builds w = A z_j.  Every Hessenberg entry is the two-round one; the
+    // subdiagonal H(j+1, j) that the host sees with column j comes from the norms
+    // (||w||^2 - sum |d_i|^2) and is replaced on the device by the directly computed
+    // norm one pass later.
     auto enqueue = [&](int j) {
-        prec(j, K->scale + j);  // Z[j] = preconditioned V[j] (scaled by scale[j] if !z_scaled)
-        LAUNCH(c, ((j + 3) * sizeof(Cp) + sizeof(P)) * double(N), (k_arnoldi_helm_ws<P, MAXM>), dim3(nbf),
-               dim3(BLOCK), st, G, (const P*)n2_fine, (const Cp*)Z[j], z_scaled ? 0 : 1, Vs, j, (Cp*)V[j + 1],
-               (const KrylovScal*)K, c->partials);
-        krylov_fin<MAXM>(c, st, nbf, FIN_MV, j, m, K, 0.0);
-        LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass1_ws<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,
-               (Cp*)V[j + 1], (const KrylovScal*)K, c->partials);
-        krylov_fin<MAXM>(c, st, nbf, FIN_ORTH1, j, m, K, 0.0);
-        LAUNCH(c, (j + 3) * sizeof(Cp) * double(N), (k_orth_pass2<P, MAXM>), dim3(nbf), dim3(BLOCK), st, N, Vs, j,
-               (Cp*)V[j + 1], (const KrylovScal*)K, c->partials);
-        krylov_fin<MAXM>(c, st, nbf, FIN_ORTH2, j, m, K, 0.0);
+        prec(j, K->zscale + j);  // Z[j] = preconditioned V[j] (scaled by zscale[j] if !z_scaled)
+        static_for_host<MAXM>(j, [&](auto jc) {
+            constexpr int J = decltype(jc)::value;
+            LAUNCH(c, ((2 * J + 4) * sizeof(Cp) + sizeof(P)) * double(N), (k_fg_arnoldi<P, J>), dim3(nbf),
+                   dim3(BLOCK), st, G, (const P*)n2_fine, (const Cp*)Z[J], z_scaled ? 0 : 1, Vs, (Cp*)V[J],
+                   (Cp*)V[J + 1], (const KrylovScal*)K, c->partials);
+            krylov_fin<MAXM>(c, st, nbf, FIN_LMV, J, m, K, 0.0);
+            LAUNCH(c, (J + 3) * sizeof(Cp) * double(N), (k_fg_orth<P, J>), dim3(nbf), dim3(BLOCK), st, N, Vs,
+                   (Cp*)V[J + 1], (const KrylovScal*)K, c->partials);
+            krylov_fin<MAXM>(c, st, nbf, FIN_LORTH, J, m, K, 0.0);
+        });
         HIPCHK(hipMemcpyAsync(c->hcol + j * cstride, K->H + 2 * (j * (MAXM + 1)), sizeof(double) * 2 * (j + 2),
                               hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(c->col_ev[j], st));
@@ -670,29 +762,14 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
             break;
         }
         if (std::abs(e[j + 1]) < stop_abs || hn == 0.0) break;
-        scale[j + 1] = 1.0 / hn;
     }
-    // y by back substitution; x += sum y_i zs_i Z_i
-    std::vector<cd> y(used);
-    for (int i = used - 1; i >= 0; --i) {
-        cd acc = e[i];
-        for (int q = i + 1; q < used; ++q) acc -= H[i][q] * y[q];
-        y[i] = acc / H[i][i];
+    // y from the device Hessenberg (exact subdiagonals wherever the next Arnoldi pass
+    // has run); x += sum y_i s_i Z_i with the factors the preconditioner inputs had
+    if (used > 0) {
+        LAUNCH(c, 0.0, k_fgmres_lsq, dim3(1), dim3(64), st, K, used);
+        LAUNCH(c, (used + 2) * sizeof(Cp) * double(N), (k_krylov_combine<P, MAXM>), dim3(flat_blocks(N)), dim3(BLOCK),
+               st, N, Zs, (const KrylovScal*)K, (const Cp*)x, (Cp*)x, z_scaled ? 2 : 1);
     }
-    // write y and cols, and the Z scales, into the device state
-    std::vector<double> ybuf(2 * MAXM, 0.0);
-    for (int i = 0; i < used; ++i) {
-        ybuf[2 * i] = y[i].real();
-        ybuf[2 * i + 1] = y[i].imag();
-    }
-    std::vector<double> zs(MAXM + 1, 1.0);
-    if (!z_scaled)
-        for (int i = 0; i < used; ++i) zs[i] = scale[i];
-    HIPCHK(hipMemcpyAsync(K->y, ybuf.data(), sizeof(double) * 2 * MAXM, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(K->scale, zs.data(), sizeof(double) * (MAXM + 1), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(&K->cols, &used, sizeof(int), hipMemcpyHostToDevice, st));
-    LAUNCH(c, (used + 2) * sizeof(Cp) * double(N), (k_krylov_combine<P, MAXM>), dim3(flat_blocks(N)), dim3(BLOCK), st, N, Zs,
-                       (const KrylovScal*)K, (const Cp*)x, (Cp*)x);
     HIPCHK(hipStreamSynchronize(st));
     *est_out = est;
     return used;
@@ -748,7 +825,8 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     const size_t NF = (size_t)n * n;
     // reduction scratch: enough partials for any tiled kernel on the fine grid
     const size_t maxblk = std::max<size_t>((size_t)tiles_of(n), 2048);
-    c->partials = (double*)dalloc(c, maxblk * (2 * MAXM + 4) * sizeof(double));
+    c->partials_cap = maxblk * (2 * MAXM + 4);
+    c->partials = (double*)dalloc(c, c->partials_cap * sizeof(double));
     c->dscal = (double*)dalloc(c, 64 * sizeof(double));
     c->Kout = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
     c->Kin = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
@@ -855,7 +933,9 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
             for (int i = 0; i <= m; ++i) A.V[i] = vb + (size_t)i * Nl * csize(f64c);
             A.K = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
             HIPCHK(hipMemsetAsync(A.K, 0, sizeof(KrylovScal), st));
+            if (l == 2) A.balt = dalloc(c, Nl * csize(f64c));
         }
+        c->wl[2].ualt = dalloc(c, (size_t)c->wl[2].n * c->wl[2].n * csize(c->wl[2].f64));
         c->theta2 = dalloc(c, (size_t)(n / 2) * (n / 2) * rsize(f64c));
     }
     // FP64 residual vectors; the Krylov bases of the outer solvers are allocated by
@@ -1455,7 +1535,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                     const size_t Nl = (size_t)W.n * W.n;
                     HIPCHK(hipMemcpyAsync(W.g, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     HIPCHK(hipMemcpyAsync(W.u, in, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
-                    E.adr_step();
+                    E.adr_steps(1);
                     HIPCHK(hipMemcpyAsync(out, W.u, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     break;
                 }

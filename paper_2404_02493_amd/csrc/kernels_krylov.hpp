@@ -172,41 +172,6 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_adr(AdrGeom A, const T* __res
     store_partials(sums, 2 * (jj + 1), partials);
 }
 
-// Arnoldi matvec pass with the Helmholtz operator on z: w = A (s z), s = scale[jj] if
-// use_scale else 1; partial sums of conj(V_i) w  (FGMRES: z = C(0, V_jj) or C(0, v_jj)).
-template <typename T, int NV>
-__global__ __launch_bounds__(BLOCK) void k_arnoldi_helm(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ z,
-                                                        int use_scale, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
-                                                        const KrylovScal* K, double* partials) {
-    __shared__ double red[4 * (2 * NV + 2)];
-    __shared__ double sums[2 * NV + 2];
-    if (K->done) return;
-    const T sj = use_scale ? T(K->scale[jj]) : T(1);
-    T acc[2 * NV + 2];
-#pragma unroll
-    for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = T(0);
-    int t0, t1;
-    tile_chunk(G.n, t0, t1);
-    for (int t = t0; t < t1; ++t) {
-        int j, i0;
-        tile_xy(G.n, t, j, i0);
-        if (j >= G.n) continue;
-        for (int r = 0; r < RPT; ++r) {
-            const int i = i0 + r;
-            if (i >= G.n) break;
-            const size_t p = (size_t)i * G.n + j;
-            cplx<T> v{};
-            if (i > 0 && j > 0) v = sj * applyA_at(G, n2, z, i, j, false);
-            w[p] = v;
-            acc_dots<T, NV, T>(acc, V, jj, p, v);
-        }
-    }
-    double accd[2 * NV + 2];
-    to_double(acc, accd);
-    block_sum<2 * NV + 2, 4>(accd, 2 * (jj + 1), red, sums);
-    store_partials(sums, 2 * (jj + 1), partials);
-}
-
 // Loads the coefficients c_i = dots_i * scale_i (complex) of the current correction.
 template <typename T, int NV>
 __device__ __forceinline__ void load_coefs(const KrylovScal* K, int jj, cplx<T> (&c)[NV]) {
@@ -273,169 +238,171 @@ __global__ __launch_bounds__(BLOCK) void k_orth_pass2(size_t N, VecSet<T> V, int
     store_partials(sums, 1, partials);
 }
 
-// ---- wave-split passes for the outer FGMRES (up to MAXM + 1 basis vectors)
-// The 4 wavefronts of a block walk the same elements, 64 * E at a time; wave w owns
-// the basis vectors i = w, w + 4, ...: it loads them once per element, adds its
-// share of the projection (exchanged through LDS) and accumulates their inner
-// products with the updated vector.  Each vector is read once per pass and a thread
-// holds the accumulators of a quarter of the basis only.
-constexpr int WS_WAVES = 4;
-
+// ---- streaming passes of the outer FGMRES, one instantiation per column J
+// A thread owns E consecutive elements (16-byte loads) of a grid-stride sweep and
+// streams every basis vector the column needs; J is a template parameter so that
+// the loops over the basis are unrolled with exactly the registers the column uses.
 template <typename T>
-struct WsShape {
-    static constexpr int E = sizeof(T) == 4 ? 4 : 2;  // elements per lane per step
-    static constexpr int STEP = 64 * E;
+struct FgShape {
+    static constexpr int E = sizeof(T) == 4 ? 2 : 1;
 };
 
-// Contiguous element range of this block, a multiple of the step.
-template <typename T>
-__device__ __forceinline__ void ws_range(size_t N, size_t& b0, size_t& b1) {
-    const size_t step = WsShape<T>::STEP;
-    const size_t per = ((N + gridDim.x - 1) / gridDim.x + step - 1) / step * step;
-    b0 = (size_t)blockIdx.x * per;
-    b1 = b0 + per < N ? b0 + per : N;
-}
+template <typename T, int E>
+struct Pack;
+template <>
+struct Pack<float, 2> {
+    using V = float4;
+};
+template <>
+struct Pack<double, 1> {
+    using V = double2;
+};
 
-// Per-wave accumulators (vectors i = wave + 4k) -> partials[(2i + c) * nblk + block].
-template <typename T, int NPW>
-__device__ __forceinline__ void ws_store(const T (&acc)[2 * NPW], int jj, double* sums, double* partials) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < NPW; ++k) {
-        const int i = wave + WS_WAVES * k;
-        if (i <= jj) {
-            const double re = wave_sum(double(acc[2 * k])), im = wave_sum(double(acc[2 * k + 1]));
-            if (lane == 0) {
-                sums[2 * i] = re;
-                sums[2 * i + 1] = im;
-            }
-        }
+template <typename T, int E>
+__device__ __forceinline__ void ld_pack(const cplx<T>* __restrict__ a, size_t p, cplx<T> (&v)[E]) {
+    using PV = typename Pack<T, E>::V;
+    const PV q = *reinterpret_cast<const PV*>(a + p);
+    if constexpr (E == 2) {
+        v[0] = mk<T>(q.x, q.y);
+        v[1] = mk<T>(q.z, q.w);
+    } else {
+        v[0] = mk<T>(q.x, q.y);
     }
-    __syncthreads();
-    store_partials(sums, 2 * (jj + 1), partials);
 }
 
-// w = A (s z) on the fine grid and partial conj(V_i) w, i <= jj (finalize with FIN_MV).
-// Wave e of the block evaluates the stencil for slice e of the step (E slices of 64
-// elements, E = 4 waves for complex64) and shares it through LDS, so z is read once.
-template <typename T, int NV>
-__global__ __launch_bounds__(BLOCK) void k_arnoldi_helm_ws(Geom G, const T* __restrict__ n2,
-                                                           const cplx<T>* __restrict__ z, int use_scale, VecSet<T> V,
-                                                           int jj, cplx<T>* __restrict__ w, const KrylovScal* K,
-                                                           double* partials) {
-    constexpr int NPW = (NV + WS_WAVES - 1) / WS_WAVES;
-    constexpr int E = WsShape<T>::E;
-    __shared__ double sums[2 * NV + 2];
-    __shared__ cplx<T> xs[E][64];
-    if (K->done) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const T sj = use_scale ? T(K->scale[jj]) : T(1);
-    const size_t N = (size_t)G.n * G.n;
-    T acc[2 * NPW];
+template <typename T, int E>
+__device__ __forceinline__ void st_pack(cplx<T>* __restrict__ a, size_t p, const cplx<T> (&v)[E]) {
+    using PV = typename Pack<T, E>::V;
+    PV q;
+    if constexpr (E == 2) {
+        q.x = v[0].re;
+        q.y = v[0].im;
+        q.z = v[1].re;
+        q.w = v[1].im;
+    } else {
+        q.x = v[0].re;
+        q.y = v[0].im;
+    }
+    *reinterpret_cast<PV*>(a + p) = q;
+}
+
+// Block sum of K per-thread values (working precision) to partials[v * nblk + block].
+template <int K, typename A>
+__device__ __forceinline__ void fg_store(const A (&acc)[K], double* partials) {
+    __shared__ double red[4 * K];
+    __shared__ double sums[K];
+    double d[K];
 #pragma unroll
-    for (int q = 0; q < 2 * NPW; ++q) acc[q] = T(0);
-    size_t b0, b1;
-    ws_range<T>(N, b0, b1);
-    for (size_t base = b0; base < b1; base += WsShape<T>::STEP) {
-        // stencil slices: wave w computes slices w, w + 4, ... (E <= 4: one or none)
-        for (int e = wave; e < E; e += WS_WAVES) {
-            const size_t p = base + (size_t)e * 64 + lane;
-            cplx<T> v{};
-            if (p < b1) {
-                const int i = (int)(p / G.n), j = (int)(p % G.n);
-                if (i > 0 && j > 0) v = sj * applyA_at(G, n2, z, i, j, false);
-                w[p] = v;
-            }
-            xs[e][lane] = v;
-        }
-        __syncthreads();
+    for (int q = 0; q < K; ++q) d[q] = double(acc[q]);
+    block_sum<K, 4>(d, K, red, sums);
+    store_partials(sums, K, partials);
+}
+
+// FGMRES Arnoldi pass of column J, with the second Gram-Schmidt round of column J-1
+// applied on the fly (classical Gram-Schmidt twice, the second round lagging into
+// this pass):
+//   V_J <- V_J - sum_{i<J} c_i V_i,  c_i = dots_i scale_i (second-round coefficients
+//          left by FIN_LORTH; nothing to do for J = 0),
+//   w = A (s z),  s = zscale[J] if use_scale else 1,
+// with partial sums of conj(V_i) w, i <= J (V_J the corrected vector), and of
+// ||V_J||^2 (finalize with FIN_LMV).  The inner products with V_i, i < J, are taken
+// as each vector streams past, so no basis value is kept.
+template <typename T, int J>
+__global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restrict__ n2,
+                                                      const cplx<T>* __restrict__ z, int use_scale, VecSet<T> V,
+                                                      cplx<T>* __restrict__ vj, cplx<T>* __restrict__ w,
+                                                      const KrylovScal* K, double* partials) {
+    constexpr int E = FgShape<T>::E;
+    constexpr int NA = 2 * (J + 1) + 1;
+    if (K->done) return;
+    cplx<T> cs[J > 0 ? J : 1];
+#pragma unroll
+    for (int i = 0; i < J; ++i) cs[i] = mk<T>(T(K->dots[2 * i] * K->scale[i]), T(K->dots[2 * i + 1] * K->scale[i]));
+    const T sj = use_scale ? T(K->zscale[J]) : T(1);
+    const int n = G.n;
+    const size_t N = (size_t)n * n;
+    T acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = T(0);
+    for (size_t p = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * E; p < N; p += (size_t)gridDim.x * BLOCK * E) {
+        const int i = (int)(p / n), j0 = (int)(p - (size_t)i * n);
         cplx<T> x[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = xs[e][lane];
-#pragma unroll
-        for (int k = 0; k < NPW; ++k) {
-            const int iv = wave + WS_WAVES * k;
-            if (iv <= jj) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const size_t p = base + (size_t)e * 64 + lane;
-                    if (p < b1) {
-                        const cplx<T> v = V.v[iv][p];
-                        acc[2 * k] += v.re * x[e].re + v.im * x[e].im;
-                        acc[2 * k + 1] += v.re * x[e].im - v.im * x[e].re;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    ws_store<T, NPW>(acc, jj, sums, partials);
-}
-
-// Gram-Schmidt pass 1: w -= sum_i dots_i v_i; partial conj(V_i) w (FIN_ORTH1).
-template <typename T, int NV>
-__global__ __launch_bounds__(BLOCK) void k_orth_pass1_ws(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
-                                                         const KrylovScal* K, double* partials) {
-    constexpr int NPW = (NV + WS_WAVES - 1) / WS_WAVES;
-    constexpr int E = WsShape<T>::E;
-    __shared__ cplx<T> cs[NV];
-    __shared__ cplx<T> part[WS_WAVES][E][64];
-    __shared__ double sums[2 * NV + 2];
-    if (K->done) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if ((int)threadIdx.x < NV) {
-        const int i = threadIdx.x;
-        cs[i] = i <= jj ? mk<T>(T(K->dots[2 * i] * K->scale[i]), T(K->dots[2 * i + 1] * K->scale[i])) : cplx<T>{};
-    }
-    __syncthreads();
-    T acc[2 * NPW];
-#pragma unroll
-    for (int q = 0; q < 2 * NPW; ++q) acc[q] = T(0);
-    size_t b0, b1;
-    ws_range<T>(N, b0, b1);
-    for (size_t base = b0; base < b1; base += WsShape<T>::STEP) {
-        cplx<T> v[NPW][E];
-        cplx<T> px[E], wv[E];
-#pragma unroll
         for (int e = 0; e < E; ++e) {
-            // every wave reads w before the barrier; wave 0 overwrites it after
-            const size_t p = base + (size_t)e * 64 + lane;
-            px[e] = cplx<T>{};
-            wv[e] = p < b1 ? w[p] : cplx<T>{};
+            const int j = j0 + e;
+            x[e] = (i > 0 && j > 0) ? sj * applyA_at(G, n2, z, i, j, false) : cplx<T>{};
         }
+        st_pack<T, E>(w, p, x);
+        cplx<T> corr[E];
 #pragma unroll
-        for (int k = 0; k < NPW; ++k) {
-            const int iv = wave + WS_WAVES * k;
+        for (int e = 0; e < E; ++e) corr[e] = cplx<T>{};
+#pragma unroll
+        for (int iv = 0; iv < J; ++iv) {
+            cplx<T> v[E];
+            ld_pack<T, E>(V.v[iv], p, v);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const size_t p = base + (size_t)e * 64 + lane;
-                v[k][e] = (iv <= jj && p < b1) ? V.v[iv][p] : cplx<T>{};
-                px[e] = px[e] + cs[iv <= jj ? iv : 0] * v[k][e];
+                acc[2 * iv] += v[e].re * x[e].re + v[e].im * x[e].im;
+                acc[2 * iv + 1] += v[e].re * x[e].im - v[e].im * x[e].re;
+                corr[e] = corr[e] + cs[iv] * v[e];
             }
         }
+        cplx<T> v[E];
+        ld_pack<T, E>(V.v[J], p, v);
+        if constexpr (J > 0) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) part[wave][e][lane] = px[e];
-        __syncthreads();
+            for (int e = 0; e < E; ++e) v[e] = v[e] - corr[e];
+            st_pack<T, E>(vj, p, v);
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const size_t p = base + (size_t)e * 64 + lane;
-            cplx<T> x{};
-            if (p < b1) {
-                x = wv[e] - ((part[0][e][lane] + part[1][e][lane]) + (part[2][e][lane] + part[3][e][lane]));
-                if (wave == 0) w[p] = x;
-            }
-#pragma unroll
-            for (int k = 0; k < NPW; ++k) {
-                acc[2 * k] += v[k][e].re * x.re + v[k][e].im * x.im;
-                acc[2 * k + 1] += v[k][e].re * x.im - v[k][e].im * x.re;
-            }
+            acc[2 * J] += v[e].re * x[e].re + v[e].im * x[e].im;
+            acc[2 * J + 1] += v[e].re * x[e].im - v[e].im * x[e].re;
+            acc[2 * J + 2] += v[e].re * v[e].re + v[e].im * v[e].im;
         }
-        __syncthreads();
     }
-    ws_store<T, NPW>(acc, jj, sums, partials);
+    fg_store<NA>(acc, partials);
 }
 
-enum FinOp { FIN_INIT = 0, FIN_MV = 1, FIN_ORTH1 = 2, FIN_ORTH2 = 3 };
+// First Gram-Schmidt round of column J: w -= sum_{i<=J} c_i V_i, c_i = dots_i scale_i;
+// partial sums of conj(V_i) w, i <= J, and ||w||^2 (finalize with FIN_LORTH).
+template <typename T, int J>
+__global__ __launch_bounds__(BLOCK) void k_fg_orth(size_t N, VecSet<T> V, cplx<T>* __restrict__ w,
+                                                   const KrylovScal* K, double* partials) {
+    constexpr int E = FgShape<T>::E;
+    constexpr int NA = 2 * (J + 1) + 1;
+    if (K->done) return;
+    cplx<T> cs[J + 1];
+#pragma unroll
+    for (int i = 0; i <= J; ++i) cs[i] = mk<T>(T(K->dots[2 * i] * K->scale[i]), T(K->dots[2 * i + 1] * K->scale[i]));
+    T acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = T(0);
+    for (size_t p = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * E; p < N; p += (size_t)gridDim.x * BLOCK * E) {
+        cplx<T> x[E];
+        ld_pack<T, E>(w, p, x);
+        cplx<T> v[J + 1][E];
+#pragma unroll
+        for (int iv = 0; iv <= J; ++iv) {
+            ld_pack<T, E>(V.v[iv], p, v[iv]);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = x[e] - cs[iv] * v[iv][e];
+        }
+        st_pack<T, E>(w, p, x);
+#pragma unroll
+        for (int iv = 0; iv <= J; ++iv)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                acc[2 * iv] += v[iv][e].re * x[e].re + v[iv][e].im * x[e].im;
+                acc[2 * iv + 1] += v[iv][e].re * x[e].im - v[iv][e].im * x[e].re;
+            }
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[2 * J + 2] += x[e].re * x[e].re + x[e].im * x[e].im;
+    }
+    fg_store<NA>(acc, partials);
+}
+
+enum FinOp { FIN_INIT = 0, FIN_MV = 1, FIN_ORTH1 = 2, FIN_ORTH2 = 3, FIN_LMV = 4, FIN_LORTH = 5 };
 
 // One block: sums the partials of the previous Krylov pass and updates the state.
 //   FIN_INIT : beta = ||r0||, scale[0] = 1/beta, cols = 0, done if beta == 0
@@ -443,13 +410,23 @@ enum FinOp { FIN_INIT = 0, FIN_MV = 1, FIN_ORTH1 = 2, FIN_ORTH2 = 3 };
 //   FIN_ORTH1: H(i, jj) = dots_i (first round), dots_i = second-round products
 //   FIN_ORTH2: H(i, jj) += dots_i, H(jj+1, jj) = ||w||, next scale; on breakdown
 //              (||w|| <= tol beta) or at jj + 1 == m the Hessenberg least squares.
+// The outer FGMRES (second Gram-Schmidt round lagging one pass):
+//   FIN_LMV  : after k_fg_arnoldi.  jj > 0: scale_jj = 1/||V_jj||, H(jj, jj-1) =
+//              ||V_jj|| (the exact norm replaces the estimate); dots_i = scale_i *
+//              sum conj(V_i) w, i <= jj (first-round coefficients of column jj)
+//   FIN_LORTH: after k_fg_orth.  d_i = scale_i * sum conj(V_i) w; H(i, jj) =
+//              dots_i + d_i; dots_i = d_i (second round, applied by the next
+//              k_fg_arnoldi); H(jj+1, jj) = (||w||^2 - sum |d_i|^2)^(1/2), which
+//              is the norm of w after the second round; zscale and scale of jj + 1
 template <int KV>
 __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __restrict__ partials, int nblk, int op,
                                                             int jj, int m, KrylovScal* K, double tol) {
     __shared__ double red[(FBLOCK / 64) * KV];
     __shared__ double sums[KV];
     if (op != FIN_INIT && K->done) return;
-    const int kcount = (op == FIN_MV || op == FIN_ORTH1) ? 2 * (jj + 1) : 1;
+    const int kcount = (op == FIN_MV || op == FIN_ORTH1)     ? 2 * (jj + 1)
+                       : (op == FIN_LMV || op == FIN_LORTH) ? 2 * (jj + 1) + 1
+                                                            : 1;
     final_sum<KV>(partials, nblk, kcount, red, sums);
     if (threadIdx.x != 0) return;
     if (op == FIN_INIT) {
@@ -459,8 +436,50 @@ __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __rest
         K->cols = 0;
         K->done = (b == 0.0 || !isfinite(b)) ? 1 : 0;
         K->scale[0] = b > 0.0 ? 1.0 / b : 0.0;
+        K->zscale[0] = K->scale[0];
         if (K->done)
             for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
+    } else if (op == FIN_LMV) {
+        if (jj > 0) {
+            const double nv = sqrt(sums[2 * (jj + 1)]);
+            Hp(K, jj, jj - 1)[0] = nv;
+            Hp(K, jj, jj - 1)[1] = 0.0;
+            if (nv > 0.0 && isfinite(nv)) {
+                K->scale[jj] = 1.0 / nv;
+            } else {
+                K->scale[jj] = 0.0;
+                K->done = isfinite(nv) ? 1 : 2;
+            }
+        }
+        for (int i = 0; i <= jj; ++i) {
+            double s = K->scale[i];
+            K->dots[2 * i] = s * sums[2 * i];
+            K->dots[2 * i + 1] = s * sums[2 * i + 1];
+        }
+    } else if (op == FIN_LORTH) {
+        double dd = 0.0;
+        for (int i = 0; i <= jj; ++i) {
+            const double s = K->scale[i];
+            const double dr = s * sums[2 * i], di = s * sums[2 * i + 1];
+            Hp(K, i, jj)[0] = K->dots[2 * i] + dr;
+            Hp(K, i, jj)[1] = K->dots[2 * i + 1] + di;
+            K->dots[2 * i] = dr;
+            K->dots[2 * i + 1] = di;
+            dd += dr * dr + di * di;
+        }
+        const double h2 = sums[2 * (jj + 1)] - dd;
+        const double hn = h2 > 0.0 ? sqrt(h2) : 0.0;
+        Hp(K, jj + 1, jj)[0] = isfinite(h2) ? hn : h2;
+        Hp(K, jj + 1, jj)[1] = 0.0;
+        K->cols = jj + 1;
+        if (!isfinite(h2)) {
+            K->done = 2;
+        } else if (hn <= tol * K->beta || hn == 0.0 || jj + 1 == K->m) {
+            K->done = 1;
+        } else {
+            K->scale[jj + 1] = 1.0 / hn;
+            K->zscale[jj + 1] = 1.0 / hn;
+        }
     } else if (op == FIN_MV) {
         for (int i = 0; i <= jj; ++i) {
             double s = K->scale[i];
@@ -496,16 +515,25 @@ __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __rest
     }
 }
 
-// x = x0 + sum_{i < cols} y_i scale_i V_i  (x0 == nullptr: 0; x may alias x0).
+// FGMRES end of a restart cycle: K->cols = cols and y from the device Hessenberg
+// (Givens least squares, one thread).
+__global__ void k_fgmres_lsq(KrylovScal* K, int cols) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    K->cols = cols;
+    ks_least_squares(K, cols);
+}
+
+// x = x0 + sum_{i < cols} y_i s_i V_i, s_i = scale_i (zs == 0), zscale_i (zs == 1) or 1
+// (zs == 2)  (x0 == nullptr: 0; x may alias x0).
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_krylov_combine(size_t N, VecSet<T> V, const KrylovScal* K,
-                                                          const cplx<T>* x0, cplx<T>* x) {
+                                                          const cplx<T>* x0, cplx<T>* x, int zs = 0) {
     const int cols = K->cols;
     cplx<T> c[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         if (i < cols) {
-            double s = K->scale[i];
+            double s = zs == 0 ? K->scale[i] : zs == 1 ? K->zscale[i] : 1.0;
             c[i] = mk<T>(T(K->y[2 * i] * s), T(K->y[2 * i + 1] * s));
         } else {
             c[i] = cplx<T>{};

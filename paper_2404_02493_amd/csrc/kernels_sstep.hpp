@@ -3,191 +3,287 @@
 // GMRES(m) from x0 returns x = x0 + z, z in span{r0, M r0, ..., M^{m-1} r0}, that
 // minimises ||r0 - M z||.  With K_j = M^j r0 this is the least-squares problem
 // min_c || K_0 - sum_{j=1..m} c_j K_j ||, and then x = x0 + sum_j c_j K_{j-1}.
-// The Krylov vectors are never stored: each pass rebuilds them on a 64 x 16 tile
-// plus a halo of one node per operator application, staged through LDS.
-//   pass 1 (k_sstep_gram):    K_0..K_m on the tile, Gram matrix G = K^H K (FP64)
-//   reduce (k_sstep_reduce):  the Gram partials summed, one block per entry
-//   (the normalised Cholesky solve for c runs at the start of every combine block)
+// The Krylov vectors are never stored; each pass rebuilds them:
+//   pass 1 (k_sstep_gram):    K_0..K_m, Gram matrix G = K^H K (FP64 partial sums)
+//   k_sstep_solve:            the partials summed (one block per Gram entry), then
+//                             the normalised Cholesky solve of the normal
+//                             equations for c (the last block to finish)
 //   pass 2 (k_sstep_combine): K_0..K_{m-1} again, x_out = x0 + sum c_j K_{j-1}
 // The normalised monomial basis of the ADR operator is well conditioned for
 // m <= 4 (condition numbers of 5-40 measured on the workloads), so the normal
 // equations lose at most about three digits of FP64 accuracy.
+//
+// Both passes march: one wavefront owns a strip of 64 consecutive columns and
+// walks down the rows of one segment, one row per step (S steps for S - 2H rows).  Lane l holds column
+// j = jb - H + l, where [jb, jb + 64 - 2H) are the strip's own columns and H is
+// the number of operator applications between the loaded fields and the last
+// Krylov vector (the halo).  At the step that loads row q, K_j is produced on row
+// q - j - D (D = 1 when K_0 = b - M x0 needs one application itself), so every
+// operand row is already in registers: up/down neighbours come from register
+// windows of the last rows of every field, left/right neighbours from the
+// adjacent lanes (DPP lane shifts).  There is no LDS and no barrier; only the 2H
+// halo columns and the 2H warm-up rows of a segment are computed twice.
 #pragma once
+
+#include <type_traits>
 
 #include "kernels_krylov.hpp"
 
 namespace helm {
 
-template <int M, bool X0>
-struct SStep {
-    static constexpr int HMAX = M + (X0 ? 1 : 0);  // halo of the first loaded field
-    static constexpr int PW = TX + 2 * HMAX;
-    static constexpr int PH = TY + 2 * HMAX;
-    static constexpr int PN = PW * PH;
-    static constexpr int NG = (M + 1) * (M + 1);  // doubles of the Gram (diag real + upper complex)
+// The value held by lane l - 1 (lane_prev) or lane l + 1 (lane_next) of the
+// wavefront; 0 where that lane does not exist.
+__device__ __forceinline__ float lane_prev(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138 /* wave_shr:1 */, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_next(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130 /* wave_shl:1 */, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double lane_prev(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x138, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_next(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x130, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> lane_prev(cplx<T> v) {
+    return {lane_prev(v.re), lane_prev(v.im)};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> lane_next(cplx<T> v) {
+    return {lane_next(v.re), lane_next(v.im)};
+}
+
+// f(std::integral_constant<int, i>) for i = 0..N-1, unrolled at compile time.
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
+// Upwind ADR stencil of one node with its constant factors folded in:
+//   M a = C a_c - l sum_nb a_nb - i sum_nb g_nb a_nb,
+//   l = 1/h^2,  C = c0 + 4 l - i g_c,  g = 2 sigma k / (2h) * (upwind weight of the node).
+// Off the unknowns every factor is zero (l included), so M a = 0 there.
+template <typename T>
+struct UpCoef {
+    T gw, ge, gs, gn;  // west (j-1), east (j+1), south (i-1), north (i+1)
+    T cr, ci;          // C
+    T l;               // 1/h^2
 };
 
-// Top-left node of tile t.
-__device__ __forceinline__ void sstep_tile(int n, int t, int& j0, int& i0) {
-    const int ntx = (n + TX - 1) / TX;
-    j0 = (t % ntx) * TX;
-    i0 = (t / ntx) * TY;
-}
-
-// M applied at LDS position (li, lj) of a field stored with padded width PW.
-template <typename T, int PW>
-__device__ __forceinline__ cplx<T> applyM_lds(const AdrGeom& A, const cplx<T>* __restrict__ s, int li, int lj, T fx,
-                                              T fy, cplx<T> cc) {
-    const cplx<T> c = s[li * PW + lj];
-    const cplx<T> w = s[li * PW + lj - 1], e = s[li * PW + lj + 1];
-    const cplx<T> so = s[(li - 1) * PW + lj], nn = s[(li + 1) * PW + lj];
+// fx, fy, c0 must be zero off the unknowns (ok == false).
+template <typename T>
+__device__ __forceinline__ UpCoef<T> up_coef(const AdrGeom& A, T fx, T fy, cplx<T> c0, bool ok) {
+    const T a = T(A.inv_2h) * T(A.two_sk);
     const T ax = fx < T(0) ? -fx : fx, ay = fy < T(0) ? -fy : fy;
-    const cplx<T> lap = T(A.inv_h2) * (T(4) * c - (((so + nn) + w) + e));
-    const cplx<T> U = T(A.inv_2h) * (((((T(2) * (ax + ay)) * c - (fx + ax) * w) + (fx - ax) * e) - (fy + ay) * so) +
-                                    (fy - ay) * nn);
-    const cplx<T> adv = mk<T>(T(A.two_sk) * U.im, -T(A.two_sk) * U.re);
-    return lap + (adv + cc * c);
+    UpCoef<T> k;
+    k.l = ok ? T(A.inv_h2) : T(0);
+    k.gw = -a * (fx + ax);
+    k.ge = a * (fx - ax);
+    k.gs = -a * (fy + ay);
+    k.gn = a * (fy - ay);
+    k.cr = c0.re + T(4) * k.l;
+    k.ci = c0.im - a * (T(2) * (ax + ay));
+    return k;
 }
 
-// dst = M src on the tile region with halo h (src valid on halo h+1); zero off the unknowns.
-template <typename T, int M, bool X0>
-__device__ __forceinline__ void sstep_stage(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,
-                                            const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ src,
-                                            cplx<T>* __restrict__ dst, int h, int i0, int j0) {
-    using S = SStep<M, X0>;
-    const int tid = threadIdx.x + threadIdx.y * TX;
-    const int rw = TX + 2 * h, rh = TY + 2 * h;
-    const int off = S::HMAX - h;
-    for (int q = tid; q < rw * rh; q += BLOCK) {
-        const int ri = q / rw, rj = q - ri * rw;
-        const int gi = i0 - h + ri, gj = j0 - h + rj;
-        const int li = off + ri, lj = off + rj;
-        cplx<T> v{};
-        if (gi >= 1 && gj >= 1 && gi < A.n && gj < A.n) {
-            const size_t p = (size_t)gi * A.n + gj;
-            v = applyM_lds<T, S::PW>(A, src, li, lj, px[p], py[p], c0[p]);
-        }
-        dst[li * S::PW + lj] = v;
-    }
-    __syncthreads();
+template <typename T>
+__device__ __forceinline__ cplx<T> up_apply(const UpCoef<T>& k, cplx<T> c, cplx<T> w, cplx<T> e, cplx<T> s,
+                                            cplx<T> n) {
+    const T sr = (s.re + n.re) + (w.re + e.re);
+    const T si = (s.im + n.im) + (w.im + e.im);
+    T re = (k.cr * c.re - k.ci * c.im) - k.l * sr;
+    T im = (k.cr * c.im + k.ci * c.re) - k.l * si;
+    re += ((k.gw * w.im + k.ge * e.im) + (k.gs * s.im + k.gn * n.im));
+    im -= ((k.gw * w.re + k.ge * e.re) + (k.gs * s.re + k.gn * n.re));
+    return {re, im};
 }
 
-// Loads K_0 = b - M x0 (X0) or K_0 = b on the region with halo M (+0), into buffer k0.
-template <typename T, int M, bool X0>
-__device__ __forceinline__ void sstep_load(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,
-                                           const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
-                                           const cplx<T>* __restrict__ x0, cplx<T>* __restrict__ xs,
-                                           cplx<T>* __restrict__ k0, int hk0, int i0, int j0) {
-    using S = SStep<M, X0>;
-    const int tid = threadIdx.x + threadIdx.y * TX;
-    if (X0) {
-        const int h = hk0 + 1;
-        const int rw = TX + 2 * h, rh = TY + 2 * h;
-        const int off = S::HMAX - h;
-        for (int q = tid; q < rw * rh; q += BLOCK) {
-            const int ri = q / rw, rj = q - ri * rw;
-            const int gi = i0 - h + ri, gj = j0 - h + rj;
-            cplx<T> v{};
-            if (gi >= 1 && gj >= 1 && gi < A.n && gj < A.n) v = x0[(size_t)gi * A.n + gj];
-            xs[(off + ri) * S::PW + off + rj] = v;
-        }
-        __syncthreads();
-    }
-    const int h = hk0;
-    const int rw = TX + 2 * h, rh = TY + 2 * h;
-    const int off = S::HMAX - h;
-    for (int q = tid; q < rw * rh; q += BLOCK) {
-        const int ri = q / rw, rj = q - ri * rw;
-        const int gi = i0 - h + ri, gj = j0 - h + rj;
-        const int li = off + ri, lj = off + rj;
-        cplx<T> v{};
-        if (gi >= 1 && gj >= 1 && gi < A.n && gj < A.n) {
-            const size_t p = (size_t)gi * A.n + gj;
-            v = b[p];
-            if (X0) v = v - applyM_lds<T, S::PW>(A, xs, li, lj, px[p], py[p], c0[p]);
-        }
-        k0[li * S::PW + lj] = v;
-    }
-    __syncthreads();
-}
+// Strip/segment geometry of the marching passes.  GRAM: the pass builds K_0..K_M
+// (else K_0..K_{M-1}).
+template <int M, bool X0, bool GRAM, int XH = 0>
+struct March {
+    static constexpr int D = X0 ? 1 : 0;
+    static constexpr int NK = GRAM ? M : M - 1;  // last Krylov vector built
+    static constexpr int H = NK + D + XH;        // halo of the loaded fields (XH: rows and
+                                                 // columns beyond its own that a unit emits)
+    static constexpr int TXW = 64 - 2 * H;       // columns owned by one strip
+    static constexpr int W = 8;                  // rows kept per field (ring of registers)
+    static constexpr int P = 3;                  // rows loaded ahead of the row they feed
+    // steps after its own step that a loaded row is still read: x0 by K_0 of the next
+    // row (and by the combination NK + D rows later), b by K_0
+    static constexpr int LAST = X0 ? (GRAM ? 2 : (NK + D > 2 ? NK + D : 2)) : 1;
+    static_assert(P + LAST < W, "register ring too short for the prefetch");
+    // steps from the prefetch of a row to its emit (an epilogue's fields of the row
+    // are read there, and by the emit of the next row when XH > 0)
+    static constexpr int EMIT_SPAN = P + NK + D + (XH > 0 ? 1 : 0);
+    // A unit marches S steps (S a multiple of W) over a segment of S - 2H rows.
+    __host__ __device__ static int rows(int S) { return S - 2 * H; }
+    __host__ __device__ static int strips(int n) { return (n - 2) / TXW + 1; }
+    __host__ __device__ static int units(int n, int S) { return strips(n) * ((n - 2) / rows(S) + 1); }
+};
 
-// Interior points of a tile per thread, and the interior values of a buffer copied
-// to registers (point q = tid + e * BLOCK of the tile).
-constexpr int IPT = TX * TY / BLOCK;
+// No fields beyond those of the Krylov vectors.
+struct NoExtra {
+    __device__ void init(int, bool, int) {}
+    template <int SL>
+    __device__ void load(int) {}
+};
 
-template <typename T, int PW, int HMAX>
-__device__ __forceinline__ void sstep_keep(const cplx<T>* __restrict__ buf, cplx<T> (&k)[IPT], int tid) {
+// Shared body of both passes.  Per step: prefetch row q + P (and ex's fields of it),
+// fold the stencil of row q, then K_0 (X0: on row q - 1) and K_1..K_NK on the rows
+// behind it; the finished row r = q - NK - D is handed to emit(r, slot, k) (k[j] =
+// K_j on row r; slot: the std::integral_constant ring position of row r) for the
+// unit's rows and XH rows beyond them on either side.
+template <typename T, int M, bool X0, bool GRAM, int XH, typename Extra, typename Emit>
+__device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __restrict__ px,
+                                            const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                            const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
+                                            int& jcol, int& rb, int& re, cplx<T> (&xr)[8], Extra& ex,
+                                            Emit&& emit) {
+    using Mc = March<M, X0, GRAM, XH>;
+    constexpr int H = Mc::H, D = Mc::D, NK = Mc::NK, W = Mc::W, P = Mc::P;
+    const int n = A.n;
+    const int lane = threadIdx.x;
+    const int ns = Mc::strips(n);
+    int u = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) u = (u & 7) * (nb >> 3) + (u >> 3);  // neighbouring units on one XCD
+    const int sg = u / ns, st = u - sg * ns;
+    const int j = 1 + st * Mc::TXW - H + lane;
+    jcol = j;
+    const bool colok = j >= 1 && j <= n - 1;
+    const int R = Mc::rows(S);
+    rb = 1 + sg * R;
+    re = rb + R - 1 < n - 1 ? rb + R - 1 : n - 1;
+    const int qs = rb - H;
+    ex.init(j, colok, n);
+
+    cplx<T> bw[W], kw[NK + 1][W];  // kw[NK] only holds the current row
+    T fxw[W], fyw[W];
+    cplx<T> cw0[W];
+    UpCoef<T> cw[W];
 #pragma unroll
-    for (int e = 0; e < IPT; ++e) {
-        const int q = tid + e * BLOCK;
-        const int ri = q / TX, rj = q - ri * TX;
-        k[e] = buf[(HMAX + ri) * PW + HMAX + rj];
+    for (int s = 0; s < W; ++s) {
+        xr[s] = cplx<T>{};
+        bw[s] = cplx<T>{};
+        fxw[s] = fyw[s] = T(0);
+        cw0[s] = cplx<T>{};
+        cw[s] = UpCoef<T>{};
+#pragma unroll
+        for (int q = 0; q <= NK; ++q) kw[q][s] = cplx<T>{};
+    }
+    auto load_row = [&](int r, cplx<T>& xv, cplx<T>& bv, T& fx, T& fy, cplx<T>& cv) {
+        if (r >= 1 && r <= n - 1 && colok) {
+            const int p = r * n + j;
+            if (X0) xv = x0[p];
+            bv = b[p];
+            fx = px[p];
+            fy = py[p];
+            cv = c0[p];
+        } else {
+            xv = cplx<T>{};
+            bv = cplx<T>{};
+            fx = fy = T(0);
+            cv = cplx<T>{};
+        }
+    };
+    static_for<P>([&](auto pc) {
+        constexpr int s = decltype(pc)::value;
+        load_row(qs + s, xr[s], bw[s], fxw[s], fyw[s], cw0[s]);
+        ex.template load<s>(qs + s);
+    });
+    for (int t0 = 0; t0 < S; t0 += W) {
+        static_for<W>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            const int q = qs + t0 + s;
+            // prefetch row q + P
+            constexpr int s1 = (s + P) % W;
+            load_row(q + P, xr[s1], bw[s1], fxw[s1], fyw[s1], cw0[s1]);
+            ex.template load<s1>(q + P);
+            cw[s] = up_coef<T>(A, fxw[s], fyw[s], cw0[s], q >= 1 && q <= n - 1 && colok);
+            // K_0 (zero off the unknowns: b and the stencil factors are)
+            if constexpr (X0) {
+                constexpr int sr = (s + W - 1) % W;
+                const cplx<T> c = xr[sr];
+                kw[0][sr] = bw[sr] - up_apply<T>(cw[sr], c, lane_prev(c), lane_next(c), xr[(s + W - 2) % W], xr[s]);
+            } else {
+                kw[0][s] = bw[s];
+            }
+            // K_1..K_NK
+            static_for<NK>([&](auto jc) {
+                constexpr int jj = decltype(jc)::value + 1;
+                constexpr int sr = (s + 2 * W - jj - D) % W;
+                const cplx<T> c = kw[jj - 1][sr];
+                kw[jj][sr] = up_apply<T>(cw[sr], c, lane_prev(c), lane_next(c), kw[jj - 1][(sr + W - 1) % W],
+                                         kw[jj - 1][(sr + 1) % W]);
+            });
+            const int r = q - NK - D;
+            if (r >= rb - XH && r <= re + XH) {
+                constexpr int sr = (s + 2 * W - NK - D) % W;
+                cplx<T> k[NK + 1];
+#pragma unroll
+                for (int jj = 0; jj <= NK; ++jj) k[jj] = kw[jj][sr];
+                emit(r, std::integral_constant<int, sr>{}, k);
+            }
+        });
     }
 }
 
-// Pass 1: K_0..K_M on the tile and the Gram matrix; per-block sums to partials[blk * NG].
-// Layout of the NG doubles: G(i,i) real for i = 0..M, then G(i,j), i < j, as (re, im).
-// Two LDS buffers alternate between the stages; the interior values of every K_j
-// are kept in registers as soon as the stage has produced them.
+// Pass 1: per-wavefront Gram sums of K_0..K_M over the unit's own nodes, to
+// partials[v * gridDim.x + blockIdx.x].  Layout of the NG doubles: G(i,i) real for
+// i = 0..M, then G(i,j), i < j, as (re, im).  One wavefront per block.
 template <typename T, int M, bool X0>
-__global__ __launch_bounds__(BLOCK) void k_sstep_gram(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
-                                                      const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
-                                                      const cplx<T>* __restrict__ x0, double* __restrict__ partials) {
-    using S = SStep<M, X0>;
-    __shared__ cplx<T> bufA[S::PN], bufB[S::PN];
-    __shared__ double red[4 * S::NG];
-    __shared__ double sums[S::NG];
+__global__ __launch_bounds__(64) void k_sstep_gram(AdrGeom A, int S, const T* __restrict__ px,
+                                                   const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                                   const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
+                                                   double* __restrict__ partials) {
+    using Mc = March<M, X0, true>;
+    constexpr int NG = (M + 1) * (M + 1);
     // FP64 products: the unscaled powers M^j K_0 span many decades (|M| ~ 8/h^2)
-    double acc[S::NG];
+    double acc[NG];
 #pragma unroll
-    for (int q = 0; q < S::NG; ++q) acc[q] = 0.0;
-    const int tid = threadIdx.x + threadIdx.y * TX;
-    int t0, t1;
-    tile_chunk(A.n, t0, t1);
-    for (int t = t0; t < t1; ++t) {
-        int j0, i0;
-        sstep_tile(A.n, t, j0, i0);
-        __syncthreads();
-        // x0 staging in bufB, K_0 in bufA, then K_j alternating
-        sstep_load<T, M, X0>(A, px, py, c0, b, x0, bufB, bufA, M, i0, j0);
-        cplx<T> k[M + 1][IPT];
-        sstep_keep<T, S::PW, S::HMAX>(bufA, k[0], tid);
-        cplx<T>* src = bufA;
-        cplx<T>* dst = bufB;
+    for (int q = 0; q < NG; ++q) acc[q] = 0.0;
+    const int lane = threadIdx.x;
+    int j, rb, re;
+    cplx<T> xr[8];
+    const bool own_lane = lane >= Mc::H && lane < 64 - Mc::H;
+    NoExtra ex;
+    sstep_march<T, M, X0, true, 0>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex, [&](int r, auto, const cplx<T>(&k)[M + 1]) {
+        (void)r;
+        if (!(own_lane && j <= A.n - 1)) return;
+        double kr[M + 1], ki[M + 1];
 #pragma unroll
-        for (int j = 1; j < M; ++j) {
-            sstep_stage<T, M, X0>(A, px, py, c0, src, dst, M - j, i0, j0);
-            sstep_keep<T, S::PW, S::HMAX>(dst, k[j], tid);
-            cplx<T>* tmp = src;
-            src = dst;
-            dst = tmp;
+        for (int i = 0; i <= M; ++i) {
+            kr[i] = double(k[i].re);
+            ki[i] = double(k[i].im);
         }
+        int o = M + 1;
 #pragma unroll
-        for (int e = 0; e < IPT; ++e) {
-            const int q = tid + e * BLOCK;
-            const int ri = q / TX, rj = q - ri * TX;
-            const int gi = i0 + ri, gj = j0 + rj;
-            if (gi < 1 || gj < 1 || gi >= A.n || gj >= A.n) continue;
-            const int li = S::HMAX + ri, lj = S::HMAX + rj;
-            const size_t p = (size_t)gi * A.n + gj;
-            k[M][e] = applyM_lds<T, S::PW>(A, src, li, lj, px[p], py[p], c0[p]);
-            int o = M + 1;
+        for (int i = 0; i <= M; ++i) {
+            acc[i] = fma(ki[i], ki[i], fma(kr[i], kr[i], acc[i]));
 #pragma unroll
-            for (int i = 0; i <= M; ++i) {
-                const double ar = double(k[i][e].re), ai = double(k[i][e].im);
-                acc[i] += ar * ar + ai * ai;
-#pragma unroll
-                for (int jv = i + 1; jv <= M; ++jv) {
-                    const double br = double(k[jv][e].re), bi = double(k[jv][e].im);
-                    acc[o] += ar * br + ai * bi;
-                    acc[o + 1] += ar * bi - ai * br;
-                    o += 2;
-                }
+            for (int jv = i + 1; jv <= M; ++jv) {
+                acc[o] = fma(ki[i], ki[jv], fma(kr[i], kr[jv], acc[o]));
+                acc[o + 1] = fma(-ki[i], kr[jv], fma(kr[i], ki[jv], acc[o + 1]));
+                o += 2;
             }
         }
+    });
+#pragma unroll
+    for (int v = 0; v < NG; ++v) {
+        const double sum = wave_sum(acc[v]);
+        if (lane == 0) partials[(size_t)v * gridDim.x + blockIdx.x] = sum;
     }
-    block_sum<S::NG, 4>(acc, S::NG, red, sums);
-    store_partials(sums, S::NG, partials);
 }
 
 // Normalised Cholesky solve of the normal equations from the Gram sums (layout of
@@ -292,87 +388,203 @@ __device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sum
     }
 }
 
-// Grid reduction of the Gram partials: block v sums partials[v * nblk + b] over b
-// (fixed order) into gsum[v]; NG blocks of BLOCK threads.
-__global__ __launch_bounds__(BLOCK) void k_sstep_reduce(const double* __restrict__ partials, int nblk,
-                                                        double* __restrict__ gsum) {
+// Grid reduction of the Gram partials and the coefficient solve, in one launch of NG
+// blocks: block v sums partials[v * nblk + b] over b (fixed order) into gsum[v]; the
+// last block to arrive (ticket in K) solves the normal equations on one thread and
+// writes K->y (c_j of K_{j-1}, zero for dropped columns), K->cols, K->beta = ||K_0||
+// and K->done (1; 2 if the norm is not finite), then rearms the ticket.
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_sstep_solve(const double* __restrict__ partials, int nblk,
+                                                       double breakdown_tol, double* gsum, KrylovScal* K) {
+    constexpr int NG = (M + 1) * (M + 1);
     __shared__ double red[4];
     __shared__ double sums[1];
+    __shared__ int last;
     const int v = blockIdx.x;
     double acc[1] = {0.0};
     for (int b = threadIdx.x; b < nblk; b += BLOCK) acc[0] += partials[(size_t)v * nblk + b];
     block_sum<1, 4>(acc, 1, red, sums);
-    if (threadIdx.x == 0) gsum[v] = sums[0];
+    if (threadIdx.x == 0) {
+        gsum[v] = sums[0];
+        __threadfence();  // publish gsum[v] before arriving
+        last = atomicAdd(&K->ticket, 1u) == (unsigned)(NG - 1);
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();  // every block's gsum is visible after its arrival
+    double g[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) g[q] = gsum[q];
+    double yr[M], yi[M], beta;
+    int cols;
+    sstep_small_solve<M>(g, breakdown_tol, yr, yi, cols, beta);
+    K->beta = beta;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        K->y[2 * j] = yr[j];
+        K->y[2 * j + 1] = yi[j];
+    }
+    K->cols = cols;
+    K->done = isfinite(beta) ? 1 : 2;
+    K->ticket = 0u;
 }
 
-// Pass 2: x_out = x0 + sum_{j=1..cols} c_j K_{j-1} on the tile interior, with the
-// coefficients solved per block from the Gram sums gsum (thread 0, overlapped with
-// the other threads' tile loads); block 0 also records them in K.
-template <typename T, int M, bool X0>
-__global__ __launch_bounds__(BLOCK) void k_sstep_combine(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
-                                                         const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
-                                                         const cplx<T>* __restrict__ x0,
-                                                         const double* __restrict__ gsum, double breakdown_tol,
-                                                         KrylovScal* K, cplx<T>* __restrict__ xout) {
-    using S = SStep<M, X0>;
-    __shared__ cplx<T> bufA[S::PN], bufB[S::PN];
-    __shared__ cplx<T> cs[M];
-    int j0, i0;
-    {
-        int jj, ii;
-        tile_origin(A.n, jj, ii);
-        j0 = jj - (int)threadIdx.x;
-        i0 = ii - (int)threadIdx.y * RPT;
+// What pass 2 does with x = x0 + sum c_j K_{j-1} (X0 only for the last two): write
+// it (EPI_X); add it, re-modulated, to the level-2 iterate (EPI_MOD: u_out = u + x
+// e^{i theta}); or do that and also demodulate the next ADR right-hand side from the
+// updated iterate (EPI_MODRD: b_out = (g - A u_out) e^{-i theta}), which needs x one
+// node beyond the unit, so that variant runs with one more halo row and column.
+enum { EPI_X = 0, EPI_MOD = 1, EPI_MODRD = 2 };
+
+// Level-2 fields of the modulated epilogues.
+template <typename T>
+struct ModArgs {
+    Geom G;                   // wave geometry of level 2 (n as on the ADR level)
+    const T* theta;           // sigma k phi reduced to [-pi, pi]
+    const T* n2;              // n^2 on level 2 (EPI_MODRD)
+    const cplx<T>* g;         // level-2 right-hand side (EPI_MODRD)
+    const cplx<T>* u;         // level-2 iterate, read
+    cplx<T>* uout;            // level-2 iterate, written (may be u for EPI_MOD)
+    cplx<T>* bout;            // next ADR right-hand side (EPI_MODRD)
+};
+
+// Rows of the level-2 fields, prefetched with the Krylov rows.
+template <typename T, int EPI>
+struct ModExtra {
+    const ModArgs<T>& a;
+    int j = 0, n = 0;
+    bool colok = false;
+    T th[8];
+    cplx<T> uu[8];
+    cplx<T> gg[EPI == EPI_MODRD ? 8 : 1];
+    T nn[EPI == EPI_MODRD ? 8 : 1];
+    __device__ explicit ModExtra(const ModArgs<T>& args) : a(args) {}
+    __device__ void init(int jj, bool ok, int nl) {
+        j = jj;
+        colok = ok;
+        n = nl;
     }
-    const int tid = threadIdx.x + threadIdx.y * TX;
-    if (tid == 0) {
-        double yr[M], yi[M], beta;
-        int cols;
-        sstep_small_solve<M>(gsum, breakdown_tol, yr, yi, cols, beta);
-#pragma unroll
-        for (int j = 0; j < M; ++j) cs[j] = mk<T>(T(yr[j]), T(yi[j]));
-        if (blockIdx.x == 0) {
-            K->beta = beta;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-                K->y[2 * j] = yr[j];
-                K->y[2 * j + 1] = yi[j];
+    template <int SL>
+    __device__ void load(int r) {
+        if constexpr (EPI != EPI_X) {
+            if (r >= 1 && r <= n - 1 && colok) {
+                const int p = r * n + j;
+                th[SL] = a.theta[p];
+                uu[SL] = a.u[p];
+                if constexpr (EPI == EPI_MODRD) {
+                    gg[SL] = a.g[p];
+                    nn[SL] = a.n2[p];
+                }
+            } else {
+                th[SL] = T(0);
+                uu[SL] = cplx<T>{};
+                if constexpr (EPI == EPI_MODRD) {
+                    gg[SL] = cplx<T>{};
+                    nn[SL] = T(0);
+                }
             }
-            K->cols = cols;
-            K->done = isfinite(beta) ? 1 : 2;
         }
     }
-    // K_0 needs halo M-1 here (the loads end with a barrier, which also publishes cs)
-    sstep_load<T, M, X0>(A, px, py, c0, b, x0, bufB, bufA, M - 1, i0, j0);
-    cplx<T> k[M][IPT];
-    sstep_keep<T, S::PW, S::HMAX>(bufA, k[0], tid);
-    cplx<T>* src = bufA;
-    cplx<T>* dst = bufB;
-#pragma unroll
-    for (int j = 1; j < M; ++j) {
-        sstep_stage<T, M, X0>(A, px, py, c0, src, dst, M - 1 - j, i0, j0);
-        sstep_keep<T, S::PW, S::HMAX>(dst, k[j], tid);
-        cplx<T>* tmp = src;
-        src = dst;
-        dst = tmp;
-    }
+};
+
+// Pass 2: x = x0 + sum_{j=1..cols} c_j K_{j-1} on the unit's own nodes with the
+// coefficients of k_sstep_solve, then the epilogue EPI; also writes the zero ring
+// (row 0, column 0) of every array it writes in full.
+template <typename T, int M, bool X0, int EPI>
+__global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T* __restrict__ px,
+                                                      const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                                      const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
+                                                      const KrylovScal* __restrict__ K, cplx<T>* __restrict__ xout,
+                                                      ModArgs<T> mod) {
+    static_assert(EPI == EPI_X || X0, "the modulated epilogues follow the post-smoother");
+    constexpr int XH = EPI == EPI_MODRD ? 1 : 0;
+    using Mc = March<M, X0, false, XH>;
+    constexpr int W = Mc::W;
+    static_assert(EPI == EPI_X || Mc::EMIT_SPAN < W, "register ring too short for the epilogue");
+    const int lane = threadIdx.x;
+    const int n = A.n;
     cplx<T> c[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) c[j] = cs[j];
+    for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
+    int j, rb, re;
+    cplx<T> xr[8];
+    const bool own_lane = lane >= Mc::H && lane < 64 - Mc::H;
+    if constexpr (EPI != EPI_MOD) {
+        // the ring: column 0 of the segment's rows (strip 0), row 0 (segment 0)
+        const int ns = Mc::strips(n);
+        int u = blockIdx.x;
+        const int nb = gridDim.x;
+        if ((nb & 7) == 0) u = (u & 7) * (nb >> 3) + (u >> 3);
+        const int sg = u / ns, st = u - sg * ns;
+        const int jj = 1 + st * Mc::TXW - Mc::H + lane;
+        const int R = Mc::rows(S);
+        const int r0 = 1 + sg * R, r1 = r0 + R - 1 < n - 1 ? r0 + R - 1 : n - 1;
+        auto zero_at = [&](size_t p) {
+            if constexpr (EPI == EPI_X) {
+                xout[p] = cplx<T>{};
+            } else {
+                mod.uout[p] = cplx<T>{};
+                mod.bout[p] = cplx<T>{};
+            }
+        };
+        if (jj == 0)
+            for (int r = r0; r <= r1; ++r) zero_at((size_t)r * n);
+        if (sg == 0 && ((own_lane && jj <= n - 1) || jj == 0)) zero_at((size_t)jj);
+    }
+    auto xval = [&](auto slot, const cplx<T>(&k)[M]) {
+        constexpr int sr = decltype(slot)::value;
+        cplx<T> v = X0 ? xr[sr] : cplx<T>{};
 #pragma unroll
-    for (int e = 0; e < IPT; ++e) {
-        const int q = tid + e * BLOCK;
-        const int ri = q / TX, rj = q - ri * TX;
-        const int gi = i0 + ri, gj = j0 + rj;
-        if (gi >= A.n || gj >= A.n) continue;
-        const size_t p = (size_t)gi * A.n + gj;
-        cplx<T> v{};
-        if (gi >= 1 && gj >= 1) {
-            v = X0 ? x0[p] : cplx<T>{};
-#pragma unroll
-            for (int j = 0; j < M; ++j) v = v + c[j] * k[j][e];
-        }
-        xout[p] = v;
+        for (int q = 0; q < M; ++q) v = v + c[q] * k[q];
+        return v;
+    };
+    if constexpr (EPI == EPI_X) {
+        NoExtra ex;
+        sstep_march<T, M, X0, false, 0>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
+                                        [&](int r, auto slot, const cplx<T>(&k)[M]) {
+                                            const cplx<T> v = xval(slot, k);
+                                            if (own_lane && j <= n - 1) xout[(size_t)r * n + j] = v;
+                                        });
+    } else if constexpr (EPI == EPI_MOD) {
+        ModExtra<T, EPI> ex(mod);
+        sstep_march<T, M, X0, false, 0>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
+                                        [&](int r, auto slot, const cplx<T>(&k)[M]) {
+                                            constexpr int sr = decltype(slot)::value;
+                                            const cplx<T> v = xval(slot, k);
+                                            T sn, cs;
+                                            sincos_t(ex.th[sr], &sn, &cs);
+                                            if (own_lane && j <= n - 1)
+                                                mod.uout[(size_t)r * n + j] = ex.uu[sr] + v * mk<T>(cs, sn);
+                                        });
+    } else {
+        ModExtra<T, EPI> ex(mod);
+        cplx<T> un[W], car[W];  // updated iterate and carrier e^{i theta} of the emitted rows
+        const Geom& G = mod.G;
+        const T ih2 = T(G.inv_h2);
+        sstep_march<T, M, X0, false, 1>(
+            A, S, px, py, c0, b, x0, j, rb, re, xr, ex, [&](int r, auto slot, const cplx<T>(&k)[M]) {
+                constexpr int sr = decltype(slot)::value;
+                constexpr int s1 = (sr + W - 1) % W, s2 = (sr + W - 2) % W;
+                const cplx<T> v = xval(slot, k);
+                T sn, cs;
+                sincos_t(ex.th[sr], &sn, &cs);
+                car[sr] = mk<T>(cs, sn);
+                un[sr] = ex.uu[sr] + v * car[sr];
+                const int ri = r - 1;
+                if (ri >= rb && ri <= re) {
+                    const cplx<T> cu = un[s1];
+                    const cplx<T> w = lane_prev(cu), e = lane_next(cu);
+                    const cplx<T> nb = ((un[s2] + un[sr]) + w) + e;
+                    const cplx<T> lap = ih2 * (T(4) * cu - nb);
+                    const cplx<T> kap = kappa_at<T>(G, ex.nn[s1], ri, j);
+                    const cplx<T> res = ex.gg[s1] - (lap - kap * cu);
+                    if (own_lane && j <= n - 1) {
+                        const size_t p = (size_t)ri * n + j;
+                        mod.bout[p] = res * conjg(car[s1]);
+                        mod.uout[p] = cu;
+                    }
+                }
+            });
     }
 }
 

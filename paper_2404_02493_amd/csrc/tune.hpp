@@ -1,10 +1,11 @@
 // Autotuner of launch shapes, measured on the context's own hierarchy.
 //
-// Knobs (each changes only how a reduction is split over blocks, hence only the
-// summation order of FP64 partial sums):
-//   sstep_blocks[l]  blocks of the s-step GMRES Gram pass on ADR level l: fewer
-//                    blocks shorten the one-block solve that sums their partials,
-//                    more blocks expose more parallelism in the Gram pass;
+// Knobs (each changes only how the work and the FP64 partial sums of a reduction are
+// split, hence only the summation order of those sums):
+//   sstep_rows[l]    steps per marching unit of the s-step GMRES passes on ADR
+//                    level l (rows of the unit plus its warm-up rows): longer units
+//                    recompute fewer warm-up rows and leave fewer partials to sum,
+//                    shorter ones give more wavefronts;
 //   fgmres_blocks    blocks of the outer FGMRES passes on the fine grid.
 // Every candidate runs the real kernels on the level's buffers filled with
 // hashed data; the fastest (HIP-event time over a few repetitions) is kept.  The
@@ -35,7 +36,7 @@ __global__ void k_tune_kstate(KrylovScal* K) {
     if (threadIdx.x != 0) return;
     K->done = 0;
     K->beta = 1.0;
-    for (int i = 0; i <= MAXM; ++i) K->scale[i] = 1.0;
+    for (int i = 0; i <= MAXM; ++i) K->scale[i] = K->zscale[i] = 1.0;
     for (int i = 0; i < 2 * (MAXM + 2); ++i) K->dots[i] = 0.0;
 }
 
@@ -58,11 +59,11 @@ static double time_ms(hipStream_t st, int reps, F&& f) {
 
 static std::string tuning_json(helm_ctx c, const std::string& timings) {
     std::string out = "{\"n\": " + std::to_string(c->d.n) + ", \"levels\": " + std::to_string(c->L) +
-                      ", \"prec\": \"" + (c->f32 ? "c64" : "c128") + "\", \"sstep_blocks\": {";
+                      ", \"prec\": \"" + (c->f32 ? "c64" : "c128") + "\", \"sstep_rows\": {";
     bool first = true;
     for (int l = 2; l <= c->LA && l < 16; ++l) {
-        if (c->tn.sstep_blocks[l] <= 0) continue;
-        out += std::string(first ? "" : ", ") + "\"" + std::to_string(l) + "\": " + std::to_string(c->tn.sstep_blocks[l]);
+        if (c->tn.sstep_rows[l] <= 0) continue;
+        out += std::string(first ? "" : ", ") + "\"" + std::to_string(l) + "\": " + std::to_string(c->tn.sstep_rows[l]);
         first = false;
     }
     out += "}, \"fgmres_blocks\": " + std::to_string(c->tn.fgmres_blocks);
@@ -93,9 +94,9 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
             HIPCHK(hipGetLastError());
             int best = 0;
             double tbest = 1e30;
-            for (int cand = 64; cand <= MAXRED; cand *= 2) {
-                if (cand > red_blocks(A.n)) break;
-                c->tn.sstep_blocks[l] = cand;
+            for (int cand : {16, 24, 32, 40, 48, 64, 80, 96, 128}) {
+                if (cand > 16 && cand >= 2 * A.n) break;
+                c->tn.sstep_rows[l] = cand;
                 const double t = time_ms(st, reps, [&] {
                     E.gmres(l, m, true);
                     E.gmres(l, m, false);
@@ -106,7 +107,7 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
                     best = cand;
                 }
             }
-            c->tn.sstep_blocks[l] = best;
+            c->tn.sstep_rows[l] = best;
         }
     }
     // outer FGMRES passes on the fine grid (basis of the inner solver for complex64
@@ -132,13 +133,14 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
         double tbest = 1e30;
         for (int cand = 256; cand <= MAXRED; cand *= 2) {
             const double t = time_ms(st, reps, [&] {
-                hipLaunchKernelGGL((k_arnoldi_helm_ws<T, MAXM>), dim3(cand), dim3(BLOCK), 0, st, G, (const T*)n2,
-                                   (const cplx<T>*)Zp[0], 0, Vs, jj, (cplx<T>*)Vp[jj + 1], (const KrylovScal*)c->Kin,
-                                   c->partials);
-                hipLaunchKernelGGL((k_orth_pass1_ws<T, MAXM>), dim3(cand), dim3(BLOCK), 0, st, NF, Vs, jj,
-                                   (cplx<T>*)Vp[jj + 1], (const KrylovScal*)c->Kin, c->partials);
-                hipLaunchKernelGGL((k_orth_pass2<T, MAXM>), dim3(cand), dim3(BLOCK), 0, st, NF, Vs, jj,
-                                   (cplx<T>*)Vp[jj + 1], (const KrylovScal*)c->Kin, c->partials);
+                static_for_host<MAXM>(jj, [&](auto jc) {
+                    constexpr int J = decltype(jc)::value;
+                    hipLaunchKernelGGL((k_fg_arnoldi<T, J>), dim3(cand), dim3(BLOCK), 0, st, G, (const T*)n2,
+                                       (const cplx<T>*)Zp[0], 0, Vs, (cplx<T>*)Vp[J], (cplx<T>*)Vp[J + 1],
+                                       (const KrylovScal*)c->Kin, c->partials);
+                    hipLaunchKernelGGL((k_fg_orth<T, J>), dim3(cand), dim3(BLOCK), 0, st, NF, Vs,
+                                       (cplx<T>*)Vp[J + 1], (const KrylovScal*)c->Kin, c->partials);
+                });
             });
             HIPCHK(hipGetLastError());
             note("fgmres_" + std::to_string(cand), t);
@@ -154,7 +156,7 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
     return tuning_json(c, tim);
 }
 
-// Applies {"sstep_blocks": {"l": blocks, ...}, "fgmres_blocks": blocks} (other keys ignored).
+// Applies {"sstep_rows": {"l": rows, ...}, "fgmres_blocks": blocks} (other keys ignored).
 static void apply_tuning(helm_ctx c, const char* json) {
     const std::string s(json);
     helm_ctx_s::Tuning t = c->tn;
@@ -169,15 +171,15 @@ static void apply_tuning(helm_ctx c, const char* json) {
         i += used;
         return v;
     };
-    size_t k = s.find("\"sstep_blocks\"");
+    size_t k = s.find("\"sstep_rows\"");
     if (k != std::string::npos) {
         size_t i = s.find('{', k);
-        REQUIRE(i != std::string::npos, "tuning: sstep_blocks must be an object");
+        REQUIRE(i != std::string::npos, "tuning: sstep_rows must be an object");
         ++i;
-        for (int l = 0; l < 16; ++l) t.sstep_blocks[l] = 0;
+        for (int l = 0; l < 16; ++l) t.sstep_rows[l] = 0;
         for (;;) {
             skip_ws(i);
-            REQUIRE(i < s.size(), "tuning: unterminated sstep_blocks");
+            REQUIRE(i < s.size(), "tuning: unterminated sstep_rows");
             if (s[i] == '}') break;
             if (s[i] == ',') {
                 ++i;
@@ -193,8 +195,8 @@ static void apply_tuning(helm_ctx c, const char* json) {
             ++i;
             const long v = read_int(i);
             REQUIRE(l >= 2 && l <= c->LA && l < 16, "tuning: level out of range");
-            REQUIRE(v >= 0 && v <= MAXRED, "tuning: block count out of range");
-            t.sstep_blocks[l] = (int)v;
+            REQUIRE(v == 0 || (v >= 16 && v <= 256 && v % 8 == 0), "tuning: unit steps out of range");
+            t.sstep_rows[l] = (int)v;
         }
     }
     k = s.find("\"fgmres_blocks\"");

@@ -1,6 +1,7 @@
 """Measured memory traffic of one kernel from rocprofv3 counter runs.
 
-FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc run each) are
+FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc run each; a kernel name
+without template arguments matches every instantiation) are
 scaled by what the same counters read for a plain copy kernel of known size
 (bench.py --copy-probe: 128 MiB read and 128 MiB written per dispatch), then
 stored with a hash of the kernel sources.  bench.py reports the stored figure
@@ -21,6 +22,19 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["common.hpp", "reduce.hpp", "kernels_wave.hpp", "kernels_adr.hpp", "kernels_krylov.hpp",
            "kernels_sstep.hpp"]
+
+
+def find(profiles_dir: str, profile_key: str) -> float | None:
+    """Measured bytes per dispatch from any traffic_*.json record in profiles_dir for the
+    kernel profiled under profile_key (current sources only), else None."""
+    if not os.path.isdir(profiles_dir):
+        return None
+    for name in sorted(os.listdir(profiles_dir)):
+        if name.startswith("traffic_") and name.endswith(".json"):
+            v = load(os.path.join(profiles_dir, name), profile_key)
+            if v is not None:
+                return v
+    return None
 COPY_BYTES = 4096 * 4096 * 8  # bench.py --copy-probe: complex64 4096^2, read once and written once
 
 
@@ -39,7 +53,9 @@ def _per_dispatch(run_dir: str, counter: str, kernel: str, grid: int | None = No
             if r["Counter_Name"] != counter:
                 continue
             name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("helm::", "")
-            if name != kernel or (grid is not None and int(r["Grid_Size"]) != grid):
+            if name != kernel and name.split("<")[0] != kernel:
+                continue
+            if grid is not None and int(r["Grid_Size"]) != grid:
                 continue
             vals.append(float(r["Counter_Value"]))
     if not vals:
@@ -86,7 +102,7 @@ def main():
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--kernel", required=True)
-    ap.add_argument("--grid", type=int, required=True)
+    ap.add_argument("--grid", type=int, default=None, help="grid size in work-items (all grids if omitted)")
     ap.add_argument("--profile-key", required=True)
     ap.add_argument("--workload", default="layered4096 FP32+refinement solve")
     ap.add_argument("--algorithmic-bytes", type=float, default=None)

@@ -28,9 +28,9 @@ def test_tuned_cycle_keeps_parity(prec, tol, tmp_path):
     res = H.tune(cache=cache)
     print(json.dumps(res), flush=True)
     assert res["fgmres_blocks"] in (256, 512, 1024, 2048)
-    for l, nb in res["sstep_blocks"].items():
-        assert 2 <= int(l) <= c.levels and 64 <= nb <= 2048
-    assert H.get_tuning()["sstep_blocks"] == res["sstep_blocks"]
+    for l, rows in res["sstep_rows"].items():
+        assert 2 <= int(l) <= c.levels and rows in (16, 24, 32, 40, 48, 64, 80, 96, 128)
+    assert H.get_tuning()["sstep_rows"] == res["sstep_rows"]
     rng = np.random.default_rng(1)
     u0 = rng.standard_normal((256, 256)) + 1j * rng.standard_normal((256, 256))
     u0[0, :] = 0
@@ -60,11 +60,12 @@ def test_set_tuning_rejects_bad_input():
     c = hi.make_problem(128, 80.0, 4, seed=1, medium="const", phase="analytic", damping_cells=16)
     H = Helmholtz(c.velocity, c.k, levels=c.levels, damping_cells=16)
     before = H.get_tuning()
-    for bad in ['{"sstep_blocks": {"9": 64}}', '{"fgmres_blocks": 99999}', '{"sstep_blocks": {"2": x}}']:
+    for bad in ['{"sstep_rows": {"9": 16}}', '{"fgmres_blocks": 99999}', '{"sstep_rows": {"2": x}}',
+                '{"sstep_rows": {"2": 8}}', '{"sstep_rows": {"2": 36}}']:
         with pytest.raises(HelmError):
             H.set_tuning(bad)
         assert H.get_tuning() == before
-    H.set_tuning('{"sstep_blocks": {"2": 128}, "fgmres_blocks": 512}')
+    H.set_tuning('{"sstep_rows": {"2": 32}, "fgmres_blocks": 512}')
     t = H.get_tuning()
-    assert t["sstep_blocks"] == {"2": 128} and t["fgmres_blocks"] == 512
+    assert t["sstep_rows"] == {"2": 32} and t["fgmres_blocks"] == 512
     H.close()
