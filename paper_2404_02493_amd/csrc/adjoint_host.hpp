@@ -199,10 +199,10 @@ struct AdjEngine {
         WaveLevel& W = c->wl[2];
         AdrTape& Tp = S.adr[s][2];
         LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st,
-               W.G, (const T*)W.n2, (const C*)S.g[2], (const C*)W.u, (const T*)c->theta2, (C*)Tp.b);
+               W.G, (const T*)W.n2, (const C*)S.g[2], (const C*)W.u, (const C*)c->car2, (C*)Tp.b);
         rec_adrv(s, 2);
         LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
-               (const C*)Tp.xo, (const T*)c->theta2, (C*)W.u);
+               (const C*)Tp.xo, (const C*)c->car2, (C*)W.u);
     }
 
     void rec_adrv(int s, int l) {
@@ -363,10 +363,10 @@ struct AdjEngine {
         AdrTape& Tp = S.adr[s][2];
         const size_t n = N(2);
         LAUNCH(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_modadd_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
-               (const C*)S.lub[2], (const C*)Tp.xo, (const T*)c->theta2, (C*)S.axb[2], S.thb);
+               (const C*)S.lub[2], (const C*)Tp.xo, (const C*)c->car2, (C*)S.axb[2], S.thb);
         rev_adrv(s, 2);
         LAUNCH(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_demod_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
-               (const C*)S.abb[2], (const C*)Tp.b, (const T*)c->theta2, (C*)S.rbar2, S.thb);
+               (const C*)S.abb[2], (const C*)Tp.b, (const C*)c->car2, (C*)S.rbar2, S.thb);
         LAUNCH(c, (5.0 * sizeof(C) + sizeof(T)) * n, (k_adj_ahsub<T>), dim3(fb(n)), dim3(BLOCK), st, W.G,
                (const T*)W.n2, (const C*)S.rbar2, (C*)S.lub[2], (C*)S.lgb[2]);
     }

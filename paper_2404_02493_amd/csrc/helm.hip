@@ -87,7 +87,7 @@ struct helm_ctx_s {
     double* n2f = nullptr;  // fine n^2 (FP64)
     std::vector<helm::WaveLevel> wl;
     std::vector<helm::AdrLevel> al;
-    void* theta2 = nullptr;  // reduced carrier phase on level 2 (cycle precision)
+    void* car2 = nullptr;    // carrier e^{i sigma k phi} on level 2 (cycle precision)
     bool phase_set = false;
     std::vector<double> w, w_default;
     void* ws1 = nullptr;     // second level-1 iterate (cycle precision)
@@ -458,7 +458,7 @@ struct Engine {
         WaveLevel& W = c->wl[2];
         ModArgs<T> a{};
         a.G = W.G;
-        a.theta = (const T*)c->theta2;
+        a.car = (const C*)c->car2;
         a.n2 = (const T*)W.n2;
         a.g = (const C*)W.g;
         a.u = (const C*)W.u;
@@ -475,11 +475,11 @@ struct Engine {
         for (int s = 0; s < M; ++s) {
             if (s == 0 || !fused)
                 LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(),
-                       st, W.G, (const T*)W.n2, (const C*)W.g, (const C*)W.u, (const T*)c->theta2, (C*)A.b);
+                       st, W.G, (const T*)W.n2, (const C*)W.g, (const C*)W.u, (const C*)c->car2, (C*)A.b);
             if (!fused) {
                 adr_vcycle(2);
                 LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))),
-                       dim3(BLOCK), st, N(2), (const C*)A.x, (const T*)c->theta2, (C*)W.u);
+                       dim3(BLOCK), st, N(2), (const C*)A.x, (const C*)c->car2, (C*)W.u);
                 continue;
             }
             if (s + 1 < M) {
@@ -530,8 +530,8 @@ struct Engine {
                            (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
                            (C*)c->al[l + 1].b);
         adr_vcycle(l + 1);
-        LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), st, A.n,
-                           (const C*)c->al[l + 1].x, (C*)A.x);
+        LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)),
+               tile_block(), st, A.n, (const C*)c->al[l + 1].x, (C*)A.x);
         gmres(l, c->d.gmres_m, false, epi, ma);
     }
 
@@ -605,24 +605,25 @@ struct Engine {
         }
         const int ng = March<MM, true, true>::units(A.n, S);
         REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many segments for the reduction scratch");
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_gram<T, MM, true>), dim3(ng), dim3(64), st, A.A,
-               S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x, c->partials);
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_gram<T, MM, true>), dim3(ng), dim3(64), st,
+               A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
+               c->partials);
         LAUNCH(c, 8.0 * NG * ng, (k_sstep_solve<MM>), dim3(NG), dim3(BLOCK), st, (const double*)c->partials, ng, tolb,
                gsum, A.K);
         if (epi == EPI_X) {
             const int nc = March<MM, true, false>::units(A.n, S);
-            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_X>), dim3(nc), dim3(64),
-                   st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
+            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_X>), dim3(nc),
+                   dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
                    (const KrylovScal*)A.K, (C*)A.xalt, none);
             std::swap(A.x, A.xalt);
         } else if (epi == EPI_MOD) {
             const int nc = March<MM, true, false>::units(A.n, S);
-            LAUNCH(c, (5 * sizeof(C) + 3 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MOD>), dim3(nc),
+            LAUNCH(c, (6 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MOD>), dim3(nc),
                    dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                    (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
         } else if constexpr (MM <= 3) {
             const int nc = March<MM, true, false, 1>::units(A.n, S);
-            LAUNCH(c, (7 * sizeof(C) + 4 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MODRD>), dim3(nc),
+            LAUNCH(c, (9 * sizeof(C) + 3 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MODRD>), dim3(nc),
                    dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                    (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
         } else {
@@ -632,10 +633,11 @@ struct Engine {
 
     // GMRES(m) smoother on ADR level l (x = A.x, b = A.b); epi != EPI_X (s-step form,
     // x0 != 0 only) hands the result to that epilogue instead of A.x.
+    bool sstep_form(int m) const { return m <= 4 && !c->d.gmres_arnoldi; }
     void gmres(int l, int m, bool x0_zero, int epi = EPI_X, const ModArgs<T>* ma = nullptr) {
         // one workgroup on the coarsest level, s-step form on the larger ones
         if (l == c->LA && gmres_block(l, m, x0_zero)) return;
-        if (m <= 4 && !c->d.gmres_arnoldi) {
+        if (sstep_form(m)) {
             switch (m) {
                 case 1: gmres_sstep<1>(l, x0_zero, epi, ma); break;
                 case 2: gmres_sstep<2>(l, x0_zero, epi, ma); break;
@@ -724,7 +726,7 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
         prec(j, K->zscale + j);  // Z[j] = preconditioned V[j] (scaled by zscale[j] if !z_scaled)
         static_for_host<MAXM>(j, [&](auto jc) {
             constexpr int J = decltype(jc)::value;
-            LAUNCH(c, ((2 * J + 4) * sizeof(Cp) + sizeof(P)) * double(N), (k_fg_arnoldi<P, J>), dim3(nbf),
+            LAUNCH(c, ((J + (J > 0 ? 4 : 3)) * sizeof(Cp) + sizeof(P)) * double(N), (k_fg_arnoldi<P, J>), dim3(nbf),
                    dim3(BLOCK), st, G, (const P*)n2_fine, (const Cp*)Z[J], z_scaled ? 0 : 1, Vs, (Cp*)V[J],
                    (Cp*)V[J + 1], (const KrylovScal*)K, c->partials);
             krylov_fin<MAXM>(c, st, nbf, FIN_LMV, J, m, K, 0.0);
@@ -936,7 +938,7 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
             if (l == 2) A.balt = dalloc(c, Nl * csize(f64c));
         }
         c->wl[2].ualt = dalloc(c, (size_t)c->wl[2].n * c->wl[2].n * csize(c->wl[2].f64));
-        c->theta2 = dalloc(c, (size_t)(n / 2) * (n / 2) * rsize(f64c));
+        c->car2 = dalloc(c, (size_t)(n / 2) * (n / 2) * csize(f64c));
     }
     // FP64 residual vectors; the Krylov bases of the outer solvers are allocated by
     // the first solve in each mode (ensure_solver_ws)
@@ -955,26 +957,26 @@ static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
         AdrLevel& A = c->al[l];
         const Geom G = make_geom(c, l);
         const size_t Nl = (size_t)A.n * A.n;
-        void* th = (l == 2) ? c->theta2 : nullptr;
+        void* th = (l == 2) ? c->car2 : nullptr;
         const int nb = flat_blocks(Nl);
         if (c->f32) {
             if (is64)
                 hipLaunchKernelGGL((k_adr_coef<float, double>), dim3(nb), dim3(BLOCK), 0, st, G, (const double*)c->n2f,
                                    (const double*)phi, c->d.k, c->d.sign, c->d.damping_strength, (float*)A.px,
-                                   (float*)A.py, (c64*)A.c0, (float*)th);
+                                   (float*)A.py, (c64*)A.c0, (c64*)th);
             else
                 hipLaunchKernelGGL((k_adr_coef<float, float>), dim3(nb), dim3(BLOCK), 0, st, G, (const double*)c->n2f,
                                    (const float*)phi, c->d.k, c->d.sign, c->d.damping_strength, (float*)A.px,
-                                   (float*)A.py, (c64*)A.c0, (float*)th);
+                                   (float*)A.py, (c64*)A.c0, (c64*)th);
         } else {
             if (is64)
                 hipLaunchKernelGGL((k_adr_coef<double, double>), dim3(nb), dim3(BLOCK), 0, st, G,
                                    (const double*)c->n2f, (const double*)phi, c->d.k, c->d.sign,
-                                   c->d.damping_strength, (double*)A.px, (double*)A.py, (c128*)A.c0, (double*)th);
+                                   c->d.damping_strength, (double*)A.px, (double*)A.py, (c128*)A.c0, (c128*)th);
             else
                 hipLaunchKernelGGL((k_adr_coef<double, float>), dim3(nb), dim3(BLOCK), 0, st, G,
                                    (const double*)c->n2f, (const float*)phi, c->d.k, c->d.sign,
-                                   c->d.damping_strength, (double*)A.px, (double*)A.py, (c128*)A.c0, (double*)th);
+                                   c->d.damping_strength, (double*)A.px, (double*)A.py, (c128*)A.c0, (c128*)th);
         }
     }
     HIPCHK(hipGetLastError());

@@ -252,16 +252,14 @@ __global__ __launch_bounds__(BLOCK) void k_dot_ah(Geom G, const T* __restrict__ 
 
 // ------------------------------------------------------------------ ADR correction (level 2)
 
-// Reverse of u' = u + a e^{i theta}:  abar = e^{-i theta} ubar',
+// Reverse of u' = u + a e^{i theta} (car = e^{i theta}):  abar = e^{-i theta} ubar',
 // thbar += Re <ubar', i a e^{i theta}> = -Im(conj(ubar') a e^{i theta}).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* __restrict__ ub, const cplx<T>* __restrict__ a,
-                                                      const T* __restrict__ theta, cplx<T>* __restrict__ abar,
+                                                      const cplx<T>* __restrict__ car, cplx<T>* __restrict__ abar,
                                                       double* __restrict__ thbar) {
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        T sn, cs;
-        sincos_t(theta[p], &sn, &cs);
-        const cplx<T> e = mk<T>(cs, sn);
+        const cplx<T> e = car[p];
         const cplx<T> y = ub[p];
         abar[p] = conjg(e) * y;
         const cplx<T> ae = a[p] * e;
@@ -270,15 +268,14 @@ __global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* _
     }
 }
 
-// Reverse of b = r e^{-i theta}:  rbar = e^{i theta} bbar,  thbar += Im(conj(bbar) b).
+// Reverse of b = r e^{-i theta} (car = e^{i theta}):  rbar = e^{i theta} bbar,
+// thbar += Im(conj(bbar) b).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_demod_adj(size_t N, const cplx<T>* __restrict__ bbar, const cplx<T>* __restrict__ b,
-                                                     const T* __restrict__ theta, cplx<T>* __restrict__ rbar,
+                                                     const cplx<T>* __restrict__ car, cplx<T>* __restrict__ rbar,
                                                      double* __restrict__ thbar) {
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        T sn, cs;
-        sincos_t(theta[p], &sn, &cs);
-        const cplx<T> e = mk<T>(cs, sn);
+        const cplx<T> e = car[p];
         const cplx<T> y = bbar[p], bv = b[p];
         rbar[p] = e * y;
         thbar[p] += double(y.re) * double(bv.im) - double(y.im) * double(bv.re);

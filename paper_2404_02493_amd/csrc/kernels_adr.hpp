@@ -18,26 +18,29 @@ struct AdrGeom {
 // fine phase by injection (stride s); second-order central differences inside,
 // first-order one-sided ones at the last unknown (the node x = 1 is not stored).
 //   c0 = -i sigma k Lap(phi) + k^2 (phi_x^2 + phi_y^2 - n2) - i sigma k^2 n2 delta
-// theta (level 2 only, may be null): sigma k phi reduced to [-pi, pi] in FP64.
+// car (level 2 only, may be null): the carrier e^{i sigma k phi}, from the phase reduced
+// to [-pi, pi] and its sine and cosine, all in FP64.
 template <typename T, typename TP>
 __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __restrict__ n2f,
                                                     const TP* __restrict__ phi, double k, int sigma, double strength,
                                                     T* __restrict__ px_out, T* __restrict__ py_out,
-                                                    cplx<T>* __restrict__ c0_out, T* __restrict__ theta_out) {
+                                                    cplx<T>* __restrict__ c0_out, cplx<T>* __restrict__ car_out) {
     const int n = G.n, s = G.s, nf = G.nf;
     const size_t N = (size_t)n * n;
     const double h = 1.0 / n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         const int i = (int)(p / n), j = (int)(p % n);
         auto P = [&](int a, int b) -> double { return double(phi[(size_t)a * s * nf + (size_t)b * s]); };
-        if (theta_out) {
+        if (car_out) {
             // Cody-Waite reduction with a two-part 2 pi
             const double P1 = 6.283185307179586, P2 = 2.4492935982947064e-16;
             double a = double(sigma) * k * P(i, j);
             double q = rint(a / P1);
             double t = fma(-q, P1, a);
             t = fma(-q, P2, t);
-            theta_out[p] = T(t);
+            double sn, cs;
+            sincos(t, &sn, &cs);
+            car_out[p] = mk<T>(T(cs), T(sn));
         }
         if (i == 0 || j == 0) {
             px_out[p] = T(0);
@@ -139,10 +142,10 @@ __global__ __launch_bounds__(BLOCK) void k_adr_resid_restrict(AdrGeom A, const T
     restrict_tile<T, T>(A.n, AdrRes<T>{A, px, py, c0, b, x}, rc);
 }
 
-// r_hat = (g - A u) e^{-i theta}
+// r_hat = (g - A u) e^{-i theta}   (car = e^{i theta})
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_demod(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
-                                                     const cplx<T>* __restrict__ u, const T* __restrict__ theta,
+                                                     const cplx<T>* __restrict__ u, const cplx<T>* __restrict__ car,
                                                      cplx<T>* __restrict__ rhat) {
     int j, i0;
     tile_origin(G.n, j, i0);
@@ -154,23 +157,18 @@ __global__ __launch_bounds__(BLOCK) void k_adr_demod(Geom G, const T* __restrict
         const size_t p = (size_t)i * G.n + j;
         if (i > 0 && j > 0) {
             cplx<T> r = resid_at(G, n2, g, u, i, j);
-            T sn, cs;
-            sincos_t(theta[p], &sn, &cs);
-            v = r * mk<T>(cs, -sn);
+            v = r * conjg(car[p]);
         }
         rhat[p] = v;
     }
 }
 
-// u += a e^{+i theta}
+// u += a e^{+i theta}   (car = e^{i theta})
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_adr_modadd(size_t N, const cplx<T>* __restrict__ a, const T* __restrict__ theta,
-                                                      cplx<T>* __restrict__ u) {
-    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        T sn, cs;
-        sincos_t(theta[p], &sn, &cs);
-        u[p] = u[p] + a[p] * mk<T>(cs, sn);
-    }
+__global__ __launch_bounds__(BLOCK) void k_adr_modadd(size_t N, const cplx<T>* __restrict__ a,
+                                                      const cplx<T>* __restrict__ car, cplx<T>* __restrict__ u) {
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK)
+        u[p] = u[p] + a[p] * car[p];
 }
 
 }  // namespace helm

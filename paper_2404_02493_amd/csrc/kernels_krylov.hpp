@@ -305,8 +305,7 @@ __device__ __forceinline__ void fg_store(const A (&acc)[K], double* partials) {
 //          left by FIN_LORTH; nothing to do for J = 0),
 //   w = A (s z),  s = zscale[J] if use_scale else 1,
 // with partial sums of conj(V_i) w, i <= J (V_J the corrected vector), and of
-// ||V_J||^2 (finalize with FIN_LMV).  The inner products with V_i, i < J, are taken
-// as each vector streams past, so no basis value is kept.
+// ||V_J||^2 (finalize with FIN_LMV).
 template <typename T, int J>
 __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restrict__ n2,
                                                       const cplx<T>* __restrict__ z, int use_scale, VecSet<T> V,
@@ -326,6 +325,10 @@ __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restric
     for (int q = 0; q < NA; ++q) acc[q] = T(0);
     for (size_t p = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * E; p < N; p += (size_t)gridDim.x * BLOCK * E) {
         const int i = (int)(p / n), j0 = (int)(p - (size_t)i * n);
+        // every basis load is issued before the stencil, so they are all in flight at once
+        cplx<T> vv[J + 1][E];
+#pragma unroll
+        for (int iv = 0; iv <= J; ++iv) ld_pack<T, E>(V.v[iv], p, vv[iv]);
         cplx<T> x[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -338,17 +341,15 @@ __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restric
         for (int e = 0; e < E; ++e) corr[e] = cplx<T>{};
 #pragma unroll
         for (int iv = 0; iv < J; ++iv) {
-            cplx<T> v[E];
-            ld_pack<T, E>(V.v[iv], p, v);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                acc[2 * iv] += v[e].re * x[e].re + v[e].im * x[e].im;
-                acc[2 * iv + 1] += v[e].re * x[e].im - v[e].im * x[e].re;
-                corr[e] = corr[e] + cs[iv] * v[e];
+                const cplx<T> v = vv[iv][e];
+                acc[2 * iv] += v.re * x[e].re + v.im * x[e].im;
+                acc[2 * iv + 1] += v.re * x[e].im - v.im * x[e].re;
+                corr[e] = corr[e] + cs[iv] * v;
             }
         }
-        cplx<T> v[E];
-        ld_pack<T, E>(V.v[J], p, v);
+        cplx<T> (&v)[E] = vv[J];
         if constexpr (J > 0) {
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = v[e] - corr[e];

@@ -110,7 +110,7 @@ __device__ __forceinline__ cplx<T> up_apply(const UpCoef<T>& k, cplx<T> c, cplx<
 
 // Strip/segment geometry of the marching passes.  GRAM: the pass builds K_0..K_M
 // (else K_0..K_{M-1}).
-template <int M, bool X0, bool GRAM, int XH = 0>
+template <int M, bool X0, bool GRAM, int XH = 0, int EP = -1>
 struct March {
     static constexpr int D = X0 ? 1 : 0;
     static constexpr int NK = GRAM ? M : M - 1;  // last Krylov vector built
@@ -118,14 +118,15 @@ struct March {
                                                  // columns beyond its own that a unit emits)
     static constexpr int TXW = 64 - 2 * H;       // columns owned by one strip
     static constexpr int W = 8;                  // rows kept per field (ring of registers)
-    static constexpr int P = 3;                  // rows loaded ahead of the row they feed
-    // steps after its own step that a loaded row is still read: x0 by K_0 of the next
-    // row (and by the combination NK + D rows later), b by K_0
-    static constexpr int LAST = X0 ? (GRAM ? 2 : (NK + D > 2 ? NK + D : 2)) : 1;
-    static_assert(P + LAST < W, "register ring too short for the prefetch");
-    // steps from the prefetch of a row to its emit (an epilogue's fields of the row
-    // are read there, and by the emit of the next row when XH > 0)
-    static constexpr int EMIT_SPAN = P + NK + D + (XH > 0 ? 1 : 0);
+    // Steps after its own step that a loaded row is still read: x0 by K_0 of the next
+    // row (and by the combination NK + D rows later), b by K_0, and the fields an
+    // epilogue loads with the row by the emit of that row (EP = 0) or of the next one
+    // (EP = 1; EP < 0: no such fields).  Rows are loaded as far ahead as the ring of W
+    // registers allows.
+    static constexpr int LAST0 = X0 ? (GRAM ? 2 : (NK + D > 2 ? NK + D : 2)) : 1;
+    static constexpr int LAST = EP >= 0 && NK + D + EP > LAST0 ? NK + D + EP : LAST0;
+    static constexpr int P = W - 1 - LAST;       // rows loaded ahead of the row they feed
+    static_assert(P >= 1, "register ring too short for the halo");
     // A unit marches S steps (S a multiple of W) over a segment of S - 2H rows.
     __host__ __device__ static int rows(int S) { return S - 2 * H; }
     __host__ __device__ static int strips(int n) { return (n - 2) / TXW + 1; }
@@ -144,13 +145,13 @@ struct NoExtra {
 // behind it; the finished row r = q - NK - D is handed to emit(r, slot, k) (k[j] =
 // K_j on row r; slot: the std::integral_constant ring position of row r) for the
 // unit's rows and XH rows beyond them on either side.
-template <typename T, int M, bool X0, bool GRAM, int XH, typename Extra, typename Emit>
+template <typename T, int M, bool X0, bool GRAM, int XH, int EP, typename Extra, typename Emit>
 __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __restrict__ px,
                                             const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                             const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
                                             int& jcol, int& rb, int& re, cplx<T> (&xr)[8], Extra& ex,
                                             Emit&& emit) {
-    using Mc = March<M, X0, GRAM, XH>;
+    using Mc = March<M, X0, GRAM, XH, EP>;
     constexpr int H = Mc::H, D = Mc::D, NK = Mc::NK, W = Mc::W, P = Mc::P;
     const int n = A.n;
     const int lane = threadIdx.x;
@@ -258,7 +259,8 @@ __global__ __launch_bounds__(64) void k_sstep_gram(AdrGeom A, int S, const T* __
     cplx<T> xr[8];
     const bool own_lane = lane >= Mc::H && lane < 64 - Mc::H;
     NoExtra ex;
-    sstep_march<T, M, X0, true, 0>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex, [&](int r, auto, const cplx<T>(&k)[M + 1]) {
+    sstep_march<T, M, X0, true, 0, -1>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
+                                       [&](int r, auto, const cplx<T>(&k)[M + 1]) {
         (void)r;
         if (!(own_lane && j <= A.n - 1)) return;
         double kr[M + 1], ki[M + 1];
@@ -440,7 +442,7 @@ enum { EPI_X = 0, EPI_MOD = 1, EPI_MODRD = 2 };
 template <typename T>
 struct ModArgs {
     Geom G;                   // wave geometry of level 2 (n as on the ADR level)
-    const T* theta;           // sigma k phi reduced to [-pi, pi]
+    const cplx<T>* car;       // carrier e^{i sigma k phi}
     const T* n2;              // n^2 on level 2 (EPI_MODRD)
     const cplx<T>* g;         // level-2 right-hand side (EPI_MODRD)
     const cplx<T>* u;         // level-2 iterate, read
@@ -454,7 +456,7 @@ struct ModExtra {
     const ModArgs<T>& a;
     int j = 0, n = 0;
     bool colok = false;
-    T th[8];
+    cplx<T> cr[8];
     cplx<T> uu[8];
     cplx<T> gg[EPI == EPI_MODRD ? 8 : 1];
     T nn[EPI == EPI_MODRD ? 8 : 1];
@@ -469,14 +471,14 @@ struct ModExtra {
         if constexpr (EPI != EPI_X) {
             if (r >= 1 && r <= n - 1 && colok) {
                 const int p = r * n + j;
-                th[SL] = a.theta[p];
+                cr[SL] = a.car[p];
                 uu[SL] = a.u[p];
                 if constexpr (EPI == EPI_MODRD) {
                     gg[SL] = a.g[p];
                     nn[SL] = a.n2[p];
                 }
             } else {
-                th[SL] = T(0);
+                cr[SL] = cplx<T>{};
                 uu[SL] = cplx<T>{};
                 if constexpr (EPI == EPI_MODRD) {
                     gg[SL] = cplx<T>{};
@@ -498,9 +500,9 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                                                       ModArgs<T> mod) {
     static_assert(EPI == EPI_X || X0, "the modulated epilogues follow the post-smoother");
     constexpr int XH = EPI == EPI_MODRD ? 1 : 0;
-    using Mc = March<M, X0, false, XH>;
+    constexpr int EP = EPI == EPI_X ? -1 : EPI == EPI_MOD ? 0 : 1;
+    using Mc = March<M, X0, false, XH, EP>;
     constexpr int W = Mc::W;
-    static_assert(EPI == EPI_X || Mc::EMIT_SPAN < W, "register ring too short for the epilogue");
     const int lane = threadIdx.x;
     const int n = A.n;
     cplx<T> c[M];
@@ -540,36 +542,31 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
     };
     if constexpr (EPI == EPI_X) {
         NoExtra ex;
-        sstep_march<T, M, X0, false, 0>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
-                                        [&](int r, auto slot, const cplx<T>(&k)[M]) {
+        sstep_march<T, M, X0, false, 0, EP>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
+                                            [&](int r, auto slot, const cplx<T>(&k)[M]) {
                                             const cplx<T> v = xval(slot, k);
                                             if (own_lane && j <= n - 1) xout[(size_t)r * n + j] = v;
                                         });
     } else if constexpr (EPI == EPI_MOD) {
         ModExtra<T, EPI> ex(mod);
-        sstep_march<T, M, X0, false, 0>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
-                                        [&](int r, auto slot, const cplx<T>(&k)[M]) {
+        sstep_march<T, M, X0, false, 0, EP>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
+                                            [&](int r, auto slot, const cplx<T>(&k)[M]) {
                                             constexpr int sr = decltype(slot)::value;
                                             const cplx<T> v = xval(slot, k);
-                                            T sn, cs;
-                                            sincos_t(ex.th[sr], &sn, &cs);
                                             if (own_lane && j <= n - 1)
-                                                mod.uout[(size_t)r * n + j] = ex.uu[sr] + v * mk<T>(cs, sn);
+                                                mod.uout[(size_t)r * n + j] = ex.uu[sr] + v * ex.cr[sr];
                                         });
     } else {
         ModExtra<T, EPI> ex(mod);
-        cplx<T> un[W], car[W];  // updated iterate and carrier e^{i theta} of the emitted rows
+        cplx<T> un[W];  // updated iterate of the emitted rows
         const Geom& G = mod.G;
         const T ih2 = T(G.inv_h2);
-        sstep_march<T, M, X0, false, 1>(
+        sstep_march<T, M, X0, false, 1, EP>(
             A, S, px, py, c0, b, x0, j, rb, re, xr, ex, [&](int r, auto slot, const cplx<T>(&k)[M]) {
                 constexpr int sr = decltype(slot)::value;
                 constexpr int s1 = (sr + W - 1) % W, s2 = (sr + W - 2) % W;
                 const cplx<T> v = xval(slot, k);
-                T sn, cs;
-                sincos_t(ex.th[sr], &sn, &cs);
-                car[sr] = mk<T>(cs, sn);
-                un[sr] = ex.uu[sr] + v * car[sr];
+                un[sr] = ex.uu[sr] + v * ex.cr[sr];
                 const int ri = r - 1;
                 if (ri >= rb && ri <= re) {
                     const cplx<T> cu = un[s1];
@@ -580,7 +577,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                     const cplx<T> res = ex.gg[s1] - (lap - kap * cu);
                     if (own_lane && j <= n - 1) {
                         const size_t p = (size_t)ri * n + j;
-                        mod.bout[p] = res * conjg(car[s1]);
+                        mod.bout[p] = res * conjg(ex.cr[s1]);
                         mod.uout[p] = cu;
                     }
                 }
