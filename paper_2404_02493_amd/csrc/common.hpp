@@ -60,29 +60,30 @@ using c128 = cplx<double>;
 //   n      nodes per side on this level (h = 1/n)
 //   s      stride of the level in fine-grid indices, 2^(l-1)
 //   nf     fine-grid nodes per side
-//   W      sponge width in fine cells
+//   W      sponge width in fine cells (ramp 1 - d/W evaluated as 1 - d * inv_W)
 // kappa(i, j) = k2 * n2(i, j) * (1 + i * sig_str * rho^2), rho from the indices.
 struct Geom {
     int n;
     int s;
     int nf;
     int W;
+    double inv_W;    // 1 / W
     double inv_h2;
     double k2;
     double sig_str;
 };
 
 template <typename T>
-__device__ __forceinline__ T sponge_ramp(int t, int nf, int W) {
+__device__ __forceinline__ T sponge_ramp(int t, int nf, T inv_W) {
     int d = t < nf - t ? t : nf - t;
-    T r = T(1) - T(d) / T(W);
+    T r = T(1) - T(d) * inv_W;
     return r > T(0) ? r : T(0);
 }
 
 template <typename T>
 __device__ __forceinline__ cplx<T> kappa_at(const Geom& G, T n2, int i, int j) {
-    T ri = sponge_ramp<T>(i * G.s, G.nf, G.W);
-    T rj = sponge_ramp<T>(j * G.s, G.nf, G.W);
+    T ri = sponge_ramp<T>(i * G.s, G.nf, T(G.inv_W));
+    T rj = sponge_ramp<T>(j * G.s, G.nf, T(G.inv_W));
     T rho = ri > rj ? ri : rj;
     T kr = T(G.k2) * n2;
     return {kr, kr * (T(G.sig_str) * (rho * rho))};

@@ -198,6 +198,7 @@ static Geom make_geom(const helm_ctx c, int level) {
     G.s = 1 << (level - 1);
     G.nf = c->d.n;
     G.W = c->d.damping_cells;
+    G.inv_W = 1.0 / double(G.W);
     G.inv_h2 = double(G.n) * double(G.n);
     G.k2 = c->d.k * c->d.k;
     G.sig_str = double(c->d.sign) * c->d.damping_strength;

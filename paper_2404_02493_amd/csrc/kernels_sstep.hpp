@@ -69,6 +69,17 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+// a[p] addressed as a uniform base plus a 32-bit byte offset (every level array is
+// below 4 GiB), which the hardware adds itself (no 64-bit address arithmetic).
+template <typename V>
+__device__ __forceinline__ V ld_off(const V* __restrict__ a, unsigned p) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(a) + p * (unsigned)sizeof(V));
+}
+template <typename V>
+__device__ __forceinline__ void st_off(V* __restrict__ a, unsigned p, V v) {
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(a) + p * (unsigned)sizeof(V)) = v;
+}
+
 // Upwind ADR stencil of one node with its constant factors folded in:
 //   M a = C a_c - l sum_nb a_nb - i sum_nb g_nb a_nb,
 //   l = 1/h^2,  C = c0 + 4 l - i g_c,  g = 2 sigma k / (2h) * (upwind weight of the node).
@@ -185,12 +196,12 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
     }
     auto load_row = [&](int r, cplx<T>& xv, cplx<T>& bv, T& fx, T& fy, cplx<T>& cv) {
         if (r >= 1 && r <= n - 1 && colok) {
-            const int p = r * n + j;
-            if (X0) xv = x0[p];
-            bv = b[p];
-            fx = px[p];
-            fy = py[p];
-            cv = c0[p];
+            const unsigned p = (unsigned)(r * n + j);
+            if (X0) xv = ld_off(x0, p);
+            bv = ld_off(b, p);
+            fx = ld_off(px, p);
+            fy = ld_off(py, p);
+            cv = ld_off(c0, p);
         } else {
             xv = cplx<T>{};
             bv = cplx<T>{};
@@ -470,12 +481,12 @@ struct ModExtra {
     __device__ void load(int r) {
         if constexpr (EPI != EPI_X) {
             if (r >= 1 && r <= n - 1 && colok) {
-                const int p = r * n + j;
-                cr[SL] = a.car[p];
-                uu[SL] = a.u[p];
+                const unsigned p = (unsigned)(r * n + j);
+                cr[SL] = ld_off(a.car, p);
+                uu[SL] = ld_off(a.u, p);
                 if constexpr (EPI == EPI_MODRD) {
-                    gg[SL] = a.g[p];
-                    nn[SL] = a.n2[p];
+                    gg[SL] = ld_off(a.g, p);
+                    nn[SL] = ld_off(a.n2, p);
                 }
             } else {
                 cr[SL] = cplx<T>{};
@@ -545,7 +556,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
         sstep_march<T, M, X0, false, 0, EP>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
                                             [&](int r, auto slot, const cplx<T>(&k)[M]) {
                                             const cplx<T> v = xval(slot, k);
-                                            if (own_lane && j <= n - 1) xout[(size_t)r * n + j] = v;
+                                            if (own_lane && j <= n - 1) st_off(xout, (unsigned)(r * n + j), v);
                                         });
     } else if constexpr (EPI == EPI_MOD) {
         ModExtra<T, EPI> ex(mod);
@@ -554,7 +565,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                                             constexpr int sr = decltype(slot)::value;
                                             const cplx<T> v = xval(slot, k);
                                             if (own_lane && j <= n - 1)
-                                                mod.uout[(size_t)r * n + j] = ex.uu[sr] + v * ex.cr[sr];
+                                                st_off(mod.uout, (unsigned)(r * n + j), ex.uu[sr] + v * ex.cr[sr]);
                                         });
     } else {
         ModExtra<T, EPI> ex(mod);
@@ -576,9 +587,9 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                     const cplx<T> kap = kappa_at<T>(G, ex.nn[s1], ri, j);
                     const cplx<T> res = ex.gg[s1] - (lap - kap * cu);
                     if (own_lane && j <= n - 1) {
-                        const size_t p = (size_t)ri * n + j;
-                        mod.bout[p] = res * conjg(ex.cr[s1]);
-                        mod.uout[p] = cu;
+                        const unsigned p = (unsigned)(ri * n + j);
+                        st_off(mod.bout, p, res * conjg(ex.cr[s1]));
+                        st_off(mod.uout, p, cu);
                     }
                 }
             });
