@@ -198,10 +198,10 @@ struct AdjEngine {
     void rec_adr_step(int s) {
         WaveLevel& W = c->wl[2];
         AdrTape& Tp = S.adr[s][2];
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st,
+        LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st,
                W.G, (const T*)W.n2, (const C*)S.g[2], (const C*)W.u, (const C*)c->car2, (C*)Tp.b);
         rec_adrv(s, 2);
-        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
+        LAUNCH(c, 4 * sizeof(C) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
                (const C*)Tp.xo, (const C*)c->car2, (C*)W.u);
     }
 

@@ -325,7 +325,7 @@ struct Engine {
                 const double den = 2.0 * theta - dc * rho;
                 const double rho_new = dc / den;
                 const double c1 = rho_new * rho, c2 = 2.0 / den;
-                LAUNCH(c, (7 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_fused<P>), dim3(tiles_of(G.n)),
+                LAUNCH(c, (6 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_fused<P>), dim3(tiles_of(G.n)),
                        tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)dcur, (cplx<P>*)dnext, (cplx<P>*)W.r,
                        (cplx<P>*)u, P(c1), P(c2));
                 std::swap(dcur, dnext);
@@ -475,11 +475,11 @@ struct Engine {
         const bool fused = adr_fused();
         for (int s = 0; s < M; ++s) {
             if (s == 0 || !fused)
-                LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(),
+                LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(),
                        st, W.G, (const T*)W.n2, (const C*)W.g, (const C*)W.u, (const C*)c->car2, (C*)A.b);
             if (!fused) {
                 adr_vcycle(2);
-                LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))),
+                LAUNCH(c, 4 * sizeof(C) * double(N(2)), (k_adr_modadd<T>), dim3(flat_blocks(N(2))),
                        dim3(BLOCK), st, N(2), (const C*)A.x, (const C*)c->car2, (C*)W.u);
                 continue;
             }
@@ -624,7 +624,7 @@ struct Engine {
                    (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
         } else if constexpr (MM <= 3) {
             const int nc = March<MM, true, false, 1>::units(A.n, S);
-            LAUNCH(c, (9 * sizeof(C) + 3 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MODRD>), dim3(nc),
+            LAUNCH(c, (8 * sizeof(C) + 3 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MODRD>), dim3(nc),
                    dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                    (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
         } else {
