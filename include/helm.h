@@ -211,7 +211,9 @@ helm_status helm_get_tuning(helm_ctx ctx, char* json, int64_t cap);
  *   7  out = GMRES(M_l; b=in2, x0=in, m=gmres_m)   (level l >= 2)
  *   8  out = ADR V-cycle(b=in2, x0=0) (level l >= 2)
  *   9  out = ADR step(u=in, g=in2) (level 2)
- *  10  out = wave-ADR cycle on level l from (u=in, g=in2)
+ *  10  out = wave-ADR cycle on level l from (u=in, g=in2); in NULL means u = 0 (on
+ *      level 1 this is the zero-start form used as the FGMRES preconditioner; coarser
+ *      levels require NULL)
  *  11  out = R(in2 - A_l in)     (fused residual + restriction)
  *  12  out = in                  (plain copy of a level array: a probe of known
  *                                 size for hardware memory counters)

@@ -89,6 +89,14 @@ __device__ __forceinline__ cplx<T> kappa_at(const Geom& G, T n2, int i, int j) {
     return {kr, kr * (T(G.sig_str) * (rho * rho))};
 }
 
+// Workgroup b of nb is dispatched to XCD b mod 8 (round robin).  This renumbering gives
+// each XCD a contiguous range of work items (the first nb mod 8 XCDs one more), so that
+// neighbouring tiles or strips share one L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Load with the implicit zero ring at index n (i, j >= 0 always holds for callers).
 template <typename V>
 __device__ __forceinline__ V ldz(const V* __restrict__ a, int i, int j, int n) {

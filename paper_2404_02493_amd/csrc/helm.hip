@@ -436,6 +436,29 @@ struct Engine {
         WaveLevel& W = c->wl[1];
         const Geom& G = W.G;
         const T w0 = T(c->w[0]);
+        if (u_in == nullptr) {
+            // the zero-start Jacobi sweep is recomputed inside the restriction and the
+            // post-smoother instead of being stored
+            const bool c64 = c->wl[2].f64;
+            const double bc = c64 ? 16.0 : sizeof(C);
+            if (c64)
+                LAUNCH(c, (sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_restrict<T, double>),
+                       dim3(rr_blocks(G.n)), dim3(BLOCK), st, G, (const T*)W.n2, (const C*)g, w0,
+                       (c128*)c->wl[2].g);
+            else
+                LAUNCH(c, (sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_restrict<T, T>),
+                       dim3(rr_blocks(G.n)), dim3(BLOCK), st, G, (const T*)W.n2, (const C*)g, w0, (C*)c->wl[2].g);
+            cycle_coarse(2);
+            if (c64)
+                LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_prolong_jacobi<double, T>),
+                       dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2, (const C*)g,
+                       (const c128*)c->wl[2].u, w0, (C*)u_out);
+            else
+                LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_prolong_jacobi<T, T>),
+                       dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2, (const C*)g,
+                       (const C*)c->wl[2].u, w0, (C*)u_out);
+            return;
+        }
         LAUNCH(c, ((u_in ? 3 : 2) * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2,
                            (const C*)g, (const C*)u_in, (C*)c->ws1, w0);
         restrict_down(1, g, c->ws1, c->wl[2].g);

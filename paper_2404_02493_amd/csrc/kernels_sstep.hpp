@@ -169,7 +169,7 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
     const int ns = Mc::strips(n);
     int u = blockIdx.x;
     const int nb = gridDim.x;
-    if ((nb & 7) == 0) u = (u & 7) * (nb >> 3) + (u >> 3);  // neighbouring units on one XCD
+    u = xcd_remap(u, nb);  // neighbouring units on one XCD
     const int sg = u / ns, st = u - sg * ns;
     const int j = 1 + st * Mc::TXW - H + lane;
     jcol = j;
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
         const int ns = Mc::strips(n);
         int u = blockIdx.x;
         const int nb = gridDim.x;
-        if ((nb & 7) == 0) u = (u & 7) * (nb >> 3) + (u >> 3);
+        u = xcd_remap(u, nb);
         const int sg = u / ns, st = u - sg * ns;
         const int jj = 1 + st * Mc::TXW - Mc::H + lane;
         const int R = Mc::rows(S);

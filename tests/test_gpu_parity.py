@@ -138,6 +138,9 @@ def test_operator_parity(small_case, prec, form):
     u, g = rounded(_rand(rng, c.n), cd), rounded(_rand(rng, c.n), cd)
     out = H.debug_op(10, 1, to_dev(u, cd), to_dev(g, cd))
     report["W1"] = rel(out, cycle(P, g, u))
+    # fine cycle from a zero iterate (the preconditioner application inside FGMRES)
+    out = H.debug_op(10, 1, None, to_dev(g, cd))
+    report["W1z"] = rel(out, cycle(P, g, torch.zeros_like(g)))
     H.close()
     bad = {k: v for k, v in report.items() if not v < tol}
     print({k: f"{v:.2e}" for k, v in report.items()})
