@@ -185,17 +185,18 @@ helm_status helm_batch_solve(helm_batch b, const void* const* g, void* const* u,
                              int32_t* status, void* stream);
 helm_status helm_batch_destroy(helm_batch b); /* NULL-safe */
 
-/* Autotuner of launch shapes (steps per marching unit of the s-step GMRES passes
- * per ADR level, block count of the outer FGMRES passes), measured with HIP events
- * on this context's own hierarchy filled with hashed data.  The choice is applied to
- * the context and returned as JSON text in json (host, cap bytes; may be NULL):
- *   {"n": .., "levels": .., "prec": "c64"|"c128", "sstep_rows": {"<level>": steps, ..},
+/* Autotuner of launch shapes (form of the s-step GMRES passes per ADR level: steps
+ * per marching unit, or 1 / 2 for overlapped 16 x 16 / 32 x 32 tiles; block count of
+ * the outer FGMRES passes), measured with HIP events on this context's own
+ * hierarchy filled with hashed data.  The choice is applied to the context and
+ * returned as JSON text in json (host, cap bytes; may be NULL):
+ *   {"n": .., "levels": .., "prec": "c64"|"c128", "sstep_rows": {"<level>": form, ..},
  *    "fgmres_blocks": blocks, "timings_ms": {..}}
  * Only the split of FP64 partial sums changes, so results change at rounding level.
  * Synchronises the stream; overwrites the ADR work buffers (call it between cycles). */
 helm_status helm_tune(helm_ctx ctx, char* json, int64_t cap, void* stream);
 /* Applies a tuning JSON from helm_tune (a cached one); unknown keys are ignored,
- * invalid levels, unit steps (0, or a multiple of 8 in 16..256) or block counts give
+ * invalid levels, forms (0 = default, 1, 2, or a multiple of 8 in 16..256) or block counts give
  * HELM_EINVAL and change nothing. */
 helm_status helm_set_tuning(helm_ctx ctx, const char* json);
 /* The tuning in effect (0 = built-in default) as JSON (host, cap bytes). */

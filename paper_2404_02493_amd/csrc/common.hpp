@@ -120,7 +120,7 @@ struct KrylovScal {
     int cols;                             // Arnoldi columns completed
     int done;                             // 1: no further Arnoldi work (solved, breakdown, zero rhs)
     int m;                                // requested Krylov dimension
-    unsigned ticket;                      // arrivals at a last-block reduction (0 between launches)
+    unsigned pad;
 };
 
 

@@ -110,7 +110,7 @@ struct helm_ctx_s {
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
     // launch shapes chosen by the autotuner (0 = built-in default)
     struct Tuning {
-        int sstep_rows[16] = {};    // rows per marching segment of the s-step passes on ADR level l
+        int sstep_rows[16] = {};    // s-step form on ADR level l: steps per marching unit, 1/2 tiles, 0 default
         int fgmres_blocks = 0;      // blocks of the outer FGMRES passes on the fine grid
     } tn;
     // captured cycles, keyed by the (g, u_in, u_out) pointers they were captured with
@@ -596,49 +596,87 @@ struct Engine {
     // unit covers that many rows minus twice its halo): the tuned value, else the
     // shortest (24..128) that keeps the Gram pass at 2048 wavefronts or fewer.
     int sstep_steps(int l) const {
-        if (c->tn.sstep_rows[l] > 0) return c->tn.sstep_rows[l];
+        if (c->tn.sstep_rows[l] >= 16) return c->tn.sstep_rows[l];
         const int n = c->al[l].n;
         int S = 24;
         while (S < 128 && March<3, true, true>::units(n, S) > 2048) S += 8;
         return S;
+    }
+    // Tile edge of the overlapped-tile form on level l (tuned value 1: 16, 2: 32), 0 when
+    // the level marches.
+    int sstep_tile_edge(int l) const {
+        const int v = c->tn.sstep_rows[l];
+        return v == 1 ? 16 : v == 2 ? 32 : 0;
+    }
+    template <typename F>
+    static void with_edge(int tt, F&& f) {
+        if (tt == 16)
+            f(std::integral_constant<int, 16>{});
+        else
+            f(std::integral_constant<int, 32>{});
+    }
+
+    // Pass 1 and the coefficient solve of the s-step GMRES(MM) on level l (x0 = A.x if X0).
+    template <int MM, bool X0>
+    void sstep_gram_solve(int l, int S, int tt) {
+        AdrLevel& A = c->al[l];
+        constexpr int NG = (MM + 1) * (MM + 1);
+        const double bytes = ((X0 ? 3 : 2) * sizeof(C) + 2 * sizeof(T)) * NN(A.n);
+        const C* x0 = X0 ? (const C*)A.x : nullptr;
+        int ng = 0;
+        if (tt) {
+            with_edge(tt, [&](auto e) {
+                constexpr int TT = decltype(e)::value;
+                ng = Tile<MM, X0, true, TT>::tiles(A.n);
+                REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many tiles for the reduction scratch");
+                LAUNCH(c, bytes, (k_sstep_gram_tile<T, MM, X0, TT>), dim3(ng), dim3(BLOCK), st, A.A,
+                       (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0, c->partials);
+            });
+        } else {
+            ng = March<MM, X0, true>::units(A.n, S);
+            REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many segments for the reduction scratch");
+            LAUNCH(c, bytes, (k_sstep_gram<T, MM, X0>), dim3(ng), dim3(64), st, A.A, S, (const T*)A.px,
+                   (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0, c->partials);
+        }
+        LAUNCH(c, 8.0 * NG * ng, (k_sstep_solve<MM>), dim3(1), dim3(SOLVE_THREADS), st, (const double*)c->partials,
+               ng, 1e-12, A.K);
+    }
+
+    // Pass 2 with the plain epilogue: xout = x0 + sum c_j K_{j-1} (x0 = A.x if X0).
+    template <int MM, bool X0>
+    void sstep_combine_x(int l, int S, int tt, C* xout) {
+        AdrLevel& A = c->al[l];
+        const double bytes = ((X0 ? 4 : 3) * sizeof(C) + 2 * sizeof(T)) * NN(A.n);
+        const C* x0 = X0 ? (const C*)A.x : nullptr;
+        if (tt) {
+            with_edge(tt, [&](auto e) {
+                constexpr int TT = decltype(e)::value;
+                LAUNCH(c, bytes, (k_sstep_combine_tile<T, MM, X0, TT>), dim3(Tile<MM, X0, false, TT>::tiles(A.n)),
+                       dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0,
+                       (const KrylovScal*)A.K, xout);
+            });
+        } else {
+            LAUNCH(c, bytes, (k_sstep_combine<T, MM, X0, EPI_X>), dim3(March<MM, X0, false>::units(A.n, S)), dim3(64),
+                   st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0,
+                   (const KrylovScal*)A.K, xout, ModArgs<T>{});
+        }
     }
 
     // s-step GMRES(MM) on ADR level l.
     template <int MM>
     void gmres_sstep(int l, bool x0_zero, int epi, const ModArgs<T>* ma) {
         AdrLevel& A = c->al[l];
-        const int S = sstep_steps(l);
-        constexpr int NG = (MM + 1) * (MM + 1);
-        const double tolb = 1e-12;
+        const int S = sstep_steps(l), tt = sstep_tile_edge(l);
         const double nn = NN(A.n);
-        double* gsum = A.K->R;  // device scratch inside the Krylov state
-        const ModArgs<T> none{};
         if (x0_zero) {
             REQUIRE(epi == EPI_X, "fused ADR epilogue on a pre-smoother");
-            const int ng = March<MM, false, true>::units(A.n, S), nc = March<MM, false, false>::units(A.n, S);
-            REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many segments for the reduction scratch");
-            LAUNCH(c, (2 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_gram<T, MM, false>), dim3(ng), dim3(64), st,
-                   A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)nullptr,
-                   c->partials);
-            LAUNCH(c, 8.0 * NG * ng, (k_sstep_solve<MM>), dim3(NG), dim3(BLOCK), st, (const double*)c->partials, ng,
-                   tolb, gsum, A.K);
-            LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, false, EPI_X>), dim3(nc), dim3(64),
-                   st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)nullptr,
-                   (const KrylovScal*)A.K, (C*)A.x, none);
+            sstep_gram_solve<MM, false>(l, S, tt);
+            sstep_combine_x<MM, false>(l, S, tt, (C*)A.x);
             return;
         }
-        const int ng = March<MM, true, true>::units(A.n, S);
-        REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many segments for the reduction scratch");
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_gram<T, MM, true>), dim3(ng), dim3(64), st,
-               A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
-               c->partials);
-        LAUNCH(c, 8.0 * NG * ng, (k_sstep_solve<MM>), dim3(NG), dim3(BLOCK), st, (const double*)c->partials, ng, tolb,
-               gsum, A.K);
+        sstep_gram_solve<MM, true>(l, S, tt);
         if (epi == EPI_X) {
-            const int nc = March<MM, true, false>::units(A.n, S);
-            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_X>), dim3(nc),
-                   dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
-                   (const KrylovScal*)A.K, (C*)A.xalt, none);
+            sstep_combine_x<MM, true>(l, S, tt, (C*)A.xalt);
             std::swap(A.x, A.xalt);
         } else if (epi == EPI_MOD) {
             const int nc = March<MM, true, false>::units(A.n, S);

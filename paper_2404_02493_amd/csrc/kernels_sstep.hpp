@@ -5,9 +5,9 @@
 // min_c || K_0 - sum_{j=1..m} c_j K_j ||, and then x = x0 + sum_j c_j K_{j-1}.
 // The Krylov vectors are never stored; each pass rebuilds them:
 //   pass 1 (k_sstep_gram):    K_0..K_m, Gram matrix G = K^H K (FP64 partial sums)
-//   k_sstep_solve:            the partials summed (one block per Gram entry), then
+//   k_sstep_solve:            the partials summed (one wavefront per Gram entry), then
 //                             the normalised Cholesky solve of the normal
-//                             equations for c (the last block to finish)
+//                             equations for c (one block)
 //   pass 2 (k_sstep_combine): K_0..K_{m-1} again, x_out = x0 + sum c_j K_{j-1}
 // The normalised monomial basis of the ADR operator is well conditioned for
 // m <= 4 (condition numbers of 5-40 measured on the workloads), so the normal
@@ -251,6 +251,28 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
     }
 }
 
+// acc += the Gram entries of one node's K_0..K_M (layout of k_sstep_gram), in FP64.
+template <typename T, int M>
+__device__ __forceinline__ void gram_add(double (&acc)[(M + 1) * (M + 1)], const cplx<T> (&k)[M + 1]) {
+    double kr[M + 1], ki[M + 1];
+#pragma unroll
+    for (int i = 0; i <= M; ++i) {
+        kr[i] = double(k[i].re);
+        ki[i] = double(k[i].im);
+    }
+    int o = M + 1;
+#pragma unroll
+    for (int i = 0; i <= M; ++i) {
+        acc[i] = fma(ki[i], ki[i], fma(kr[i], kr[i], acc[i]));
+#pragma unroll
+        for (int jv = i + 1; jv <= M; ++jv) {
+            acc[o] = fma(ki[i], ki[jv], fma(kr[i], kr[jv], acc[o]));
+            acc[o + 1] = fma(-ki[i], kr[jv], fma(kr[i], ki[jv], acc[o + 1]));
+            o += 2;
+        }
+    }
+}
+
 // Pass 1: per-wavefront Gram sums of K_0..K_M over the unit's own nodes, to
 // partials[v * gridDim.x + blockIdx.x].  Layout of the NG doubles: G(i,i) real for
 // i = 0..M, then G(i,j), i < j, as (re, im).  One wavefront per block.
@@ -274,23 +296,7 @@ __global__ __launch_bounds__(64) void k_sstep_gram(AdrGeom A, int S, const T* __
                                        [&](int r, auto, const cplx<T>(&k)[M + 1]) {
         (void)r;
         if (!(own_lane && j <= A.n - 1)) return;
-        double kr[M + 1], ki[M + 1];
-#pragma unroll
-        for (int i = 0; i <= M; ++i) {
-            kr[i] = double(k[i].re);
-            ki[i] = double(k[i].im);
-        }
-        int o = M + 1;
-#pragma unroll
-        for (int i = 0; i <= M; ++i) {
-            acc[i] = fma(ki[i], ki[i], fma(kr[i], kr[i], acc[i]));
-#pragma unroll
-            for (int jv = i + 1; jv <= M; ++jv) {
-                acc[o] = fma(ki[i], ki[jv], fma(kr[i], kr[jv], acc[o]));
-                acc[o + 1] = fma(-ki[i], kr[jv], fma(kr[i], ki[jv], acc[o + 1]));
-                o += 2;
-            }
-        }
+        gram_add<T, M>(acc, k);
     });
 #pragma unroll
     for (int v = 0; v < NG; ++v) {
@@ -401,33 +407,40 @@ __device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sum
     }
 }
 
-// Grid reduction of the Gram partials and the coefficient solve, in one launch of NG
-// blocks: block v sums partials[v * nblk + b] over b (fixed order) into gsum[v]; the
-// last block to arrive (ticket in K) solves the normal equations on one thread and
-// writes K->y (c_j of K_{j-1}, zero for dropped columns), K->cols, K->beta = ||K_0||
-// and K->done (1; 2 if the norm is not finite), then rearms the ticket.
+// Reduction of the Gram partials and the coefficient solve in one block of SOLVE_THREADS
+// threads: wavefront v sums partials[v * nblk + b] over b (fixed order; the loads of a
+// lane are issued in batches of SOLVE_BATCH before the adds), then thread 0 solves the
+// normal equations and writes K->y (c_j of K_{j-1}, zero for dropped columns), K->cols,
+// K->beta = ||K_0|| and K->done (1; 2 if the norm is not finite).
+constexpr int SOLVE_THREADS = 1024, SOLVE_BATCH = 32;
+
 template <int M>
-__global__ __launch_bounds__(BLOCK) void k_sstep_solve(const double* __restrict__ partials, int nblk,
-                                                       double breakdown_tol, double* gsum, KrylovScal* K) {
-    constexpr int NG = (M + 1) * (M + 1);
-    __shared__ double red[4];
-    __shared__ double sums[1];
-    __shared__ int last;
-    const int v = blockIdx.x;
-    double acc[1] = {0.0};
-    for (int b = threadIdx.x; b < nblk; b += BLOCK) acc[0] += partials[(size_t)v * nblk + b];
-    block_sum<1, 4>(acc, 1, red, sums);
-    if (threadIdx.x == 0) {
-        gsum[v] = sums[0];
-        __threadfence();  // publish gsum[v] before arriving
-        last = atomicAdd(&K->ticket, 1u) == (unsigned)(NG - 1);
+__global__ __launch_bounds__(SOLVE_THREADS) void k_sstep_solve(const double* __restrict__ partials, int nblk,
+                                                               double breakdown_tol, KrylovScal* K) {
+    constexpr int NG = (M + 1) * (M + 1), NW = SOLVE_THREADS / 64;
+    __shared__ double sums[NG];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int v = wv; v < NG; v += NW) {
+        const double* __restrict__ row = partials + (size_t)v * nblk;
+        double acc = 0.0;
+        for (int b0 = 0; b0 < nblk; b0 += 64 * SOLVE_BATCH) {
+            double t[SOLVE_BATCH];
+#pragma unroll
+            for (int k = 0; k < SOLVE_BATCH; ++k) {
+                const int bb = b0 + k * 64 + lane;
+                t[k] = bb < nblk ? row[bb] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < SOLVE_BATCH; ++k) acc += t[k];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) sums[v] = acc;
     }
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
-    __threadfence();  // every block's gsum is visible after its arrival
+    if (threadIdx.x != 0) return;
     double g[NG];
 #pragma unroll
-    for (int q = 0; q < NG; ++q) g[q] = gsum[q];
+    for (int q = 0; q < NG; ++q) g[q] = sums[q];
     double yr[M], yi[M], beta;
     int cols;
     sstep_small_solve<M>(g, breakdown_tol, yr, yi, cols, beta);
@@ -439,7 +452,6 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_solve(const double* __restrict_
     }
     K->cols = cols;
     K->done = isfinite(beta) ? 1 : 2;
-    K->ticket = 0u;
 }
 
 // What pass 2 does with x = x0 + sum c_j K_{j-1} (X0 only for the last two): write
@@ -594,6 +606,172 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                 }
             });
     }
+}
+
+// ------------------------------------------------------------------ overlapped-tile form
+// On the small ADR levels one marching unit per SIMD cannot hide its row-to-row
+// latency.  There a block of BLOCK threads owns a TT x TT tile of unknowns and builds
+// the Krylov vectors on the tile and a ring of H nodes around it, one vector per
+// barrier, in LDS.  Values outside the ring are taken as zero, so the ring's values
+// are wrong by one more node per operator application and the tile's own values are
+// exact after the H applications; the region's border nodes are simply set to zero.
+template <int M, bool X0, bool GRAM, int TT>
+struct Tile {
+    static constexpr int D = X0 ? 1 : 0;
+    static constexpr int NK = GRAM ? M : M - 1;
+    static constexpr int H = NK + D;
+    static constexpr int RW = TT + 2 * H;  // region width
+    static constexpr int NR = RW * RW;
+    static constexpr int NPT = (NR + BLOCK - 1) / BLOCK;  // region nodes per thread
+    __host__ __device__ static int per_side(int n) { return (n - 2) / TT + 1; }
+    __host__ __device__ static int tiles(int n) { return per_side(n) * per_side(n); }
+};
+
+// Shared body of both tile passes; buf: 2 NR values of LDS.  emit(gi, gj, x0, k) for
+// every own node (k[j] = K_j there, x0 the iterate there, 0 without X0).
+template <typename T, int M, bool X0, bool GRAM, int TT, typename Emit>
+__device__ __forceinline__ void sstep_tile(const AdrGeom& A, int ti, int tj, const T* __restrict__ px,
+                                           const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                           const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
+                                           cplx<T>* buf, Emit&& emit) {
+    using Tg = Tile<M, X0, GRAM, TT>;
+    constexpr int RW = Tg::RW, NR = Tg::NR, NPT = Tg::NPT, H = Tg::H, NK = Tg::NK;
+    const int n = A.n;
+    const int i0 = 1 + ti * TT - H, j0 = 1 + tj * TT - H;  // region node (0, 0)
+    const int tid = threadIdx.x;
+    cplx<T> xv[NPT], bv[NPT], cv[NPT];
+    T fx[NPT], fy[NPT];
+    bool ok[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = tid + k * BLOCK;
+        const int ri = q / RW, rj = q - ri * RW;
+        const int gi = i0 + ri, gj = j0 + rj;
+        xv[k] = bv[k] = cv[k] = cplx<T>{};
+        fx[k] = fy[k] = T(0);
+        ok[k] = q < NR && gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1;
+        if (ok[k]) {
+            const unsigned p = (unsigned)(gi * n + gj);
+            if constexpr (X0) xv[k] = ld_off(x0, p);
+            bv[k] = ld_off(b, p);
+            fx[k] = ld_off(px, p);
+            fy[k] = ld_off(py, p);
+            cv[k] = ld_off(c0, p);
+        }
+    }
+    UpCoef<T> cf[NPT];
+    bool inner[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = tid + k * BLOCK;
+        const int ri = q / RW, rj = q - ri * RW;
+        cf[k] = up_coef<T>(A, fx[k], fy[k], cv[k], ok[k]);
+        inner[k] = q < NR && ri >= 1 && ri <= RW - 2 && rj >= 1 && rj <= RW - 2;
+    }
+    auto apply = [&](const cplx<T>* src, int k) -> cplx<T> {
+        const int q = tid + k * BLOCK;
+        return up_apply<T>(cf[k], src[q], src[q - 1], src[q + 1], src[q - RW], src[q + RW]);
+    };
+    // K_j lives in buffer (j + D) % 2; x0 (X0) in buffer 0
+    cplx<T> kv[NK + 1][NPT];
+    if constexpr (X0) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+            if (tid + k * BLOCK < NR) buf[tid + k * BLOCK] = xv[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) kv[0][k] = inner[k] ? bv[k] - apply(buf, k) : cplx<T>{};
+    } else {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) kv[0][k] = bv[k];
+    }
+    static_for<NK>([&](auto jc) {
+        constexpr int jj = decltype(jc)::value + 1;
+        cplx<T>* src = buf + ((jj - 1 + Tg::D) % 2) * NR;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+            if (tid + k * BLOCK < NR) src[tid + k * BLOCK] = kv[jj - 1][k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) kv[jj][k] = inner[k] ? apply(src, k) : cplx<T>{};
+    });
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = tid + k * BLOCK;
+        const int ri = q / RW, rj = q - ri * RW;
+        const int gi = i0 + ri, gj = j0 + rj;
+        if (q < NR && ri >= H && ri < H + TT && rj >= H && rj < H + TT && gi <= n - 1 && gj <= n - 1) {
+            cplx<T> kk[NK + 1];
+#pragma unroll
+            for (int jj = 0; jj <= NK; ++jj) kk[jj] = kv[jj][k];
+            emit(gi, gj, xv[k], kk);
+        }
+    }
+}
+
+__device__ __forceinline__ void tile_index(int per_side, int& ti, int& tj) {
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    ti = t / per_side;
+    tj = t - ti * per_side;
+}
+
+// Pass 1 in tile form: per-block Gram sums to partials[v * gridDim.x + blockIdx.x]
+// (layout of k_sstep_gram); Tile<M, X0, true, TT>::tiles(n) blocks.
+template <typename T, int M, bool X0, int TT>
+__global__ __launch_bounds__(BLOCK) void k_sstep_gram_tile(AdrGeom A, const T* __restrict__ px,
+                                                           const T* __restrict__ py,
+                                                           const cplx<T>* __restrict__ c0,
+                                                           const cplx<T>* __restrict__ b,
+                                                           const cplx<T>* __restrict__ x0,
+                                                           double* __restrict__ partials) {
+    using Tg = Tile<M, X0, true, TT>;
+    constexpr int NG = (M + 1) * (M + 1);
+    __shared__ cplx<T> buf[2 * Tg::NR];
+    __shared__ double red[(BLOCK / 64) * NG];
+    __shared__ double sums[NG];
+    double acc[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) acc[q] = 0.0;
+    int ti, tj;
+    tile_index(Tg::per_side(A.n), ti, tj);
+    sstep_tile<T, M, X0, true, TT>(A, ti, tj, px, py, c0, b, x0, buf,
+                                   [&](int, int, cplx<T>, const cplx<T>(&k)[M + 1]) { gram_add<T, M>(acc, k); });
+    block_sum<NG, BLOCK / 64>(acc, NG, red, sums);
+    store_partials(sums, NG, partials);
+}
+
+// Pass 2 in tile form with the EPI_X epilogue: xout = x0 + sum c_j K_{j-1} on the own
+// nodes, and the zero ring (row 0, column 0); Tile<M, X0, false, TT>::tiles(n) blocks.
+template <typename T, int M, bool X0, int TT>
+__global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile(AdrGeom A, const T* __restrict__ px,
+                                                              const T* __restrict__ py,
+                                                              const cplx<T>* __restrict__ c0,
+                                                              const cplx<T>* __restrict__ b,
+                                                              const cplx<T>* __restrict__ x0,
+                                                              const KrylovScal* __restrict__ K,
+                                                              cplx<T>* __restrict__ xout) {
+    using Tg = Tile<M, X0, false, TT>;
+    __shared__ cplx<T> buf[2 * Tg::NR];
+    const int n = A.n;
+    cplx<T> c[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
+    int ti, tj;
+    tile_index(Tg::per_side(n), ti, tj);
+    const int tid = threadIdx.x;
+    if (tid < TT) {
+        const int jr = 1 + tj * TT + tid, ir = 1 + ti * TT + tid;
+        if (ti == 0 && jr <= n - 1) xout[jr] = cplx<T>{};
+        if (tj == 0 && ir <= n - 1) xout[(size_t)ir * n] = cplx<T>{};
+        if (ti == 0 && tj == 0 && tid == 0) xout[0] = cplx<T>{};
+    }
+    sstep_tile<T, M, X0, false, TT>(A, ti, tj, px, py, c0, b, x0, buf,
+                                    [&](int gi, int gj, cplx<T> xo, const cplx<T>(&k)[M]) {
+                                        cplx<T> v = X0 ? xo : cplx<T>{};
+#pragma unroll
+                                        for (int q = 0; q < M; ++q) v = v + c[q] * k[q];
+                                        st_off(xout, (unsigned)(gi * n + gj), v);
+                                    });
 }
 
 }  // namespace helm

@@ -2,10 +2,12 @@
 //
 // Knobs (each changes only how the work and the FP64 partial sums of a reduction are
 // split, hence only the summation order of those sums):
-//   sstep_rows[l]    steps per marching unit of the s-step GMRES passes on ADR
-//                    level l (rows of the unit plus its warm-up rows): longer units
-//                    recompute fewer warm-up rows and leave fewer partials to sum,
-//                    shorter ones give more wavefronts;
+//   sstep_rows[l]    form of the s-step GMRES passes on ADR level l: steps per
+//                    marching unit (rows of the unit plus its warm-up rows; longer
+//                    units recompute fewer warm-up rows and leave fewer partials to
+//                    sum, shorter ones give more wavefronts), or 1 / 2 for the
+//                    overlapped-tile form with 16 x 16 / 32 x 32 tiles (more
+//                    parallelism on small levels, more recomputed ring nodes);
 //   fgmres_blocks    blocks of the outer FGMRES passes on the fine grid.
 // Every candidate runs the real kernels on the level's buffers filled with
 // hashed data; the fastest (HIP-event time over a few repetitions) is kept.  The
@@ -94,14 +96,14 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
             HIPCHK(hipGetLastError());
             int best = 0;
             double tbest = 1e30;
-            for (int cand : {16, 24, 32, 40, 48, 64, 80, 96, 128}) {
+            for (int cand : {1, 2, 16, 24, 32, 40, 48, 64, 80, 96, 128}) {
                 if (cand > 16 && cand >= 2 * A.n) break;
                 c->tn.sstep_rows[l] = cand;
                 const double t = time_ms(st, reps, [&] {
                     E.gmres(l, m, true);
                     E.gmres(l, m, false);
                 });
-                note("sstep_l" + std::to_string(l) + "_" + std::to_string(cand), t);
+                note("sstep_l" + std::to_string(l) + "_" + (cand == 1 ? std::string("tile16") : cand == 2 ? std::string("tile32") : std::to_string(cand)), t);
                 if (t < tbest) {
                     tbest = t;
                     best = cand;
@@ -156,7 +158,7 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
     return tuning_json(c, tim);
 }
 
-// Applies {"sstep_rows": {"l": rows, ...}, "fgmres_blocks": blocks} (other keys ignored).
+// Applies {"sstep_rows": {"l": steps or tile form, ...}, "fgmres_blocks": blocks} (other keys ignored).
 static void apply_tuning(helm_ctx c, const char* json) {
     const std::string s(json);
     helm_ctx_s::Tuning t = c->tn;
@@ -195,7 +197,8 @@ static void apply_tuning(helm_ctx c, const char* json) {
             ++i;
             const long v = read_int(i);
             REQUIRE(l >= 2 && l <= c->LA && l < 16, "tuning: level out of range");
-            REQUIRE(v == 0 || (v >= 16 && v <= 256 && v % 8 == 0), "tuning: unit steps out of range");
+            REQUIRE(v == 0 || v == 1 || v == 2 || (v >= 16 && v <= 256 && v % 8 == 0),
+                    "tuning: unit steps out of range");
             t.sstep_rows[l] = (int)v;
         }
     }
