@@ -337,18 +337,23 @@ __device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sum
     for (int i = 0; i < M; ++i) yr[i] = yi[i] = 0.0;
     cols = 0;
     if (beta > 0.0 && isfinite(beta)) {
-        double d[M + 1];
+        // reciprocals up front: one thread runs this, so the serial chain of divisions
+        // and square roots is what it costs
+        double d[M + 1], rd[M + 1];
 #pragma unroll
-        for (int i = 0; i <= M; ++i) d[i] = sqrt(gr[i][i]);
+        for (int i = 0; i <= M; ++i) {
+            d[i] = sqrt(gr[i][i]);
+            rd[i] = d[i] > 0 ? 1.0 / d[i] : 0.0;
+        }
         // normalised normal equations N c' = r, N(i,j) = G(i,j)/(d_i d_j), r(i) = G(i,0)/(d_i d_0)
-        double Lr[M][M], Li[M][M];
+        double Lr[M][M], Li[M][M], il[M];
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                const double s = (d[i + 1] > 0 && d[j + 1] > 0) ? 1.0 / (d[i + 1] * d[j + 1]) : 0.0;
-                Lr[i][j] = gr[i + 1][j + 1] * s;
-                Li[i][j] = gi[i + 1][j + 1] * s;
+                const double sc = rd[i + 1] * rd[j + 1];
+                Lr[i][j] = gr[i + 1][j + 1] * sc;
+                Li[i][j] = gi[i + 1][j + 1] * sc;
             }
         // Cholesky N = L L^H; columns after the first negligible pivot are dropped
         bool ok = true;
@@ -360,6 +365,7 @@ __device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sum
             ok = ok && (p > breakdown_tol * breakdown_tol);
             if (ok) cols = j + 1;
             const double lj = ok ? sqrt(p) : 1.0;
+            il[j] = 1.0 / lj;
             Lr[j][j] = lj;
             Li[j][j] = 0.0;
 #pragma unroll
@@ -370,22 +376,22 @@ __device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sum
                     sr -= Lr[i][q] * Lr[j][q] + Li[i][q] * Li[j][q];
                     si -= Li[i][q] * Lr[j][q] - Lr[i][q] * Li[j][q];
                 }
-                Lr[i][j] = sr / lj;
-                Li[i][j] = si / lj;
+                Lr[i][j] = sr * il[j];
+                Li[i][j] = si * il[j];
             }
         }
         double zr[M], zi[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) {  // L z = r  (rows >= cols give zero)
-            const double s = 1.0 / (d[i + 1] * d[0]);
-            double sr = gr[i + 1][0] * s, si = gi[i + 1][0] * s;
+            const double sc = rd[i + 1] * rd[0];
+            double sr = gr[i + 1][0] * sc, si = gi[i + 1][0] * sc;
 #pragma unroll
             for (int q = 0; q < i; ++q) {
                 sr -= Lr[i][q] * zr[q] - Li[i][q] * zi[q];
                 si -= Lr[i][q] * zi[q] + Li[i][q] * zr[q];
             }
-            zr[i] = i < cols ? sr / Lr[i][i] : 0.0;
-            zi[i] = i < cols ? si / Lr[i][i] : 0.0;
+            zr[i] = i < cols ? sr * il[i] : 0.0;
+            zi[i] = i < cols ? si * il[i] : 0.0;
         }
 #pragma unroll
         for (int i = M - 1; i >= 0; --i) {  // L^H c' = z
@@ -395,14 +401,14 @@ __device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sum
                 sr -= Lr[q][i] * zr[q] + Li[q][i] * zi[q];
                 si -= Lr[q][i] * zi[q] - Li[q][i] * zr[q];
             }
-            zr[i] = i < cols ? sr / Lr[i][i] : 0.0;
-            zi[i] = i < cols ? si / Lr[i][i] : 0.0;
+            zr[i] = i < cols ? sr * il[i] : 0.0;
+            zi[i] = i < cols ? si * il[i] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < M; ++i) {  // c_j = c'_j d_0 / d_j
-            const double s = i < cols ? d[0] / d[i + 1] : 0.0;
-            yr[i] = zr[i] * s;
-            yi[i] = zi[i] * s;
+            const double sc = i < cols ? d[0] * rd[i + 1] : 0.0;
+            yr[i] = zr[i] * sc;
+            yi[i] = zi[i] * sc;
         }
     }
 }
