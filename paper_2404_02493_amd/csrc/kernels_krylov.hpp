@@ -437,6 +437,52 @@ __global__ __launch_bounds__(BLOCK) void k_fg_orth(size_t N, VecSet<T> V, cplx<T
 
 enum FinOp { FIN_INIT = 0, FIN_MV = 1, FIN_ORTH1 = 2, FIN_ORTH2 = 3, FIN_LMV = 4, FIN_LORTH = 5 };
 
+// FIN_LMV and FIN_LORTH on one wavefront, lane i for basis vector i <= jj (< MAXM).
+__device__ __forceinline__ void fin_lagged(int op, int jj, const double* sums, KrylovScal* K, double tol) {
+    const int i = threadIdx.x;
+    if (op == FIN_LMV) {
+        const double nv = jj > 0 ? sqrt(sums[2 * (jj + 1)]) : 0.0;
+        const bool okv = nv > 0.0 && isfinite(nv);
+        if (i <= jj) {
+            const double s = (jj > 0 && i == jj) ? (okv ? 1.0 / nv : 0.0) : K->scale[i];
+            K->dots[2 * i] = s * sums[2 * i];
+            K->dots[2 * i + 1] = s * sums[2 * i + 1];
+        }
+        if (i == 0 && jj > 0) {
+            Hp(K, jj, jj - 1)[0] = nv;
+            Hp(K, jj, jj - 1)[1] = 0.0;
+            K->scale[jj] = okv ? 1.0 / nv : 0.0;
+            if (!okv) K->done = isfinite(nv) ? 1 : 2;
+        }
+        return;
+    }
+    double dd = 0.0;
+    if (i <= jj) {
+        const double s = K->scale[i];
+        const double dr = s * sums[2 * i], di = s * sums[2 * i + 1];
+        Hp(K, i, jj)[0] = K->dots[2 * i] + dr;
+        Hp(K, i, jj)[1] = K->dots[2 * i + 1] + di;
+        K->dots[2 * i] = dr;
+        K->dots[2 * i + 1] = di;
+        dd = dr * dr + di * di;
+    }
+    dd = wave_sum(dd);
+    if (i != 0) return;
+    const double h2 = sums[2 * (jj + 1)] - dd;
+    const double hn = h2 > 0.0 ? sqrt(h2) : 0.0;
+    Hp(K, jj + 1, jj)[0] = isfinite(h2) ? hn : h2;
+    Hp(K, jj + 1, jj)[1] = 0.0;
+    K->cols = jj + 1;
+    if (!isfinite(h2)) {
+        K->done = 2;
+    } else if (hn <= tol * K->beta || hn == 0.0 || jj + 1 == K->m) {
+        K->done = 1;
+    } else {
+        K->scale[jj + 1] = 1.0 / hn;
+        K->zscale[jj + 1] = 1.0 / hn;
+    }
+}
+
 // One block: sums the partials of the previous Krylov pass and updates the state.
 //   FIN_INIT : beta = ||r0||, scale[0] = 1/beta, cols = 0, done if beta == 0
 //   FIN_MV   : dots_i = scale_i * sum conj(V_i) w
@@ -461,6 +507,11 @@ __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __rest
                        : (op == FIN_LMV || op == FIN_LORTH) ? 2 * (jj + 1) + 1
                                                             : 1;
     final_sum<KV>(partials, nblk, kcount, red, sums);
+    if (op == FIN_LMV || op == FIN_LORTH) {
+        // one lane per basis vector: the K fields of every i are read at once
+        if (threadIdx.x < 64) fin_lagged(op, jj, sums, K, tol);
+        return;
+    }
     if (threadIdx.x != 0) return;
     if (op == FIN_INIT) {
         double b = sqrt(sums[0]);
@@ -472,47 +523,6 @@ __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __rest
         K->zscale[0] = K->scale[0];
         if (K->done)
             for (int q = 0; q < MAXM; ++q) K->y[2 * q] = K->y[2 * q + 1] = 0.0;
-    } else if (op == FIN_LMV) {
-        if (jj > 0) {
-            const double nv = sqrt(sums[2 * (jj + 1)]);
-            Hp(K, jj, jj - 1)[0] = nv;
-            Hp(K, jj, jj - 1)[1] = 0.0;
-            if (nv > 0.0 && isfinite(nv)) {
-                K->scale[jj] = 1.0 / nv;
-            } else {
-                K->scale[jj] = 0.0;
-                K->done = isfinite(nv) ? 1 : 2;
-            }
-        }
-        for (int i = 0; i <= jj; ++i) {
-            double s = K->scale[i];
-            K->dots[2 * i] = s * sums[2 * i];
-            K->dots[2 * i + 1] = s * sums[2 * i + 1];
-        }
-    } else if (op == FIN_LORTH) {
-        double dd = 0.0;
-        for (int i = 0; i <= jj; ++i) {
-            const double s = K->scale[i];
-            const double dr = s * sums[2 * i], di = s * sums[2 * i + 1];
-            Hp(K, i, jj)[0] = K->dots[2 * i] + dr;
-            Hp(K, i, jj)[1] = K->dots[2 * i + 1] + di;
-            K->dots[2 * i] = dr;
-            K->dots[2 * i + 1] = di;
-            dd += dr * dr + di * di;
-        }
-        const double h2 = sums[2 * (jj + 1)] - dd;
-        const double hn = h2 > 0.0 ? sqrt(h2) : 0.0;
-        Hp(K, jj + 1, jj)[0] = isfinite(h2) ? hn : h2;
-        Hp(K, jj + 1, jj)[1] = 0.0;
-        K->cols = jj + 1;
-        if (!isfinite(h2)) {
-            K->done = 2;
-        } else if (hn <= tol * K->beta || hn == 0.0 || jj + 1 == K->m) {
-            K->done = 1;
-        } else {
-            K->scale[jj + 1] = 1.0 / hn;
-            K->zscale[jj + 1] = 1.0 / hn;
-        }
     } else if (op == FIN_MV) {
         for (int i = 0; i <= jj; ++i) {
             double s = K->scale[i];
@@ -572,12 +582,25 @@ __global__ __launch_bounds__(BLOCK) void k_krylov_combine(size_t N, VecSet<T> V,
             c[i] = cplx<T>{};
         }
     }
-    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        cplx<T> v = x0 ? x0[p] : cplx<T>{};
+    // N is even (n is a power of two): FP32 pairs of nodes as 16-byte accesses
+    constexpr int E = FgShape<T>::E;
+    for (size_t p = (blockIdx.x * (size_t)BLOCK + threadIdx.x) * E; p < N; p += (size_t)gridDim.x * BLOCK * E) {
+        cplx<T> v[E];
+        if (x0) {
+            ld_pack<T, E>(x0, p, v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = cplx<T>{};
+        }
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < cols) v = v + c[i] * V.v[i][p];
-        x[p] = v;
+            if (i < cols) {
+                cplx<T> b[E];
+                ld_pack_nt<T, E>(V.v[i], p, b);
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = v[e] + c[i] * b[e];
+            }
+        st_pack<T, E>(x, p, v);
     }
 }
 

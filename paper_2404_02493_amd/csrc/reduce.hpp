@@ -12,10 +12,30 @@ constexpr int BLOCK = 256;     // threads per block of the grid kernels (4 wavef
 constexpr int FBLOCK = 1024;   // threads of the one-block finalize kernels
 constexpr int MAXRED = 2048;   // at most this many blocks in a kernel that produces partials
 
+// v moved by the DPP control CTRL within the rows selected by RM; lanes without a
+// source (and rows outside RM) receive 0.
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, RM, 0xF, false);
+    return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes (all active), returned to every lane.  Scans of each row of 16
+// lanes (row_shr 1, 2, 4, 8), then the row totals carried by row_bcast 15 and 31, so lane
+// 63 ends with the sum (a fixed order; measured about 2 us less than a butterfly of
+// lane shuffles for 16 sums at the end of a 1924-wavefront kernel).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move<0x111>(v);       // row_shr:1
+    v += dpp_move<0x112>(v);       // row_shr:2
+    v += dpp_move<0x114>(v);       // row_shr:4
+    v += dpp_move<0x118>(v);       // row_shr:8
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, 63), hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+    return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // Reduce K per-thread accumulators over the block (any size up to 1024 threads);
