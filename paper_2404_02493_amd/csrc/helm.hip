@@ -549,14 +549,40 @@ struct Engine {
             gmres(l, c->d.gmres_coarse_m, true);
             return;
         }
-        gmres(l, c->d.gmres_m, true);
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.n)), dim3(BLOCK), st, A.A,
-                           (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x,
-                           (C*)c->al[l + 1].b);
+        presmooth_restrict(l);
         adr_vcycle(l + 1);
         LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)),
                tile_block(), st, A.n, (const C*)c->al[l + 1].x, (C*)A.x);
         gmres(l, c->d.gmres_m, false, epi, ma);
+    }
+
+    // Pre-smoother from zero on level l < LA and b_{l+1} = R(b - M x): in the marching
+    // s-step form the second pass also forms and restricts the residual.
+    void presmooth_restrict(int l) {
+        AdrLevel& A = c->al[l];
+        const int m = c->d.gmres_m;
+        if (sstep_form(m) && sstep_tile_edge(l) == 0) {
+            switch (m) {
+                case 1: presmooth_restrict_sstep<1>(l); break;
+                case 2: presmooth_restrict_sstep<2>(l); break;
+                case 3: presmooth_restrict_sstep<3>(l); break;
+                default: presmooth_restrict_sstep<4>(l); break;
+            }
+            return;
+        }
+        gmres(l, m, true);
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>),
+               dim3(rr_blocks(A.n)), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0,
+               (const C*)A.b, (const C*)A.x, (C*)c->al[l + 1].b);
+    }
+    template <int MM>
+    void presmooth_restrict_sstep(int l) {
+        AdrLevel& A = c->al[l];
+        const int S = sstep_steps(l);
+        sstep_gram_solve<MM, false>(l, S, 0);
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_sstep_combine_rr<T, MM>),
+               dim3(March<MM, false, true, 1>::units(A.n, S)), dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py,
+               (const C*)A.c0, (const C*)A.b, (const KrylovScal*)A.K, (C*)A.x, (C*)c->al[l + 1].b);
     }
 
     template <int NV>

@@ -614,6 +614,68 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
     }
 }
 
+// Pass 2 of a pre-smoother (x0 = 0) fused with the restriction of its residual:
+// x = sum_j c_j K_{j-1} on the own nodes, and since b - M x = K_0 - sum_j c_j K_j the
+// residual comes from one more Krylov vector instead of an application of M to x.  The
+// unit emits one row and column beyond its own, weights each residual row across lanes
+// (1 2 1) and, at every odd fine row 2I+1 whose row 2I is its own, combines the last
+// three rows (1 2 1) / 16 into the coarse row I of rc (n/2 nodes per side) at the own
+// even columns.  Also writes the zero rings of x and rc.
+template <typename T, int M>
+__global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const T* __restrict__ px,
+                                                         const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                                         const cplx<T>* __restrict__ b,
+                                                         const KrylovScal* __restrict__ K, cplx<T>* __restrict__ xout,
+                                                         cplx<T>* __restrict__ rc) {
+    using Mc = March<M, false, true, 1, -1>;
+    constexpr int W = Mc::W;
+    const int lane = threadIdx.x;
+    const int n = A.n, nc = n / 2;
+    cplx<T> c[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
+    const bool own_lane = lane >= Mc::H && lane < 64 - Mc::H;
+    {
+        const int ns = Mc::strips(n);
+        const int u = xcd_remap(blockIdx.x, gridDim.x);
+        const int sg = u / ns, st = u - sg * ns;
+        const int jj = 1 + st * Mc::TXW - Mc::H + lane;
+        const int R = Mc::rows(S);
+        const int r0 = 1 + sg * R, r1 = r0 + R - 1 < n - 1 ? r0 + R - 1 : n - 1;
+        if (jj == 0) {
+            for (int r = r0; r <= r1; ++r) xout[(size_t)r * n] = cplx<T>{};
+            for (int I = (r0 + 1) >> 1; 2 * I <= r1; ++I) rc[(size_t)I * nc] = cplx<T>{};
+        }
+        if (sg == 0 && ((own_lane && jj <= n - 1) || jj == 0)) {
+            xout[jj] = cplx<T>{};
+            if (!(jj & 1)) rc[jj >> 1] = cplx<T>{};
+        }
+    }
+    int j, rb, re;
+    cplx<T> xr[8];
+    cplx<T> hr[W];  // residual rows weighted across lanes, by ring slot
+    NoExtra ex;
+    sstep_march<T, M, false, true, 1, -1>(A, S, px, py, c0, b, nullptr, j, rb, re, xr, ex,
+                                          [&](int r, auto slot, const cplx<T>(&k)[M + 1]) {
+        constexpr int sr = decltype(slot)::value;
+        constexpr int s1 = (sr + W - 1) % W, s2 = (sr + W - 2) % W;
+        cplx<T> xv{};
+        cplx<T> rv = k[0];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            xv = xv + c[q] * k[q];
+            rv = rv - c[q] * k[q + 1];
+        }
+        if (own_lane && j <= n - 1 && r >= rb && r <= re) st_off(xout, (unsigned)(r * n + j), xv);
+        hr[sr] = (lane_prev(rv) + lane_next(rv)) + T(2) * rv;
+        const int I = (r - 1) >> 1;
+        if ((r & 1) && r - 1 >= rb && r - 1 <= re && I >= 1) {
+            const cplx<T> v = T(1.0 / 16.0) * ((hr[s2] + hr[sr]) + T(2) * hr[s1]);
+            if (own_lane && !(j & 1) && j <= n - 1) st_off(rc, (unsigned)(I * nc + (j >> 1)), v);
+        }
+    });
+}
+
 // ------------------------------------------------------------------ overlapped-tile form
 // On the small ADR levels one marching unit per SIMD cannot hide its row-to-row
 // latency.  There a block of BLOCK threads owns a TT x TT tile of unknowns and builds
