@@ -561,7 +561,7 @@ struct Engine {
     void presmooth_restrict(int l) {
         AdrLevel& A = c->al[l];
         const int m = c->d.gmres_m;
-        if (sstep_form(m) && sstep_tile_edge(l) == 0) {
+        if (sstep_form(m)) {
             switch (m) {
                 case 1: presmooth_restrict_sstep<1>(l); break;
                 case 2: presmooth_restrict_sstep<2>(l); break;
@@ -578,11 +578,21 @@ struct Engine {
     template <int MM>
     void presmooth_restrict_sstep(int l) {
         AdrLevel& A = c->al[l];
-        const int S = sstep_steps(l);
-        sstep_gram_solve<MM, false>(l, S, 0);
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_sstep_combine_rr<T, MM>),
-               dim3(March<MM, false, true, 1>::units(A.n, S)), dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py,
-               (const C*)A.c0, (const C*)A.b, (const KrylovScal*)A.K, (C*)A.x, (C*)c->al[l + 1].b);
+        const int S = sstep_steps(l), tt = sstep_tile_edge(l);
+        const double bytes = (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2);
+        sstep_gram_solve<MM, false>(l, S, tt);
+        if (tt) {
+            with_edge(tt, [&](auto e) {
+                constexpr int TT = decltype(e)::value;
+                LAUNCH(c, bytes, (k_sstep_combine_tile_rr<T, MM, TT>), dim3(Tile<MM, false, true, TT, 1>::tiles(A.n)),
+                       dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                       (const KrylovScal*)A.K, (C*)A.x, (C*)c->al[l + 1].b);
+            });
+        } else {
+            LAUNCH(c, bytes, (k_sstep_combine_rr<T, MM>), dim3(March<MM, false, true, 1>::units(A.n, S)), dim3(64),
+                   st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
+                   (const KrylovScal*)A.K, (C*)A.x, (C*)c->al[l + 1].b);
+        }
     }
 
     template <int NV>

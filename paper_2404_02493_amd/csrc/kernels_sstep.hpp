@@ -683,11 +683,11 @@ __global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const
 // barrier, in LDS.  Values outside the ring are taken as zero, so the ring's values
 // are wrong by one more node per operator application and the tile's own values are
 // exact after the H applications; the region's border nodes are simply set to zero.
-template <int M, bool X0, bool GRAM, int TT>
+template <int M, bool X0, bool GRAM, int TT, int XH = 0>
 struct Tile {
     static constexpr int D = X0 ? 1 : 0;
     static constexpr int NK = GRAM ? M : M - 1;
-    static constexpr int H = NK + D;
+    static constexpr int H = NK + D + XH;  // XH: ring of exact values beyond the tile
     static constexpr int RW = TT + 2 * H;  // region width
     static constexpr int NR = RW * RW;
     static constexpr int NPT = (NR + BLOCK - 1) / BLOCK;  // region nodes per thread
@@ -695,14 +695,17 @@ struct Tile {
     __host__ __device__ static int tiles(int n) { return per_side(n) * per_side(n); }
 };
 
-// Shared body of both tile passes; buf: 2 NR values of LDS.  emit(gi, gj, x0, k) for
-// every own node (k[j] = K_j there, x0 the iterate there, 0 without X0).
-template <typename T, int M, bool X0, bool GRAM, int TT, typename Emit>
+// Shared body of the tile passes; buf: 2 NR values of LDS.  emit(q, gi, gj, own, x0, k)
+// for every node of the tile and its ring of XH nodes (q: region index; own: a node of
+// the tile inside the grid; k[j] = K_j there, exact, and 0 off the grid; x0 the iterate
+// there, 0 without X0).  The last step reads only buffer (NK - 1 + D) % 2, so emit may
+// write the other one, (NK + D) % 2.
+template <typename T, int M, bool X0, bool GRAM, int TT, int XH = 0, typename Emit>
 __device__ __forceinline__ void sstep_tile(const AdrGeom& A, int ti, int tj, const T* __restrict__ px,
                                            const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                            const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
                                            cplx<T>* buf, Emit&& emit) {
-    using Tg = Tile<M, X0, GRAM, TT>;
+    using Tg = Tile<M, X0, GRAM, TT, XH>;
     constexpr int RW = Tg::RW, NR = Tg::NR, NPT = Tg::NPT, H = Tg::H, NK = Tg::NK;
     const int n = A.n;
     const int i0 = 1 + ti * TT - H, j0 = 1 + tj * TT - H;  // region node (0, 0)
@@ -768,11 +771,12 @@ __device__ __forceinline__ void sstep_tile(const AdrGeom& A, int ti, int tj, con
         const int q = tid + k * BLOCK;
         const int ri = q / RW, rj = q - ri * RW;
         const int gi = i0 + ri, gj = j0 + rj;
-        if (q < NR && ri >= H && ri < H + TT && rj >= H && rj < H + TT && gi <= n - 1 && gj <= n - 1) {
+        if (q < NR && ri >= H - XH && ri < H + TT + XH && rj >= H - XH && rj < H + TT + XH) {
+            const bool own = ri >= H && ri < H + TT && rj >= H && rj < H + TT && gi <= n - 1 && gj <= n - 1;
             cplx<T> kk[NK + 1];
 #pragma unroll
             for (int jj = 0; jj <= NK; ++jj) kk[jj] = kv[jj][k];
-            emit(gi, gj, xv[k], kk);
+            emit(q, gi, gj, own, xv[k], kk);
         }
     }
 }
@@ -803,7 +807,9 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_gram_tile(AdrGeom A, const T* _
     int ti, tj;
     tile_index(Tg::per_side(A.n), ti, tj);
     sstep_tile<T, M, X0, true, TT>(A, ti, tj, px, py, c0, b, x0, buf,
-                                   [&](int, int, cplx<T>, const cplx<T>(&k)[M + 1]) { gram_add<T, M>(acc, k); });
+                                   [&](int, int, int, bool own, cplx<T>, const cplx<T>(&k)[M + 1]) {
+                                       if (own) gram_add<T, M>(acc, k);
+                                   });
     block_sum<NG, BLOCK / 64>(acc, NG, red, sums);
     store_partials(sums, NG, partials);
 }
@@ -834,12 +840,76 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile(AdrGeom A, const T
         if (ti == 0 && tj == 0 && tid == 0) xout[0] = cplx<T>{};
     }
     sstep_tile<T, M, X0, false, TT>(A, ti, tj, px, py, c0, b, x0, buf,
-                                    [&](int gi, int gj, cplx<T> xo, const cplx<T>(&k)[M]) {
+                                    [&](int, int gi, int gj, bool own, cplx<T> xo, const cplx<T>(&k)[M]) {
+                                        if (!own) return;
                                         cplx<T> v = X0 ? xo : cplx<T>{};
 #pragma unroll
                                         for (int q = 0; q < M; ++q) v = v + c[q] * k[q];
                                         st_off(xout, (unsigned)(gi * n + gj), v);
                                     });
+}
+
+// Tile form of k_sstep_combine_rr: x = sum_j c_j K_{j-1} on the tile, the residual
+// K_0 - sum_j c_j K_j on the tile and a ring of one node (into the free LDS buffer),
+// then its full weighting at the coarse nodes whose centre is a node of the tile (one
+// per thread for 32 x 32 tiles), and the zero rings of x and rc.
+template <typename T, int M, int TT>
+__global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_rr(AdrGeom A, const T* __restrict__ px,
+                                                                 const T* __restrict__ py,
+                                                                 const cplx<T>* __restrict__ c0,
+                                                                 const cplx<T>* __restrict__ b,
+                                                                 const KrylovScal* __restrict__ K,
+                                                                 cplx<T>* __restrict__ xout, cplx<T>* __restrict__ rc) {
+    using Tg = Tile<M, false, true, TT, 1>;
+    constexpr int RW = Tg::RW, H = Tg::H, TC = TT / 2;
+    static_assert(TT % 2 == 0 && TC * TC <= BLOCK, "one coarse node per thread");
+    __shared__ cplx<T> buf[2 * Tg::NR];
+    const int n = A.n, nc = n / 2;
+    cplx<T> c[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
+    int ti, tj;
+    tile_index(Tg::per_side(n), ti, tj);
+    const int tid = threadIdx.x;
+    if (tid < TT) {
+        const int jr = 1 + tj * TT + tid, ir = 1 + ti * TT + tid;
+        if (ti == 0 && jr <= n - 1) xout[jr] = cplx<T>{};
+        if (tj == 0 && ir <= n - 1) xout[(size_t)ir * n] = cplx<T>{};
+        if (ti == 0 && tj == 0 && tid == 0) xout[0] = cplx<T>{};
+    }
+    if (tid < TC) {
+        const int Jr = 1 + tj * TC + tid, Ir = 1 + ti * TC + tid;
+        if (ti == 0 && Jr <= nc - 1) rc[Jr] = cplx<T>{};
+        if (tj == 0 && Ir <= nc - 1) rc[(size_t)Ir * nc] = cplx<T>{};
+        if (ti == 0 && tj == 0 && tid == 0) rc[0] = cplx<T>{};
+    }
+    cplx<T>* res = buf + ((Tg::NK + Tg::D) % 2) * Tg::NR;
+    sstep_tile<T, M, false, true, TT, 1>(A, ti, tj, px, py, c0, b, nullptr, buf,
+                                         [&](int q, int gi, int gj, bool own, cplx<T>, const cplx<T>(&k)[M + 1]) {
+                                             cplx<T> xv{};
+                                             cplx<T> rv = k[0];
+#pragma unroll
+                                             for (int qq = 0; qq < M; ++qq) {
+                                                 xv = xv + c[qq] * k[qq];
+                                                 rv = rv - c[qq] * k[qq + 1];
+                                             }
+                                             if (own) st_off(xout, (unsigned)(gi * n + gj), xv);
+                                             res[q] = rv;
+                                         });
+    __syncthreads();
+    // coarse node (I, J) = (1 + ti TC + ci, 1 + tj TC + cj): fine centre (2I, 2J) at region
+    // row 2I - (1 + ti TT - H) = 1 + 2 ci + H, column likewise
+    if (tid < TC * TC) {
+        const int ci = tid / TC, cj = tid - ci * TC;
+        const int I = 1 + ti * TC + ci, J = 1 + tj * TC + cj;
+        if (I <= nc - 1 && J <= nc - 1) {
+            const int l = (1 + 2 * ci + H) * RW + 1 + 2 * cj + H;
+            const cplx<T> cc = res[l];
+            const cplx<T> ud = ((res[l - RW] + res[l + RW]) + res[l - 1]) + res[l + 1];
+            const cplx<T> dg = ((res[l - RW - 1] + res[l - RW + 1]) + res[l + RW - 1]) + res[l + RW + 1];
+            st_off(rc, (unsigned)(I * nc + J), T(1.0 / 16.0) * ((T(4) * cc + T(2) * ud) + dg));
+        }
+    }
 }
 
 }  // namespace helm
