@@ -521,9 +521,14 @@ struct Engine {
     }
 
     // GMRES on a small level in one workgroup (the coarsest ADR level), if it fits.
+    // the coarsest level's GMRES runs in one workgroup (gmres_block)
+    bool block_form(int l, int m) const {
+        const AdrLevel& A = c->al[l];
+        return l == c->LA && A.n <= c->d.tail_n && (size_t)A.n * A.n <= 4 * 1024 && m <= 12;
+    }
     bool gmres_block(int l, int m, bool x0_zero) {
         AdrLevel& A = c->al[l];
-        if (A.n > c->d.tail_n || (size_t)A.n * A.n > 4 * 1024 || m > 12) return false;
+        if (!block_form(l, m)) return false;
         BlockLevel<T> t{};
         t.A = A.A;
         t.px = (const T*)A.px;
@@ -543,17 +548,58 @@ struct Engine {
 
     // One ADR V-cycle from x = 0 on levels l..LA (result in A.x, or handed to the
     // epilogue epi of the last smoother of level l).
-    void adr_vcycle(int l, int epi = EPI_X, const ModArgs<T>* ma = nullptr) {
+    // ADR V-cycle from level l (result in A.x); with pinto, P x_l is added into pinto (the
+    // iterate of level l - 1), by the smoother's last pass itself in the tile form (x_l is
+    // then not stored).
+    void adr_vcycle(int l, int epi = EPI_X, const ModArgs<T>* ma = nullptr, void* pinto = nullptr) {
         AdrLevel& A = c->al[l];
-        if (l == c->LA) {
-            gmres(l, c->d.gmres_coarse_m, true);
+        const bool coarse = l == c->LA;
+        const int m = coarse ? c->d.gmres_coarse_m : c->d.gmres_m;
+        if (!coarse) {
+            presmooth_restrict(l);
+            adr_vcycle(l + 1, EPI_X, nullptr, A.x);
+        }
+        if (pinto && epi == EPI_X && sstep_form(m) && sstep_tile_edge(l) && !(coarse && block_form(l, m))) {
+            switch (m) {
+                case 1: smooth_prolong_tile<1>(l, coarse, pinto); break;
+                case 2: smooth_prolong_tile<2>(l, coarse, pinto); break;
+                case 3: smooth_prolong_tile<3>(l, coarse, pinto); break;
+                default: smooth_prolong_tile<4>(l, coarse, pinto); break;
+            }
             return;
         }
-        presmooth_restrict(l);
-        adr_vcycle(l + 1);
-        LAUNCH(c, 2 * sizeof(C) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_prolong_add<T, T>), dim3(tiles_of(A.n)),
-               tile_block(), st, A.n, (const C*)c->al[l + 1].x, (C*)A.x);
-        gmres(l, c->d.gmres_m, false, epi, ma);
+        if (coarse)
+            gmres(l, m, true);
+        else
+            gmres(l, m, false, epi, ma);
+        if (pinto) {
+            const int nf = c->al[l - 1].n;
+            LAUNCH(c, 2 * sizeof(C) * NN(nf) + sizeof(C) * NN(nf / 2), (k_prolong_add<T, T>), dim3(tiles_of(nf)),
+                   tile_block(), st, nf, (const C*)A.x, (C*)pinto);
+        }
+    }
+    template <int MM>
+    void smooth_prolong_tile(int l, bool x0_zero, void* pinto) {
+        AdrLevel& A = c->al[l];
+        const int S = sstep_steps(l), tt = sstep_tile_edge(l);
+        const double bytes = ((x0_zero ? 2 : 3) * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + 2 * sizeof(C) * NN(2 * A.n);
+        if (x0_zero)
+            sstep_gram_solve<MM, false>(l, S, tt);
+        else
+            sstep_gram_solve<MM, true>(l, S, tt);
+        with_edge(tt, [&](auto e) {
+            constexpr int TT = decltype(e)::value;
+            if (x0_zero)
+                LAUNCH(c, bytes, (k_sstep_combine_tile_pa<T, MM, false, TT>),
+                       dim3(Tile<MM, false, false, TT, 1>::tiles(A.n)), dim3(BLOCK), st, A.A, (const T*)A.px,
+                       (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)nullptr, (const KrylovScal*)A.K,
+                       (C*)pinto);
+            else
+                LAUNCH(c, bytes, (k_sstep_combine_tile_pa<T, MM, true, TT>),
+                       dim3(Tile<MM, true, false, TT, 1>::tiles(A.n)), dim3(BLOCK), st, A.A, (const T*)A.px,
+                       (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x, (const KrylovScal*)A.K,
+                       (C*)pinto);
+        });
     }
 
     // Pre-smoother from zero on level l < LA and b_{l+1} = R(b - M x): in the marching

@@ -912,4 +912,61 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_rr(AdrGeom A, cons
     }
 }
 
+// Tile form of pass 2 with the prolongation epilogue: x = x0 + sum_j c_j K_{j-1} on the
+// tile and a ring of one node (LDS), then xf += P x (bilinear) on the fine nodes of the
+// tile: fine rows and columns 2I and 2I + 1 of its coarse nodes, and row / column 1 on
+// the first tiles (xf has 2 n nodes per side; its zero ring is left alone).  x itself is
+// not stored: its only use is this prolongation.
+template <typename T, int M, bool X0, int TT>
+__global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, const T* __restrict__ px,
+                                                                 const T* __restrict__ py,
+                                                                 const cplx<T>* __restrict__ c0,
+                                                                 const cplx<T>* __restrict__ b,
+                                                                 const cplx<T>* __restrict__ x0,
+                                                                 const KrylovScal* __restrict__ K,
+                                                                 cplx<T>* __restrict__ xf) {
+    using Tg = Tile<M, X0, false, TT, 1>;
+    constexpr int RW = Tg::RW, H = Tg::H;
+    __shared__ cplx<T> buf[2 * Tg::NR];
+    const int n = A.n, nf = 2 * n;
+    cplx<T> c[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
+    int ti, tj;
+    tile_index(Tg::per_side(n), ti, tj);
+    cplx<T>* xs = buf + ((Tg::NK + Tg::D) % 2) * Tg::NR;
+    sstep_tile<T, M, X0, false, TT, 1>(A, ti, tj, px, py, c0, b, x0, buf,
+                                       [&](int q, int, int, bool, cplx<T> xo, const cplx<T>(&k)[M]) {
+                                           cplx<T> v = X0 ? xo : cplx<T>{};
+#pragma unroll
+                                           for (int qq = 0; qq < M; ++qq) v = v + c[qq] * k[qq];
+                                           xs[q] = v;
+                                       });
+    __syncthreads();
+    const int Ia = 1 + ti * TT, Ib = Ia + TT - 1 < n - 1 ? Ia + TT - 1 : n - 1;
+    const int Ja = 1 + tj * TT, Jb = Ja + TT - 1 < n - 1 ? Ja + TT - 1 : n - 1;
+    const int f0 = ti == 0 ? 1 : 2 * Ia, f1 = 2 * Ib + 1;
+    const int g0 = tj == 0 ? 1 : 2 * Ja, g1 = 2 * Jb + 1;
+    const int FC = g1 - g0 + 1, NF = (f1 - f0 + 1) * FC;
+    const int i0 = Ia - H, j0 = Ja - H;  // coarse node of region (0, 0)
+    for (int q = threadIdx.x; q < NF; q += BLOCK) {
+        const int fr = q / FC;
+        const int f = f0 + fr, g = g0 + (q - fr * FC);
+        const int I = f >> 1, J = g >> 1;
+        const int l = (I - i0) * RW + (J - j0);
+        cplx<T> v;
+        if (!(f & 1) && !(g & 1)) {
+            v = xs[l];
+        } else if ((f & 1) && !(g & 1)) {
+            v = T(0.5) * (xs[l] + xs[l + RW]);
+        } else if (!(f & 1) && (g & 1)) {
+            v = T(0.5) * (xs[l] + xs[l + 1]);
+        } else {
+            v = T(0.25) * (((xs[l] + xs[l + RW]) + xs[l + 1]) + xs[l + RW + 1]);
+        }
+        const unsigned p = (unsigned)(f * nf + g);
+        st_off(xf, p, ld_off((const cplx<T>*)xf, p) + v);
+    }
+}
+
 }  // namespace helm

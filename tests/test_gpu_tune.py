@@ -75,12 +75,14 @@ def test_set_tuning_rejects_bad_input():
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-12), ("c64", 1e-5)])
 def test_tile_form_keeps_parity(form, prec, tol):
     """The overlapped-tile form of the s-step passes (forced on every ADR level, the
-    level-2 post-smoother's fused epilogues still marching) keeps the oracle parity."""
+    level-2 post-smoother's fused epilogues still marching; the coarsest ADR level in
+    the s-step form too, so that its pass adds the prolongation itself) keeps the oracle
+    parity."""
     from paper_2404_02493_amd import Helmholtz
 
     c = hi.make_problem(256, 160.0, 5, seed=6, medium="grf", phase="fmm", damping_cells=16)
     P = Problem(c.velocity, c.k, c.levels, damping_cells=16, phi=c.phi)
-    H = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=16)
+    H = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=16, tail_n=0)
     H.set_phase(c.phi)
     H.set_weights(P.weights.numpy())
     H.set_tuning(json.dumps({"sstep_rows": {"2": form, "3": form, "4": form}}))
