@@ -309,14 +309,18 @@ struct Engine {
         const double theta = 0.5 * (lam + a);
         const double dc = 0.5 * (lam - a);
         const size_t n = N(l);
-        if (u_zero) zero<P>(u, n);
-        const void* t0 = g;
-        if (!u_zero) {
-            residual<P>(G, W.n2, g, u, W.t);
-            t0 = W.t;
-        }
-        LAUNCH(c, (3 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start<P>), dim3(tiles_of(G.n)), tile_block(), st, G, (const P*)W.n2,
-                           (const cplx<P>*)t0, (cplx<P>*)W.r, (cplx<P>*)W.d, P(1.0 / theta));
+        // with two steps or more the first fused step takes u = 0 itself and the last one
+        // adds the final d (no zero fill, no closing axpy)
+        const bool fused_ends = m >= 2;
+        if (u_zero && !fused_ends) zero<P>(u, n);
+        if (u_zero)
+            LAUNCH(c, (3 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start<P>), dim3(tiles_of(G.n)),
+                   tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)g, (cplx<P>*)W.r, (cplx<P>*)W.d,
+                   P(1.0 / theta));
+        else
+            LAUNCH(c, (4 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start_res<P>), dim3(tiles_of(G.n)),
+                   tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)g, (const cplx<P>*)u, (cplx<P>*)W.r,
+                   (cplx<P>*)W.d, P(1.0 / theta));
         double rho = dc / theta;
         void* dcur = W.d;  // d alternates between W.d and W.t
         void* dnext = W.t;
@@ -325,12 +329,14 @@ struct Engine {
                 const double den = 2.0 * theta - dc * rho;
                 const double rho_new = dc / den;
                 const double c1 = rho_new * rho, c2 = 2.0 / den;
-                LAUNCH(c, (6 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_fused<P>), dim3(tiles_of(G.n)),
+                const int mode = (step == 1 && u_zero ? CHEB_UZERO : 0) | (step == m - 1 ? CHEB_LAST : 0);
+                const int nb = 6 - ((mode & CHEB_UZERO) ? 1 : 0) - ((mode & CHEB_LAST) ? 2 : 0);
+                LAUNCH(c, (nb * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_fused<P>), dim3(tiles_of(G.n)),
                        tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)dcur, (cplx<P>*)dnext, (cplx<P>*)W.r,
-                       (cplx<P>*)u, P(c1), P(c2));
+                       (cplx<P>*)u, P(c1), P(c2), mode);
                 std::swap(dcur, dnext);
                 rho = rho_new;
-            } else {
+            } else if (!fused_ends) {
                 LAUNCH(c, 3 * sizeof(cplx<P>) * double(n), (k_axpy<P>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, P(1),
                                    (const cplx<P>*)dcur, (cplx<P>*)u);
             }

@@ -289,13 +289,57 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start(Geom G, const T* __restric
     }
 }
 
+// Chebyshev start from a nonzero u: t = g - A u on the 64 x 16 tile and a halo of one
+// (in LDS, t is not stored), then r = A^* t and d = r / theta at the tile's nodes.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __restrict__ n2,
+                                                          const cplx<T>* __restrict__ g,
+                                                          const cplx<T>* __restrict__ u, cplx<T>* __restrict__ r,
+                                                          cplx<T>* __restrict__ d, T inv_theta) {
+    constexpr int HW = TX + 2, HH = TY + 2;
+    __shared__ cplx<T> ts[HH * HW];
+    int j, i0;
+    tile_origin(G.n, j, i0);
+    const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
+    const int tid = threadIdx.x + threadIdx.y * TX;
+    for (int q = tid; q < HH * HW; q += BLOCK) {
+        const int ri = q / HW, rj = q - ri * HW;
+        const int gi = it - 1 + ri, gj = jt - 1 + rj;
+        cplx<T> v{};
+        if (gi >= 1 && gj >= 1 && gi < G.n && gj < G.n) v = resid_at(G, n2, g, u, gi, gj);
+        ts[q] = v;
+    }
+    __syncthreads();
+    if (j >= G.n) return;
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int i = i0 + rr;
+        if (i >= G.n) break;
+        const size_t p = (size_t)i * G.n + j;
+        cplx<T> v{};
+        if (i > 0 && j > 0) {
+            const int l = (i - it + 1) * HW + (j - jt + 1);
+            cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
+            kap.im = -kap.im;
+            const cplx<T> tc = ts[l];
+            v = T(G.inv_h2) * (T(4) * tc - (((ts[l - HW] + ts[l + HW]) + ts[l - 1]) + ts[l + 1])) - kap * tc;
+        }
+        r[p] = v;
+        d[p] = inv_theta * v;
+    }
+}
+
 // Fused Chebyshev step on a 64 x 16 tile: t = A d_in on the tile and a halo of one
 // (in LDS), then at the tile's nodes  u += d_in;  r -= A^* t;  d_out = c1 d_in + c2 r.
 // d_in and d_out are different arrays (neighbouring tiles still read d_in).
+// mode bit 0 (CHEB_UZERO): u is zero on entry and is not read (its ring is written 0);
+// bit 1 (CHEB_LAST): the iteration's final update u += d_out is done here as well, and
+// r and d_out are not written (nothing reads them afterwards).
+enum { CHEB_UZERO = 1, CHEB_LAST = 2 };
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restrict__ n2,
                                                       const cplx<T>* __restrict__ d_in, cplx<T>* __restrict__ d_out,
-                                                      cplx<T>* __restrict__ r, cplx<T>* __restrict__ u, T c1, T c2) {
+                                                      cplx<T>* __restrict__ r, cplx<T>* __restrict__ u, T c1, T c2,
+                                                      int mode) {
     constexpr int HW = TX + 2, HH = TY + 2;
     __shared__ cplx<T> ts[HH * HW];
     int j, i0;
@@ -315,8 +359,9 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
         const int i = i0 + rr;
         if (i >= G.n) break;
         const size_t p = (size_t)i * G.n + j;
-        if (i == 0 || j == 0) {  // keep the ring of the alternate d buffer zero
-            d_out[p] = cplx<T>{};
+        if (i == 0 || j == 0) {  // keep the ring of the alternate d buffer (and of u) zero
+            if (!(mode & CHEB_LAST)) d_out[p] = cplx<T>{};
+            if (mode & CHEB_UZERO) u[p] = cplx<T>{};
             continue;
         }
         const int l = (i - it + 1) * HW + (j - jt + 1);
@@ -326,9 +371,15 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
         const cplx<T> aht = T(G.inv_h2) * (T(4) * tc - (((ts[l - HW] + ts[l + HW]) + ts[l - 1]) + ts[l + 1])) - kap * tc;
         const cplx<T> dv = d_in[p];
         const cplx<T> rv = r[p] - aht;
-        u[p] = u[p] + dv;
-        r[p] = rv;
-        d_out[p] = c1 * dv + c2 * rv;
+        const cplx<T> dn = c1 * dv + c2 * rv;
+        const cplx<T> u1 = ((mode & CHEB_UZERO) ? cplx<T>{} : u[p]) + dv;
+        if (mode & CHEB_LAST) {
+            u[p] = u1 + dn;
+        } else {
+            u[p] = u1;
+            r[p] = rv;
+            d_out[p] = dn;
+        }
     }
 }
 
