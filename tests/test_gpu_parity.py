@@ -167,6 +167,31 @@ def test_cycle_parity_along_oracle_iterates(name, prec):
     assert max(errs) < TOL[prec], errs
 
 
+@pytest.mark.parametrize("form", [0, 2])
+@pytest.mark.parametrize("m,mc", [(1, 1), (2, 4), (4, 2)])
+def test_cycle_parity_gmres_depths(m, mc, form):
+    """One FP64 cycle with other GMRES depths on the ADR levels (smoother m, coarsest
+    mc), every ADR level in the marching (form 0) or the 32 x 32 tile form (form 2), and
+    the coarsest ADR level in the s-step form: covers the fused residual restriction
+    and prolongation passes for every depth."""
+    import json
+
+    c = hi.make_problem(128, 80.0, 5, seed=21, medium="grf", phase="fmm", damping_cells=16)
+    P, H = make_pair(c, "c128", tail_n=0, gmres_m=m, gmres_coarse_m=mc)
+    if form:
+        H.set_tuning(json.dumps({"sstep_rows": {"2": form, "3": form, "4": form}}))
+    rng = np.random.default_rng(5)
+    g = torch.as_tensor(c.g).to(torch.complex128)
+    u = _rand(rng, c.n)
+    ref = cycle(P, g, u)
+    ud = to_dev(u, H.cdtype)
+    H.cycle(to_dev(g, H.cdtype), ud)
+    err = rel(ud, ref)
+    H.close()
+    print(m, mc, form, f"{err:.2e}")
+    assert err < TOL["c128"], err
+
+
 def test_solve_fp64_matches_oracle():
     from oracle.solve import fgmres
 
