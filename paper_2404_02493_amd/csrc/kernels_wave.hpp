@@ -50,6 +50,29 @@ __device__ __forceinline__ void tile_xy(int n, int t, int& j, int& i0) {
     i0 = (t / ntx) * TY + threadIdx.y * RPT;
 }
 
+// a on this block's 64 x 16 tile and a ring of R nodes into LDS s (row-major, width
+// TX + 2R; 0 off the unknowns), every load of a thread issued before its stores, so a
+// block waits for one memory round trip instead of one per loop iteration.
+template <int R, typename V>
+__device__ __forceinline__ void tile_load(const V* __restrict__ a, int n, int it, int jt, V* s) {
+    constexpr int W = TX + 2 * R, NR = (TY + 2 * R) * W, NQ = (NR + BLOCK - 1) / BLOCK;
+    const int tid = threadIdx.x + threadIdx.y * TX;
+    V v[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int q = tid + k * BLOCK;
+        const int ri = q / W, rj = q - ri * W;
+        const int gi = it - R + ri, gj = jt - R + rj;
+        v[k] = V{};
+        if (q < NR && gi >= 1 && gj >= 1 && gi < n && gj < n) v[k] = a[(size_t)gi * n + gj];
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int q = tid + k * BLOCK;
+        if (q < NR) s[q] = v[k];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ cplx<T> lap_at(const cplx<T>* __restrict__ u, int i, int j, int n, T inv_h2) {
     cplx<T> c = u[(size_t)i * n + j];
@@ -296,32 +319,46 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __res
                                                           const cplx<T>* __restrict__ g,
                                                           const cplx<T>* __restrict__ u, cplx<T>* __restrict__ r,
                                                           cplx<T>* __restrict__ d, T inv_theta) {
-    constexpr int HW = TX + 2, HH = TY + 2;
+    constexpr int UW = TX + 4, UH = TY + 4, HW = TX + 2, HH = TY + 2;
+    __shared__ cplx<T> su[UH * UW];
+    __shared__ cplx<T> sg[HH * HW];
+    __shared__ T sn[HH * HW];
     __shared__ cplx<T> ts[HH * HW];
+    const int n = G.n;
+    const T ih2 = T(G.inv_h2);
     int j, i0;
-    tile_origin(G.n, j, i0);
+    tile_origin(n, j, i0);
     const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
     const int tid = threadIdx.x + threadIdx.y * TX;
-    for (int q = tid; q < HH * HW; q += BLOCK) {
+    tile_load<2>(u, n, it, jt, su);
+    tile_load<1>(g, n, it, jt, sg);
+    tile_load<1>(n2, n, it, jt, sn);
+    __syncthreads();
+    for (int q = tid; q < HH * HW; q += BLOCK) {  // t = g - A u on the tile and a ring of one
         const int ri = q / HW, rj = q - ri * HW;
         const int gi = it - 1 + ri, gj = jt - 1 + rj;
         cplx<T> v{};
-        if (gi >= 1 && gj >= 1 && gi < G.n && gj < G.n) v = resid_at(G, n2, g, u, gi, gj);
+        if (gi >= 1 && gj >= 1 && gi < n && gj < n) {
+            const int l = (ri + 1) * UW + rj + 1;
+            const cplx<T> c = su[l];
+            const cplx<T> lap = ih2 * (T(4) * c - (((su[l - UW] + su[l + UW]) + su[l - 1]) + su[l + 1]));
+            v = sg[q] - (lap - kappa_at<T>(G, sn[q], gi, gj) * c);
+        }
         ts[q] = v;
     }
     __syncthreads();
-    if (j >= G.n) return;
+    if (j >= n) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        if (i >= G.n) break;
-        const size_t p = (size_t)i * G.n + j;
+        if (i >= n) break;
+        const size_t p = (size_t)i * n + j;
         cplx<T> v{};
         if (i > 0 && j > 0) {
             const int l = (i - it + 1) * HW + (j - jt + 1);
-            cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
+            cplx<T> kap = kappa_at<T>(G, sn[l], i, j);
             kap.im = -kap.im;
             const cplx<T> tc = ts[l];
-            v = T(G.inv_h2) * (T(4) * tc - (((ts[l - HW] + ts[l + HW]) + ts[l - 1]) + ts[l + 1])) - kap * tc;
+            v = ih2 * (T(4) * tc - (((ts[l - HW] + ts[l + HW]) + ts[l - 1]) + ts[l + 1])) - kap * tc;
         }
         r[p] = v;
         d[p] = inv_theta * v;
@@ -340,39 +377,63 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
                                                       const cplx<T>* __restrict__ d_in, cplx<T>* __restrict__ d_out,
                                                       cplx<T>* __restrict__ r, cplx<T>* __restrict__ u, T c1, T c2,
                                                       int mode) {
-    constexpr int HW = TX + 2, HH = TY + 2;
+    constexpr int DW = TX + 4, DH = TY + 4, HW = TX + 2, HH = TY + 2;
+    __shared__ cplx<T> sd[DH * DW];
+    __shared__ T sn[HH * HW];
     __shared__ cplx<T> ts[HH * HW];
+    const int n = G.n;
+    const T ih2 = T(G.inv_h2);
     int j, i0;
-    tile_origin(G.n, j, i0);
+    tile_origin(n, j, i0);
     const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
     const int tid = threadIdx.x + threadIdx.y * TX;
-    for (int q = tid; q < HH * HW; q += BLOCK) {
+    // the own rows of r and u are loaded with the tile fields, before the first barrier
+    cplx<T> rv0[RPT], uv0[RPT];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int i = i0 + rr;
+        rv0[rr] = uv0[rr] = cplx<T>{};
+        if (i >= 1 && i < n && j >= 1 && j < n) {
+            const size_t p = (size_t)i * n + j;
+            rv0[rr] = r[p];
+            if (!(mode & CHEB_UZERO)) uv0[rr] = u[p];
+        }
+    }
+    tile_load<2>(d_in, n, it, jt, sd);
+    tile_load<1>(n2, n, it, jt, sn);
+    __syncthreads();
+    for (int q = tid; q < HH * HW; q += BLOCK) {  // t = A d_in on the tile and a ring of one
         const int ri = q / HW, rj = q - ri * HW;
         const int gi = it - 1 + ri, gj = jt - 1 + rj;
         cplx<T> v{};
-        if (gi >= 1 && gj >= 1 && gi < G.n && gj < G.n) v = applyA_at(G, n2, d_in, gi, gj, false);
+        if (gi >= 1 && gj >= 1 && gi < n && gj < n) {
+            const int l = (ri + 1) * DW + rj + 1;
+            const cplx<T> c = sd[l];
+            const cplx<T> lap = ih2 * (T(4) * c - (((sd[l - DW] + sd[l + DW]) + sd[l - 1]) + sd[l + 1]));
+            v = lap - kappa_at<T>(G, sn[q], gi, gj) * c;
+        }
         ts[q] = v;
     }
     __syncthreads();
-    if (j >= G.n) return;
+    if (j >= n) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        if (i >= G.n) break;
-        const size_t p = (size_t)i * G.n + j;
+        if (i >= n) break;
+        const size_t p = (size_t)i * n + j;
         if (i == 0 || j == 0) {  // keep the ring of the alternate d buffer (and of u) zero
             if (!(mode & CHEB_LAST)) d_out[p] = cplx<T>{};
             if (mode & CHEB_UZERO) u[p] = cplx<T>{};
             continue;
         }
         const int l = (i - it + 1) * HW + (j - jt + 1);
-        cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
+        cplx<T> kap = kappa_at<T>(G, sn[l], i, j);
         kap.im = -kap.im;
         const cplx<T> tc = ts[l];
-        const cplx<T> aht = T(G.inv_h2) * (T(4) * tc - (((ts[l - HW] + ts[l + HW]) + ts[l - 1]) + ts[l + 1])) - kap * tc;
-        const cplx<T> dv = d_in[p];
-        const cplx<T> rv = r[p] - aht;
+        const cplx<T> aht = ih2 * (T(4) * tc - (((ts[l - HW] + ts[l + HW]) + ts[l - 1]) + ts[l + 1])) - kap * tc;
+        const cplx<T> dv = sd[(i - it + 2) * DW + (j - jt + 2)];
+        const cplx<T> rv = rv0[rr] - aht;
         const cplx<T> dn = c1 * dv + c2 * rv;
-        const cplx<T> u1 = ((mode & CHEB_UZERO) ? cplx<T>{} : u[p]) + dv;
+        const cplx<T> u1 = uv0[rr] + dv;
         if (mode & CHEB_LAST) {
             u[p] = u1 + dn;
         } else {
