@@ -187,6 +187,9 @@ def main():
                     help="only run a plain copy kernel of known size (reference for memory counters)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2404_02493_amd", "tuning.json"),
                     help="JSON cache of measured launch shapes ('none' = built-in defaults)")
+    ap.add_argument("--tuning", default=None,
+                    help="launch shapes to apply to the FP32-cycle context instead of measuring or "
+                         "reading a cache (the JSON of helm_set_tuning), e.g. for runs under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the solver has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -217,7 +220,11 @@ def main():
     H32 = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells)
     H32.set_phase(case.phi)
     tuning = None
-    if args.tune_cache != "none":
+    if args.tuning is not None:
+        H32.set_tuning(args.tuning)
+        tuning = H32.get_tuning()
+        log(f"tuning given: sstep_rows {tuning['sstep_rows']}, fgmres_blocks {tuning['fgmres_blocks']}")
+    elif args.tune_cache != "none":
         t = time.perf_counter()
         tuning = H32.tune(cache=args.tune_cache)
         log(f"tuning ({time.perf_counter() - t:.1f} s): sstep_rows {tuning['sstep_rows']}, "
