@@ -194,20 +194,20 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
 #pragma unroll
         for (int q = 0; q <= NK; ++q) kw[q][s] = cplx<T>{};
     }
+    // Every load is issued unconditionally: off the unknowns the row or column is replaced
+    // by 0, whose stored values are the zero ring of every field read here (px, py, c0, b
+    // and x0 all hold 0 on row 0 and column 0).  A load under a lane condition would sit
+    // in a branch, after which the compiler can only wait for every outstanding load,
+    // which would stall the prefetch at every row.
+    const int jcl = colok ? j : 0;
     auto load_row = [&](int r, cplx<T>& xv, cplx<T>& bv, T& fx, T& fy, cplx<T>& cv) {
-        if (r >= 1 && r <= n - 1 && colok) {
-            const unsigned p = (unsigned)(r * n + j);
-            if (X0) xv = ld_off(x0, p);
-            bv = ld_off(b, p);
-            fx = ld_off(px, p);
-            fy = ld_off(py, p);
-            cv = ld_off(c0, p);
-        } else {
-            xv = cplx<T>{};
-            bv = cplx<T>{};
-            fx = fy = T(0);
-            cv = cplx<T>{};
-        }
+        const int rcl = (r >= 1 && r <= n - 1) ? r : 0;
+        const unsigned p = (unsigned)(rcl * n + jcl);
+        if (X0) xv = ld_off(x0, p);
+        bv = ld_off(b, p);
+        fx = ld_off(px, p);
+        fy = ld_off(py, p);
+        cv = ld_off(c0, p);
     };
     static_for<P>([&](auto pc) {
         constexpr int s = decltype(pc)::value;
@@ -498,21 +498,15 @@ struct ModExtra {
     template <int SL>
     __device__ void load(int r) {
         if constexpr (EPI != EPI_X) {
-            if (r >= 1 && r <= n - 1 && colok) {
-                const unsigned p = (unsigned)(r * n + j);
-                cr[SL] = ld_off(a.car, p);
-                uu[SL] = ld_off(a.u, p);
-                if constexpr (EPI == EPI_MODRD) {
-                    gg[SL] = ld_off(a.g, p);
-                    nn[SL] = ld_off(a.n2, p);
-                }
-            } else {
-                cr[SL] = cplx<T>{};
-                uu[SL] = cplx<T>{};
-                if constexpr (EPI == EPI_MODRD) {
-                    gg[SL] = cplx<T>{};
-                    nn[SL] = T(0);
-                }
+            // unconditional, as the Krylov rows: off the unknowns row / column 0, where u is 0
+            // (the update there is u + 0 * car) and g, n2 feed no stored residual
+            const int rcl = (r >= 1 && r <= n - 1) ? r : 0;
+            const unsigned p = (unsigned)(rcl * n + (colok ? j : 0));
+            cr[SL] = ld_off(a.car, p);
+            uu[SL] = ld_off(a.u, p);
+            if constexpr (EPI == EPI_MODRD) {
+                gg[SL] = ld_off(a.g, p);
+                nn[SL] = ld_off(a.n2, p);
             }
         }
     }
