@@ -50,26 +50,36 @@ __device__ __forceinline__ void tile_xy(int n, int t, int& j, int& i0) {
     i0 = (t / ntx) * TY + threadIdx.y * RPT;
 }
 
-// a on this block's 64 x 16 tile and a ring of R nodes into LDS s (row-major, width
-// TX + 2R; 0 off the unknowns), every load of a thread issued before its stores, so a
-// block waits for one memory round trip instead of one per loop iteration.
+// a on this block's 64 x 16 tile and a ring of R nodes, staged for LDS (row-major, width
+// TX + 2R; 0 off the unknowns): tile_fetch issues a thread's loads into registers and
+// tile_store writes them, so that a kernel can issue the loads of all its tile fields
+// before it waits for any (one memory round trip per block).
+template <int R>
+struct TileRing {
+    static constexpr int W = TX + 2 * R, NR = (TY + 2 * R) * W, NQ = (NR + BLOCK - 1) / BLOCK;
+};
 template <int R, typename V>
-__device__ __forceinline__ void tile_load(const V* __restrict__ a, int n, int it, int jt, V* s) {
-    constexpr int W = TX + 2 * R, NR = (TY + 2 * R) * W, NQ = (NR + BLOCK - 1) / BLOCK;
+__device__ __forceinline__ void tile_fetch(const V* __restrict__ a, int n, int it, int jt,
+                                           V (&v)[TileRing<R>::NQ]) {
+    using TR = TileRing<R>;
     const int tid = threadIdx.x + threadIdx.y * TX;
-    V v[NQ];
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
+    for (int k = 0; k < TR::NQ; ++k) {
         const int q = tid + k * BLOCK;
-        const int ri = q / W, rj = q - ri * W;
+        const int ri = q / TR::W, rj = q - ri * TR::W;
         const int gi = it - R + ri, gj = jt - R + rj;
         v[k] = V{};
-        if (q < NR && gi >= 1 && gj >= 1 && gi < n && gj < n) v[k] = a[(size_t)gi * n + gj];
+        if (q < TR::NR && gi >= 1 && gj >= 1 && gi < n && gj < n) v[k] = a[(size_t)gi * n + gj];
     }
+}
+template <int R, typename V>
+__device__ __forceinline__ void tile_store(const V (&v)[TileRing<R>::NQ], V* s) {
+    using TR = TileRing<R>;
+    const int tid = threadIdx.x + threadIdx.y * TX;
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
+    for (int k = 0; k < TR::NQ; ++k) {
         const int q = tid + k * BLOCK;
-        if (q < NR) s[q] = v[k];
+        if (q < TR::NR) s[q] = v[k];
     }
 }
 
@@ -330,9 +340,14 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __res
     tile_origin(n, j, i0);
     const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
     const int tid = threadIdx.x + threadIdx.y * TX;
-    tile_load<2>(u, n, it, jt, su);
-    tile_load<1>(g, n, it, jt, sg);
-    tile_load<1>(n2, n, it, jt, sn);
+    cplx<T> fu[TileRing<2>::NQ], fg[TileRing<1>::NQ];
+    T fn[TileRing<1>::NQ];
+    tile_fetch<2>(u, n, it, jt, fu);
+    tile_fetch<1>(g, n, it, jt, fg);
+    tile_fetch<1>(n2, n, it, jt, fn);
+    tile_store<2>(fu, su);
+    tile_store<1>(fg, sg);
+    tile_store<1>(fn, sn);
     __syncthreads();
     for (int q = tid; q < HH * HW; q += BLOCK) {  // t = g - A u on the tile and a ring of one
         const int ri = q / HW, rj = q - ri * HW;
@@ -387,7 +402,11 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
     tile_origin(n, j, i0);
     const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
     const int tid = threadIdx.x + threadIdx.y * TX;
-    // the own rows of r and u are loaded with the tile fields, before the first barrier
+    // the tile fields and the own rows of r and u are all loaded before the first store
+    cplx<T> fd[TileRing<2>::NQ];
+    T fn[TileRing<1>::NQ];
+    tile_fetch<2>(d_in, n, it, jt, fd);
+    tile_fetch<1>(n2, n, it, jt, fn);
     cplx<T> rv0[RPT], uv0[RPT];
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
@@ -399,8 +418,8 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
             if (!(mode & CHEB_UZERO)) uv0[rr] = u[p];
         }
     }
-    tile_load<2>(d_in, n, it, jt, sd);
-    tile_load<1>(n2, n, it, jt, sn);
+    tile_store<2>(fd, sd);
+    tile_store<1>(fn, sn);
     __syncthreads();
     for (int q = tid; q < HH * HW; q += BLOCK) {  // t = A d_in on the tile and a ring of one
         const int ri = q / HW, rj = q - ri * HW;
