@@ -202,7 +202,7 @@ class Helmholtz:
         name = torch.cuda.get_device_name(self.device)
         return (f"{name}|n={self.n}|L={self.levels}|{'c64' if self.cdtype == torch.complex64 else 'c128'}"
                 f"|m={d.gmres_m}/{d.gmres_coarse_m}|adr={d.adr_levels}|tail={d.tail_n}|arnoldi={d.gmres_arnoldi}"
-                f"|restart={d.restart}|v3")
+                f"|restart={d.restart}|v4")
 
     def tune(self, cache: str | None = None, stream=None) -> dict:
         """Chooses launch shapes by measurement (helm_tune) and applies them.  With a

@@ -84,8 +84,11 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
     };
     const int reps = 5;
     // ADR levels that run the s-step form
+    // (coarsest level first, so that every level is timed inside what surrounds it in the
+    // cycle: a level below 2 as its V-cycle adding its prolongation into the next finer
+    // level, the fused tile epilogues included; level 2 as two ADR correction steps)
     if (c->L >= 3 && c->d.adr_steps > 0 && !c->d.gmres_arnoldi) {
-        for (int l = 2; l <= c->LA && l < 16; ++l) {
+        for (int l = std::min(c->LA, 15); l >= 2; --l) {
             AdrLevel& A = c->al[l];
             const int m = l == c->LA ? c->d.gmres_coarse_m : c->d.gmres_m;
             if (m > 4) continue;
@@ -93,6 +96,11 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
             const int nb = flat_blocks((size_t)A.n * A.n);
             hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.n, 17u + l, (cplx<T>*)A.b);
             hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.n, 91u + l, (cplx<T>*)A.x);
+            if (l == 2) {
+                WaveLevel& W = c->wl[2];
+                hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, W.n, 23u, (cplx<T>*)W.g);
+                hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, W.n, 29u, (cplx<T>*)W.u);
+            }
             HIPCHK(hipGetLastError());
             int best = 0;
             double tbest = 1e30;
@@ -100,8 +108,14 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
                 if (cand > 16 && cand >= 2 * A.n) break;
                 c->tn.sstep_rows[l] = cand;
                 const double t = time_ms(st, reps, [&] {
-                    E.gmres(l, m, true);
-                    E.gmres(l, m, false);
+                    if (l > 2) {
+                        E.adr_vcycle(l, EPI_X, nullptr, c->al[l - 1].x);
+                    } else if (c->phase_set) {
+                        E.adr_steps(2);
+                    } else {  // no carrier yet: the smoother pair alone
+                        E.gmres(l, m, true);
+                        E.gmres(l, m, false);
+                    }
                 });
                 note("sstep_l" + std::to_string(l) + "_" + (cand == 1 ? std::string("tile16") : cand == 2 ? std::string("tile32") : std::to_string(cand)), t);
                 if (t < tbest) {
