@@ -572,35 +572,33 @@ __global__ __launch_bounds__(BLOCK) void k_jac0_prolong_jacobi(Geom G, const Tf*
     tile_origin(n, j, i0);
     const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
     const int tid = threadIdx.x + threadIdx.y * TX;
-    // loads first: the own rows (g, n2 and the coarse values), then the ring node of the
-    // thread (two rows of TX and two columns of TY nodes; corners are not used)
+    // Loads first, all of them unconditional so that they are in flight together: a
+    // position off the grid reads index 0 of its array instead (the zero ring of g and ec;
+    // n2 there is not used).  The own rows (g, n2 and the coarse values), then the ring
+    // node of the thread (two rows of TX and two columns of TY nodes; corners unused).
     const bool injc = j >= 1 && j < n;
     cplx<Tf> gr[RPT];
     Tf nr[RPT];
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        gr[rr] = cplx<Tf>{};
-        nr[rr] = Tf(0);
-        if (injc && i >= 1 && i < n) {
-            const size_t p = (size_t)i * n + j;
-            gr[rr] = g[p];
-            nr[rr] = n2[p];
-        }
+        const size_t p = (injc && i >= 1 && i < n) ? (size_t)i * n + j : 0;
+        gr[rr] = g[p];
+        nr[rr] = n2[p];
     }
     // P ec on the own rows i0..i0+3 (i0 is a multiple of 4): coarse rows i0/2 .. i0/2 + 2,
     // columns J = j/2 and, for odd j, J + 1
     const int J = j >> 1, jodd = j & 1;
     auto ecl = [&](int a, int bb) -> cplx<Tc> {
-        if (a <= 0 || bb <= 0 || a >= nc || bb >= nc) return cplx<Tc>{};
-        return ec[(size_t)a * nc + bb];
+        const bool in = a >= 1 && bb >= 1 && a < nc && bb < nc;
+        return ec[in ? (size_t)a * nc + bb : 0];
     };
     cplx<Tc> e0[3], e1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int I = (i0 >> 1) + a;
         e0[a] = ecl(I, J);
-        e1[a] = jodd ? ecl(I, J + 1) : cplx<Tc>{};
+        e1[a] = ecl(I, J + 1);  // used for odd j only
     }
     const bool ring = tid < 2 * TX + 2 * TY;
     int gi = -1, gj = -1, lr = 0;
@@ -614,13 +612,12 @@ __global__ __launch_bounds__(BLOCK) void k_jac0_prolong_jacobi(Geom G, const Tf*
         gi = it + tid - 2 * TX - TY; gj = jt + TX; lr = (tid - 2 * TX - TY + 1) * HW + TX + 1;
     }
     const bool ringin = ring && gi >= 1 && gj >= 1 && gi < n && gj < n;
-    cplx<Tf> gh{};
-    Tf nh = Tf(0);
-    if (ringin) {
-        const size_t p = (size_t)gi * n + gj;
-        gh = g[p];
-        nh = n2[p];
-    }
+    const size_t ph = ringin ? (size_t)gi * n + gj : 0;
+    const cplx<Tf> gh = g[ph];
+    const Tf nh = n2[ph];
+    // bilinear value at the ring node from its four coarse neighbours (0 off the grid)
+    const int gI = ringin ? gi >> 1 : 0, gJ = ringin ? gj >> 1 : 0;
+    const cplx<Tc> q00 = ecl(gI, gJ), q10 = ecl(gI + 1, gJ), q01 = ecl(gI, gJ + 1), q11 = ecl(gI + 1, gJ + 1);
     cplx<Tf> wd[RPT], pe[RPT];
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
@@ -643,7 +640,20 @@ __global__ __launch_bounds__(BLOCK) void k_jac0_prolong_jacobi(Geom G, const Tf*
     }
     if (ring) {
         cplx<Tf> v{};
-        if (ringin) v = jac_wdiag<Tf>(G, nh, gi, gj, w) * gh + prolong_at<Tc, Tf>(ec, nc, gi, gj);
+        if (ringin) {
+            // the same cases and sums as prolong_at
+            const bool fo = gi & 1, go = gj & 1;
+            cplx<Tc> pv;
+            if (!fo && !go)
+                pv = q00;
+            else if (fo && !go)
+                pv = Tc(0.5) * (q00 + q10);
+            else if (!fo && go)
+                pv = Tc(0.5) * (q00 + q01);
+            else
+                pv = Tc(0.25) * (((q00 + q10) + q01) + q11);
+            v = jac_wdiag<Tf>(G, nh, gi, gj, w) * gh + ccast<Tf>(pv);
+        }
         us[lr] = v;
     }
     __syncthreads();
