@@ -414,13 +414,14 @@ __global__ __launch_bounds__(BLOCK) void k_fg_orth(size_t N, VecSet<T> V, cplx<T
     for (size_t p = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * E; p < N; p += (size_t)gridDim.x * BLOCK * E) {
         cplx<T> x[E];
         ld_pack<T, E>(w, p, x);
+        // every basis load is issued before the arithmetic, so they are all in flight at once
         cplx<T> v[J + 1][E];
 #pragma unroll
-        for (int iv = 0; iv <= J; ++iv) {
-            ld_pack_nt<T, E>(V.v[iv], p, v[iv]);
+        for (int iv = 0; iv <= J; ++iv) ld_pack_nt<T, E>(V.v[iv], p, v[iv]);
+#pragma unroll
+        for (int iv = 0; iv <= J; ++iv)
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = x[e] - cs[iv] * v[iv][e];
-        }
         st_pack<T, E>(w, p, x);
 #pragma unroll
         for (int iv = 0; iv <= J; ++iv)
