@@ -151,34 +151,25 @@ struct NoExtra {
     __device__ void load(int) {}
 };
 
-// Shared body of both passes.  Per step: prefetch row q + P (and ex's fields of it),
-// fold the stencil of row q, then K_0 (X0: on row q - 1) and K_1..K_NK on the rows
-// behind it; the finished row r = q - NK - D is handed to emit(r, slot, k) (k[j] =
-// K_j on row r; slot: the std::integral_constant ring position of row r) for the
-// unit's rows and XH rows beyond them on either side.
-template <typename T, int M, bool X0, bool GRAM, int XH, int EP, typename Extra, typename Emit>
-__device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __restrict__ px,
-                                            const T* __restrict__ py, const cplx<T>* __restrict__ c0,
-                                            const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
-                                            int& jcol, int& rb, int& re, cplx<T> (&xr)[8], Extra& ex,
-                                            Emit&& emit) {
+// Shared body of both passes.  Segments march down (DIR = +1) or up (DIR = -1) in
+// turn, so that the warm-up rows two vertically adjacent units share are read by both at
+// about the same time (at their starts or at their ends) and the second read hits L2.
+// Per step: prefetch row q + DIR P (and ex's fields of it), fold the stencil of row q,
+// then K_0 (X0: on row q - DIR) and K_1..K_NK on the rows behind it; the finished row
+// r = q - DIR (NK + D) is handed to emit(r, slot, k, dir) (k[j] = K_j on row r; slot: the
+// std::integral_constant ring position of row r; dir: std::integral_constant DIR) for
+// the unit's rows and XH rows beyond them on either side.
+template <typename T, int M, bool X0, bool GRAM, int XH, int EP, int DIR, typename Extra, typename Emit>
+__device__ __forceinline__ void sstep_march_dir(const AdrGeom& A, int S, const T* __restrict__ px,
+                                                const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                                const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
+                                                int j, bool colok, int rb, int re, cplx<T> (&xr)[8], Extra& ex,
+                                                Emit& emit) {
     using Mc = March<M, X0, GRAM, XH, EP>;
     constexpr int H = Mc::H, D = Mc::D, NK = Mc::NK, W = Mc::W, P = Mc::P;
     const int n = A.n;
-    const int lane = threadIdx.x;
-    const int ns = Mc::strips(n);
-    int u = blockIdx.x;
-    const int nb = gridDim.x;
-    u = xcd_remap(u, nb);  // neighbouring units on one XCD
-    const int sg = u / ns, st = u - sg * ns;
-    const int j = 1 + st * Mc::TXW - H + lane;
-    jcol = j;
-    const bool colok = j >= 1 && j <= n - 1;
-    const int R = Mc::rows(S);
-    rb = 1 + sg * R;
-    re = rb + R - 1 < n - 1 ? rb + R - 1 : n - 1;
-    const int qs = rb - H;
-    ex.init(j, colok, n);
+    // first row loaded: the segment's rows plus H warm-up rows on the side it starts from
+    const int q0 = DIR > 0 ? rb - H : rb + Mc::rows(S) - 1 + H;
 
     cplx<T> bw[W], kw[NK + 1][W];  // kw[NK] only holds the current row
     T fxw[W], fyw[W];
@@ -209,25 +200,32 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
         fy = ld_off(py, p);
         cv = ld_off(c0, p);
     };
+    // the neighbours of a ring row: the one loaded before it lies on the side the march
+    // comes from (south when marching down), the one loaded after it on the other side
+    auto apply = [&](const UpCoef<T>& k, cplx<T> c, cplx<T> before, cplx<T> after) {
+        if constexpr (DIR > 0)
+            return up_apply<T>(k, c, lane_prev(c), lane_next(c), before, after);
+        else
+            return up_apply<T>(k, c, lane_prev(c), lane_next(c), after, before);
+    };
     static_for<P>([&](auto pc) {
         constexpr int s = decltype(pc)::value;
-        load_row(qs + s, xr[s], bw[s], fxw[s], fyw[s], cw0[s]);
-        ex.template load<s>(qs + s);
+        load_row(q0 + DIR * s, xr[s], bw[s], fxw[s], fyw[s], cw0[s]);
+        ex.template load<s>(q0 + DIR * s);
     });
     for (int t0 = 0; t0 < S; t0 += W) {
         static_for<W>([&](auto sc) {
             constexpr int s = decltype(sc)::value;
-            const int q = qs + t0 + s;
-            // prefetch row q + P
+            const int q = q0 + DIR * (t0 + s);
+            // prefetch row q + DIR P
             constexpr int s1 = (s + P) % W;
-            load_row(q + P, xr[s1], bw[s1], fxw[s1], fyw[s1], cw0[s1]);
-            ex.template load<s1>(q + P);
+            load_row(q + DIR * P, xr[s1], bw[s1], fxw[s1], fyw[s1], cw0[s1]);
+            ex.template load<s1>(q + DIR * P);
             cw[s] = up_coef<T>(A, fxw[s], fyw[s], cw0[s], q >= 1 && q <= n - 1 && colok);
             // K_0 (zero off the unknowns: b and the stencil factors are)
             if constexpr (X0) {
                 constexpr int sr = (s + W - 1) % W;
-                const cplx<T> c = xr[sr];
-                kw[0][sr] = bw[sr] - up_apply<T>(cw[sr], c, lane_prev(c), lane_next(c), xr[(s + W - 2) % W], xr[s]);
+                kw[0][sr] = bw[sr] - apply(cw[sr], xr[sr], xr[(s + W - 2) % W], xr[s]);
             } else {
                 kw[0][s] = bw[s];
             }
@@ -235,20 +233,46 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
             static_for<NK>([&](auto jc) {
                 constexpr int jj = decltype(jc)::value + 1;
                 constexpr int sr = (s + 2 * W - jj - D) % W;
-                const cplx<T> c = kw[jj - 1][sr];
-                kw[jj][sr] = up_apply<T>(cw[sr], c, lane_prev(c), lane_next(c), kw[jj - 1][(sr + W - 1) % W],
-                                         kw[jj - 1][(sr + 1) % W]);
+                kw[jj][sr] = apply(cw[sr], kw[jj - 1][sr], kw[jj - 1][(sr + W - 1) % W], kw[jj - 1][(sr + 1) % W]);
             });
-            const int r = q - NK - D;
+            const int r = q - DIR * (NK + D);
             if (r >= rb - XH && r <= re + XH) {
                 constexpr int sr = (s + 2 * W - NK - D) % W;
                 cplx<T> k[NK + 1];
 #pragma unroll
                 for (int jj = 0; jj <= NK; ++jj) k[jj] = kw[jj][sr];
-                emit(r, std::integral_constant<int, sr>{}, k);
+                emit(r, std::integral_constant<int, sr>{}, k, std::integral_constant<int, DIR>{});
             }
         });
     }
+}
+
+// The unit of this wavefront (column j of lane, rows [rb, re]) and its march, down on even
+// segments and up on odd ones.
+template <typename T, int M, bool X0, bool GRAM, int XH, int EP, typename Extra, typename Emit>
+__device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __restrict__ px,
+                                            const T* __restrict__ py, const cplx<T>* __restrict__ c0,
+                                            const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
+                                            int& jcol, int& rb, int& re, cplx<T> (&xr)[8], Extra& ex,
+                                            Emit&& emit) {
+    using Mc = March<M, X0, GRAM, XH, EP>;
+    constexpr int H = Mc::H;
+    const int n = A.n;
+    const int lane = threadIdx.x;
+    const int ns = Mc::strips(n);
+    const int u = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring units on one XCD
+    const int sg = u / ns, st = u - sg * ns;
+    const int j = 1 + st * Mc::TXW - H + lane;
+    jcol = j;
+    const bool colok = j >= 1 && j <= n - 1;
+    const int R = Mc::rows(S);
+    rb = 1 + sg * R;
+    re = rb + R - 1 < n - 1 ? rb + R - 1 : n - 1;
+    ex.init(j, colok, n);
+    if (sg & 1)
+        sstep_march_dir<T, M, X0, GRAM, XH, EP, -1>(A, S, px, py, c0, b, x0, j, colok, rb, re, xr, ex, emit);
+    else
+        sstep_march_dir<T, M, X0, GRAM, XH, EP, 1>(A, S, px, py, c0, b, x0, j, colok, rb, re, xr, ex, emit);
 }
 
 // acc += the Gram entries of one node's K_0..K_M (layout of k_sstep_gram), in FP64.
@@ -293,7 +317,7 @@ __global__ __launch_bounds__(64) void k_sstep_gram(AdrGeom A, int S, const T* __
     const bool own_lane = lane >= Mc::H && lane < 64 - Mc::H;
     NoExtra ex;
     sstep_march<T, M, X0, true, 0, -1>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
-                                       [&](int r, auto, const cplx<T>(&k)[M + 1]) {
+                                       [&](int r, auto, const cplx<T>(&k)[M + 1], auto) {
         (void)r;
         if (!(own_lane && j <= A.n - 1)) return;
         gram_add<T, M>(acc, k);
@@ -566,14 +590,14 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
     if constexpr (EPI == EPI_X) {
         NoExtra ex;
         sstep_march<T, M, X0, false, 0, EP>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
-                                            [&](int r, auto slot, const cplx<T>(&k)[M]) {
+                                            [&](int r, auto slot, const cplx<T>(&k)[M], auto) {
                                             const cplx<T> v = xval(slot, k);
                                             if (own_lane && j <= n - 1) st_off(xout, (unsigned)(r * n + j), v);
                                         });
     } else if constexpr (EPI == EPI_MOD) {
         ModExtra<T, EPI> ex(mod);
         sstep_march<T, M, X0, false, 0, EP>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
-                                            [&](int r, auto slot, const cplx<T>(&k)[M]) {
+                                            [&](int r, auto slot, const cplx<T>(&k)[M], auto) {
                                             constexpr int sr = decltype(slot)::value;
                                             const cplx<T> v = xval(slot, k);
                                             if (own_lane && j <= n - 1)
@@ -585,12 +609,12 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
         const Geom& G = mod.G;
         const T ih2 = T(G.inv_h2);
         sstep_march<T, M, X0, false, 1, EP>(
-            A, S, px, py, c0, b, x0, j, rb, re, xr, ex, [&](int r, auto slot, const cplx<T>(&k)[M]) {
+            A, S, px, py, c0, b, x0, j, rb, re, xr, ex, [&](int r, auto slot, const cplx<T>(&k)[M], auto dirc) {
                 constexpr int sr = decltype(slot)::value;
                 constexpr int s1 = (sr + W - 1) % W, s2 = (sr + W - 2) % W;
                 const cplx<T> v = xval(slot, k);
                 un[sr] = ex.uu[sr] + v * ex.cr[sr];
-                const int ri = r - 1;
+                const int ri = r - decltype(dirc)::value;  // the row emitted before this one
                 if (ri >= rb && ri <= re) {
                     const cplx<T> cu = un[s1];
                     const cplx<T> w = lane_prev(cu), e = lane_next(cu);
@@ -612,7 +636,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
 // x = sum_j c_j K_{j-1} on the own nodes, and since b - M x = K_0 - sum_j c_j K_j the
 // residual comes from one more Krylov vector instead of an application of M to x.  The
 // unit emits one row and column beyond its own, weights each residual row across lanes
-// (1 2 1) and, at every odd fine row 2I+1 whose row 2I is its own, combines the last
+// (1 2 1) and, at every odd fine row whose neighbour emitted before it (2I) is its own, combines the last
 // three rows (1 2 1) / 16 into the coarse row I of rc (n/2 nodes per side) at the own
 // even columns.  Also writes the zero rings of x and rc.
 template <typename T, int M>
@@ -650,7 +674,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const
     cplx<T> hr[W];  // residual rows weighted across lanes, by ring slot
     NoExtra ex;
     sstep_march<T, M, false, true, 1, -1>(A, S, px, py, c0, b, nullptr, j, rb, re, xr, ex,
-                                          [&](int r, auto slot, const cplx<T>(&k)[M + 1]) {
+                                          [&](int r, auto slot, const cplx<T>(&k)[M + 1], auto dirc) {
         constexpr int sr = decltype(slot)::value;
         constexpr int s1 = (sr + W - 1) % W, s2 = (sr + W - 2) % W;
         cplx<T> xv{};
@@ -662,8 +686,9 @@ __global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const
         }
         if (own_lane && j <= n - 1 && r >= rb && r <= re) st_off(xout, (unsigned)(r * n + j), xv);
         hr[sr] = (lane_prev(rv) + lane_next(rv)) + T(2) * rv;
-        const int I = (r - 1) >> 1;
-        if ((r & 1) && r - 1 >= rb && r - 1 <= re && I >= 1) {
+        const int cm = r - decltype(dirc)::value;  // the middle one of the last three rows
+        const int I = cm >> 1;
+        if ((r & 1) && cm >= rb && cm <= re && I >= 1) {
             const cplx<T> v = T(1.0 / 16.0) * ((hr[s2] + hr[sr]) + T(2) * hr[s1]);
             if (own_lane && !(j & 1) && j <= n - 1) st_off(rc, (unsigned)(I * nc + (j >> 1)), v);
         }
