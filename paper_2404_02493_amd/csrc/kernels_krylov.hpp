@@ -1,8 +1,10 @@
 // Krylov kernels shared by the GMRES(m) ADR smoother and the outer FGMRES:
 // fused operator + inner-product passes, two-pass classical Gram-Schmidt with
 // re-orthogonalisation, the device-side Hessenberg least squares, and the
-// final combination x = x0 + V y.  All inner products accumulate in FP64 and
-// every grid reduction ends in the last block (no host round trip).
+// final combination x = x0 + V y.  Inner products are summed across threads and
+// blocks in FP64 (the outer FGMRES passes keep per-thread partial sums in the working
+// precision), and every grid reduction is finished on the device by a one-block
+// kernel (no host round trip).
 #pragma once
 
 #include "kernels_adr.hpp"
