@@ -965,26 +965,46 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, cons
     const int Ia = 1 + ti * TT, Ib = Ia + TT - 1 < n - 1 ? Ia + TT - 1 : n - 1;
     const int Ja = 1 + tj * TT, Jb = Ja + TT - 1 < n - 1 ? Ja + TT - 1 : n - 1;
     const int f0 = ti == 0 ? 1 : 2 * Ia, f1 = 2 * Ib + 1;
-    const int g0 = tj == 0 ? 1 : 2 * Ja, g1 = 2 * Jb + 1;
-    const int FC = g1 - g0 + 1, NF = (f1 - f0 + 1) * FC;
     const int i0 = Ia - H, j0 = Ja - H;  // coarse node of region (0, 0)
-    for (int q = threadIdx.x; q < NF; q += BLOCK) {
-        const int fr = q / FC;
-        const int f = f0 + fr, g = g0 + (q - fr * FC);
-        const int I = f >> 1, J = g >> 1;
+    // fine columns in pairs (2J, 2J + 1) over the tile's coarse columns J, one read-modify-
+    // write of both nodes per pair (16 bytes in FP32); column 1 alone on the first tiles
+    const int NP = Jb - Ja + 1, FR = f1 - f0 + 1;
+    for (int q = threadIdx.x; q < FR * NP; q += BLOCK) {
+        const int fr = q / NP;
+        const int f = f0 + fr, J = Ja + (q - fr * NP);
+        const int I = f >> 1;
         const int l = (I - i0) * RW + (J - j0);
-        cplx<T> v;
-        if (!(f & 1) && !(g & 1)) {
-            v = xs[l];
-        } else if ((f & 1) && !(g & 1)) {
-            v = T(0.5) * (xs[l] + xs[l + RW]);
-        } else if (!(f & 1) && (g & 1)) {
-            v = T(0.5) * (xs[l] + xs[l + 1]);
+        cplx<T> ve, vo;  // columns 2J and 2J + 1
+        if (!(f & 1)) {
+            ve = xs[l];
+            vo = T(0.5) * (xs[l] + xs[l + 1]);
         } else {
-            v = T(0.25) * (((xs[l] + xs[l + RW]) + xs[l + 1]) + xs[l + RW + 1]);
+            ve = T(0.5) * (xs[l] + xs[l + RW]);
+            vo = T(0.25) * (((xs[l] + xs[l + RW]) + xs[l + 1]) + xs[l + RW + 1]);
         }
-        const unsigned p = (unsigned)(f * nf + g);
-        st_off(xf, p, ld_off((const cplx<T>*)xf, p) + v);
+        const unsigned p = (unsigned)(f * nf + 2 * J);
+        if constexpr (sizeof(T) == 4) {
+            float4* a = reinterpret_cast<float4*>(reinterpret_cast<char*>(xf) + p * (unsigned)sizeof(cplx<T>));
+            float4 w4 = *a;
+            w4.x += ve.re;
+            w4.y += ve.im;
+            w4.z += vo.re;
+            w4.w += vo.im;
+            *a = w4;
+        } else {
+            st_off(xf, p, ld_off((const cplx<T>*)xf, p) + ve);
+            st_off(xf, p + 1, ld_off((const cplx<T>*)xf, p + 1) + vo);
+        }
+    }
+    if (tj == 0) {  // fine column 1: between coarse columns 0 (zero) and 1
+        for (int fr = threadIdx.x; fr < FR; fr += BLOCK) {
+            const int f = f0 + fr, I = f >> 1;
+            const int l = (I - i0) * RW + (0 - j0);
+            const cplx<T> v = (f & 1) ? T(0.25) * (((xs[l] + xs[l + RW]) + xs[l + 1]) + xs[l + RW + 1])
+                                      : T(0.5) * (xs[l] + xs[l + 1]);
+            const unsigned p = (unsigned)(f * nf + 1);
+            st_off(xf, p, ld_off((const cplx<T>*)xf, p) + v);
+        }
     }
 }
 
