@@ -351,10 +351,11 @@ struct Engine {
                            (const Pf*)c->wl[l].n2, (const cplx<Pf>*)g, (const cplx<Pf>*)u, (cplx<Pc>*)rc);
     }
     template <typename Pc, typename Pf>
-    void prolong_add(int l, const void* ec, void* u) {
+    void prolong_add(int l, const void* ec, void* u, bool assign = false) {
         const int n = c->wl[l].n;
-        LAUNCH(c, 2 * sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * NN(n / 2), (k_prolong_add<Pc, Pf>), dim3(tiles_of(n)), tile_block(), st, n,
-                           (const cplx<Pc>*)ec, (cplx<Pf>*)u);
+        const size_t np = (size_t)n * (n / 2);
+        LAUNCH(c, (assign ? 1 : 2) * sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * NN(n / 2), (k_prolong_pairs<Pc, Pf>),
+               dim3(flat_blocks(np)), dim3(BLOCK), st, n, (const cplx<Pc>*)ec, (cplx<Pf>*)u, assign ? 1 : 0);
     }
 
     void restrict_down(int l, const void* g, const void* u, void* rc) {
@@ -363,11 +364,11 @@ struct Engine {
         else
             resid_restrict<T, T>(l, g, u, rc);
     }
-    void prolong_up(int l, const void* ec, void* u) {
+    void prolong_up(int l, const void* ec, void* u, bool assign = false) {
         if (c->wl[l + 1].f64)
-            prolong_add<double, T>(l, ec, u);
+            prolong_add<double, T>(l, ec, u, assign);
         else
-            prolong_add<T, T>(l, ec, u);
+            prolong_add<T, T>(l, ec, u, assign);
     }
 
     // ---- the coarsest wave level (always FP64)
@@ -425,8 +426,7 @@ struct Engine {
         }
         restrict_down(l, W.g, u_zero ? nullptr : W.u, c->wl[l + 1].g);
         cycle_coarse(l + 1);
-        if (u_zero) zero<T>(W.u, N(l));
-        prolong_up(l, c->wl[l + 1].u, W.u);
+        prolong_up(l, c->wl[l + 1].u, W.u, u_zero);  // u = P e when no pre-smoothing ran
         if (l == 2) {
             chebyshev<T>(l, W.g, W.u, false, c->w[1], c->d.cheb_post);
             if (c->d.adr_steps > 0 && L >= 3) adr_steps(c->d.adr_steps);

@@ -281,6 +281,55 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(int n, const cplx<Tc>* __
     }
 }
 
+// u += P ec (assign: u = P ec) over pairs of fine columns (2J, 2J + 1): one coarse column
+// pair and one row parity per thread, one 16-byte read-modify-write per pair in FP32.
+// (n - 1) (n/2) pairs of rows 1..n-1 (assign also writes row 0); coarse values off the
+// unknowns read index 0 (the zero ring), so column 0 receives 0.
+template <typename Tc, typename Tf>
+__global__ __launch_bounds__(BLOCK) void k_prolong_pairs(int n, const cplx<Tc>* __restrict__ ec,
+                                                         cplx<Tf>* __restrict__ u, int assign) {
+    const int nc = n / 2;
+    const size_t NP = (size_t)n * nc;
+    auto e = [&](int a, int b) -> cplx<Tc> {
+        const bool in = a >= 1 && b >= 1 && a < nc && b < nc;
+        return ec[in ? (size_t)a * nc + b : 0];
+    };
+    for (size_t q = (size_t)blockIdx.x * BLOCK + threadIdx.x; q < NP; q += (size_t)gridDim.x * BLOCK) {
+        const int f = (int)(q / nc), J = (int)(q - (size_t)f * nc);
+        const size_t p = (size_t)f * n + 2 * J;
+        cplx<Tf> ve{}, vo{};
+        if (f > 0) {
+            const int I = f >> 1;
+            const cplx<Tc> e00 = e(I, J), e01 = e(I, J + 1);
+            cplx<Tc> a, b;
+            if (!(f & 1)) {
+                a = e00;
+                b = Tc(0.5) * (e00 + e01);
+            } else {
+                const cplx<Tc> e10 = e(I + 1, J), e11 = e(I + 1, J + 1);
+                a = Tc(0.5) * (e00 + e10);
+                b = Tc(0.25) * (((e00 + e10) + e01) + e11);
+            }
+            ve = ccast<Tf>(a);
+            vo = ccast<Tf>(b);
+        } else if (!assign) {
+            continue;  // row 0 is the ring
+        }
+        if constexpr (sizeof(Tf) == 4) {
+            float4* a4 = reinterpret_cast<float4*>(u + p);
+            float4 w4 = assign ? make_float4(0.f, 0.f, 0.f, 0.f) : *a4;
+            w4.x += ve.re;
+            w4.y += ve.im;
+            w4.z += vo.re;
+            w4.w += vo.im;
+            *a4 = w4;
+        } else {
+            u[p] = (assign ? cplx<Tf>{} : u[p]) + ve;
+            u[p + 1] = (assign ? cplx<Tf>{} : u[p + 1]) + vo;
+        }
+    }
+}
+
 // uout = uin + w (g - A uin) / (4/h^2 - kappa)   (damped Jacobi, out of place)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_jacobi(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
