@@ -192,6 +192,25 @@ def test_cycle_parity_gmres_depths(m, mc, form):
     assert err < TOL["c128"], err
 
 
+@pytest.mark.parametrize("n,levels,tail_n", [(16, 3, 0), (32, 4, 0), (32, 4, 64), (64, 5, 0)])
+def test_cycle_parity_tiny_grids(n, levels, tail_n):
+    """One FP64 cycle on tiny grids, where the ADR levels are a few nodes per side and
+    their s-step passes run in the default tile form (tail_n = 0) or the coarsest in one
+    workgroup."""
+    c = hi.make_problem(n, 0.6 * n, levels, seed=31, medium="grf", phase="fmm", damping_cells=4)
+    P, H = make_pair(c, "c128", tail_n=tail_n)
+    rng = np.random.default_rng(9)
+    g = torch.as_tensor(c.g).to(torch.complex128)
+    u = _rand(rng, c.n)
+    ref = cycle(P, g, u)
+    ud = to_dev(u, H.cdtype)
+    H.cycle(to_dev(g, H.cdtype), ud)
+    err = rel(ud, ref)
+    H.close()
+    print(n, levels, tail_n, f"{err:.2e}")
+    assert err < TOL["c128"], err
+
+
 def test_solve_fp64_matches_oracle():
     from oracle.solve import fgmres
 
