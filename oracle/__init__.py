@@ -22,7 +22,9 @@ adr       ADR coefficients, upwind ADR operator, GMRES(m), ADR V-cycle, ADR corr
 cycle     the Wave-ADR cycle (Algorithm 1) and the problem container
 solve     FGMRES(20) right-preconditioned by one cycle
 grad      loss after K unrolled cycles and its gradient (autograd and finite differences)
-dense     dense assemblies used only by the self-tests
+
+Dense assemblies of A, R and M used by the pins live in the tests themselves, so
+that they stay independent of this package.
 """
 from .grid import (level_size, damping_rho, kappa_level, apply_A, apply_Astar, restrict_fw,
                    prolong_bilinear, inject, cnorm, cdot)

@@ -7,9 +7,10 @@ Readings of the paper used here (each also listed in the design notes):
   re-discretised with h_l = 2^(l-1)/n and injected n^2 and damping;
 * smoothers: one damped Jacobi sweep before and after on level 1 (weight w[0]);
   Chebyshev(5) before and after on levels 2 and 4..L-1 (parameter alpha_l = w[l-1]);
-  Chebyshev(10) on level L and return; level 3 has no smoothing (the text's
-  "no iterations on the third level"; the literal post-smoother of Algorithm 1
-  is available with level3_literal=True);
+  Chebyshev(10) on level L and return; level 3 has no smoothing, following the
+  description of the wave cycle in Section 3.1 (Algorithm 1 read literally would
+  run a Chebyshev post-smoother there; that form is available with
+  level3_literal=True);
 * the branch order of Algorithm 1 is kept (l == 1, then l == L, then l == 3);
 * after the level-2 post-smoother, adr_steps ADR corrections (r, demodulate,
   ADR V-cycle, modulate-add) are applied; only the correction repeats;

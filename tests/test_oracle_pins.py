@@ -265,6 +265,30 @@ def test_T8_linear_phase_derivatives_exact():
     assert lap.abs().max() < 1e-9
 
 
+def test_T8_open_edge_is_one_sided_first_order():
+    """Second-order central differences inside and first-order one-sided ones at the
+    open edge x = 1 (the node x = 1 is not stored; Section 3.2.1): on phi = x^2 the
+    interior phi_x is exact and the edge value carries the backward-difference error
+    -h phi''/2; on phi = x^3 the interior phi_xx is exact and the edge value carries
+    the one-sided error -h times the third derivative.  Same along y."""
+    n = 32
+    h = 1.0 / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x)
+    for axis, C in ((1, X), (0, Y)):
+        px, py, _ = phase_derivatives(torch.as_tensor(C * C), h)
+        d = (px if axis == 1 else py).numpy()
+        exact = 2 * C
+        inner = (slice(1, n), slice(1, n - 1)) if axis == 1 else (slice(1, n - 1), slice(1, n))
+        edge = (slice(1, n), n - 1) if axis == 1 else (n - 1, slice(1, n))
+        assert np.allclose(d[inner], exact[inner], atol=1e-12)
+        assert np.allclose(d[edge], exact[edge] - h, atol=1e-12)
+        _, _, lap = phase_derivatives(torch.as_tensor(C**3), h)
+        lap = lap.numpy()
+        assert np.allclose(lap[inner], 6 * C[inner], atol=1e-9)
+        assert np.allclose(lap[edge], 6 * C[edge] - 6 * h, atol=1e-9)
+
+
 def test_T8_upwind_symbol():
     """On a(x) = e^{i(t1 j + t2 i)} the upwind operator acts (away from the ring) as
     (dx/h)(1 - e^{-i t1}) for dx > 0 and (dx/h)(e^{i t1} - 1) for dx < 0, plus the
@@ -600,3 +624,266 @@ def test_T18_autograd_gradient_matches_central_fd():
         e[i] = 1.0
         fd = (f(case.phi, w0 + 1e-6 * e) - f(case.phi, w0 - 1e-6 * e)) / 2e-6
         assert abs(fd - gw[i]) <= 1e-5 * max(abs(fd), abs(gw[i])) + 1e-9 * Lval, (i, fd, gw[i])
+
+
+# ---------------------------------------------------------------- sponge ramp and spectral bound
+def test_damping_ramp_values():
+    """The sponge ramp of the damped equation (Section 2): zero inside, one on the
+    boundary, linear over W fine cells (reading: r(t) = max(0, 1 - min(t, n - t)/W)
+    per axis, the larger of the two axes, injected to coarse levels).  Values written
+    out by hand for n = 16, W = 4."""
+    r16 = [1.0, 0.75, 0.5, 0.25, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.25, 0.5, 0.75]
+    rho = damping_rho(16, 1, 4).numpy()
+    for i in range(16):
+        for j in range(16):
+            assert rho[i, j] == max(r16[i], r16[j])
+    # coarse levels sample the fine ramp at the coincident nodes (I, J) = (2I, 2J)
+    assert np.array_equal(damping_rho(16, 2, 4).numpy(), rho[::2, ::2])
+    assert np.array_equal(damping_rho(16, 3, 4).numpy(), rho[::4, ::4])
+    # delta = strength rho^2 enters kappa as k^2 n^2 (1 + i sigma delta)
+    kap = kappa_level(torch.full((16, 16), 0.25, dtype=torch.float64), damping_rho(16, 1, 4), 10.0, 0.5, -1)
+    assert kap[1, 5] == 25.0 * (1 - 0.5j * 0.75**2)
+    assert kap[8, 8] == 25.0
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_gershgorin_bounds_spectrum_of_normal_operator(n):
+    """lambda_gershgorin is an upper bound of the spectrum of A^*A (the upper end of
+    the Chebyshev interval, eq. cheb) for heterogeneous, damped kappa: checked against
+    the eigenvalues of the dense A^*A; the bound is within a factor 2 of the true
+    largest eigenvalue on these grids."""
+    rng = np.random.default_rng(n)
+    for k, W in [(0.4 * n, 3), (1.2 * n, n // 4)]:
+        vel = 0.7 + 0.6 * rng.random((n, n))
+        P = Problem(vel, k, 2, damping_cells=W, adr_steps=0)
+        A = _dense_A(n, P.kappa[1].numpy())
+        ev = np.linalg.eigvalsh(A.conj().T @ A)
+        assert P.lam[1] >= ev.max() * (1 - 1e-12)
+        assert P.lam[1] <= 2.0 * ev.max()
+
+
+# ---------------------------------------------------------------- ADR step and ADR V-cycle compositions
+def _sparse_upwind_M(coef, n):
+    """Sparse ADR operator assembled node by node from eq. ADR with the upwind rule of
+    eq. upwind (written independently of apply_M: explicit stencil coefficients)."""
+    import scipy.sparse as sp
+
+    h, k, sigma = coef["h"], coef["k"], coef["sigma"]
+    px, py, c0 = coef["px"].numpy(), coef["py"].numpy(), coef["c0"].numpy()
+    pos = lambda i, j: (i - 1) * (n - 1) + (j - 1)
+    rows, cols, vals = [], [], []
+    for i in range(1, n):
+        for j in range(1, n):
+            fx, fy = px[i, j], py[i, j]
+            # grad(phi).grad(a): backward difference where the derivative is positive,
+            # forward where it is negative
+            bx, by = (fx, 0.0) if fx > 0 else (0.0, fx), (fy, 0.0) if fy > 0 else (0.0, fy)
+            adv = {(0, 0): (bx[0] - bx[1] + by[0] - by[1]) / h, (0, -1): -bx[0] / h, (0, 1): bx[1] / h,
+                   (-1, 0): -by[0] / h, (1, 0): by[1] / h}
+            lap = {(0, 0): 4 / h**2, (0, -1): -1 / h**2, (0, 1): -1 / h**2, (-1, 0): -1 / h**2, (1, 0): -1 / h**2}
+            for (di, dj), lv in lap.items():
+                a, b = i + di, j + dj
+                if 1 <= a <= n - 1 and 1 <= b <= n - 1:
+                    v = lv - 2j * sigma * k * adv[(di, dj)] + (c0[i, j] if (di, dj) == (0, 0) else 0.0)
+                    rows.append(pos(i, j))
+                    cols.append(pos(a, b))
+                    vals.append(v)
+    N = (n - 1) ** 2
+    return sp.csc_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def _sparse_central_M(coef, n):
+    """The same operator with central differences for grad(phi).grad(a) (the
+    unstabilised discretisation of Section 3.2.2)."""
+    import scipy.sparse as sp
+
+    h, k, sigma = coef["h"], coef["k"], coef["sigma"]
+    px, py, c0 = coef["px"].numpy(), coef["py"].numpy(), coef["c0"].numpy()
+    pos = lambda i, j: (i - 1) * (n - 1) + (j - 1)
+    rows, cols, vals = [], [], []
+    for i in range(1, n):
+        for j in range(1, n):
+            st = {(0, 0): 4 / h**2 + c0[i, j],
+                  (0, -1): -1 / h**2 - 2j * sigma * k * (-px[i, j] / (2 * h)),
+                  (0, 1): -1 / h**2 - 2j * sigma * k * (px[i, j] / (2 * h)),
+                  (-1, 0): -1 / h**2 - 2j * sigma * k * (-py[i, j] / (2 * h)),
+                  (1, 0): -1 / h**2 - 2j * sigma * k * (py[i, j] / (2 * h))}
+            for (di, dj), v in st.items():
+                a, b = i + di, j + dj
+                if 1 <= a <= n - 1 and 1 <= b <= n - 1:
+                    rows.append(pos(i, j))
+                    cols.append(pos(a, b))
+                    vals.append(v)
+    N = (n - 1) ** 2
+    return sp.csc_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def _direct_solver(M, n):
+    import scipy.sparse.linalg as spl
+
+    lu = spl.splu(M)
+
+    def solve(b):
+        out = torch.zeros((n, n), dtype=C128)
+        out[1:, 1:] = torch.as_tensor(lu.solve(b[1:, 1:].numpy().ravel()).reshape(n - 1, n - 1))
+        return out
+
+    return solve
+
+
+def _adr_step_exact(monkeypatch, P, r, solver):
+    """oracle adr_step on level 2 with its ADR V-cycle replaced by the given solver."""
+    import oracle.adr as OA
+
+    monkeypatch.setattr(OA, "adr_vcycle", lambda P_, l, b, x: solver(b))
+    return OA.adr_step(P, r, torch.zeros_like(r))
+
+
+@pytest.mark.parametrize("sigma", [1, -1])
+def test_adr_step_removes_characteristic_error(monkeypatch, sigma):
+    """A characteristic error e = a e^{i sigma k phi} (smooth envelope a, plane-wave
+    phase) has the residual r = A e.  One ADR step (Algorithm 1, the level-2 ADR
+    correction: demodulate, solve eq. ADR, re-modulate and add) with an exact ADR
+    solve must remove it up to the first-order upwind defect: the residual drops to
+    about 0.1 at kh = 1/4 and halves with h.  With the two carriers swapped the step
+    removes almost nothing, which pins the orientation of demodulation and
+    re-modulation (eq. Rytov: r_hat = r e^{-i sigma k phi}, e = a e^{+i sigma k phi})."""
+    k = 16.0
+    out = {}
+    for n in (128, 256):
+        n2 = n // 2
+        x = np.arange(n) / n
+        X, Y = np.meshgrid(x, x)
+        P = Problem(np.ones((n, n)), k, 4, damping_cells=n // 8, phi=0.8 * X + 0.6 * Y, sigma=sigma)
+        x2 = np.arange(n2) / n2
+        X2, Y2 = np.meshgrid(x2, x2)
+        env = np.exp(-((X2 - 0.45) ** 2 + (Y2 - 0.45) ** 2) / (2 * 0.08**2)).astype(np.complex128)
+        env[0, :] = 0
+        env[:, 0] = 0
+        e = P.carrier * torch.as_tensor(env)
+        r = apply_A(e, P.kappa[2], P.h[2])
+        solver = _direct_solver(_sparse_upwind_M(P.adr[2], n2), n2)
+        u = _adr_step_exact(monkeypatch, P, r, solver)
+        res = (cnorm(r - apply_A(u, P.kappa[2], P.h[2])) / cnorm(r)).item()
+        err = (cnorm(u - e) / cnorm(e)).item()
+        P.carrier, P.carrier_conj = P.carrier_conj, P.carrier
+        us = _adr_step_exact(monkeypatch, P, r, solver)
+        res_sw = (cnorm(r - apply_A(us, P.kappa[2], P.h[2])) / cnorm(r)).item()
+        out[n] = (res, err, res_sw)
+    (r1, e1, s1), (r2, e2, s2) = out[128], out[256]
+    assert r1 < 0.12 and r2 < 0.06, out
+    assert 1.7 < r1 / r2 < 2.3, out          # first order in h
+    assert e2 < 0.2 and e2 < e1, out
+    assert s1 > 0.7 and s2 > 0.7, out
+
+
+def _krylov_min(Mmat, b, x0, m):
+    """x0 + argmin over z in span{r0, M r0, ..., M^{m-1} r0} of ||b - M(x0 + z)||
+    by dense least squares over the explicit Krylov matrix (brute force GMRES(m))."""
+    r0 = b - Mmat @ x0
+    cols = [r0]
+    for _ in range(m - 1):
+        cols.append(Mmat @ cols[-1])
+    sc = [np.linalg.norm(c) for c in cols]
+    K = np.stack([c / s for c, s in zip(cols, sc)], axis=1)
+    y, *_ = np.linalg.lstsq(Mmat @ K, r0, rcond=1e-15)
+    return x0 + K @ y
+
+
+def test_adr_vcycle_two_levels_brute_force():
+    """The ADR V-cycle (Section 3.2.2: one V-cycle with GMRES(3) smoothing) on two
+    levels, rebuilt from dense pieces: GMRES(3) from zero by Krylov least squares,
+    the residual with the sparse upwind operator of eq. ADR / eq. upwind, full
+    weighting R, GMRES(mc) from zero on the coarse level with the coarse operator
+    re-discretised from the injected phase, prolongation 4 R^T, GMRES(3) from the
+    corrected iterate.  Dropping the coarse correction would change the result by
+    far more than the tolerance (checked)."""
+    n = 64
+    case = hi.make_problem(n, 30.0, 3, seed=4, medium="grf", phase="fmm", damping_cells=6)
+    P = Problem(case.velocity, case.k, 3, damping_cells=6, phi=case.phi, gmres_m=3, gmres_coarse_m=4,
+                adr_levels=2)
+    assert P.LA == 3
+    from oracle.adr import adr_vcycle
+
+    n2, n3 = n // 2, n // 4
+    M2 = _sparse_upwind_M(P.adr[2], n2).toarray()
+    M3 = _sparse_upwind_M(P.adr[3], n3).toarray()
+    R = _dense_R(n2)
+    rng = np.random.default_rng(8)
+    b = _rand_grid(rng, n2)
+    bv = b[1:, 1:].numpy().ravel()
+    x = _krylov_min(M2, bv, np.zeros_like(bv), 3)
+    rc = R @ (bv - M2 @ x)
+    ec = _krylov_min(M3, rc, np.zeros_like(rc), 4)
+    x_nc = _krylov_min(M2, bv, x, 3)
+    x = _krylov_min(M2, bv, x + 4 * R.T @ ec, 3)
+    ref = adr_vcycle(P, 2, b, None)[1:, 1:].numpy().ravel()
+    assert np.linalg.norm(ref - x) / np.linalg.norm(x) < 1e-9
+    assert np.linalg.norm(x_nc - x) / np.linalg.norm(x) > 1e-2
+
+
+# ---------------------------------------------------------------- T13c reflection
+def test_T13c_reflection_x_to_one_minus_x():
+    """Reflecting every input in x -> 1 - x reflects the cycle's output (velocity,
+    phase, source, iterate), including 8 ADR steps: phi_x changes sign and the upwind
+    side follows it (eq. upwind).  The phase is linear in x within three coarsest-ADR
+    cells of both edges, where the central and the one-sided differences agree, and
+    has a bump in the middle on which phi_x takes both signs."""
+    n, L = 64, 4
+    rng = np.random.default_rng(13)
+
+    def phase(x, y):
+        s = (x - 0.5) / 0.1
+        bump = np.where(np.abs(s) < 1, np.exp(-1.0 / np.maximum(1e-300, 1 - s * s)), 0.0)
+        return 0.7 * x + 0.05 * np.sin(2 * np.pi * y) + 0.2 * y + 0.6 * bump
+
+    x = np.arange(n) / n
+    X, Y = np.meshgrid(x, x)
+    px = np.gradient(phase(X, Y), axis=1) * n
+    assert px.min() < 0 < px.max()
+    vel = 1.0 + 0.3 * rng.random((n, n))
+
+    def refl(a):
+        out = np.zeros_like(a)
+        out[:, 1:] = a[:, :0:-1]
+        return out
+
+    vel_r = refl(vel)
+    vel_r[:, 0] = 1.0
+    P = Problem(vel, 0.5 * n, L, damping_cells=6, phi=phase(X, Y))
+    Pr = Problem(vel_r, 0.5 * n, L, damping_cells=6, phi=phase(1.0 - X, Y))
+    assert np.allclose(Pr.weights.numpy(), P.weights.numpy(), rtol=1e-14)
+    g = _rand_grid(rng, n).numpy()
+    u = _rand_grid(rng, n).numpy()
+    a = cycle(P, torch.as_tensor(g), torch.as_tensor(u)).numpy()
+    b = cycle(Pr, torch.as_tensor(refl(g)), torch.as_tensor(refl(u))).numpy()
+    assert np.linalg.norm(refl(a) - b) / np.linalg.norm(a) < 1e-12
+
+
+# ---------------------------------------------------------------- T15 upwind against central differences
+@pytest.mark.slow
+def test_T15_upwind_converges_central_diverges(monkeypatch):
+    """Section 3.2.2 (Figure discremethod): on the constant-medium problem with
+    N = 128 and omega = 20 pi, with the ADR system solved directly, the cycle
+    iteration converges with the upwind discretisation and diverges with central
+    differences."""
+    import oracle.adr as OA
+
+    n, k = 128, 20 * math.pi
+    x0 = np.array([[0.5, 0.5]])
+    phi = hi.analytic_phase(n, x0)
+    g = torch.as_tensor(hi.gaussian_sources(n, x0))
+    hist = {}
+    for name, build in [("upwind", _sparse_upwind_M), ("central", _sparse_central_M)]:
+        P = Problem(np.ones((n, n)), k, 4, damping_cells=16, phi=phi)
+        solver = _direct_solver(build(P.adr[2], n // 2), n // 2)
+        monkeypatch.setattr(OA, "adr_vcycle", lambda P_, l, b, x: solver(b))
+        u = torch.zeros_like(g)
+        h = []
+        for _ in range(20 if name == "upwind" else 3):
+            u = cycle(P, g, u)
+            h.append((cnorm(g - P.A(u)) / cnorm(g)).item())
+        hist[name] = h
+    up, ce = hist["upwind"], hist["central"]
+    assert up[-1] < 2e-3 and up[-1] < 1e-2 * up[0], up
+    assert ce[-1] > 1e3 * ce[0] > 1.0, ce
