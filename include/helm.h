@@ -2,13 +2,14 @@
  * helm.h -- C ABI of the MI355X (gfx950) Wave-ADR Helmholtz library (libhelm.so).
  *
  * Problem (paper Section 2, the damped equation and its 5-point discretisation):
- *     A u = -Delta_h u - kappa u = g,  kappa = k^2 n(x)^2 (1 + i sigma delta(x)),
+ *     A u = -Delta_h u - kappa u = g,  kappa = k^2 n(x)^2 (1 + i sigma (delta(x) + s0)),
  * on the unit square with zero Dirichlet values on the outer ring, where
  * n = 1/c is the slowness, k the angular frequency (the paper's omega) and
  * delta = damping_strength * rho^2 the sponge profile (rho ramps linearly from 0
  * to 1 over damping_cells fine cells towards the boundary, max over the axes).
  * sigma = +1 uses the carrier e^{+i k phi}; sigma = -1 is the paper's printed
- * sign convention (the complex conjugate of every operator).
+ * sign convention (the complex conjugate of every operator).  s0 = 0 unless the
+ * shifted equation of Section 4.3.2 is asked for (helm_desc.shift).
  *
  * Grid layout (every array argument): n x n nodes, n = 2^m, h = 1/n, row-major,
  * element (i, j) at offset i*n + j, i = y index, j = x index (x fastest).
@@ -83,6 +84,9 @@ typedef struct {
                                  4096 nodes) runs its GMRES in one workgroup (default 64; 0 = never) */
     int32_t wave_tail_n;      /* the wave levels >= 3 with at most wave_tail_n nodes per side run in
                                  one workgroup, all of them in a single launch (default 32; 0 = never) */
+    double shift;             /* relative imaginary shift s0 >= 0 of the shifted equation (Section 4.3.2,
+                                 gamma_0 = s0 k(x)^2 with k(x) = k n(x); the paper's test uses 0.01):
+                                 kappa = k^2 n^2 (1 + i sigma (delta + s0)); default 0 */
 } helm_desc;
 
 /* Defaults of every field for an n x n grid at frequency k:
@@ -108,7 +112,8 @@ helm_status helm_set_phase(helm_ctx ctx, const void* phi, int32_t phi_is_f64, vo
  * level l >= 2 (eq. cheb; interval [lambda_l/alpha_l, lambda_l]).  alpha_l >= 1. */
 helm_status helm_set_weights(helm_ctx ctx, const double* w);
 helm_status helm_get_weights(helm_ctx ctx, double* w);
-/* Spectral bound lambda_l of A_l^* A_l used by Chebyshev (host out, `levels` doubles). */
+/* Upper end lambda_l of the Chebyshev interval (eq. cheb), the Gershgorin bound of the
+ * spectrum of A_l^* A_l, (max |4/h_l^2 - kappa_l| + 4/h_l^2)^2 (host out, `levels` doubles). */
 helm_status helm_get_lambdas(helm_ctx ctx, double* lam);
 
 /* One Wave-ADR cycle (paper Algorithm 1) on the fine grid: u <- C(u, g).
@@ -124,12 +129,16 @@ helm_status helm_cycle(helm_ctx ctx, const void* g, void* u, void* stream);
  * iters (host out): preconditioner applications; relres (host out): true FP64
  * relative residual at exit; history (host out, may be NULL): maxit+1 doubles,
  * the residual estimate after each iteration.  Returns HELM_ENOCONV if tol was
- * not reached within maxit (iters and relres still filled). */
+ * not reached within maxit (iters and relres still filled), HELM_EBREAKDOWN if g or
+ * the initial u holds NaN or Inf (nothing is iterated; u is left as given, iters = 0)
+ * or if the residual becomes non-finite or grows above 1e4 times its initial value. */
 helm_status helm_solve(helm_ctx ctx, const void* g, void* u, double tol, int32_t maxit, int32_t mode,
                        int32_t* iters, double* relres, double* history, void* stream);
 
-/* FP64 residual on the fine grid: r = g - A u (device, complex128, r may be NULL)
- * and its 2-norm plus ||g|| (host out, may be NULL).  Synchronises the stream. */
+/* FP64 residual of the discrete damped equation (Section 2, the 5-point stencil with
+ * the sponge term) on the fine grid: r = g - A u (device, complex128, r may be NULL)
+ * and its 2-norm plus ||g|| (host out, may be NULL), the quantities of the stopping
+ * test ||r|| / ||g|| (Section 4.3.1).  Synchronises the stream. */
 helm_status helm_residual(helm_ctx ctx, const void* g, const void* u, void* r, double* rnorm,
                           double* gnorm, void* stream);
 

@@ -49,10 +49,11 @@ def phase_derivatives(phi: torch.Tensor, h: float):
     return _mask_ring(px), _mask_ring(py), _mask_ring(lap)
 
 
-def adr_coefficients(phi_l, n2_l, rho_l, k, strength, sigma, h):
-    """Per-level coefficients of M: phi_x, phi_y and the reaction term c0 (eq. ADR)."""
+def adr_coefficients(phi_l, n2_l, rho_l, k, strength, sigma, h, shift: float = 0.0):
+    """Per-level coefficients of M: phi_x, phi_y and the reaction term c0 (eq. ADR);
+    the relative shift s0 of the shifted equation enters c0 like the sponge term."""
     px, py, lap = phase_derivatives(phi_l, h)
-    delta = strength * rho_l * rho_l
+    delta = strength * rho_l * rho_l + shift
     c0 = (-1j * sigma * k) * lap + (k * k) * (px * px + py * py - n2_l) \
         - 1j * sigma * (k * k) * n2_l * delta
     return dict(px=px, py=py, c0=_mask_ring(c0), h=h, k=k, sigma=sigma)

@@ -35,13 +35,14 @@ class Problem:
 
     velocity: (n, n) array c(x) > 0 (n^2 = 1/c^2 on the fine grid).
     weights:  length-L vector, w[0] = Jacobi weight, w[l-1] = Chebyshev alpha_l.
+    shift:    relative imaginary shift s0 of the shifted equation (Section 4.3.2).
     phi:      fine-grid phase (n, n); may be a tensor that requires grad."""
 
     def __init__(self, velocity, k: float, levels: int, damping_cells: int = 16,
                  damping_strength: float = 0.5, sigma: int = 1, adr_steps: int = 8,
                  cheb_pre: int = 5, cheb_post: int = 5, cheb_coarse: int = 10,
                  gmres_m: int = 3, gmres_coarse_m: int = 3, level3_literal: bool = False,
-                 weights=None, phi=None, adr_levels=3):
+                 weights=None, phi=None, adr_levels=3, shift: float = 0.0):
         vel = torch.as_tensor(np.asarray(velocity, dtype=np.float64))
         self.n = int(vel.shape[0])
         if self.n & (self.n - 1) or self.n < 8:
@@ -53,6 +54,7 @@ class Problem:
         self.W = int(damping_cells)
         self.strength = float(damping_strength)
         self.sigma = int(sigma)
+        self.shift = float(shift)
         self.adr_steps = int(adr_steps)
         self.cheb_pre, self.cheb_post, self.cheb_coarse = cheb_pre, cheb_post, cheb_coarse
         self.gmres_m, self.gmres_coarse_m = gmres_m, gmres_coarse_m
@@ -68,7 +70,7 @@ class Problem:
             self.h[l] = 1.0 / nl
             self.n2[l] = inject(self.n2_fine, l)
             self.rho[l] = damping_rho(self.n, l, self.W)
-            self.kappa[l] = kappa_level(self.n2[l], self.rho[l], self.k, self.strength, self.sigma)
+            self.kappa[l] = kappa_level(self.n2[l], self.rho[l], self.k, self.strength, self.sigma, self.shift)
             self.lam[l] = lambda_gershgorin(self.kappa[l], self.h[l])
         self.weights = self.default_weights() if weights is None else torch.as_tensor(weights, dtype=F64)
         self.adr = {}
@@ -97,7 +99,7 @@ class Problem:
         self.adr = {}
         for l in range(2, self.LA + 1):
             self.adr[l] = adr_coefficients(inject(phi, l), self.n2[l], self.rho[l], self.k,
-                                           self.strength, self.sigma, self.h[l])
+                                           self.strength, self.sigma, self.h[l], self.shift)
         phi2 = inject(phi, 2)
         arg = (self.sigma * self.k) * phi2
         self.carrier = torch.complex(torch.cos(arg), torch.sin(arg))

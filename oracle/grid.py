@@ -41,13 +41,15 @@ def damping_rho(n: int, level: int, cells: int) -> torch.Tensor:
 
 
 def kappa_level(n2_l: torch.Tensor, rho_l: torch.Tensor, k: float, strength: float,
-                sigma: int) -> torch.Tensor:
-    """kappa = k^2 n^2 (1 + i sigma delta), delta = strength * rho^2.
+                sigma: int, shift: float = 0.0) -> torch.Tensor:
+    """kappa = k^2 n^2 (1 + i sigma (delta + s0)), delta = strength * rho^2.
 
     The damped equation (Section 2) adds i*omega*gamma/c^2 to -Delta - omega^2/c^2;
     with gamma/omega = delta this is -kappa with sigma = -1 (paper's sign) or the
-    conjugate with sigma = +1."""
-    delta = strength * rho_l * rho_l
+    conjugate with sigma = +1.  The shifted equation (Section 4.3.2) adds
+    i gamma_0 u with gamma_0 = 0.01 k(x)^2; reading: k(x) = k n(x) is the local
+    wavenumber, so the shift is the relative term s0 = gamma_0 / k(x)^2 (0.01 there)."""
+    delta = strength * rho_l * rho_l + shift
     return (k * k) * n2_l * (1.0 + 1j * sigma * delta)
 
 

@@ -43,6 +43,7 @@ class HelmDesc(ctypes.Structure):
         ("adr_levels", ctypes.c_int32),
         ("tail_n", ctypes.c_int32),
         ("wave_tail_n", ctypes.c_int32),
+        ("shift", ctypes.c_double),
     ]
 
 

@@ -61,7 +61,8 @@ using c128 = cplx<double>;
 //   s      stride of the level in fine-grid indices, 2^(l-1)
 //   nf     fine-grid nodes per side
 //   W      sponge width in fine cells (ramp 1 - d/W evaluated as 1 - d * inv_W)
-// kappa(i, j) = k2 * n2(i, j) * (1 + i * sig_str * rho^2), rho from the indices.
+//   sig_shift  sigma times the relative shift s0 of the shifted equation
+// kappa(i, j) = k2 * n2(i, j) * (1 + i * (sig_str * rho^2 + sig_shift)), rho from the indices.
 struct Geom {
     int n;
     int s;
@@ -71,6 +72,7 @@ struct Geom {
     double inv_h2;
     double k2;
     double sig_str;
+    double sig_shift;
 };
 
 template <typename T>
@@ -86,7 +88,7 @@ __device__ __forceinline__ cplx<T> kappa_at(const Geom& G, T n2, int i, int j) {
     T rj = sponge_ramp<T>(j * G.s, G.nf, T(G.inv_W));
     T rho = ri > rj ? ri : rj;
     T kr = T(G.k2) * n2;
-    return {kr, kr * (T(G.sig_str) * (rho * rho))};
+    return {kr, kr * (T(G.sig_str) * (rho * rho) + T(G.sig_shift))};
 }
 
 // Workgroup b of nb is dispatched to XCD b mod 8 (round robin).  This renumbering gives

@@ -202,6 +202,7 @@ static Geom make_geom(const helm_ctx c, int level) {
     G.inv_h2 = double(G.n) * double(G.n);
     G.k2 = c->d.k * c->d.k;
     G.sig_str = double(c->d.sign) * c->d.damping_strength;
+    G.sig_shift = double(c->d.sign) * c->d.shift;
     return G;
 }
 
@@ -957,6 +958,7 @@ static void validate(const helm_desc* d) {
     REQUIRE(d->k > 0 && std::isfinite(d->k), "k must be positive");
     REQUIRE(d->damping_cells >= 1, "damping_cells must be >= 1");
     REQUIRE(d->damping_strength >= 0 && std::isfinite(d->damping_strength), "damping_strength must be >= 0");
+    REQUIRE(d->shift >= 0 && std::isfinite(d->shift), "shift must be >= 0");
     REQUIRE(d->sign == 1 || d->sign == -1, "sign must be +1 or -1");
     REQUIRE(d->cycle_prec == HELM_C64 || d->cycle_prec == HELM_C128, "cycle_prec must be HELM_C64 or HELM_C128");
     REQUIRE(d->adr_steps >= 0 && d->adr_steps <= 64, "adr_steps must be in [0, 64]");
@@ -1228,6 +1230,12 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
     residual_fp64(c, st, g, u, c->fV[0], &rn, &gn);
     std::vector<double> hist;
     int its = 0;
+    if (!std::isfinite(gn) || !std::isfinite(rn)) {
+        // NaN or Inf in g or in the initial iterate: nothing is iterated, u is left as given
+        *iters = 0;
+        *relres = rn / gn;
+        return HELM_EBREAKDOWN;
+    }
     if (!(gn > 0.0)) {
         LAUNCH(c, 16.0 * double(NF), (k_zero<double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF, (c128*)u);
         HIPCHK(hipStreamSynchronize(st));
@@ -1356,6 +1364,7 @@ void helm_desc_default(helm_desc* d, int32_t n, double k) {
     d->tail_n = 64;
     d->wave_tail_n = 32;
     d->adr_levels = 3;
+    d->shift = 0.0;
 }
 
 helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* out, void* stream) {

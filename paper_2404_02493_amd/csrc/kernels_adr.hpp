@@ -68,7 +68,7 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __rest
         const double nn = n2f[(size_t)i * s * nf + (size_t)j * s];
         const double ri = sponge_ramp<double>(i * s, nf, G.inv_W), rj = sponge_ramp<double>(j * s, nf, G.inv_W);
         const double rho = ri > rj ? ri : rj;
-        const double delta = strength * rho * rho;
+        const double delta = strength * rho * rho + double(sigma) * G.sig_shift;  // sponge plus shift
         const double k2 = k * k;
         const double re = k2 * ((px * px + py * py) - nn);
         const double im = -(double(sigma) * k) * lap - ((double(sigma) * k2) * nn) * delta;

@@ -48,6 +48,8 @@ CASES = {
     "grf64": (64, 40.0, 4, 11, "grf", "fmm", 8, 2, {}),
     "const128_variant": (128, 80.0, 5, 3, "const", "analytic", 16, 1,
                          dict(sign=-1, level3_literal=1, gmres_m=2, gmres_coarse_m=4, adr_steps=3)),
+    # heterogeneous 256^2 medium, three cycles, the default sponge of one wavelength
+    "grf256": (256, 160.0, 5, 7, "grf", "fmm", None, 3, {}),
 }
 
 
@@ -60,7 +62,8 @@ def oracle_grads():
             n, k, L, seed, med, ph, W, K, kw = CASES[name]
             case = hi.make_problem(n, k, L, seed=seed, medium=med, phase=ph, damping_cells=W)
             okw = {key: v for key, v in kw.items() if key != "sign"}
-            P = Problem(case.velocity, case.k, case.levels, damping_cells=W, sigma=kw.get("sign", 1), **okw)
+            P = Problem(case.velocity, case.k, case.levels, damping_cells=case.damping_cells,
+                        sigma=kw.get("sign", 1), **okw)
             w = P.weights.numpy().copy()
             Lo, dphi, dw = grad_autograd(P, torch.as_tensor(case.g), K, case.phi, w)
             cache[name] = (case, w, K, kw, Lo, dphi, dw)

@@ -48,6 +48,18 @@ def test_batch_equals_single_solves(small_batch, prec, mode):
         assert it == its[p] and r == rr[p]
         assert torch.equal(u, us[p]), p
         H.close()
+    if prec == "c128":
+        # one problem of the batch against the FP64 oracle's FGMRES(20)
+        from oracle.cycle import Problem
+        from oracle.solve import fgmres
+
+        p = min(range(len(small_batch)), key=lambda q: small_batch[q].n)
+        c = small_batch[p]
+        P = Problem(c.velocity, c.k, c.levels, damping_cells=c.damping_cells, phi=c.phi)
+        x_or, its_or, rr_or, ok = fgmres(P, torch.as_tensor(c.g), tol=1e-6, maxit=400)
+        err = (torch.linalg.norm(us[p].cpu() - x_or) / torch.linalg.norm(x_or)).item()
+        print("batch problem", p, "n", c.n, "iterations", its[p], "oracle", its_or, "error", err, flush=True)
+        assert ok and abs(int(its[p]) - its_or) <= 1 and err < 1e-6
     B.close()
 
 
