@@ -142,6 +142,17 @@ helm_status helm_solve(helm_ctx ctx, const void* g, void* u, double tol, int32_t
 helm_status helm_residual(helm_ctx ctx, const void* g, const void* u, void* r, double* rnorm,
                           double* gnorm, void* stream);
 
+/* helm_residual without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops or harnesses that forbid hipMalloc): the
+ * same results bit for bit, with the reduction scratch (per-block partial sums, at most
+ * 2 * 2048 doubles, and the two totals) in one static device array per GPU that the
+ * library holds until the process ends, instead of the context's workspace.  Calls that
+ * overlap on one GPU share that array and race; a call on the same stream after another
+ * is safe (every call rewrites the partials it reads).  Every grid the context accepts
+ * (n <= 8192) fits; a larger reduction would give HELM_EINVAL.  Synchronises the stream. */
+helm_status helm_residual_noalloc(helm_ctx ctx, const void* g, const void* u, void* r, double* rnorm,
+                                  double* gnorm, void* stream);
+
 /* Adjoint of K unrolled cycles (Section 3.3: the training loss after K cycles,
  * eq. loss, and its back-propagation; Algorithm 1 reversed).
  *   u_{k+1} = C(u_k, g), k = 0..K-1, from u_0 (device, cycle_prec, NULL = zero).

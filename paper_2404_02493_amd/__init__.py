@@ -141,15 +141,17 @@ class Helmholtz:
         n = its.value if mode == 0 else len([h for h in hist[: maxit + 1] if h > 0])
         return u, its.value, rr.value, np.array(hist[: max(n, 0)])
 
-    def residual(self, g, u, r=None, stream=None):
-        """(r = g - A u, ||r||, ||g||) in FP64."""
+    def residual(self, g, u, r=None, noalloc: bool = False, stream=None):
+        """(r = g - A u, ||r||, ||g||) in FP64; noalloc=True takes the entry point whose
+        reduction scratch is the library's static device array (no allocation)."""
         torch = _torch()
         g = self._grid(g, torch.complex128)
         u = self._grid(u, torch.complex128)
         r = torch.empty_like(g) if r is None else r
         rn = ctypes.c_double()
         gn = ctypes.c_double()
-        check(lib().helm_residual(self._ctx, _ptr(g), _ptr(u), _ptr(r), ctypes.byref(rn), ctypes.byref(gn), _stream_ptr(stream)))
+        fn = lib().helm_residual_noalloc if noalloc else lib().helm_residual
+        check(fn(self._ctx, _ptr(g), _ptr(u), _ptr(r), ctypes.byref(rn), ctypes.byref(gn), _stream_ptr(stream)))
         return r, rn.value, gn.value
 
     # ------------------------------------------------------------------ unrolled cycles and their adjoint

@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -1313,6 +1314,59 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
 #include "batch.hpp"
 #include "tune.hpp"
 
+// ------------------------------------------------------------------ allocation-free residual
+// helm_residual_noalloc keeps its reduction scratch in this file-scope device array
+// instead of the context's workspace: the per-block partial sums of ||r||^2 and ||g||^2
+// (two doubles for each of at most MAXRED blocks), then the two totals.  Each GPU holds
+// its own copy for the life of the process.  In host code the name `scratch` is only a
+// host-side handle; the device address comes from hipGetSymbolAddress, resolved once per
+// device (helm_setup, or the first call on a device) and kept in g_scratch_dev.
+constexpr size_t NOALLOC_PARTIALS = 2 * (size_t)MAXRED;
+constexpr size_t NOALLOC_DOUBLES = NOALLOC_PARTIALS + 32;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device.
+static double* noalloc_scratch() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        throw Error(HELM_EINVAL, "device ordinal " + std::to_string(dev) + " beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(HELM_EHIP, "hipGetSymbolAddress returned a null address for the residual scratch");
+        g_scratch_dev[dev] = (double*)p;
+    }
+    return g_scratch_dev[dev];
+}
+
+// FP64 residual and norms of residual_fp64 with the reduction in `scratch`: no
+// allocation, no event, no graph; the same kernels in the same order, so the results
+// equal helm_residual's bit for bit.
+static void residual_fp64_noalloc(helm_ctx c, hipStream_t st, const void* g, const void* u, void* r, double* rn,
+                                  double* gn) {
+    const Geom G = make_geom(c, 1);
+    const int nbt = red_blocks(G.n);
+    if ((size_t)2 * nbt > NOALLOC_PARTIALS)
+        throw Error(HELM_EINVAL, "helm_residual_noalloc: " + std::to_string(nbt) + " reduction blocks exceed the " +
+                                     std::to_string(NOALLOC_PARTIALS / 2) + " of the static scratch");
+    double* sp = noalloc_scratch();
+    hipLaunchKernelGGL(k_residual_norms, dim3(nbt), tile_block(), 0, st, G, (const double*)c->n2f, (const c128*)g,
+                       (const c128*)u, (c128*)r, sp);
+    hipLaunchKernelGGL((k_finalize_sums<2>), dim3(1), dim3(FBLOCK), 0, st, (const double*)sp, nbt, 2,
+                       sp + NOALLOC_PARTIALS);
+    HIPCHK(hipGetLastError());
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, sp + NOALLOC_PARTIALS, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (rn) *rn = std::sqrt(h[0]);
+    if (gn) *gn = std::sqrt(h[1]);
+}
+
 }  // namespace helm
 
 // ================================================================== C ABI
@@ -1376,6 +1430,7 @@ helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* 
         c->d = *desc;
         try {
             build(c, velocity, (hipStream_t)stream);
+            (void)noalloc_scratch();
         } catch (...) {
             helm_destroy(c);
             throw;
@@ -1459,6 +1514,15 @@ helm_status helm_residual(helm_ctx ctx, const void* g, const void* u, void* r, d
     ABI_GUARD({
         REQUIRE(ctx != nullptr && g != nullptr && u != nullptr, "NULL argument");
         residual_fp64(ctx, (hipStream_t)stream, g, u, r, rnorm, gnorm);
+        return HELM_OK;
+    })
+}
+
+helm_status helm_residual_noalloc(helm_ctx ctx, const void* g, const void* u, void* r, double* rnorm,
+                                  double* gnorm, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && u != nullptr, "NULL argument");
+        residual_fp64_noalloc(ctx, (hipStream_t)stream, g, u, r, rnorm, gnorm);
         return HELM_OK;
     })
 }
