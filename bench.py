@@ -96,6 +96,73 @@ def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):
                     "re-recording of the tape"}
 
 
+HBM_CLEAN = ("k_jac0_restrict", "k_jac0_prolong_jacobi", "k_fg_arnoldi", "k_fg_orth")
+
+
+def hbm_rooflines(kernels):
+    """Kernels of the 4096^2 solve whose data streams through HBM on every launch (the
+    fine-grid level-1 passes and the outer Krylov passes: their inputs are not reused
+    within the 256 MB Infinity Cache between launches), each with its algorithmic bytes
+    per launch over its average event-timed launch duration."""
+    out = []
+    for fam in HBM_CLEAN:
+        ks = [k for k in kernels if k["name"].startswith(f"({fam}<") or k["name"].startswith(f"{fam} ")
+              or k["name"].startswith(f"({fam})")]
+        if not ks:
+            continue
+        launches = sum(k["launches"] for k in ks)
+        ms = sum(k["ms"] for k in ks)
+        by = sum(k["bytes"] for k in ks)
+        gbs = by / (ms * 1e-3) / 1e9
+        out.append({"kernel": fam, "launches": launches, "avg_launch_us": round(1e3 * ms / launches, 2),
+                    "bytes_per_launch": by / launches, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return out
+
+
+def bench_sharp(seed: int, maxit: int = 1000):
+    """The same 4096^2 workload without the smoothing of the medium (sharp layers and
+    inclusions as generated): FP32+refinement with a bounded iteration count, so that
+    the gap to the unsmoothed medium is a measured number (iterations, final relres)."""
+    import torch
+
+    import helm_inputs as hi
+    from paper_2404_02493_amd import Helmholtz
+
+    case = hi.make_case("layered4096_sharp", seed=seed)
+    H = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells)
+    H.set_phase(case.phi)
+    g = torch.as_tensor(case.g).to("cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, rr, hist = H.solve(g, tol=1e-6, maxit=maxit, mode=1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    H.close()
+    return {"workload": "layered4096_sharp (no smoothing of the medium)", "damping_cells": case.damping_cells,
+            "maxit": maxit, "iterations": its, "relres": rr, "seconds": round(dt, 3), "converged": rr < 1e-6}
+
+
+def bench_shifted(case, g, tol: float = 1e-7, shift: float = 0.01):
+    """The shifted equation (relative imaginary shift 0.01 of kappa, the paper's
+    Section 4.3.2 test) on the same 4096^2 medium, FP32+refinement to 1e-7."""
+    import torch
+
+    from paper_2404_02493_amd import Helmholtz
+
+    H = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells,
+                  shift=shift)
+    H.set_phase(case.phi)
+    H.solve(g, tol=tol, maxit=400, mode=1)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, rr, _ = H.solve(g, tol=tol, maxit=2000, mode=1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    H.close()
+    return {"shift": shift, "tol": tol, "iterations": its, "relres": rr, "seconds": round(dt, 4)}
+
+
 def copy_probe(reps: int = 5):
     """A plain device copy of 4096^2 complex64 values (128 MiB read + 128 MiB written per
     dispatch), the known-size reference for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -115,10 +182,14 @@ def copy_probe(reps: int = 5):
     H.close()
 
 
-def bench_batch(args):
+def batch_measure(seed: int, lanes: int, tol: float, maxit: int, steps: int = 1, warmup: int = 1,
+                  one_lane: bool = False, tune: bool = True):
     """Mixed batch: 64 problems with n drawn from {256, 512, 1024}, k = 0.625 n, own random
     medium, 1-4 sources with a multi-source fast-marching phase; every problem solved to
-    tol with FP32 cycles inside FP64 refinement.  value = problems per second."""
+    tol with FP32 cycles inside FP64 refinement.  Per size: one problem
+    solved alone with per-launch timing gives its algorithmic bytes over its kernel time, with
+    the untuned default launch shapes (those the batch runs with) and with the tuner's choice
+    for that size."""
     import numpy as np
     import torch
 
@@ -126,45 +197,81 @@ def bench_batch(args):
     from paper_2404_02493_amd import HelmholtzBatch
 
     t = time.perf_counter()
-    cases = hi.make_batch(args.seed)
+    cases = hi.make_batch(seed)
     log(f"batch inputs ready in {time.perf_counter() - t:.1f} s")
     probs = [dict(velocity=c.velocity, k=c.k, levels=c.levels, damping_cells=c.damping_cells, phi=c.phi)
              for c in cases]
     gs = [torch.as_tensor(c.g).to("cuda:0") for c in cases]
+    sizes = sorted({c.n for c in cases})
     res = {}
-    for lanes in (args.lanes, 1):
+    tuned, per_size = {}, {}
+    for nl in ([lanes, 1] if one_lane else [lanes]):
         t = time.perf_counter()
-        B = HelmholtzBatch(probs, precision="c64", lanes=lanes)
+        B = HelmholtzBatch(probs, precision="c64", lanes=nl)
         torch.cuda.synchronize()
-        log(f"lanes={lanes}: setup of {len(cases)} contexts in {time.perf_counter() - t:.1f} s")
-        for w in range(args.warmup):
-            B.solve(gs, tol=args.tol, maxit=args.maxit, mode=1)
+        log(f"lanes={nl}: setup of {len(cases)} contexts in {time.perf_counter() - t:.1f} s")
+        if not per_size:
+            # one problem of each size alone: untuned default shapes, then the tuner's choice
+            for n in sizes:
+                p = next(q for q, c in enumerate(cases) if c.n == n)
+                P = B.problem(p)
+                per_size[str(n)] = {"problems": sum(1 for c in cases if c.n == n)}
+                for label in (("default", "tuned") if tune else ("default",)):
+                    if label == "tuned":
+                        tn = P.tune()
+                        tuned[n] = {"sstep_rows": tn["sstep_rows"], "fgmres_blocks": tn["fgmres_blocks"]}
+                    P.solve(gs[p], tol=tol, maxit=maxit, mode=1)
+                    P.profile_begin()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, its1, _, _ = P.solve(gs[p], tol=tol, maxit=maxit, mode=1)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    prof = P.profile_end()
+                    ms = sum(k["ms"] for k in prof["kernels"])
+                    by = sum(k["bytes"] for k in prof["kernels"])
+                    per_size[str(n)][label] = {
+                        "iterations": its1, "seconds_profiled": round(dt, 4), "kernel_ms": round(ms, 3),
+                        "algorithmic_GBs_in_kernels": round(by / (ms * 1e-3) / 1e9, 1),
+                        "kernel_busy_frac": round(ms * 1e-3 / dt, 3)}
+                P.set_tuning({"sstep_rows": {}, "fgmres_blocks": 0})
+        for w in range(warmup):
+            B.solve(gs, tol=tol, maxit=maxit, mode=1)
         torch.cuda.synchronize()
         times = []
-        for s in range(args.steps):
+        for s_ in range(steps):
             t0 = time.perf_counter()
-            us, its, rr, st = B.solve(gs, tol=args.tol, maxit=args.maxit, mode=1)
+            us, its, rr, st = B.solve(gs, tol=tol, maxit=maxit, mode=1)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
-            log(f"lanes={lanes} step {s}: {times[-1]:.3f} s, iterations {int(its.sum())}, "
+            log(f"lanes={nl} step {s_}: {times[-1]:.3f} s, iterations {int(its.sum())}, "
                 f"max relres {rr.max():.2e}, statuses {sorted(set(st.tolist()))}")
-        res[lanes] = (float(np.mean(times)), its, rr, st)
+        res[nl] = (float(np.mean(times)), its, rr, st)
         B.close()
-    tb, its, rr, st = res[args.lanes]
-    t1 = res[1][0]
-    npts = sum(c.n * c.n for c in cases)
+    tb, its, rr, st = res[lanes]
+    out = {"problems_per_s": round(len(cases) / tb, 3), "seconds": round(tb, 3), "problems": len(cases),
+           "fine_points": sum(c.n * c.n for c in cases), "lanes": lanes,
+           "sizes": {str(n): sum(1 for c in cases if c.n == n) for n in sizes},
+           "all_converged": bool(np.all(st == 0)), "total_iterations": int(its.sum()),
+           "max_relres": float(rr.max()), "per_size": per_size, "tuned": {str(k): v for k, v in tuned.items()}}
+    if one_lane:
+        t1 = res[1][0]
+        out["one_lane"] = {"seconds": round(t1, 3), "problems_per_s": round(len(cases) / t1, 3),
+                           "speedup_of_lanes": round(t1 / tb, 2)}
+    return out
+
+
+def bench_batch(args):
+    """--workload batch64: the mixed batch as the main line (value = problems per second)."""
+    r = batch_measure(args.seed, args.lanes, args.tol, args.maxit, args.steps, args.warmup, one_lane=True)
     out = {
         "metric": "problems/s, 64-problem mixed batch (n in {256,512,1024}, k=0.625n), FP32+refine to 1e-6",
-        "value": round(len(cases) / tb, 3), "unit": "problems/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * tb, 2), "higher_is_better": True, "scaling": "strong",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batch64", "problems": len(cases), "fine_points": npts, "lanes": args.lanes,
-                   "sizes": {str(n): sum(1 for c in cases if c.n == n) for n in (256, 512, 1024)},
-                   "seed": args.seed, "tol": args.tol},
-        "all_converged": bool(np.all(st == 0)), "total_iterations": int(its.sum()),
-        "max_relres": float(rr.max()),
-        "one_lane": {"seconds": round(t1, 3), "problems_per_s": round(len(cases) / t1, 3),
-                     "speedup_of_lanes": round(t1 / tb, 2)},
+        "value": r["problems_per_s"], "unit": "problems/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * r["seconds"], 2), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "problems": r["problems"], "fine_points": r["fine_points"],
+                   "lanes": args.lanes, "sizes": r["sizes"], "seed": args.seed, "tol": args.tol},
+        "batch": r,
     }
     print(json.dumps(out), flush=True)
 
@@ -183,6 +290,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side measurements (sharp medium, shifted equation, batch)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain copy kernel of known size (reference for memory counters)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2404_02493_amd", "tuning.json"),
@@ -308,6 +417,20 @@ def main():
                    "top_kernels": [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),
                                     "GBs": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)} for k in ks[:8]]}
 
+    roofline_hbm = hbm_rooflines(prof32["kernels"]) if prof32 else None
+
+    shifted = sharp = batch = None
+    if not args.no_extras:
+        log("shifted equation (relative shift 0.01) to 1e-7")
+        shifted = bench_shifted(case, g)
+        log(f"shifted: {shifted}")
+        log("mixed batch of 64 problems")
+        batch = batch_measure(args.seed, args.lanes, args.tol, args.maxit)
+        log(f"batch: {batch['problems_per_s']} problems/s, per size {batch['per_size']}")
+        log("unsmoothed layered medium, at most 1000 iterations")
+        sharp = bench_sharp(args.seed)
+        log(f"sharp: {sharp}")
+
     adjoint = None
     if not args.no_adjoint:
         log("timing the adjoint of 10 unrolled cycles at 1024^2")
@@ -334,14 +457,23 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": case.n, "k": case.k, "levels": case.levels,
-                   "seed": args.seed, "medium": case.meta["medium"], "phase": "first-order fast marching",
+                   "seed": args.seed, "medium": case.meta["medium"],
+                   "medium_detail": "8 layers + 20 elliptical inclusions (+-30%), c in [1.5, 4.5]"
+                                    + (f", Gaussian-smoothed with sigma {case.meta['smooth']}"
+                                       if case.meta.get("smooth") else ", not smoothed"),
+                   "smooth": case.meta.get("smooth", 0.0), "damping_cells": case.damping_cells,
+                   "phase": "first-order fast marching",
                    "solver": "FP64 iterative refinement around FP32 FGMRES(20), FP32 Wave-ADR cycles (coarsest FP64)",
                    "adr_steps": 8, "tol": args.tol},
         "iterations": int(np.mean(iters)),
         "relres": rr32,
         "fp64": fp64,
         "roofline": roofline,
+        "roofline_hbm": roofline_hbm,
         "cpu_baseline": cpu,
+        "shifted": shifted,
+        "sharp": sharp,
+        "batch64": batch,
         "profile_fp32": summary,
         "adjoint": adjoint,
         "tuning": {k: v for k, v in tuning.items() if k != "timings_ms"} if tuning else None,

@@ -212,7 +212,7 @@ class Helmholtz:
         solver shape is applied instead of measuring, and new measurements are stored."""
         import json
 
-        key = self.tuning_key()
+        key = self.tuning_key() if cache else None
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
