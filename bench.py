@@ -163,6 +163,34 @@ def bench_shifted(case, g, tol: float = 1e-7, shift: float = 0.01):
     return {"shift": shift, "tol": tol, "iterations": its, "relres": rr, "seconds": round(dt, 4)}
 
 
+def bench_comparison(case, g, maxit: int = 600):
+    """The comparison preconditioners of Section 4.3.1 on the same 4096^2 workload and the
+    same kernels, FP32+refinement under a bounded iteration count: CSL (cycle for the
+    operator shifted by 0.5 k^2 n^2, no ADR correction) and Wave-Ray (eight plane-wave
+    ray corrections instead of the eikonal phase)."""
+    import torch
+
+    from paper_2404_02493_amd import Helmholtz
+
+    out = {}
+    for name, kw in (("csl", dict(cycle_shift=0.5, adr_steps=0)), ("wave_ray", {})):
+        H = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64",
+                      damping_cells=case.damping_cells, **kw)
+        if name == "wave_ray":
+            H.set_rays(8)
+        else:
+            H.set_phase(case.phi)
+        H.solve(g, tol=1e-6, maxit=5, mode=1)  # graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, its, rr, _ = H.solve(g, tol=1e-6, maxit=maxit, mode=1)
+        torch.cuda.synchronize()
+        out[name] = {"iterations": its, "relres": rr, "seconds": round(time.perf_counter() - t0, 3),
+                     "converged": rr < 1e-6, "maxit": maxit}
+        H.close()
+    return out
+
+
 def copy_probe(reps: int = 5):
     """A plain device copy of 4096^2 complex64 values (128 MiB read + 128 MiB written per
     dispatch), the known-size reference for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -419,7 +447,7 @@ def main():
 
     roofline_hbm = hbm_rooflines(prof32["kernels"]) if prof32 else None
 
-    shifted = sharp = batch = None
+    shifted = sharp = batch = comparison = None
     if not args.no_extras:
         log("shifted equation (relative shift 0.01) to 1e-7")
         shifted = bench_shifted(case, g)
@@ -427,6 +455,9 @@ def main():
         log("mixed batch of 64 problems")
         batch = batch_measure(args.seed, args.lanes, args.tol, args.maxit)
         log(f"batch: {batch['problems_per_s']} problems/s, per size {batch['per_size']}")
+        log("comparison preconditioners (CSL, Wave-Ray), at most 600 iterations")
+        comparison = bench_comparison(case, g)
+        log(f"comparison: {comparison}")
         log("unsmoothed layered medium, at most 1000 iterations")
         sharp = bench_sharp(args.seed)
         log(f"sharp: {sharp}")
@@ -474,6 +505,7 @@ def main():
         "shifted": shifted,
         "sharp": sharp,
         "batch64": batch,
+        "comparison": comparison,
         "profile_fp32": summary,
         "adjoint": adjoint,
         "tuning": {k: v for k, v in tuning.items() if k != "timings_ms"} if tuning else None,

@@ -87,6 +87,11 @@ typedef struct {
     double shift;             /* relative imaginary shift s0 >= 0 of the shifted equation (Section 4.3.2,
                                  gamma_0 = s0 k(x)^2 with k(x) = k n(x); the paper's test uses 0.01):
                                  kappa = k^2 n^2 (1 + i sigma (delta + s0)); default 0 */
+    double cycle_shift;       /* relative imaginary shift >= 0 added to kappa inside the cycle only: the
+                                 cycle is then a V-cycle for a complex-shifted operator while the
+                                 system (helm_solve's operator, helm_residual, helm_loss) keeps kappa.
+                                 With adr_steps = 0 and 0.5 this is the CSL preconditioner of the
+                                 paper's comparison (Section 4.3.1); default 0 */
 } helm_desc;
 
 /* Defaults of every field for an n x n grid at frequency k:
@@ -106,6 +111,14 @@ helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* 
  * ADR coefficients (phase derivatives, reaction term) on levels 2..L and the
  * level-2 carrier.  Required before helm_cycle when adr_steps > 0. */
 helm_status helm_set_phase(helm_ctx ctx, const void* phi, int32_t phi_is_f64, void* stream);
+
+/* Wave-Ray phases instead of one phase (the ray functions of the Wave-Ray method, Section 3.2):
+ * count plane waves phi_m = nbar (cos theta_m x + sin theta_m y), theta_m = 2 pi m / count,
+ * m = 0..count-1, nbar^2 the mean of n^2 over the fine unknowns.  The m-th ADR correction of
+ * a cycle (adr_steps of them, 8 for the paper's comparison) solves the ray equation of ray
+ * m mod count, eq. ADR with phi_m, by the same ADR V-cycle.  count in 1..64; a later
+ * helm_set_phase returns to one phase.  The adjoint supports one phase only. */
+helm_status helm_set_rays(helm_ctx ctx, int32_t count, void* stream);
 
 /* Per-level smoother weights (host, `levels` doubles): w[0] = damped-Jacobi weight
  * of level 1 (Section 3.1.1), w[l-1] = Chebyshev interval parameter alpha_l of

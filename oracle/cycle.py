@@ -19,6 +19,8 @@ Readings of the paper used here (each also listed in the design notes):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import torch
 
@@ -36,13 +38,17 @@ class Problem:
     velocity: (n, n) array c(x) > 0 (n^2 = 1/c^2 on the fine grid).
     weights:  length-L vector, w[0] = Jacobi weight, w[l-1] = Chebyshev alpha_l.
     shift:    relative imaginary shift s0 of the shifted equation (Section 4.3.2).
+    cycle_shift: relative imaginary shift added inside the cycle only, so that the cycle
+              is a V-cycle for a complex-shifted operator while the system keeps
+              kappa (the CSL preconditioner of the comparison in Section 4.3.1 is
+              cycle_shift = 0.5 with adr_steps = 0).
     phi:      fine-grid phase (n, n); may be a tensor that requires grad."""
 
     def __init__(self, velocity, k: float, levels: int, damping_cells: int = 16,
                  damping_strength: float = 0.5, sigma: int = 1, adr_steps: int = 8,
                  cheb_pre: int = 5, cheb_post: int = 5, cheb_coarse: int = 10,
                  gmres_m: int = 3, gmres_coarse_m: int = 3, level3_literal: bool = False,
-                 weights=None, phi=None, adr_levels=3, shift: float = 0.0):
+                 weights=None, phi=None, adr_levels=3, shift: float = 0.0, cycle_shift: float = 0.0):
         vel = torch.as_tensor(np.asarray(velocity, dtype=np.float64))
         self.n = int(vel.shape[0])
         if self.n & (self.n - 1) or self.n < 8:
@@ -55,6 +61,7 @@ class Problem:
         self.strength = float(damping_strength)
         self.sigma = int(sigma)
         self.shift = float(shift)
+        self.cycle_shift = float(cycle_shift)
         self.adr_steps = int(adr_steps)
         self.cheb_pre, self.cheb_post, self.cheb_coarse = cheb_pre, cheb_post, cheb_coarse
         self.gmres_m, self.gmres_coarse_m = gmres_m, gmres_coarse_m
@@ -70,10 +77,14 @@ class Problem:
             self.h[l] = 1.0 / nl
             self.n2[l] = inject(self.n2_fine, l)
             self.rho[l] = damping_rho(self.n, l, self.W)
-            self.kappa[l] = kappa_level(self.n2[l], self.rho[l], self.k, self.strength, self.sigma, self.shift)
+            self.kappa[l] = kappa_level(self.n2[l], self.rho[l], self.k, self.strength, self.sigma,
+                                        self.shift + self.cycle_shift)
             self.lam[l] = lambda_gershgorin(self.kappa[l], self.h[l])
+        # the operator of the linear system (level 1); the cycle's operators add cycle_shift
+        self.kappa_sys = kappa_level(self.n2[1], self.rho[1], self.k, self.strength, self.sigma, self.shift)
         self.weights = self.default_weights() if weights is None else torch.as_tensor(weights, dtype=F64)
         self.adr = {}
+        self.phase_sets = []
         if phi is not None:
             self.set_phase(phi)
 
@@ -95,19 +106,43 @@ class Problem:
         """Inject phi to the ADR levels 2..L, build their coefficients, and the
         level-2 carrier e^{+- i sigma k phi_2}."""
         phi = phi if isinstance(phi, torch.Tensor) else torch.as_tensor(np.asarray(phi))
-        phi = phi.to(F64)
-        self.adr = {}
+        self.phase_sets = [self._phase_set(phi.to(F64))]
+        self.use_phase(0)
+
+    def _phase_set(self, phi):
+        adr = {}
         for l in range(2, self.LA + 1):
-            self.adr[l] = adr_coefficients(inject(phi, l), self.n2[l], self.rho[l], self.k,
-                                           self.strength, self.sigma, self.h[l], self.shift)
-        phi2 = inject(phi, 2)
-        arg = (self.sigma * self.k) * phi2
-        self.carrier = torch.complex(torch.cos(arg), torch.sin(arg))
-        self.carrier_conj = torch.complex(torch.cos(arg), -torch.sin(arg))
+            adr[l] = adr_coefficients(inject(phi, l), self.n2[l], self.rho[l], self.k,
+                                      self.strength, self.sigma, self.h[l], self.shift + self.cycle_shift)
+        arg = (self.sigma * self.k) * inject(phi, 2)
+        return adr, torch.complex(torch.cos(arg), torch.sin(arg)), torch.complex(torch.cos(arg), -torch.sin(arg))
+
+    def use_phase(self, m: int):
+        """Makes phase set m the one the ADR correction uses (ADR coefficients and carrier)."""
+        self.adr, self.carrier, self.carrier_conj = self.phase_sets[m]
+
+    def set_rays(self, count: int = 8):
+        """Wave-Ray phases (Section 3.2, the plane-wave basis of the Wave-Ray method):
+        phi_m = nbar (cos theta_m x + sin theta_m y), theta_m = 2 pi (m - 1)/count,
+        m = 1..count, with nbar^2 the mean of n^2 over the fine unknowns (reading: the
+        paper's rays have unit slowness, |grad phi_m| = 1 on its unit-slowness medium).
+        The m-th ADR correction of a cycle uses ray (m - 1) mod count; the ray equation
+        is eq. ADR with phi_m (for n = nbar its reaction term is the damping term alone,
+        the paper's ray equation)."""
+        nbar = math.sqrt(float(self.n2_fine[1:, 1:].mean()))
+        x = torch.arange(self.n, dtype=F64) / self.n
+        Y, X = torch.meshgrid(x, x, indexing="ij")
+        sets = []
+        for m in range(count):
+            th = 2.0 * math.pi * m / count
+            sets.append(self._phase_set(nbar * (math.cos(th) * X + math.sin(th) * Y)))
+        self.phase_sets = sets
+        self.use_phase(0)
 
     # convenience
     def A(self, u, level: int = 1):
-        return apply_A(u, self.kappa[level], self.h[level])
+        """The system operator on level 1; the cycle's (re-discretised) operator below."""
+        return apply_A(u, self.kappa_sys if level == 1 else self.kappa[level], self.h[level])
 
     def zeros(self, level: int = 1):
         nl = level_size(self.n, level)
@@ -137,10 +172,12 @@ def wave_adr_cycle(P: Problem, level: int, g: torch.Tensor, u: torch.Tensor) -> 
     elif level == 2:
         u = chebyshev(u, g, kap, h, w[1], P.cheb_post, P.lam[2])
         if P.adr_steps > 0 and L >= 3:
-            if not P.adr:
+            if not P.phase_sets:
                 raise RuntimeError("phase not set")
-            for _ in range(P.adr_steps):
+            for s in range(P.adr_steps):
+                P.use_phase(s % len(P.phase_sets))
                 u = adr_step(P, g, u)
+            P.use_phase(0)
     elif level == 3 and not P.level3_literal:
         pass
     else:

@@ -34,7 +34,7 @@ def loss_after_cycles(P: Problem, g, K: int, phi=None, w=None, u0=None, use_chec
             u = checkpoint(lambda uu: cycle(P, g, uu), u, use_reentrant=False)
         else:
             u = cycle(P, g, u)
-    r = g - apply_A(u, P.kappa[1], P.h[1])
+    r = g - apply_A(u, P.kappa_sys, P.h[1])
     return torch.sum(r.real * r.real + r.imag * r.imag), u
 
 
@@ -58,7 +58,7 @@ def grad_autograd(P: Problem, g, K: int, phi, w, use_checkpoint: bool = True):
         u = torch.zeros_like(g_t)
         for _ in range(K):
             u = checkpoint(one, u, phi_t, w_t, use_reentrant=False)
-        r = g_t - apply_A(u, P.kappa[1], P.h[1])
+        r = g_t - apply_A(u, P.kappa_sys, P.h[1])
         L = torch.sum(r.real * r.real + r.imag * r.imag)
     else:
         L = run(phi_t, w_t)

@@ -41,7 +41,7 @@ def fgmres(P: Problem, g: torch.Tensor, x0=None, tol: float = 1e-6, restart: int
         return torch.zeros_like(g), 0, 0.0, True
     its = 0
     while True:
-        r = g - apply_A(x, P.kappa[1], P.h[1])
+        r = g - apply_A(x, P.kappa_sys, P.h[1])
         beta = cnorm(r).item()
         if beta / gnorm < tol:
             return x, its, beta / gnorm, True
@@ -57,7 +57,7 @@ def fgmres(P: Problem, g: torch.Tensor, x0=None, tol: float = 1e-6, restart: int
         for j in range(restart):
             z = prec(V[j])
             Z.append(z)
-            w = apply_A(z, P.kappa[1], P.h[1])
+            w = apply_A(z, P.kappa_sys, P.h[1])
             for i in range(j + 1):
                 hij = cdot(V[i], w)
                 H[i][j] = complex(hij.item())

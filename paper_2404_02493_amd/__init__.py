@@ -94,6 +94,10 @@ class Helmholtz:
         self._phi = t
         check(lib().helm_set_phase(self._ctx, _ptr(t), int(is64), _stream_ptr(stream)))
 
+    def set_rays(self, count: int = 8, stream=None):
+        """Wave-Ray phases: the ADR corrections cycle through count plane waves."""
+        check(lib().helm_set_rays(self._ctx, int(count), _stream_ptr(stream)))
+
     @property
     def weights(self) -> np.ndarray:
         w = (ctypes.c_double * self.levels)()

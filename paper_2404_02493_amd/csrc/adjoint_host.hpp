@@ -507,7 +507,7 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
 // L = ||g - A u||^2 (FP64) and, if grad_u, its cotangent -2 A^H (g - A u) in cycle precision.
 template <typename T>
 static double loss_grad(helm_ctx c, const void* g, const void* u, void* grad_u, hipStream_t st) {
-    const Geom G = make_geom(c, 1);
+    const Geom G = make_geom_sys(c);
     const size_t NF = (size_t)G.n * G.n;
     const int nb = flat_blocks(NF);
     LAUNCH(c, (2.0 * sizeof(cplx<T>) + 8.0 + 16.0) * NF, (k_loss_resid<T>), dim3(nb), dim3(BLOCK), st, G,

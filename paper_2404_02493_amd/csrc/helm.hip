@@ -90,6 +90,16 @@ struct helm_ctx_s {
     std::vector<helm::AdrLevel> al;
     void* car2 = nullptr;    // carrier e^{i sigma k phi} on level 2 (cycle precision)
     bool phase_set = false;
+    // phase sets of the ADR correction: set 0 is the phase of helm_set_phase; helm_set_rays
+    // fills nsets plane-wave sets and the m-th ADR step of a cycle uses set m mod nsets
+    struct PhaseSet {
+        void* px[16];
+        void* py[16];
+        void* c0[16];
+        void* car;
+    };
+    std::vector<PhaseSet> sets;
+    int nsets = 1;
     std::vector<double> w, w_default;
     void* ws1 = nullptr;     // second level-1 iterate (cycle precision)
     double* partials = nullptr;
@@ -203,6 +213,14 @@ static Geom make_geom(const helm_ctx c, int level) {
     G.inv_h2 = double(G.n) * double(G.n);
     G.k2 = c->d.k * c->d.k;
     G.sig_str = double(c->d.sign) * c->d.damping_strength;
+    G.sig_shift = double(c->d.sign) * (c->d.shift + c->d.cycle_shift);
+    return G;
+}
+
+// Level-1 geometry of the system operator (without the cycle-only shift): the outer
+// Krylov solver, the FP64 residual and the loss.
+static Geom make_geom_sys(const helm_ctx c) {
+    Geom G = make_geom(c, 1);
     G.sig_shift = double(c->d.sign) * c->d.shift;
     return G;
 }
@@ -271,6 +289,8 @@ static void krylov_fin(helm_ctx c, hipStream_t st, int nblk, int op, int jj, int
                (const double*)c->partials, nblk, op, jj, m, K, tol);
     }
 }
+
+static void use_set(helm_ctx c, int m);
 
 // ------------------------------------------------------------------ engine
 template <typename T>
@@ -484,7 +504,7 @@ struct Engine {
     // the buffers they started on.
     bool adr_fused() const {
         const int m = c->d.gmres_m;
-        return c->LA > 2 && m <= 3 && !c->d.gmres_arnoldi && c->wl[2].ualt && c->al[2].balt;
+        return c->LA > 2 && m <= 3 && !c->d.gmres_arnoldi && c->wl[2].ualt && c->al[2].balt && c->nsets == 1;
     }
     ModArgs<T> mod_args(void* uout, void* bout) {
         WaveLevel& W = c->wl[2];
@@ -505,6 +525,7 @@ struct Engine {
         void* const b_home = A.b;
         const bool fused = adr_fused();
         for (int s = 0; s < M; ++s) {
+            if (c->nsets > 1) use_set(c, s % c->nsets);
             if (s == 0 || !fused)
                 LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(),
                        st, W.G, (const T*)W.n2, (const C*)W.g, (const C*)W.u, (const C*)c->car2, (C*)A.b);
@@ -526,6 +547,7 @@ struct Engine {
             }
         }
         if (A.b != b_home) std::swap(A.b, A.balt);
+        if (c->nsets > 1) use_set(c, 0);
     }
 
     // GMRES on a small level in one workgroup (the coarsest ADR level), if it fits.
@@ -841,7 +863,7 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
                         std::vector<double>* history, double* est_out, bool* breakdown) {
     using Cp = cplx<P>;
     const int m = c->d.restart;
-    const Geom G = make_geom(c, 1);
+    const Geom G = make_geom_sys(c);
     const size_t N = (size_t)G.n * G.n;
     // K init from V[0]
     const int nbf = c->tn.fgmres_blocks > 0 ? std::min(c->tn.fgmres_blocks, MAXRED) : flat_blocks(N, MAXRED);
@@ -936,7 +958,7 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
 }
 
 static void residual_fp64(helm_ctx c, hipStream_t st, const void* g, const void* u, void* r, double* rn, double* gn) {
-    const Geom G = make_geom(c, 1);
+    const Geom G = make_geom_sys(c);
     const int nbt = red_blocks(G.n);
     LAUNCH(c, (3 * 16.0 + 8.0 + (r ? 16.0 : 0.0)) * NN(G.n), k_residual_norms, dim3(nbt), tile_block(), st, G,
            (const double*)c->n2f, (const c128*)g, (const c128*)u, (c128*)r, c->partials);
@@ -949,6 +971,8 @@ static void residual_fp64(helm_ctx c, hipStream_t st, const void* g, const void*
     if (gn) *gn = std::sqrt(h[1]);
 }
 
+static void drop_graphs(helm_ctx c);
+
 // ------------------------------------------------------------------ setup
 static void validate(const helm_desc* d) {
     REQUIRE(d != nullptr, "desc is NULL");
@@ -960,6 +984,7 @@ static void validate(const helm_desc* d) {
     REQUIRE(d->damping_cells >= 1, "damping_cells must be >= 1");
     REQUIRE(d->damping_strength >= 0 && std::isfinite(d->damping_strength), "damping_strength must be >= 0");
     REQUIRE(d->shift >= 0 && std::isfinite(d->shift), "shift must be >= 0");
+    REQUIRE(d->cycle_shift >= 0 && std::isfinite(d->cycle_shift), "cycle_shift must be >= 0");
     REQUIRE(d->sign == 1 || d->sign == -1, "sign must be +1 or -1");
     REQUIRE(d->cycle_prec == HELM_C64 || d->cycle_prec == HELM_C128, "cycle_prec must be HELM_C64 or HELM_C128");
     REQUIRE(d->adr_steps >= 0 && d->adr_steps <= 64, "adr_steps must be in [0, 64]");
@@ -1098,6 +1123,14 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
         }
         c->wl[2].ualt = dalloc(c, (size_t)c->wl[2].n * c->wl[2].n * csize(c->wl[2].f64));
         c->car2 = dalloc(c, (size_t)(n / 2) * (n / 2) * csize(f64c));
+        helm_ctx_s::PhaseSet s0{};
+        for (int l = 2; l <= c->LA; ++l) {
+            s0.px[l] = c->al[l].px;
+            s0.py[l] = c->al[l].py;
+            s0.c0[l] = c->al[l].c0;
+        }
+        s0.car = c->car2;
+        c->sets.assign(1, s0);
     }
     // FP64 residual vectors; the Krylov bases of the outer solvers are allocated by
     // the first solve in each mode (ensure_solver_ws)
@@ -1107,11 +1140,20 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
 }
 
-static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
-    if (c->L < 3) {
-        c->phase_set = true;
-        return;
+// Points the ADR levels and the level-2 carrier at phase set m.
+static void use_set(helm_ctx c, int m) {
+    const helm_ctx_s::PhaseSet& S = c->sets[m];
+    for (int l = 2; l <= c->LA; ++l) {
+        c->al[l].px = S.px[l];
+        c->al[l].py = S.py[l];
+        c->al[l].c0 = S.c0[l];
     }
+    c->car2 = S.car;
+}
+
+// ADR coefficients of every ADR level and the level-2 carrier from the fine phase phi,
+// into the current phase set.
+static void build_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
     for (int l = 2; l <= c->LA; ++l) {
         AdrLevel& A = c->al[l];
         const Geom G = make_geom(c, l);
@@ -1139,7 +1181,66 @@ static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
         }
     }
     HIPCHK(hipGetLastError());
+}
+
+static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
+    if (c->L < 3) {
+        c->phase_set = true;
+        return;
+    }
+    use_set(c, 0);
+    c->nsets = 1;
+    build_phase(c, phi, is64, st);
     HIPCHK(hipStreamSynchronize(st));
+    drop_graphs(c);
+    c->phase_set = true;
+}
+
+// Wave-Ray phases: count plane waves phi_m = nbar (cos theta_m x + sin theta_m y),
+// theta_m = 2 pi m / count, nbar^2 the mean of n^2 over the fine unknowns.
+static void set_rays(helm_ctx c, int count, hipStream_t st) {
+    REQUIRE(count >= 1 && count <= 64, "helm_set_rays: count must be in 1..64");
+    if (c->L < 3) {
+        c->phase_set = true;
+        return;
+    }
+    const bool f64c = !c->f32;
+    while ((int)c->sets.size() < count) {
+        helm_ctx_s::PhaseSet S{};
+        for (int l = 2; l <= c->LA; ++l) {
+            const size_t Nl = (size_t)c->al[l].n * c->al[l].n;
+            S.px[l] = dalloc(c, Nl * rsize(f64c));
+            S.py[l] = dalloc(c, Nl * rsize(f64c));
+            S.c0[l] = dalloc(c, Nl * csize(f64c));
+        }
+        const size_t N2 = (size_t)c->al[2].n * c->al[2].n;
+        S.car = dalloc(c, N2 * csize(f64c));
+        c->sets.push_back(S);
+    }
+    const int n = c->d.n;
+    const size_t NF = (size_t)n * n;
+    double* phi = nullptr;
+    HIPCHK(hipMalloc((void**)&phi, NF * sizeof(double)));
+    const double nbar = std::sqrt(c->wl[1].n2mean);
+    try {
+        for (int m = 0; m < count; ++m) {
+            const double th = 2.0 * M_PI * double(m) / double(count);
+            hipLaunchKernelGGL(k_ray_phase, dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, n, nbar, std::cos(th),
+                               std::sin(th), phi);
+            use_set(c, m);
+            build_phase(c, phi, 1, st);
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(phi);
+        use_set(c, 0);
+        throw;
+    }
+    HIPCHK(hipFree(phi));
+    use_set(c, 0);
+    c->nsets = count;
+    drop_graphs(c);
     c->phase_set = true;
 }
 
@@ -1349,7 +1450,7 @@ static double* noalloc_scratch() {
 // equal helm_residual's bit for bit.
 static void residual_fp64_noalloc(helm_ctx c, hipStream_t st, const void* g, const void* u, void* r, double* rn,
                                   double* gn) {
-    const Geom G = make_geom(c, 1);
+    const Geom G = make_geom_sys(c);
     const int nbt = red_blocks(G.n);
     if ((size_t)2 * nbt > NOALLOC_PARTIALS)
         throw Error(HELM_EINVAL, "helm_residual_noalloc: " + std::to_string(nbt) + " reduction blocks exceed the " +
@@ -1419,6 +1520,7 @@ void helm_desc_default(helm_desc* d, int32_t n, double k) {
     d->wave_tail_n = 32;
     d->adr_levels = 3;
     d->shift = 0.0;
+    d->cycle_shift = 0.0;
 }
 
 helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* out, void* stream) {
@@ -1444,6 +1546,14 @@ helm_status helm_set_phase(helm_ctx ctx, const void* phi, int32_t phi_is_f64, vo
     ABI_GUARD({
         REQUIRE(ctx != nullptr && phi != nullptr, "NULL argument");
         set_phase(ctx, phi, phi_is_f64 != 0, (hipStream_t)stream);
+        return HELM_OK;
+    })
+}
+
+helm_status helm_set_rays(helm_ctx ctx, int32_t count, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr, "NULL argument");
+        set_rays(ctx, count, (hipStream_t)stream);
         return HELM_OK;
     })
 }
@@ -1530,6 +1640,7 @@ helm_status helm_residual_noalloc(helm_ctx ctx, const void* g, const void* u, vo
 helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const void* u0, const void* grad_uK,
                                 void* grad_phi, double* grad_w, void* ckpt_ws, void* stream) {
     ABI_GUARD({
+        REQUIRE(ctx == nullptr || ctx->nsets == 1, "helm_cycle_backward needs a single phase (helm_set_phase), not Wave-Ray phases");
         REQUIRE(ctx != nullptr && g != nullptr && grad_uK != nullptr && grad_phi != nullptr && grad_w != nullptr,
                 "NULL argument");
         REQUIRE(K >= 1 && K <= 100000, "K must be in [1, 100000]");

@@ -78,6 +78,18 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __rest
     }
 }
 
+// Plane-wave phase nbar (cs x + sn y) at the fine nodes, x = j / n, y = i / n, in FP64 with
+// the products and the sum rounded separately (no contraction).
+__global__ __launch_bounds__(BLOCK) void k_ray_phase(int n, double nbar, double cs, double sn,
+                                                     double* __restrict__ phi) {
+    const size_t N = (size_t)n * n;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        const int i = (int)(p / n), j = (int)(p - (size_t)i * n);
+        const double x = double(j) / double(n), y = double(i) / double(n);
+        phi[p] = __dmul_rn(nbar, __dadd_rn(__dmul_rn(cs, x), __dmul_rn(sn, y)));
+    }
+}
+
 // (M x)(i,j) = -Delta_h x - 2 i sigma k U_h[x] + c0 x   (x scaled by xs)
 template <typename T>
 __device__ __forceinline__ cplx<T> applyM_at(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,

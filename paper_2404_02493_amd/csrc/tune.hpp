@@ -131,7 +131,7 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
     {
         const int mode = c->f32 ? 1 : 0;
         ensure_solver_ws(c, mode);
-        const Geom G = make_geom(c, 1);
+        const Geom G = make_geom_sys(c);
         const size_t NF = (size_t)G.n * G.n;
         const int jj = std::max(0, c->d.restart / 2);
         void** Vp = c->f32 ? c->iV : c->fV;

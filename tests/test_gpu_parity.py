@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import helm_inputs as hi
-from gpu_util import TOL, assert_close, make_pair, measure, rand_grid, rounded, to_dev, within
+from gpu_util import (TOL, assert_close, check_report, make_pair, measure, operator_report, rand_grid, rounded,
+                      to_dev, within)
 from oracle.adr import adr_step, adr_vcycle, apply_M, gmres
 from oracle.cycle import Problem, cycle, wave_adr_cycle
 from oracle.grid import apply_A, prolong_bilinear, restrict_fw
@@ -40,78 +41,6 @@ def test_default_weights_match_oracle(small_case, prec):
 
 
 MARCH = {"sstep_rows": {"2": 48, "3": 24, "4": 24}}
-
-
-def operator_report(c, P, H, prec, rng):
-    """Every internal operator of the library on identical random inputs against the
-    oracle: {name: (relative 2-norm, element-wise)}."""
-    cd = H.cdtype
-    L = c.levels
-    report = {}
-    for l in range(1, L + 1):
-        nl = c.n >> (l - 1)
-        dt = H.level_dtype(l)
-        x = rounded(_rand(rng, nl), dt)
-        out = H.debug_op(1, l, to_dev(x, dt), out_dtype=dt)
-        report[f"A{l}"] = measure(out, apply_A(x, P.kappa[l], P.h[l]))
-        if l < L:
-            dtc = H.level_dtype(l + 1)
-            out = H.debug_op(2, l, to_dev(x, dt), out_shape_level=l + 1, out_dtype=dtc)
-            report[f"R{l}"] = measure(out, restrict_fw(x))
-            e = rounded(_rand(rng, nl // 2), dtc)
-            base = rounded(_rand(rng, nl), dt)
-            outp = to_dev(base, dt)
-            H.debug_op(3, l, to_dev(e, dtc), out=outp)
-            report[f"P{l}"] = measure(outp, base + prolong_bilinear(e))
-            g = rounded(_rand(rng, nl), dt)
-            out = H.debug_op(11, l, to_dev(x, dt), to_dev(g, dt), out_shape_level=l + 1, out_dtype=dtc)
-            report[f"RR{l}"] = measure(out, restrict_fw(g - apply_A(x, P.kappa[l], P.h[l])))
-    # Jacobi (level 1)
-    x, g = rounded(_rand(rng, c.n), cd), rounded(_rand(rng, c.n), cd)
-    out = H.debug_op(4, 1, to_dev(x, cd), to_dev(g, cd))
-    report["J1"] = measure(out, jacobi(x, g, P.kappa[1], P.h[1], P.weights[0]))
-    # Chebyshev on level 2 (pre count) and the coarsest level
-    for l, m in [(2, P.cheb_pre), (L, P.cheb_coarse)]:
-        nl = c.n >> (l - 1)
-        dt = H.level_dtype(l)
-        x, g = rounded(_rand(rng, nl), dt), rounded(_rand(rng, nl), dt)
-        out = H.debug_op(5, l, to_dev(x, dt), to_dev(g, dt), out_dtype=dt)
-        report[f"C{l}"] = measure(out, chebyshev(x, g, P.kappa[l], P.h[l], P.weights[l - 1], m, P.lam[l]))
-    # ADR operator on every ADR level
-    for l in range(2, P.LA + 1):
-        nl = c.n >> (l - 1)
-        x = rounded(_rand(rng, nl), cd)
-        out = H.debug_op(6, l, to_dev(x, cd))
-        report[f"M{l}"] = measure(out, apply_M(x, P.adr[l]))
-    # GMRES(3) from a nonzero x0 on level 2
-    n2 = c.n // 2
-    x0, b = rounded(_rand(rng, n2), cd), rounded(_rand(rng, n2), cd)
-    out = H.debug_op(7, 2, to_dev(x0, cd), to_dev(b, cd))
-    report["G2"] = measure(out, gmres(lambda v: apply_M(v, P.adr[2]), b, x0, P.gmres_m))
-    # ADR V-cycle from level 2
-    out = H.debug_op(8, 2, None, to_dev(b, cd))
-    report["V2"] = measure(out, adr_vcycle(P, 2, b, None))
-    # one ADR step on level 2
-    u2, g2 = rounded(_rand(rng, n2), cd), rounded(_rand(rng, n2), cd)
-    out = H.debug_op(9, 2, to_dev(u2, cd), to_dev(g2, cd))
-    report["S2"] = measure(out, adr_step(P, g2, u2))
-    # coarse cycle from level 2 with zero iterate
-    out = H.debug_op(10, 2, None, to_dev(g2, cd))
-    report["W2"] = measure(out, wave_adr_cycle(P, 2, g2, torch.zeros_like(g2)))
-    # fine cycle from a random iterate
-    u, g = rounded(_rand(rng, c.n), cd), rounded(_rand(rng, c.n), cd)
-    out = H.debug_op(10, 1, to_dev(u, cd), to_dev(g, cd))
-    report["W1"] = measure(out, cycle(P, g, u))
-    # fine cycle from a zero iterate (the preconditioner application inside FGMRES)
-    out = H.debug_op(10, 1, None, to_dev(g, cd))
-    report["W1z"] = measure(out, cycle(P, g, torch.zeros_like(g)))
-    return report
-
-
-def check_report(report, tol):
-    bad = {k: v for k, v in report.items() if not within(v, tol)}
-    print({k: f"{v[0]:.2e}/{v[1]:.2e}" for k, v in report.items()}, flush=True)
-    assert not bad, bad
 
 
 @pytest.mark.parametrize("form", ["sstep", "arnoldi", "tail"])

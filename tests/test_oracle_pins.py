@@ -948,3 +948,118 @@ def test_shift_reduces_iterations():
         assert ok and rr < 1e-7
         its.append(it)
     assert its[1] < its[0] - 5, its
+
+
+# ---------------------------------------------------------------- comparison preconditioners (CSL, Wave-Ray)
+def test_csl_shift_only_inside_the_cycle():
+    """The CSL preconditioner (Section 4.3.1: a V-cycle for the complex-shifted operator,
+    shift 0.5 k^2) keeps the system operator: kappa of the cycle's levels is
+    k^2 n^2 (1 + i sigma (delta + s0 + beta)), the system's k^2 n^2 (1 + i sigma (delta + s0)),
+    written out at sample nodes."""
+    n, k = 32, 20.0
+    vel = np.linspace(1.0, 2.0, n * n).reshape(n, n)
+    for sigma in (1, -1):
+        P = Problem(vel, k, 3, damping_cells=4, sigma=sigma, shift=0.01, cycle_shift=0.5, adr_steps=0)
+        for (i, j) in [(1, 1), (5, 17), (16, 16), (31, 2)]:
+            r = max(max(0.0, 1 - min(i, n - i) / 4), max(0.0, 1 - min(j, n - j) / 4))
+            delta = 0.5 * r * r
+            nsq = 1.0 / vel[i, j] ** 2
+            assert abs(P.kappa_sys[i, j].item() - k * k * nsq * (1 + 1j * sigma * (delta + 0.01))) < 1e-9
+            assert abs(P.kappa[1][i, j].item() - k * k * nsq * (1 + 1j * sigma * (delta + 0.51))) < 1e-9
+        u = _rand_grid(np.random.default_rng(3), n)
+        assert torch.allclose(P.A(u), apply_A(u, P.kappa_sys, 1.0 / n))
+
+
+def test_T10_csl_cycle_dense_error_propagation():
+    """T10 for the CSL cycle: the error propagation of the cycle with the cycle-only
+    shift equals S_post (I - P B_c R A_beta) S_pre assembled densely from the shifted
+    operator A_beta on every level."""
+    n, L = 16, 3
+    rng = np.random.default_rng(6)
+    vel = 1.0 + 0.3 * rng.random((n, n))
+    P = Problem(vel, 0.45 * n, L, damping_cells=3, adr_steps=0, cycle_shift=0.5, level3_literal=True)
+    w = P.weights.numpy()
+    B = None
+    for l in range(L, 0, -1):
+        nl = n >> (l - 1)
+        A = _dense_A(nl, P.kappa[l].numpy())
+        I = np.eye(A.shape[0])
+        if l == L:
+            E = _cheb_poly_matrix(A, P.lam[l], w[l - 1], P.cheb_coarse)
+        else:
+            R = _dense_R(nl)
+            CG = I - 4 * R.T @ B @ R @ A
+            if l == 1:
+                D = np.diag(4 * nl**2 - P.kappa[1].numpy()[1:, 1:].ravel())
+                S = I - w[0] * np.linalg.solve(D, A)
+                E = S @ CG @ S
+            else:
+                S = _cheb_poly_matrix(A, P.lam[l], w[l - 1], 5)
+                E = S @ CG @ S
+        B = (I - E) @ np.linalg.inv(A)
+    idx = [(i, j) for i in range(1, n) for j in range(1, n)]
+    zero = torch.zeros((n, n), dtype=C128)
+    for c in rng.choice(len(idx), size=30, replace=False):
+        e = torch.zeros((n, n), dtype=C128)
+        e[idx[c]] = 1.0
+        out = cycle(P, zero, e).numpy()
+        col = np.array([out[p] for p in idx])
+        assert np.linalg.norm(col - E[:, c]) <= 1e-10 * max(1.0, np.linalg.norm(E[:, c]))
+
+
+def test_ray_phases_constant_medium():
+    """Wave-Ray phases (Section 3.2): on a unit-slowness medium the m-th ray has
+    phi_x = cos theta_m and phi_y = sin theta_m exactly (linear phase, also at the open
+    edge), and its ADR reaction term is the damping term alone, -i sigma k^2 delta (the
+    paper's ray equation); the carrier is e^{i sigma k (cos theta x + sin theta y)}."""
+    n, k = 32, 15.0
+    P = Problem(np.ones((n, n)), k, 4, damping_cells=5)
+    P.set_rays(8)
+    assert len(P.phase_sets) == 8
+    delta = 0.5 * P.rho[2] ** 2
+    h2 = P.h[2]
+    x = np.arange(n // 2) * h2
+    X, Y = np.meshgrid(x, x)
+    for m, (adr, car, carc) in enumerate(P.phase_sets):
+        th = 2 * math.pi * m / 8
+        px, py, c0 = adr[2]["px"], adr[2]["py"], adr[2]["c0"]
+        assert np.allclose(px[1:, 1:].numpy(), math.cos(th), atol=1e-11)
+        assert np.allclose(py[1:, 1:].numpy(), math.sin(th), atol=1e-11)
+        assert np.allclose(c0[1:, 1:].numpy(), (-1j * k * k * delta)[1:, 1:].numpy(), atol=1e-7)
+        assert np.allclose(car.numpy(), np.exp(1j * k * (math.cos(th) * X + math.sin(th) * Y)), atol=1e-12)
+
+
+def test_T11_ray_cycle_fixed_point_is_dense_solution():
+    """With Wave-Ray phases the cycle still has the dense solution A^{-1} g as its
+    fixed point (every ray correction acts on the residual)."""
+    n, L = 32, 3
+    case = hi.make_problem(n, 16.0, L, seed=7, medium="grf", phase="fmm", damping_cells=4)
+    P = Problem(case.velocity, case.k, L, damping_cells=4, phi=case.phi)
+    P.set_rays(8)
+    A = _dense_A(n, P.kappa[1].numpy())
+    idx = [(i, j) for i in range(1, n) for j in range(1, n)]
+    us = np.linalg.solve(A, np.array([case.g[p] for p in idx]))
+    ustar = torch.zeros((n, n), dtype=C128)
+    for v, p in zip(us, idx):
+        ustar[p] = v
+    out = cycle(P, torch.as_tensor(case.g), ustar)
+    assert cnorm(out - ustar) / cnorm(ustar) < 1e-12
+
+
+@pytest.mark.slow
+def test_comparison_preconditioners_converge():
+    """FGMRES(20) to 1e-6 on the 128^2 constant medium with the three preconditioners of
+    the comparison (Section 4.3.1): Wave-ADR (one first-arrival phase, 8 ADR steps),
+    Wave-Ray (8 rays) and CSL (shift 0.5, one V-cycle, no ADR) all converge, and CSL
+    needs several times the Wave-ADR count (Table 2's ordering between them)."""
+    c = hi.make_case("const128")
+    g = torch.as_tensor(c.g)
+    its = {}
+    for name, kw in [("adr", {}), ("ray", {}), ("csl", dict(cycle_shift=0.5, adr_steps=0))]:
+        P = Problem(c.velocity, c.k, c.levels, damping_cells=c.damping_cells, phi=c.phi, **kw)
+        if name == "ray":
+            P.set_rays(8)
+        x, it, rr, ok = fgmres(P, g, tol=1e-6, maxit=400)
+        assert ok and rr < 1e-6, name
+        its[name] = it
+    assert its["csl"] > 2.5 * its["adr"] and its["csl"] > 2.5 * its["ray"], its
