@@ -275,13 +275,16 @@ def batch_measure(seed: int, lanes: int, tol: float, maxit: int, steps: int = 1,
             log(f"lanes={nl} step {s_}: {times[-1]:.3f} s, iterations {int(its.sum())}, "
                 f"max relres {rr.max():.2e}, statuses {sorted(set(st.tolist()))}")
         res[nl] = (float(np.mean(times)), its, rr, st)
+        classes = B.classes()
         B.close()
     tb, its, rr, st = res[lanes]
     out = {"problems_per_s": round(len(cases) / tb, 3), "seconds": round(tb, 3), "problems": len(cases),
            "fine_points": sum(c.n * c.n for c in cases), "lanes": lanes,
            "sizes": {str(n): sum(1 for c in cases if c.n == n) for n in sizes},
            "all_converged": bool(np.all(st == 0)), "total_iterations": int(its.sum()),
-           "max_relres": float(rr.max()), "per_size": per_size, "tuned": {str(k): v for k, v in tuned.items()}}
+           "max_relres": float(rr.max()), "per_size": per_size, "tuned": {str(k): v for k, v in tuned.items()},
+           "lockstep_classes": int(len(set(classes.tolist()) - {-1})),
+           "problems_in_lockstep": int(np.sum(classes >= 0))}
     if one_lane:
         t1 = res[1][0]
         out["one_lane"] = {"seconds": round(t1, 3), "problems_per_s": round(len(cases) / t1, 3),

@@ -200,22 +200,34 @@ helm_status helm_loss(helm_ctx ctx, const void* g, const void* u, double* loss, 
  * Sections 1 and 4).  desc: host array of nprob descriptors; velocity, phi: host
  * arrays of nprob device pointers (phi may be NULL, or phi[p] NULL, to set the phase
  * later through helm_batch_get + helm_set_phase; phi_is_f64 as in helm_set_phase).
- * lanes: problems in flight at once (0 = 4), each on its own stream and host thread.
- * The contexts are built concurrently; the call returns when all are ready. */
+ * lanes: jobs in flight at once (0 = 4), each on its own stream and host thread; a job is
+ * a lockstep class (see helm_batch_classes) or one problem.  Problems with equal
+ * descriptors in FP32 cycles are grouped into classes of at most 64 and built in one
+ * arena.  The contexts are built concurrently; the call returns when all are ready. */
 helm_status helm_batch_setup(int32_t nprob, const helm_desc* desc, const double* const* velocity,
                              const void* const* phi, int32_t phi_is_f64, int32_t lanes,
                              helm_batch* out, void* stream);
 /* The context of problem p (owned by the batch; valid until helm_batch_destroy). */
 helm_status helm_batch_get(helm_batch b, int32_t p, helm_ctx* out);
 /* helm_solve of every problem: g, u host arrays of nprob device pointers (complex128
- * n_p*n_p); iters, relres, status: host arrays of nprob outputs.  Problems are taken
- * longest first (n^2) by the lanes; each runs exactly the single-problem solve, so
+ * n_p*n_p); iters, relres, status: host arrays of nprob outputs.  The lockstep classes
+ * (mode 1, helm_batch_classes) and the remaining problems are taken largest first by the
+ * lanes; every problem goes through exactly the operations of its single solve, so
  * results equal helm_solve on the same context bit for bit.  Work already queued on
  * `stream` is waited for; the call returns when every problem is done.  Returns
  * HELM_OK if all converged, otherwise the most severe per-problem status. */
 helm_status helm_batch_solve(helm_batch b, const void* const* g, void* const* u, double tol,
                              int32_t maxit, int32_t mode, int32_t* iters, double* relres,
                              int32_t* status, void* stream);
+/* Lockstep classes of the last helm_batch_solve (host out, nprob): class_of[p] = the class
+ * problem p ran in, or -1 if it ran alone.  In mode 1, problems with equal descriptors
+ * (FP32 cycles, at most 64 per class) are built region by region in one arena at setup and
+ * solved in lockstep: every kernel is launched once for all problems of the class still
+ * iterating (gridDim.z of them), each problem keeping its own Krylov scalars, Givens
+ * rotations, stopping test and iteration count, so that its result equals its single
+ * solve bit for bit.  A class runs in lockstep only while its contexts have one phase and
+ * equal launch shapes; otherwise its problems run alone. */
+helm_status helm_batch_classes(helm_batch b, int32_t* class_of);
 helm_status helm_batch_destroy(helm_batch b); /* NULL-safe */
 
 /* Autotuner of launch shapes (form of the s-step GMRES passes per ADR level: steps

@@ -338,6 +338,12 @@ class HelmholtzBatch:
             check(code)
         return us, np.array(its[:]), np.array(rr[:]), np.array(st[:])
 
+    def classes(self) -> np.ndarray:
+        """Lockstep class of every problem at the last solve (-1: it ran alone)."""
+        out = (ctypes.c_int32 * self.nprob)()
+        check(lib().helm_batch_classes(self._b, out))
+        return np.array(out[:])
+
     def close(self):
         if getattr(self, "_b", None) and self._b.value:
             lib().helm_batch_destroy(self._b)

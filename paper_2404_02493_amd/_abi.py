@@ -17,7 +17,7 @@ STATUS = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP", 4: "
 EXPORTS = ["helm_desc_default", "helm_setup", "helm_set_phase", "helm_set_rays", "helm_set_weights", "helm_get_weights",
            "helm_get_lambdas", "helm_cycle", "helm_solve", "helm_residual", "helm_residual_noalloc",
            "helm_cycle_backward", "helm_loss",
-           "helm_batch_setup", "helm_batch_get", "helm_batch_solve", "helm_batch_destroy",
+           "helm_batch_setup", "helm_batch_get", "helm_batch_solve", "helm_batch_classes", "helm_batch_destroy",
            "helm_tune", "helm_set_tuning", "helm_get_tuning",
            "helm_debug_op", "helm_profile_begin", "helm_profile_end", "helm_destroy", "helm_status_string", "helm_last_error", "helm_version"]
 
@@ -104,6 +104,8 @@ def lib():
     L.helm_batch_get.argtypes = [vp, i32, P(vp)]
     L.helm_batch_solve.restype = i32
     L.helm_batch_solve.argtypes = [vp, P(vp), P(vp), dbl, i32, i32, P(i32), P(dbl), P(i32), vp]
+    L.helm_batch_classes.restype = i32
+    L.helm_batch_classes.argtypes = [vp, P(i32)]
     L.helm_batch_destroy.restype = i32
     L.helm_tune.restype = i32
     L.helm_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64, vp]

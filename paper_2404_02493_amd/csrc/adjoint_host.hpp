@@ -155,7 +155,7 @@ struct AdjEngine {
         HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
     }
     void fin_add(int nblk, int slot) {
-        LAUNCH(c, 8.0 * nblk, (k_finalize_add<1>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nblk, 1, 1.0,
+        LAUNCH_NB(c, 8.0 * nblk, (k_finalize_add<1>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nblk, 1, 1.0,
                S.wacc + slot);
     }
 
@@ -164,7 +164,7 @@ struct AdjEngine {
         WaveLevel& W = c->wl[1];
         const Geom& G = W.G;
         LAUNCH(c, ((u0 ? 3 : 2) * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(),
-               st, G, (const T*)W.n2, (const C*)g, (const C*)u0, (C*)S.uB, T(c->w[0]));
+               st, G, (const T*)W.n2, (const C*)g, (const C*)u0, (C*)S.uB, (const double*)c->cdev->la);
         E.restrict_down(1, g, S.uB, S.g[2]);
         rec_level(2);
         E.prolong_up(1, c->wl[2].u, S.uB);
@@ -230,18 +230,18 @@ struct AdjEngine {
         const int nb = fb(n);
         VecSet<T> K{};
         for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
-        LAUNCH(c, (x0 ? 4.0 : 2.0) * sizeof(C) * n, (k_gr_r0<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
+        LAUNCH_NB(c, (x0 ? 4.0 : 2.0) * sizeof(C) * n, (k_gr_r0<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
                (const T*)A.py, (const C*)A.c0, (const C*)b, (const C*)x0, (C*)kv[0], c->partials);
         double* gram = R->gram;  // device address arithmetic only
         LAUNCH(c, 16.0 * nb, (k_finalize_sums<2>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, 2, gram);
         for (int jj = 1; jj <= m; ++jj) {
-            LAUNCH(c, (jj + 2.0) * sizeof(C) * n, (k_gr_chain<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
+            LAUNCH_NB(c, (jj + 2.0) * sizeof(C) * n, (k_gr_chain<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
                    (const T*)A.py, (const C*)A.c0, K, jj, 1.0 / tau(l), (C*)kv[jj], c->partials);
             LAUNCH(c, 16.0 * nb * (jj + 1), (k_finalize_sums<2 * (GMAX + 1)>), dim3(1), dim3(FBLOCK), st,
                    (const double*)c->partials, nb, 2 * (jj + 1), gram + 2 * (jj * (jj + 1) / 2));
         }
-        LAUNCH(c, 0.0, k_gr_solve, dim3(1), dim3(64), st, R, tau(l));
-        LAUNCH(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n, K, m,
+        LAUNCH_NB(c, 0.0, k_gr_solve, dim3(1), dim3(64), st, R, tau(l));
+        LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n, K, m,
                (const GRec*)R, (const C*)x0, (C*)xout);
     }
 
@@ -252,13 +252,13 @@ struct AdjEngine {
         const Geom& G = W.G;
         const size_t NF = N(1);
         const int nb = fb(NF);
-        LAUNCH(c, (5.0 * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G, (const T*)W.n2,
+        LAUNCH_NB(c, (5.0 * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G, (const T*)W.n2,
                (const C*)g, (const C*)S.uB, (const C*)S.fb[0], (C*)S.fb[1], T(c->w[0]), c->partials);
         fin_add(nb, 0);
         restrict_adj(1, S.fb[1], S.lub[2]);
         rev_level(2);
         prolong_adj(1, S.lgb[2], S.fb[1], nullptr);
-        LAUNCH(c, ((u0 ? 5.0 : 4.0) * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G,
+        LAUNCH_NB(c, ((u0 ? 5.0 : 4.0) * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G,
                (const T*)W.n2, (const C*)g, (const C*)u0, (const C*)S.fb[1], (C*)S.fb[0], T(c->w[0]), c->partials);
         fin_add(nb, 0);
     }
@@ -270,7 +270,7 @@ struct AdjEngine {
         auto go = [&](auto tf, auto tc) {
             using Pf = decltype(tf);
             using Pc = decltype(tc);
-            LAUNCH(c, sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * double(nc), (k_restrict_scale<Pf, Pc>),
+            LAUNCH_NB(c, sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * double(nc), (k_restrict_scale<Pf, Pc>),
                    dim3(fb(nc)), dim3(BLOCK), st, n, (const cplx<Pf>*)x, (cplx<Pc>*)out, 4.0);
         };
         if (c->wl[l].f64) go(double{}, double{});
@@ -284,7 +284,7 @@ struct AdjEngine {
         auto go = [&](auto tf, auto tc) {
             using Pf = decltype(tf);
             using Pc = decltype(tc);
-            LAUNCH(c, (3.0 * sizeof(cplx<Pf>) + sizeof(Pf)) * n + sizeof(cplx<Pc>) * double(N(l + 1)),
+            LAUNCH_NB(c, (3.0 * sizeof(cplx<Pf>) + sizeof(Pf)) * n + sizeof(cplx<Pc>) * double(N(l + 1)),
                    (k_prolong_adj<Pc, Pf>), dim3(fb(n)), dim3(BLOCK), st, W.G, (const Pf*)W.n2,
                    (const cplx<Pc>*)rcbar, (cplx<Pf>*)ubar, (cplx<Pf>*)gbar);
         };
@@ -311,27 +311,27 @@ struct AdjEngine {
         const double th = 0.5 * (lam + a), dc = 0.5 * (lam - a);
         const double th_t = -lam / (2.0 * alpha * alpha), dc_t = lam / (2.0 * alpha * alpha);
         double rho = dc / th, rho_t = (dc_t * th - dc * th_t) / (th * th);
-        LAUNCH(c, 7.0 * sizeof(Cp) * n, (k_chebadj_start<P>), dim3(nb), dim3(BLOCK), st, n, (const Cp*)ubar, r, rt, d,
+        LAUNCH_NB(c, 7.0 * sizeof(Cp) * n, (k_chebadj_start<P>), dim3(nb), dim3(BLOCK), st, n, (const Cp*)ubar, r, rt, d,
                dt, s, stt, P(1.0 / th), P(-th_t / (th * th)));
         for (int t = 1; t < m; ++t) {
-            LAUNCH(c, (4.0 * sizeof(Cp) + sizeof(P)) * n, (k_apply_A2<P>), dim3(nb), dim3(BLOCK), st, G,
+            LAUNCH_NB(c, (4.0 * sizeof(Cp) + sizeof(P)) * n, (k_apply_A2<P>), dim3(nb), dim3(BLOCK), st, G,
                    (const P*)W.n2, (const Cp*)d, (const Cp*)dt, t1, t2);
             const double den = 2.0 * th - dc * rho;
             const double den_t = 2.0 * th_t - dc_t * rho - dc * rho_t;
             const double rn = dc / den, rn_t = (dc_t * den - dc * den_t) / (den * den);
             const double c1 = rn * rho, c1t = rn_t * rho + rn * rho_t;
             const double c2 = 2.0 / den, c2t = -2.0 * den_t / (den * den);
-            LAUNCH(c, (14.0 * sizeof(Cp) + sizeof(P)) * n, (k_chebadj_step<P>), dim3(nb), dim3(BLOCK), st, G,
+            LAUNCH_NB(c, (14.0 * sizeof(Cp) + sizeof(P)) * n, (k_chebadj_step<P>), dim3(nb), dim3(BLOCK), st, G,
                    (const P*)W.n2, (const Cp*)t1, (const Cp*)t2, r, rt, d, dt, s, stt, P(c1), P(c2), P(c1t), P(c2t));
             rho = rn;
             rho_t = rn_t;
         }
         E.template residual<P>(G, W.n2, g, u, res);
-        LAUNCH(c, (2.0 * sizeof(Cp) + sizeof(P)) * n, (k_dot_ah<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,
+        LAUNCH_NB(c, (2.0 * sizeof(Cp) + sizeof(P)) * n, (k_dot_ah<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,
                (const Cp*)stt, (const Cp*)res, c->partials);
         fin_add(nb, l - 1);
         E.template applyA<P>(G, W.n2, s, t1, 0);
-        LAUNCH(c, (5.0 * sizeof(Cp) + sizeof(P)) * n, (k_adj_ahsub<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,
+        LAUNCH_NB(c, (5.0 * sizeof(Cp) + sizeof(P)) * n, (k_adj_ahsub<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,
                (const Cp*)t1, (Cp*)(u ? ubar : nullptr), (Cp*)gbar);
     }
 
@@ -362,12 +362,12 @@ struct AdjEngine {
         WaveLevel& W = c->wl[2];
         AdrTape& Tp = S.adr[s][2];
         const size_t n = N(2);
-        LAUNCH(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_modadd_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
+        LAUNCH_NB(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_modadd_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
                (const C*)S.lub[2], (const C*)Tp.xo, (const C*)c->car2, (C*)S.axb[2], S.thb);
         rev_adrv(s, 2);
-        LAUNCH(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_demod_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
+        LAUNCH_NB(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_demod_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
                (const C*)S.abb[2], (const C*)Tp.b, (const C*)c->car2, (C*)S.rbar2, S.thb);
-        LAUNCH(c, (5.0 * sizeof(C) + sizeof(T)) * n, (k_adj_ahsub<T>), dim3(fb(n)), dim3(BLOCK), st, W.G,
+        LAUNCH_NB(c, (5.0 * sizeof(C) + sizeof(T)) * n, (k_adj_ahsub<T>), dim3(fb(n)), dim3(BLOCK), st, W.G,
                (const T*)W.n2, (const C*)S.rbar2, (C*)S.lub[2], (C*)S.lgb[2]);
     }
 
@@ -381,10 +381,10 @@ struct AdjEngine {
         }
         rev_gmres(l, Tp.x2, m, Tp.kpost, Tp.rpost, S.axb[l], S.abb[l], true, S.axb2[l]);
         const size_t nc = N(l + 1);
-        LAUNCH(c, sizeof(C) * (double(N(l)) + nc), (k_restrict_scale<T, T>), dim3(fb(nc)), dim3(BLOCK), st, A.n,
+        LAUNCH_NB(c, sizeof(C) * (double(N(l)) + nc), (k_restrict_scale<T, T>), dim3(fb(nc)), dim3(BLOCK), st, A.n,
                (const C*)S.axb2[l], (C*)S.axb[l + 1], 4.0);
         rev_adrv(s, l + 1);
-        LAUNCH(c, (6.0 * sizeof(C) + 2 * sizeof(T) + 32.0 * 2) * NN(A.n), (k_adr_rr_adj<T>), dim3(fb(N(l))),
+        LAUNCH_NB(c, (6.0 * sizeof(C) + 2 * sizeof(T) + 32.0 * 2) * NN(A.n), (k_adr_rr_adj<T>), dim3(fb(N(l))),
                dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)S.abb[l + 1],
                (const C*)Tp.x1, (C*)S.axb2[l], (C*)S.abb[l], S.pxb[l], S.pyb[l], S.c0b[l]);
         rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb2[l], S.abb[l], false, nullptr);
@@ -399,11 +399,11 @@ struct AdjEngine {
         const int nb = fb(n);
         VecSet<T> K{};
         for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
-        LAUNCH(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
+        LAUNCH_NB(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
                c->partials);
         LAUNCH(c, 16.0 * nb * m, (k_finalize_sums<2 * GMAX>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb,
                2 * m, (double*)R->cbar);
-        LAUNCH(c, 0.0, k_ga_prep, dim3(1), dim3(64), st, R, tau(l));
+        LAUNCH_NB(c, 0.0, k_ga_prep, dim3(1), dim3(64), st, R, tau(l));
         VecSet<T> V{};
         V.v[0] = (const C*)xbar;
         for (int q = 0; q <= m; ++q) V.v[q + 1] = (const C*)kv[q];
@@ -412,11 +412,11 @@ struct AdjEngine {
         C* nxt = (C*)S.acc1[l];
         const double* coef = R->coef;
         const double gbytes = 32.0 * 2 + sizeof(C);  // coefficient cotangents (read-modify-write) and a
-        LAUNCH(c, (nv + 1.0) * sizeof(C) * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
+        LAUNCH_NB(c, (nv + 1.0) * sizeof(C) * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
                (const T*)A.py, (const C*)A.c0, V, nv, coef + m * GCOEF_STRIDE, (const C*)nullptr, 0.0,
                (const C*)nullptr, acc, S.pxb[l], S.pyb[l], S.c0b[l]);
         for (int j = m + 1; j >= 2; --j) {
-            LAUNCH(c, ((nv + 2.0) * sizeof(C) + 2 * sizeof(T)) * n + gbytes * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK),
+            LAUNCH_NB(c, ((nv + 2.0) * sizeof(C) + 2 * sizeof(T)) * n + gbytes * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK),
                    st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, V, nv, coef + (j - 2) * GCOEF_STRIDE,
                    (const C*)acc, 1.0 / tau(l), (const C*)kv[j - 2], nxt, S.pxb[l], S.pyb[l], S.c0b[l]);
             std::swap(acc, nxt);
@@ -426,7 +426,7 @@ struct AdjEngine {
         if (x0) {
             VecSet<T> V1{};
             V1.v[0] = (const C*)xbar;
-            LAUNCH(c, (4.0 * sizeof(C) + 2 * sizeof(T)) * n + gbytes * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK), st,
+            LAUNCH_NB(c, (4.0 * sizeof(C) + 2 * sizeof(T)) * n + gbytes * n, (k_ga_step<T>), dim3(nb), dim3(BLOCK), st,
                    A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, V1, 1, (const double*)R->one, (const C*)acc,
                    -1.0, (const C*)x0, (C*)xbar0, S.pxb[l], S.pyb[l], S.c0b[l]);
         }
@@ -440,12 +440,12 @@ struct AdjEngine {
         if (S.M > 0) {
             for (int l = 2; l <= c->LA; ++l) {
                 const int nl = n >> (l - 1);
-                LAUNCH(c, (2.0 * sizeof(T) + 32.0 + 16.0) * NN(nl), (k_phi_adj<T>), dim3(fb(N(l))), dim3(BLOCK), st, nl,
+                LAUNCH_NB(c, (2.0 * sizeof(T) + 32.0 + 16.0) * NN(nl), (k_phi_adj<T>), dim3(fb(N(l))), dim3(BLOCK), st, nl,
                        1 << (l - 2), n / 2, c->d.k, c->d.sign, (const T*)c->al[l].px, (const T*)c->al[l].py,
                        (const double*)S.pxb[l], (const double*)S.pyb[l], (const c128*)S.c0b[l],
                        (const double*)(l == 2 ? S.thb : nullptr), S.phib2);
             }
-            LAUNCH(c, (sizeof(TO) + 2.0) * NF, (k_phi_out<TO>), dim3(fb(NF)), dim3(BLOCK), st, n,
+            LAUNCH_NB(c, (sizeof(TO) + 2.0) * NF, (k_phi_out<TO>), dim3(fb(NF)), dim3(BLOCK), st, n,
                    (const double*)S.phib2, (TO*)grad_phi);
         } else {
             HIPCHK(hipMemsetAsync(grad_phi, 0, NF * sizeof(TO), st));
@@ -510,11 +510,11 @@ static double loss_grad(helm_ctx c, const void* g, const void* u, void* grad_u, 
     const Geom G = make_geom_sys(c);
     const size_t NF = (size_t)G.n * G.n;
     const int nb = flat_blocks(NF);
-    LAUNCH(c, (2.0 * sizeof(cplx<T>) + 8.0 + 16.0) * NF, (k_loss_resid<T>), dim3(nb), dim3(BLOCK), st, G,
+    LAUNCH_NB(c, (2.0 * sizeof(cplx<T>) + 8.0 + 16.0) * NF, (k_loss_resid<T>), dim3(nb), dim3(BLOCK), st, G,
            (const double*)c->n2f, (const cplx<T>*)g, (const cplx<T>*)u, (c128*)c->rbuf, c->partials);
     LAUNCH(c, 8.0 * nb, (k_finalize_sums<1>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, 1, c->dscal);
     if (grad_u)
-        LAUNCH(c, (16.0 + 8.0 + sizeof(cplx<T>)) * NF, (k_loss_grad<T>), dim3(nb), dim3(BLOCK), st, G,
+        LAUNCH_NB(c, (16.0 + 8.0 + sizeof(cplx<T>)) * NF, (k_loss_grad<T>), dim3(nb), dim3(BLOCK), st, G,
                (const double*)c->n2f, (const c128*)c->rbuf, (cplx<T>*)grad_u);
     double h = 0.0;
     HIPCHK(hipMemcpyAsync(&h, c->dscal, sizeof(double), hipMemcpyDeviceToHost, st));

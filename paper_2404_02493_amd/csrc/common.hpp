@@ -106,6 +106,35 @@ __device__ __forceinline__ V ldz(const V* __restrict__ a, int i, int j, int n) {
     return a[(size_t)i * n + j];
 }
 
+// ------------------------------------------------------------------ batched launches
+// One launch can serve several problems of the same shape: launched with gridDim.z =
+// n, block (x, y, z) works on problem p[z], whose device arrays all sit p[z] * stride
+// bytes after those of problem 0 (the problems of one batch class are laid out in one
+// arena, region by region in the same order).  A kernel therefore shifts every pointer
+// argument by off() before it touches memory.  A single problem: n = 1, p[0] = 0,
+// stride = 0.  aux carries one integer per problem for the kernels that need one.
+constexpr int BMAX = 64;
+struct BatchIdx {
+    long long stride;
+    int n;
+    int p[BMAX];
+    int aux[BMAX];
+    __device__ __forceinline__ size_t off() const { return (size_t)p[blockIdx.z] * (size_t)stride; }
+    __device__ __forceinline__ int aux_here() const { return aux[blockIdx.z]; }
+};
+
+// A pointer moved by o bytes (null stays null); argument structs define bsh_one too.  The
+// shift is pointer arithmetic on the argument itself, so the result stays based on it
+// (the restrict qualification of kernel arguments keeps its meaning).
+template <typename Q>
+__device__ __forceinline__ Q bsh_one(size_t o, Q q) {
+    return q ? (Q)((const char*)q + o) : q;
+}
+template <typename... Q>
+__device__ __forceinline__ void bshift(size_t o, Q&... q) {
+    ((q = bsh_one(o, q)), ...);
+}
+
 // Maximum Krylov dimension supported by the device-side least squares.
 constexpr int MAXM = 24;
 

@@ -76,6 +76,16 @@ struct AdrLevel {
 
 struct AdjState;
 
+// Chebyshev coefficient tables and per-level (lambda, alpha) in device memory (one copy per
+// problem): la[0] = the Jacobi weight of level 1, la[2 l], la[2 l + 1] = (lambda_l, alpha_l);
+// cheb[l][kind] rows of 3 doubles, row 0 = {1/theta, 0, 0},
+// row s = {0, c1, c2} of step s; kind 0/1/2 = the pre, post and coarsest step counts.
+constexpr int CHEB_ROWS = 65;
+struct CycleDev {
+    double la[2 * 16];
+    double cheb[16][3][CHEB_ROWS * 3];
+};
+
 }  // namespace helm
 
 struct helm_ctx_s {
@@ -105,6 +115,14 @@ struct helm_ctx_s {
     double* partials = nullptr;
     size_t partials_cap = 0;  // doubles
     double* dscal = nullptr;  // small device scratch (norms)
+    helm::CycleDev* cdev = nullptr;  // Chebyshev tables and level (lambda, alpha) on the device
+    helm::BatchIdx bi{};             // problems served by each launch (zero: this context alone)
+    // batch arena: the context's device buffers are carved from [arena, arena + arena_cap)
+    // in allocation order (its region of a batch class); count_bytes sums every allocation
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0, count_bytes = 0;
+    void* bg = nullptr;  // batch staging of g and u (complex128, fine grid)
+    void* bu = nullptr;
     helm::KrylovScal* Kout = nullptr;
     helm::KrylovScal* Kin = nullptr;
     // outer FGMRES (complex128) and inner (cycle precision, iterative refinement)
@@ -163,6 +181,17 @@ struct helm_ctx_s {
 // A batch of independent problems (see batch.hpp): one context per problem and
 // one stream + host thread per lane.
 struct helm_batch_s {
+    // problems of equal descriptors, built region by region in one arena, solved in lockstep
+    struct Class {
+        std::vector<int> probs;     // problem indices, region q holds probs[q]
+        char* arena = nullptr;
+        size_t stride = 0;          // bytes per region
+        double* dg = nullptr;       // device gather buffer (per-problem scalars and columns)
+        double* hg = nullptr;       // pinned host copy of it
+        hipEvent_t ev[helm::MAXM + 1] = {};
+    };
+    std::vector<Class> classes;
+    std::vector<int> last_class;  // per problem: the class it ran in at the last solve, -1 alone
     std::vector<helm_ctx> ctx;
     int lanes = 0;
     int device = 0;
@@ -171,8 +200,11 @@ struct helm_batch_s {
     hipEvent_t ev_in = nullptr;
 };
 
-// Launch with optional per-launch event timing (name = kernel expression).
-#define LAUNCH(CTX, BYTES, KERN, GRID, BLK, ST, ...)                                    \
+// Launch with optional per-launch event timing (name = kernel expression).  LAUNCH
+// appends the context's batch index (the problems the launch serves, gridDim.z of them;
+// one for a single problem) to the kernel arguments; LAUNCH_NB is for kernels that
+// serve one problem only.
+#define LAUNCH_IMPL(CTX, BYTES, KERN, GRID, BLK, ST, ...)                               \
     do {                                                                                \
         hipEvent_t e0_ = nullptr;                                                       \
         if ((CTX)->prof.on) e0_ = (CTX)->prof.next(ST);                                 \
@@ -182,12 +214,28 @@ struct helm_batch_s {
             (CTX)->prof.recs.push_back({#KERN, (int)dim3(GRID).x, (double)(BYTES), e0_, e1_}); \
         }                                                                               \
     } while (0)
+#define LAUNCH(CTX, BYTES, KERN, GRID, BLK, ST, ...)                                                       \
+    LAUNCH_IMPL(CTX, BYTES, KERN, helm::bgrid(CTX, GRID), BLK, ST, __VA_ARGS__, (CTX)->bi)
+#define LAUNCH_NB(CTX, BYTES, KERN, GRID, BLK, ST, ...) LAUNCH_IMPL(CTX, BYTES, KERN, GRID, BLK, ST, __VA_ARGS__)
 
 namespace helm {
+
+// Grid of a launch: gridDim.z = the number of problems the context's batch index serves.
+static inline dim3 bgrid(const helm_ctx c, dim3 g) {
+    g.z = c->bi.n > 1 ? (unsigned)c->bi.n : 1u;
+    return g;
+}
 
 static void* dalloc(helm_ctx c, size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 256;
+    const size_t rb = (bytes + 255) & ~size_t(255);
+    c->count_bytes += rb;
+    if (c->arena && c->arena_used + rb <= c->arena_cap) {
+        p = c->arena + c->arena_used;
+        c->arena_used += rb;
+        return p;
+    }
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -322,42 +370,42 @@ struct Engine {
         LAUNCH(c, sizeof(cplx<P>) * double(n), (k_zero<P>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, (cplx<P>*)y);
     }
 
+    // Coefficient table of level l for m steps (see CycleDev; the pre, post and coarsest
+    // counts of the descriptor).
+    const double* cheb_table(int l, int m, double alpha) const {
+        const int kind = m == c->d.cheb_pre ? 0 : m == c->d.cheb_post ? 1 : m == c->d.cheb_coarse ? 2 : -1;
+        REQUIRE(kind >= 0, "Chebyshev step count without a coefficient table");
+        REQUIRE(alpha == c->w[l - 1], "Chebyshev alpha other than the level's weight");
+        return c->cdev->cheb[l][kind];
+    }
+
     template <typename P>
     void chebyshev(int l, const void* g, void* u, bool u_zero, double alpha, int m) {
         WaveLevel& W = c->wl[l];
         const Geom& G = W.G;
-        const double lam = W.lam;
-        const double a = lam / alpha;
-        const double theta = 0.5 * (lam + a);
-        const double dc = 0.5 * (lam - a);
         const size_t n = N(l);
+        const double* tab = cheb_table(l, m, alpha);
         // with two steps or more the first fused step takes u = 0 itself and the last one
         // adds the final d (no zero fill, no closing axpy)
         const bool fused_ends = m >= 2;
         if (u_zero && !fused_ends) zero<P>(u, n);
         if (u_zero)
             LAUNCH(c, (3 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start<P>), dim3(tiles_of(G.n)),
-                   tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)g, (cplx<P>*)W.r, (cplx<P>*)W.d,
-                   P(1.0 / theta));
+                   tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)g, (cplx<P>*)W.r, (cplx<P>*)W.d, tab);
         else
             LAUNCH(c, (4 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start_res<P>), dim3(tiles_of(G.n)),
                    tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)g, (const cplx<P>*)u, (cplx<P>*)W.r,
-                   (cplx<P>*)W.d, P(1.0 / theta));
-        double rho = dc / theta;
+                   (cplx<P>*)W.d, tab);
         void* dcur = W.d;  // d alternates between W.d and W.t
         void* dnext = W.t;
         for (int step = 1; step <= m; ++step) {
             if (step < m) {
-                const double den = 2.0 * theta - dc * rho;
-                const double rho_new = dc / den;
-                const double c1 = rho_new * rho, c2 = 2.0 / den;
                 const int mode = (step == 1 && u_zero ? CHEB_UZERO : 0) | (step == m - 1 ? CHEB_LAST : 0);
                 const int nb = 6 - ((mode & CHEB_UZERO) ? 1 : 0) - ((mode & CHEB_LAST) ? 2 : 0);
                 LAUNCH(c, (nb * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_fused<P>), dim3(tiles_of(G.n)),
                        tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)dcur, (cplx<P>*)dnext, (cplx<P>*)W.r,
-                       (cplx<P>*)u, P(c1), P(c2), mode);
+                       (cplx<P>*)u, tab + 3 * step, mode);
                 std::swap(dcur, dnext);
-                rho = rho_new;
             } else if (!fused_ends) {
                 LAUNCH(c, 3 * sizeof(cplx<P>) * double(n), (k_axpy<P>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, P(1),
                                    (const cplx<P>*)dcur, (cplx<P>*)u);
@@ -413,8 +461,7 @@ struct Engine {
             t.r = W.r;
             t.d = W.d;
             t.t = W.t;
-            t.lam = W.lam;
-            t.alpha = c->w[l - 1];
+            t.la = c->cdev->la + 2 * l;
         }
         a.l0 = l0;
         a.L = c->L;
@@ -463,7 +510,7 @@ struct Engine {
     void cycle(const void* g, const void* u_in, void* u_out) {
         WaveLevel& W = c->wl[1];
         const Geom& G = W.G;
-        const T w0 = T(c->w[0]);
+        const double* w0 = c->cdev->la;  // la[0]: the Jacobi weight of this problem
         if (u_in == nullptr) {
             // the zero-start Jacobi sweep is recomputed inside the restriction and the
             // post-smoother instead of being stored
@@ -702,7 +749,7 @@ struct Engine {
             krylov_fin<NV>(c, st, nbf, FIN_ORTH2, j, m, A.K, 1e-14);
         }
         LAUNCH(c, (m + 1 + (x0_zero ? 0 : 1)) * sizeof(C) * double(n), (k_krylov_combine<T, NV>), dim3(flat_blocks(n)), dim3(BLOCK), st, n, V,
-                           (const KrylovScal*)A.K, (const C*)(x0_zero ? nullptr : A.x), (C*)A.x);
+                           (const KrylovScal*)A.K, (const C*)(x0_zero ? nullptr : A.x), (C*)A.x, 0);
     }
     // Steps per unit of the marching s-step passes on ADR level l (a multiple of 8; a
     // unit covers that many rows minus twice its halo): the tuned value, else the
@@ -973,6 +1020,36 @@ static void residual_fp64(helm_ctx c, hipStream_t st, const void* g, const void*
 
 static void drop_graphs(helm_ctx c);
 
+// Chebyshev coefficients of every level for the pre, post and coarsest step counts (the
+// three-term recurrence of eq. cheb on [lambda_l / alpha_l, lambda_l]) and the per-level
+// (lambda, alpha), written to the context's device table.
+static void write_cycle_tables(helm_ctx c) {
+    CycleDev h{};
+    const int ms[3] = {c->d.cheb_pre, c->d.cheb_post, c->d.cheb_coarse};
+    h.la[0] = c->w[0];
+    for (int l = 2; l <= c->L; ++l) {
+        const double lam = c->wl[l].lam, alpha = c->w[l - 1];
+        h.la[2 * l] = lam;
+        h.la[2 * l + 1] = alpha;
+        const double a = lam / alpha;
+        const double theta = 0.5 * (lam + a);
+        const double dc = 0.5 * (lam - a);
+        for (int kind = 0; kind < 3; ++kind) {
+            double* t = h.cheb[l][kind];
+            t[0] = double(1.0 / theta);
+            double rho = dc / theta;
+            for (int step = 1; step < ms[kind] && step < CHEB_ROWS; ++step) {
+                const double den = 2.0 * theta - dc * rho;
+                const double rho_new = dc / den;
+                t[3 * step + 1] = rho_new * rho;
+                t[3 * step + 2] = 2.0 / den;
+                rho = rho_new;
+            }
+        }
+    }
+    HIPCHK(hipMemcpy(c->cdev, &h, sizeof(h), hipMemcpyHostToDevice));
+}
+
 // ------------------------------------------------------------------ setup
 static void validate(const helm_desc* d) {
     REQUIRE(d != nullptr, "desc is NULL");
@@ -1058,7 +1135,7 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
         const double* n2d = c->n2f;
         double* tmp = nullptr;
         if (l > 1) {
-            tmp = (double*)dalloc(c, Nl * sizeof(double));
+            HIPCHK(hipMalloc((void**)&tmp, Nl * sizeof(double)));
             hipLaunchKernelGGL((k_inject_real<double, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.n,
                                1 << (l - 1), n, (const double*)c->n2f, tmp);
             n2d = tmp;
@@ -1079,7 +1156,6 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
         W.n2mean = hs[2] / double((size_t)(W.n - 1) * (W.n - 1));
         if (tmp) {
             HIPCHK(hipFree(tmp));
-            c->allocs.pop_back();
         }
     }
     // first level (>= 3) small enough for the one-workgroup tail of the wave cycle
@@ -1098,6 +1174,8 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
         for (int l = 2; l <= L; ++l) c->w[l - 1] = median_alpha(d.k, c->wl[l].n2mean, c->wl[l].n, c->wl[l].lam);
     }
     c->w_default = c->w;
+    c->cdev = (CycleDev*)dalloc(c, sizeof(CycleDev));
+    write_cycle_tables(c);
     // level-1 second iterate
     c->ws1 = dalloc(c, NF * csize(f64c));
     // ADR levels
@@ -1381,8 +1459,9 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
         const double eta = 1e-4;
         while (!converged && its < maxit) {
             // inner right-hand side r / ||r|| in complex64 (fV[0] holds r)
-            LAUNCH(c, 24.0 * double(NF), (k_cast_scale<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
-                               (const c128*)c->fV[0], (c64*)c->iV[0], 1.0 / rn);
+            LAUNCH(c, 0.0, k_norm_scales, dim3(1), dim3(64), st, c->dscal);
+            LAUNCH(c, 24.0 * double(NF), (k_cast_scale_dev<float, double>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
+                   (const c128*)c->fV[0], (c64*)c->iV[0], (const double*)c->dscal + 2);
             LAUNCH(c, 8.0 * double(NF), (k_zero<float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF, (c64*)c->dbuf);
             auto prec = [&](int j, const double*) { cycle_any(c, c->iV[j], nullptr, c->iZ[j], st); };
             double est = 0;
@@ -1391,8 +1470,8 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
             int used = fgmres_cycle<float>(c, st, c->wl[1].n2, c->iV, c->iZ, c->Kin, false, c->dbuf, 1.0, target,
                                            maxit - its, prec, nullptr, &est, &bd);
             its += used;
-            LAUNCH(c, 40.0 * double(NF), (k_add_cast<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
-                               (const c64*)c->dbuf, (c128*)u, rn);
+            LAUNCH(c, 40.0 * double(NF), (k_add_cast_dev<double, float>), dim3(flat_blocks(NF)), dim3(BLOCK), st, NF,
+                   (const c64*)c->dbuf, (c128*)u, (const double*)c->dscal + 3);
             residual_fp64(c, st, g, u, c->fV[0], &rn, &gn);
             hist.push_back(rn / gn);
             if (bd || !std::isfinite(rn) || rn > 1e4 * r0) {
@@ -1457,9 +1536,9 @@ static void residual_fp64_noalloc(helm_ctx c, hipStream_t st, const void* g, con
                                      std::to_string(NOALLOC_PARTIALS / 2) + " of the static scratch");
     double* sp = noalloc_scratch();
     hipLaunchKernelGGL(k_residual_norms, dim3(nbt), tile_block(), 0, st, G, (const double*)c->n2f, (const c128*)g,
-                       (const c128*)u, (c128*)r, sp);
+                       (const c128*)u, (c128*)r, sp, BatchIdx{});
     hipLaunchKernelGGL((k_finalize_sums<2>), dim3(1), dim3(FBLOCK), 0, st, (const double*)sp, nbt, 2,
-                       sp + NOALLOC_PARTIALS);
+                       sp + NOALLOC_PARTIALS, BatchIdx{});
     HIPCHK(hipGetLastError());
     double h[2];
     HIPCHK(hipMemcpyAsync(h, sp + NOALLOC_PARTIALS, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -1566,6 +1645,7 @@ helm_status helm_set_weights(helm_ctx ctx, const double* w) {
             if (l >= 1) REQUIRE(w[l] >= 1.0, "Chebyshev alpha must be >= 1");
         }
         ctx->w.assign(w, w + ctx->L);
+        write_cycle_tables(ctx);
         drop_graphs(ctx);
         return HELM_OK;
     })
@@ -1692,16 +1772,68 @@ helm_status helm_batch_setup(int32_t nprob, const helm_desc* desc, const double*
             }
             HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
             lanes_after(b, (hipStream_t)stream);
+            // classes: equal descriptors in FP32 cycles, at most BMAX problems each; the others alone
+            std::vector<int> single;
+            std::vector<char> taken(nprob, 0);
+            for (int p : longest_first_desc(desc, nprob)) {
+                if (taken[p]) continue;
+                taken[p] = 1;
+                std::vector<int> members{p};
+                if (desc[p].cycle_prec == HELM_C64)
+                    for (int q = p + 1; q < nprob && (int)members.size() < BMAX; ++q)
+                        if (!taken[q] && same_desc(desc[p], desc[q])) {
+                            taken[q] = 1;
+                            members.push_back(q);
+                        }
+                if (members.size() >= 2) {
+                    helm_batch_s::Class K;
+                    K.probs = members;
+                    b->classes.push_back(K);
+                } else {
+                    single.push_back(p);
+                }
+            }
+            for (auto& K : b->classes) {
+                K.stride = class_stride(desc[K.probs[0]], velocity[K.probs[0]], b->streams[0]);
+                HIPCHK(hipMalloc((void**)&K.arena, K.stride * K.probs.size()));
+                const size_t gsz = sizeof(double) * (size_t)(MAXM + 1) * BMAX * CLASS_GATHER;
+                HIPCHK(hipMalloc((void**)&K.dg, gsz));
+                HIPCHK(hipHostMalloc((void**)&K.hg, gsz, hipHostMallocDefault));
+                for (auto& e : K.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            }
+            // build: every problem of a class in its region, the others on their own
+            struct Item {
+                int p, cls, q;
+            };
+            std::vector<Item> items;
+            for (int k = 0; k < (int)b->classes.size(); ++k)
+                for (int q = 0; q < (int)b->classes[k].probs.size(); ++q) items.push_back({b->classes[k].probs[q], k, q});
+            for (int p : single) items.push_back({p, -1, 0});
             std::vector<helm_status> st(nprob, HELM_OK);
             std::vector<std::string> msg(nprob);
-            run_lanes(b, longest_first_desc(desc, nprob), [&](int p, int lane) {
-                helm_ctx c = new helm_ctx_s();
-                c->d = desc[p];
-                b->ctx[p] = c;
-                build(c, velocity[p], b->streams[lane]);
-                if (phi && phi[p]) set_phase(c, phi[p], phi_is_f64 != 0, b->streams[lane]);
-                return HELM_OK;
-            }, st, msg);
+            run_jobs(b, (int)items.size(), [&](int j, int lane, bool dev_ok) {
+                const Item it = items[j];
+                try {
+                    REQUIRE(dev_ok, "hipSetDevice failed on a lane thread");
+                    const void* ph = phi ? phi[it.p] : nullptr;
+                    if (it.cls >= 0) {
+                        b->ctx[it.p] = class_build(b->classes[it.cls], it.q, desc[it.p], velocity[it.p], ph,
+                                                   phi_is_f64 != 0, b->streams[lane]);
+                    } else {
+                        helm_ctx c = new helm_ctx_s();
+                        c->d = desc[it.p];
+                        b->ctx[it.p] = c;
+                        build(c, velocity[it.p], b->streams[lane]);
+                        if (ph) set_phase(c, ph, phi_is_f64 != 0, b->streams[lane]);
+                    }
+                } catch (const Error& e) {
+                    st[it.p] = e.code;
+                    msg[it.p] = e.what();
+                } catch (const std::exception& e) {
+                    st[it.p] = HELM_EHIP;
+                    msg[it.p] = e.what();
+                }
+            });
             helm_status s = first_error(st, msg);
             if (s != HELM_OK) throw Error(s, g_last_error);
             caller_after(b, (hipStream_t)stream);
@@ -1740,20 +1872,75 @@ helm_status helm_batch_solve(helm_batch b, const void* const* g, void* const* u,
             if (mode == 1) REQUIRE(c->f32, "mode 1 needs cycle_prec = HELM_C64 for every problem");
         }
         lanes_after(b, (hipStream_t)stream);
+        // jobs: the classes that can run in lockstep (mode 1), then every other problem alone,
+        // the largest amount of work first
+        struct Job {
+            int cls, p;
+            double work;
+        };
+        std::vector<Job> jobs;
+        std::vector<char> in_class(np, 0);
+        if (mode == 1)
+            for (int k = 0; k < (int)b->classes.size(); ++k)
+                if (class_lockstep_ok(b, b->classes[k])) {
+                    const auto& K = b->classes[k];
+                    for (int p : K.probs) in_class[p] = 1;
+                    jobs.push_back({k, -1, NN(b->ctx[K.probs[0]]->d.n) * K.probs.size()});
+                }
+        for (int p = 0; p < np; ++p)
+            if (!in_class[p]) jobs.push_back({-1, p, NN(b->ctx[p]->d.n)});
+        std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& c) { return a.work > c.work; });
+        b->last_class.assign(np, -1);
+        for (const Job& jb : jobs)
+            if (jb.cls >= 0)
+                for (int p : b->classes[jb.cls].probs) b->last_class[p] = jb.cls;
         std::vector<helm_status> st(np, HELM_OK);
         std::vector<std::string> msg(np);
-        run_lanes(b, longest_first(b), [&](int p, int lane) {
-            int it = 0;
-            double rr = 0.0;
-            helm_status s = solve(b->ctx[p], g[p], u[p], tol, maxit, mode, &it, &rr, nullptr, b->streams[lane]);
-            HIPCHK(hipGetLastError());
-            iters[p] = it;
-            relres[p] = rr;
-            return s;
-        }, st, msg);
+        run_jobs(b, (int)jobs.size(), [&](int j, int lane, bool dev_ok) {
+            const Job jb = jobs[j];
+            auto fail_all = [&](helm_status code, const std::string& m) {
+                if (jb.cls >= 0) {
+                    for (int p : b->classes[jb.cls].probs) {
+                        st[p] = code;
+                        msg[p] = m;
+                    }
+                } else {
+                    st[jb.p] = code;
+                    msg[jb.p] = m;
+                }
+            };
+            try {
+                REQUIRE(dev_ok, "hipSetDevice failed on a lane thread");
+                if (jb.cls >= 0) {
+                    class_solve(b, b->classes[jb.cls], g, u, tol, maxit, iters, relres, st, b->streams[lane]);
+                } else {
+                    int it = 0;
+                    double rr = 0.0;
+                    st[jb.p] = solve(b->ctx[jb.p], g[jb.p], u[jb.p], tol, maxit, mode, &it, &rr, nullptr,
+                                     b->streams[lane]);
+                    HIPCHK(hipGetLastError());
+                    iters[jb.p] = it;
+                    relres[jb.p] = rr;
+                }
+            } catch (const Error& e) {
+                fail_all(e.code, e.what());
+            } catch (const std::exception& e) {
+                fail_all(HELM_EHIP, e.what());
+            }
+            if (jb.cls >= 0) b->ctx[b->classes[jb.cls].probs[0]]->bi = BatchIdx{};
+        });
         for (int p = 0; p < np; ++p) status[p] = st[p];
         caller_after(b, (hipStream_t)stream);
         return first_error(st, msg);
+    })
+}
+
+helm_status helm_batch_classes(helm_batch b, int32_t* class_of) {
+    ABI_GUARD({
+        REQUIRE(b != nullptr && class_of != nullptr, "NULL argument");
+        for (size_t p = 0; p < b->ctx.size(); ++p)
+            class_of[p] = p < b->last_class.size() ? b->last_class[p] : -1;
+        return HELM_OK;
     })
 }
 
@@ -1828,7 +2015,8 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                 case 4:
                     REQUIRE(level == 1, "Jacobi runs on level 1");
                     hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(W.n)), tile_block(), 0, st, W.G, (const T*)W.n2,
-                                       (const cplx<T>*)in2, (const cplx<T>*)in, (cplx<T>*)out, T(ctx->w[0]));
+                                       (const cplx<T>*)in2, (const cplx<T>*)in, (cplx<T>*)out,
+                                       (const double*)ctx->cdev->la, BatchIdx{});
                     break;
                 case 5: {
                     REQUIRE(level >= 2, "Chebyshev runs on levels >= 2");
@@ -1849,7 +2037,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                     AdrLevel& A = ctx->al[level];
                     hipLaunchKernelGGL((k_adr_apply<T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
                                        (const T*)A.px, (const T*)A.py, (const cplx<T>*)A.c0, (const cplx<T>*)in,
-                                       (cplx<T>*)out);
+                                       (cplx<T>*)out, BatchIdx{});
                     break;
                 }
                 case 7: {

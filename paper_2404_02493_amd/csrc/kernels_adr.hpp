@@ -113,7 +113,8 @@ __device__ __forceinline__ cplx<T> applyM_at(const AdrGeom& A, const T* __restri
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_apply(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                      const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ x,
-                                                     cplx<T>* __restrict__ y) {
+                                                     cplx<T>* __restrict__ y, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, x, y);
     int j, i0;
     tile_origin(A.n, j, i0);
     if (j >= A.n) return;
@@ -150,7 +151,8 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_resid_restrict(AdrGeom A, const T* __restrict__ px,
                                                               const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                                               const cplx<T>* __restrict__ b,
-                                                              const cplx<T>* __restrict__ x, cplx<T>* __restrict__ rc) {
+                                                              const cplx<T>* __restrict__ x, cplx<T>* __restrict__ rc, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, x, rc);
     restrict_tile<T, T>(A.n, AdrRes<T>{A, px, py, c0, b, x}, rc);
 }
 
@@ -158,7 +160,8 @@ __global__ __launch_bounds__(BLOCK) void k_adr_resid_restrict(AdrGeom A, const T
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_demod(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
                                                      const cplx<T>* __restrict__ u, const cplx<T>* __restrict__ car,
-                                                     cplx<T>* __restrict__ rhat) {
+                                                     cplx<T>* __restrict__ rhat, BatchIdx bi) {
+    bshift(bi.off(), n2, g, u, car, rhat);
     int j, i0;
     tile_origin(G.n, j, i0);
     if (j >= G.n) return;
@@ -178,7 +181,8 @@ __global__ __launch_bounds__(BLOCK) void k_adr_demod(Geom G, const T* __restrict
 // u += a e^{+i theta}   (car = e^{i theta})
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_modadd(size_t N, const cplx<T>* __restrict__ a,
-                                                      const cplx<T>* __restrict__ car, cplx<T>* __restrict__ u) {
+                                                      const cplx<T>* __restrict__ car, cplx<T>* __restrict__ u, BatchIdx bi) {
+    bshift(bi.off(), a, car, u);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK)
         u[p] = u[p] + a[p] * car[p];
 }

@@ -16,6 +16,13 @@ struct VecSet {
     const cplx<T>* v[MAXM + 1];
 };
 
+template <typename T>
+__device__ __forceinline__ VecSet<T> bsh_one(size_t o, VecSet<T> s) {
+#pragma unroll
+    for (int i = 0; i <= MAXM; ++i) s.v[i] = bsh_one(o, s.v[i]);
+    return s;
+}
+
 __device__ __forceinline__ double* Hp(KrylovScal* K, int i, int j) { return K->H + 2 * (i + j * (MAXM + 1)); }
 
 // Solve min || beta e1 - H y || for the leading (cols+1) x cols block with complex
@@ -80,7 +87,8 @@ __device__ inline void ks_least_squares(KrylovScal* K, int cols) {
 
 // Partial ||x||^2 of a Krylov start vector (finalize with FIN_INIT).
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_krylov_init_norm(size_t N, const cplx<T>* __restrict__ x, double* partials) {
+__global__ __launch_bounds__(BLOCK) void k_krylov_init_norm(size_t N, const cplx<T>* __restrict__ x, double* partials, BatchIdx bi) {
+    bshift(bi.off(), x, partials);
     __shared__ double red[4];
     __shared__ double sums[1];
     double acc[1] = {0.0};
@@ -97,7 +105,8 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_residual_init(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                              const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
                                                              const cplx<T>* __restrict__ x, cplx<T>* __restrict__ r0,
-                                                             double* partials) {
+                                                             double* partials, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, x, r0, partials);
     __shared__ double red[4];
     __shared__ double sums[1];
     double acc[1] = {0.0};
@@ -124,11 +133,12 @@ __global__ __launch_bounds__(BLOCK) void k_adr_residual_init(AdrGeom A, const T*
 // sums run in the working precision A (a thread sums a few dozen products); the
 // block and grid reductions are FP64.
 template <typename T, int NV, typename A = double>
-__device__ __forceinline__ void acc_dots(A (&acc)[2 * NV + 2], const VecSet<T>& V, int jj, size_t p, cplx<T> w) {
+__device__ __forceinline__ void acc_dots(A (&acc)[2 * NV + 2], const VecSet<T>& V, int jj, size_t p, cplx<T> w,
+                                         size_t o = 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         if (i <= jj) {
-            cplx<T> v = V.v[i][p];
+            cplx<T> v = bsh_one(o, V.v[i])[p];
             acc[2 * i] += A(v.re) * A(w.re) + A(v.im) * A(w.im);
             acc[2 * i + 1] += A(v.re) * A(w.im) - A(v.im) * A(w.re);
         }
@@ -146,7 +156,11 @@ __device__ __forceinline__ void to_double(const A (&a)[K], double (&d)[K]) {
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_arnoldi_adr(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                        const cplx<T>* __restrict__ c0, VecSet<T> V, int jj,
-                                                       cplx<T>* __restrict__ w, const KrylovScal* K, double* partials) {
+                                                       cplx<T>* __restrict__ w, const KrylovScal* K, double* partials, BatchIdx bi) {
+    // V is shifted where it is read (jj is a runtime index into it)
+    const size_t bo = bi.off();
+    const cplx<T>* vjj = bsh_one(bo, V.v[jj]);
+    bshift(bo, px, py, c0, w, K, partials);
     __shared__ double red[4 * (2 * NV + 2)];
     __shared__ double sums[2 * NV + 2];
     if (K->done) return;
@@ -165,9 +179,9 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_adr(AdrGeom A, const T* __res
             if (i >= A.n) break;
             const size_t p = (size_t)i * A.n + j;
             cplx<T> v{};
-            if (i > 0 && j > 0) v = sj * applyM_at(A, px, py, c0, V.v[jj], i, j);
+            if (i > 0 && j > 0) v = sj * applyM_at(A, px, py, c0, vjj, i, j);
             w[p] = v;
-            acc_dots<T, NV>(acc, V, jj, p, v);
+            acc_dots<T, NV>(acc, V, jj, p, v, bo);
         }
     }
     block_sum<2 * NV + 2, 4>(acc, 2 * (jj + 1), red, sums);
@@ -191,7 +205,8 @@ __device__ __forceinline__ void load_coefs(const KrylovScal* K, int jj, cplx<T> 
 // Gram-Schmidt pass 1: w -= sum_i dots_i v_i, partial sums of conj(V_i) w (FIN_ORTH1).
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_orth_pass1(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
-                                                      const KrylovScal* K, double* partials) {
+                                                      const KrylovScal* K, double* partials, BatchIdx bi) {
+    bshift(bi.off(), V, w, K, partials);
     __shared__ double red[4 * (2 * NV + 2)];
     __shared__ double sums[2 * NV + 2];
     __shared__ cplx<T> c[NV];
@@ -221,7 +236,8 @@ __global__ __launch_bounds__(BLOCK) void k_orth_pass1(size_t N, VecSet<T> V, int
 // Gram-Schmidt pass 2: w -= sum_i dots2_i v_i, partial ||w||^2 (FIN_ORTH2).
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_orth_pass2(size_t N, VecSet<T> V, int jj, cplx<T>* __restrict__ w,
-                                                      const KrylovScal* K, double* partials) {
+                                                      const KrylovScal* K, double* partials, BatchIdx bi) {
+    bshift(bi.off(), V, w, K, partials);
     __shared__ double red[4];
     __shared__ double sums[1];
     if (K->done) return;
@@ -327,7 +343,8 @@ template <typename T, int J>
 __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restrict__ n2,
                                                       const cplx<T>* __restrict__ z, int use_scale, VecSet<T> V,
                                                       cplx<T>* __restrict__ vj, cplx<T>* __restrict__ w,
-                                                      const KrylovScal* K, double* partials) {
+                                                      const KrylovScal* K, double* partials, BatchIdx bi) {
+    bshift(bi.off(), n2, z, V, vj, w, K, partials);
     constexpr int E = FgShape<T>::E;
     constexpr int NA = 2 * (J + 1) + 1;
     if (K->done) return;
@@ -403,7 +420,8 @@ __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restric
 // partial sums of conj(V_i) w, i <= J, and ||w||^2 (finalize with FIN_LORTH).
 template <typename T, int J>
 __global__ __launch_bounds__(BLOCK) void k_fg_orth(size_t N, VecSet<T> V, cplx<T>* __restrict__ w,
-                                                   const KrylovScal* K, double* partials) {
+                                                   const KrylovScal* K, double* partials, BatchIdx bi) {
+    bshift(bi.off(), V, w, K, partials);
     constexpr int E = FgShape<T>::E;
     constexpr int NA = 2 * (J + 1) + 1;
     if (K->done) return;
@@ -502,7 +520,8 @@ __device__ __forceinline__ void fin_lagged(int op, int jj, const double* sums, K
 //              is the norm of w after the second round; zscale and scale of jj + 1
 template <int KV>
 __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __restrict__ partials, int nblk, int op,
-                                                            int jj, int m, KrylovScal* K, double tol) {
+                                                            int jj, int m, KrylovScal* K, double tol, BatchIdx bi) {
+    bshift(bi.off(), partials, K);
     __shared__ double red[(FBLOCK / 64) * KV];
     __shared__ double sums[KV];
     if (op != FIN_INIT && K->done) return;
@@ -563,17 +582,27 @@ __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __rest
 
 // FGMRES end of a restart cycle: K->cols = cols and y from the device Hessenberg
 // (Givens least squares, one thread).
-__global__ void k_fgmres_lsq(KrylovScal* K, int cols) {
+__global__ void k_fgmres_lsq(KrylovScal* K, int cols, BatchIdx bi) {
+    bshift(bi.off(), K);
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (cols < 0) cols = bi.aux_here();  // batched launch: one count per problem
     K->cols = cols;
     ks_least_squares(K, cols);
 }
 
 // x = x0 + sum_{i < cols} y_i s_i V_i, s_i = scale_i (zs == 0), zscale_i (zs == 1) or 1
 // (zs == 2)  (x0 == nullptr: 0; x may alias x0).
+// out[z count + i] = src[i] of the z-th problem of the launch, i < count: per-problem
+// scalars gathered into one array (out itself is not per problem, so it is not shifted).
+__global__ void k_gather(const double* __restrict__ src, int count, double* __restrict__ out, BatchIdx bi) {
+    src = bsh_one(bi.off(), src);
+    for (int i = threadIdx.x; i < count; i += blockDim.x) out[(size_t)blockIdx.z * count + i] = src[i];
+}
+
 template <typename T, int NV>
 __global__ __launch_bounds__(BLOCK) void k_krylov_combine(size_t N, VecSet<T> V, const KrylovScal* K,
-                                                          const cplx<T>* x0, cplx<T>* x, int zs = 0) {
+                                                          const cplx<T>* x0, cplx<T>* x, int zs, BatchIdx bi) {
+    bshift(bi.off(), V, K, x0, x);
     const int cols = K->cols;
     cplx<T> c[NV];
 #pragma unroll

@@ -304,7 +304,8 @@ template <typename T, int M, bool X0>
 __global__ __launch_bounds__(64) void k_sstep_gram(AdrGeom A, int S, const T* __restrict__ px,
                                                    const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                                    const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
-                                                   double* __restrict__ partials) {
+                                                   double* __restrict__ partials, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, x0, partials);
     using Mc = March<M, X0, true>;
     constexpr int NG = (M + 1) * (M + 1);
     // FP64 products: the unscaled powers M^j K_0 span many decades (|M| ~ 8/h^2)
@@ -446,7 +447,8 @@ constexpr int SOLVE_THREADS = 1024, SOLVE_BATCH = 32;
 
 template <int M>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_sstep_solve(const double* __restrict__ partials, int nblk,
-                                                               double breakdown_tol, KrylovScal* K) {
+                                                               double breakdown_tol, KrylovScal* K, BatchIdx bi) {
+    bshift(bi.off(), partials, K);
     constexpr int NG = (M + 1) * (M + 1), NW = SOLVE_THREADS / 64;
     __shared__ double sums[NG];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -503,6 +505,17 @@ struct ModArgs {
     cplx<T>* bout;            // next ADR right-hand side (EPI_MODRD)
 };
 
+template <typename T>
+__device__ __forceinline__ ModArgs<T> bsh_one(size_t o, ModArgs<T> a) {
+    a.car = bsh_one(o, a.car);
+    a.n2 = bsh_one(o, a.n2);
+    a.g = bsh_one(o, a.g);
+    a.u = bsh_one(o, a.u);
+    a.uout = bsh_one(o, a.uout);
+    a.bout = bsh_one(o, a.bout);
+    return a;
+}
+
 // Rows of the level-2 fields, prefetched with the Krylov rows.
 template <typename T, int EPI>
 struct ModExtra {
@@ -544,7 +557,8 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                                                       const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                                       const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
                                                       const KrylovScal* __restrict__ K, cplx<T>* __restrict__ xout,
-                                                      ModArgs<T> mod) {
+                                                      ModArgs<T> mod, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, x0, K, xout, mod);
     static_assert(EPI == EPI_X || X0, "the modulated epilogues follow the post-smoother");
     constexpr int XH = EPI == EPI_MODRD ? 1 : 0;
     constexpr int EP = EPI == EPI_X ? -1 : EPI == EPI_MOD ? 0 : 1;
@@ -644,7 +658,8 @@ __global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const
                                                          const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                                          const cplx<T>* __restrict__ b,
                                                          const KrylovScal* __restrict__ K, cplx<T>* __restrict__ xout,
-                                                         cplx<T>* __restrict__ rc) {
+                                                         cplx<T>* __restrict__ rc, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, K, xout, rc);
     using Mc = March<M, false, true, 1, -1>;
     constexpr int W = Mc::W;
     const int lane = threadIdx.x;
@@ -814,7 +829,8 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_gram_tile(AdrGeom A, const T* _
                                                            const cplx<T>* __restrict__ c0,
                                                            const cplx<T>* __restrict__ b,
                                                            const cplx<T>* __restrict__ x0,
-                                                           double* __restrict__ partials) {
+                                                           double* __restrict__ partials, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, x0, partials);
     using Tg = Tile<M, X0, true, TT>;
     constexpr int NG = (M + 1) * (M + 1);
     __shared__ cplx<T> buf[2 * Tg::NR];
@@ -842,7 +858,8 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile(AdrGeom A, const T
                                                               const cplx<T>* __restrict__ b,
                                                               const cplx<T>* __restrict__ x0,
                                                               const KrylovScal* __restrict__ K,
-                                                              cplx<T>* __restrict__ xout) {
+                                                              cplx<T>* __restrict__ xout, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, x0, K, xout);
     using Tg = Tile<M, X0, false, TT>;
     __shared__ cplx<T> buf[2 * Tg::NR];
     const int n = A.n;
@@ -878,7 +895,8 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_rr(AdrGeom A, cons
                                                                  const cplx<T>* __restrict__ c0,
                                                                  const cplx<T>* __restrict__ b,
                                                                  const KrylovScal* __restrict__ K,
-                                                                 cplx<T>* __restrict__ xout, cplx<T>* __restrict__ rc) {
+                                                                 cplx<T>* __restrict__ xout, cplx<T>* __restrict__ rc, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, K, xout, rc);
     using Tg = Tile<M, false, true, TT, 1>;
     constexpr int RW = Tg::RW, H = Tg::H, TC = TT / 2;
     static_assert(TT % 2 == 0 && TC * TC <= BLOCK, "one coarse node per thread");
@@ -943,7 +961,8 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, cons
                                                                  const cplx<T>* __restrict__ b,
                                                                  const cplx<T>* __restrict__ x0,
                                                                  const KrylovScal* __restrict__ K,
-                                                                 cplx<T>* __restrict__ xf) {
+                                                                 cplx<T>* __restrict__ xf, BatchIdx bi) {
+    bshift(bi.off(), px, py, c0, b, x0, K, xf);
     using Tg = Tile<M, X0, false, TT, 1>;
     constexpr int RW = Tg::RW, H = Tg::H;
     __shared__ cplx<T> buf[2 * Tg::NR];

@@ -145,6 +145,17 @@ struct BlockLevel {
     int m;
 };
 
+template <typename T>
+__device__ __forceinline__ BlockLevel<T> bsh_one(size_t o, BlockLevel<T> t) {
+    t.px = bsh_one(o, t.px);
+    t.py = bsh_one(o, t.py);
+    t.c0 = bsh_one(o, t.c0);
+    t.b = bsh_one(o, t.b);
+    t.x = bsh_one(o, t.x);
+    t.V = bsh_one(o, t.V);
+    return t;
+}
+
 // GMRES(m) for the ADR operator of one small level (n*n <= NMAX) in one workgroup:
 // x = x0 + argmin over K_m(M, r0) of ||b - M x||, x0 = 0 when x0_zero, m <= NQ.
 // Arnoldi with two-pass classical Gram-Schmidt.  The current Arnoldi vector lives
@@ -152,7 +163,8 @@ struct BlockLevel {
 // accumulator per basis vector, so the passes are not serialised over the basis.
 // Stops early when h(j+1,j) <= tol beta.
 template <typename T, int TB, int NQ, int NMAX>
-__global__ __launch_bounds__(TB) void k_gmres_block(BlockLevel<T> L, int x0_zero, double tol) {
+__global__ __launch_bounds__(TB) void k_gmres_block(BlockLevel<T> L, int x0_zero, double tol, BatchIdx bi) {
+    bshift(bi.off(), L);
     __shared__ TailLds S;
     __shared__ cplx<T> wl[NMAX];
     using C = cplx<T>;

@@ -111,7 +111,8 @@ __device__ __forceinline__ cplx<T> resid_at(const Geom& G, const T* __restrict__
 // y = A x  (or A^* x)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_apply_A(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ x,
-                                                   cplx<T>* __restrict__ y, int conj_k) {
+                                                   cplx<T>* __restrict__ y, int conj_k, BatchIdx bi) {
+    bshift(bi.off(), n2, x, y);
     int j, i0;
     tile_origin(G.n, j, i0);
     if (j >= G.n) return;
@@ -127,7 +128,8 @@ __global__ __launch_bounds__(BLOCK) void k_apply_A(Geom G, const T* __restrict__
 // r = g - A u   (u == nullptr means u = 0)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_residual(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
-                                                    const cplx<T>* __restrict__ u, cplx<T>* __restrict__ r) {
+                                                    const cplx<T>* __restrict__ u, cplx<T>* __restrict__ r, BatchIdx bi) {
+    bshift(bi.off(), n2, g, u, r);
     int j, i0;
     tile_origin(G.n, j, i0);
     if (j >= G.n) return;
@@ -144,7 +146,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom G, const T* __restrict_
 // (finalized by k_finalize_sums).
 __global__ __launch_bounds__(BLOCK) void k_residual_norms(Geom G, const double* __restrict__ n2,
                                                           const c128* __restrict__ g, const c128* __restrict__ u,
-                                                          c128* __restrict__ r, double* partials) {
+                                                          c128* __restrict__ r, double* partials, BatchIdx bi) {
+    bshift(bi.off(), n2, g, u, r, partials);
     __shared__ double red[4 * 2];
     __shared__ double sums[2];
     double acc[2] = {0.0, 0.0};
@@ -174,7 +177,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual_norms(Geom G, const double* 
 // out[v] = sum over blocks of partials (one block of FBLOCK threads).
 template <int K>
 __global__ __launch_bounds__(FBLOCK) void k_finalize_sums(const double* __restrict__ partials, int nblk, int kcount,
-                                                          double* out) {
+                                                          double* out, BatchIdx bi) {
+    bshift(bi.off(), partials, out);
     __shared__ double red[(FBLOCK / 64) * K];
     __shared__ double sums[K];
     final_sum<K>(partials, nblk, kcount, red, sums);
@@ -241,7 +245,8 @@ struct HelmRes {
 template <typename Tf, typename Tc>
 __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Geom G, const Tf* __restrict__ n2,
                                                           const cplx<Tf>* __restrict__ g,
-                                                          const cplx<Tf>* __restrict__ u, cplx<Tc>* __restrict__ rc) {
+                                                          const cplx<Tf>* __restrict__ u, cplx<Tc>* __restrict__ rc, BatchIdx bi) {
+    bshift(bi.off(), n2, g, u, rc);
     restrict_tile<Tf, Tc>(G.n, HelmRes<Tf>{G, n2, g, u}, rc);
 }
 
@@ -267,7 +272,8 @@ __device__ __forceinline__ cplx<Tf> prolong_at(const cplx<Tc>* __restrict__ ec, 
 }
 
 template <typename Tc, typename Tf>
-__global__ __launch_bounds__(BLOCK) void k_prolong_add(int n, const cplx<Tc>* __restrict__ ec, cplx<Tf>* __restrict__ u) {
+__global__ __launch_bounds__(BLOCK) void k_prolong_add(int n, const cplx<Tc>* __restrict__ ec, cplx<Tf>* __restrict__ u, BatchIdx bi) {
+    bshift(bi.off(), ec, u);
     int j, i0;
     tile_origin(n, j, i0);
     if (j >= n) return;
@@ -287,7 +293,8 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(int n, const cplx<Tc>* __
 // unknowns read index 0 (the zero ring), so column 0 receives 0.
 template <typename Tc, typename Tf>
 __global__ __launch_bounds__(BLOCK) void k_prolong_pairs(int n, const cplx<Tc>* __restrict__ ec,
-                                                         cplx<Tf>* __restrict__ u, int assign) {
+                                                         cplx<Tf>* __restrict__ u, int assign, BatchIdx bi) {
+    bshift(bi.off(), ec, u);
     const int nc = n / 2;
     const size_t NP = (size_t)n * nc;
     auto e = [&](int a, int b) -> cplx<Tc> {
@@ -333,7 +340,10 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_pairs(int n, const cplx<Tc>* 
 // uout = uin + w (g - A uin) / (4/h^2 - kappa)   (damped Jacobi, out of place)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_jacobi(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
-                                                  const cplx<T>* __restrict__ uin, cplx<T>* __restrict__ uout, T w) {
+                                                  const cplx<T>* __restrict__ uin, cplx<T>* __restrict__ uout,
+                                                  const double* __restrict__ wp, BatchIdx bi) {
+    bshift(bi.off(), n2, g, uin, uout, wp);
+    const T w = T(wp[0]);
     int j, i0;
     tile_origin(G.n, j, i0);
     if (j >= G.n) return;
@@ -353,10 +363,14 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(Geom G, const T* __restrict__ 
     }
 }
 
-// Chebyshev start: r = A^* t, d = r / theta    (t = g - A u)
+// Chebyshev start: r = A^* t, d = r / theta    (t = g - A u); cc[0] = 1 / theta of the
+// level's coefficient table (a device array, one per problem).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cheb_start(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ t,
-                                                      cplx<T>* __restrict__ r, cplx<T>* __restrict__ d, T inv_theta) {
+                                                      cplx<T>* __restrict__ r, cplx<T>* __restrict__ d,
+                                                      const double* __restrict__ cc, BatchIdx bi) {
+    bshift(bi.off(), n2, t, r, d, cc);
+    const T inv_theta = T(cc[0]);
     int j, i0;
     tile_origin(G.n, j, i0);
     if (j >= G.n) return;
@@ -372,12 +386,15 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start(Geom G, const T* __restric
 }
 
 // Chebyshev start from a nonzero u: t = g - A u on the 64 x 16 tile and a halo of one
-// (in LDS, t is not stored), then r = A^* t and d = r / theta at the tile's nodes.
+// (in LDS, t is not stored), then r = A^* t and d = r / theta at the tile's nodes (cc[0] = 1/theta).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __restrict__ n2,
                                                           const cplx<T>* __restrict__ g,
                                                           const cplx<T>* __restrict__ u, cplx<T>* __restrict__ r,
-                                                          cplx<T>* __restrict__ d, T inv_theta) {
+                                                          cplx<T>* __restrict__ d, const double* __restrict__ cc,
+                                                          BatchIdx bi) {
+    bshift(bi.off(), n2, g, u, r, d, cc);
+    const T inv_theta = T(cc[0]);
     constexpr int UW = TX + 4, UH = TY + 4, HW = TX + 2, HH = TY + 2;
     __shared__ cplx<T> su[UH * UW];
     __shared__ cplx<T> sg[HH * HW];
@@ -431,7 +448,8 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __res
 
 // Fused Chebyshev step on a 64 x 16 tile: t = A d_in on the tile and a halo of one
 // (in LDS), then at the tile's nodes  u += d_in;  r -= A^* t;  d_out = c1 d_in + c2 r.
-// d_in and d_out are different arrays (neighbouring tiles still read d_in).
+// d_in and d_out are different arrays (neighbouring tiles still read d_in).  c1 = cc[1],
+// c2 = cc[2]: the row of this step in the level's coefficient table.
 // mode bit 0 (CHEB_UZERO): u is zero on entry and is not read (its ring is written 0);
 // bit 1 (CHEB_LAST): the iteration's final update u += d_out is done here as well, and
 // r and d_out are not written (nothing reads them afterwards).
@@ -439,8 +457,10 @@ enum { CHEB_UZERO = 1, CHEB_LAST = 2 };
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restrict__ n2,
                                                       const cplx<T>* __restrict__ d_in, cplx<T>* __restrict__ d_out,
-                                                      cplx<T>* __restrict__ r, cplx<T>* __restrict__ u, T c1, T c2,
-                                                      int mode) {
+                                                      cplx<T>* __restrict__ r, cplx<T>* __restrict__ u,
+                                                      const double* __restrict__ cc, int mode, BatchIdx bi) {
+    bshift(bi.off(), n2, d_in, d_out, r, u, cc);
+    const T c1 = T(cc[1]), c2 = T(cc[2]);
     constexpr int DW = TX + 4, DH = TY + 4, HW = TX + 2, HH = TY + 2;
     __shared__ cplx<T> sd[DH * DW];
     __shared__ T sn[HH * HW];
@@ -535,8 +555,11 @@ __device__ __forceinline__ cplx<T> jac_wdiag(const Geom& G, T n2v, int i, int j,
 // rr_blocks(G.n) blocks.
 template <typename Tf, typename Tc>
 __global__ __launch_bounds__(BLOCK) void k_jac0_restrict(Geom G, const Tf* __restrict__ n2,
-                                                         const cplx<Tf>* __restrict__ g, Tf w,
-                                                         cplx<Tc>* __restrict__ rc) {
+                                                         const cplx<Tf>* __restrict__ g,
+                                                         const double* __restrict__ wp,
+                                                         cplx<Tc>* __restrict__ rc, BatchIdx bi) {
+    bshift(bi.off(), n2, g, wp, rc);
+    const Tf w = Tf(wp[0]);
     constexpr int FW = 2 * RCX + 1, FH = 2 * RCY + 1, UW = FW + 2, UH = FH + 2;
     __shared__ cplx<Tf> us[UH * UW];
     __shared__ cplx<Tf> r[FH * FW];
@@ -612,8 +635,11 @@ __global__ __launch_bounds__(BLOCK) void k_jac0_restrict(Geom G, const Tf* __res
 template <typename Tc, typename Tf>
 __global__ __launch_bounds__(BLOCK) void k_jac0_prolong_jacobi(Geom G, const Tf* __restrict__ n2,
                                                                const cplx<Tf>* __restrict__ g,
-                                                               const cplx<Tc>* __restrict__ ec, Tf w,
-                                                               cplx<Tf>* __restrict__ out) {
+                                                               const cplx<Tc>* __restrict__ ec,
+                                                               const double* __restrict__ wp,
+                                                               cplx<Tf>* __restrict__ out, BatchIdx bi) {
+    bshift(bi.off(), n2, g, ec, wp, out);
+    const Tf w = Tf(wp[0]);
     constexpr int HW = TX + 2, HH = TY + 2;
     __shared__ cplx<Tf> us[HH * HW];
     const int n = G.n, nc = n / 2;
@@ -723,13 +749,15 @@ __global__ __launch_bounds__(BLOCK) void k_jac0_prolong_jacobi(Geom G, const Tf*
 
 // ------------------------------------------------------------------ flat helpers
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_axpy(size_t N, T a, const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y) {
+__global__ __launch_bounds__(BLOCK) void k_axpy(size_t N, T a, const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, BatchIdx bi) {
+    bshift(bi.off(), x, y);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) y[p] = y[p] + a * x[p];
 }
 
 template <typename To, typename Ti>
 __global__ __launch_bounds__(BLOCK) void k_cast_scale(size_t N, const cplx<Ti>* __restrict__ x, cplx<To>* __restrict__ y,
-                                                      double s) {
+                                                      double s, BatchIdx bi) {
+    bshift(bi.off(), x, y);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         cplx<Ti> v = x[p];
         y[p] = mk<To>(To(s * double(v.re)), To(s * double(v.im)));
@@ -739,7 +767,8 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scale(size_t N, const cplx<Ti>* 
 // y = (*s) cast(x) with the scale read from device memory
 template <typename To, typename Ti>
 __global__ __launch_bounds__(BLOCK) void k_cast_scale_dev(size_t N, const cplx<Ti>* __restrict__ x,
-                                                          cplx<To>* __restrict__ y, const double* __restrict__ s) {
+                                                          cplx<To>* __restrict__ y, const double* __restrict__ s, BatchIdx bi) {
+    bshift(bi.off(), x, y, s);
     const double sc = *s;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         cplx<Ti> v = x[p];
@@ -750,7 +779,8 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scale_dev(size_t N, const cplx<T
 // y += s * cast(x)
 template <typename To, typename Ti>
 __global__ __launch_bounds__(BLOCK) void k_add_cast(size_t N, const cplx<Ti>* __restrict__ x, cplx<To>* __restrict__ y,
-                                                    double s) {
+                                                    double s, BatchIdx bi) {
+    bshift(bi.off(), x, y);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         cplx<Ti> v = x[p];
         cplx<To> w = y[p];
@@ -758,13 +788,39 @@ __global__ __launch_bounds__(BLOCK) void k_add_cast(size_t N, const cplx<Ti>* __
     }
 }
 
+// y += (*s) cast(x) with the scale read from device memory
+template <typename To, typename Ti>
+__global__ __launch_bounds__(BLOCK) void k_add_cast_dev(size_t N, const cplx<Ti>* __restrict__ x, cplx<To>* __restrict__ y,
+                                                        const double* __restrict__ s, BatchIdx bi) {
+    bshift(bi.off(), x, y, s);
+    const double sc = *s;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        cplx<Ti> v = x[p];
+        cplx<To> w = y[p];
+        y[p] = mk<To>(To(double(w.re) + sc * double(v.re)), To(double(w.im) + sc * double(v.im)));
+    }
+}
+
+// From the squared norm sums[0] of a residual: sums[2] = 1 / ||r||, sums[3] = ||r||, with
+// correctly rounded square root and division (the values the host computes).
+__global__ void k_norm_scales(double* sums, BatchIdx bi) {
+    bshift(bi.off(), sums);
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double rn = __dsqrt_rn(sums[0]);
+        sums[2] = __ddiv_rn(1.0, rn);
+        sums[3] = rn;
+    }
+}
+
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_copy(size_t N, const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y) {
+__global__ __launch_bounds__(BLOCK) void k_copy(size_t N, const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, BatchIdx bi) {
+    bshift(bi.off(), x, y);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) y[p] = x[p];
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_zero(size_t N, cplx<T>* __restrict__ y) {
+__global__ __launch_bounds__(BLOCK) void k_zero(size_t N, cplx<T>* __restrict__ y, BatchIdx bi) {
+    bshift(bi.off(), y);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) y[p] = cplx<T>{};
 }
 

@@ -26,8 +26,7 @@ struct TailWaveLevel {
     void* r;
     void* d;
     void* t;
-    double lam;        // spectral bound of A^* A
-    double alpha;      // Chebyshev interval parameter
+    const double* la;  // device: la[0] = spectral bound of A^* A, la[1] = Chebyshev alpha
 };
 
 struct TailWaveArgs {
@@ -40,17 +39,18 @@ struct TailWaveArgs {
 
 // r = A^* (g - A u) (u == nullptr: A^* g), d = r / theta; t holds g - A u.
 template <typename P>
-__device__ void wt_cheb(const TailWaveLevel& W, bool u_zero, int m) {
+__device__ void wt_cheb(const TailWaveLevel& W, bool u_zero, int m, size_t o) {
     const Geom& G = W.G;
     const int n = G.n;
     const int N = n * n;
-    const P* n2 = (const P*)W.n2;
-    cplx<P>* g = (cplx<P>*)W.g;
-    cplx<P>* u = (cplx<P>*)W.u;
-    cplx<P>* r = (cplx<P>*)W.r;
-    cplx<P>* d = (cplx<P>*)W.d;
-    cplx<P>* t = (cplx<P>*)W.t;
-    const double lam = W.lam, a = lam / W.alpha;
+    const P* n2 = (const P*)bsh_one(o, W.n2);
+    cplx<P>* g = (cplx<P>*)bsh_one(o, W.g);
+    cplx<P>* u = (cplx<P>*)bsh_one(o, W.u);
+    cplx<P>* r = (cplx<P>*)bsh_one(o, W.r);
+    cplx<P>* d = (cplx<P>*)bsh_one(o, W.d);
+    cplx<P>* t = (cplx<P>*)bsh_one(o, W.t);
+    const double* la = bsh_one(o, W.la);
+    const double lam = la[0], a = lam / la[1];
     const double theta = 0.5 * (lam + a), dc = 0.5 * (lam - a);
     // t = g - A u (or g)
     for (int p = threadIdx.x; p < N; p += WT_THREADS) {
@@ -103,13 +103,13 @@ __device__ void wt_cheb(const TailWaveLevel& W, bool u_zero, int m) {
 
 // gc = R (g - A u) from level l (precision Pf) to level l + 1 (precision Pc); u may be zero.
 template <typename Pf, typename Pc>
-__device__ void wt_restrict(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero) {
+__device__ void wt_restrict(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero, size_t o) {
     const Geom& G = F.G;
     const int n = G.n, nc = n / 2;
-    const Pf* n2 = (const Pf*)F.n2;
-    const cplx<Pf>* g = (const cplx<Pf>*)F.g;
-    const cplx<Pf>* u = u_zero ? nullptr : (const cplx<Pf>*)F.u;
-    cplx<Pc>* gc = (cplx<Pc>*)Cl.g;
+    const Pf* n2 = (const Pf*)bsh_one(o, F.n2);
+    const cplx<Pf>* g = (const cplx<Pf>*)bsh_one(o, F.g);
+    const cplx<Pf>* u = u_zero ? nullptr : (const cplx<Pf>*)bsh_one(o, F.u);
+    cplx<Pc>* gc = (cplx<Pc>*)bsh_one(o, Cl.g);
     for (int q = threadIdx.x; q < nc * nc; q += WT_THREADS) {
         const int I = q / nc, J = q - I * nc;
         cplx<Pf> v{};
@@ -128,10 +128,10 @@ __device__ void wt_restrict(const TailWaveLevel& F, const TailWaveLevel& Cl, boo
 
 // u (level l, precision Pf) += P e (level l + 1, precision Pc); u_zero: u = P e.
 template <typename Pc, typename Pf>
-__device__ void wt_prolong(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero) {
+__device__ void wt_prolong(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero, size_t o) {
     const int n = F.G.n, nc = n / 2;
-    cplx<Pf>* u = (cplx<Pf>*)F.u;
-    const cplx<Pc>* ec = (const cplx<Pc>*)Cl.u;
+    cplx<Pf>* u = (cplx<Pf>*)bsh_one(o, F.u);
+    const cplx<Pc>* ec = (const cplx<Pc>*)bsh_one(o, Cl.u);
     for (int p = threadIdx.x; p < n * n; p += WT_THREADS) {
         const int i = p / n, j = p - i * n;
         cplx<Pf> v{};
@@ -142,31 +142,32 @@ __device__ void wt_prolong(const TailWaveLevel& F, const TailWaveLevel& Cl, bool
 }
 
 template <typename T>
-__device__ void wt_transfer_down(const TailWaveArgs& a, int l, bool u_zero) {
-    if (a.lv[l + 1].f64) wt_restrict<T, double>(a.lv[l], a.lv[l + 1], u_zero);
-    else wt_restrict<T, T>(a.lv[l], a.lv[l + 1], u_zero);
+__device__ void wt_transfer_down(const TailWaveArgs& a, int l, bool u_zero, size_t o) {
+    if (a.lv[l + 1].f64) wt_restrict<T, double>(a.lv[l], a.lv[l + 1], u_zero, o);
+    else wt_restrict<T, T>(a.lv[l], a.lv[l + 1], u_zero, o);
 }
 template <typename T>
-__device__ void wt_transfer_up(const TailWaveArgs& a, int l, bool u_zero) {
-    if (a.lv[l + 1].f64) wt_prolong<double, T>(a.lv[l], a.lv[l + 1], u_zero);
-    else wt_prolong<T, T>(a.lv[l], a.lv[l + 1], u_zero);
+__device__ void wt_transfer_up(const TailWaveArgs& a, int l, bool u_zero, size_t o) {
+    if (a.lv[l + 1].f64) wt_prolong<double, T>(a.lv[l], a.lv[l + 1], u_zero, o);
+    else wt_prolong<T, T>(a.lv[l], a.lv[l + 1], u_zero, o);
 }
 
 // The cycle on levels l0..L from a zero iterate, as the per-level host recursion runs
 // it (no ADR correction here: l0 >= 3).  Levels below L are in precision T (or FP64
 // when the whole cycle is FP64); level L is FP64.
 template <typename T>
-__global__ __launch_bounds__(WT_THREADS) void k_wave_tail(TailWaveArgs a) {
+__global__ __launch_bounds__(WT_THREADS) void k_wave_tail(TailWaveArgs a, BatchIdx bi) {
+    const size_t o = bi.off();  // the level arrays of this problem (shifted where they are read)
     for (int l = a.l0; l < a.L; ++l) {  // descend: pre-smoothing and restriction
         const bool smooth = l != 3;
-        if (smooth) wt_cheb<T>(a.lv[l], true, a.cheb_pre);
-        wt_transfer_down<T>(a, l, !smooth);
+        if (smooth) wt_cheb<T>(a.lv[l], true, a.cheb_pre, o);
+        wt_transfer_down<T>(a, l, !smooth, o);
     }
-    wt_cheb<double>(a.lv[a.L], true, a.cheb_coarse);
+    wt_cheb<double>(a.lv[a.L], true, a.cheb_coarse, o);
     for (int l = a.L - 1; l >= a.l0; --l) {  // ascend: prolongation and post-smoothing
         const bool pre = l != 3;
-        wt_transfer_up<T>(a, l, !pre);
-        if (l != 3 || a.level3_literal) wt_cheb<T>(a.lv[l], false, a.cheb_post);
+        wt_transfer_up<T>(a, l, !pre, o);
+        if (l != 3 || a.level3_literal) wt_cheb<T>(a.lv[l], false, a.cheb_post, o);
     }
 }
 

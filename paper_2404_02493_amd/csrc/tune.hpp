@@ -153,9 +153,9 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
                     constexpr int J = decltype(jc)::value;
                     hipLaunchKernelGGL((k_fg_arnoldi<T, J>), dim3(cand), dim3(BLOCK), 0, st, G, (const T*)n2,
                                        (const cplx<T>*)Zp[0], 0, Vs, (cplx<T>*)Vp[J], (cplx<T>*)Vp[J + 1],
-                                       (const KrylovScal*)c->Kin, c->partials);
+                                       (const KrylovScal*)c->Kin, c->partials, BatchIdx{});
                     hipLaunchKernelGGL((k_fg_orth<T, J>), dim3(cand), dim3(BLOCK), 0, st, NF, Vs,
-                                       (cplx<T>*)Vp[J + 1], (const KrylovScal*)c->Kin, c->partials);
+                                       (cplx<T>*)Vp[J + 1], (const KrylovScal*)c->Kin, c->partials, BatchIdx{});
                 });
             });
             HIPCHK(hipGetLastError());

@@ -39,7 +39,10 @@ def test_batch_equals_single_solves(small_batch, prec, mode):
     gs = [torch.as_tensor(c.g).to("cuda:0") for c in small_batch]
     us, its, rr, st = B.solve(gs, tol=1e-6, maxit=400, mode=mode)
     torch.cuda.synchronize()
-    print("iters", its.tolist(), "relres", rr.tolist(), flush=True)
+    cls = B.classes()
+    print("iters", its.tolist(), "relres", rr.tolist(), "classes", cls.tolist(), flush=True)
+    # FP32 refinement: the problems of each size share a lockstep class; FP64 runs alone
+    assert np.all(cls >= 0) if mode == 1 else np.all(cls == -1)
     assert np.all(st == 0) and np.all(rr < 1e-6)
     for p, c in enumerate(small_batch):
         H = Helmholtz(c.velocity, c.k, levels=c.levels, precision=prec, damping_cells=c.damping_cells)
@@ -104,3 +107,44 @@ def test_batch_sample_of_the_mixed_size_batch():
         H.close()
     B.close()
     del rng
+
+
+def test_lockstep_class_matches_single_solves_and_oracle():
+    """Four problems of one size form a lockstep class (one launch per kernel for all of
+    them): each result equals its single solve bit for bit, also with one lane, and one
+    of them is checked against the FP64 oracle's solution."""
+    from oracle.cycle import Problem
+    from oracle.solve import fgmres
+    from paper_2404_02493_amd import Helmholtz, HelmholtzBatch
+
+    cases = [hi.make_problem(128, 80.0, 4, seed=700 + p, medium="grf", nsrc=(1, 3), phase="fmm", name=f"l{p}")
+             for p in range(4)]
+    assert len({c.damping_cells for c in cases}) == 1
+    gs = [torch.as_tensor(c.g).to("cuda:0") for c in cases]
+    results = []
+    for lanes in (2, 1):
+        B = HelmholtzBatch(_problems(cases), precision="c64", lanes=lanes)
+        us, its, rr, st = B.solve(gs, tol=1e-6, maxit=600, mode=1)
+        torch.cuda.synchronize()
+        assert np.all(st == 0) and np.all(rr < 1e-6), (st, rr)
+        cls = B.classes()
+        assert np.all(cls == cls[0]) and cls[0] >= 0, cls  # one lockstep class
+        results.append((us, its, rr))
+        B.close()
+    us, its, rr = results[0]
+    print("lockstep iterations", its.tolist(), flush=True)
+    assert np.array_equal(its, results[1][1])
+    for p, c in enumerate(cases):
+        assert torch.equal(us[p], results[1][0][p])
+        H = Helmholtz(c.velocity, c.k, levels=c.levels, precision="c64", damping_cells=c.damping_cells)
+        H.set_phase(c.phi)
+        u, it, r, _ = H.solve(gs[p], tol=1e-6, maxit=600, mode=1)
+        H.close()
+        assert it == its[p] and r == rr[p], (p, it, its[p], r, rr[p])
+        assert torch.equal(u, us[p]), p
+    c = cases[1]
+    P = Problem(c.velocity, c.k, c.levels, damping_cells=c.damping_cells, phi=c.phi)
+    x_or, _, _, ok = fgmres(P, torch.as_tensor(c.g), tol=1e-9, maxit=400)
+    err = (torch.linalg.norm(us[1].cpu() - x_or) / torch.linalg.norm(x_or)).item()
+    print("lockstep problem 1 error against the oracle", err, flush=True)
+    assert ok and err < 1e-4
