@@ -22,6 +22,8 @@ adr       ADR coefficients, upwind ADR operator, GMRES(m), ADR V-cycle, ADR corr
 cycle     the Wave-ADR cycle (Algorithm 1) and the problem container
 solve     FGMRES(20) right-preconditioned by one cycle
 grad      loss after K unrolled cycles and its gradient (autograd and finite differences)
+eikonal   factored eikonal travel time (plain C, fast sweeping) and the product-rule
+          phase derivatives of the ADR coefficients
 
 Dense assemblies of A, R and M used by the pins live in the tests themselves, so
 that they stay independent of this package.
