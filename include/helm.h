@@ -120,6 +120,34 @@ helm_status helm_set_phase(helm_ctx ctx, const void* phi, int32_t phi_is_f64, vo
  * helm_set_phase returns to one phase.  The adjoint supports one phase only. */
 helm_status helm_set_rays(helm_ctx ctx, int32_t count, void* stream);
 
+/* Travel-time phase of point sources computed on the device and installed as the
+ * phase of the ADR correction (Section 3.2.1, the factored eikonal equation).
+ * tau = tau0 tau1 with tau0 = |x - x0| (eq. eikonal_cons) and tau1 the solution
+ * of |tau0 grad tau1 + tau1 grad tau0|^2 = s^2 (eq. eikeq), s = sqrt(n^2) from the
+ * context's velocity, in the first-order upwind (Godunov) discretisation on the
+ * fine nodes with grad tau0 exact; nodes within sqrt(2) h of the source are fixed
+ * at tau1 = (s(node) + s(node nearest x0)) / 2.  Solved by fast sweeping: rounds of
+ * four Gauss-Seidel passes ((i up, j up), (i up, j down), (i down, j up),
+ * (i down, j down)), until the largest single decrease of tau1 in a round is
+ * <= tol (tol < 0: exactly max_rounds rounds).  The result equals, bit for bit,
+ * the sequential passes computed in IEEE double precision without contraction.
+ * src_xy: host, nsrc (x, y) pairs in [0, (n-1) h]^2, 1 <= nsrc <= 64; several
+ * sources give the first arrival, the smallest of their travel times.
+ * The phase is then installed as by helm_set_phase, except that with one source the
+ * ADR coefficients take the phase derivatives from the product rule of Section 3.2.1
+ * (grad tau = tau0 grad tau1 + tau1 grad tau0, Lap tau = tau1 Lap tau0 +
+ * 2 grad tau0 . grad tau1 + tau0 Lap tau1, the finite-difference rule of the phase
+ * applied to tau1; at level nodes closer than one level spacing to the source, to
+ * tau itself); that phase has no adjoint (helm_cycle_backward returns HELM_ESTATE).
+ * tau1_out, phi_out (device, n x n doubles, may be NULL): tau1 of the last source
+ * and tau.  rounds, change (host, may be NULL): the most rounds run for a source and
+ * the largest last-round decrease.  Returns HELM_ENOCONV, leaving the phase
+ * unchanged, if a node is still unreached after max_rounds (1..100000).
+ * Allocates and frees its own work arrays (about 3 n^2 doubles) and synchronises
+ * the stream once per round. */
+helm_status helm_eikonal(helm_ctx ctx, const double* src_xy, int32_t nsrc, int32_t max_rounds, double tol,
+                         void* tau1_out, void* phi_out, int32_t* rounds, double* change, void* stream);
+
 /* Per-level smoother weights (host, `levels` doubles): w[0] = damped-Jacobi weight
  * of level 1 (Section 3.1.1), w[l-1] = Chebyshev interval parameter alpha_l of
  * level l >= 2 (eq. cheb; interval [lambda_l/alpha_l, lambda_l]).  alpha_l >= 1. */

@@ -117,6 +117,27 @@ class Problem:
         arg = (self.sigma * self.k) * inject(phi, 2)
         return adr, torch.complex(torch.cos(arg), torch.sin(arg)), torch.complex(torch.cos(arg), -torch.sin(arg))
 
+    def set_phase_factored(self, tau1, src):
+        """The travel time tau = tau0 tau1 of one point source (Section 3.2.1) as the
+        phase: ADR coefficients from the product-rule derivatives of
+        ``eikonal.factored_derivatives`` on each ADR level (tau1 injected), and the
+        carrier of tau on level 2."""
+        from .eikonal import factored_adr_coefficients
+        t1 = tau1 if isinstance(tau1, torch.Tensor) else torch.as_tensor(np.asarray(tau1))
+        t1 = t1.to(F64)
+        adr = {}
+        for l in range(2, self.LA + 1):
+            adr[l] = factored_adr_coefficients(inject(t1, l), src, self.n2[l], self.rho[l], self.k, self.strength,
+                                               self.sigma, self.h[l], self.shift + self.cycle_shift)
+        t2 = inject(t1, 2)
+        x = torch.arange(t2.shape[0], dtype=F64) * self.h[2]
+        Y, X = torch.meshgrid(x, x, indexing="ij")
+        phi2 = torch.sqrt((X - src[0]) ** 2 + (Y - src[1]) ** 2) * t2
+        arg = (self.sigma * self.k) * phi2
+        self.phase_sets = [(adr, torch.complex(torch.cos(arg), torch.sin(arg)),
+                            torch.complex(torch.cos(arg), -torch.sin(arg)))]
+        self.use_phase(0)
+
     def use_phase(self, m: int):
         """Makes phase set m the one the ADR correction uses (ADR coefficients and carrier)."""
         self.adr, self.carrier, self.carrier_conj = self.phase_sets[m]

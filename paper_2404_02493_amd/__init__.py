@@ -94,6 +94,26 @@ class Helmholtz:
         self._phi = t
         check(lib().helm_set_phase(self._ctx, _ptr(t), int(is64), _stream_ptr(stream)))
 
+    def eikonal(self, sources, max_rounds: int = 1000, tol: float = 1e-12, tau1_out=None, phi_out=None,
+                stream=None):
+        """Travel-time phase of the point sources, computed on the device (factored
+        eikonal equation, fast sweeping) and installed as the ADR phase; one source
+        uses product-rule phase derivatives.  tau1_out / phi_out: optional float64
+        device tensors (n, n).  Returns (rounds, last-round largest decrease)."""
+        torch = _torch()
+        src = np.ascontiguousarray(np.atleast_2d(np.asarray(sources, dtype=np.float64)))
+        for t in (tau1_out, phi_out):
+            if t is not None and (t.dtype != torch.float64 or tuple(t.shape) != (self.n, self.n)
+                                  or not t.is_contiguous() or t.device != self.device):
+                raise ValueError("tau1_out / phi_out must be contiguous float64 (n, n) tensors on the context's device")
+        rounds = ctypes.c_int32(0)
+        change = ctypes.c_double(0.0)
+        check(lib().helm_eikonal(self._ctx, src.ctypes.data, int(src.shape[0]), int(max_rounds), float(tol),
+                                 _ptr(tau1_out) if tau1_out is not None else None,
+                                 _ptr(phi_out) if phi_out is not None else None,
+                                 ctypes.byref(rounds), ctypes.byref(change), _stream_ptr(stream)))
+        return int(rounds.value), float(change.value)
+
     def set_rays(self, count: int = 8, stream=None):
         """Wave-Ray phases: the ADR corrections cycle through count plane waves."""
         check(lib().helm_set_rays(self._ctx, int(count), _stream_ptr(stream)))

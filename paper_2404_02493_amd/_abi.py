@@ -14,7 +14,7 @@ STATUS = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP", 4: "
           5: "HELM_EBREAKDOWN", 6: "HELM_ESTATE"}
 
 # every symbol declared in include/helm.h
-EXPORTS = ["helm_desc_default", "helm_setup", "helm_set_phase", "helm_set_rays", "helm_set_weights", "helm_get_weights",
+EXPORTS = ["helm_desc_default", "helm_setup", "helm_set_phase", "helm_set_rays", "helm_eikonal", "helm_set_weights", "helm_get_weights",
            "helm_get_lambdas", "helm_cycle", "helm_solve", "helm_residual", "helm_residual_noalloc",
            "helm_cycle_backward", "helm_loss",
            "helm_batch_setup", "helm_batch_get", "helm_batch_solve", "helm_batch_classes", "helm_batch_destroy",
@@ -81,6 +81,8 @@ def lib():
     L.helm_set_phase.argtypes = [vp, vp, i32, vp]
     L.helm_set_rays.restype = i32
     L.helm_set_rays.argtypes = [vp, i32, vp]
+    L.helm_eikonal.restype = i32
+    L.helm_eikonal.argtypes = [vp, vp, i32, i32, ctypes.c_double, vp, vp, vp, vp, vp]
     L.helm_set_weights.restype = i32
     L.helm_set_weights.argtypes = [vp, P(dbl)]
     L.helm_get_weights.restype = i32

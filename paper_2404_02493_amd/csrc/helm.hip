@@ -22,6 +22,7 @@
 #include "kernels_tail.hpp"
 #include "kernels_adjoint.hpp"
 #include "kernels_wtail.hpp"
+#include "kernels_eik.hpp"
 
 namespace helm {
 
@@ -100,6 +101,7 @@ struct helm_ctx_s {
     std::vector<helm::AdrLevel> al;
     void* car2 = nullptr;    // carrier e^{i sigma k phi} on level 2 (cycle precision)
     bool phase_set = false;
+    bool phase_factored = false;  // ADR coefficients from the product rule (helm_eikonal)
     // phase sets of the ADR correction: set 0 is the phase of helm_set_phase; helm_set_rays
     // fills nsets plane-wave sets and the m-th ADR step of a cycle uses set m mod nsets
     struct PhaseSet {
@@ -1272,6 +1274,7 @@ static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     drop_graphs(c);
     c->phase_set = true;
+    c->phase_factored = false;
 }
 
 // Wave-Ray phases: count plane waves phi_m = nbar (cos theta_m x + sin theta_m y),
@@ -1320,6 +1323,7 @@ static void set_rays(helm_ctx c, int count, hipStream_t st) {
     c->nsets = count;
     drop_graphs(c);
     c->phase_set = true;
+    c->phase_factored = false;
 }
 
 template <typename T>
@@ -1490,6 +1494,7 @@ static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int max
     return status;
 }
 
+#include "eik_host.hpp"
 #include "adjoint_host.hpp"
 #include "batch.hpp"
 #include "tune.hpp"
@@ -1637,6 +1642,20 @@ helm_status helm_set_rays(helm_ctx ctx, int32_t count, void* stream) {
     })
 }
 
+helm_status helm_eikonal(helm_ctx ctx, const double* src_xy, int32_t nsrc, int32_t max_rounds, double tol,
+                         void* tau1_out, void* phi_out, int32_t* rounds, double* change, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr, "NULL argument");
+        int r = 0;
+        double ch = 0.0;
+        const helm_status st = eikonal(ctx, src_xy, nsrc, max_rounds, tol, tau1_out, phi_out, &r, &ch,
+                                       (hipStream_t)stream);
+        if (rounds) *rounds = r;
+        if (change) *change = ch;
+        return st;
+    })
+}
+
 helm_status helm_set_weights(helm_ctx ctx, const double* w) {
     ABI_GUARD({
         REQUIRE(ctx != nullptr && w != nullptr, "NULL argument");
@@ -1726,6 +1745,9 @@ helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const vo
         REQUIRE(K >= 1 && K <= 100000, "K must be in [1, 100000]");
         if (ctx->d.adr_steps > 0 && ctx->L >= 3 && !ctx->phase_set)
             throw Error(HELM_ESTATE, "helm_set_phase must be called before helm_cycle_backward");
+        if (ctx->phase_factored)
+            throw Error(HELM_ESTATE, "helm_cycle_backward needs a phase from helm_set_phase (the product-rule "
+                                     "coefficients of helm_eikonal have no adjoint)");
         REQUIRE(ctx->d.gmres_m <= GMAX && ctx->d.gmres_coarse_m <= GMAX,
                 "the adjoint supports GMRES dimensions up to 6");
         hipStream_t st = (hipStream_t)stream;

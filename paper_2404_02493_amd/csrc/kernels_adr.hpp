@@ -14,12 +14,69 @@ struct AdrGeom {
     double two_sk;     // 2 * sigma * k (the advection factor is -i * two_sk)
 };
 
-// Phase derivatives and reaction term on one ADR level, computed in FP64 from the
-// fine phase by injection (stride s); second-order central differences inside,
-// first-order one-sided ones at the last unknown (the node x = 1 is not stored).
+// The level-2 carrier e^{i sigma k phi} from the phase reduced to [-pi, pi]
+// (Cody-Waite reduction with a two-part 2 pi) and its sine and cosine, in FP64.
+template <typename T>
+__device__ __forceinline__ cplx<T> adr_carrier(double phi, double k, int sigma) {
+    const double P1 = 6.283185307179586, P2 = 2.4492935982947064e-16;
+    const double a = double(sigma) * k * phi;
+    const double q = rint(a / P1);
+    double t = fma(-q, P1, a);
+    t = fma(-q, P2, t);
+    double sn, cs;
+    sincos(t, &sn, &cs);
+    return mk<T>(T(cs), T(sn));
+}
+
+// phi_x, phi_y and Lap phi at unknown (i, j) of a level of n nodes per side with
+// spacing h from the values P(a, b) of a field: second-order central differences
+// inside, first-order one-sided ones at the last unknown (the node x = 1 is not
+// stored).
+template <typename F>
+__device__ __forceinline__ void fd_phase_rule(const F& P, int i, int j, int n, double h, double& px, double& py,
+                                              double& lap) {
+    double pxx, pyy;
+    const double c = P(i, j);
+    if (j <= n - 2) {
+        px = (P(i, j + 1) - P(i, j - 1)) / (2.0 * h);
+        pxx = ((P(i, j + 1) - 2.0 * c) + P(i, j - 1)) / (h * h);
+    } else {
+        px = (c - P(i, j - 1)) / h;
+        pxx = ((c - 2.0 * P(i, j - 1)) + P(i, j - 2)) / (h * h);
+    }
+    if (i <= n - 2) {
+        py = (P(i + 1, j) - P(i - 1, j)) / (2.0 * h);
+        pyy = ((P(i + 1, j) - 2.0 * c) + P(i - 1, j)) / (h * h);
+    } else {
+        py = (c - P(i - 1, j)) / h;
+        pyy = ((c - 2.0 * P(i - 1, j)) + P(i - 2, j)) / (h * h);
+    }
+    lap = pxx + pyy;
+}
+
+// Stores phi_x, phi_y and the reaction term of level node p = (i, j):
 //   c0 = -i sigma k Lap(phi) + k^2 (phi_x^2 + phi_y^2 - n2) - i sigma k^2 n2 delta
-// car (level 2 only, may be null): the carrier e^{i sigma k phi}, from the phase reduced
-// to [-pi, pi] and its sine and cosine, all in FP64.
+template <typename T>
+__device__ __forceinline__ void adr_coef_store(const Geom& G, const double* __restrict__ n2f, int i, int j,
+                                               size_t p, double px, double py, double lap, double k, int sigma,
+                                               double strength, T* __restrict__ px_out, T* __restrict__ py_out,
+                                               cplx<T>* __restrict__ c0_out) {
+    const int s = G.s, nf = G.nf;
+    const double nn = n2f[(size_t)i * s * nf + (size_t)j * s];
+    const double ri = sponge_ramp<double>(i * s, nf, G.inv_W), rj = sponge_ramp<double>(j * s, nf, G.inv_W);
+    const double rho = ri > rj ? ri : rj;
+    const double delta = strength * rho * rho + double(sigma) * G.sig_shift;  // sponge plus shift
+    const double k2 = k * k;
+    const double re = k2 * ((px * px + py * py) - nn);
+    const double im = -(double(sigma) * k) * lap - ((double(sigma) * k2) * nn) * delta;
+    px_out[p] = T(px);
+    py_out[p] = T(py);
+    c0_out[p] = mk<T>(T(re), T(im));
+}
+
+// Phase derivatives and reaction term on one ADR level, computed in FP64 from the
+// fine phase by injection (stride s) with the finite-difference rule above.
+// car (level 2 only, may be null): the carrier.
 template <typename T, typename TP>
 __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __restrict__ n2f,
                                                     const TP* __restrict__ phi, double k, int sigma, double strength,
@@ -31,50 +88,16 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __rest
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         const int i = (int)(p / n), j = (int)(p % n);
         auto P = [&](int a, int b) -> double { return double(phi[(size_t)a * s * nf + (size_t)b * s]); };
-        if (car_out) {
-            // Cody-Waite reduction with a two-part 2 pi
-            const double P1 = 6.283185307179586, P2 = 2.4492935982947064e-16;
-            double a = double(sigma) * k * P(i, j);
-            double q = rint(a / P1);
-            double t = fma(-q, P1, a);
-            t = fma(-q, P2, t);
-            double sn, cs;
-            sincos(t, &sn, &cs);
-            car_out[p] = mk<T>(T(cs), T(sn));
-        }
+        if (car_out) car_out[p] = adr_carrier<T>(P(i, j), k, sigma);
         if (i == 0 || j == 0) {
             px_out[p] = T(0);
             py_out[p] = T(0);
             c0_out[p] = cplx<T>{};
             continue;
         }
-        double px, py, pxx, pyy;
-        const double c = P(i, j);
-        if (j <= n - 2) {
-            px = (P(i, j + 1) - P(i, j - 1)) / (2.0 * h);
-            pxx = ((P(i, j + 1) - 2.0 * c) + P(i, j - 1)) / (h * h);
-        } else {
-            px = (c - P(i, j - 1)) / h;
-            pxx = ((c - 2.0 * P(i, j - 1)) + P(i, j - 2)) / (h * h);
-        }
-        if (i <= n - 2) {
-            py = (P(i + 1, j) - P(i - 1, j)) / (2.0 * h);
-            pyy = ((P(i + 1, j) - 2.0 * c) + P(i - 1, j)) / (h * h);
-        } else {
-            py = (c - P(i - 1, j)) / h;
-            pyy = ((c - 2.0 * P(i - 1, j)) + P(i - 2, j)) / (h * h);
-        }
-        const double lap = pxx + pyy;
-        const double nn = n2f[(size_t)i * s * nf + (size_t)j * s];
-        const double ri = sponge_ramp<double>(i * s, nf, G.inv_W), rj = sponge_ramp<double>(j * s, nf, G.inv_W);
-        const double rho = ri > rj ? ri : rj;
-        const double delta = strength * rho * rho + double(sigma) * G.sig_shift;  // sponge plus shift
-        const double k2 = k * k;
-        const double re = k2 * ((px * px + py * py) - nn);
-        const double im = -(double(sigma) * k) * lap - ((double(sigma) * k2) * nn) * delta;
-        px_out[p] = T(px);
-        py_out[p] = T(py);
-        c0_out[p] = mk<T>(T(re), T(im));
+        double px, py, lap;
+        fd_phase_rule(P, i, j, n, h, px, py, lap);
+        adr_coef_store<T>(G, n2f, i, j, p, px, py, lap, k, sigma, strength, px_out, py_out, c0_out);
     }
 }
 
