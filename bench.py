@@ -191,6 +191,42 @@ def bench_comparison(case, g, maxit: int = 600):
     return out
 
 
+def bench_eikonal(case, g, maxit: int = 1000):
+    """The travel-time phase computed on the device (helm_eikonal: factored eikonal
+    equation by fast sweeping, product-rule ADR coefficients) against the host
+    fast-marching helper that prepares the headline phase, and the FP32+refinement
+    solve with that phase."""
+    import numpy as np
+    import torch
+
+    import helm_inputs as hi
+    from paper_2404_02493_amd import Helmholtz
+
+    src = np.asarray(case.sources, dtype=np.float64)
+    t0 = time.perf_counter()
+    hi.fmm_phase(case.velocity, src)
+    host_s = time.perf_counter() - t0
+    H = Helmholtz(case.velocity, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells)
+    H.eikonal(src, max_rounds=1000, tol=1e-10)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rounds, change = H.eikonal(src, max_rounds=1000, tol=1e-10)
+    torch.cuda.synchronize()
+    dev_s = time.perf_counter() - t0
+    H.solve(g, tol=1e-6, maxit=5, mode=1)  # graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, rr, _ = H.solve(g, tol=1e-6, maxit=maxit, mode=1)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    H.close()
+    n = case.n
+    return {"sources": int(src.shape[0]), "rounds": rounds, "last_change": change, "seconds": round(dev_s, 4),
+            "node_updates_per_s": round(4.0 * rounds * n * n / dev_s, 1),
+            "host_fast_marching_seconds": round(host_s, 3),
+            "solve_iterations": its, "solve_relres": rr, "solve_seconds": round(solve_s, 3), "maxit": maxit}
+
+
 def copy_probe(reps: int = 5):
     """A plain device copy of 4096^2 complex64 values (128 MiB read + 128 MiB written per
     dispatch), the known-size reference for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -450,7 +486,7 @@ def main():
 
     roofline_hbm = hbm_rooflines(prof32["kernels"]) if prof32 else None
 
-    shifted = sharp = batch = comparison = None
+    shifted = sharp = batch = comparison = eikonal = None
     if not args.no_extras:
         log("shifted equation (relative shift 0.01) to 1e-7")
         shifted = bench_shifted(case, g)
@@ -464,6 +500,9 @@ def main():
         log("unsmoothed layered medium, at most 1000 iterations")
         sharp = bench_sharp(args.seed)
         log(f"sharp: {sharp}")
+        log("travel-time phase on the device (factored eikonal) and its solve")
+        eikonal = bench_eikonal(case, g)
+        log(f"eikonal: {eikonal}")
 
     adjoint = None
     if not args.no_adjoint:
@@ -509,6 +548,7 @@ def main():
         "sharp": sharp,
         "batch64": batch,
         "comparison": comparison,
+        "eikonal_phase": eikonal,
         "profile_fp32": summary,
         "adjoint": adjoint,
         "tuning": {k: v for k, v in tuning.items() if k != "timings_ms"} if tuning else None,

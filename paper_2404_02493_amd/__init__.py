@@ -94,7 +94,7 @@ class Helmholtz:
         self._phi = t
         check(lib().helm_set_phase(self._ctx, _ptr(t), int(is64), _stream_ptr(stream)))
 
-    def eikonal(self, sources, max_rounds: int = 1000, tol: float = 1e-12, tau1_out=None, phi_out=None,
+    def eikonal(self, sources, max_rounds: int = 1000, tol: float = 1e-10, tau1_out=None, phi_out=None,
                 stream=None):
         """Travel-time phase of the point sources, computed on the device (factored
         eikonal equation, fast sweeping) and installed as the ADR phase; one source

@@ -18,9 +18,9 @@
 // the node anti-diagonals with the tile and its one-node halo in LDS.  A node then
 // sees exactly the values the sequential pass would give it (updated neighbours
 // behind it, old ones ahead), so every pass equals the sequential one; the local
-// update rounds every operation separately (no contraction), so the result is
-// the same double precision numbers as a sequential implementation of the same
-// steps.
+// update rounds every operation separately (no contraction; quotients by h = 2^-m
+// are the exact products by n), so the result is the same double precision numbers
+// as a sequential implementation of the same steps.
 #pragma once
 
 #include "kernels_adr.hpp"
@@ -40,26 +40,28 @@ __device__ __forceinline__ double eik_r(const EikSrc& E, int i, int j) {
     return sqrt(dx * dx + dy * dy);
 }
 
-// New tau1 at global node (i, j) (not fixed) from the neighbour values tw, te, ts, tn
-// (+inf where missing or not reached yet), or +inf when no candidate exists.
-__device__ __forceinline__ double eik_update(const EikSrc& E, int i, int j, double sp, double tw, double te,
-                                             double ts, double tn) {
+// New tau1 at global node (i, j) (not fixed, r = tau0 there, sp = s there) from the
+// neighbour values tw, te, ts, tn (+inf where missing or not reached yet) and their
+// tau0 values rw, re, rs, rn, or +inf when no candidate exists.  h = 1/n is a power
+// of two, so a quotient by h is the product by n, exactly.
+__device__ __forceinline__ double eik_update(const EikSrc& E, int i, int j, double r, double sp, double tw,
+                                             double te, double ts, double tn, double rw, double re, double rs,
+                                             double rn) {
 #pragma clang fp contract(off)
     const double inf = __builtin_huge_val();
-    const double h = E.h;
+    const double h = E.h, nh = double(E.n);
     const double dx = double(j) * h - E.xs, dy = double(i) * h - E.ys;
-    const double r = sqrt(dx * dx + dy * dy);
     const double gx = dx / r, gy = dy / r;
     bool hx = false, hy = false;
     double tqx = inf, tqy = inf, ux = 0.0, uy = 0.0, sgx = 0.0, sgy = 0.0;
     if (tw < inf) {
         hx = true;
-        tqx = eik_r(E, i, j - 1) * tw;
+        tqx = rw * tw;
         ux = tw;
         sgx = 1.0;
     }
     if (te < inf) {
-        const double v = eik_r(E, i, j + 1) * te;
+        const double v = re * te;
         if (!hx || v < tqx) {
             hx = true;
             tqx = v;
@@ -69,12 +71,12 @@ __device__ __forceinline__ double eik_update(const EikSrc& E, int i, int j, doub
     }
     if (ts < inf) {
         hy = true;
-        tqy = eik_r(E, i - 1, j) * ts;
+        tqy = rs * ts;
         uy = ts;
         sgy = 1.0;
     }
     if (tn < inf) {
-        const double v = eik_r(E, i + 1, j) * tn;
+        const double v = rn * tn;
         if (!hy || v < tqy) {
             hy = true;
             tqy = v;
@@ -84,8 +86,8 @@ __device__ __forceinline__ double eik_update(const EikSrc& E, int i, int j, doub
     }
     double best = inf;
     const double s2 = sp * sp;
-    const double ax = sgx * r / h + gx, bx = sgx * r * ux / h;
-    const double ay = sgy * r / h + gy, by = sgy * r * uy / h;
+    const double ax = sgx * r * nh + gx, bx = sgx * r * ux * nh;
+    const double ay = sgy * r * nh + gy, by = sgy * r * uy * nh;
     if (hx && hy) {
         const double A = ax * ax + ay * ay, B = ax * bx + ay * by, C = (bx * bx + by * by) - s2;
         if (A > 0.0) {
@@ -134,7 +136,8 @@ template <int B>
 __global__ __launch_bounds__(B) void k_eik_pass(EikSrc E, const double* __restrict__ s, double* __restrict__ t1,
                                                 int iup, int jup, int d, double* __restrict__ part) {
     constexpr int R = B + 2;
-    __shared__ double tl[R * R];
+    __shared__ double tl[R * R];  // tau1 of the tile and its halo
+    __shared__ double rl[R * R];  // tau0 there
     __shared__ double sl[B * B];
     __shared__ double red[B];
     const int n = E.n, T = n / B;
@@ -146,7 +149,9 @@ __global__ __launch_bounds__(B) void k_eik_pass(EikSrc E, const double* __restri
     auto gj = [&](int b) { return jup ? b : n - 1 - b; };
     for (int q = lane; q < R * R; q += B) {
         const int a = a0 - 1 + q / R, b = b0 - 1 + q % R;
-        tl[q] = (a >= 0 && a < n && b >= 0 && b < n) ? t1[(size_t)gi(a) * n + gj(b)] : inf;
+        const bool in = a >= 0 && a < n && b >= 0 && b < n;
+        tl[q] = in ? t1[(size_t)gi(a) * n + gj(b)] : inf;
+        rl[q] = in ? eik_r(E, gi(a), gj(b)) : 0.0;
     }
     for (int q = lane; q < B * B; q += B) sl[q] = s[(size_t)gi(a0 + q / B) * n + gj(b0 + q % B)];
     __syncthreads();
@@ -158,9 +163,10 @@ __global__ __launch_bounds__(B) void k_eik_pass(EikSrc E, const double* __restri
         if (lb >= 0 && lb < B) {
             const int i = gi(a0 + la), j = gj(b0 + lb);
             const int q = (la + 1) * R + (lb + 1);
-            if (eik_r(E, i, j) > E.rfix) {
-                const double t = eik_update(E, i, j, sl[la * B + lb], tl[q + dw], tl[q - dw], tl[q + ds * R],
-                                            tl[q - ds * R]);
+            const double r = rl[q];
+            if (r > E.rfix) {
+                const double t = eik_update(E, i, j, r, sl[la * B + lb], tl[q + dw], tl[q - dw], tl[q + ds * R],
+                                            tl[q - ds * R], rl[q + dw], rl[q - dw], rl[q + ds * R], rl[q - ds * R]);
                 const double old = tl[q];
                 if (t < old) {
                     const double dec = old == inf ? inf : old - t;
