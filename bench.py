@@ -103,7 +103,11 @@ def hbm_rooflines(kernels):
     """Kernels of the 4096^2 solve whose data streams through HBM on every launch (the
     fine-grid level-1 passes and the outer Krylov passes: their inputs are not reused
     within the 256 MB Infinity Cache between launches), each with its algorithmic bytes
-    per launch over its average event-timed launch duration."""
+    per launch over its average event-timed launch duration, and the counter-measured
+    HBM bytes of a profiles/ traffic record over the same duration while the kernel
+    sources are those the record was taken with."""
+    from paper_2404_02493_amd.traffic import find as find_traffic
+
     out = []
     for fam in HBM_CLEAN:
         ks = [k for k in kernels if k["name"].startswith(f"({fam}<") or k["name"].startswith(f"{fam} ")
@@ -114,9 +118,12 @@ def hbm_rooflines(kernels):
         ms = sum(k["ms"] for k in ks)
         by = sum(k["bytes"] for k in ks)
         gbs = by / (ms * 1e-3) / 1e9
-        out.append({"kernel": fam, "launches": launches, "avg_launch_us": round(1e3 * ms / launches, 2),
+        tb = find_traffic(os.path.join(ROOT, "profiles"), fam)
+        avg_s = 1e-3 * ms / launches
+        out.append({"kernel": fam, "launches": launches, "avg_launch_us": round(1e6 * avg_s, 2),
                     "bytes_per_launch": by / launches, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)})
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "traffic": round(tb / avg_s / 1e9, 1) if tb else None, "traffic_bytes_per_launch": tb})
     return out
 
 

@@ -23,6 +23,7 @@
 #include "kernels_adjoint.hpp"
 #include "kernels_wtail.hpp"
 #include "kernels_eik.hpp"
+#include "kernels_jac0.hpp"
 
 namespace helm {
 
@@ -520,19 +521,19 @@ struct Engine {
             const double bc = c64 ? 16.0 : sizeof(C);
             if (c64)
                 LAUNCH(c, (sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_restrict<T, double>),
-                       dim3(rr_blocks(G.n)), dim3(BLOCK), st, G, (const T*)W.n2, (const C*)g, w0,
+                       dim3(jac0r_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g, w0,
                        (c128*)c->wl[2].g);
             else
                 LAUNCH(c, (sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_restrict<T, T>),
-                       dim3(rr_blocks(G.n)), dim3(BLOCK), st, G, (const T*)W.n2, (const C*)g, w0, (C*)c->wl[2].g);
+                       dim3(jac0r_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g, w0, (C*)c->wl[2].g);
             cycle_coarse(2);
             if (c64)
                 LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_prolong_jacobi<double, T>),
-                       dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2, (const C*)g,
+                       dim3(jac0p_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g,
                        (const c128*)c->wl[2].u, w0, (C*)u_out);
             else
                 LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_prolong_jacobi<T, T>),
-                       dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2, (const C*)g,
+                       dim3(jac0p_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g,
                        (const C*)c->wl[2].u, w0, (C*)u_out);
             return;
         }

@@ -532,221 +532,6 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
     }
 }
 
-// ------------------------------------------------------------------ level 1 from a zero iterate
-// One damped Jacobi sweep from u = 0 is pointwise, u0 = (w/d) g with d = 4/h^2 - kappa
-// the diagonal of A.  Since d u0 = w g, the residual of u0 needs no kappa:
-//   g - A u0 = (1 - w) g + h^-2 (sum of the four neighbours of u0),
-// and the post-smoothing sweep from u = u0 + P ec folds to
-//   u + (w/d)(g - A u) = (w/d) ((2 - w) g + h^-2 (sum of the neighbours of u)) + (1 - w) P ec.
-// The two kernels below use these forms and recompute u0 where they need it instead of
-// storing it.
-
-// w / d (one real division)
-template <typename T>
-__device__ __forceinline__ cplx<T> jac_wdiag(const Geom& G, T n2v, int i, int j, T w) {
-    const cplx<T> kap = kappa_at<T>(G, n2v, i, j);
-    const T dr = T(4) * T(G.inv_h2) - kap.re, di = -kap.im;
-    const T s = w / (dr * dr + di * di);
-    return mk<T>(dr * s, -di * s);
-}
-
-// rc = R (g - A u0): u0 on the fine nodes around a RCX x RCY coarse tile and (1 - w) g on
-// the residual nodes (LDS), the residual from them, then the 9-point full weighting;
-// rr_blocks(G.n) blocks.
-template <typename Tf, typename Tc>
-__global__ __launch_bounds__(BLOCK) void k_jac0_restrict(Geom G, const Tf* __restrict__ n2,
-                                                         const cplx<Tf>* __restrict__ g,
-                                                         const double* __restrict__ wp,
-                                                         cplx<Tc>* __restrict__ rc, BatchIdx bi) {
-    bshift(bi.off(), n2, g, wp, rc);
-    const Tf w = Tf(wp[0]);
-    constexpr int FW = 2 * RCX + 1, FH = 2 * RCY + 1, UW = FW + 2, UH = FH + 2;
-    __shared__ cplx<Tf> us[UH * UW];
-    __shared__ cplx<Tf> r[FH * FW];
-    const int n = G.n, nc = n / 2;
-    const int ntx = (nc + RCX - 1) / RCX;
-    const int nb = gridDim.x;
-    int b = blockIdx.x;
-    b = xcd_remap(b, nb);
-    const int I0 = (b / ntx) * RCY, J0 = (b % ntx) * RCX;
-    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;  // first fine node of the residual tile
-    const Tf w1 = Tf(1) - w;
-    // all loads of a thread first, then the arithmetic
-    constexpr int NQ = (UH * UW + BLOCK - 1) / BLOCK;
-    cplx<Tf> gv[NQ];
-    Tf nv[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-        const int q = threadIdx.x + k * BLOCK;
-        const int ri = q / UW, rj = q - ri * UW;
-        const int fi = fi0 - 1 + ri, fj = fj0 - 1 + rj;
-        gv[k] = cplx<Tf>{};
-        nv[k] = Tf(0);
-        if (q < UH * UW && fi >= 1 && fj >= 1 && fi < n && fj < n) {
-            const size_t p = (size_t)fi * n + fj;
-            gv[k] = g[p];
-            nv[k] = n2[p];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-        const int q = threadIdx.x + k * BLOCK;
-        if (q >= UH * UW) break;
-        const int ri = q / UW, rj = q - ri * UW;
-        const int fi = fi0 - 1 + ri, fj = fj0 - 1 + rj;
-        cplx<Tf> u{}, gw{};
-        if (fi >= 1 && fj >= 1 && fi < n && fj < n) {
-            u = jac_wdiag<Tf>(G, nv[k], fi, fj, w) * gv[k];
-            gw = w1 * gv[k];
-        }
-        us[q] = u;
-        if (ri >= 1 && rj >= 1 && ri <= FH && rj <= FW) r[(ri - 1) * FW + rj - 1] = gw;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < FH * FW; q += BLOCK) {
-        const int ri = q / FW, rj = q - ri * FW;
-        const int fi = fi0 + ri, fj = fj0 + rj;
-        if (fi >= 1 && fj >= 1 && fi < n && fj < n) {
-            const int l = (ri + 1) * UW + rj + 1;
-            r[q] = r[q] + Tf(G.inv_h2) * (((us[l - UW] + us[l + UW]) + us[l - 1]) + us[l + 1]);
-        }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < RCX * RCY; q += BLOCK) {
-        const int ci = q / RCX, cj = q - ci * RCX;
-        const int I = I0 + ci, J = J0 + cj;
-        if (I >= nc || J >= nc) continue;
-        cplx<Tf> v{};
-        if (I > 0 && J > 0) {
-            const int l = (2 * ci + 1) * FW + 2 * cj + 1;
-            const cplx<Tf> c = r[l];
-            const cplx<Tf> ud = ((r[l - FW] + r[l + FW]) + r[l - 1]) + r[l + 1];
-            const cplx<Tf> dg = ((r[l - FW - 1] + r[l - FW + 1]) + r[l + FW - 1]) + r[l + FW + 1];
-            v = Tf(1.0 / 16.0) * ((Tf(4) * c + Tf(2) * ud) + dg);
-        }
-        rc[(size_t)I * nc + J] = ccast<Tc>(v);
-    }
-}
-
-// out = (w/d) ((2 - w) g + h^-2 sum_nb u) + (1 - w) P ec with u = u0 + P ec (the
-// post-smoothing sweep after the zero-start pre-smoothing and the coarse correction).
-// A thread keeps g, w/d and P ec of its own four rows in registers; u of the 64 x 16 tile
-// and its one-node ring sits in LDS.  ec has nc = n/2 nodes per side.
-template <typename Tc, typename Tf>
-__global__ __launch_bounds__(BLOCK) void k_jac0_prolong_jacobi(Geom G, const Tf* __restrict__ n2,
-                                                               const cplx<Tf>* __restrict__ g,
-                                                               const cplx<Tc>* __restrict__ ec,
-                                                               const double* __restrict__ wp,
-                                                               cplx<Tf>* __restrict__ out, BatchIdx bi) {
-    bshift(bi.off(), n2, g, ec, wp, out);
-    const Tf w = Tf(wp[0]);
-    constexpr int HW = TX + 2, HH = TY + 2;
-    __shared__ cplx<Tf> us[HH * HW];
-    const int n = G.n, nc = n / 2;
-    int j, i0;
-    tile_origin(n, j, i0);
-    const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
-    const int tid = threadIdx.x + threadIdx.y * TX;
-    // Loads first, all of them unconditional so that they are in flight together: a
-    // position off the grid reads index 0 of its array instead (the zero ring of g and ec;
-    // n2 there is not used).  The own rows (g, n2 and the coarse values), then the ring
-    // node of the thread (two rows of TX and two columns of TY nodes; corners unused).
-    const bool injc = j >= 1 && j < n;
-    cplx<Tf> gr[RPT];
-    Tf nr[RPT];
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-        const int i = i0 + rr;
-        const size_t p = (injc && i >= 1 && i < n) ? (size_t)i * n + j : 0;
-        gr[rr] = g[p];
-        nr[rr] = n2[p];
-    }
-    // P ec on the own rows i0..i0+3 (i0 is a multiple of 4): coarse rows i0/2 .. i0/2 + 2,
-    // columns J = j/2 and, for odd j, J + 1
-    const int J = j >> 1, jodd = j & 1;
-    auto ecl = [&](int a, int bb) -> cplx<Tc> {
-        const bool in = a >= 1 && bb >= 1 && a < nc && bb < nc;
-        return ec[in ? (size_t)a * nc + bb : 0];
-    };
-    cplx<Tc> e0[3], e1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int I = (i0 >> 1) + a;
-        e0[a] = ecl(I, J);
-        e1[a] = ecl(I, J + 1);  // used for odd j only
-    }
-    const bool ring = tid < 2 * TX + 2 * TY;
-    int gi = -1, gj = -1, lr = 0;
-    if (tid < TX) {
-        gi = it - 1; gj = jt + tid; lr = tid + 1;
-    } else if (tid < 2 * TX) {
-        gi = it + TY; gj = jt + tid - TX; lr = (TY + 1) * HW + tid - TX + 1;
-    } else if (tid < 2 * TX + TY) {
-        gi = it + tid - 2 * TX; gj = jt - 1; lr = (tid - 2 * TX + 1) * HW;
-    } else if (ring) {
-        gi = it + tid - 2 * TX - TY; gj = jt + TX; lr = (tid - 2 * TX - TY + 1) * HW + TX + 1;
-    }
-    const bool ringin = ring && gi >= 1 && gj >= 1 && gi < n && gj < n;
-    const size_t ph = ringin ? (size_t)gi * n + gj : 0;
-    const cplx<Tf> gh = g[ph];
-    const Tf nh = n2[ph];
-    // bilinear value at the ring node from its four coarse neighbours (0 off the grid)
-    const int gI = ringin ? gi >> 1 : 0, gJ = ringin ? gj >> 1 : 0;
-    const cplx<Tc> q00 = ecl(gI, gJ), q10 = ecl(gI + 1, gJ), q01 = ecl(gI, gJ + 1), q11 = ecl(gI + 1, gJ + 1);
-    cplx<Tf> wd[RPT], pe[RPT];
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-        const int i = i0 + rr;
-        const int a = rr >> 1;
-        const cplx<Tc> h0 = jodd ? Tc(0.5) * (e0[a] + e1[a]) : e0[a];
-        cplx<Tc> pc = h0;
-        if (rr & 1) {
-            const cplx<Tc> h1 = jodd ? Tc(0.5) * (e0[a + 1] + e1[a + 1]) : e0[a + 1];
-            pc = Tc(0.5) * (h0 + h1);
-        }
-        pe[rr] = ccast<Tf>(pc);
-        wd[rr] = cplx<Tf>{};
-        cplx<Tf> v{};
-        if (injc && i >= 1 && i < n) {
-            wd[rr] = jac_wdiag<Tf>(G, nr[rr], i, j, w);
-            v = wd[rr] * gr[rr] + pe[rr];
-        }
-        us[(i - it + 1) * HW + threadIdx.x + 1] = v;
-    }
-    if (ring) {
-        cplx<Tf> v{};
-        if (ringin) {
-            // the same cases and sums as prolong_at
-            const bool fo = gi & 1, go = gj & 1;
-            cplx<Tc> pv;
-            if (!fo && !go)
-                pv = q00;
-            else if (fo && !go)
-                pv = Tc(0.5) * (q00 + q10);
-            else if (!fo && go)
-                pv = Tc(0.5) * (q00 + q01);
-            else
-                pv = Tc(0.25) * (((q00 + q10) + q01) + q11);
-            v = jac_wdiag<Tf>(G, nh, gi, gj, w) * gh + ccast<Tf>(pv);
-        }
-        us[lr] = v;
-    }
-    __syncthreads();
-    if (j >= n) return;
-    const Tf w1 = Tf(1) - w, w2 = Tf(2) - w;
-    for (int rr = 0; rr < RPT; ++rr) {
-        const int i = i0 + rr;
-        if (i >= n) break;
-        cplx<Tf> v{};
-        if (i > 0 && j > 0) {
-            const int l = (i - it + 1) * HW + threadIdx.x + 1;
-            const cplx<Tf> nbs = ((us[l - HW] + us[l + HW]) + us[l - 1]) + us[l + 1];
-            v = wd[rr] * (w2 * gr[rr] + Tf(G.inv_h2) * nbs) + w1 * pe[rr];
-        }
-        out[(size_t)i * n + j] = v;
-    }
-}
-
 // ------------------------------------------------------------------ flat helpers
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_axpy(size_t N, T a, const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, BatchIdx bi) {

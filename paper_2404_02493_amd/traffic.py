@@ -21,7 +21,7 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["common.hpp", "reduce.hpp", "kernels_wave.hpp", "kernels_adr.hpp", "kernels_krylov.hpp",
-           "kernels_sstep.hpp"]
+           "kernels_sstep.hpp", "kernels_jac0.hpp"]
 
 
 def find(profiles_dir: str, profile_key: str) -> float | None:
