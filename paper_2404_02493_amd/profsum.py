@@ -69,11 +69,12 @@ def counter_groups(pmc_dir: str):
 
 
 def trace_by_instance(trace_dir: str):
-    """{(kernel with template arguments, grid threads): (dispatches, mean ns)}."""
+    """{(kernel with template arguments, grid threads in all dimensions): (dispatches, mean ns)}."""
     agg = collections.defaultdict(lambda: [0, 0.0])
     for r in csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))):
         name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("helm::", "").strip()
-        key = (name, int(r["Grid_Size_X"]))
+        grid = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y") or 1) * int(r.get("Grid_Size_Z") or 1)
+        key = (name, grid)
         agg[key][0] += 1
         agg[key][1] += float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     return {k: (v[0], v[1] / v[0]) for k, v in agg.items()}
