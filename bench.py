@@ -366,6 +366,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the side measurements (sharp medium, shifted equation, batch)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the adjoint of 10 unrolled cycles at 1024^2 and print its record")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain copy kernel of known size (reference for memory counters)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2404_02493_amd", "tuning.json"),
@@ -384,6 +386,9 @@ def main():
         return
     if args.copy_probe:
         copy_probe()
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": bench_adjoint()}), flush=True)
         return
 
     import numpy as np

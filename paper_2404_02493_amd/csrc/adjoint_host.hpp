@@ -27,6 +27,7 @@ struct AdrTape {  // one GMRES-smoothed ADR level inside one ADR step
 struct AdjState {
     bool ready = false;
     int M = 0;
+    void* ubuf = nullptr;                    // u_k of the cycle being reversed (graph input)
     void* uB = nullptr;                      // level 1: input of the post-Jacobi sweep
     void* fb[2] = {};                        // level-1 cotangents
     std::vector<void*> g, ub;                // wave levels: right-hand side, input of the post-smoother
@@ -61,6 +62,7 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
     const size_t NF = (size_t)n * n;
     const bool adr_on = c->d.adr_steps > 0 && L >= 3;
     S.M = adr_on ? c->d.adr_steps : 0;
+    S.ubuf = dalloc(c, NF * csize(f64c));
     S.uB = dalloc(c, NF * csize(f64c));
     S.fb[0] = dalloc(c, NF * csize(f64c));
     S.fb[1] = dalloc(c, NF * csize(f64c));
@@ -230,17 +232,17 @@ struct AdjEngine {
         const int nb = fb(n);
         VecSet<T> K{};
         for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
+        // the partials of k_{j+1} go to entries j (j + 1) .. (j + 1)(j + 2) - 1, the layout of
+        // the record's Gram matrix, summed once by the solve
+        REQUIRE((size_t)(m + 1) * (m + 2) * nb <= c->partials_cap, "adjoint: reduction scratch too small");
         LAUNCH_NB(c, (x0 ? 4.0 : 2.0) * sizeof(C) * n, (k_gr_r0<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
                (const T*)A.py, (const C*)A.c0, (const C*)b, (const C*)x0, (C*)kv[0], c->partials);
-        double* gram = R->gram;  // device address arithmetic only
-        LAUNCH(c, 16.0 * nb, (k_finalize_sums<2>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, 2, gram);
-        for (int jj = 1; jj <= m; ++jj) {
+        for (int jj = 1; jj <= m; ++jj)
             LAUNCH_NB(c, (jj + 2.0) * sizeof(C) * n, (k_gr_chain<T>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
-                   (const T*)A.py, (const C*)A.c0, K, jj, 1.0 / tau(l), (C*)kv[jj], c->partials);
-            LAUNCH(c, 16.0 * nb * (jj + 1), (k_finalize_sums<2 * (GMAX + 1)>), dim3(1), dim3(FBLOCK), st,
-                   (const double*)c->partials, nb, 2 * (jj + 1), gram + 2 * (jj * (jj + 1) / 2));
-        }
-        LAUNCH_NB(c, 0.0, k_gr_solve, dim3(1), dim3(64), st, R, tau(l));
+                   (const T*)A.py, (const C*)A.c0, K, jj, 1.0 / tau(l), (C*)kv[jj],
+                   c->partials + (size_t)jj * (jj + 1) * nb);
+        LAUNCH_NB(c, 8.0 * (m + 1) * (m + 2) * nb, k_gr_solve, dim3(1), dim3(FBLOCK), st, (const double*)c->partials,
+               nb, R, tau(l));
         LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n, K, m,
                (const GRec*)R, (const C*)x0, (C*)xout);
     }
@@ -401,9 +403,7 @@ struct AdjEngine {
         for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
         LAUNCH_NB(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
                c->partials);
-        LAUNCH(c, 16.0 * nb * m, (k_finalize_sums<2 * GMAX>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb,
-               2 * m, (double*)R->cbar);
-        LAUNCH_NB(c, 0.0, k_ga_prep, dim3(1), dim3(64), st, R, tau(l));
+        LAUNCH_NB(c, 16.0 * nb * m, k_ga_prep, dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, R, tau(l));
         VecSet<T> V{};
         V.v[0] = (const C*)xbar;
         for (int q = 0; q <= m; ++q) V.v[q + 1] = (const C*)kv[q];
@@ -490,13 +490,43 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
     if (u0) HIPCHK(hipMemcpyAsync(ck, u0, vb, hipMemcpyDeviceToDevice, st));
     else HIPCHK(hipMemsetAsync(ck, 0, vb, st));
     for (int k = 0; k + 1 < K; ++k) cycle_any(c, g, ck + (size_t)k * vb, ck + (size_t)(k + 1) * vb, st);
-    // reverse sweep
+    // reverse sweep: per cycle, u_k into a fixed buffer, then the recording and the
+    // reverse of that cycle, replayed from one captured graph (about 1100 launches a cycle)
     AdjEngine<T> R(c, st);
     HIPCHK(hipMemcpyAsync(S.fb[0], grad_uK, vb, hipMemcpyDeviceToDevice, st));
+    const bool graphs = c->d.use_graphs && !c->prof.on;
     for (int k = K - 1; k >= 0; --k) {
         const void* uk = ck + (size_t)k * vb;
-        R.rec_cycle(g, uk);
-        R.rev_cycle(g, uk);
+        if (!graphs) {
+            R.rec_cycle(g, uk);
+            R.rev_cycle(g, uk);
+            continue;
+        }
+        HIPCHK(hipMemcpyAsync(S.ubuf, uk, vb, hipMemcpyDeviceToDevice, st));
+        if (!c->adj_exec || c->adj_g != g) {
+            if (c->adj_exec) (void)hipGraphExecDestroy(c->adj_exec);
+            c->adj_exec = nullptr;
+            if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            try {
+                AdjEngine<T> Rc(c, c->cap_stream);
+                Rc.rec_cycle(g, S.ubuf);
+                Rc.rev_cycle(g, S.ubuf);
+            } catch (...) {
+                (void)hipStreamEndCapture(c->cap_stream, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                throw;
+            }
+            HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(e);
+            c->adj_exec = exec;
+            c->adj_g = g;
+        }
+        HIPCHK(hipGraphLaunch(c->adj_exec, st));
     }
     if (c->f32) R.template phase_out<float>(grad_phi);
     else R.template phase_out<double>(grad_phi);

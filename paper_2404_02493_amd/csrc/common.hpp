@@ -91,6 +91,14 @@ __device__ __forceinline__ cplx<T> kappa_at(const Geom& G, T n2, int i, int j) {
     return {kr, kr * (T(G.sig_str) * (rho * rho) + T(G.sig_shift))};
 }
 
+// Row and column of the flat index p on a grid of n nodes per side; n is a power of two,
+// so this is a shift and a mask instead of a 64-bit division.
+__device__ __forceinline__ void rowcol(size_t p, int n, int& i, int& j) {
+    const int sh = __builtin_ctz((unsigned)n);
+    i = (int)(p >> sh);
+    j = (int)(p & (size_t)(n - 1));
+}
+
 // Workgroup b of nb is dispatched to XCD b mod 8 (round robin).  This renumbering gives
 // each XCD a contiguous range of work items (the first nb mod 8 XCDs one more), so that
 // neighbouring tiles or strips share one L2.

@@ -140,6 +140,8 @@ struct helm_ctx_s {
     hipEvent_t col_ev[helm::MAXM] = {};
     void* dbuf = nullptr;    // inner correction (mode 1)
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
+    hipGraphExec_t adj_exec = nullptr;  // one cycle of the adjoint (record + reverse), for adj_g
+    const void* adj_g = nullptr;
     // launch shapes chosen by the autotuner (0 = built-in default)
     struct Tuning {
         int sstep_rows[16] = {};    // s-step form on ADR level l: steps per marching unit, 1/2 tiles, 0 default
@@ -1091,7 +1093,7 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     const size_t NF = (size_t)n * n;
     // reduction scratch: enough partials for any tiled kernel on the fine grid
     const size_t maxblk = std::max<size_t>((size_t)tiles_of(n), 2048);
-    c->partials_cap = maxblk * (2 * MAXM + 4);
+    c->partials_cap = maxblk * std::max(2 * MAXM + 4, (GMAX + 1) * (GMAX + 2));
     c->partials = (double*)dalloc(c, c->partials_cap * sizeof(double));
     c->dscal = (double*)dalloc(c, 64 * sizeof(double));
     c->Kout = (KrylovScal*)dalloc(c, sizeof(KrylovScal));
@@ -1343,6 +1345,9 @@ static void cycle_eager(helm_ctx c, const void* g, const void* u_in, void* u_out
 static void drop_graphs(helm_ctx c) {
     for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
     c->graphs.clear();
+    if (c->adj_exec) (void)hipGraphExecDestroy(c->adj_exec);
+    c->adj_exec = nullptr;
+    c->adj_g = nullptr;
 }
 
 // One cycle: replays the graph captured for these pointers (capturing it on first

@@ -86,7 +86,8 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_adj(Geom G, const T* __restric
         return cdiv(yb[q], dh);
     };
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         cplx<T> out{};
         if (i > 0 && j > 0) {
             cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
@@ -112,7 +113,8 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_scale(int n, const cplx<Tf>*
     const int nc = n / 2;
     const size_t N = (size_t)nc * nc;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int I = (int)(p / nc), J = (int)(p % nc);
+        int I, J;
+        rowcol(p, nc, I, J);
         cplx<Tc> out{};
         if (I > 0 && J > 0) {
             const int fi = 2 * I, fj = 2 * J;
@@ -140,7 +142,8 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_adj(Geom G, const Tf* __restr
         return Tf(0.25) * prolong_at<Tc, Tf>(rcbar, nc, a, b);
     };
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         if (i == 0 || j == 0) continue;
         const cplx<Tf> t = tq(i, j);
         if (gbar) gbar[p] = gbar[p] + t;
@@ -160,7 +163,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ahsub(Geom G, const T* __restrict
     const int n = G.n;
     const size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         if (i == 0 || j == 0) continue;
         if (gbar) gbar[p] = gbar[p] + t[p];
         if (ubar) ubar[p] = ubar[p] - applyA_at(G, n2, t, i, j, true);
@@ -194,7 +198,8 @@ __global__ __launch_bounds__(BLOCK) void k_apply_A2(Geom G, const T* __restrict_
     const int n = G.n;
     const size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         cplx<T> a{}, b{};
         if (i > 0 && j > 0) {
             a = applyA_at(G, n2, d, i, j, false);
@@ -217,7 +222,8 @@ __global__ __launch_bounds__(BLOCK) void k_chebadj_step(Geom G, const T* __restr
     const int n = G.n;
     const size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         if (i == 0 || j == 0) continue;
         const cplx<T> rv = r[p] - applyA_at(G, n2, t1, i, j, true);
         const cplx<T> rtv = rt[p] - applyA_at(G, n2, t2, i, j, true);
@@ -241,7 +247,8 @@ __global__ __launch_bounds__(BLOCK) void k_dot_ah(Geom G, const T* __restrict__ 
     const size_t N = (size_t)n * n;
     double acc[1] = {0.0};
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         if (i == 0 || j == 0) continue;
         const cplx<T> v = applyA_at(G, n2, b, i, j, true);
         const cplx<T> x = a[p];
@@ -363,7 +370,8 @@ __global__ __launch_bounds__(BLOCK) void k_gr_r0(AdrGeom A, const T* __restrict_
     const size_t N = (size_t)n * n;
     double acc[2] = {0.0, 0.0};
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         cplx<T> v{};
         if (i > 0 && j > 0) {
             v = b[p];
@@ -387,7 +395,8 @@ __global__ __launch_bounds__(BLOCK) void k_gr_chain(AdrGeom A, const T* __restri
     for (int v = 0; v < 2 * (GMAX + 1); ++v) acc[v] = 0.0;
     const cplx<T>* __restrict__ kin = Kv.v[jj - 1];
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         cplx<T> v{};
         if (i > 0 && j > 0) {
             v = T(inv_tau) * applyM_at(A, px, py, c0, kin, i, j);
@@ -407,87 +416,136 @@ __global__ __launch_bounds__(BLOCK) void k_gr_chain(AdrGeom A, const T* __restri
     reduce_store<2 * (GMAX + 1)>(acc, 2 * (jj + 1), partials);
 }
 
-// Least squares of one GMRES call from the Gram matrix of k_1..k_{m+1} (one thread):
-// normalised Cholesky of W^H W; columns whose pivot falls below 1e-14 (an invariant
-// Krylov space) are dropped, which reproduces the early exit of Arnoldi.
-__global__ void k_gr_solve(GRec* __restrict__ R, double tau) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int m = R->m;
-    auto Gc = [&](int i, int j) -> c128 {  // <k_i, k_j>, 1-based
-        if (i <= j) return c128{R->gram[gram_off(i, j)], R->gram[gram_off(i, j) + 1]};
-        return c128{R->gram[gram_off(j, i)], -R->gram[gram_off(j, i) + 1]};
-    };
-    for (int a = 0; a < 2 * GMAX; ++a) {
-        R->c[a] = 0.0;
-        R->z[a] = 0.0;
+// sum over blocks b < nblk of row[b] in one wavefront: each lane issues its loads in
+// batches of 32 before adding them (fixed order), then the wavefront sum.
+__device__ __forceinline__ double wave_row_sum(const double* __restrict__ row, int nblk) {
+    constexpr int SB = 32;
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    for (int b0 = 0; b0 < nblk; b0 += 64 * SB) {
+        double t[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const int b = b0 + k * 64 + lane;
+            t[k] = b < nblk ? row[b] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) acc += t[k];
     }
-    const double b2 = Gc(1, 1).re;
-    R->zero = !(b2 > 0.0) || !isfinite(b2);
-    R->rank = 0;
-    if (R->zero) return;
-    double s[GMAX];
-    for (int a = 0; a < m; ++a) {
-        const double dg = tau * tau * Gc(a + 2, a + 2).re;
-        s[a] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
-        R->dsc[a] = s[a];
+    return wave_sum(acc);
+}
+
+// Sums the per-block Gram partials of one taped GMRES call (entry e of every block at
+// partials[e * nblk + b], e < (m+1)(m+2): the entries of k_1 first, then those of each
+// k_{j+1} with k_1..k_{j+1}, the layout of R->gram), one wavefront per entry in a fixed
+// order, into R->gram, then solves the least squares of the call from that Gram matrix
+// of k_1..k_{m+1} (one thread, on LDS copies): normalised Cholesky of W^H W; columns whose
+// pivot falls below 1e-14 (an invariant Krylov space) are dropped, which reproduces the
+// early exit of Arnoldi.  One block of FBLOCK threads.
+__global__ __launch_bounds__(FBLOCK) void k_gr_solve(const double* __restrict__ partials, int nblk,
+                                                     GRec* __restrict__ R, double tau) {
+    constexpr int NE = (GMAX + 1) * (GMAX + 2);
+    __shared__ double gs[NE];
+    __shared__ double Lf[2 * GMAX * GMAX], cs[2 * GMAX], ds[GMAX];
+    __shared__ int rank_s, zero_s;
+    const int m = R->m, ne = (m + 1) * (m + 2);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e = wv; e < ne; e += FBLOCK / 64) {
+        const double acc = wave_row_sum(partials + (size_t)e * nblk, nblk);
+        if (lane == 0) {
+            gs[e] = acc;
+            R->gram[e] = acc;
+        }
     }
-    // normalised matrix G^_ab = s_a s_b tau^2 <k_{a+2}, k_{b+2}>, Cholesky row by row
-    int rank = 0;
-    for (int a = 0; a < m; ++a) {
-        if (s[a] == 0.0) break;
-        for (int b = 0; b <= a; ++b) {
-            c128 g = Gc(a + 2, b + 2);
-            double gr = s[a] * s[b] * tau * tau * g.re, gi = s[a] * s[b] * tau * tau * g.im;
-            for (int q = 0; q < b; ++q) {  // - L_aq conj(L_bq)
-                const double lr = R->Lf[2 * (a * GMAX + q)], li = R->Lf[2 * (a * GMAX + q) + 1];
-                const double mr = R->Lf[2 * (b * GMAX + q)], mi = R->Lf[2 * (b * GMAX + q) + 1];
-                gr -= lr * mr + li * mi;
-                gi -= li * mr - lr * mi;
+    for (int q = threadIdx.x; q < 2 * GMAX * GMAX; q += FBLOCK) Lf[q] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        auto Gc = [&](int i, int j) -> c128 {  // <k_i, k_j>, 1-based
+            if (i <= j) return c128{gs[gram_off(i, j)], gs[gram_off(i, j) + 1]};
+            return c128{gs[gram_off(j, i)], -gs[gram_off(j, i) + 1]};
+        };
+        for (int a = 0; a < 2 * GMAX; ++a) cs[a] = 0.0;
+        for (int a = 0; a < GMAX; ++a) ds[a] = 0.0;
+        const double b2 = Gc(1, 1).re;
+        const int zero = !(b2 > 0.0) || !isfinite(b2);
+        int rank = 0;
+        if (!zero) {
+            double sc[GMAX];
+            for (int a = 0; a < m; ++a) {
+                const double dg = tau * tau * Gc(a + 2, a + 2).re;
+                sc[a] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
+                ds[a] = sc[a];
             }
-            if (b < a) {
-                const double d = R->Lf[2 * (b * GMAX + b)];
-                R->Lf[2 * (a * GMAX + b)] = gr / d;
-                R->Lf[2 * (a * GMAX + b) + 1] = gi / d;
-            } else {
-                if (!(gr > 1e-14)) goto done;
-                R->Lf[2 * (a * GMAX + a)] = sqrt(gr);
-                R->Lf[2 * (a * GMAX + a) + 1] = 0.0;
+            // normalised matrix G^_ab = s_a s_b tau^2 <k_{a+2}, k_{b+2}>, Cholesky row by row
+            for (int a = 0; a < m; ++a) {
+                if (sc[a] == 0.0) break;
+                bool ok = true;
+                for (int b = 0; b <= a; ++b) {
+                    const c128 g = Gc(a + 2, b + 2);
+                    double gr = sc[a] * sc[b] * tau * tau * g.re, gi = sc[a] * sc[b] * tau * tau * g.im;
+                    for (int q = 0; q < b; ++q) {  // - L_aq conj(L_bq)
+                        const double lr = Lf[2 * (a * GMAX + q)], li = Lf[2 * (a * GMAX + q) + 1];
+                        const double mr = Lf[2 * (b * GMAX + q)], mi = Lf[2 * (b * GMAX + q) + 1];
+                        gr -= lr * mr + li * mi;
+                        gi -= li * mr - lr * mi;
+                    }
+                    if (b < a) {
+                        const double d = Lf[2 * (b * GMAX + b)];
+                        Lf[2 * (a * GMAX + b)] = gr / d;
+                        Lf[2 * (a * GMAX + b) + 1] = gi / d;
+                    } else if (!(gr > 1e-14)) {
+                        ok = false;
+                    } else {
+                        Lf[2 * (a * GMAX + a)] = sqrt(gr);
+                        Lf[2 * (a * GMAX + a) + 1] = 0.0;
+                    }
+                }
+                if (!ok) break;
+                rank = a + 1;
+            }
+            // rhs_a = s_a tau <k_{a+2}, k_1>;  L L^H y = rhs;  c_a = s_a y_a
+            double yr[GMAX], yi[GMAX];
+            for (int a = 0; a < rank; ++a) {
+                const c128 g = Gc(a + 2, 1);
+                double rr = sc[a] * tau * g.re, ri = sc[a] * tau * g.im;
+                for (int q = 0; q < a; ++q) {
+                    const double lr = Lf[2 * (a * GMAX + q)], li = Lf[2 * (a * GMAX + q) + 1];
+                    rr -= lr * yr[q] - li * yi[q];
+                    ri -= lr * yi[q] + li * yr[q];
+                }
+                const double d = Lf[2 * (a * GMAX + a)];
+                yr[a] = rr / d;
+                yi[a] = ri / d;
+            }
+            for (int a = rank - 1; a >= 0; --a) {
+                double rr = yr[a], ri = yi[a];
+                for (int q = a + 1; q < rank; ++q) {  // - conj(L_qa) y_q
+                    const double lr = Lf[2 * (q * GMAX + a)], li = Lf[2 * (q * GMAX + a) + 1];
+                    rr -= lr * yr[q] + li * yi[q];
+                    ri -= lr * yi[q] - li * yr[q];
+                }
+                const double d = Lf[2 * (a * GMAX + a)];
+                yr[a] = rr / d;
+                yi[a] = ri / d;
+            }
+            for (int a = 0; a < rank; ++a) {
+                cs[2 * a] = sc[a] * yr[a];
+                cs[2 * a + 1] = sc[a] * yi[a];
             }
         }
-        rank = a + 1;
+        rank_s = rank;
+        zero_s = zero;
     }
-done:
-    R->rank = rank;
-    {
-        // rhs_a = s_a tau <k_{a+2}, k_1>;  L L^H y = rhs;  c_a = s_a y_a
-        double yr[GMAX], yi[GMAX];
-        for (int a = 0; a < rank; ++a) {
-            c128 g = Gc(a + 2, 1);
-            double rr = s[a] * tau * g.re, ri = s[a] * tau * g.im;
-            for (int q = 0; q < a; ++q) {
-                const double lr = R->Lf[2 * (a * GMAX + q)], li = R->Lf[2 * (a * GMAX + q) + 1];
-                rr -= lr * yr[q] - li * yi[q];
-                ri -= lr * yi[q] + li * yr[q];
-            }
-            const double d = R->Lf[2 * (a * GMAX + a)];
-            yr[a] = rr / d;
-            yi[a] = ri / d;
-        }
-        for (int a = rank - 1; a >= 0; --a) {
-            double rr = yr[a], ri = yi[a];
-            for (int q = a + 1; q < rank; ++q) {  // - conj(L_qa) y_q
-                const double lr = R->Lf[2 * (q * GMAX + a)], li = R->Lf[2 * (q * GMAX + a) + 1];
-                rr -= lr * yr[q] + li * yi[q];
-                ri -= lr * yi[q] - li * yr[q];
-            }
-            const double d = R->Lf[2 * (a * GMAX + a)];
-            yr[a] = rr / d;
-            yi[a] = ri / d;
-        }
-        for (int a = 0; a < rank; ++a) {
-            R->c[2 * a] = s[a] * yr[a];
-            R->c[2 * a + 1] = s[a] * yi[a];
-        }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * GMAX * GMAX; q += FBLOCK) R->Lf[q] = Lf[q];
+    for (int q = threadIdx.x; q < 2 * GMAX; q += FBLOCK) {
+        R->c[q] = cs[q];
+        R->z[q] = 0.0;
+    }
+    for (int q = threadIdx.x; q < GMAX; q += FBLOCK) R->dsc[q] = ds[q];
+    if (threadIdx.x == 0) {
+        R->rank = rank_s;
+        R->zero = zero_s;
     }
 }
 
@@ -528,80 +586,102 @@ __global__ __launch_bounds__(BLOCK) void k_ga_dots(size_t N, VecSet<T> Kv, int m
     reduce_store<2 * GMAX>(acc, 2 * m, partials);
 }
 
+// cbar = <k_j, xbar> summed from the per-block partials of k_ga_dots (one wavefront per
+// entry, fixed order) into R->cbar, then (one thread, on LDS copies of the record)
 // z = (W^H W)^{-1} cbar and the coefficients of kbar_1..kbar_{m+1} over (xbar, k_1..k_{m+1}):
 //   rho = r0 - W c = k_1 - tau sum c_j k_{j+1},   Wz = tau sum z_j k_{j+1},
 //   kbar_1 = conj(c_1) xbar + Wz,
 //   kbar_{j+1} = [j < m] conj(c_{j+1}) xbar + tau (conj(z_j) rho - conj(c_j) Wz),  j = 1..m
 // (differential of the normal equations: dc = (W^H W)^{-1} (dW^H rho + W^H (dr0 - dW c))).
-__global__ void k_ga_prep(GRec* __restrict__ R, double tau) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int m = R->m, rank = R->rank;
-    for (int q = 0; q < 2 * (GMAX + 1) * (GMAX + 2); ++q) R->coef[q] = 0.0;
-    R->one[0] = 1.0;
-    R->one[1] = 0.0;
-    if (R->zero) return;
-    double s[GMAX];
-    for (int a = 0; a < rank; ++a) s[a] = R->dsc[a];
-    double yr[GMAX], yi[GMAX];
-    for (int a = 0; a < rank; ++a) {
-        double rr = s[a] * R->cbar[2 * a], ri = s[a] * R->cbar[2 * a + 1];
-        for (int q = 0; q < a; ++q) {
-            const double lr = R->Lf[2 * (a * GMAX + q)], li = R->Lf[2 * (a * GMAX + q) + 1];
-            rr -= lr * yr[q] - li * yi[q];
-            ri -= lr * yi[q] + li * yr[q];
-        }
-        const double d = R->Lf[2 * (a * GMAX + a)];
-        yr[a] = rr / d;
-        yi[a] = ri / d;
-    }
-    for (int a = rank - 1; a >= 0; --a) {
-        double rr = yr[a], ri = yi[a];
-        for (int q = a + 1; q < rank; ++q) {
-            const double lr = R->Lf[2 * (q * GMAX + a)], li = R->Lf[2 * (q * GMAX + a) + 1];
-            rr -= lr * yr[q] + li * yi[q];
-            ri -= lr * yi[q] - li * yr[q];
-        }
-        const double d = R->Lf[2 * (a * GMAX + a)];
-        yr[a] = rr / d;
-        yi[a] = ri / d;
-    }
-    for (int a = 0; a < 2 * GMAX; ++a) R->z[a] = 0.0;
-    for (int a = 0; a < rank; ++a) {
-        R->z[2 * a] = s[a] * yr[a];
-        R->z[2 * a + 1] = s[a] * yi[a];
-    }
-    // vectors over (xbar, k_1, ..., k_{m+1}) as complex coefficient lists
-    c128 rho[GMAX + 2], wz[GMAX + 2];
-    for (int q = 0; q < m + 2; ++q) rho[q] = wz[q] = c128{0.0, 0.0};
-    rho[1] = c128{1.0, 0.0};
-    for (int j = 1; j <= m; ++j) {
-        rho[j + 1] = c128{-tau * R->c[2 * (j - 1)], -tau * R->c[2 * (j - 1) + 1]};
-        wz[j + 1] = c128{tau * R->z[2 * (j - 1)], tau * R->z[2 * (j - 1) + 1]};
-    }
-    auto row = [&](int r) { return R->coef + r * GCOEF_STRIDE; };
-    // kbar_1
-    {
-        double* o = row(0);
-        o[0] = R->c[0];
-        o[1] = -R->c[1];
-        for (int q = 1; q < m + 2; ++q) {
-            o[2 * q] += wz[q].re;
-            o[2 * q + 1] += wz[q].im;
+// One block of FBLOCK threads.
+__global__ __launch_bounds__(FBLOCK) void k_ga_prep(const double* __restrict__ partials, int nblk,
+                                                    GRec* __restrict__ R, double tau) {
+    constexpr int NC = 2 * (GMAX + 1) * (GMAX + 2);
+    __shared__ double cb[2 * GMAX], Lf[2 * GMAX * GMAX], cs[2 * GMAX], ds[GMAX], zs[2 * GMAX], co[NC];
+    const int m = R->m, rank = R->rank, zero = R->zero;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e = wv; e < 2 * m; e += FBLOCK / 64) {
+        const double acc = wave_row_sum(partials + (size_t)e * nblk, nblk);
+        if (lane == 0) {
+            cb[e] = acc;
+            R->cbar[e] = acc;
         }
     }
-    for (int j = 1; j <= m; ++j) {
-        double* o = row(j);
-        if (j < m) {
-            o[0] = R->c[2 * j];
-            o[1] = -R->c[2 * j + 1];
+    for (int q = threadIdx.x; q < 2 * GMAX * GMAX; q += FBLOCK) Lf[q] = R->Lf[q];
+    for (int q = threadIdx.x; q < 2 * GMAX; q += FBLOCK) {
+        cs[q] = R->c[q];
+        zs[q] = 0.0;
+    }
+    for (int q = threadIdx.x; q < GMAX; q += FBLOCK) ds[q] = R->dsc[q];
+    for (int q = threadIdx.x; q < NC; q += FBLOCK) co[q] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0 && !zero) {
+        double yr[GMAX], yi[GMAX];
+        for (int a = 0; a < rank; ++a) {
+            double rr = ds[a] * cb[2 * a], ri = ds[a] * cb[2 * a + 1];
+            for (int q = 0; q < a; ++q) {
+                const double lr = Lf[2 * (a * GMAX + q)], li = Lf[2 * (a * GMAX + q) + 1];
+                rr -= lr * yr[q] - li * yi[q];
+                ri -= lr * yi[q] + li * yr[q];
+            }
+            const double d = Lf[2 * (a * GMAX + a)];
+            yr[a] = rr / d;
+            yi[a] = ri / d;
         }
-        const c128 zc = c128{tau * R->z[2 * (j - 1)], -tau * R->z[2 * (j - 1) + 1]};   // tau conj(z_j)
-        const c128 cc = c128{tau * R->c[2 * (j - 1)], -tau * R->c[2 * (j - 1) + 1]};   // tau conj(c_j)
-        for (int q = 1; q < m + 2; ++q) {
-            const c128 a = zc * rho[q], b = cc * wz[q];
-            o[2 * q] += a.re - b.re;
-            o[2 * q + 1] += a.im - b.im;
+        for (int a = rank - 1; a >= 0; --a) {
+            double rr = yr[a], ri = yi[a];
+            for (int q = a + 1; q < rank; ++q) {
+                const double lr = Lf[2 * (q * GMAX + a)], li = Lf[2 * (q * GMAX + a) + 1];
+                rr -= lr * yr[q] + li * yi[q];
+                ri -= lr * yi[q] - li * yr[q];
+            }
+            const double d = Lf[2 * (a * GMAX + a)];
+            yr[a] = rr / d;
+            yi[a] = ri / d;
         }
+        for (int a = 0; a < rank; ++a) {
+            zs[2 * a] = ds[a] * yr[a];
+            zs[2 * a + 1] = ds[a] * yi[a];
+        }
+        // vectors over (xbar, k_1, ..., k_{m+1}) as complex coefficient lists
+        c128 rho[GMAX + 2], wz[GMAX + 2];
+        for (int q = 0; q < m + 2; ++q) rho[q] = wz[q] = c128{0.0, 0.0};
+        rho[1] = c128{1.0, 0.0};
+        for (int j = 1; j <= m; ++j) {
+            rho[j + 1] = c128{-tau * cs[2 * (j - 1)], -tau * cs[2 * (j - 1) + 1]};
+            wz[j + 1] = c128{tau * zs[2 * (j - 1)], tau * zs[2 * (j - 1) + 1]};
+        }
+        auto row = [&](int r) { return co + r * GCOEF_STRIDE; };
+        {  // kbar_1
+            double* o = row(0);
+            o[0] = cs[0];
+            o[1] = -cs[1];
+            for (int q = 1; q < m + 2; ++q) {
+                o[2 * q] += wz[q].re;
+                o[2 * q + 1] += wz[q].im;
+            }
+        }
+        for (int j = 1; j <= m; ++j) {
+            double* o = row(j);
+            if (j < m) {
+                o[0] = cs[2 * j];
+                o[1] = -cs[2 * j + 1];
+            }
+            const c128 zc = c128{tau * zs[2 * (j - 1)], -tau * zs[2 * (j - 1) + 1]};  // tau conj(z_j)
+            const c128 cc = c128{tau * cs[2 * (j - 1)], -tau * cs[2 * (j - 1) + 1]};  // tau conj(c_j)
+            for (int q = 1; q < m + 2; ++q) {
+                const c128 a = zc * rho[q], b = cc * wz[q];
+                o[2 * q] += a.re - b.re;
+                o[2 * q + 1] += a.im - b.im;
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NC; q += FBLOCK) R->coef[q] = co[q];
+    for (int q = threadIdx.x; q < 2 * GMAX; q += FBLOCK) R->z[q] = zs[q];
+    if (threadIdx.x == 0) {
+        R->one[0] = 1.0;
+        R->one[1] = 0.0;
     }
 }
 
@@ -620,7 +700,8 @@ __global__ __launch_bounds__(BLOCK) void k_ga_step(AdrGeom A, const T* __restric
     const int n = A.n;
     const size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         cplx<T> v{};
         if (i > 0 && j > 0) {
             for (int q = 0; q < nv; ++q) v = v + mk<T>(cf[2 * q], cf[2 * q + 1]) * V.v[q][p];
@@ -649,7 +730,8 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
         return T(0.25) * prolong_at<T, T>(bcbar, nc, a, b);
     };
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         if (i == 0 || j == 0) continue;
         const cplx<T> t = tq(i, j);
         bbar[p] = bbar[p] + t;
@@ -711,7 +793,8 @@ __global__ __launch_bounds__(BLOCK) void k_phi_adj(int n, int s2, int n2side, do
     };
     (void)h;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         double v = 0.0;
         // along x (rows i >= 1): derivative index q = j-1, j, j+1 and the edge q = n-1
         if (i >= 1) {
@@ -743,7 +826,8 @@ __global__ __launch_bounds__(BLOCK) void k_phi_out(int nf, const double* __restr
     const size_t N = (size_t)nf * nf;
     const int n2 = nf / 2;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / nf), j = (int)(p % nf);
+        int i, j;
+        rowcol(p, nf, i, j);
         double v = 0.0;
         if (!(i & 1) && !(j & 1)) v = phib2[(size_t)(i >> 1) * n2 + (j >> 1)];
         out[p] = TO(v);
@@ -761,7 +845,8 @@ __global__ __launch_bounds__(BLOCK) void k_loss_resid(Geom G, const double* __re
     const size_t N = (size_t)n * n;
     double acc[1] = {0.0};
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         c128 v{};
         if (i > 0 && j > 0) {
             auto U = [&](int a, int b) { return ccast<double>(ldz(u, a, b, n)); };
@@ -784,7 +869,8 @@ __global__ __launch_bounds__(BLOCK) void k_loss_grad(Geom G, const double* __res
     const int n = G.n;
     const size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         cplx<T> v{};
         if (i > 0 && j > 0) v = ccast<T>(-2.0 * applyA_at(G, n2, r, i, j, true));
         gu[p] = v;

@@ -86,7 +86,8 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __rest
     const size_t N = (size_t)n * n;
     const double h = 1.0 / n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         auto P = [&](int a, int b) -> double { return double(phi[(size_t)a * s * nf + (size_t)b * s]); };
         if (car_out) car_out[p] = adr_carrier<T>(P(i, j), k, sigma);
         if (i == 0 || j == 0) {
@@ -107,7 +108,8 @@ __global__ __launch_bounds__(BLOCK) void k_ray_phase(int n, double nbar, double 
                                                      double* __restrict__ phi) {
     const size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p - (size_t)i * n);
+        int i, j;
+        rowcol(p, n, i, j);
         const double x = double(j) / double(n), y = double(i) / double(n);
         phi[p] = __dmul_rn(nbar, __dadd_rn(__dmul_rn(cs, x), __dmul_rn(sn, y)));
     }

@@ -123,7 +123,8 @@ __global__ __launch_bounds__(BLOCK) void k_eik_init(EikSrc E, const double* __re
     const size_t N = (size_t)n * n;
     const double ssrc = s[psrc];
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p - (size_t)i * n);
+        int i, j;
+        rowcol(p, n, i, j);
         t1[p] = eik_r(E, i, j) <= E.rfix ? (s[p] + ssrc) / 2.0 : __builtin_huge_val();
     }
 }
@@ -210,7 +211,8 @@ __global__ __launch_bounds__(BLOCK) void k_eik_phase(EikSrc E, const double* __r
     const int n = E.n;
     const size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p - (size_t)i * n);
+        int i, j;
+        rowcol(p, n, i, j);
         const double v = eik_r(E, i, j) * t1[p];
         phi[p] = v < phi[p] ? v : phi[p];
     }
@@ -243,7 +245,8 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef_fac(Geom G, const double* __
     auto T1 = [&](int a, int b) -> double { return tau1[(size_t)a * s * nf + (size_t)b * s]; };
     auto PHI = [&](int a, int b) -> double { return R(a, b) * T1(a, b); };
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         if (car_out) car_out[p] = adr_carrier<T>(PHI(i, j), k, sigma);
         if (i == 0 || j == 0) {
             px_out[p] = T(0);

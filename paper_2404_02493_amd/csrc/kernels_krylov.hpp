@@ -358,7 +358,8 @@ __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restric
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = T(0);
     for (size_t p = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * E; p < N; p += (size_t)gridDim.x * BLOCK * E) {
-        const int i = (int)(p / n), j0 = (int)(p - (size_t)i * n);
+        int i, j0;
+        rowcol(p, n, i, j0);
         // every basis load is issued before the stencil, so they are all in flight at once
         cplx<T> vv[J + 1][E];
 #pragma unroll

@@ -614,7 +614,8 @@ template <typename T, typename Ti>
 __global__ __launch_bounds__(BLOCK) void k_inject_real(int n, int s, int nf, const Ti* __restrict__ fine, T* __restrict__ out) {
     size_t N = (size_t)n * n;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         out[p] = T(fine[(size_t)i * s * nf + (size_t)j * s]);
     }
 }
@@ -641,7 +642,8 @@ __global__ __launch_bounds__(BLOCK) void k_level_stats(Geom G, const double* __r
     const size_t N = (size_t)n * n;
     double mx = 0.0, mn2 = 0.0, sn2 = 0.0;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        int i = (int)(p / n), j = (int)(p % n);
+        int i, j;
+        rowcol(p, n, i, j);
         if (i == 0 || j == 0) continue;
         double v = n2[p];
         c128 kap = kappa_at<double>(G, v, i, j);

@@ -147,8 +147,11 @@ def main():
         bench = json.loads(f.read().strip().splitlines()[-1])
     roof = bench.get("roofline") or {}
     lines = [f"# {a.title}", "", "Command (from the repository root, MI355X, ROCm 7.2):", "", "```", a.command, "```", ""]
-    lines.append(f"bench.py line of this run: value {bench.get('value')} {bench.get('unit')}, "
-                 f"{bench.get('iterations')} iterations, relres {bench.get('relres')}.")
+    if "value" in bench:
+        lines.append(f"bench.py line of this run: value {bench.get('value')} {bench.get('unit')}, "
+                     f"{bench.get('iterations')} iterations, relres {bench.get('relres')}.")
+    else:
+        lines.append(f"bench.py record of this run: {json.dumps(bench)}")
     lines.append("")
     if roof:
         key = bench_key(roof.get("kernel", ""))
