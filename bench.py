@@ -47,10 +47,63 @@ def cpu_baseline(case, iterations: int, budget_s: float = 30.0):
     w = w - h * v
     _ = cnorm(w)
     t_iter = time.perf_counter() - t0
-    return {"value": t_iter * iterations, "unit": "s", "cores": torch.get_num_threads(), "kind": "oracle",
+    cores = torch.get_num_threads()
+    single = single_thread_oracle()
+    torch.set_num_threads(threads)
+    return {"value": t_iter * iterations, "unit": "s", "cores": cores, "kind": "oracle",
             "sample": f"one FP64 FGMRES iteration (cycle + A z + Arnoldi step) at {case.n}x{case.n}, "
                       f"{t_iter:.2f} s, times {iterations} iterations of the FP64 solve",
-            "sample_seconds": t_iter}
+            "sample_seconds": t_iter, "cpu_model": cpu_model(), "single_thread": single}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def single_thread_oracle():
+    """The oracle on one thread: the whole FP64 FGMRES(20) solve of the 128^2 constant
+    medium (k = 80), and one FGMRES iteration of the 512^2 random medium (k = 320)
+    times the iteration count of its FP64 GPU solve."""
+    import torch
+
+    import helm_inputs as hi
+    from oracle.cycle import Problem, cycle
+    from oracle.grid import apply_A, cdot, cnorm
+    from oracle.solve import fgmres
+    from paper_2404_02493_amd import Helmholtz
+
+    torch.set_num_threads(1)
+    out = {}
+    c1 = hi.make_case("const128", seed=0)
+    P = Problem(c1.velocity, c1.k, c1.levels, damping_cells=c1.damping_cells, phi=c1.phi)
+    t0 = time.perf_counter()
+    _, its, rr, _ = fgmres(P, torch.as_tensor(c1.g), tol=1e-6, maxit=500)
+    out["const128"] = {"seconds": round(time.perf_counter() - t0, 3), "iterations": its, "relres": rr}
+    c2 = hi.make_case("grf512", seed=0)
+    H = Helmholtz(c2.velocity, c2.k, levels=c2.levels, precision="c128", damping_cells=c2.damping_cells)
+    H.set_phase(c2.phi)
+    gd = torch.as_tensor(c2.g).to("cuda:0")
+    _, its2, rr2, _ = H.solve(gd, tol=1e-6, maxit=2000, mode=0)
+    H.close()
+    P2 = Problem(c2.velocity, c2.k, c2.levels, damping_cells=c2.damping_cells, phi=c2.phi)
+    g2 = torch.as_tensor(c2.g)
+    t0 = time.perf_counter()
+    v = g2 / cnorm(g2)
+    z = cycle(P2, v, torch.zeros_like(v))
+    w = apply_A(z, P2.kappa[1], P2.h[1])
+    w = w - cdot(v, w) * v
+    _ = cnorm(w)
+    t_it = time.perf_counter() - t0
+    out["grf512"] = {"seconds_per_iteration": round(t_it, 3), "gpu_fp64_iterations": its2,
+                     "extrapolated_seconds": round(t_it * its2, 1)}
+    return out
 
 
 def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):

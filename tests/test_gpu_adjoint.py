@@ -3,8 +3,9 @@
 The loss is L = ||g - A u_K||^2 with u_0 = 0.  Small problems: the phase and
 weight gradients of the HIP adjoint (helm_cycle_backward) against torch autograd
 through the FP64 oracle (with one checkpoint per cycle).  Full-size 1024^2 problem
-(k = 640, L = 7, K = 10): against central differences of the GPU's own FP64 loss
-along random directions (a property that holds at any size).
+(k = 640, L = 7): one cycle against oracle autograd, and K = 10 against central
+differences of the GPU's own FP64 loss along random directions (a property that holds
+at any size).
 """
 import numpy as np
 import pytest
@@ -144,6 +145,34 @@ def test_loss_matches_oracle():
     ref[0, :] = 0
     ref[:, 0] = 0
     assert (torch.linalg.norm(gu.cpu() - ref) / torch.linalg.norm(ref)).item() < 1e-13
+    H.close()
+
+
+@pytest.fixture(scope="module")
+def oracle_1024():
+    """Oracle autograd of one cycle on the 1024^2, k = 640 workload (about 15 s and 25 GB
+    on the host)."""
+    case = hi.make_case("grf1024", seed=0)
+    P = Problem(case.velocity, case.k, case.levels, damping_cells=case.damping_cells)
+    w = P.weights.numpy().copy()
+    phi = case.phi.astype(np.float64)
+    Lo, dphi, dw = grad_autograd(P, torch.as_tensor(case.g), 1, phi, w)
+    return case, w, phi, Lo, dphi, dw
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_full_size_1024_one_cycle_matches_oracle_autograd(oracle_1024, prec):
+    """The C4 workload at full size (1024^2, k = 640, 7 levels, 8 ADR steps), one cycle
+    from zero: loss, phase gradient and weight gradient against oracle autograd."""
+    case, w, phi, Lo, dphi, dw = oracle_1024
+    H = _helm(case, prec)
+    L, gphi, gw, _ = gpu_grad(H, case.g, phi if prec == "c128" else case.phi, w, 1)
+    tol_phi, tol_w, tol_L = (1e-8, 1e-8, 1e-11) if prec == "c128" else (2e-3, 2e-3, 1e-4)
+    print(f"grf1024 K=1 {prec}: L {L:.6e} vs {Lo:.6e}; phi rel {relerr(gphi, dphi):.2e}; "
+          f"w {np.abs(gw - dw).max() / np.abs(dw).max():.2e}", flush=True)
+    assert abs(L - Lo) <= tol_L * abs(Lo)
+    assert relerr(gphi, dphi) <= tol_phi
+    assert np.abs(gw - dw).max() <= tol_w * np.abs(dw).max()
     H.close()
 
 
