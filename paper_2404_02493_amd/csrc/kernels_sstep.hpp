@@ -86,10 +86,9 @@ __device__ __forceinline__ void st_off(V* __restrict__ a, unsigned p, V v) {
 // Off the unknowns every factor is zero (l included), so M a = 0 there.
 template <typename T>
 struct UpCoef {
-    T gw, ge, gs, gn;      // west (j-1), east (j+1), south (i-1), north (i+1)
-    T ngw, nge, ngs, ngn;  // their negatives
-    T cr, ci, nci;         // C, -Im C
-    T nl;                  // -1/h^2
+    T gw, ge, gs, gn;  // west (j-1), east (j+1), south (i-1), north (i+1)
+    T cr, ci;          // C
+    T nl;              // -1/h^2
 };
 
 // fx, fy, c0 must be zero off the unknowns (ok == false).
@@ -100,30 +99,23 @@ __device__ __forceinline__ UpCoef<T> up_coef(const AdrGeom& A, T fx, T fy, cplx<
     UpCoef<T> k;
     const T l = ok ? T(A.inv_h2) : T(0);
     k.nl = -l;
-    k.ngw = a * (fx + ax);
+    k.gw = -a * (fx + ax);
     k.ge = a * (fx - ax);
-    k.ngs = a * (fy + ay);
+    k.gs = -a * (fy + ay);
     k.gn = a * (fy - ay);
-    k.gw = -k.ngw;
-    k.nge = -k.ge;
-    k.gs = -k.ngs;
-    k.ngn = -k.gn;
     k.cr = c0.re + T(4) * l;
     k.ci = c0.im - a * (T(2) * (ax + ay));
-    k.nci = -k.ci;
     return k;
 }
 
 // One accumulation chain per component, every neighbour value entering through its own
-// multiply-add: in the marching passes the west and east values are lane shifts of the
-// centre, and each shifted operand is then read by multiply-adds alone, which take the
-// lane shift as an operand modifier (no separate move per shifted value).
+// multiply-add (signs as operand modifiers).
 template <typename T>
 __device__ __forceinline__ cplx<T> up_apply(const UpCoef<T>& k, cplx<T> c, cplx<T> w, cplx<T> e, cplx<T> s,
                                             cplx<T> n) {
     T re = k.cr * c.re;
     T im = k.cr * c.im;
-    re = fma(k.nci, c.im, re);
+    re = fma(-k.ci, c.im, re);
     im = fma(k.ci, c.re, im);
     re = fma(k.nl, s.re, re);
     im = fma(k.nl, s.im, im);
@@ -134,13 +126,13 @@ __device__ __forceinline__ cplx<T> up_apply(const UpCoef<T>& k, cplx<T> c, cplx<
     re = fma(k.nl, e.re, re);
     im = fma(k.nl, e.im, im);
     re = fma(k.gs, s.im, re);
-    im = fma(k.ngs, s.re, im);
+    im = fma(-k.gs, s.re, im);
     re = fma(k.gn, n.im, re);
-    im = fma(k.ngn, n.re, im);
+    im = fma(-k.gn, n.re, im);
     re = fma(k.gw, w.im, re);
-    im = fma(k.ngw, w.re, im);
+    im = fma(-k.gw, w.re, im);
     re = fma(k.ge, e.im, re);
-    im = fma(k.nge, e.re, im);
+    im = fma(-k.ge, e.re, im);
     return {re, im};
 }
 
