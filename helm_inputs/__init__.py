@@ -4,9 +4,10 @@ This module is shared by the CPU oracle and by the GPU path; it holds none of
 the solver's arithmetic.  Every generator takes an explicit seed and draws from
 ``numpy.random.Generator(PCG64(seed))``.
 
-Grid convention (both sides): n = 2^m nodes per side, h = 1/n, node (i, j) sits
-at (x, y) = (j h, i h); arrays are n x n, row-major, x fastest.  Row 0 and
-column 0 are the zero Dirichlet ring; the ring at index n is implicit.
+Grid convention (both sides): n = 2^a columns (x) and ny = 2^b rows (y) of nodes
+(ny = n for the square domains), h = 1/max(n, ny), node (i, j) sits at
+(x, y) = (j h, i h); arrays are (ny, n), row-major, x fastest.  Row 0 and column 0
+are the zero Dirichlet ring; the ring at index ny (rows) and n (columns) is implicit.
 
 The paper's workloads use CIFAR-10, OpenFWI and STL-10 derived media, which
 are not available; the media below are synthetic stand-ins of the same kind
@@ -46,11 +47,20 @@ class Case:
     k: float
     levels: int
     damping_cells: int
-    velocity: np.ndarray  # (n, n) float64, c(x) > 0
-    g: np.ndarray  # (n, n) complex128, zero on the boundary ring
-    phi: np.ndarray  # (n, n) float64 or float32
+    velocity: np.ndarray  # (ny, n) float64, c(x) > 0
+    g: np.ndarray  # (ny, n) complex128, zero on the boundary ring
+    phi: np.ndarray  # (ny, n) float64 or float32
     sources: np.ndarray  # (ns, 2) source positions (x, y)
     meta: dict = field(default_factory=dict)
+    ny: int = 0  # rows of nodes; 0: ny = n (square domain)
+
+    @property
+    def rows(self) -> int:
+        return self.ny if self.ny else self.n
+
+    @property
+    def shape(self):
+        return (self.rows, self.n)
 
 
 def default_levels(n: int) -> int:
@@ -62,60 +72,72 @@ def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def gaussian_sources(n: int, xy: np.ndarray, sigma_cells: float = 2.0) -> np.ndarray:
+def gaussian_sources(n: int, xy: np.ndarray, sigma_cells: float = 2.0, ny: int | None = None) -> np.ndarray:
     """Sum of unit-mass Gaussians exp(-|x-x0|^2/(2 s^2)) / (2 pi s^2), s = sigma_cells*h,
     sampled at interior nodes; zero on the boundary ring."""
-    h = 1.0 / n
+    ny = n if ny is None else ny
+    h = 1.0 / max(n, ny)
     s = sigma_cells * h
     x = np.arange(n) * h
-    g = np.zeros((n, n), dtype=np.float64)
+    y = np.arange(ny) * h
+    g = np.zeros((ny, n), dtype=np.float64)
     for x0, y0 in np.atleast_2d(xy):
         gx = np.exp(-((x - x0) ** 2) / (2 * s * s))
-        gy = np.exp(-((x - y0) ** 2) / (2 * s * s))
+        gy = np.exp(-((y - y0) ** 2) / (2 * s * s))
         g += np.outer(gy, gx) / (2 * np.pi * s * s)
     g[0, :] = 0.0
     g[:, 0] = 0.0
     return g.astype(np.complex128)
 
 
-def _source_positions(rng: np.random.Generator, n: int, count: int, margin_cells: int) -> np.ndarray:
-    h = 1.0 / n
-    lo, hi = margin_cells * h, 1.0 - margin_cells * h
+def _source_positions(rng: np.random.Generator, n: int, count: int, margin_cells: int,
+                      ny: int | None = None) -> np.ndarray:
+    ny = n if ny is None else ny
+    h = 1.0 / max(n, ny)
+    if ny == n:
+        lo, hi = margin_cells * h, 1.0 - margin_cells * h
+        return rng.uniform(lo, hi, size=(count, 2))
+    lo = np.array([margin_cells * h, margin_cells * h])
+    hi = np.array([n * h - margin_cells * h, ny * h - margin_cells * h])
     return rng.uniform(lo, hi, size=(count, 2))
 
 
 def grf_velocity(rng: np.random.Generator, n: int, corr_len: float = 0.1,
-                 cmin: float = 1.5, cmax: float = 4.5) -> np.ndarray:
+                 cmin: float = 1.5, cmax: float = 4.5, ny: int | None = None) -> np.ndarray:
     """Gaussian random field with squared-exponential covariance exp(-r^2/(2 l^2)):
-    white noise on a 2n x 2n periodic grid, Gaussian filter of std l/sqrt(2),
-    crop n x n, affine min-max map to [cmin, cmax]."""
-    m = 2 * n
-    h = 1.0 / n
-    xi = rng.standard_normal((m, m))
-    f = np.fft.fftfreq(m, d=h)
+    white noise on a 2ny x 2n periodic grid, Gaussian filter of std l/sqrt(2),
+    crop ny x n, affine min-max map to [cmin, cmax]."""
+    ny = n if ny is None else ny
+    h = 1.0 / max(n, ny)
+    xi = rng.standard_normal((2 * ny, 2 * n))
+    fy = np.fft.fftfreq(2 * ny, d=h)
+    fx = np.fft.fftfreq(2 * n, d=h)
     s = corr_len / np.sqrt(2.0)
-    filt = np.exp(-2.0 * (np.pi ** 2) * (s ** 2) * (f[:, None] ** 2 + f[None, :] ** 2))
-    field_ = np.real(np.fft.ifft2(np.fft.fft2(xi) * filt))[:n, :n]
+    filt = np.exp(-2.0 * (np.pi ** 2) * (s ** 2) * (fy[:, None] ** 2 + fx[None, :] ** 2))
+    field_ = np.real(np.fft.ifft2(np.fft.fft2(xi) * filt))[:ny, :n]
     lo, hi = field_.min(), field_.max()
     return cmin + (cmax - cmin) * (field_ - lo) / (hi - lo)
 
 
 def layered_velocity(rng: np.random.Generator, n: int, nlayers: int = 8, nellipses: int = 20,
                      cmin: float = 1.5, cmax: float = 4.5, contrast: float = 0.3,
-                     smooth: float = 0.0) -> np.ndarray:
+                     smooth: float = 0.0, ny: int | None = None) -> np.ndarray:
     """Horizontal layers (sorted uniform interface depths, per-layer speed
     U[cmin, cmax]) plus elliptical inclusions multiplying the speed by
     (1 +/- contrast), applied in order; then, if smooth > 0, a Gaussian filter of
-    standard deviation ``smooth`` (physical units, nearest-value boundaries)."""
-    h = 1.0 / n
-    depths = np.sort(rng.uniform(0.0, 1.0, size=nlayers - 1))
+    standard deviation ``smooth`` (physical units, nearest-value boundaries).
+    Depths and inclusion centres scale with the extents (n h, ny h) of the domain."""
+    ny = n if ny is None else ny
+    h = 1.0 / max(n, ny)
+    ext_x, ext_y = n * h, ny * h
+    depths = np.sort(rng.uniform(0.0, 1.0, size=nlayers - 1)) * ext_y
     speeds = rng.uniform(cmin, cmax, size=nlayers)
-    y = np.arange(n) * h
+    y = np.arange(ny) * h
     layer = np.searchsorted(depths, y, side="right")
     c = np.repeat(speeds[layer][:, None], n, axis=1)
     X, Y = np.meshgrid(np.arange(n) * h, y)
     for _ in range(nellipses):
-        cx, cy = rng.uniform(0.05, 0.95, size=2)
+        cx, cy = rng.uniform(0.05, 0.95, size=2) * np.array([ext_x, ext_y])
         a, b = rng.uniform(0.02, 0.08, size=2)
         th = rng.uniform(0.0, np.pi)
         sign = 1.0 if rng.uniform() < 0.5 else -1.0
@@ -127,15 +149,16 @@ def layered_velocity(rng: np.random.Generator, n: int, nlayers: int = 8, nellips
     if smooth > 0.0:
         from scipy.ndimage import gaussian_filter
 
-        c = gaussian_filter(c, smooth * n, mode="nearest")
+        c = gaussian_filter(c, smooth / h, mode="nearest")
     return c
 
 
-def analytic_phase(n: int, xy: np.ndarray, slowness: float = 1.0) -> np.ndarray:
+def analytic_phase(n: int, xy: np.ndarray, slowness: float = 1.0, ny: int | None = None) -> np.ndarray:
     """phi = s * min over sources |x - x0| (exact eikonal solution for constant s)."""
-    h = 1.0 / n
-    X, Y = np.meshgrid(np.arange(n) * h, np.arange(n) * h)
-    d = np.full((n, n), np.inf)
+    ny = n if ny is None else ny
+    h = 1.0 / max(n, ny)
+    X, Y = np.meshgrid(np.arange(n) * h, np.arange(ny) * h)
+    d = np.full((ny, n), np.inf)
     for x0, y0 in np.atleast_2d(xy):
         d = np.minimum(d, np.hypot(X - x0, Y - y0))
     return slowness * d
@@ -147,18 +170,19 @@ def _load_fmm():
             f"{_FMM_LIB} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
     lib = ctypes.CDLL(_FMM_LIB)
     lib.fmm_eikonal.restype = ctypes.c_int
-    lib.fmm_eikonal.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
+    lib.fmm_eikonal.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
 def fmm_phase(velocity: np.ndarray, xy: np.ndarray) -> np.ndarray:
     """First-arrival travel time from the sources (first-order fast marching)."""
-    n = velocity.shape[0]
+    ny, n = velocity.shape
     s = np.ascontiguousarray(1.0 / velocity, dtype=np.float64)
     src = np.ascontiguousarray(np.atleast_2d(xy), dtype=np.float64)
-    T = np.empty((n, n), dtype=np.float64)
-    rc = _load_fmm().fmm_eikonal(n, 1.0 / n, s.ctypes.data, src.shape[0], src.ctypes.data, T.ctypes.data)
+    T = np.empty((ny, n), dtype=np.float64)
+    rc = _load_fmm().fmm_eikonal(n, ny, 1.0 / max(n, ny), s.ctypes.data, src.shape[0], src.ctypes.data,
+                                 T.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"fmm_eikonal failed with code {rc}")
     return T
@@ -191,35 +215,38 @@ CONFIGS = {
 
 def sponge_cells(n: int, k: float, cmax: float, minimum: int = 16) -> int:
     """Sponge width in fine cells: one wavelength 2 pi c_max / k at the largest wave
-    speed of the medium (the usual thickness of the damping layer), at least 16."""
+    speed of the medium (the usual thickness of the damping layer), at least 16;
+    n = 1/h, the node count of the longer side."""
     return int(max(minimum, int(np.ceil(2.0 * np.pi * cmax * n / k))))
 
 
 def make_problem(n: int, k: float, levels: int, seed: int, medium: str = "const",
                  nsrc=(1, 1), phase: str = "analytic", damping_cells=None,
-                 name: str = "custom", smooth: float = 0.0) -> Case:
-    """Build one seeded problem.  medium in {const, grf, layered};
-    phase in {analytic, fmm, fmm32}; nsrc = (min, max) number of sources;
-    damping_cells None = one wavelength at the top speed, at least 16."""
+                 name: str = "custom", smooth: float = 0.0, ny: int | None = None) -> Case:
+    """Build one seeded problem on n columns and ny rows of nodes (ny None: square).
+    medium in {const, grf, layered}; phase in {analytic, fmm, fmm32};
+    nsrc = (min, max) number of sources; damping_cells None = one wavelength at the
+    top speed, at least 16."""
+    rows = n if ny is None else ny
     rng = _rng(seed)
     count = int(rng.integers(nsrc[0], nsrc[1] + 1))
     if medium == "const":
-        vel = np.ones((n, n))
+        vel = np.ones((rows, n))
     elif medium == "grf":
-        vel = grf_velocity(rng, n)
+        vel = grf_velocity(rng, n, ny=rows)
     elif medium == "layered":
-        vel = layered_velocity(rng, n, smooth=smooth)
+        vel = layered_velocity(rng, n, smooth=smooth, ny=rows)
     else:
         raise ValueError(medium)
     if damping_cells is None:
-        damping_cells = sponge_cells(n, k, float(vel.max()))
+        damping_cells = sponge_cells(max(n, rows), k, float(vel.max()))
     # sources at least 4 cells inside the sponge-free region
-    xy = _source_positions(rng, n, count, damping_cells + 4)
-    g = gaussian_sources(n, xy)
+    xy = _source_positions(rng, n, count, damping_cells + 4, ny=rows)
+    g = gaussian_sources(n, xy, ny=rows)
     if phase == "analytic":
         if medium != "const":
             raise ValueError("analytic phase needs a constant medium")
-        phi = analytic_phase(n, xy, 1.0 / vel[0, 0])
+        phi = analytic_phase(n, xy, 1.0 / vel[0, 0], ny=rows)
     elif phase in ("fmm", "fmm32"):
         phi = fmm_phase(vel, xy)
         if phase == "fmm32":
@@ -228,7 +255,7 @@ def make_problem(n: int, k: float, levels: int, seed: int, medium: str = "const"
         raise ValueError(phase)
     return Case(name=name, n=n, k=float(k), levels=int(levels), damping_cells=damping_cells,
                 velocity=np.ascontiguousarray(vel, dtype=np.float64), g=g, phi=phi, sources=xy,
-                meta=dict(seed=seed, medium=medium, phase=phase, smooth=smooth))
+                meta=dict(seed=seed, medium=medium, phase=phase, smooth=smooth), ny=0 if rows == n else rows)
 
 
 def make_case(name: str, seed: int = 0) -> Case:

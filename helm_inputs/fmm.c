@@ -1,13 +1,14 @@
 /*
  * First-order fast-marching solver for the eikonal equation |grad T| = s(x)
- * on a uniform n x n node grid with spacing h (Sethian's upwind scheme).
+ * on a uniform grid of nx columns and ny rows of nodes with spacing h (Sethian's upwind
+ * scheme).
  *
  * The phase field that demodulates the level-2 residual is the first-arrival
  * travel time from the source(s) (the paper's eikonal equation for the phase,
  * Section 3.2).  This file only builds that INPUT field; it holds none of the
  * solver's arithmetic.
  *
- * Layout: row-major, index i*n + j with i the y index and j the x index.
+ * Layout: row-major, index i*nx + j with i the y index and j the x index.
  * Seeds: for every source, the 5x5 box of nodes around the node nearest x0 is
  * set to s(x0_node) * |x - x0| (minimum over sources) and frozen.
  * Heap ties are broken by (value, linear index), which makes the result
@@ -91,13 +92,13 @@ static int64_t heap_pop(heap_t *H) {
 }
 
 /* Upwind update at (i,j) from frozen neighbours. */
-static double local_update(const double *T, const unsigned char *frozen, int64_t n,
+static double local_update(const double *T, const unsigned char *frozen, int64_t nx, int64_t ny,
                            int64_t i, int64_t j, double hs) {
     double a = INFINITY, b = INFINITY;
-    if (i > 0 && frozen[(i - 1) * n + j]) a = T[(i - 1) * n + j];
-    if (i + 1 < n && frozen[(i + 1) * n + j] && T[(i + 1) * n + j] < a) a = T[(i + 1) * n + j];
-    if (j > 0 && frozen[i * n + j - 1]) b = T[i * n + j - 1];
-    if (j + 1 < n && frozen[i * n + j + 1] && T[i * n + j + 1] < b) b = T[i * n + j + 1];
+    if (i > 0 && frozen[(i - 1) * nx + j]) a = T[(i - 1) * nx + j];
+    if (i + 1 < ny && frozen[(i + 1) * nx + j] && T[(i + 1) * nx + j] < a) a = T[(i + 1) * nx + j];
+    if (j > 0 && frozen[i * nx + j - 1]) b = T[i * nx + j - 1];
+    if (j + 1 < nx && frozen[i * nx + j + 1] && T[i * nx + j + 1] < b) b = T[i * nx + j + 1];
     double lo = a < b ? a : b, hi = a < b ? b : a;
     if (!isfinite(lo)) return INFINITY;
     if (!isfinite(hi) || hi - lo >= hs) return lo + hs;
@@ -106,10 +107,10 @@ static double local_update(const double *T, const unsigned char *frozen, int64_t
     return 0.5 * (lo + hi + sqrt(2.0 * hs * hs - d * d));
 }
 
-int fmm_eikonal(int64_t n, double h, const double *slowness, int64_t nsrc,
+int fmm_eikonal(int64_t nx, int64_t ny, double h, const double *slowness, int64_t nsrc,
                 const double *src_xy, double *T) {
-    if (n < 4 || h <= 0 || nsrc < 1 || !slowness || !src_xy || !T) return -1;
-    int64_t N = n * n;
+    if (nx < 4 || ny < 4 || h <= 0 || nsrc < 1 || !slowness || !src_xy || !T) return -1;
+    int64_t N = nx * ny;
     unsigned char *frozen = (unsigned char *)calloc((size_t)N, 1);
     heap_t H;
     H.key = (double *)malloc((size_t)N * sizeof(double));
@@ -126,45 +127,45 @@ int fmm_eikonal(int64_t n, double h, const double *slowness, int64_t nsrc,
         double x0 = src_xy[2 * s], y0 = src_xy[2 * s + 1];
         int64_t jc = (int64_t)llround(x0 / h), ic = (int64_t)llround(y0 / h);
         if (jc < 0) jc = 0;
-        if (jc > n - 1) jc = n - 1;
+        if (jc > nx - 1) jc = nx - 1;
         if (ic < 0) ic = 0;
-        if (ic > n - 1) ic = n - 1;
-        double s0 = slowness[ic * n + jc];
+        if (ic > ny - 1) ic = ny - 1;
+        double s0 = slowness[ic * nx + jc];
         for (int64_t di = -2; di <= 2; ++di)
             for (int64_t dj = -2; dj <= 2; ++dj) {
                 int64_t i = ic + di, j = jc + dj;
-                if (i < 0 || j < 0 || i >= n || j >= n) continue;
+                if (i < 0 || j < 0 || i >= ny || j >= nx) continue;
                 double dx = j * h - x0, dy = i * h - y0;
                 double t = s0 * sqrt(dx * dx + dy * dy);
-                if (t < T[i * n + j]) T[i * n + j] = t;
-                frozen[i * n + j] = 1;
+                if (t < T[i * nx + j]) T[i * nx + j] = t;
+                frozen[i * nx + j] = 1;
             }
     }
     /* initial trial band */
     for (int64_t p = 0; p < N; ++p) {
         if (!frozen[p]) continue;
-        int64_t i = p / n, j = p % n;
+        int64_t i = p / nx, j = p % nx;
         const int64_t nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
         for (int q = 0; q < 4; ++q) {
             int64_t a = nb[q][0], b = nb[q][1];
-            if (a < 0 || b < 0 || a >= n || b >= n || frozen[a * n + b]) continue;
-            double t = local_update(T, frozen, n, a, b, h * slowness[a * n + b]);
-            if (t < T[a * n + b]) T[a * n + b] = t;
-            heap_push_or_decrease(&H, a * n + b, T[a * n + b]);
+            if (a < 0 || b < 0 || a >= ny || b >= nx || frozen[a * nx + b]) continue;
+            double t = local_update(T, frozen, nx, ny, a, b, h * slowness[a * nx + b]);
+            if (t < T[a * nx + b]) T[a * nx + b] = t;
+            heap_push_or_decrease(&H, a * nx + b, T[a * nx + b]);
         }
     }
     while (H.size > 0) {
         int64_t p = heap_pop(&H);
         frozen[p] = 1;
-        int64_t i = p / n, j = p % n;
+        int64_t i = p / nx, j = p % nx;
         const int64_t nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
         for (int q = 0; q < 4; ++q) {
             int64_t a = nb[q][0], b = nb[q][1];
-            if (a < 0 || b < 0 || a >= n || b >= n || frozen[a * n + b]) continue;
-            double t = local_update(T, frozen, n, a, b, h * slowness[a * n + b]);
-            if (t < T[a * n + b]) {
-                T[a * n + b] = t;
-                heap_push_or_decrease(&H, a * n + b, t);
+            if (a < 0 || b < 0 || a >= ny || b >= nx || frozen[a * nx + b]) continue;
+            double t = local_update(T, frozen, nx, ny, a, b, h * slowness[a * nx + b]);
+            if (t < T[a * nx + b]) {
+                T[a * nx + b] = t;
+                heap_push_or_decrease(&H, a * nx + b, t);
             }
         }
     }

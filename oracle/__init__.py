@@ -14,6 +14,10 @@ slowness s^2, phi is the paper's phase tau, sigma = +1 selects the carrier
 e^{+i k phi} (sigma = -1 gives the paper's printed signs, which are the complex
 conjugate of every operator).
 
+Grids are n_x columns by n_y rows of nodes (powers of two; square domains have
+n_x = n_y), spacing h = 1/max(n_x, n_y) on both axes, each axis halved per level
+(the non-square domains of Section 4.3.2 use the same method on such grids).
+
 Modules
 -------
 grid      levels, damping, Helmholtz operator, full weighting, bilinear prolongation

@@ -28,16 +28,18 @@ def phase_derivatives(phi: torch.Tensor, h: float):
     Interior (1 <= j <= n-2): central (phi[j+1] - phi[j-1])/(2h) and
     (phi[j+1] - 2 phi[j] + phi[j-1])/h^2.  At the last unknown j = n-1 (the node
     x = 1 is not stored) the one-sided first-order forms (phi[j] - phi[j-1])/h and
-    (phi[j] - 2 phi[j-1] + phi[j-2])/h^2.  Same along y.  Zero on the ring."""
-    n = phi.shape[0]
+    (phi[j] - 2 phi[j-1] + phi[j-2])/h^2.  Same along y (n the node count of the
+    axis).  Zero on the ring."""
 
     def d1(p):  # derivative along the last axis
+        n = p.shape[1]
         out = torch.zeros_like(p)
         out[:, 1:n - 1] = (p[:, 2:n] - p[:, 0:n - 2]) / (2.0 * h)
         out[:, n - 1] = (p[:, n - 1] - p[:, n - 2]) / h
         return out
 
     def d2(p):
+        n = p.shape[1]
         out = torch.zeros_like(p)
         out[:, 1:n - 1] = (p[:, 2:n] - 2.0 * p[:, 1:n - 1] + p[:, 0:n - 2]) / (h * h)
         out[:, n - 1] = (p[:, n - 1] - 2.0 * p[:, n - 2] + p[:, n - 3]) / (h * h)

@@ -3,8 +3,9 @@
 Test infrastructure only (see the package docstring).
 
 Readings of the paper used here (each also listed in the design notes):
-* levels: l = 1 finest ... L coarsest, n_l = n / 2^(l-1); coarse operators are
-  re-discretised with h_l = 2^(l-1)/n and injected n^2 and damping;
+* levels: l = 1 finest ... L coarsest, each axis halves per level; coarse operators are
+  re-discretised with h_l = 2^(l-1) h_1 (h_1 = 1/max(n_x, n_y)) and injected n^2 and
+  damping;
 * smoothers: one damped Jacobi sweep before and after on level 1 (weight w[0]);
   Chebyshev(5) before and after on levels 2 and 4..L-1 (parameter alpha_l = w[l-1]);
   Chebyshev(10) on level L and return; level 3 has no smoothing, following the
@@ -35,7 +36,8 @@ C128 = torch.complex128
 class Problem:
     """Discrete damped Helmholtz problem and the parameters of the Wave-ADR cycle.
 
-    velocity: (n, n) array c(x) > 0 (n^2 = 1/c^2 on the fine grid).
+    velocity: (n_y, n_x) array c(x) > 0 (n^2 = 1/c^2 on the fine grid); n_x and n_y are
+              powers of two, h_1 = 1/max(n_x, n_y) (``n`` below is that maximum).
     weights:  length-L vector, w[0] = Jacobi weight, w[l-1] = Chebyshev alpha_l.
     shift:    relative imaginary shift s0 of the shifted equation (Section 4.3.2).
     cycle_shift: relative imaginary shift added inside the cycle only, so that the cycle
@@ -50,10 +52,12 @@ class Problem:
                  gmres_m: int = 3, gmres_coarse_m: int = 3, level3_literal: bool = False,
                  weights=None, phi=None, adr_levels=3, shift: float = 0.0, cycle_shift: float = 0.0):
         vel = torch.as_tensor(np.asarray(velocity, dtype=np.float64))
-        self.n = int(vel.shape[0])
-        if self.n & (self.n - 1) or self.n < 8:
-            raise ValueError("n must be a power of two >= 8")
-        if not 2 <= levels <= int(np.log2(self.n)) - 1:
+        self.ny, self.nx = int(vel.shape[0]), int(vel.shape[1])
+        for m in (self.nx, self.ny):
+            if m & (m - 1) or m < 8:
+                raise ValueError("grid sides must be powers of two >= 8")
+        self.n = max(self.nx, self.ny)
+        if not 2 <= levels <= int(np.log2(min(self.nx, self.ny))) - 1:
             raise ValueError("bad number of levels")
         self.k = float(k)
         self.L = int(levels)
@@ -73,10 +77,9 @@ class Problem:
         self.n2_fine = 1.0 / (vel * vel)
         self.h, self.n2, self.rho, self.kappa, self.lam = {}, {}, {}, {}, {}
         for l in range(1, self.L + 1):
-            nl = level_size(self.n, l)
-            self.h[l] = 1.0 / nl
+            self.h[l] = float(1 << (l - 1)) / self.n
             self.n2[l] = inject(self.n2_fine, l)
-            self.rho[l] = damping_rho(self.n, l, self.W)
+            self.rho[l] = damping_rho(self.nx, l, self.W, self.ny)
             self.kappa[l] = kappa_level(self.n2[l], self.rho[l], self.k, self.strength, self.sigma,
                                         self.shift + self.cycle_shift)
             self.lam[l] = lambda_gershgorin(self.kappa[l], self.h[l])
@@ -95,8 +98,8 @@ class Problem:
         w = np.zeros(self.L)
         w[0] = default_jacobi_weight(self.k, float(self.n2[1][1:, 1:].max()), self.h[1])
         for l in range(2, self.L + 1):
-            nl = level_size(self.n, l)
-            w[l - 1] = alpha_median_rule(self.k, float(self.n2[l][1:, 1:].mean()), nl, self.lam[l])
+            w[l - 1] = alpha_median_rule(self.k, float(self.n2[l][1:, 1:].mean()), level_size(self.nx, l),
+                                         self.lam[l], level_size(self.ny, l), self.h[l])
         return torch.as_tensor(w, dtype=F64)
 
     def set_weights(self, w):
@@ -130,8 +133,8 @@ class Problem:
             adr[l] = factored_adr_coefficients(inject(t1, l), src, self.n2[l], self.rho[l], self.k, self.strength,
                                                self.sigma, self.h[l], self.shift + self.cycle_shift)
         t2 = inject(t1, 2)
-        x = torch.arange(t2.shape[0], dtype=F64) * self.h[2]
-        Y, X = torch.meshgrid(x, x, indexing="ij")
+        Y, X = torch.meshgrid(torch.arange(t2.shape[0], dtype=F64) * self.h[2],
+                              torch.arange(t2.shape[1], dtype=F64) * self.h[2], indexing="ij")
         phi2 = torch.sqrt((X - src[0]) ** 2 + (Y - src[1]) ** 2) * t2
         arg = (self.sigma * self.k) * phi2
         self.phase_sets = [(adr, torch.complex(torch.cos(arg), torch.sin(arg)),
@@ -151,8 +154,8 @@ class Problem:
         is eq. ADR with phi_m (for n = nbar its reaction term is the damping term alone,
         the paper's ray equation)."""
         nbar = math.sqrt(float(self.n2_fine[1:, 1:].mean()))
-        x = torch.arange(self.n, dtype=F64) / self.n
-        Y, X = torch.meshgrid(x, x, indexing="ij")
+        Y, X = torch.meshgrid(torch.arange(self.ny, dtype=F64) * self.h[1],
+                              torch.arange(self.nx, dtype=F64) * self.h[1], indexing="ij")
         sets = []
         for m in range(count):
             th = 2.0 * math.pi * m / count
@@ -166,8 +169,7 @@ class Problem:
         return apply_A(u, self.kappa_sys if level == 1 else self.kappa[level], self.h[level])
 
     def zeros(self, level: int = 1):
-        nl = level_size(self.n, level)
-        return torch.zeros((nl, nl), dtype=C128)
+        return torch.zeros((level_size(self.ny, level), level_size(self.nx, level)), dtype=C128)
 
 
 def wave_adr_cycle(P: Problem, level: int, g: torch.Tensor, u: torch.Tensor) -> torch.Tensor:

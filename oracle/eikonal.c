@@ -6,8 +6,8 @@
  * tau0 = |x - x0| (the exact solution for unit slowness, eq. eikonal_cons), so
  * that tau1 solves |tau0 grad tau1 + tau1 grad tau0|^2 = s^2 and stays smooth at
  * the source.  The paper does not print a discretisation; the one used here is
- * the first-order upwind (Godunov) form of that equation on the stored n x n
- * nodes (x = j h, y = i h), with grad tau0 exact:
+ * the first-order upwind (Godunov) form of that equation on the stored nodes, nx
+ * columns and ny rows (x = j h, y = i h), with grad tau0 exact:
  *
  *   per axis, the neighbour with the smaller tau = tau0 tau1 is the upwind one q;
  *   with sgn = +1 for the west / south neighbour and -1 for the east / north one,
@@ -32,14 +32,14 @@
  *
  * Every operation is a single IEEE double operation (compile without contraction,
  * -ffp-contract=off), so that another implementation of the same steps can be
- * compared bit for bit.  Layout: row-major, index i n + j.
+ * compared bit for bit.  Layout: row-major, index i nx + j.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 
 typedef struct {
-    int64_t n;
+    int64_t nx, ny;
     double h, xs, ys;
     const double *s;
 } eik_t;
@@ -61,7 +61,7 @@ static int big_root(double A, double B, double C, double *t) {
 
 /* New tau1 at (i, j) from the current values T (tau1), or +inf if no candidate. */
 static double local_update(const eik_t *E, const double *T, int64_t i, int64_t j) {
-    const int64_t n = E->n;
+    const int64_t n = E->nx, ny = E->ny;
     const double h = E->h;
     const double x = (double)j * h, y = (double)i * h;
     const double dx = x - E->xs, dy = y - E->ys;
@@ -83,7 +83,7 @@ static double local_update(const eik_t *E, const double *T, int64_t i, int64_t j
         const double v = node_r(E, i - 1, j) * T[(i - 1) * n + j];
         hy = 1; tqy = v; uy = T[(i - 1) * n + j]; sgy = 1.0;
     }
-    if (i < n - 1 && T[(i + 1) * n + j] < INFINITY) {
+    if (i < ny - 1 && T[(i + 1) * n + j] < INFINITY) {
         const double v = node_r(E, i + 1, j) * T[(i + 1) * n + j];
         if (!hy || v < tqy) { hy = 1; tqy = v; uy = T[(i + 1) * n + j]; sgy = -1.0; }
     }
@@ -109,15 +109,15 @@ static double local_update(const eik_t *E, const double *T, int64_t i, int64_t j
 
 /* Fixed nodes (within sqrt(2) h of the source) and +inf elsewhere; fixed[] may be NULL. */
 static void init_field(const eik_t *E, double *T, unsigned char *fixed) {
-    const int64_t n = E->n;
+    const int64_t n = E->nx, ny = E->ny;
     int64_t in = (int64_t)floor(E->ys / E->h + 0.5), jn = (int64_t)floor(E->xs / E->h + 0.5);
     if (in < 0) in = 0;
-    if (in > n - 1) in = n - 1;
+    if (in > ny - 1) in = ny - 1;
     if (jn < 0) jn = 0;
     if (jn > n - 1) jn = n - 1;
     const double ssrc = E->s[in * n + jn];
     const double rfix = sqrt(2.0) * E->h;
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; i < ny; ++i)
         for (int64_t j = 0; j < n; ++j) {
             const int f = node_r(E, i, j) <= rfix;
             T[i * n + j] = f ? (E->s[i * n + j] + ssrc) / 2.0 : INFINITY;
@@ -125,17 +125,17 @@ static void init_field(const eik_t *E, double *T, unsigned char *fixed) {
         }
 }
 
-static int check(int64_t n, double h, const double *s, double xs, double ys) {
-    if (n < 2 || !(h > 0.0) || !s) return -1;
-    if (!(xs >= 0.0 && xs <= (double)(n - 1) * h && ys >= 0.0 && ys <= (double)(n - 1) * h)) return -1;
+static int check(int64_t nx, int64_t ny, double h, const double *s, double xs, double ys) {
+    if (nx < 2 || ny < 2 || !(h > 0.0) || !s) return -1;
+    if (!(xs >= 0.0 && xs <= (double)(nx - 1) * h && ys >= 0.0 && ys <= (double)(ny - 1) * h)) return -1;
     return 0;
 }
 
-int oracle_eik_sweep(int64_t n, double h, const double *s, double xs, double ys, int32_t max_rounds, double tol,
-                     double *tau1, int32_t *rounds, double *change) {
-    if (check(n, h, s, xs, ys) || !tau1 || max_rounds < 0) return -1;
-    eik_t E = {n, h, xs, ys, s};
-    unsigned char *fixed = (unsigned char *)malloc((size_t)(n * n));
+int oracle_eik_sweep(int64_t n, int64_t ny, double h, const double *s, double xs, double ys, int32_t max_rounds,
+                     double tol, double *tau1, int32_t *rounds, double *change) {
+    if (check(n, ny, h, s, xs, ys) || !tau1 || max_rounds < 0) return -1;
+    eik_t E = {n, ny, h, xs, ys, s};
+    unsigned char *fixed = (unsigned char *)malloc((size_t)(n * ny));
     if (!fixed) return -2;
     init_field(&E, tau1, fixed);
     int32_t done = 0;
@@ -144,8 +144,8 @@ int oracle_eik_sweep(int64_t n, double h, const double *s, double xs, double ys,
         double dmax = 0.0;
         for (int pass = 0; pass < 4; ++pass) {
             const int iup = pass < 2, jup = (pass % 2) == 0;
-            for (int64_t a = 0; a < n; ++a) {
-                const int64_t i = iup ? a : n - 1 - a;
+            for (int64_t a = 0; a < ny; ++a) {
+                const int64_t i = iup ? a : ny - 1 - a;
                 for (int64_t b = 0; b < n; ++b) {
                     const int64_t j = jup ? b : n - 1 - b;
                     if (fixed[i * n + j]) continue;

@@ -51,45 +51,45 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         dp = ctypes.c_void_p
         lib.oracle_eik_sweep.restype = ctypes.c_int
-        lib.oracle_eik_sweep.argtypes = [ctypes.c_int64, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double,
+        lib.oracle_eik_sweep.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int32, ctypes.c_double, dp, dp, dp]
         _lib = lib
     return _lib
 
 
 def eikonal_sweep(slowness: np.ndarray, src, h: float, max_rounds: int = 100, tol: float = 0.0):
-    """tau1 on the n x n nodes by fast sweeping; returns (tau1, rounds, last change)."""
+    """tau1 on the (rows, columns) nodes of ``slowness`` by fast sweeping; returns
+    (tau1, rounds, last change)."""
     s = np.ascontiguousarray(slowness, dtype=np.float64)
-    n = s.shape[0]
-    t = np.empty((n, n), dtype=np.float64)
+    ny, n = s.shape
+    t = np.empty((ny, n), dtype=np.float64)
     rounds = ctypes.c_int32(0)
     change = ctypes.c_double(0.0)
-    rc = _load().oracle_eik_sweep(n, h, s.ctypes.data, float(src[0]), float(src[1]), int(max_rounds), float(tol),
+    rc = _load().oracle_eik_sweep(n, ny, h, s.ctypes.data, float(src[0]), float(src[1]), int(max_rounds), float(tol),
                                   t.ctypes.data, ctypes.addressof(rounds), ctypes.addressof(change))
     if rc != 0:
         raise ValueError(f"oracle_eik_sweep failed ({rc})")
     return t, int(rounds.value), float(change.value)
 
 
-def tau0(n: int, h: float, src) -> np.ndarray:
-    """|x - x0| at the nodes (x = j h, y = i h)."""
-    x = np.arange(n) * h
-    X, Y = np.meshgrid(x, x)
+def tau0(n: int, h: float, src, ny: int | None = None) -> np.ndarray:
+    """|x - x0| at the nodes (x = j h, y = i h) of n columns and ny rows (ny = n by default)."""
+    ny = n if ny is None else ny
+    X, Y = np.meshgrid(np.arange(n) * h, np.arange(ny) * h)
     return np.sqrt((X - src[0]) ** 2 + (Y - src[1]) ** 2)
 
 
 def factored_phase(tau1: np.ndarray, src, h: float) -> np.ndarray:
     """tau = tau0 tau1."""
-    return tau0(tau1.shape[0], h, src) * tau1
+    return tau0(tau1.shape[1], h, src, tau1.shape[0]) * tau1
 
 
 def factored_derivatives(tau1_l: torch.Tensor, src, h: float):
     """phi_x, phi_y and Lap phi at the unknowns of one level from tau1 on that level
     (injected) by the product rule, zero on the ring (same layout as
     ``phase_derivatives``)."""
-    n = tau1_l.shape[0]
-    x = torch.arange(n, dtype=F64) * h
-    Y, X = torch.meshgrid(x, x, indexing="ij")
+    Y, X = torch.meshgrid(torch.arange(tau1_l.shape[0], dtype=F64) * h,
+                          torch.arange(tau1_l.shape[1], dtype=F64) * h, indexing="ij")
     dx, dy = X - src[0], Y - src[1]
     r = torch.sqrt(dx * dx + dy * dy)
     near = r < h

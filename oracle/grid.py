@@ -2,10 +2,13 @@
 
 Test infrastructure only (see the package docstring).
 
-Grid: level l has n_l = n / 2^(l-1) stored nodes per side and h_l = 1/n_l.
-Stored node (i, j) is at (x, y) = (j h_l, i h_l); unknowns are 1 <= i, j <= n_l - 1,
-the ring i or j in {0, n_l} is a zero Dirichlet boundary (index n_l is not
-stored).  Coarse node (I, J) coincides with fine node (2I, 2J).
+Grid: the fine grid has n_x = 2^a columns and n_y = 2^b rows of stored nodes (square
+domains: n_x = n_y = n), spacing h_1 = 1/max(n_x, n_y) in both directions, so the longer
+side of the domain has unit length.  Level l has n_x/2^(l-1) x n_y/2^(l-1) stored nodes
+and h_l = 2^(l-1) h_1.  Stored node (i, j) is at (x, y) = (j h_l, i h_l); unknowns are
+1 <= i <= n_y,l - 1 and 1 <= j <= n_x,l - 1, the ring i in {0, n_y,l} or j in {0, n_x,l}
+is a zero Dirichlet boundary (the last index of each axis is not stored).  Arrays are
+(rows, columns) = (n_y,l, n_x,l).  Coarse node (I, J) coincides with fine node (2I, 2J).
 """
 from __future__ import annotations
 
@@ -26,18 +29,23 @@ def inject(fine: torch.Tensor, level: int) -> torch.Tensor:
     return fine[::s, ::s].clone()
 
 
-def damping_rho(n: int, level: int, cells: int) -> torch.Tensor:
-    """Sponge ramp rho in [0, 1] at the nodes of level l.
+def damping_rho(n: int, level: int, cells: int, ny: int | None = None) -> torch.Tensor:
+    """Sponge ramp rho in [0, 1] at the nodes of level l of a fine grid with n columns
+    and ny rows (ny = n by default).
 
     The damping mask grows from 0 inside the domain to its full value at the
     boundary over a layer of ``cells`` fine cells (Section 2, the damped
-    equation).  Reading: linear ramp r(t) = max(0, 1 - min(t, n - t)/W) in fine
-    index units per axis, combined by max over the two axes, injected to coarse
-    levels."""
-    nl = level_size(n, level)
-    t = torch.arange(nl, dtype=F64) * (n // nl)
-    r = torch.clamp(1.0 - torch.minimum(t, n - t) / cells, min=0.0)
-    return torch.maximum(r[:, None], r[None, :])
+    equation).  Reading: linear ramp r(t) = max(0, 1 - min(t, N - t)/W) in fine
+    index units along each axis (N the fine node count of that axis), combined by
+    max over the two axes, injected to coarse levels."""
+    ny = n if ny is None else ny
+
+    def ramp(nf):
+        nl = level_size(nf, level)
+        t = torch.arange(nl, dtype=F64) * (nf // nl)
+        return torch.clamp(1.0 - torch.minimum(t, nf - t) / cells, min=0.0)
+
+    return torch.maximum(ramp(ny)[:, None], ramp(n)[None, :])
 
 
 def kappa_level(n2_l: torch.Tensor, rho_l: torch.Tensor, k: float, strength: float,
@@ -90,16 +98,15 @@ def restrict_fw(r: torch.Tensor) -> torch.Tensor:
     """Full weighting (1/16)[1 2 1; 2 4 2; 1 2 1] at stride 2 (Section 3.1.2, Section 3.3).
 
     r_c(I, J) = (1/16)[4 r(2I,2J) + 2 (r(2I+-1,2J) + r(2I,2J+-1)) + sum r(2I+-1,2J+-1)]
-    for 1 <= I, J <= n_c - 1; zero on the coarse ring."""
-    n = r.shape[0]
-    nc = n // 2
-    ev = slice(2, n, 2)       # fine rows/cols 2I,   I = 1..nc-1
-    lo = slice(1, n - 1, 2)   # fine rows/cols 2I-1
-    hi = slice(3, n, 2)       # fine rows/cols 2I+1
-    c = r[ev, ev]
-    ud = r[lo, ev] + r[hi, ev] + r[ev, lo] + r[ev, hi]
-    dg = r[lo, lo] + r[lo, hi] + r[hi, lo] + r[hi, hi]
-    out = torch.zeros((nc, nc), dtype=r.dtype)
+    at the coarse unknowns; zero on the coarse ring.  Each axis halves."""
+    ny, nx = r.shape
+    eyi, exj = slice(2, ny, 2), slice(2, nx, 2)          # fine rows/cols 2I, 2J
+    lyi, lxj = slice(1, ny - 1, 2), slice(1, nx - 1, 2)  # 2I-1, 2J-1
+    hyi, hxj = slice(3, ny, 2), slice(3, nx, 2)          # 2I+1, 2J+1
+    c = r[eyi, exj]
+    ud = r[lyi, exj] + r[hyi, exj] + r[eyi, lxj] + r[eyi, hxj]
+    dg = r[lyi, lxj] + r[lyi, hxj] + r[hyi, lxj] + r[hyi, hxj]
+    out = torch.zeros((ny // 2, nx // 2), dtype=r.dtype)
     out[1:, 1:] = (4.0 * c + 2.0 * ud + dg) / 16.0
     return out
 
@@ -109,18 +116,18 @@ def prolong_bilinear(ec: torch.Tensor) -> torch.Tensor:
     (1/4)[1 2 1; 2 4 2; 1 2 1] (Section 3.3); equals 4 R^T.
 
     Even-even fine nodes copy the coarse value, edge midpoints average 2 coarse
-    neighbours, cell centres average 4.  Coarse ring values are zero."""
-    nc = ec.shape[0]
-    n = 2 * nc
-    ep = torch.zeros((nc + 1, nc + 1), dtype=ec.dtype)
-    ep[:nc, :nc] = ec
+    neighbours, cell centres average 4.  Coarse ring values are zero.  Each axis
+    doubles."""
+    ncy, ncx = ec.shape
+    ep = torch.zeros((ncy + 1, ncx + 1), dtype=ec.dtype)
+    ep[:ncy, :ncx] = ec
     ep[0, :] = 0.0
     ep[:, 0] = 0.0
-    a = ep[:nc, :nc]
-    b = ep[1:, :nc]  # (I+1, J)
-    c = ep[:nc, 1:]  # (I, J+1)
+    a = ep[:ncy, :ncx]
+    b = ep[1:, :ncx]  # (I+1, J)
+    c = ep[:ncy, 1:]  # (I, J+1)
     d = ep[1:, 1:]  # (I+1, J+1)
-    out = torch.zeros((n, n), dtype=ec.dtype)
+    out = torch.zeros((2 * ncy, 2 * ncx), dtype=ec.dtype)
     out[0::2, 0::2] = a
     out[1::2, 0::2] = 0.5 * (a + b)
     out[0::2, 1::2] = 0.5 * (a + c)

@@ -76,15 +76,19 @@ def alpha_median_rule_1d(k: float, N: int) -> float:
     return float(l2.max() / np.median(l2))
 
 
-def alpha_median_rule(k: float, n2mean: float, nl: int, lam_bound: float) -> float:
-    """2-D default for the Chebyshev parameter on a level with n_l nodes per side:
-    alpha = lam_bound / median |sigma_ab|^2 where sigma_ab = (4/h^2)(sin^2(pi a h/2)
-    + sin^2(pi b h/2)) - k^2 n2mean over the Dirichlet sine modes 1 <= a, b < n_l,
-    so that the lower end lam_bound/alpha of the interval sits at the median of
-    the spectrum of A^*A (the paper's criterion for alpha, Section 3.1.1).
+def alpha_median_rule(k: float, n2mean: float, nl: int, lam_bound: float, nly: int | None = None,
+                      h: float | None = None) -> float:
+    """2-D default for the Chebyshev parameter on a level with n_l columns and nly rows
+    of nodes (nly = n_l by default) and spacing h (1/max(n_l, nly) by default):
+    alpha = lam_bound / median |sigma_ab|^2 where sigma_ab = (4/h^2)(sin^2(pi a/(2 n_l))
+    + sin^2(pi b/(2 nly))) - k^2 n2mean over the Dirichlet sine modes 1 <= a < n_l,
+    1 <= b < nly, so that the lower end lam_bound/alpha of the interval sits at the
+    median of the spectrum of A^*A (the paper's criterion for alpha, Section 3.1.1).
     ``lam_bound`` is the Gershgorin bound actually used as the upper end."""
-    h = 1.0 / nl
-    s = np.sin(np.arange(1, nl) * math.pi * h / 2.0) ** 2
-    sig = 4.0 / (h * h) * (s[:, None] + s[None, :]) - k * k * n2mean
+    nly = nl if nly is None else nly
+    h = 1.0 / max(nl, nly) if h is None else h
+    sx = np.sin(np.arange(1, nl) * math.pi / (2.0 * nl)) ** 2
+    sy = np.sin(np.arange(1, nly) * math.pi / (2.0 * nly)) ** 2
+    sig = 4.0 / (h * h) * (sy[:, None] + sx[None, :]) - k * k * n2mean
     med = float(np.median((sig * sig).ravel()))
     return max(1.0, lam_bound / med)
