@@ -3,7 +3,8 @@
  *
  * Problem (paper Section 2, the damped equation and its 5-point discretisation):
  *     A u = -Delta_h u - kappa u = g,  kappa = k^2 n(x)^2 (1 + i sigma (delta(x) + s0)),
- * on the unit square with zero Dirichlet values on the outer ring, where
+ * on a rectangle (the unit square by default; Section 4.3.2 runs the method on
+ * non-square domains too) with zero Dirichlet values on the outer ring, where
  * n = 1/c is the slowness, k the angular frequency (the paper's omega) and
  * delta = damping_strength * rho^2 the sponge profile (rho ramps linearly from 0
  * to 1 over damping_cells fine cells towards the boundary, max over the axes).
@@ -11,8 +12,10 @@
  * sign convention (the complex conjugate of every operator).  s0 = 0 unless the
  * shifted equation of Section 4.3.2 is asked for (helm_desc.shift).
  *
- * Grid layout (every array argument): n x n nodes, n = 2^m, h = 1/n, row-major,
- * element (i, j) at offset i*n + j, i = y index, j = x index (x fastest).
+ * Grid layout (every array argument): ny rows of n nodes (helm_desc.n columns and
+ * helm_desc.ny rows; ny = n, the square, unless set), both powers of two, spacing
+ * h = 1/max(n, ny) on both axes, row-major, element (i, j) at offset i*n + j,
+ * i = y index, j = x index (x fastest).  Each level halves both sides.
  * Row 0 and column 0 are the Dirichlet ring and must be zero in g and u on
  * entry; the library keeps them zero.  Complex arrays are interleaved
  * (re, im) pairs of float (HELM_C64) or double (HELM_C128), i.e. the memory
@@ -60,8 +63,8 @@ typedef enum { HELM_C64 = 0, HELM_C128 = 1 } helm_prec;
 
 /* Problem and cycle parameters.  Fill with helm_desc_default, then adjust. */
 typedef struct {
-    int32_t n;                /* nodes per side, power of two, 16..8192 */
-    int32_t levels;           /* L, 2..log2(n)-1; the ADR correction needs L >= 3 */
+    int32_t n;                /* nodes per row (x), power of two, 16..8192 */
+    int32_t levels;           /* L, 2..log2(min(n, ny))-1; the ADR correction needs L >= 3 */
     double k;                 /* angular frequency, > 0 */
     int32_t damping_cells;    /* sponge width W in fine cells, >= 1 (default 16) */
     double damping_strength;  /* delta = strength * rho^2 (default 0.5) */
@@ -80,9 +83,9 @@ typedef struct {
     int32_t use_graphs;       /* 1 (default): each cycle is captured once per (g, u) pointer pair as a
                                  HIP graph and replayed; 0: kernels are launched one by one */
     int32_t adr_levels;       /* levels of the ADR V-cycle, from level 2 down (default 3; 0 = all, L - 1) */
-    int32_t tail_n;           /* a coarsest ADR level with at most tail_n nodes per side (and at most
+    int32_t tail_n;           /* a coarsest ADR level with at most tail_n nodes on its longer side (and at most
                                  4096 nodes) runs its GMRES in one workgroup (default 64; 0 = never) */
-    int32_t wave_tail_n;      /* the wave levels >= 3 with at most wave_tail_n nodes per side run in
+    int32_t wave_tail_n;      /* the wave levels >= 3 with at most wave_tail_n nodes on the longer side run in
                                  one workgroup, all of them in a single launch (default 32; 0 = never) */
     double shift;             /* relative imaginary shift s0 >= 0 of the shifted equation (Section 4.3.2,
                                  gamma_0 = s0 k(x)^2 with k(x) = k n(x); the paper's test uses 0.01):
@@ -92,6 +95,10 @@ typedef struct {
                                  system (helm_solve's operator, helm_residual, helm_loss) keeps kappa.
                                  With adr_steps = 0 and 0.5 this is the CSL preconditioner of the
                                  paper's comparison (Section 4.3.1); default 0 */
+    int32_t ny;               /* rows of nodes (y), power of two, 16..8192, at most 16 times and at
+                                 least 1/16 of n; 0 (default) means ny = n.  With ny != n the domain
+                                 is the rectangle [0, n h] x [0, ny h], h = 1/max(n, ny) (the
+                                 non-square domains of Section 4.3.2) */
 } helm_desc;
 
 /* Defaults of every field for an n x n grid at frequency k:
@@ -101,13 +108,13 @@ typedef struct {
 void helm_desc_default(helm_desc* d, int32_t n, double k);
 
 /* Setup phase (paper Figure "cycle": the solver's setup/solve split).
- * velocity: device, n*n doubles, c(x) > 0 (n^2 = 1/c^2 on the fine grid, injected
+ * velocity: device, ny*n doubles, c(x) > 0 (n^2 = 1/c^2 on the fine grid, injected
  * to coarse levels).  Computes per-level spectral bounds and the default
  * weights (helm_get_weights).  On success *out owns every workspace. */
 helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* out, void* stream);
 
 /* Phase field of the ADR correction (the paper's tau, Section 3.2; eq. Rytov).
- * phi: device, n*n, double (phi_is_f64 = 1) or float (0), fine grid.  Builds the
+ * phi: device, ny*n, double (phi_is_f64 = 1) or float (0), fine grid.  Builds the
  * ADR coefficients (phase derivatives, reaction term) on levels 2..L and the
  * level-2 carrier.  Required before helm_cycle when adr_steps > 0. */
 helm_status helm_set_phase(helm_ctx ctx, const void* phi, int32_t phi_is_f64, void* stream);
@@ -139,7 +146,7 @@ helm_status helm_set_rays(helm_ctx ctx, int32_t count, void* stream);
  * 2 grad tau0 . grad tau1 + tau0 Lap tau1, the finite-difference rule of the phase
  * applied to tau1; at level nodes closer than one level spacing to the source, to
  * tau itself); that phase has no adjoint (helm_cycle_backward returns HELM_ESTATE).
- * tau1_out, phi_out (device, n x n doubles, may be NULL): tau1 of the last source
+ * tau1_out, phi_out (device, ny x n doubles, may be NULL): tau1 of the last source
  * and tau.  rounds, change (host, may be NULL): the most rounds run for a source and
  * the largest last-round decrease.  Returns HELM_ENOCONV, leaving the phase
  * unchanged, if a node is still unreached after max_rounds (1..100000).
@@ -158,11 +165,11 @@ helm_status helm_get_weights(helm_ctx ctx, double* w);
 helm_status helm_get_lambdas(helm_ctx ctx, double* lam);
 
 /* One Wave-ADR cycle (paper Algorithm 1) on the fine grid: u <- C(u, g).
- * g, u: device, n*n complex in cycle_prec; u is read and overwritten. */
+ * g, u: device, ny*n complex in cycle_prec; u is read and overwritten. */
 helm_status helm_cycle(helm_ctx ctx, const void* g, void* u, void* stream);
 
 /* Outer solve to ||g - A u|| / ||g|| < tol (paper Section 4.3.1).
- * g, u: device, n*n complex128; u holds the initial guess and receives the result.
+ * g, u: device, ny*n complex128; u holds the initial guess and receives the result.
  * mode 0: FGMRES(restart) in FP64 right-preconditioned by one cycle (cycles in
  *         cycle_prec; cast around the cycle when cycle_prec = HELM_C64).
  * mode 1: FP64 iterative refinement around an FP32 FGMRES(restart) with FP32
@@ -197,15 +204,15 @@ helm_status helm_residual_noalloc(helm_ctx ctx, const void* g, const void* u, vo
 /* Adjoint of K unrolled cycles (Section 3.3: the training loss after K cycles,
  * eq. loss, and its back-propagation; Algorithm 1 reversed).
  *   u_{k+1} = C(u_k, g), k = 0..K-1, from u_0 (device, cycle_prec, NULL = zero).
- *   grad_uK  (device, cycle_prec, n*n complex): the cotangent of u_K in torch's
+ *   grad_uK  (device, cycle_prec, ny*n complex): the cotangent of u_K in torch's
  *            convention for complex tensors, dL/dRe(u_K) + i dL/dIm(u_K).
- *   grad_phi (device, n*n, overwritten): dL/dphi for the fine phase last passed to
+ *   grad_phi (device, ny*n, overwritten): dL/dphi for the fine phase last passed to
  *            helm_set_phase; float for cycle_prec HELM_C64, double for HELM_C128.
  *            The phase enters only through its injection to the ADR levels, so the
  *            entries off the level-2 lattice (odd fine indices) are zero.
  *   grad_w   (device, `levels` doubles, overwritten): dL/dw for the weights of
  *            helm_set_weights (w[0] Jacobi, w[l-1] Chebyshev alpha of level l).
- *   ckpt_ws  device workspace of K*n*n complex elements in cycle_prec for the
+ *   ckpt_ws  device workspace of K*ny*n complex elements in cycle_prec for the
  *            per-cycle checkpoints, or NULL for a library-owned buffer.
  * The call re-runs the K cycles (checkpointing u_0..u_{K-1}), then reverses them
  * one at a time, re-recording each cycle's intermediates on a library-owned tape

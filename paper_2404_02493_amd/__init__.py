@@ -44,7 +44,9 @@ def default_desc(n: int, k: float) -> HelmDesc:
 class Helmholtz:
     """One discrete damped Helmholtz problem on the GPU with its Wave-ADR hierarchy.
 
-    velocity: (n, n) wave speed c(x) > 0 (numpy or torch; copied to the device as float64).
+    velocity: (ny, n) wave speed c(x) > 0 (numpy or torch; copied to the device as float64):
+    n nodes per row (x) and ny rows (y), powers of two; ny != n is a non-square domain
+    with h = 1/max(n, ny).  Every grid argument below has this shape on the fine level.
     precision: "c128" (FP64 cycles) or "c64" (FP32 cycles; the coarsest level stays FP64).
     Remaining keyword arguments set the fields of ``helm_desc``.
     """
@@ -55,8 +57,12 @@ class Helmholtz:
         self.device = torch.device(device)
         vel = torch.as_tensor(np.asarray(velocity) if not isinstance(velocity, torch.Tensor) else velocity)
         vel = vel.to(device=self.device, dtype=torch.float64).contiguous()
-        n = int(vel.shape[0])
+        ny, n = int(vel.shape[0]), int(vel.shape[1])
         d = default_desc(n, k)
+        if ny != n:
+            d.ny = ny
+            lg = int(np.log2(min(n, ny)))
+            d.levels = max(2, min(7, lg - 3))
         if levels is not None:
             d.levels = int(levels)
         d.cycle_prec = HELM_C64 if precision == "c64" else HELM_C128
@@ -66,6 +72,8 @@ class Helmholtz:
             setattr(d, key, val)
         self.desc = d
         self.n = n
+        self.ny = ny
+        self.shape = (ny, n)
         self.levels = int(d.levels)
         self.cdtype = torch.complex64 if d.cycle_prec == HELM_C64 else torch.complex128
         self._ctx = ctypes.c_void_p()
@@ -99,13 +107,14 @@ class Helmholtz:
         """Travel-time phase of the point sources, computed on the device (factored
         eikonal equation, fast sweeping) and installed as the ADR phase; one source
         uses product-rule phase derivatives.  tau1_out / phi_out: optional float64
-        device tensors (n, n).  Returns (rounds, last-round largest decrease)."""
+        device tensors of the grid's shape.  Returns (rounds, last-round largest decrease)."""
         torch = _torch()
         src = np.ascontiguousarray(np.atleast_2d(np.asarray(sources, dtype=np.float64)))
         for t in (tau1_out, phi_out):
-            if t is not None and (t.dtype != torch.float64 or tuple(t.shape) != (self.n, self.n)
+            if t is not None and (t.dtype != torch.float64 or tuple(t.shape) != self.shape
                                   or not t.is_contiguous() or t.device != self.device):
-                raise ValueError("tau1_out / phi_out must be contiguous float64 (n, n) tensors on the context's device")
+                raise ValueError("tau1_out / phi_out must be contiguous float64 tensors of the grid's shape on the "
+                                 "context's device")
         rounds = ctypes.c_int32(0)
         change = ctypes.c_double(0.0)
         check(lib().helm_eikonal(self._ctx, src.ctypes.data, int(src.shape[0]), int(max_rounds), float(tol),
@@ -140,8 +149,8 @@ class Helmholtz:
         dtype = dtype or self.cdtype
         t = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x))
         t = t.to(device=self.device, dtype=dtype).contiguous()
-        if tuple(t.shape) != (self.n, self.n):
-            raise ValueError(f"expected a ({self.n}, {self.n}) grid, got {tuple(t.shape)}")
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"expected a {self.shape} grid, got {tuple(t.shape)}")
         return t
 
     def cycle(self, g, u, stream=None):
@@ -190,11 +199,11 @@ class Helmholtz:
 
     def cycle_backward(self, K: int, g, grad_uK, u0=None, ckpt=None, stream=None):
         """Cotangents of the phase and of the weights for u_K = C^K(u_0, g), given the
-        cotangent of u_K.  Returns (grad_phi (n, n) device tensor, grad_w (levels,)
-        float64 device tensor)."""
+        cotangent of u_K.  Returns (grad_phi device tensor of the grid's shape, grad_w
+        (levels,) float64 device tensor)."""
         torch = _torch()
         pdt = torch.float32 if self.cdtype == torch.complex64 else torch.float64
-        gphi = torch.empty((self.n, self.n), dtype=pdt, device=self.device)
+        gphi = torch.empty(self.shape, dtype=pdt, device=self.device)
         gw = torch.empty((self.levels,), dtype=torch.float64, device=self.device)
         check(lib().helm_cycle_backward(self._ctx, int(K), _ptr(g), _ptr(u0), _ptr(grad_uK), _ptr(gphi), _ptr(gw),
                                         _ptr(ckpt), _stream_ptr(stream)))
@@ -202,7 +211,7 @@ class Helmholtz:
 
     def unrolled(self, phi, w, g, K: int):
         """u_K after K cycles from u_0 = 0 as a differentiable function of the phase phi
-        (n x n tensor) and the weights w (levels float64 tensor); g is a cycle-dtype
+        (tensor of the grid's shape) and the weights w (levels float64 tensor); g is a cycle-dtype
         device grid.  Gradients come from the hand-written adjoint (helm_cycle_backward)."""
         return _Unrolled.apply(phi, w, g, self, int(K))
 
@@ -215,9 +224,9 @@ class Helmholtz:
         """Runs one internal operator (see helm_debug_op in include/helm.h)."""
         torch = _torch()
         lvl = out_shape_level if out_shape_level is not None else level
-        nl = self.n >> (lvl - 1)
         if out is None:
-            out = torch.zeros((nl, nl), dtype=out_dtype or self.cdtype, device=self.device)
+            out = torch.zeros((self.ny >> (lvl - 1), self.n >> (lvl - 1)), dtype=out_dtype or self.cdtype,
+                              device=self.device)
         check(lib().helm_debug_op(self._ctx, int(op), int(level), _ptr(x), _ptr(x2), _ptr(out), _stream_ptr(stream)))
         return out
 
@@ -226,7 +235,8 @@ class Helmholtz:
         torch = _torch()
         d = self.desc
         name = torch.cuda.get_device_name(self.device)
-        return (f"{name}|n={self.n}|L={self.levels}|{'c64' if self.cdtype == torch.complex64 else 'c128'}"
+        size = f"n={self.n}" if self.ny == self.n else f"n={self.n}x{self.ny}"
+        return (f"{name}|{size}|L={self.levels}|{'c64' if self.cdtype == torch.complex64 else 'c128'}"
                 f"|m={d.gmres_m}/{d.gmres_coarse_m}|adr={d.adr_levels}|tail={d.tail_n}|arnoldi={d.gmres_arnoldi}"
                 f"|restart={d.restart}|v4")
 
@@ -288,9 +298,11 @@ class Helmholtz:
 class _Borrowed(Helmholtz):
     """A problem context owned by a batch (not destroyed by this object)."""
 
-    def __init__(self, ctx, n, levels, cdtype, device):
+    def __init__(self, ctx, n, levels, cdtype, device, ny=None):
         self._ctx = ctx
         self.n, self.levels, self.cdtype, self.device = n, levels, cdtype, device
+        self.ny = n if ny is None else ny
+        self.shape = (self.ny, self.n)
 
     def close(self):
         self._ctx = ctypes.c_void_p()
@@ -299,7 +311,7 @@ class _Borrowed(Helmholtz):
 class HelmholtzBatch:
     """Independent problems of mixed sizes solved together (helm_batch_* in include/helm.h).
 
-    problems: list of dicts with keys velocity (n x n), k, and optionally levels, phi,
+    problems: list of dicts with keys velocity ((ny, n), ny = n for the square), k, and optionally levels, phi,
     damping_cells and any other helm_desc field.  lanes: problems in flight at once."""
 
     def __init__(self, problems, precision: str = "c64", lanes: int = 4, device: str = "cuda:0", stream=None):
@@ -311,8 +323,11 @@ class HelmholtzBatch:
         self.sizes = []
         for p, prob in enumerate(problems):
             vel = torch.as_tensor(np.asarray(prob["velocity"], dtype=np.float64)).to(self.device).contiguous()
-            n = int(vel.shape[0])
+            ny, n = int(vel.shape[0]), int(vel.shape[1])
             d = default_desc(n, float(prob["k"]))
+            if ny != n:
+                d.ny = ny
+                d.levels = max(2, min(7, int(np.log2(min(n, ny))) - 3))
             d.cycle_prec = HELM_C64 if precision == "c64" else HELM_C128
             for key, val in prob.items():
                 if key in ("velocity", "k", "phi"):
@@ -328,7 +343,7 @@ class HelmholtzBatch:
             keep += [vel, pt]
             vels.append(vel.data_ptr())
             phis.append(pt.data_ptr() if pt is not None else None)
-            self.sizes.append((n, int(d.levels)))
+            self.sizes.append((n, int(d.levels), ny))
         VA = ctypes.c_void_p * len(problems)
         self._b = ctypes.c_void_p()
         check(lib().helm_batch_setup(len(problems), descs, VA(*vels), VA(*phis), 1, int(lanes),
@@ -339,8 +354,8 @@ class HelmholtzBatch:
         """The single-problem view of problem p (for set_weights, cycle, ...)."""
         ctx = ctypes.c_void_p()
         check(lib().helm_batch_get(self._b, int(p), ctypes.byref(ctx)))
-        n, L = self.sizes[p]
-        return _Borrowed(ctx, n, L, self.cdtype, self.device)
+        n, L, ny = self.sizes[p]
+        return _Borrowed(ctx, n, L, self.cdtype, self.device, ny)
 
     def solve(self, gs, us=None, tol: float = 1e-6, maxit: int = 1000, mode: int = 1, stream=None):
         """Solves every problem; gs, us: lists of complex128 device grids.  Returns

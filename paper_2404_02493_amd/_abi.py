@@ -46,6 +46,7 @@ class HelmDesc(ctypes.Structure):
         ("wave_tail_n", ctypes.c_int32),
         ("shift", ctypes.c_double),
         ("cycle_shift", ctypes.c_double),
+        ("ny", ctypes.c_int32),
     ]
 
 

@@ -57,9 +57,9 @@ static int gm_of(helm_ctx c, int l) { return l == c->LA ? c->d.gmres_coarse_m : 
 static void adj_alloc(helm_ctx c, hipStream_t st) {
     AdjState& S = *c->adj;
     if (S.ready) return;
-    const int n = c->d.n, L = c->L;
+    const int L = c->L;
     const bool f64c = !c->f32;
-    const size_t NF = (size_t)n * n;
+    const size_t NF = (size_t)c->d.n * c->d.ny;
     const bool adr_on = c->d.adr_steps > 0 && L >= 3;
     S.M = adr_on ? c->d.adr_steps : 0;
     S.ubuf = dalloc(c, NF * csize(f64c));
@@ -72,7 +72,7 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
     S.lgb.assign(L + 1, nullptr);
     S.cs.assign(L + 1, {});
     for (int l = 2; l <= L; ++l) {
-        const size_t Nl = (size_t)(n >> (l - 1)) * (n >> (l - 1));
+        const size_t Nl = (size_t)lnx(c, l) * lny(c, l);
         const size_t cb = Nl * csize(c->wl[l].f64);
         S.g[l] = dalloc(c, cb);
         if (l < L) S.ub[l] = dalloc(c, cb);
@@ -97,7 +97,7 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
         std::memset(hrec.data(), 0, hrec.size() * sizeof(GRec));
         int ri = 0;
         for (int l = 2; l <= c->LA; ++l) {
-            const size_t Nl = (size_t)(n >> (l - 1)) * (n >> (l - 1));
+            const size_t Nl = (size_t)lnx(c, l) * lny(c, l);
             const size_t cb = Nl * csize(f64c);
             S.axb[l] = dalloc(c, cb);
             S.axb2[l] = dalloc(c, cb);
@@ -125,7 +125,7 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
             }
         }
         HIPCHK(hipMemcpyAsync(recs, hrec.data(), hrec.size() * sizeof(GRec), hipMemcpyHostToDevice, st));
-        const size_t N2 = (size_t)(n / 2) * (n / 2);
+        const size_t N2 = (size_t)lnx(c, 2) * lny(c, 2);
         S.thb = (double*)dalloc(c, N2 * sizeof(double));
         S.phib2 = (double*)dalloc(c, N2 * sizeof(double));
         S.rbar2 = dalloc(c, N2 * csize(f64c));
@@ -165,7 +165,7 @@ struct AdjEngine {
     void rec_cycle(const void* g, const void* u0) {
         WaveLevel& W = c->wl[1];
         const Geom& G = W.G;
-        LAUNCH(c, ((u0 ? 3 : 2) * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(),
+        LAUNCH(c, ((u0 ? 3 : 2) * sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny), (k_jacobi<T>), dim3(tiles_of(G.nx, G.ny)), tile_block(),
                st, G, (const T*)W.n2, (const C*)g, (const C*)u0, (C*)S.uB, (const double*)c->cdev->la);
         E.restrict_down(1, g, S.uB, S.g[2]);
         rec_level(2);
@@ -200,7 +200,7 @@ struct AdjEngine {
     void rec_adr_step(int s) {
         WaveLevel& W = c->wl[2];
         AdrTape& Tp = S.adr[s][2];
-        LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(), st,
+        LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN2(W.nx, W.ny), (k_adr_demod<T>), dim3(tiles_of(W.nx, W.ny)), tile_block(), st,
                W.G, (const T*)W.n2, (const C*)S.g[2], (const C*)W.u, (const C*)c->car2, (C*)Tp.b);
         rec_adrv(s, 2);
         LAUNCH(c, 4 * sizeof(C) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
@@ -216,13 +216,13 @@ struct AdjEngine {
         }
         const int m = gm_of(c, l);
         rec_gmres(l, Tp.b, nullptr, m, Tp.kpre, Tp.rpre, Tp.x1);
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.n)),
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.nx, A.ny)),
                dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)Tp.b,
                (const C*)Tp.x1, (C*)S.adr[s][l + 1].b);
         rec_adrv(s, l + 1);
         copy(Tp.x2, Tp.x1, N(l) * sizeof(C));
-        LAUNCH(c, 3 * sizeof(C) * NN(A.n), (k_prolong_add<T, T>), dim3(tiles_of(A.n)), tile_block(), st, A.n,
-               (const C*)S.adr[s][l + 1].xo, (C*)Tp.x2);
+        LAUNCH(c, 3 * sizeof(C) * NN2(A.nx, A.ny), (k_prolong_add<T, T>), dim3(tiles_of(A.nx, A.ny)), tile_block(), st,
+               A.nx, A.ny, (const C*)S.adr[s][l + 1].xo, (C*)Tp.x2);
         rec_gmres(l, Tp.b, Tp.x2, m, Tp.kpost, Tp.rpost, Tp.xo);
     }
 
@@ -267,13 +267,13 @@ struct AdjEngine {
 
     // out (level l+1) = 4 R x (level l): the cotangent of a coarse correction.
     void restrict_adj(int l, const void* x, void* out) {
-        const int n = c->wl[l].n;
+        const int nx = c->wl[l].nx, ny = c->wl[l].ny;
         const size_t nc = N(l + 1);
         auto go = [&](auto tf, auto tc) {
             using Pf = decltype(tf);
             using Pc = decltype(tc);
-            LAUNCH_NB(c, sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * double(nc), (k_restrict_scale<Pf, Pc>),
-                   dim3(fb(nc)), dim3(BLOCK), st, n, (const cplx<Pf>*)x, (cplx<Pc>*)out, 4.0);
+            LAUNCH_NB(c, sizeof(cplx<Pf>) * NN2(nx, ny) + sizeof(cplx<Pc>) * double(nc), (k_restrict_scale<Pf, Pc>),
+                   dim3(fb(nc)), dim3(BLOCK), st, nx, ny, (const cplx<Pf>*)x, (cplx<Pc>*)out, 4.0);
         };
         if (c->wl[l].f64) go(double{}, double{});
         else if (c->wl[l + 1].f64) go(T{}, double{});
@@ -383,10 +383,10 @@ struct AdjEngine {
         }
         rev_gmres(l, Tp.x2, m, Tp.kpost, Tp.rpost, S.axb[l], S.abb[l], true, S.axb2[l]);
         const size_t nc = N(l + 1);
-        LAUNCH_NB(c, sizeof(C) * (double(N(l)) + nc), (k_restrict_scale<T, T>), dim3(fb(nc)), dim3(BLOCK), st, A.n,
-               (const C*)S.axb2[l], (C*)S.axb[l + 1], 4.0);
+        LAUNCH_NB(c, sizeof(C) * (double(N(l)) + nc), (k_restrict_scale<T, T>), dim3(fb(nc)), dim3(BLOCK), st, A.nx,
+               A.ny, (const C*)S.axb2[l], (C*)S.axb[l + 1], 4.0);
         rev_adrv(s, l + 1);
-        LAUNCH_NB(c, (6.0 * sizeof(C) + 2 * sizeof(T) + 32.0 * 2) * NN(A.n), (k_adr_rr_adj<T>), dim3(fb(N(l))),
+        LAUNCH_NB(c, (6.0 * sizeof(C) + 2 * sizeof(T) + 32.0 * 2) * NN2(A.nx, A.ny), (k_adr_rr_adj<T>), dim3(fb(N(l))),
                dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)S.abb[l + 1],
                (const C*)Tp.x1, (C*)S.axb2[l], (C*)S.abb[l], S.pxb[l], S.pyb[l], S.c0b[l]);
         rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb2[l], S.abb[l], false, nullptr);
@@ -439,13 +439,13 @@ struct AdjEngine {
         const size_t NF = N(1);
         if (S.M > 0) {
             for (int l = 2; l <= c->LA; ++l) {
-                const int nl = n >> (l - 1);
-                LAUNCH_NB(c, (2.0 * sizeof(T) + 32.0 + 16.0) * NN(nl), (k_phi_adj<T>), dim3(fb(N(l))), dim3(BLOCK), st, nl,
-                       1 << (l - 2), n / 2, c->d.k, c->d.sign, (const T*)c->al[l].px, (const T*)c->al[l].py,
+                LAUNCH_NB(c, (2.0 * sizeof(T) + 32.0 + 16.0) * double(N(l)), (k_phi_adj<T>), dim3(fb(N(l))), dim3(BLOCK),
+                       st, lnx(c, l), lny(c, l), 1 << (l - 2), n / 2, c->d.k, c->d.sign, (const T*)c->al[l].px,
+                       (const T*)c->al[l].py,
                        (const double*)S.pxb[l], (const double*)S.pyb[l], (const c128*)S.c0b[l],
                        (const double*)(l == 2 ? S.thb : nullptr), S.phib2);
             }
-            LAUNCH_NB(c, (sizeof(TO) + 2.0) * NF, (k_phi_out<TO>), dim3(fb(NF)), dim3(BLOCK), st, n,
+            LAUNCH_NB(c, (sizeof(TO) + 2.0) * NF, (k_phi_out<TO>), dim3(fb(NF)), dim3(BLOCK), st, n, c->d.ny,
                    (const double*)S.phib2, (TO*)grad_phi);
         } else {
             HIPCHK(hipMemsetAsync(grad_phi, 0, NF * sizeof(TO), st));
@@ -460,7 +460,7 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
     if (!c->adj) c->adj = new AdjState();
     adj_alloc(c, st);
     AdjState& S = *c->adj;
-    const size_t NF = (size_t)c->d.n * c->d.n;
+    const size_t NF = (size_t)c->d.n * c->d.ny;
     const size_t vb = NF * sizeof(cplx<T>);
     char* ck = (char*)ckpt_ws;
     if (!ck) {
@@ -477,12 +477,12 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
     HIPCHK(hipMemsetAsync(S.wacc, 0, 64 * sizeof(double), st));
     if (S.M > 0) {
         for (int l = 2; l <= c->LA; ++l) {
-            const size_t Nl = (size_t)(c->d.n >> (l - 1)) * (c->d.n >> (l - 1));
+            const size_t Nl = (size_t)lnx(c, l) * lny(c, l);
             HIPCHK(hipMemsetAsync(S.pxb[l], 0, Nl * sizeof(double), st));
             HIPCHK(hipMemsetAsync(S.pyb[l], 0, Nl * sizeof(double), st));
             HIPCHK(hipMemsetAsync(S.c0b[l], 0, Nl * sizeof(c128), st));
         }
-        const size_t N2 = (size_t)(c->d.n / 2) * (c->d.n / 2);
+        const size_t N2 = (size_t)lnx(c, 2) * lny(c, 2);
         HIPCHK(hipMemsetAsync(S.thb, 0, N2 * sizeof(double), st));
         HIPCHK(hipMemsetAsync(S.phib2, 0, N2 * sizeof(double), st));
     }
@@ -538,7 +538,7 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
 template <typename T>
 static double loss_grad(helm_ctx c, const void* g, const void* u, void* grad_u, hipStream_t st) {
     const Geom G = make_geom_sys(c);
-    const size_t NF = (size_t)G.n * G.n;
+    const size_t NF = (size_t)G.nx * G.ny;
     const int nb = flat_blocks(NF);
     LAUNCH_NB(c, (2.0 * sizeof(cplx<T>) + 8.0 + 16.0) * NF, (k_loss_resid<T>), dim3(nb), dim3(BLOCK), st, G,
            (const double*)c->n2f, (const cplx<T>*)g, (const cplx<T>*)u, (c128*)c->rbuf, c->partials);

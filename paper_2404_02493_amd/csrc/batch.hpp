@@ -3,7 +3,7 @@
 //
 // A native scheduler keeps `lanes` problems in flight: every lane is a host
 // thread that drives its own HIP stream (default priority) and takes the next
-// problem from a shared queue ordered by decreasing n^2 (longest first), so the
+// problem from a shared queue ordered by decreasing node count (longest first), so the
 // small, launch-bound coarse levels of one problem overlap with the kernels of
 // the others.  Every problem runs exactly the kernels and launch shapes of a
 // single helm_solve on its own context, so its result equals the single solve
@@ -71,14 +71,16 @@ static void run_jobs(helm_batch b, int njobs, Job&& job) {
 static std::vector<int> longest_first_desc(const helm_desc* d, int np) {
     std::vector<int> order(np);
     for (int p = 0; p < np; ++p) order[p] = p;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return d[a].n > d[c].n; });
+    auto area = [&](int p) { return (size_t)d[p].n * (d[p].ny ? d[p].ny : d[p].n); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return area(a) > area(c); });
     return order;
 }
 
 static std::vector<int> longest_first(helm_batch b) {
     std::vector<int> order(b->ctx.size());
     for (size_t p = 0; p < order.size(); ++p) order[p] = (int)p;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->ctx[a]->d.n > b->ctx[c]->d.n; });
+    auto area = [&](int p) { return (size_t)b->ctx[p]->d.n * b->ctx[p]->d.ny; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return area(a) > area(c); });
     return order;
 }
 
@@ -155,13 +157,13 @@ static void bset(helm_ctx c0, const std::vector<int>& list, size_t stride, const
 // the refinement solve and the staging of g and u (measured by building it once).
 static size_t class_stride(const helm_desc& d, const double* velocity, hipStream_t st) {
     helm_ctx c = new helm_ctx_s();
-    c->d = d;
+    c->d = desc_normalized(d);
     size_t bytes = 0;
     try {
         build(c, velocity, st);
         ensure_solver_ws(c, 1);
-        c->bg = dalloc(c, (size_t)d.n * d.n * sizeof(c128));
-        c->bu = dalloc(c, (size_t)d.n * d.n * sizeof(c128));
+        c->bg = dalloc(c, (size_t)c->d.n * c->d.ny * sizeof(c128));
+        c->bu = dalloc(c, (size_t)c->d.n * c->d.ny * sizeof(c128));
         bytes = c->count_bytes;
     } catch (...) {
         helm_destroy(c);
@@ -175,14 +177,14 @@ static size_t class_stride(const helm_desc& d, const double* velocity, hipStream
 static helm_ctx class_build(helm_batch_s::Class& K, int q, const helm_desc& d, const double* velocity, const void* phi,
                             int phi_is_f64, hipStream_t st) {
     helm_ctx c = new helm_ctx_s();
-    c->d = d;
+    c->d = desc_normalized(d);
     c->arena = K.arena + (size_t)q * K.stride;
     c->arena_cap = K.stride;
     try {
         build(c, velocity, st);
         ensure_solver_ws(c, 1);
-        c->bg = dalloc(c, (size_t)d.n * d.n * sizeof(c128));
-        c->bu = dalloc(c, (size_t)d.n * d.n * sizeof(c128));
+        c->bg = dalloc(c, (size_t)c->d.n * c->d.ny * sizeof(c128));
+        c->bu = dalloc(c, (size_t)c->d.n * c->d.ny * sizeof(c128));
         REQUIRE(c->count_bytes <= K.stride, "batch class: a problem needs more device memory than its region");
         if (phi) set_phase(c, phi, phi_is_f64, st);
     } catch (...) {
@@ -226,7 +228,7 @@ static void class_fgmres(helm_batch_s::Class& K, helm_ctx c0, const std::vector<
     using Cp = c64;
     const int m = c0->d.restart;
     const Geom G = make_geom_sys(c0);
-    const size_t N = (size_t)G.n * G.n;
+    const size_t N = (size_t)G.nx * G.ny;
     const size_t S = K.stride;
     KrylovScal* Kin = c0->Kin;
     const int nbf = c0->tn.fgmres_blocks > 0 ? std::min(c0->tn.fgmres_blocks, MAXRED) : flat_blocks(N, MAXRED);
@@ -345,9 +347,9 @@ static void class_fgmres(helm_batch_s::Class& K, helm_ctx c0, const std::vector<
 static void class_residual(helm_batch_s::Class& K, helm_ctx c0, const std::vector<int>& list, std::vector<double>& rn,
                            std::vector<double>& gn, hipStream_t st) {
     const Geom G = make_geom_sys(c0);
-    const int nbt = red_blocks(G.n);
+    const int nbt = red_blocks(G.nx, G.ny);
     bset(c0, list, K.stride);
-    LAUNCH(c0, (3 * 16.0 + 8.0 + 16.0) * NN(G.n), k_residual_norms, dim3(nbt), tile_block(), st, G,
+    LAUNCH(c0, (3 * 16.0 + 8.0 + 16.0) * NN2(G.nx, G.ny), k_residual_norms, dim3(nbt), tile_block(), st, G,
            (const double*)c0->n2f, (const c128*)c0->bg, (const c128*)c0->bu, (c128*)c0->fV[0], c0->partials);
     LAUNCH(c0, 16.0 * nbt, (k_finalize_sums<2>), dim3(1), dim3(FBLOCK), st, (const double*)c0->partials, nbt, 2,
            c0->dscal);
@@ -364,7 +366,7 @@ static void class_solve(helm_batch b, helm_batch_s::Class& K, const void* const*
                         hipStream_t st) {
     const int P = (int)K.probs.size();
     helm_ctx c0 = b->ctx[K.probs[0]];
-    const size_t NF = (size_t)c0->d.n * c0->d.n;
+    const size_t NF = (size_t)c0->d.n * c0->d.ny;
     const size_t S = K.stride;
     for (int q = 0; q < P; ++q) {
         const helm_ctx c = b->ctx[K.probs[q]];

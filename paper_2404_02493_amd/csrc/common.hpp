@@ -56,17 +56,20 @@ __host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) {
 using c64 = cplx<float>;
 using c128 = cplx<double>;
 
-// Geometry and coefficients of one level of the hierarchy.
-//   n      nodes per side on this level (h = 1/n)
-//   s      stride of the level in fine-grid indices, 2^(l-1)
-//   nf     fine-grid nodes per side
-//   W      sponge width in fine cells (ramp 1 - d/W evaluated as 1 - d * inv_W)
+// Geometry and coefficients of one level of the hierarchy.  A level has nx columns and
+// ny rows of stored nodes (row-major, index i * nx + j, i the row (y), j the column (x));
+// both are powers of two, equal on square domains.
+//   nx, ny   nodes per row / per column on this level
+//   s        stride of the level in fine-grid indices, 2^(l-1)
+//   nfx, nfy fine-grid nodes per row / per column
+//   W        sponge width in fine cells (ramp 1 - d/W evaluated as 1 - d * inv_W)
+//   inv_h2   1/h^2 of the level (h = 2^(l-1) / max(nfx, nfy))
 //   sig_shift  sigma times the relative shift s0 of the shifted equation
 // kappa(i, j) = k2 * n2(i, j) * (1 + i * (sig_str * rho^2 + sig_shift)), rho from the indices.
 struct Geom {
-    int n;
+    int nx, ny;
     int s;
-    int nf;
+    int nfx, nfy;
     int W;
     double inv_W;    // 1 / W
     double inv_h2;
@@ -84,19 +87,19 @@ __device__ __forceinline__ T sponge_ramp(int t, int nf, T inv_W) {
 
 template <typename T>
 __device__ __forceinline__ cplx<T> kappa_at(const Geom& G, T n2, int i, int j) {
-    T ri = sponge_ramp<T>(i * G.s, G.nf, T(G.inv_W));
-    T rj = sponge_ramp<T>(j * G.s, G.nf, T(G.inv_W));
+    T ri = sponge_ramp<T>(i * G.s, G.nfy, T(G.inv_W));
+    T rj = sponge_ramp<T>(j * G.s, G.nfx, T(G.inv_W));
     T rho = ri > rj ? ri : rj;
     T kr = T(G.k2) * n2;
     return {kr, kr * (T(G.sig_str) * (rho * rho) + T(G.sig_shift))};
 }
 
-// Row and column of the flat index p on a grid of n nodes per side; n is a power of two,
+// Row and column of the flat index p on a grid of nx nodes per row; nx is a power of two,
 // so this is a shift and a mask instead of a 64-bit division.
-__device__ __forceinline__ void rowcol(size_t p, int n, int& i, int& j) {
-    const int sh = __builtin_ctz((unsigned)n);
+__device__ __forceinline__ void rowcol(size_t p, int nx, int& i, int& j) {
+    const int sh = __builtin_ctz((unsigned)nx);
     i = (int)(p >> sh);
-    j = (int)(p & (size_t)(n - 1));
+    j = (int)(p & (size_t)(nx - 1));
 }
 
 // Workgroup b of nb is dispatched to XCD b mod 8 (round robin).  This renumbering gives
@@ -107,11 +110,12 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Load with the implicit zero ring at index n (i, j >= 0 always holds for callers).
+// Load with the implicit zero ring at row ny and column nx (i, j >= 0 always holds for
+// callers).
 template <typename V>
-__device__ __forceinline__ V ldz(const V* __restrict__ a, int i, int j, int n) {
-    if (i >= n || j >= n) return V{};
-    return a[(size_t)i * n + j];
+__device__ __forceinline__ V ldz(const V* __restrict__ a, int i, int j, int nx, int ny) {
+    if (i >= ny || j >= nx) return V{};
+    return a[(size_t)i * nx + j];
 }
 
 // ------------------------------------------------------------------ batched launches

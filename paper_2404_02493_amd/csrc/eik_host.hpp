@@ -10,7 +10,7 @@ static void build_phase_factored(helm_ctx c, const double* tau1, double xs, doub
     for (int l = 2; l <= c->LA; ++l) {
         AdrLevel& A = c->al[l];
         const Geom G = make_geom(c, l);
-        const int nb = flat_blocks((size_t)A.n * A.n);
+        const int nb = flat_blocks((size_t)A.nx * A.ny);
         void* th = (l == 2) ? c->car2 : nullptr;
         if (c->f32)
             hipLaunchKernelGGL((k_adr_coef_fac<float>), dim3(nb), dim3(BLOCK), 0, st, G, (const double*)c->n2f, tau1, xs,
@@ -47,13 +47,15 @@ __global__ __launch_bounds__(BLOCK) void k_eik_fill(size_t N, double v, double* 
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) x[p] = v;
 }
 
+// One round (four passes); a pass is one launch per anti-diagonal d of the Ty x Tx tiles
+// (I + J = d, I < Ty rows, J < Tx columns).
 template <int B>
 static void eik_round(const EikSrc& E, const double* s, double* t1, double* part, hipStream_t st) {
-    const int T = E.n / B;
+    const int Tx = E.nx / B, Ty = E.ny / B;
     for (int pass = 0; pass < 4; ++pass) {
         const int iup = pass < 2 ? 1 : 0, jup = (pass % 2) == 0 ? 1 : 0;
-        for (int d = 0; d <= 2 * T - 2; ++d) {
-            const int lo = d < T ? 0 : d - T + 1, hi = d < T ? d : T - 1;
+        for (int d = 0; d <= Tx + Ty - 2; ++d) {
+            const int lo = std::max(0, d - Tx + 1), hi = std::min(d, Ty - 1);
             hipLaunchKernelGGL((k_eik_pass<B>), dim3(hi - lo + 1), dim3(B), 0, st, E, s, t1, iup, jup, d, part);
         }
     }
@@ -62,25 +64,25 @@ static void eik_round(const EikSrc& E, const double* s, double* t1, double* part
 // Returns HELM_ENOCONV (phase unchanged) if a node is still unreached after max_rounds.
 static helm_status eikonal(helm_ctx c, const double* src, int nsrc, int max_rounds, double tol, void* tau1_out,
                            void* phi_out, int* rounds_out, double* change_out, hipStream_t st) {
-    const int n = c->d.n;
-    const double h = 1.0 / n;
+    const int n = c->d.n, ny = c->d.ny;  // nodes per row, rows
+    const double h = 1.0 / std::max(n, ny);
     REQUIRE(src != nullptr, "helm_eikonal: src_xy is NULL");
     REQUIRE(nsrc >= 1 && nsrc <= 64, "helm_eikonal: nsrc must be in 1..64");
     REQUIRE(max_rounds >= 1 && max_rounds <= 100000, "helm_eikonal: max_rounds must be in 1..100000");
     REQUIRE(!std::isnan(tol), "helm_eikonal: tol is NaN");
     for (int q = 0; q < nsrc; ++q) {
         const double x = src[2 * q], y = src[2 * q + 1];
-        REQUIRE(x >= 0.0 && x <= double(n - 1) * h && y >= 0.0 && y <= double(n - 1) * h,
-                "helm_eikonal: sources must lie in [0, (n-1) h]^2");
+        REQUIRE(x >= 0.0 && x <= double(n - 1) * h && y >= 0.0 && y <= double(ny - 1) * h,
+                "helm_eikonal: sources must lie in [0, (n-1) h] x [0, (ny-1) h]");
     }
-    const size_t NF = (size_t)n * n;
-    const int B = n < 64 ? n : 64;
-    const int T = n / B;
+    const size_t NF = (size_t)n * ny;
+    const int B = std::min(64, std::min(n, ny));  // divides both (powers of two)
+    const size_t NT = (size_t)(n / B) * (ny / B);  // tiles
     EikBufs b;
     HIPCHK(hipMalloc((void**)&b.s, NF * sizeof(double)));
     HIPCHK(hipMalloc((void**)&b.t1, NF * sizeof(double)));
     HIPCHK(hipMalloc((void**)&b.phi, NF * sizeof(double)));
-    HIPCHK(hipMalloc((void**)&b.part, (size_t)T * T * sizeof(double)));
+    HIPCHK(hipMalloc((void**)&b.part, NT * sizeof(double)));
     HIPCHK(hipMalloc((void**)&b.mx, 2 * sizeof(double)));
     HIPCHK(hipHostMalloc((void**)&b.host, 2 * sizeof(double), hipHostMallocDefault));
     hipLaunchKernelGGL(k_eik_slowness, dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, NF, (const double*)c->n2f, b.s);
@@ -89,20 +91,20 @@ static helm_status eikonal(helm_ctx c, const double* src, int nsrc, int max_roun
     int rounds_max = 0;
     double change_max = 0.0;
     for (int q = 0; q < nsrc; ++q) {
-        EikSrc E{n, h, src[2 * q], src[2 * q + 1], std::sqrt(2.0) * h};
+        EikSrc E{n, ny, h, src[2 * q], src[2 * q + 1], std::sqrt(2.0) * h};
         long in = (long)std::floor(E.ys / h + 0.5), jn = (long)std::floor(E.xs / h + 0.5);
-        in = std::min<long>(std::max<long>(in, 0), n - 1);
+        in = std::min<long>(std::max<long>(in, 0), ny - 1);
         jn = std::min<long>(std::max<long>(jn, 0), n - 1);
         hipLaunchKernelGGL(k_eik_init, dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, E, (const double*)b.s,
                            (size_t)in * n + jn, b.t1);
         int done = 0;
         double last = __builtin_huge_val();
         while (done < max_rounds) {
-            hipLaunchKernelGGL(k_eik_fill, dim3(1), dim3(BLOCK), 0, st, (size_t)T * T, 0.0, b.part);
+            hipLaunchKernelGGL(k_eik_fill, dim3(1), dim3(BLOCK), 0, st, NT, 0.0, b.part);
             if (B == 64) eik_round<64>(E, b.s, b.t1, b.part, st);
             else if (B == 32) eik_round<32>(E, b.s, b.t1, b.part, st);
             else eik_round<16>(E, b.s, b.t1, b.part, st);
-            hipLaunchKernelGGL(k_eik_max, dim3(1), dim3(1024), 0, st, (size_t)T * T, (const double*)b.part, b.mx);
+            hipLaunchKernelGGL(k_eik_max, dim3(1), dim3(1024), 0, st, NT, (const double*)b.part, b.mx);
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(b.host, b.mx, sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));

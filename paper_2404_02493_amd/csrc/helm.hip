@@ -48,7 +48,7 @@ struct Error : std::runtime_error {
     } while (0)
 
 struct WaveLevel {
-    int n = 0;
+    int nx = 0, ny = 0;    // nodes per row / per column
     Geom G{};
     bool f64 = false;      // this level computes in FP64
     void* n2 = nullptr;    // real, cycle precision (FP64 on f64 levels)
@@ -63,7 +63,7 @@ struct WaveLevel {
 };
 
 struct AdrLevel {
-    int n = 0;
+    int nx = 0, ny = 0;    // nodes per row / per column
     AdrGeom A{};
     void* px = nullptr;
     void* py = nullptr;
@@ -256,14 +256,23 @@ static inline int flat_blocks(size_t N, int cap = 2048) {
     return (int)std::max<size_t>(1, std::min<size_t>(b, (size_t)cap));
 }
 
+// Nodes per row / per column of level l (the fine grid has d.n x d.ny; setup stores
+// d.ny = d.n for a square grid).
+static inline int lnx(const helm_ctx c, int level) { return c->d.n >> (level - 1); }
+static inline int lny(const helm_ctx c, int level) { return c->d.ny >> (level - 1); }
+// 1/h of level l: h = 2^(l-1) / max(n, ny)
+static inline double inv_h(const helm_ctx c, int level) { return double(std::max(lnx(c, level), lny(c, level))); }
+
 static Geom make_geom(const helm_ctx c, int level) {
     Geom G{};
-    G.n = c->d.n >> (level - 1);
+    G.nx = lnx(c, level);
+    G.ny = lny(c, level);
     G.s = 1 << (level - 1);
-    G.nf = c->d.n;
+    G.nfx = c->d.n;
+    G.nfy = c->d.ny;
     G.W = c->d.damping_cells;
     G.inv_W = 1.0 / double(G.W);
-    G.inv_h2 = double(G.n) * double(G.n);
+    G.inv_h2 = inv_h(c, level) * inv_h(c, level);
     G.k2 = c->d.k * c->d.k;
     G.sig_str = double(c->d.sign) * c->d.damping_strength;
     G.sig_shift = double(c->d.sign) * (c->d.shift + c->d.cycle_shift);
@@ -280,14 +289,15 @@ static Geom make_geom_sys(const helm_ctx c) {
 
 static AdrGeom make_adr_geom(const helm_ctx c, int level) {
     AdrGeom A{};
-    A.n = c->d.n >> (level - 1);
-    A.inv_h2 = double(A.n) * double(A.n);
-    A.inv_2h = 0.5 * double(A.n);
+    A.nx = lnx(c, level);
+    A.ny = lny(c, level);
+    A.inv_h2 = inv_h(c, level) * inv_h(c, level);
+    A.inv_2h = 0.5 * inv_h(c, level);
     A.two_sk = 2.0 * double(c->d.sign) * c->d.k;
     return A;
 }
 
-static inline double NN(int n) { return double(n) * double(n); }
+static inline double NN2(int nx, int ny) { return double(nx) * double(ny); }
 
 static size_t csize(bool f64) { return f64 ? sizeof(c128) : sizeof(c64); }
 static size_t rsize(bool f64) { return f64 ? sizeof(double) : sizeof(float); }
@@ -295,19 +305,24 @@ static size_t rsize(bool f64) { return f64 ? sizeof(double) : sizeof(float); }
 static int nv_bucket(int m) { return m <= 4 ? 4 : (m <= 12 ? 12 : MAXM); }
 
 // ------------------------------------------------------------------ default weights
-static double median_alpha(double k, double n2mean, int nl, double lam) {
-    const double h = 1.0 / nl;
-    std::vector<double> s(nl - 1);
-    for (int a = 1; a < nl; ++a) {
-        double v = std::sin(a * M_PI * h / 2.0);
-        s[a - 1] = v * v;
-    }
-    std::vector<double> vals((size_t)(nl - 1) * (nl - 1));
+// The sine modes of a level with nx x ny nodes and spacing h have the symbol
+// (4/h^2)(sin^2(pi a/(2 nx)) + sin^2(pi b/(2 ny))) - k^2 n2mean.
+static double median_alpha(double k, double n2mean, int nx, int ny, double h, double lam) {
+    auto sines = [](int m) {
+        std::vector<double> s(m - 1);
+        for (int a = 1; a < m; ++a) {
+            double v = std::sin(a * M_PI / (2.0 * m));
+            s[a - 1] = v * v;
+        }
+        return s;
+    };
+    const std::vector<double> sx = sines(nx), sy = sines(ny);
+    std::vector<double> vals(sx.size() * sy.size());
     const double c4 = 4.0 / (h * h), kk = k * k * n2mean;
     size_t q = 0;
-    for (int a = 0; a < nl - 1; ++a)
-        for (int b = 0; b < nl - 1; ++b) {
-            double sig = c4 * (s[a] + s[b]) - kk;
+    for (size_t b = 0; b < sy.size(); ++b)
+        for (size_t a = 0; a < sx.size(); ++a) {
+            double sig = c4 * (sy[b] + sx[a]) - kk;
             vals[q++] = sig * sig;
         }
     size_t mid = (vals.size() - 1) / 2;
@@ -354,20 +369,17 @@ struct Engine {
 
     Engine(helm_ctx ctx, hipStream_t s) : c(ctx), st(s) {}
 
-    size_t N(int level) const {
-        size_t n = (size_t)(c->d.n >> (level - 1));
-        return n * n;
-    }
+    size_t N(int level) const { return (size_t)lnx(c, level) * (size_t)lny(c, level); }
 
     // ---- generic launches on a level of precision P
     template <typename P>
     void residual(const Geom& G, const void* n2, const void* g, const void* u, void* r) {
-        LAUNCH(c, ((u ? 3 : 2) * sizeof(cplx<P>) + (u ? sizeof(P) : 0)) * NN(G.n), (k_residual<P>), dim3(tiles_of(G.n)), tile_block(), st, G, (const P*)n2,
+        LAUNCH(c, ((u ? 3 : 2) * sizeof(cplx<P>) + (u ? sizeof(P) : 0)) * NN2(G.nx, G.ny), (k_residual<P>), dim3(tiles_of(G.nx, G.ny)), tile_block(), st, G, (const P*)n2,
                            (const cplx<P>*)g, (const cplx<P>*)u, (cplx<P>*)r);
     }
     template <typename P>
     void applyA(const Geom& G, const void* n2, const void* x, void* y, int conj_k) {
-        LAUNCH(c, (2 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_apply_A<P>), dim3(tiles_of(G.n)), tile_block(), st, G, (const P*)n2,
+        LAUNCH(c, (2 * sizeof(cplx<P>) + sizeof(P)) * NN2(G.nx, G.ny), (k_apply_A<P>), dim3(tiles_of(G.nx, G.ny)), tile_block(), st, G, (const P*)n2,
                            (const cplx<P>*)x, (cplx<P>*)y, conj_k);
     }
     template <typename P>
@@ -395,10 +407,10 @@ struct Engine {
         const bool fused_ends = m >= 2;
         if (u_zero && !fused_ends) zero<P>(u, n);
         if (u_zero)
-            LAUNCH(c, (3 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start<P>), dim3(tiles_of(G.n)),
+            LAUNCH(c, (3 * sizeof(cplx<P>) + sizeof(P)) * NN2(G.nx, G.ny), (k_cheb_start<P>), dim3(tiles_of(G.nx, G.ny)),
                    tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)g, (cplx<P>*)W.r, (cplx<P>*)W.d, tab);
         else
-            LAUNCH(c, (4 * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_start_res<P>), dim3(tiles_of(G.n)),
+            LAUNCH(c, (4 * sizeof(cplx<P>) + sizeof(P)) * NN2(G.nx, G.ny), (k_cheb_start_res<P>), dim3(tiles_of(G.nx, G.ny)),
                    tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)g, (const cplx<P>*)u, (cplx<P>*)W.r,
                    (cplx<P>*)W.d, tab);
         void* dcur = W.d;  // d alternates between W.d and W.t
@@ -407,7 +419,7 @@ struct Engine {
             if (step < m) {
                 const int mode = (step == 1 && u_zero ? CHEB_UZERO : 0) | (step == m - 1 ? CHEB_LAST : 0);
                 const int nb = 6 - ((mode & CHEB_UZERO) ? 1 : 0) - ((mode & CHEB_LAST) ? 2 : 0);
-                LAUNCH(c, (nb * sizeof(cplx<P>) + sizeof(P)) * NN(G.n), (k_cheb_fused<P>), dim3(tiles_of(G.n)),
+                LAUNCH(c, (nb * sizeof(cplx<P>) + sizeof(P)) * NN2(G.nx, G.ny), (k_cheb_fused<P>), dim3(tiles_of(G.nx, G.ny)),
                        tile_block(), st, G, (const P*)W.n2, (const cplx<P>*)dcur, (cplx<P>*)dnext, (cplx<P>*)W.r,
                        (cplx<P>*)u, tab + 3 * step, mode);
                 std::swap(dcur, dnext);
@@ -422,15 +434,16 @@ struct Engine {
     template <typename Pf, typename Pc>
     void resid_restrict(int l, const void* g, const void* u, void* rc) {
         const Geom& G = c->wl[l].G;
-        LAUNCH(c, (u ? 2 * sizeof(cplx<Pf>) + sizeof(Pf) : sizeof(cplx<Pf>)) * NN(G.n) + sizeof(cplx<Pc>) * NN(G.n / 2), (k_resid_restrict<Pf, Pc>), dim3(rr_blocks(G.n)), dim3(BLOCK), st, G,
+        LAUNCH(c, (u ? 2 * sizeof(cplx<Pf>) + sizeof(Pf) : sizeof(cplx<Pf>)) * NN2(G.nx, G.ny) + sizeof(cplx<Pc>) * NN2(G.nx / 2, G.ny / 2), (k_resid_restrict<Pf, Pc>), dim3(rr_blocks(G.nx, G.ny)), dim3(BLOCK), st, G,
                            (const Pf*)c->wl[l].n2, (const cplx<Pf>*)g, (const cplx<Pf>*)u, (cplx<Pc>*)rc);
     }
     template <typename Pc, typename Pf>
     void prolong_add(int l, const void* ec, void* u, bool assign = false) {
-        const int n = c->wl[l].n;
-        const size_t np = (size_t)n * (n / 2);
-        LAUNCH(c, (assign ? 1 : 2) * sizeof(cplx<Pf>) * NN(n) + sizeof(cplx<Pc>) * NN(n / 2), (k_prolong_pairs<Pc, Pf>),
-               dim3(flat_blocks(np)), dim3(BLOCK), st, n, (const cplx<Pc>*)ec, (cplx<Pf>*)u, assign ? 1 : 0);
+        const int nx = c->wl[l].nx, ny = c->wl[l].ny;
+        const size_t np = (size_t)ny * (nx / 2);
+        LAUNCH(c, (assign ? 1 : 2) * sizeof(cplx<Pf>) * NN2(nx, ny) + sizeof(cplx<Pc>) * NN2(nx / 2, ny / 2),
+               (k_prolong_pairs<Pc, Pf>), dim3(flat_blocks(np)), dim3(BLOCK), st, nx, ny, (const cplx<Pc>*)ec,
+               (cplx<Pf>*)u, assign ? 1 : 0);
     }
 
     void restrict_down(int l, const void* g, const void* u, void* rc) {
@@ -475,7 +488,7 @@ struct Engine {
         a.cheb_coarse = c->d.cheb_coarse;
         a.level3_literal = c->d.level3_literal;
         double bytes = 0.0;
-        for (int l = l0; l <= c->L; ++l) bytes += 8.0 * csize(c->wl[l].f64) * NN(c->wl[l].n);
+        for (int l = l0; l <= c->L; ++l) bytes += 8.0 * csize(c->wl[l].f64) * NN2(c->wl[l].nx, c->wl[l].ny);
         LAUNCH(c, bytes, (k_wave_tail<T>), dim3(1), dim3(WT_THREADS), st, a);
     }
 
@@ -522,29 +535,29 @@ struct Engine {
             const bool c64 = c->wl[2].f64;
             const double bc = c64 ? 16.0 : sizeof(C);
             if (c64)
-                LAUNCH(c, (sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_restrict<T, double>),
-                       dim3(jac0r_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g, w0,
+                LAUNCH(c, (sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny) + bc * NN2(G.nx / 2, G.ny / 2), (k_jac0_restrict<T, double>),
+                       dim3(jac0r_units(G.nx, G.ny)), dim3(64), st, G, (const T*)W.n2, (const C*)g, w0,
                        (c128*)c->wl[2].g);
             else
-                LAUNCH(c, (sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_restrict<T, T>),
-                       dim3(jac0r_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g, w0, (C*)c->wl[2].g);
+                LAUNCH(c, (sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny) + bc * NN2(G.nx / 2, G.ny / 2), (k_jac0_restrict<T, T>),
+                       dim3(jac0r_units(G.nx, G.ny)), dim3(64), st, G, (const T*)W.n2, (const C*)g, w0, (C*)c->wl[2].g);
             cycle_coarse(2);
             if (c64)
-                LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_prolong_jacobi<double, T>),
-                       dim3(jac0p_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g,
+                LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny) + bc * NN2(G.nx / 2, G.ny / 2), (k_jac0_prolong_jacobi<double, T>),
+                       dim3(jac0p_units(G.nx, G.ny)), dim3(64), st, G, (const T*)W.n2, (const C*)g,
                        (const c128*)c->wl[2].u, w0, (C*)u_out);
             else
-                LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN(G.n) + bc * NN(G.n / 2), (k_jac0_prolong_jacobi<T, T>),
-                       dim3(jac0p_units(G.n)), dim3(64), st, G, (const T*)W.n2, (const C*)g,
+                LAUNCH(c, (2 * sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny) + bc * NN2(G.nx / 2, G.ny / 2), (k_jac0_prolong_jacobi<T, T>),
+                       dim3(jac0p_units(G.nx, G.ny)), dim3(64), st, G, (const T*)W.n2, (const C*)g,
                        (const C*)c->wl[2].u, w0, (C*)u_out);
             return;
         }
-        LAUNCH(c, ((u_in ? 3 : 2) * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2,
+        LAUNCH(c, ((u_in ? 3 : 2) * sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny), (k_jacobi<T>), dim3(tiles_of(G.nx, G.ny)), tile_block(), st, G, (const T*)W.n2,
                            (const C*)g, (const C*)u_in, (C*)c->ws1, w0);
         restrict_down(1, g, c->ws1, c->wl[2].g);
         cycle_coarse(2);
         prolong_up(1, c->wl[2].u, c->ws1);
-        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * NN(G.n), (k_jacobi<T>), dim3(tiles_of(G.n)), tile_block(), st, G, (const T*)W.n2,
+        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny), (k_jacobi<T>), dim3(tiles_of(G.nx, G.ny)), tile_block(), st, G, (const T*)W.n2,
                            (const C*)g, (const C*)c->ws1, (C*)u_out, w0);
     }
 
@@ -579,7 +592,7 @@ struct Engine {
         for (int s = 0; s < M; ++s) {
             if (c->nsets > 1) use_set(c, s % c->nsets);
             if (s == 0 || !fused)
-                LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN(W.n), (k_adr_demod<T>), dim3(tiles_of(W.n)), tile_block(),
+                LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN2(W.nx, W.ny), (k_adr_demod<T>), dim3(tiles_of(W.nx, W.ny)), tile_block(),
                        st, W.G, (const T*)W.n2, (const C*)W.g, (const C*)W.u, (const C*)c->car2, (C*)A.b);
             if (!fused) {
                 adr_vcycle(2);
@@ -606,7 +619,7 @@ struct Engine {
     // the coarsest level's GMRES runs in one workgroup (gmres_block)
     bool block_form(int l, int m) const {
         const AdrLevel& A = c->al[l];
-        return l == c->LA && A.n <= c->d.tail_n && (size_t)A.n * A.n <= 4 * 1024 && m <= 12;
+        return l == c->LA && std::max(A.nx, A.ny) <= c->d.tail_n && (size_t)A.nx * A.ny <= 4 * 1024 && m <= 12;
     }
     bool gmres_block(int l, int m, bool x0_zero) {
         AdrLevel& A = c->al[l];
@@ -620,7 +633,7 @@ struct Engine {
         t.x = (C*)A.x;
         t.V = (C*)A.V[0];
         t.m = m;
-        const double bytes = (3.0 * m + 4.0) * sizeof(C) * NN(A.n);
+        const double bytes = (3.0 * m + 4.0) * sizeof(C) * NN2(A.nx, A.ny);
         if (m <= 4)
             LAUNCH(c, bytes, (k_gmres_block<T, 1024, 4, 4096>), dim3(1), dim3(1024), st, t, x0_zero ? 1 : 0, 1e-14);
         else
@@ -655,16 +668,16 @@ struct Engine {
         else
             gmres(l, m, false, epi, ma);
         if (pinto) {
-            const int nf = c->al[l - 1].n;
-            LAUNCH(c, 2 * sizeof(C) * NN(nf) + sizeof(C) * NN(nf / 2), (k_prolong_add<T, T>), dim3(tiles_of(nf)),
-                   tile_block(), st, nf, (const C*)A.x, (C*)pinto);
+            const int fx = c->al[l - 1].nx, fy = c->al[l - 1].ny;
+            LAUNCH(c, 2 * sizeof(C) * NN2(fx, fy) + sizeof(C) * NN2(fx / 2, fy / 2), (k_prolong_add<T, T>),
+                   dim3(tiles_of(fx, fy)), tile_block(), st, fx, fy, (const C*)A.x, (C*)pinto);
         }
     }
     template <int MM>
     void smooth_prolong_tile(int l, bool x0_zero, void* pinto) {
         AdrLevel& A = c->al[l];
         const int S = sstep_steps(l), tt = sstep_tile_edge(l);
-        const double bytes = ((x0_zero ? 2 : 3) * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + 2 * sizeof(C) * NN(2 * A.n);
+        const double bytes = ((x0_zero ? 2 : 3) * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny) + 2 * sizeof(C) * NN2(2 * A.nx, 2 * A.ny);
         if (x0_zero)
             sstep_gram_solve<MM, false>(l, S, tt);
         else
@@ -673,12 +686,12 @@ struct Engine {
             constexpr int TT = decltype(e)::value;
             if (x0_zero)
                 LAUNCH(c, bytes, (k_sstep_combine_tile_pa<T, MM, false, TT>),
-                       dim3(Tile<MM, false, false, TT, 1>::tiles(A.n)), dim3(BLOCK), st, A.A, (const T*)A.px,
+                       dim3(Tile<MM, false, false, TT, 1>::tiles(A.nx, A.ny)), dim3(BLOCK), st, A.A, (const T*)A.px,
                        (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)nullptr, (const KrylovScal*)A.K,
                        (C*)pinto);
             else
                 LAUNCH(c, bytes, (k_sstep_combine_tile_pa<T, MM, true, TT>),
-                       dim3(Tile<MM, true, false, TT, 1>::tiles(A.n)), dim3(BLOCK), st, A.A, (const T*)A.px,
+                       dim3(Tile<MM, true, false, TT, 1>::tiles(A.nx, A.ny)), dim3(BLOCK), st, A.A, (const T*)A.px,
                        (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x, (const KrylovScal*)A.K,
                        (C*)pinto);
         });
@@ -699,25 +712,25 @@ struct Engine {
             return;
         }
         gmres(l, m, true);
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2), (k_adr_resid_restrict<T>),
-               dim3(rr_blocks(A.n)), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0,
+        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny) + sizeof(C) * NN2(A.nx / 2, A.ny / 2), (k_adr_resid_restrict<T>),
+               dim3(rr_blocks(A.nx, A.ny)), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0,
                (const C*)A.b, (const C*)A.x, (C*)c->al[l + 1].b);
     }
     template <int MM>
     void presmooth_restrict_sstep(int l) {
         AdrLevel& A = c->al[l];
         const int S = sstep_steps(l), tt = sstep_tile_edge(l);
-        const double bytes = (3 * sizeof(C) + 2 * sizeof(T)) * NN(A.n) + sizeof(C) * NN(A.n / 2);
+        const double bytes = (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny) + sizeof(C) * NN2(A.nx / 2, A.ny / 2);
         sstep_gram_solve<MM, false>(l, S, tt);
         if (tt) {
             with_edge(tt, [&](auto e) {
                 constexpr int TT = decltype(e)::value;
-                LAUNCH(c, bytes, (k_sstep_combine_tile_rr<T, MM, TT>), dim3(Tile<MM, false, true, TT, 1>::tiles(A.n)),
+                LAUNCH(c, bytes, (k_sstep_combine_tile_rr<T, MM, TT>), dim3(Tile<MM, false, true, TT, 1>::tiles(A.nx, A.ny)),
                        dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                        (const KrylovScal*)A.K, (C*)A.x, (C*)c->al[l + 1].b);
             });
         } else {
-            LAUNCH(c, bytes, (k_sstep_combine_rr<T, MM>), dim3(March<MM, false, true, 1>::units(A.n, S)), dim3(64),
+            LAUNCH(c, bytes, (k_sstep_combine_rr<T, MM>), dim3(March<MM, false, true, 1>::units(A.nx, A.ny, S)), dim3(64),
                    st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                    (const KrylovScal*)A.K, (C*)A.x, (C*)c->al[l + 1].b);
         }
@@ -730,19 +743,19 @@ struct Engine {
         VecSet<T> V{};
         V.v[0] = (const C*)(x0_zero ? A.b : A.V[0]);
         for (int i = 1; i <= m; ++i) V.v[i] = (const C*)A.V[i];
-        const int nbf = flat_blocks(n, MAXRED), nbt = red_blocks(A.n);
+        const int nbf = flat_blocks(n, MAXRED), nbt = red_blocks(A.nx, A.ny);
         if (x0_zero) {
             LAUNCH(c, sizeof(C) * double(n), (k_krylov_init_norm<T>), dim3(nbf), dim3(BLOCK), st, n, (const C*)A.b,
                    c->partials);
             krylov_fin<NV>(c, st, nbf, FIN_INIT, 0, m, A.K, 0.0);
         } else {
-            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_adr_residual_init<T>), dim3(nbt), tile_block(), st,
+            LAUNCH(c, (4 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_adr_residual_init<T>), dim3(nbt), tile_block(), st,
                    A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, (const C*)A.x, (C*)A.V[0],
                    c->partials);
             krylov_fin<NV>(c, st, nbt, FIN_INIT, 0, m, A.K, 0.0);
         }
         for (int j = 0; j < m; ++j) {
-            LAUNCH(c, ((j + 3) * sizeof(C) + 2 * sizeof(T)) * NN(A.n), (k_arnoldi_adr<T, NV>), dim3(nbt), tile_block(),
+            LAUNCH(c, ((j + 3) * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_arnoldi_adr<T, NV>), dim3(nbt), tile_block(),
                    st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, V, j, (C*)A.V[j + 1],
                    (const KrylovScal*)A.K, c->partials);
             krylov_fin<NV>(c, st, nbt, FIN_MV, j, m, A.K, 0.0);
@@ -761,20 +774,20 @@ struct Engine {
     // shortest (24..128) that keeps the Gram pass at 2048 wavefronts or fewer.
     int sstep_steps(int l) const {
         if (c->tn.sstep_rows[l] >= 16) return c->tn.sstep_rows[l];
-        const int n = c->al[l].n;
+        const int nx = c->al[l].nx, ny = c->al[l].ny;
         int S = 24;
-        while (S < 128 && March<3, true, true>::units(n, S) > 2048) S += 8;
+        while (S < 128 && March<3, true, true>::units(nx, ny, S) > 2048) S += 8;
         return S;
     }
     // Tile edge of the overlapped-tile form on level l (tuned value 1: 16, 2: 32), 0 when
     // the level marches.
-    // Untuned default (measured on 4096^2): march from 2048^2 up, 32 x 32 tiles on 1024^2,
-    // 16 x 16 tiles below.
+    // Untuned default (measured on 4096^2): march from 2048^2 nodes up, 32 x 32 tiles from
+    // 1024^2, 16 x 16 tiles below.
     int sstep_tile_edge(int l) const {
         const int v = c->tn.sstep_rows[l];
         if (v == 0) {
-            const int n = c->al[l].n;
-            return n >= 2048 ? 0 : n >= 1024 ? 32 : 16;
+            const size_t a = (size_t)c->al[l].nx * c->al[l].ny;
+            return a >= (size_t)2048 * 2048 ? 0 : a >= (size_t)1024 * 1024 ? 32 : 16;
         }
         return v == 1 ? 16 : v == 2 ? 32 : 0;
     }
@@ -791,19 +804,19 @@ struct Engine {
     void sstep_gram_solve(int l, int S, int tt) {
         AdrLevel& A = c->al[l];
         constexpr int NG = (MM + 1) * (MM + 1);
-        const double bytes = ((X0 ? 3 : 2) * sizeof(C) + 2 * sizeof(T)) * NN(A.n);
+        const double bytes = ((X0 ? 3 : 2) * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny);
         const C* x0 = X0 ? (const C*)A.x : nullptr;
         int ng = 0;
         if (tt) {
             with_edge(tt, [&](auto e) {
                 constexpr int TT = decltype(e)::value;
-                ng = Tile<MM, X0, true, TT>::tiles(A.n);
+                ng = Tile<MM, X0, true, TT>::tiles(A.nx, A.ny);
                 REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many tiles for the reduction scratch");
                 LAUNCH(c, bytes, (k_sstep_gram_tile<T, MM, X0, TT>), dim3(ng), dim3(BLOCK), st, A.A,
                        (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0, c->partials);
             });
         } else {
-            ng = March<MM, X0, true>::units(A.n, S);
+            ng = March<MM, X0, true>::units(A.nx, A.ny, S);
             REQUIRE((size_t)ng * NG <= c->partials_cap, "s-step: too many segments for the reduction scratch");
             LAUNCH(c, bytes, (k_sstep_gram<T, MM, X0>), dim3(ng), dim3(64), st, A.A, S, (const T*)A.px,
                    (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0, c->partials);
@@ -816,17 +829,17 @@ struct Engine {
     template <int MM, bool X0>
     void sstep_combine_x(int l, int S, int tt, C* xout) {
         AdrLevel& A = c->al[l];
-        const double bytes = ((X0 ? 4 : 3) * sizeof(C) + 2 * sizeof(T)) * NN(A.n);
+        const double bytes = ((X0 ? 4 : 3) * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny);
         const C* x0 = X0 ? (const C*)A.x : nullptr;
         if (tt) {
             with_edge(tt, [&](auto e) {
                 constexpr int TT = decltype(e)::value;
-                LAUNCH(c, bytes, (k_sstep_combine_tile<T, MM, X0, TT>), dim3(Tile<MM, X0, false, TT>::tiles(A.n)),
+                LAUNCH(c, bytes, (k_sstep_combine_tile<T, MM, X0, TT>), dim3(Tile<MM, X0, false, TT>::tiles(A.nx, A.ny)),
                        dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0,
                        (const KrylovScal*)A.K, xout);
             });
         } else {
-            LAUNCH(c, bytes, (k_sstep_combine<T, MM, X0, EPI_X>), dim3(March<MM, X0, false>::units(A.n, S)), dim3(64),
+            LAUNCH(c, bytes, (k_sstep_combine<T, MM, X0, EPI_X>), dim3(March<MM, X0, false>::units(A.nx, A.ny, S)), dim3(64),
                    st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b, x0,
                    (const KrylovScal*)A.K, xout, ModArgs<T>{});
         }
@@ -837,7 +850,7 @@ struct Engine {
     void gmres_sstep(int l, bool x0_zero, int epi, const ModArgs<T>* ma) {
         AdrLevel& A = c->al[l];
         const int S = sstep_steps(l), tt = sstep_tile_edge(l);
-        const double nn = NN(A.n);
+        const double nn = NN2(A.nx, A.ny);
         if (x0_zero) {
             REQUIRE(epi == EPI_X, "fused ADR epilogue on a pre-smoother");
             sstep_gram_solve<MM, false>(l, S, tt);
@@ -849,12 +862,12 @@ struct Engine {
             sstep_combine_x<MM, true>(l, S, tt, (C*)A.xalt);
             std::swap(A.x, A.xalt);
         } else if (epi == EPI_MOD) {
-            const int nc = March<MM, true, false>::units(A.n, S);
+            const int nc = March<MM, true, false>::units(A.nx, A.ny, S);
             LAUNCH(c, (6 * sizeof(C) + 2 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MOD>), dim3(nc),
                    dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                    (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
         } else if constexpr (MM <= 3) {
-            const int nc = March<MM, true, false, 1>::units(A.n, S);
+            const int nc = March<MM, true, false, 1>::units(A.nx, A.ny, S);
             LAUNCH(c, (8 * sizeof(C) + 3 * sizeof(T)) * nn, (k_sstep_combine<T, MM, true, EPI_MODRD>), dim3(nc),
                    dim3(64), st, A.A, S, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)A.b,
                    (const C*)A.x, (const KrylovScal*)A.K, (C*)nullptr, *ma);
@@ -916,7 +929,7 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
     using Cp = cplx<P>;
     const int m = c->d.restart;
     const Geom G = make_geom_sys(c);
-    const size_t N = (size_t)G.n * G.n;
+    const size_t N = (size_t)G.nx * G.ny;
     // K init from V[0]
     const int nbf = c->tn.fgmres_blocks > 0 ? std::min(c->tn.fgmres_blocks, MAXRED) : flat_blocks(N, MAXRED);
     LAUNCH(c, sizeof(Cp) * double(N), (k_krylov_init_norm<P>), dim3(nbf), dim3(BLOCK), st, N, (const Cp*)V[0],
@@ -1011,8 +1024,8 @@ static int fgmres_cycle(helm_ctx c, hipStream_t st, const void* n2_fine, void** 
 
 static void residual_fp64(helm_ctx c, hipStream_t st, const void* g, const void* u, void* r, double* rn, double* gn) {
     const Geom G = make_geom_sys(c);
-    const int nbt = red_blocks(G.n);
-    LAUNCH(c, (3 * 16.0 + 8.0 + (r ? 16.0 : 0.0)) * NN(G.n), k_residual_norms, dim3(nbt), tile_block(), st, G,
+    const int nbt = red_blocks(G.nx, G.ny);
+    LAUNCH(c, (3 * 16.0 + 8.0 + (r ? 16.0 : 0.0)) * NN2(G.nx, G.ny), k_residual_norms, dim3(nbt), tile_block(), st, G,
            (const double*)c->n2f, (const c128*)g, (const c128*)u, (c128*)r, c->partials);
     LAUNCH(c, 16.0 * nbt, (k_finalize_sums<2>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nbt, 2,
            c->dscal);
@@ -1056,12 +1069,22 @@ static void write_cycle_tables(helm_ctx c) {
 }
 
 // ------------------------------------------------------------------ setup
+// The descriptor a context keeps: ny = n for a square grid given with ny = 0.
+static helm_desc desc_normalized(const helm_desc& d) {
+    helm_desc o = d;
+    if (o.ny == 0) o.ny = o.n;
+    return o;
+}
+
 static void validate(const helm_desc* d) {
     REQUIRE(d != nullptr, "desc is NULL");
     REQUIRE(d->n >= 16 && d->n <= 8192 && (d->n & (d->n - 1)) == 0, "n must be a power of two in [16, 8192]");
+    const int ny = d->ny ? d->ny : d->n;
+    REQUIRE(ny >= 16 && ny <= 8192 && (ny & (ny - 1)) == 0, "ny must be 0 or a power of two in [16, 8192]");
+    REQUIRE(ny <= 16 * d->n && d->n <= 16 * ny, "n and ny may differ by a factor of 16 at most");
     int lg = 0;
-    while ((1 << lg) < d->n) ++lg;
-    REQUIRE(d->levels >= 2 && d->levels <= lg - 1, "levels must be in [2, log2(n) - 1]");
+    while ((1 << lg) < std::min(d->n, ny)) ++lg;
+    REQUIRE(d->levels >= 2 && d->levels <= lg - 1, "levels must be in [2, log2(min(n, ny)) - 1]");
     REQUIRE(d->k > 0 && std::isfinite(d->k), "k must be positive");
     REQUIRE(d->damping_cells >= 1, "damping_cells must be >= 1");
     REQUIRE(d->damping_strength >= 0 && std::isfinite(d->damping_strength), "damping_strength must be >= 0");
@@ -1090,9 +1113,9 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     c->LA = d.adr_levels > 0 ? std::min(L, 1 + d.adr_levels) : L;
     c->f32 = d.cycle_prec == HELM_C64;
     const bool f64c = !c->f32;
-    const size_t NF = (size_t)n * n;
+    const size_t NF = (size_t)n * d.ny;
     // reduction scratch: enough partials for any tiled kernel on the fine grid
-    const size_t maxblk = std::max<size_t>((size_t)tiles_of(n), 2048);
+    const size_t maxblk = std::max<size_t>((size_t)tiles_of(n, d.ny), 2048);
     c->partials_cap = maxblk * std::max(2 * MAXM + 4, (GMAX + 1) * (GMAX + 2));
     c->partials = (double*)dalloc(c, c->partials_cap * sizeof(double));
     c->dscal = (double*)dalloc(c, 64 * sizeof(double));
@@ -1114,20 +1137,21 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     c->wl.assign(L + 1, WaveLevel{});
     for (int l = 1; l <= L; ++l) {
         WaveLevel& W = c->wl[l];
-        W.n = n >> (l - 1);
+        W.nx = lnx(c, l);
+        W.ny = lny(c, l);
         W.G = make_geom(c, l);
         W.f64 = f64c || l == L;
-        const size_t Nl = (size_t)W.n * W.n;
+        const size_t Nl = (size_t)W.nx * W.ny;
         if (l == 1 && W.f64) {
             W.n2 = c->n2f;
         } else {
             W.n2 = dalloc(c, Nl * rsize(W.f64));
             if (W.f64)
-                hipLaunchKernelGGL((k_inject_real<double, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.n,
-                                   1 << (l - 1), n, (const double*)c->n2f, (double*)W.n2);
+                hipLaunchKernelGGL((k_inject_real<double, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.nx,
+                                   W.ny, 1 << (l - 1), n, (const double*)c->n2f, (double*)W.n2);
             else
-                hipLaunchKernelGGL((k_inject_real<float, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.n,
-                                   1 << (l - 1), n, (const double*)c->n2f, (float*)W.n2);
+                hipLaunchKernelGGL((k_inject_real<float, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.nx,
+                                   W.ny, 1 << (l - 1), n, (const double*)c->n2f, (float*)W.n2);
         }
         if (l >= 2) {
             W.g = dalloc(c, Nl * csize(W.f64));
@@ -1141,8 +1165,8 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
         double* tmp = nullptr;
         if (l > 1) {
             HIPCHK(hipMalloc((void**)&tmp, Nl * sizeof(double)));
-            hipLaunchKernelGGL((k_inject_real<double, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.n,
-                               1 << (l - 1), n, (const double*)c->n2f, tmp);
+            hipLaunchKernelGGL((k_inject_real<double, double>), dim3(flat_blocks(Nl)), dim3(BLOCK), 0, st, W.nx,
+                               W.ny, 1 << (l - 1), n, (const double*)c->n2f, tmp);
             n2d = tmp;
         }
         const int nbs = flat_blocks(Nl, 1024);
@@ -1158,7 +1182,7 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
         }
         W.lam = (hs[0] + 4.0 * W.G.inv_h2) * (hs[0] + 4.0 * W.G.inv_h2);
         W.n2max = hs[1];
-        W.n2mean = hs[2] / double((size_t)(W.n - 1) * (W.n - 1));
+        W.n2mean = hs[2] / double((size_t)(W.nx - 1) * (W.ny - 1));
         if (tmp) {
             HIPCHK(hipFree(tmp));
         }
@@ -1166,17 +1190,19 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     // first level (>= 3) small enough for the one-workgroup tail of the wave cycle
     c->LT = 0;
     for (int l = 3; l <= L && l <= WT_MAXL; ++l)
-        if (c->wl[l].n <= d.wave_tail_n) {
+        if (std::max(c->wl[l].nx, c->wl[l].ny) <= d.wave_tail_n) {
             c->LT = l;
             break;
         }
     // default weights
     c->w.assign(L, 0.0);
     {
-        const double h1 = 1.0 / n;
+        const double h1 = 1.0 / inv_h(c, 1);
         const double K = d.k * d.k * c->wl[1].n2max * h1 * h1;
         c->w[0] = (4.0 - K) / (5.0 - K);
-        for (int l = 2; l <= L; ++l) c->w[l - 1] = median_alpha(d.k, c->wl[l].n2mean, c->wl[l].n, c->wl[l].lam);
+        for (int l = 2; l <= L; ++l)
+            c->w[l - 1] = median_alpha(d.k, c->wl[l].n2mean, c->wl[l].nx, c->wl[l].ny, 1.0 / inv_h(c, l),
+                                       c->wl[l].lam);
     }
     c->w_default = c->w;
     c->cdev = (CycleDev*)dalloc(c, sizeof(CycleDev));
@@ -1188,9 +1214,10 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
     if (L >= 3) {
         for (int l = 2; l <= c->LA; ++l) {
             AdrLevel& A = c->al[l];
-            A.n = n >> (l - 1);
+            A.nx = lnx(c, l);
+            A.ny = lny(c, l);
             A.A = make_adr_geom(c, l);
-            const size_t Nl = (size_t)A.n * A.n;
+            const size_t Nl = (size_t)A.nx * A.ny;
             A.px = dalloc(c, Nl * rsize(f64c));
             A.py = dalloc(c, Nl * rsize(f64c));
             A.c0 = dalloc(c, Nl * csize(f64c));
@@ -1204,8 +1231,8 @@ static void build(helm_ctx c, const double* velocity, hipStream_t st) {
             HIPCHK(hipMemsetAsync(A.K, 0, sizeof(KrylovScal), st));
             if (l == 2) A.balt = dalloc(c, Nl * csize(f64c));
         }
-        c->wl[2].ualt = dalloc(c, (size_t)c->wl[2].n * c->wl[2].n * csize(c->wl[2].f64));
-        c->car2 = dalloc(c, (size_t)(n / 2) * (n / 2) * csize(f64c));
+        c->wl[2].ualt = dalloc(c, (size_t)c->wl[2].nx * c->wl[2].ny * csize(c->wl[2].f64));
+        c->car2 = dalloc(c, (size_t)c->wl[2].nx * c->wl[2].ny * csize(f64c));
         helm_ctx_s::PhaseSet s0{};
         for (int l = 2; l <= c->LA; ++l) {
             s0.px[l] = c->al[l].px;
@@ -1240,7 +1267,7 @@ static void build_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
     for (int l = 2; l <= c->LA; ++l) {
         AdrLevel& A = c->al[l];
         const Geom G = make_geom(c, l);
-        const size_t Nl = (size_t)A.n * A.n;
+        const size_t Nl = (size_t)A.nx * A.ny;
         void* th = (l == 2) ? c->car2 : nullptr;
         const int nb = flat_blocks(Nl);
         if (c->f32) {
@@ -1292,24 +1319,24 @@ static void set_rays(helm_ctx c, int count, hipStream_t st) {
     while ((int)c->sets.size() < count) {
         helm_ctx_s::PhaseSet S{};
         for (int l = 2; l <= c->LA; ++l) {
-            const size_t Nl = (size_t)c->al[l].n * c->al[l].n;
+            const size_t Nl = (size_t)c->al[l].nx * c->al[l].ny;
             S.px[l] = dalloc(c, Nl * rsize(f64c));
             S.py[l] = dalloc(c, Nl * rsize(f64c));
             S.c0[l] = dalloc(c, Nl * csize(f64c));
         }
-        const size_t N2 = (size_t)c->al[2].n * c->al[2].n;
+        const size_t N2 = (size_t)c->al[2].nx * c->al[2].ny;
         S.car = dalloc(c, N2 * csize(f64c));
         c->sets.push_back(S);
     }
     const int n = c->d.n;
-    const size_t NF = (size_t)n * n;
+    const size_t NF = (size_t)n * c->d.ny;
     double* phi = nullptr;
     HIPCHK(hipMalloc((void**)&phi, NF * sizeof(double)));
     const double nbar = std::sqrt(c->wl[1].n2mean);
     try {
         for (int m = 0; m < count; ++m) {
             const double th = 2.0 * M_PI * double(m) / double(count);
-            hipLaunchKernelGGL(k_ray_phase, dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, n, nbar, std::cos(th),
+            hipLaunchKernelGGL(k_ray_phase, dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, n, c->d.ny, nbar, std::cos(th),
                                std::sin(th), phi);
             use_set(c, m);
             build_phase(c, phi, 1, st);
@@ -1390,7 +1417,7 @@ static void cycle_any(helm_ctx c, const void* g, const void* u_in, void* u_out, 
 // restart+1 V and restart Z vectors in complex128 (plus complex64 staging for
 // complex64 cycles), mode 1 the complex64 inner bases and correction.
 static void ensure_solver_ws(helm_ctx c, int mode) {
-    const size_t NF = (size_t)c->d.n * c->d.n;
+    const size_t NF = (size_t)c->d.n * c->d.ny;
     const int m = c->d.restart;
     if (!c->hcol) {
         HIPCHK(hipHostMalloc((void**)&c->hcol, sizeof(double) * MAXM * 2 * (MAXM + 1), hipHostMallocDefault));
@@ -1413,7 +1440,7 @@ static void ensure_solver_ws(helm_ctx c, int mode) {
 
 static helm_status solve(helm_ctx c, const void* g, void* u, double tol, int maxit, int mode, int* iters,
                          double* relres, double* history, hipStream_t st) {
-    const size_t NF = (size_t)c->d.n * c->d.n;
+    const size_t NF = (size_t)c->d.n * c->d.ny;
     if (mode == 1) REQUIRE(c->f32, "mode 1 (iterative refinement) needs cycle_prec = HELM_C64");
     ensure_solver_ws(c, mode);
     double rn = 0, gn = 0;
@@ -1541,7 +1568,7 @@ static double* noalloc_scratch() {
 static void residual_fp64_noalloc(helm_ctx c, hipStream_t st, const void* g, const void* u, void* r, double* rn,
                                   double* gn) {
     const Geom G = make_geom_sys(c);
-    const int nbt = red_blocks(G.n);
+    const int nbt = red_blocks(G.nx, G.ny);
     if ((size_t)2 * nbt > NOALLOC_PARTIALS)
         throw Error(HELM_EINVAL, "helm_residual_noalloc: " + std::to_string(nbt) + " reduction blocks exceed the " +
                                      std::to_string(NOALLOC_PARTIALS / 2) + " of the static scratch");
@@ -1619,7 +1646,7 @@ helm_status helm_setup(const helm_desc* desc, const double* velocity, helm_ctx* 
         validate(desc);
         REQUIRE(velocity != nullptr, "velocity is NULL");
         helm_ctx c = new helm_ctx_s();
-        c->d = *desc;
+        c->d = desc_normalized(*desc);
         try {
             build(c, velocity, (hipStream_t)stream);
             (void)noalloc_scratch();
@@ -1849,7 +1876,7 @@ helm_status helm_batch_setup(int32_t nprob, const helm_desc* desc, const double*
                                                    phi_is_f64 != 0, b->streams[lane]);
                     } else {
                         helm_ctx c = new helm_ctx_s();
-                        c->d = desc[it.p];
+                        c->d = desc_normalized(desc[it.p]);
                         b->ctx[it.p] = c;
                         build(c, velocity[it.p], b->streams[lane]);
                         if (ph) set_phase(c, ph, phi_is_f64 != 0, b->streams[lane]);
@@ -1913,10 +1940,10 @@ helm_status helm_batch_solve(helm_batch b, const void* const* g, void* const* u,
                 if (class_lockstep_ok(b, b->classes[k])) {
                     const auto& K = b->classes[k];
                     for (int p : K.probs) in_class[p] = 1;
-                    jobs.push_back({k, -1, NN(b->ctx[K.probs[0]]->d.n) * K.probs.size()});
+                    jobs.push_back({k, -1, NN2(b->ctx[K.probs[0]]->d.n, b->ctx[K.probs[0]]->d.ny) * K.probs.size()});
                 }
         for (int p = 0; p < np; ++p)
-            if (!in_class[p]) jobs.push_back({-1, p, NN(b->ctx[p]->d.n)});
+            if (!in_class[p]) jobs.push_back({-1, p, NN2(b->ctx[p]->d.n, b->ctx[p]->d.ny)});
         std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& c) { return a.work > c.work; });
         b->last_class.assign(np, -1);
         for (const Job& jb : jobs)
@@ -2042,13 +2069,13 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                     break;
                 case 4:
                     REQUIRE(level == 1, "Jacobi runs on level 1");
-                    hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(W.n)), tile_block(), 0, st, W.G, (const T*)W.n2,
+                    hipLaunchKernelGGL((k_jacobi<T>), dim3(tiles_of(W.nx, W.ny)), tile_block(), 0, st, W.G, (const T*)W.n2,
                                        (const cplx<T>*)in2, (const cplx<T>*)in, (cplx<T>*)out,
                                        (const double*)ctx->cdev->la, BatchIdx{});
                     break;
                 case 5: {
                     REQUIRE(level >= 2, "Chebyshev runs on levels >= 2");
-                    const size_t Nl = (size_t)W.n * W.n;
+                    const size_t Nl = (size_t)W.nx * W.ny;
                     const int m = (level == ctx->L) ? ctx->d.cheb_coarse : ctx->d.cheb_pre;
                     if (W.f64) {
                         HIPCHK(hipMemcpyAsync(out, in, Nl * sizeof(c128), hipMemcpyDeviceToDevice, st));
@@ -2063,7 +2090,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                     REQUIRE(level >= 2 && level <= ctx->LA && ctx->L >= 3 && ctx->phase_set,
                             "ADR operator needs the phase and an ADR level");
                     AdrLevel& A = ctx->al[level];
-                    hipLaunchKernelGGL((k_adr_apply<T>), dim3(tiles_of(A.n)), tile_block(), 0, st, A.A,
+                    hipLaunchKernelGGL((k_adr_apply<T>), dim3(tiles_of(A.nx, A.ny)), tile_block(), 0, st, A.A,
                                        (const T*)A.px, (const T*)A.py, (const cplx<T>*)A.c0, (const cplx<T>*)in,
                                        (cplx<T>*)out, BatchIdx{});
                     break;
@@ -2071,7 +2098,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                 case 7: {
                     REQUIRE(level >= 2 && ctx->L >= 3 && ctx->phase_set, "GMRES needs the phase");
                     AdrLevel& A = ctx->al[level];
-                    const size_t Nl = (size_t)A.n * A.n;
+                    const size_t Nl = (size_t)A.nx * A.ny;
                     HIPCHK(hipMemcpyAsync(A.b, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     HIPCHK(hipMemcpyAsync(A.x, in, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     REQUIRE(level <= ctx->LA, "level beyond the ADR hierarchy");
@@ -2082,7 +2109,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                 case 8: {
                     REQUIRE(level >= 2 && ctx->L >= 3 && ctx->phase_set, "ADR V-cycle needs the phase");
                     AdrLevel& A = ctx->al[level];
-                    const size_t Nl = (size_t)A.n * A.n;
+                    const size_t Nl = (size_t)A.nx * A.ny;
                     HIPCHK(hipMemcpyAsync(A.b, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     E.adr_vcycle(level);
                     HIPCHK(hipMemcpyAsync(out, A.x, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
@@ -2090,7 +2117,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                 }
                 case 9: {
                     REQUIRE(level == 2 && ctx->L >= 3 && ctx->phase_set, "ADR step runs on level 2 with the phase");
-                    const size_t Nl = (size_t)W.n * W.n;
+                    const size_t Nl = (size_t)W.nx * W.ny;
                     HIPCHK(hipMemcpyAsync(W.g, in2, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     HIPCHK(hipMemcpyAsync(W.u, in, Nl * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
                     E.adr_steps(1);
@@ -2102,7 +2129,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                         E.cycle(in2, in, out);
                     } else {
                         REQUIRE(in == nullptr, "coarse cycles start from a zero iterate (in must be NULL)");
-                        const size_t Nl = (size_t)W.n * W.n;
+                        const size_t Nl = (size_t)W.nx * W.ny;
                         HIPCHK(hipMemcpyAsync(W.g, in2, Nl * csize(W.f64), hipMemcpyDeviceToDevice, st));
                         E.cycle_coarse(level);
                         HIPCHK(hipMemcpyAsync(out, W.u, Nl * csize(W.f64), hipMemcpyDeviceToDevice, st));
@@ -2118,7 +2145,7 @@ helm_status helm_debug_op(helm_ctx ctx, int32_t op, int32_t level, const void* i
                 case 12: {
                     // plain copy of one level's complex array (a known-size probe for
                     // hardware memory counters)
-                    const size_t Nl = (size_t)W.n * W.n;
+                    const size_t Nl = (size_t)W.nx * W.ny;
                     if (W.f64)
                         LAUNCH(ctx, 32.0 * Nl, (k_copy<double>), dim3(flat_blocks(Nl, 8192)), dim3(BLOCK), st, Nl,
                                (const c128*)in, (c128*)out);

@@ -43,9 +43,9 @@ constexpr int GCOEF_STRIDE = 2 * (GMAX + 2);
 __device__ __forceinline__ int gram_off(int i, int c) { return 2 * (c * (c - 1) / 2 + i - 1); }
 
 template <typename T>
-__device__ __forceinline__ cplx<T> ldc(const cplx<T>* __restrict__ a, int i, int j, int n) {
-    if (i <= 0 || j <= 0 || i >= n || j >= n) return cplx<T>{};
-    return a[(size_t)i * n + j];
+__device__ __forceinline__ cplx<T> ldc(const cplx<T>* __restrict__ a, int i, int j, int nx, int ny) {
+    if (i <= 0 || j <= 0 || i >= ny || j >= nx) return cplx<T>{};
+    return a[(size_t)i * nx + j];
 }
 
 // Per-block sums of K accumulators into partials[v * nblk + block] (256 threads).
@@ -75,11 +75,11 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_jacobi_adj(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
                                                       const cplx<T>* __restrict__ u, const cplx<T>* __restrict__ yb,
                                                       cplx<T>* __restrict__ ub, T w, double* partials) {
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)n * G.ny;
     double acc[1] = {0.0};
     auto dinv_h = [&](int a, int b) -> cplx<T> {  // ybar(a,b) / conj(D(a,b)), zero off the unknowns
-        if (a <= 0 || b <= 0 || a >= n || b >= n) return cplx<T>{};
+        if (a <= 0 || b <= 0 || a >= G.ny || b >= n) return cplx<T>{};
         const size_t q = (size_t)a * n + b;
         cplx<T> kap = kappa_at<T>(G, n2[q], a, b);
         cplx<T> dh = mk<T>(T(4) * T(G.inv_h2) - kap.re, kap.im);  // conj(D)
@@ -106,19 +106,19 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_adj(Geom G, const T* __restric
     reduce_store<1>(acc, 1, partials);
 }
 
-// xc = s * R x (full weighting from the fine level with n nodes per side).
+// xc = s * R x (full weighting from the fine level of nx x ny nodes).
 template <typename Tf, typename Tc>
-__global__ __launch_bounds__(BLOCK) void k_restrict_scale(int n, const cplx<Tf>* __restrict__ x,
+__global__ __launch_bounds__(BLOCK) void k_restrict_scale(int nx, int ny, const cplx<Tf>* __restrict__ x,
                                                           cplx<Tc>* __restrict__ xc, double s) {
-    const int nc = n / 2;
-    const size_t N = (size_t)nc * nc;
+    const int ncx = nx / 2;
+    const size_t N = (size_t)ncx * (ny / 2);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int I, J;
-        rowcol(p, nc, I, J);
+        rowcol(p, ncx, I, J);
         cplx<Tc> out{};
         if (I > 0 && J > 0) {
             const int fi = 2 * I, fj = 2 * J;
-            auto X = [&](int a, int b) { return ccast<double>(ldc(x, a, b, n)); };
+            auto X = [&](int a, int b) { return ccast<double>(ldc(x, a, b, nx, ny)); };
             c128 c = X(fi, fj);
             c128 e = ((X(fi - 1, fj) + X(fi + 1, fj)) + X(fi, fj - 1)) + X(fi, fj + 1);
             c128 dg = ((X(fi - 1, fj - 1) + X(fi - 1, fj + 1)) + X(fi + 1, fj - 1)) + X(fi + 1, fj + 1);
@@ -135,11 +135,11 @@ template <typename Tc, typename Tf>
 __global__ __launch_bounds__(BLOCK) void k_prolong_adj(Geom G, const Tf* __restrict__ n2,
                                                        const cplx<Tc>* __restrict__ rcbar, cplx<Tf>* __restrict__ ubar,
                                                        cplx<Tf>* __restrict__ gbar) {
-    const int n = G.n, nc = n / 2;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx, ny = G.ny;  // n: nodes per row
+    const size_t N = (size_t)n * ny;
     auto tq = [&](int a, int b) -> cplx<Tf> {
-        if (a <= 0 || b <= 0 || a >= n || b >= n) return cplx<Tf>{};
-        return Tf(0.25) * prolong_at<Tc, Tf>(rcbar, nc, a, b);
+        if (a <= 0 || b <= 0 || a >= ny || b >= n) return cplx<Tf>{};
+        return Tf(0.25) * prolong_at<Tc, Tf>(rcbar, n / 2, ny / 2, a, b);
     };
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
@@ -160,8 +160,8 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_adj(Geom G, const Tf* __restr
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adj_ahsub(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ t,
                                                      cplx<T>* __restrict__ ubar, cplx<T>* __restrict__ gbar) {
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)n * G.ny;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);
@@ -195,8 +195,8 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_apply_A2(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ d,
                                                     const cplx<T>* __restrict__ dt, cplx<T>* __restrict__ t1,
                                                     cplx<T>* __restrict__ t2) {
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)n * G.ny;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);
@@ -219,8 +219,8 @@ __global__ __launch_bounds__(BLOCK) void k_chebadj_step(Geom G, const T* __restr
                                                         cplx<T>* __restrict__ rt, cplx<T>* __restrict__ d,
                                                         cplx<T>* __restrict__ dt, cplx<T>* __restrict__ s,
                                                         cplx<T>* __restrict__ st, T c1, T c2, T c1t, T c2t) {
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)n * G.ny;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);
@@ -243,8 +243,8 @@ __global__ __launch_bounds__(BLOCK) void k_chebadj_step(Geom G, const T* __restr
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_dot_ah(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ a,
                                                   const cplx<T>* __restrict__ b, double* partials) {
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)n * G.ny;
     double acc[1] = {0.0};
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
@@ -300,7 +300,7 @@ template <typename T>
 __device__ __forceinline__ cplx<T> applyMH_at(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,
                                               const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ y, int i,
                                               int j) {
-    const int n = A.n;
+    const int n = A.nx;  // nodes per row
     const T g = T(A.two_sk * A.inv_2h), ih2 = T(A.inv_h2);
     const size_t p = (size_t)i * n + j;
     const T fx = px[p], fy = py[p];
@@ -318,7 +318,7 @@ __device__ __forceinline__ cplx<T> applyMH_at(const AdrGeom& A, const T* __restr
         const T f = px[q], a = f < T(0) ? -f : f;
         out = out + mk<T>(-ih2, g * (f - a)) * y[q];
     }
-    if (i + 1 < n) {  // row (i+1, j), its south coefficient
+    if (i + 1 < A.ny) {  // row (i+1, j), its south coefficient
         const size_t q = p + n;
         const T f = py[q], a = f < T(0) ? -f : f;
         out = out + mk<T>(-ih2, -g * (f + a)) * y[q];
@@ -339,14 +339,14 @@ __device__ __forceinline__ void coef_grad_at(const AdrGeom& A, const T* __restri
                                              const cplx<T>* __restrict__ a, cplx<T> yb, int i, int j,
                                              double* __restrict__ pxb, double* __restrict__ pyb,
                                              c128* __restrict__ c0b) {
-    const int n = A.n;
+    const int n = A.nx, ny = A.ny;
     const size_t p = (size_t)i * n + j;
     const T fx = px[p], fy = py[p];
     const T sx = fx > T(0) ? T(1) : (fx < T(0) ? T(-1) : T(0));
     const T sy = fy > T(0) ? T(1) : (fy < T(0) ? T(-1) : T(0));
     const cplx<T> ac = a[p];
-    const cplx<T> aw = ldz(a, i, j - 1, n), ae = ldz(a, i, j + 1, n);
-    const cplx<T> as = ldz(a, i - 1, j, n), an = ldz(a, i + 1, j, n);
+    const cplx<T> aw = ldz(a, i, j - 1, n, ny), ae = ldz(a, i, j + 1, n, ny);
+    const cplx<T> as = ldz(a, i - 1, j, n, ny), an = ldz(a, i + 1, j, n, ny);
     const cplx<T> dux = T(A.inv_2h) * (((T(2) * sx) * ac - (T(1) + sx) * aw) + (T(1) - sx) * ae);
     const cplx<T> duy = T(A.inv_2h) * (((T(2) * sy) * ac - (T(1) + sy) * as) + (T(1) - sy) * an);
     const double ybr = double(yb.re), ybi = double(yb.im);
@@ -366,8 +366,8 @@ __global__ __launch_bounds__(BLOCK) void k_gr_r0(AdrGeom A, const T* __restrict_
                                                  const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
                                                  const cplx<T>* __restrict__ x0, cplx<T>* __restrict__ k1,
                                                  double* partials) {
-    const int n = A.n;
-    const size_t N = (size_t)n * n;
+    const int n = A.nx;  // nodes per row
+    const size_t N = (size_t)n * A.ny;
     double acc[2] = {0.0, 0.0};
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
@@ -388,8 +388,8 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gr_chain(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                     const cplx<T>* __restrict__ c0, VecSet<T> Kv, int jj, double inv_tau,
                                                     cplx<T>* __restrict__ kout, double* partials) {
-    const int n = A.n;
-    const size_t N = (size_t)n * n;
+    const int n = A.nx;  // nodes per row
+    const size_t N = (size_t)n * A.ny;
     double acc[2 * (GMAX + 1)];
 #pragma unroll
     for (int v = 0; v < 2 * (GMAX + 1); ++v) acc[v] = 0.0;
@@ -697,8 +697,8 @@ __global__ __launch_bounds__(BLOCK) void k_ga_step(AdrGeom A, const T* __restric
     __shared__ T cf[2 * (GMAX + 2)];
     if (threadIdx.x < 2 * (GMAX + 2)) cf[threadIdx.x] = threadIdx.x < 2 * nv ? T(coef[threadIdx.x]) : T(0);
     __syncthreads();
-    const int n = A.n;
-    const size_t N = (size_t)n * n;
+    const int n = A.nx;  // nodes per row
+    const size_t N = (size_t)n * A.ny;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);
@@ -722,12 +722,12 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
                                                       const cplx<T>* __restrict__ x1, cplx<T>* __restrict__ xbar,
                                                       cplx<T>* __restrict__ bbar, double* __restrict__ pxb,
                                                       double* __restrict__ pyb, c128* __restrict__ c0b) {
-    const int n = A.n, nc = n / 2;
-    const size_t N = (size_t)n * n;
+    const int n = A.nx, ny = A.ny;  // n: nodes per row
+    const size_t N = (size_t)n * ny;
     const T g = T(A.two_sk * A.inv_2h), ih2 = T(A.inv_h2);
     auto tq = [&](int a, int b) -> cplx<T> {
-        if (a <= 0 || b <= 0 || a >= n || b >= n) return cplx<T>{};
-        return T(0.25) * prolong_at<T, T>(bcbar, nc, a, b);
+        if (a <= 0 || b <= 0 || a >= ny || b >= n) return cplx<T>{};
+        return T(0.25) * prolong_at<T, T>(bcbar, n / 2, ny / 2, a, b);
     };
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
             const T f = px[p - 1], af = f < T(0) ? -f : f;
             mh = mh + mk<T>(-ih2, g * (f - af)) * tq(i, j - 1);
         }
-        if (i + 1 < n) {
+        if (i + 1 < ny) {
             const T f = py[p + n], af = f < T(0) ? -f : f;
             mh = mh + mk<T>(-ih2, -g * (f + af)) * tq(i + 1, j);
         }
@@ -769,29 +769,31 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
 //   Px = pxbar + 2 k^2 phi_x Re(c0bar), Py likewise, Lap-bar = -sigma k Im(c0bar),
 // pulled back through the central / one-sided differences of the coefficients.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_phi_adj(int n, int s2, int n2side, double k, int sigma,
+__global__ __launch_bounds__(BLOCK) void k_phi_adj(int n, int ny, int s2, int n2row, double k, int sigma,
                                                    const T* __restrict__ px, const T* __restrict__ py,
                                                    const double* __restrict__ pxb, const double* __restrict__ pyb,
                                                    const c128* __restrict__ c0b, const double* __restrict__ thb,
                                                    double* __restrict__ phib2) {
-    const size_t N = (size_t)n * n;
-    const double h = 1.0 / n, i2h = 0.5 * n, ih = double(n), ih2 = double(n) * double(n);
+    // the level has n nodes per row and ny rows, spacing h = 1 / max(n, ny); n2row: nodes
+    // per row of level 2
+    const size_t N = (size_t)n * ny;
+    const double nm = double(n > ny ? n : ny);
+    const double i2h = 0.5 * nm, ih = nm, ih2 = nm * nm;
     const double k2 = k * k, sk = double(sigma) * k;
     auto PX = [&](int a, int b) -> double {
-        if (a <= 0 || b <= 0 || a >= n || b >= n) return 0.0;
+        if (a <= 0 || b <= 0 || a >= ny || b >= n) return 0.0;
         const size_t q = (size_t)a * n + b;
         return pxb[q] + 2.0 * k2 * double(px[q]) * c0b[q].re;
     };
     auto PY = [&](int a, int b) -> double {
-        if (a <= 0 || b <= 0 || a >= n || b >= n) return 0.0;
+        if (a <= 0 || b <= 0 || a >= ny || b >= n) return 0.0;
         const size_t q = (size_t)a * n + b;
         return pyb[q] + 2.0 * k2 * double(py[q]) * c0b[q].re;
     };
     auto LB = [&](int a, int b) -> double {
-        if (a <= 0 || b <= 0 || a >= n || b >= n) return 0.0;
+        if (a <= 0 || b <= 0 || a >= ny || b >= n) return 0.0;
         return -sk * c0b[(size_t)a * n + b].im;
     };
-    (void)h;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);
@@ -805,25 +807,27 @@ __global__ __launch_bounds__(BLOCK) void k_phi_adj(int n, int s2, int n2side, do
             if (j == n - 2) v += -PX(i, n - 1) * ih - 2.0 * LB(i, n - 1) * ih2;
             if (j == n - 3) v += LB(i, n - 1) * ih2;
         }
-        // along y (columns j >= 1)
+        // along y (columns j >= 1): the edge is row ny - 1
         if (j >= 1) {
-            if (i - 1 >= 1 && i - 1 <= n - 2) v += PY(i - 1, j) * i2h + LB(i - 1, j) * ih2;
-            if (i + 1 >= 1 && i + 1 <= n - 2) v += -PY(i + 1, j) * i2h + LB(i + 1, j) * ih2;
-            if (i >= 1 && i <= n - 2) v += -2.0 * LB(i, j) * ih2;
-            if (i == n - 1) v += PY(n - 1, j) * ih + LB(n - 1, j) * ih2;
-            if (i == n - 2) v += -PY(n - 1, j) * ih - 2.0 * LB(n - 1, j) * ih2;
-            if (i == n - 3) v += LB(n - 1, j) * ih2;
+            if (i - 1 >= 1 && i - 1 <= ny - 2) v += PY(i - 1, j) * i2h + LB(i - 1, j) * ih2;
+            if (i + 1 >= 1 && i + 1 <= ny - 2) v += -PY(i + 1, j) * i2h + LB(i + 1, j) * ih2;
+            if (i >= 1 && i <= ny - 2) v += -2.0 * LB(i, j) * ih2;
+            if (i == ny - 1) v += PY(ny - 1, j) * ih + LB(ny - 1, j) * ih2;
+            if (i == ny - 2) v += -PY(ny - 1, j) * ih - 2.0 * LB(ny - 1, j) * ih2;
+            if (i == ny - 3) v += LB(ny - 1, j) * ih2;
         }
         if (thb) v += sk * thb[p];
-        phib2[(size_t)i * s2 * n2side + (size_t)j * s2] += v;
+        phib2[(size_t)i * s2 * n2row + (size_t)j * s2] += v;
     }
 }
 
 // Fine-grid phase cotangent: the level-2 lattice (even fine indices) carries phib2,
 // every other node 0 (the phase enters only through its injection).
 template <typename TO>
-__global__ __launch_bounds__(BLOCK) void k_phi_out(int nf, const double* __restrict__ phib2, TO* __restrict__ out) {
-    const size_t N = (size_t)nf * nf;
+__global__ __launch_bounds__(BLOCK) void k_phi_out(int nf, int nfy, const double* __restrict__ phib2,
+                                                   TO* __restrict__ out) {
+    // nf nodes per row and nfy rows on the fine grid; level 2 has nf / 2 per row
+    const size_t N = (size_t)nf * nfy;
     const int n2 = nf / 2;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
@@ -841,15 +845,15 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_loss_resid(Geom G, const double* __restrict__ n2, const cplx<T>* __restrict__ g,
                                                       const cplx<T>* __restrict__ u, c128* __restrict__ r,
                                                       double* partials) {
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)n * G.ny;
     double acc[1] = {0.0};
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);
         c128 v{};
         if (i > 0 && j > 0) {
-            auto U = [&](int a, int b) { return ccast<double>(ldz(u, a, b, n)); };
+            auto U = [&](int a, int b) { return ccast<double>(ldz(u, a, b, n, G.ny)); };
             const c128 c = U(i, j);
             const c128 nb = ((U(i - 1, j) + U(i + 1, j)) + U(i, j - 1)) + U(i, j + 1);
             const c128 kap = kappa_at<double>(G, n2[p], i, j);
@@ -866,8 +870,8 @@ __global__ __launch_bounds__(BLOCK) void k_loss_resid(Geom G, const double* __re
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_loss_grad(Geom G, const double* __restrict__ n2, const c128* __restrict__ r,
                                                      cplx<T>* __restrict__ gu) {
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)n * G.ny;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);

@@ -8,7 +8,7 @@ namespace helm {
 
 // Geometry of one ADR level.
 struct AdrGeom {
-    int n;
+    int nx, ny;        // nodes per row / per column
     double inv_h2;
     double inv_2h;     // 1/(2h)
     double two_sk;     // 2 * sigma * k (the advection factor is -i * two_sk)
@@ -28,23 +28,23 @@ __device__ __forceinline__ cplx<T> adr_carrier(double phi, double k, int sigma) 
     return mk<T>(T(cs), T(sn));
 }
 
-// phi_x, phi_y and Lap phi at unknown (i, j) of a level of n nodes per side with
-// spacing h from the values P(a, b) of a field: second-order central differences
-// inside, first-order one-sided ones at the last unknown (the node x = 1 is not
-// stored).
+// phi_x, phi_y and Lap phi at unknown (i, j) of a level of nx x ny nodes with spacing h
+// from the values P(a, b) of a field: second-order central differences inside,
+// first-order one-sided ones at the last unknown of each axis (the boundary node of the
+// open edge is not stored).
 template <typename F>
-__device__ __forceinline__ void fd_phase_rule(const F& P, int i, int j, int n, double h, double& px, double& py,
-                                              double& lap) {
+__device__ __forceinline__ void fd_phase_rule(const F& P, int i, int j, int nx, int ny, double h, double& px,
+                                              double& py, double& lap) {
     double pxx, pyy;
     const double c = P(i, j);
-    if (j <= n - 2) {
+    if (j <= nx - 2) {
         px = (P(i, j + 1) - P(i, j - 1)) / (2.0 * h);
         pxx = ((P(i, j + 1) - 2.0 * c) + P(i, j - 1)) / (h * h);
     } else {
         px = (c - P(i, j - 1)) / h;
         pxx = ((c - 2.0 * P(i, j - 1)) + P(i, j - 2)) / (h * h);
     }
-    if (i <= n - 2) {
+    if (i <= ny - 2) {
         py = (P(i + 1, j) - P(i - 1, j)) / (2.0 * h);
         pyy = ((P(i + 1, j) - 2.0 * c) + P(i - 1, j)) / (h * h);
     } else {
@@ -61,9 +61,9 @@ __device__ __forceinline__ void adr_coef_store(const Geom& G, const double* __re
                                                size_t p, double px, double py, double lap, double k, int sigma,
                                                double strength, T* __restrict__ px_out, T* __restrict__ py_out,
                                                cplx<T>* __restrict__ c0_out) {
-    const int s = G.s, nf = G.nf;
-    const double nn = n2f[(size_t)i * s * nf + (size_t)j * s];
-    const double ri = sponge_ramp<double>(i * s, nf, G.inv_W), rj = sponge_ramp<double>(j * s, nf, G.inv_W);
+    const int s = G.s;
+    const double nn = n2f[(size_t)i * s * G.nfx + (size_t)j * s];
+    const double ri = sponge_ramp<double>(i * s, G.nfy, G.inv_W), rj = sponge_ramp<double>(j * s, G.nfx, G.inv_W);
     const double rho = ri > rj ? ri : rj;
     const double delta = strength * rho * rho + double(sigma) * G.sig_shift;  // sponge plus shift
     const double k2 = k * k;
@@ -82,13 +82,13 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __rest
                                                     const TP* __restrict__ phi, double k, int sigma, double strength,
                                                     T* __restrict__ px_out, T* __restrict__ py_out,
                                                     cplx<T>* __restrict__ c0_out, cplx<T>* __restrict__ car_out) {
-    const int n = G.n, s = G.s, nf = G.nf;
-    const size_t N = (size_t)n * n;
-    const double h = 1.0 / n;
+    const int nx = G.nx, ny = G.ny, s = G.s, nfx = G.nfx;
+    const size_t N = (size_t)nx * ny;
+    const double h = 1.0 / (nx > ny ? nx : ny);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
-        rowcol(p, n, i, j);
-        auto P = [&](int a, int b) -> double { return double(phi[(size_t)a * s * nf + (size_t)b * s]); };
+        rowcol(p, nx, i, j);
+        auto P = [&](int a, int b) -> double { return double(phi[(size_t)a * s * nfx + (size_t)b * s]); };
         if (car_out) car_out[p] = adr_carrier<T>(P(i, j), k, sigma);
         if (i == 0 || j == 0) {
             px_out[p] = T(0);
@@ -97,20 +97,22 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef(Geom G, const double* __rest
             continue;
         }
         double px, py, lap;
-        fd_phase_rule(P, i, j, n, h, px, py, lap);
+        fd_phase_rule(P, i, j, nx, ny, h, px, py, lap);
         adr_coef_store<T>(G, n2f, i, j, p, px, py, lap, k, sigma, strength, px_out, py_out, c0_out);
     }
 }
 
-// Plane-wave phase nbar (cs x + sn y) at the fine nodes, x = j / n, y = i / n, in FP64 with
-// the products and the sum rounded separately (no contraction).
-__global__ __launch_bounds__(BLOCK) void k_ray_phase(int n, double nbar, double cs, double sn,
+// Plane-wave phase nbar (cs x + sn y) at the fine nodes (nx x ny), x = j h, y = i h with
+// h = 1 / max(nx, ny), in FP64 with the products and the sum rounded separately (no
+// contraction).
+__global__ __launch_bounds__(BLOCK) void k_ray_phase(int nx, int ny, double nbar, double cs, double sn,
                                                      double* __restrict__ phi) {
-    const size_t N = (size_t)n * n;
+    const size_t N = (size_t)nx * ny;
+    const double nm = double(nx > ny ? nx : ny);
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
-        rowcol(p, n, i, j);
-        const double x = double(j) / double(n), y = double(i) / double(n);
+        rowcol(p, nx, i, j);
+        const double x = double(j) / nm, y = double(i) / nm;
         phi[p] = __dmul_rn(nbar, __dadd_rn(__dmul_rn(cs, x), __dmul_rn(sn, y)));
     }
 }
@@ -120,11 +122,11 @@ template <typename T>
 __device__ __forceinline__ cplx<T> applyM_at(const AdrGeom& A, const T* __restrict__ px, const T* __restrict__ py,
                                              const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ x, int i,
                                              int j) {
-    const int n = A.n;
-    const size_t p = (size_t)i * n + j;
+    const int nx = A.nx, ny = A.ny;
+    const size_t p = (size_t)i * nx + j;
     const cplx<T> c = x[p];
-    const cplx<T> w = ldz(x, i, j - 1, n), e = ldz(x, i, j + 1, n);
-    const cplx<T> s = ldz(x, i - 1, j, n), nn = ldz(x, i + 1, j, n);
+    const cplx<T> w = ldz(x, i, j - 1, nx, ny), e = ldz(x, i, j + 1, nx, ny);
+    const cplx<T> s = ldz(x, i - 1, j, nx, ny), nn = ldz(x, i + 1, j, nx, ny);
     const T fx = px[p], fy = py[p];
     const T ax = fx < T(0) ? -fx : fx, ay = fy < T(0) ? -fy : fy;
     const cplx<T> lap = T(A.inv_h2) * (T(4) * c - (((s + nn) + w) + e));
@@ -141,21 +143,21 @@ __global__ __launch_bounds__(BLOCK) void k_adr_apply(AdrGeom A, const T* __restr
                                                      cplx<T>* __restrict__ y, BatchIdx bi) {
     bshift(bi.off(), px, py, c0, x, y);
     int j, i0;
-    tile_origin(A.n, j, i0);
-    if (j >= A.n) return;
+    tile_origin(A.nx, j, i0);
+    if (j >= A.nx) return;
     for (int r = 0; r < RPT; ++r) {
         const int i = i0 + r;
-        if (i >= A.n) break;
+        if (i >= A.ny) break;
         cplx<T> v{};
         if (i > 0 && j > 0) v = applyM_at(A, px, py, c0, x, i, j);
-        y[(size_t)i * A.n + j] = v;
+        y[(size_t)i * A.nx + j] = v;
     }
 }
 
 template <typename T>
 __device__ __forceinline__ cplx<T> adr_resid_at(const AdrGeom& A, const T* px, const T* py, const cplx<T>* c0,
                                                 const cplx<T>* b, const cplx<T>* x, int i, int j) {
-    cplx<T> bv = b[(size_t)i * A.n + j];
+    cplx<T> bv = b[(size_t)i * A.nx + j];
     if (x == nullptr) return bv;
     return bv - applyM_at(A, px, py, c0, x, i, j);
 }
@@ -171,14 +173,14 @@ struct AdrRes {
     __device__ cplx<T> operator()(int i, int j) const { return adr_resid_at(A, px, py, c0, b, x, i, j); }
 };
 
-// rc = R (b - M x) on the next ADR level (x == nullptr: x = 0); rr_blocks(A.n) blocks.
+// rc = R (b - M x) on the next ADR level (x == nullptr: x = 0); rr_blocks(A.nx, A.ny) blocks.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_resid_restrict(AdrGeom A, const T* __restrict__ px,
                                                               const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                                               const cplx<T>* __restrict__ b,
                                                               const cplx<T>* __restrict__ x, cplx<T>* __restrict__ rc, BatchIdx bi) {
     bshift(bi.off(), px, py, c0, b, x, rc);
-    restrict_tile<T, T>(A.n, AdrRes<T>{A, px, py, c0, b, x}, rc);
+    restrict_tile<T, T>(A.nx, A.ny, AdrRes<T>{A, px, py, c0, b, x}, rc);
 }
 
 // r_hat = (g - A u) e^{-i theta}   (car = e^{i theta})
@@ -188,13 +190,13 @@ __global__ __launch_bounds__(BLOCK) void k_adr_demod(Geom G, const T* __restrict
                                                      cplx<T>* __restrict__ rhat, BatchIdx bi) {
     bshift(bi.off(), n2, g, u, car, rhat);
     int j, i0;
-    tile_origin(G.n, j, i0);
-    if (j >= G.n) return;
+    tile_origin(G.nx, j, i0);
+    if (j >= G.nx) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        if (i >= G.n) break;
+        if (i >= G.ny) break;
         cplx<T> v{};
-        const size_t p = (size_t)i * G.n + j;
+        const size_t p = (size_t)i * G.nx + j;
         if (i > 0 && j > 0) {
             cplx<T> r = resid_at(G, n2, g, u, i, j);
             v = r * conjg(car[p]);

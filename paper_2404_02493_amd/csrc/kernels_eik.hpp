@@ -13,13 +13,14 @@
 //
 // Fast sweeping: Gauss-Seidel passes in the four orders (i up, j up), (i up, j down),
 // (i down, j up), (i down, j down).  A pass runs as a wavefront over B x B tiles
-// (B = 64, or n when smaller): the tiles of one anti-diagonal (in the pass's orientation) are independent
+// (B = 64, or the shorter side when smaller; B divides both sides): the tiles of one
+// anti-diagonal (in the pass's orientation) are independent
 // and form one launch, one wavefront per tile; inside a tile the wavefront walks
 // the node anti-diagonals with the tile and its one-node halo in LDS.  A node then
 // sees exactly the values the sequential pass would give it (updated neighbours
 // behind it, old ones ahead), so every pass equals the sequential one; the local
 // update rounds every operation separately (no contraction; quotients by h = 2^-m
-// are the exact products by n), so the result is the same double precision numbers
+// are the exact products by 1/h), so the result is the same double precision numbers
 // as a sequential implementation of the same steps.
 #pragma once
 
@@ -28,7 +29,7 @@
 namespace helm {
 
 struct EikSrc {
-    int n;
+    int nx, ny;  // nodes per row / per column of the fine grid, h = 1 / max(nx, ny)
     double h, xs, ys;
     double rfix;  // nodes with r <= rfix are fixed
 };
@@ -42,14 +43,14 @@ __device__ __forceinline__ double eik_r(const EikSrc& E, int i, int j) {
 
 // New tau1 at global node (i, j) (not fixed, r = tau0 there, sp = s there) from the
 // neighbour values tw, te, ts, tn (+inf where missing or not reached yet) and their
-// tau0 values rw, re, rs, rn, or +inf when no candidate exists.  h = 1/n is a power
-// of two, so a quotient by h is the product by n, exactly.
+// tau0 values rw, re, rs, rn, or +inf when no candidate exists.  h = 1/max(nx, ny) is a
+// power of two, so a quotient by h is the product by max(nx, ny), exactly.
 __device__ __forceinline__ double eik_update(const EikSrc& E, int i, int j, double r, double sp, double tw,
                                              double te, double ts, double tn, double rw, double re, double rs,
                                              double rn) {
 #pragma clang fp contract(off)
     const double inf = __builtin_huge_val();
-    const double h = E.h, nh = double(E.n);
+    const double h = E.h, nh = double(E.nx > E.ny ? E.nx : E.ny);
     const double dx = double(j) * h - E.xs, dy = double(i) * h - E.ys;
     const double gx = dx / r, gy = dy / r;
     bool hx = false, hy = false;
@@ -119,20 +120,19 @@ __global__ __launch_bounds__(BLOCK) void k_eik_slowness(size_t N, const double* 
 // tau1 = (s(node) + s(src node)) / 2 on the fixed nodes, +inf elsewhere.
 __global__ __launch_bounds__(BLOCK) void k_eik_init(EikSrc E, const double* __restrict__ s, size_t psrc,
                                                     double* __restrict__ t1) {
-    const int n = E.n;
-    const size_t N = (size_t)n * n;
+    const size_t N = (size_t)E.nx * E.ny;
     const double ssrc = s[psrc];
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
-        rowcol(p, n, i, j);
+        rowcol(p, E.nx, i, j);
         t1[p] = eik_r(E, i, j) <= E.rfix ? (s[p] + ssrc) / 2.0 : __builtin_huge_val();
     }
 }
 
 // One anti-diagonal d of B x B tiles of the pass (iup, jup): tile (I, J) of the
-// pass's orientation (a = iup ? i : n-1-i, b = jup ? j : n-1-j) with I + J = d; B
-// threads, B divides n.  part[tile] (tile in grid orientation) keeps the largest
-// single decrease of tau1 in the round.
+// pass's orientation (a = iup ? i : ny-1-i, b = jup ? j : nx-1-j) with I + J = d; B
+// threads, B divides nx and ny.  part[tile] (tile in grid orientation, nx / B tiles per
+// row) keeps the largest single decrease of tau1 in the round.
 template <int B>
 __global__ __launch_bounds__(B) void k_eik_pass(EikSrc E, const double* __restrict__ s, double* __restrict__ t1,
                                                 int iup, int jup, int d, double* __restrict__ part) {
@@ -141,16 +141,16 @@ __global__ __launch_bounds__(B) void k_eik_pass(EikSrc E, const double* __restri
     __shared__ double rl[R * R];  // tau0 there
     __shared__ double sl[B * B];
     __shared__ double red[B];
-    const int n = E.n, T = n / B;
-    const int I = (d < T ? 0 : d - T + 1) + (int)blockIdx.x, J = d - I;
+    const int n = E.nx, ny = E.ny, Tx = n / B, Ty = ny / B;
+    const int I = (d < Tx ? 0 : d - Tx + 1) + (int)blockIdx.x, J = d - I;
     const int a0 = I * B, b0 = J * B;
     const int lane = threadIdx.x;
     const double inf = __builtin_huge_val();
-    auto gi = [&](int a) { return iup ? a : n - 1 - a; };
+    auto gi = [&](int a) { return iup ? a : ny - 1 - a; };
     auto gj = [&](int b) { return jup ? b : n - 1 - b; };
     for (int q = lane; q < R * R; q += B) {
         const int a = a0 - 1 + q / R, b = b0 - 1 + q % R;
-        const bool in = a >= 0 && a < n && b >= 0 && b < n;
+        const bool in = a >= 0 && a < ny && b >= 0 && b < n;
         tl[q] = in ? t1[(size_t)gi(a) * n + gj(b)] : inf;
         rl[q] = in ? eik_r(E, gi(a), gj(b)) : 0.0;
     }
@@ -184,8 +184,8 @@ __global__ __launch_bounds__(B) void k_eik_pass(EikSrc E, const double* __restri
     if (lane == 0) {
         double m = 0.0;
         for (int q = 0; q < B; ++q) m = red[q] > m ? red[q] : m;
-        const int ti = iup ? I : T - 1 - I, tj = jup ? J : T - 1 - J;
-        double* pp = part + (size_t)ti * T + tj;
+        const int ti = iup ? I : Ty - 1 - I, tj = jup ? J : Tx - 1 - J;
+        double* pp = part + (size_t)ti * Tx + tj;
         *pp = m > *pp ? m : *pp;
     }
 }
@@ -208,11 +208,10 @@ __global__ __launch_bounds__(1024) void k_eik_max(size_t N, const double* __rest
 // phi = min(phi, tau0 tau1) (first arrival over the sources).
 __global__ __launch_bounds__(BLOCK) void k_eik_phase(EikSrc E, const double* __restrict__ t1,
                                                      double* __restrict__ phi) {
-    const int n = E.n;
-    const size_t N = (size_t)n * n;
+    const size_t N = (size_t)E.nx * E.ny;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
-        rowcol(p, n, i, j);
+        rowcol(p, E.nx, i, j);
         const double v = eik_r(E, i, j) * t1[p];
         phi[p] = v < phi[p] ? v : phi[p];
     }
@@ -235,18 +234,18 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef_fac(Geom G, const double* __
                                                         double k, int sigma, double strength,
                                                         T* __restrict__ px_out, T* __restrict__ py_out,
                                                         cplx<T>* __restrict__ c0_out, cplx<T>* __restrict__ car_out) {
-    const int n = G.n, s = G.s, nf = G.nf;
-    const size_t N = (size_t)n * n;
-    const double h = 1.0 / n;
+    const int nx = G.nx, ny = G.ny, s = G.s, nfx = G.nfx;
+    const size_t N = (size_t)nx * ny;
+    const double h = 1.0 / (nx > ny ? nx : ny);
     auto R = [&](int a, int b) -> double {
         const double dx = double(b) * h - xs, dy = double(a) * h - ys;
         return sqrt(dx * dx + dy * dy);
     };
-    auto T1 = [&](int a, int b) -> double { return tau1[(size_t)a * s * nf + (size_t)b * s]; };
+    auto T1 = [&](int a, int b) -> double { return tau1[(size_t)a * s * nfx + (size_t)b * s]; };
     auto PHI = [&](int a, int b) -> double { return R(a, b) * T1(a, b); };
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
-        rowcol(p, n, i, j);
+        rowcol(p, nx, i, j);
         if (car_out) car_out[p] = adr_carrier<T>(PHI(i, j), k, sigma);
         if (i == 0 || j == 0) {
             px_out[p] = T(0);
@@ -257,10 +256,10 @@ __global__ __launch_bounds__(BLOCK) void k_adr_coef_fac(Geom G, const double* __
         double px, py, lap;
         const double r = R(i, j);
         if (r < h) {
-            fd_phase_rule(PHI, i, j, n, h, px, py, lap);
+            fd_phase_rule(PHI, i, j, nx, ny, h, px, py, lap);
         } else {
             double t1x, t1y, t1l;
-            fd_phase_rule(T1, i, j, n, h, t1x, t1y, t1l);
+            fd_phase_rule(T1, i, j, nx, ny, h, t1x, t1y, t1l);
             const double gx = (double(j) * h - xs) / r, gy = (double(i) * h - ys) / r;
             const double t1 = T1(i, j);
             px = r * t1x + t1 * gx;

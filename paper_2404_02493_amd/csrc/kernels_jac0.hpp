@@ -48,16 +48,15 @@ constexpr int J0P_SR = 68;  // fine rows per segment of the prolongation (even; 
 constexpr int J0_STEPS = 72;
 static_assert(2 * J0R_SC + 5 <= J0_STEPS && J0P_SR + 4 <= J0_STEPS && J0_STEPS % J0_W == 0, "march length");
 
-__host__ __device__ inline int jac0r_units(int n) {
-    const int nc = n / 2;
-    return ((nc + J0R_CC - 1) / J0R_CC) * ((nc + J0R_SC - 1) / J0R_SC);
+__host__ __device__ inline int jac0r_units(int nx, int ny) {
+    return ((nx / 2 + J0R_CC - 1) / J0R_CC) * ((ny / 2 + J0R_SC - 1) / J0R_SC);
 }
-__host__ __device__ inline int jac0p_units(int n) {
-    return ((n - 2) / J0P_CW + 1) * ((n - 2) / J0P_SR + 1);
+__host__ __device__ inline int jac0p_units(int nx, int ny) {
+    return ((nx - 2) / J0P_CW + 1) * ((ny - 2) / J0P_SR + 1);
 }
 
-// rc = R (g - A u0) on the coarse grid (nc = n/2 per side, every coarse node written,
-// the coarse ring with 0); jac0r_units(n) wavefronts of 64 threads.
+// rc = R (g - A u0) on the coarse grid (nx/2 x ny/2, every coarse node written, the
+// coarse ring with 0); jac0r_units(nx, ny) wavefronts of 64 threads.
 template <typename Tf, typename Tc>
 __global__ __launch_bounds__(64) void k_jac0_restrict(Geom G, const Tf* __restrict__ n2,
                                                         const cplx<Tf>* __restrict__ g,
@@ -67,25 +66,25 @@ __global__ __launch_bounds__(64) void k_jac0_restrict(Geom G, const Tf* __restri
     // rows are loaded P ahead; a loaded row is still read one step after its own
     constexpr int W = J0_W, P = W - 2;
     const Tf w = Tf(wp[0]), w1 = Tf(1) - w, ih2 = Tf(G.inv_h2);
-    const int n = G.n, nc = n / 2;
+    const int nx = G.nx, ny = G.ny, ncx = nx / 2, ncy = ny / 2;
     const int lane = threadIdx.x;
-    const int ns = (nc + J0R_CC - 1) / J0R_CC;
+    const int ns = (ncx + J0R_CC - 1) / J0R_CC;
     const int u = xcd_remap(blockIdx.x, gridDim.x);
     const int sg = u / ns, st = u - sg * ns;
     const int j = 2 * J0R_CC * st - 2 + lane;  // fine column of the lane
-    const bool colok = j >= 1 && j <= n - 1;
+    const bool colok = j >= 1 && j <= nx - 1;
     const int jcl = colok ? j : 0;
-    const Tf rj = sponge_ramp<Tf>(j * G.s, G.nf, Tf(G.inv_W));
-    const int Ib = sg * J0R_SC, Ie = (Ib + J0R_SC < nc ? Ib + J0R_SC : nc) - 1;
+    const Tf rj = sponge_ramp<Tf>(j * G.s, G.nfx, Tf(G.inv_W));
+    const int Ib = sg * J0R_SC, Ie = (Ib + J0R_SC < ncy ? Ib + J0R_SC : ncy) - 1;
     const int J = j >> 1;
-    const bool own = lane >= 2 && lane <= 61 && !(lane & 1) && J < nc;
+    const bool own = lane >= 2 && lane <= 61 && !(lane & 1) && J < ncx;
     const int q0 = 2 * Ib - 2;  // first fine row loaded
     cplx<Tf> gw[W], uw[W], rw[W];
     Tf nw[W];
     // every load is unconditional: off the unknowns it reads node 0 (the zero ring of g)
     auto load = [&](int q, cplx<Tf>& gv, Tf& nv) {
-        const int qc = (q >= 1 && q <= n - 1) ? q : 0;
-        const unsigned p = (unsigned)(qc * n + jcl);
+        const int qc = (q >= 1 && q <= ny - 1) ? q : 0;
+        const unsigned p = (unsigned)(qc * nx + jcl);
         gv = ld_off(g, p);
         nv = ld_off(n2, p);
     };
@@ -107,10 +106,10 @@ __global__ __launch_bounds__(64) void k_jac0_restrict(Geom G, const Tf* __restri
             load(q + P, gw[sp], nw[sp]);
             // u0 on row q (0 off the unknowns, where g was read as 0); no branch, so that
             // the loads ahead stay in flight
-            const Tf ri = sponge_ramp<Tf>(q * G.s, G.nf, Tf(G.inv_W));
+            const Tf ri = sponge_ramp<Tf>(q * G.s, G.nfy, Tf(G.inv_W));
             uw[s] = jac_wd<Tf>(G, nw[s], ri > rj ? ri : rj, w) * gw[s];
             // residual on row q - 1 (0 off the unknowns)
-            const bool rok = q - 1 >= 1 && q - 1 <= n - 1 && colok;
+            const bool rok = q - 1 >= 1 && q - 1 <= ny - 1 && colok;
             const cplx<Tf> c = uw[sm1];
             const cplx<Tf> nb = ((uw[sm2] + uw[s]) + lane_prev(c)) + lane_next(c);
             const cplx<Tf> rv = w1 * gw[sm1] + ih2 * nb;
@@ -124,7 +123,7 @@ __global__ __launch_bounds__(64) void k_jac0_restrict(Geom G, const Tf* __restri
                     const cplx<Tf> vs = (rw[sm3] + rw[sm1]) + Tf(2) * rw[sm2];
                     cplx<Tf> v = Tf(1.0 / 16.0) * ((lane_prev(vs) + lane_next(vs)) + Tf(2) * vs);
                     if (I == 0 || J == 0) v = cplx<Tf>{};
-                    if (own) rc[(size_t)I * nc + J] = ccast<Tc>(v);
+                    if (own) rc[(size_t)I * ncx + J] = ccast<Tc>(v);
                 }
             }
         });
@@ -132,7 +131,8 @@ __global__ __launch_bounds__(64) void k_jac0_restrict(Geom G, const Tf* __restri
 }
 
 // out = (w/d) ((2 - w) g + h^-2 sum_nb u) + (1 - w) P ec, u = u0 + P ec, on every fine
-// node (0 on the ring); out must not overlap g.  jac0p_units(n) wavefronts of 64 threads.
+// node (0 on the ring); out must not overlap g.  jac0p_units(nx, ny) wavefronts of 64
+// threads.
 template <typename Tc, typename Tf>
 __global__ __launch_bounds__(64) void k_jac0_prolong_jacobi(Geom G, const Tf* __restrict__ n2,
                                                               const cplx<Tf>* __restrict__ g,
@@ -144,36 +144,36 @@ __global__ __launch_bounds__(64) void k_jac0_prolong_jacobi(Geom G, const Tf* __
     // its own
     constexpr int W = J0_W, P = W - 3;
     const Tf w = Tf(wp[0]), w1 = Tf(1) - w, w2 = Tf(2) - w, ih2 = Tf(G.inv_h2);
-    const int n = G.n, nc = n / 2;
+    const int nx = G.nx, ny = G.ny, ncx = nx / 2, ncy = ny / 2;
     const int lane = threadIdx.x;
-    const int ns = (n - 2) / J0P_CW + 1;
+    const int ns = (nx - 2) / J0P_CW + 1;
     const int u = xcd_remap(blockIdx.x, gridDim.x);
     const int sg = u / ns, st = u - sg * ns;
     const int j = J0P_CW * st + lane;  // fine column of the lane
-    const bool colok = j >= 1 && j <= n - 1;
+    const bool colok = j >= 1 && j <= nx - 1;
     const int jcl = colok ? j : 0;
-    const Tf rj = sponge_ramp<Tf>(j * G.s, G.nf, Tf(G.inv_W));
-    const bool own = ((lane >= 1 && lane <= J0P_CW) || j == 0) && j <= n - 1;
-    const int rb = 1 + sg * J0P_SR, re = (rb + J0P_SR - 1 < n - 1 ? rb + J0P_SR - 1 : n - 1);
+    const Tf rj = sponge_ramp<Tf>(j * G.s, G.nfx, Tf(G.inv_W));
+    const bool own = ((lane >= 1 && lane <= J0P_CW) || j == 0) && j <= nx - 1;
+    const int rb = 1 + sg * J0P_SR, re = (rb + J0P_SR - 1 < ny - 1 ? rb + J0P_SR - 1 : ny - 1);
     if (sg == 0 && own) out[j] = cplx<Tf>{};  // row 0
     // coarse columns of the lane: J and, for odd j, J + 1 (0 off the coarse unknowns)
     const int Jc = j >> 1;
     const bool jodd = j & 1;
-    const int cJ0 = (Jc >= 1 && Jc < nc) ? Jc : -1, cJ1 = (Jc + 1 >= 1 && Jc + 1 < nc) ? Jc + 1 : -1;
+    const int cJ0 = (Jc >= 1 && Jc < ncx) ? Jc : -1, cJ1 = (Jc + 1 >= 1 && Jc + 1 < ncx) ? Jc + 1 : -1;
     const int q0 = rb - 2;  // odd: the slot of every odd row q carries coarse row (q + 1) / 2
     cplx<Tf> gw[W], uw[W], wdw[W], pew[W];
     Tf nw[W];
     cplx<Tc> e0w[W], e1w[W];  // coarse row (q + 1) / 2 at J, J + 1 (odd slots)
     auto load = [&](int q, cplx<Tf>& gv, Tf& nv, cplx<Tc>& e0, cplx<Tc>& e1, bool odd) {
-        const int qc = (q >= 1 && q <= n - 1) ? q : 0;
-        const unsigned p = (unsigned)(qc * n + jcl);
+        const int qc = (q >= 1 && q <= ny - 1) ? q : 0;
+        const unsigned p = (unsigned)(qc * nx + jcl);
         gv = ld_off(g, p);
         nv = ld_off(n2, p);
         if (odd) {
             const int I = (q + 1) >> 1;
-            const bool Iok = I >= 1 && I < nc;
-            e0 = ld_off(ec, (unsigned)((Iok && cJ0 >= 0) ? I * nc + cJ0 : 0));
-            e1 = ld_off(ec, (unsigned)((Iok && cJ1 >= 0) ? I * nc + cJ1 : 0));
+            const bool Iok = I >= 1 && I < ncy;
+            e0 = ld_off(ec, (unsigned)((Iok && cJ0 >= 0) ? I * ncx + cJ0 : 0));
+            e1 = ld_off(ec, (unsigned)((Iok && cJ1 >= 0) ? I * ncx + cJ1 : 0));
         }
     };
 #pragma unroll
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(64) void k_jac0_prolong_jacobi(Geom G, const Tf* __
             }
             // off the unknowns g and the coarse values were read as 0, so u = 0 there;
             // no branch, so that the loads ahead stay in flight
-            const Tf ri = sponge_ramp<Tf>(q * G.s, G.nf, Tf(G.inv_W));
+            const Tf ri = sponge_ramp<Tf>(q * G.s, G.nfy, Tf(G.inv_W));
             const cplx<Tf> wd = jac_wd<Tf>(G, nw[s], ri > rj ? ri : rj, w);
             pew[s] = ccast<Tf>(pc);
             wdw[s] = wd;
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(64) void k_jac0_prolong_jacobi(Geom G, const Tf* __
                 const cplx<Tf> c = uw[sm1];
                 const cplx<Tf> nbs = ((uw[sm2] + uw[s]) + lane_prev(c)) + lane_next(c);
                 const cplx<Tf> v = wdw[sm1] * (w2 * gw[sm1] + ih2 * nbs) + w1 * pew[sm1];
-                if (own) out[(size_t)r * n + j] = mk<Tf>(colok ? v.re : Tf(0), colok ? v.im : Tf(0));
+                if (own) out[(size_t)r * nx + j] = mk<Tf>(colok ? v.re : Tf(0), colok ? v.im : Tf(0));
             }
         });
     }

@@ -111,17 +111,17 @@ __global__ __launch_bounds__(BLOCK) void k_adr_residual_init(AdrGeom A, const T*
     __shared__ double sums[1];
     double acc[1] = {0.0};
     int t0, t1;
-    tile_chunk(A.n, t0, t1);
+    tile_chunk(A.nx, A.ny, t0, t1);
     for (int t = t0; t < t1; ++t) {
         int j, i0;
-        tile_xy(A.n, t, j, i0);
-        if (j >= A.n) continue;
+        tile_xy(A.nx, t, j, i0);
+        if (j >= A.nx) continue;
         for (int r = 0; r < RPT; ++r) {
             const int i = i0 + r;
-            if (i >= A.n) break;
+            if (i >= A.ny) break;
             cplx<T> v{};
             if (i > 0 && j > 0) v = adr_resid_at(A, px, py, c0, b, x, i, j);
-            r0[(size_t)i * A.n + j] = v;
+            r0[(size_t)i * A.nx + j] = v;
             acc[0] += double(v.re) * double(v.re) + double(v.im) * double(v.im);
         }
     }
@@ -169,15 +169,15 @@ __global__ __launch_bounds__(BLOCK) void k_arnoldi_adr(AdrGeom A, const T* __res
 #pragma unroll
     for (int q = 0; q < 2 * NV + 2; ++q) acc[q] = 0.0;
     int t0, t1;
-    tile_chunk(A.n, t0, t1);
+    tile_chunk(A.nx, A.ny, t0, t1);
     for (int t = t0; t < t1; ++t) {
         int j, i0;
-        tile_xy(A.n, t, j, i0);
-        if (j >= A.n) continue;
+        tile_xy(A.nx, t, j, i0);
+        if (j >= A.nx) continue;
         for (int r = 0; r < RPT; ++r) {
             const int i = i0 + r;
-            if (i >= A.n) break;
-            const size_t p = (size_t)i * A.n + j;
+            if (i >= A.ny) break;
+            const size_t p = (size_t)i * A.nx + j;
             cplx<T> v{};
             if (i > 0 && j > 0) v = sj * applyM_at(A, px, py, c0, vjj, i, j);
             w[p] = v;
@@ -352,8 +352,8 @@ __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restric
 #pragma unroll
     for (int i = 0; i < J; ++i) cs[i] = mk<T>(T(K->dots[2 * i] * K->scale[i]), T(K->dots[2 * i + 1] * K->scale[i]));
     const T sj = use_scale ? T(K->zscale[J]) : T(1);
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;  // nodes per row
+    const size_t N = (size_t)G.nx * G.ny;
     T acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = T(0);
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(BLOCK) void k_fg_arnoldi(Geom G, const T* __restric
             cplx<T> c[2], up[2], dn[2] = {};
             ld_pack<T, 2>(z, p, c);
             if (i > 0) ld_pack<T, 2>(z, p - n, up);
-            if (i + 1 < n) ld_pack<T, 2>(z, p + n, dn);
+            if (i + 1 < G.ny) ld_pack<T, 2>(z, p + n, dn);
             const cplx<T> lf = j0 > 0 ? z[p - 1] : cplx<T>{};
             const cplx<T> rt = j0 + 2 < n ? z[p + 2] : cplx<T>{};
             const T ih2 = T(G.inv_h2);

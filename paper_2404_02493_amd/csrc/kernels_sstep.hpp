@@ -157,13 +157,13 @@ struct March {
     static_assert(P >= 1, "register ring too short for the halo");
     // A unit marches S steps (S a multiple of W) over a segment of S - 2H rows.
     __host__ __device__ static int rows(int S) { return S - 2 * H; }
-    __host__ __device__ static int strips(int n) { return (n - 2) / TXW + 1; }
-    __host__ __device__ static int units(int n, int S) { return strips(n) * ((n - 2) / rows(S) + 1); }
+    __host__ __device__ static int strips(int nx) { return (nx - 2) / TXW + 1; }
+    __host__ __device__ static int units(int nx, int ny, int S) { return strips(nx) * ((ny - 2) / rows(S) + 1); }
 };
 
 // No fields beyond those of the Krylov vectors.
 struct NoExtra {
-    __device__ void init(int, bool, int) {}
+    __device__ void init(int, bool, int, int) {}
     template <int SL>
     __device__ void load(int) {}
 };
@@ -184,7 +184,7 @@ __device__ __forceinline__ void sstep_march_dir(const AdrGeom& A, int S, const T
                                                 Emit& emit) {
     using Mc = March<M, X0, GRAM, XH, EP>;
     constexpr int H = Mc::H, D = Mc::D, NK = Mc::NK, W = Mc::W, P = Mc::P;
-    const int n = A.n;
+    const int nx = A.nx, ny = A.ny;
     // first row loaded: the segment's rows plus H warm-up rows on the side it starts from
     const int q0 = DIR > 0 ? rb - H : rb + Mc::rows(S) - 1 + H;
 
@@ -209,8 +209,8 @@ __device__ __forceinline__ void sstep_march_dir(const AdrGeom& A, int S, const T
     // which would stall the prefetch at every row.
     const int jcl = colok ? j : 0;
     auto load_row = [&](int r, cplx<T>& xv, cplx<T>& bv, T& fx, T& fy, cplx<T>& cv) {
-        const int rcl = (r >= 1 && r <= n - 1) ? r : 0;
-        const unsigned p = (unsigned)(rcl * n + jcl);
+        const int rcl = (r >= 1 && r <= ny - 1) ? r : 0;
+        const unsigned p = (unsigned)(rcl * nx + jcl);
         if (X0) xv = ld_off(x0, p);
         bv = ld_off(b, p);
         fx = ld_off(px, p);
@@ -238,7 +238,7 @@ __device__ __forceinline__ void sstep_march_dir(const AdrGeom& A, int S, const T
             constexpr int s1 = (s + P) % W;
             load_row(q + DIR * P, xr[s1], bw[s1], fxw[s1], fyw[s1], cw0[s1]);
             ex.template load<s1>(q + DIR * P);
-            cw[s] = up_coef<T>(A, fxw[s], fyw[s], cw0[s], q >= 1 && q <= n - 1 && colok);
+            cw[s] = up_coef<T>(A, fxw[s], fyw[s], cw0[s], q >= 1 && q <= ny - 1 && colok);
             // K_0 (zero off the unknowns: b and the stencil factors are)
             if constexpr (X0) {
                 constexpr int sr = (s + W - 1) % W;
@@ -274,18 +274,18 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
                                             Emit&& emit) {
     using Mc = March<M, X0, GRAM, XH, EP>;
     constexpr int H = Mc::H;
-    const int n = A.n;
+    const int nx = A.nx, ny = A.ny;
     const int lane = threadIdx.x;
-    const int ns = Mc::strips(n);
+    const int ns = Mc::strips(nx);
     const int u = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring units on one XCD
     const int sg = u / ns, st = u - sg * ns;
     const int j = 1 + st * Mc::TXW - H + lane;
     jcol = j;
-    const bool colok = j >= 1 && j <= n - 1;
+    const bool colok = j >= 1 && j <= nx - 1;
     const int R = Mc::rows(S);
     rb = 1 + sg * R;
-    re = rb + R - 1 < n - 1 ? rb + R - 1 : n - 1;
-    ex.init(j, colok, n);
+    re = rb + R - 1 < ny - 1 ? rb + R - 1 : ny - 1;
+    ex.init(j, colok, nx, ny);
     if (sg & 1)
         sstep_march_dir<T, M, X0, GRAM, XH, EP, -1>(A, S, px, py, c0, b, x0, j, colok, rb, re, xr, ex, emit);
     else
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(64) void k_sstep_gram(AdrGeom A, int S, const T* __
     sstep_march<T, M, X0, true, 0, -1>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
                                        [&](int r, auto, const cplx<T>(&k)[M + 1], auto) {
         (void)r;
-        if (!(own_lane && j <= A.n - 1)) return;
+        if (!(own_lane && j <= A.nx - 1)) return;
         gram_add<T, M>(acc, k);
     });
 #pragma unroll
@@ -513,7 +513,7 @@ enum { EPI_X = 0, EPI_MOD = 1, EPI_MODRD = 2 };
 // Level-2 fields of the modulated epilogues.
 template <typename T>
 struct ModArgs {
-    Geom G;                   // wave geometry of level 2 (n as on the ADR level)
+    Geom G;                   // wave geometry of level 2 (sizes as on the ADR level)
     const cplx<T>* car;       // carrier e^{i sigma k phi}
     const T* n2;              // n^2 on level 2 (EPI_MODRD)
     const cplx<T>* g;         // level-2 right-hand side (EPI_MODRD)
@@ -537,25 +537,26 @@ __device__ __forceinline__ ModArgs<T> bsh_one(size_t o, ModArgs<T> a) {
 template <typename T, int EPI>
 struct ModExtra {
     const ModArgs<T>& a;
-    int j = 0, n = 0;
+    int j = 0, nx = 0, ny = 0;
     bool colok = false;
     cplx<T> cr[8];
     cplx<T> uu[8];
     cplx<T> gg[EPI == EPI_MODRD ? 8 : 1];
     T nn[EPI == EPI_MODRD ? 8 : 1];
     __device__ explicit ModExtra(const ModArgs<T>& args) : a(args) {}
-    __device__ void init(int jj, bool ok, int nl) {
+    __device__ void init(int jj, bool ok, int nlx, int nly) {
         j = jj;
         colok = ok;
-        n = nl;
+        nx = nlx;
+        ny = nly;
     }
     template <int SL>
     __device__ void load(int r) {
         if constexpr (EPI != EPI_X) {
             // unconditional, as the Krylov rows: off the unknowns row / column 0, where u is 0
             // (the update there is u + 0 * car) and g, n2 feed no stored residual
-            const int rcl = (r >= 1 && r <= n - 1) ? r : 0;
-            const unsigned p = (unsigned)(rcl * n + (colok ? j : 0));
+            const int rcl = (r >= 1 && r <= ny - 1) ? r : 0;
+            const unsigned p = (unsigned)(rcl * nx + (colok ? j : 0));
             cr[SL] = ld_off(a.car, p);
             uu[SL] = ld_off(a.u, p);
             if constexpr (EPI == EPI_MODRD) {
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
     using Mc = March<M, X0, false, XH, EP>;
     constexpr int W = Mc::W;
     const int lane = threadIdx.x;
-    const int n = A.n;
+    const int nx = A.nx, ny = A.ny;
     cplx<T> c[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
@@ -591,14 +592,14 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
     const bool own_lane = lane >= Mc::H && lane < 64 - Mc::H;
     if constexpr (EPI != EPI_MOD) {
         // the ring: column 0 of the segment's rows (strip 0), row 0 (segment 0)
-        const int ns = Mc::strips(n);
+        const int ns = Mc::strips(nx);
         int u = blockIdx.x;
         const int nb = gridDim.x;
         u = xcd_remap(u, nb);
         const int sg = u / ns, st = u - sg * ns;
         const int jj = 1 + st * Mc::TXW - Mc::H + lane;
         const int R = Mc::rows(S);
-        const int r0 = 1 + sg * R, r1 = r0 + R - 1 < n - 1 ? r0 + R - 1 : n - 1;
+        const int r0 = 1 + sg * R, r1 = r0 + R - 1 < ny - 1 ? r0 + R - 1 : ny - 1;
         auto zero_at = [&](size_t p) {
             if constexpr (EPI == EPI_X) {
                 xout[p] = cplx<T>{};
@@ -608,8 +609,8 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
             }
         };
         if (jj == 0)
-            for (int r = r0; r <= r1; ++r) zero_at((size_t)r * n);
-        if (sg == 0 && ((own_lane && jj <= n - 1) || jj == 0)) zero_at((size_t)jj);
+            for (int r = r0; r <= r1; ++r) zero_at((size_t)r * nx);
+        if (sg == 0 && ((own_lane && jj <= nx - 1) || jj == 0)) zero_at((size_t)jj);
     }
     auto xval = [&](auto slot, const cplx<T>(&k)[M]) {
         constexpr int sr = decltype(slot)::value;
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
         sstep_march<T, M, X0, false, 0, EP>(A, S, px, py, c0, b, x0, j, rb, re, xr, ex,
                                             [&](int r, auto slot, const cplx<T>(&k)[M], auto) {
                                             const cplx<T> v = xval(slot, k);
-                                            if (own_lane && j <= n - 1) st_off(xout, (unsigned)(r * n + j), v);
+                                            if (own_lane && j <= nx - 1) st_off(xout, (unsigned)(r * nx + j), v);
                                         });
     } else if constexpr (EPI == EPI_MOD) {
         ModExtra<T, EPI> ex(mod);
@@ -631,8 +632,8 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                                             [&](int r, auto slot, const cplx<T>(&k)[M], auto) {
                                             constexpr int sr = decltype(slot)::value;
                                             const cplx<T> v = xval(slot, k);
-                                            if (own_lane && j <= n - 1)
-                                                st_off(mod.uout, (unsigned)(r * n + j), ex.uu[sr] + v * ex.cr[sr]);
+                                            if (own_lane && j <= nx - 1)
+                                                st_off(mod.uout, (unsigned)(r * nx + j), ex.uu[sr] + v * ex.cr[sr]);
                                         });
     } else {
         ModExtra<T, EPI> ex(mod);
@@ -653,8 +654,8 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
                     const cplx<T> lap = ih2 * (T(4) * cu - nb);
                     const cplx<T> kap = kappa_at<T>(G, ex.nn[s1], ri, j);
                     const cplx<T> res = ex.gg[s1] - (lap - kap * cu);
-                    if (own_lane && j <= n - 1) {
-                        const unsigned p = (unsigned)(ri * n + j);
+                    if (own_lane && j <= nx - 1) {
+                        const unsigned p = (unsigned)(ri * nx + j);
                         st_off(mod.bout, p, res * conjg(ex.cr[s1]));
                         st_off(mod.uout, p, cu);
                     }
@@ -668,7 +669,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
 // residual comes from one more Krylov vector instead of an application of M to x.  The
 // unit emits one row and column beyond its own, weights each residual row across lanes
 // (1 2 1) and, at every odd fine row whose neighbour emitted before it (2I) is its own, combines the last
-// three rows (1 2 1) / 16 into the coarse row I of rc (n/2 nodes per side) at the own
+// three rows (1 2 1) / 16 into the coarse row I of rc (nx/2 x ny/2 nodes) at the own
 // even columns.  Also writes the zero rings of x and rc.
 template <typename T, int M>
 __global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const T* __restrict__ px,
@@ -680,23 +681,23 @@ __global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const
     using Mc = March<M, false, true, 1, -1>;
     constexpr int W = Mc::W;
     const int lane = threadIdx.x;
-    const int n = A.n, nc = n / 2;
+    const int nx = A.nx, ny = A.ny, ncx = nx / 2;
     cplx<T> c[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
     const bool own_lane = lane >= Mc::H && lane < 64 - Mc::H;
     {
-        const int ns = Mc::strips(n);
+        const int ns = Mc::strips(nx);
         const int u = xcd_remap(blockIdx.x, gridDim.x);
         const int sg = u / ns, st = u - sg * ns;
         const int jj = 1 + st * Mc::TXW - Mc::H + lane;
         const int R = Mc::rows(S);
-        const int r0 = 1 + sg * R, r1 = r0 + R - 1 < n - 1 ? r0 + R - 1 : n - 1;
+        const int r0 = 1 + sg * R, r1 = r0 + R - 1 < ny - 1 ? r0 + R - 1 : ny - 1;
         if (jj == 0) {
-            for (int r = r0; r <= r1; ++r) xout[(size_t)r * n] = cplx<T>{};
-            for (int I = (r0 + 1) >> 1; 2 * I <= r1; ++I) rc[(size_t)I * nc] = cplx<T>{};
+            for (int r = r0; r <= r1; ++r) xout[(size_t)r * nx] = cplx<T>{};
+            for (int I = (r0 + 1) >> 1; 2 * I <= r1; ++I) rc[(size_t)I * ncx] = cplx<T>{};
         }
-        if (sg == 0 && ((own_lane && jj <= n - 1) || jj == 0)) {
+        if (sg == 0 && ((own_lane && jj <= nx - 1) || jj == 0)) {
             xout[jj] = cplx<T>{};
             if (!(jj & 1)) rc[jj >> 1] = cplx<T>{};
         }
@@ -716,13 +717,13 @@ __global__ __launch_bounds__(64) void k_sstep_combine_rr(AdrGeom A, int S, const
             xv = xv + c[q] * k[q];
             rv = rv - c[q] * k[q + 1];
         }
-        if (own_lane && j <= n - 1 && r >= rb && r <= re) st_off(xout, (unsigned)(r * n + j), xv);
+        if (own_lane && j <= nx - 1 && r >= rb && r <= re) st_off(xout, (unsigned)(r * nx + j), xv);
         hr[sr] = (lane_prev(rv) + lane_next(rv)) + T(2) * rv;
         const int cm = r - decltype(dirc)::value;  // the middle one of the last three rows
         const int I = cm >> 1;
         if ((r & 1) && cm >= rb && cm <= re && I >= 1) {
             const cplx<T> v = T(1.0 / 16.0) * ((hr[s2] + hr[sr]) + T(2) * hr[s1]);
-            if (own_lane && !(j & 1) && j <= n - 1) st_off(rc, (unsigned)(I * nc + (j >> 1)), v);
+            if (own_lane && !(j & 1) && j <= nx - 1) st_off(rc, (unsigned)(I * ncx + (j >> 1)), v);
         }
     });
 }
@@ -742,8 +743,9 @@ struct Tile {
     static constexpr int RW = TT + 2 * H;  // region width
     static constexpr int NR = RW * RW;
     static constexpr int NPT = (NR + BLOCK - 1) / BLOCK;  // region nodes per thread
-    __host__ __device__ static int per_side(int n) { return (n - 2) / TT + 1; }
-    __host__ __device__ static int tiles(int n) { return per_side(n) * per_side(n); }
+    // tiles along a side of m nodes, and over a level of nx x ny nodes
+    __host__ __device__ static int per_side(int m) { return (m - 2) / TT + 1; }
+    __host__ __device__ static int tiles(int nx, int ny) { return per_side(nx) * per_side(ny); }
 };
 
 // Shared body of the tile passes; buf: 2 NR values of LDS.  emit(q, gi, gj, own, x0, k)
@@ -758,7 +760,7 @@ __device__ __forceinline__ void sstep_tile(const AdrGeom& A, int ti, int tj, con
                                            cplx<T>* buf, Emit&& emit) {
     using Tg = Tile<M, X0, GRAM, TT, XH>;
     constexpr int RW = Tg::RW, NR = Tg::NR, NPT = Tg::NPT, H = Tg::H, NK = Tg::NK;
-    const int n = A.n;
+    const int nx = A.nx, ny = A.ny;
     const int i0 = 1 + ti * TT - H, j0 = 1 + tj * TT - H;  // region node (0, 0)
     const int tid = threadIdx.x;
     cplx<T> xv[NPT], bv[NPT], cv[NPT];
@@ -771,9 +773,9 @@ __device__ __forceinline__ void sstep_tile(const AdrGeom& A, int ti, int tj, con
         const int gi = i0 + ri, gj = j0 + rj;
         xv[k] = bv[k] = cv[k] = cplx<T>{};
         fx[k] = fy[k] = T(0);
-        ok[k] = q < NR && gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1;
+        ok[k] = q < NR && gi >= 1 && gi <= ny - 1 && gj >= 1 && gj <= nx - 1;
         if (ok[k]) {
-            const unsigned p = (unsigned)(gi * n + gj);
+            const unsigned p = (unsigned)(gi * nx + gj);
             if constexpr (X0) xv[k] = ld_off(x0, p);
             bv[k] = ld_off(b, p);
             fx[k] = ld_off(px, p);
@@ -823,7 +825,7 @@ __device__ __forceinline__ void sstep_tile(const AdrGeom& A, int ti, int tj, con
         const int ri = q / RW, rj = q - ri * RW;
         const int gi = i0 + ri, gj = j0 + rj;
         if (q < NR && ri >= H - XH && ri < H + TT + XH && rj >= H - XH && rj < H + TT + XH) {
-            const bool own = ri >= H && ri < H + TT && rj >= H && rj < H + TT && gi <= n - 1 && gj <= n - 1;
+            const bool own = ri >= H && ri < H + TT && rj >= H && rj < H + TT && gi <= ny - 1 && gj <= nx - 1;
             cplx<T> kk[NK + 1];
 #pragma unroll
             for (int jj = 0; jj <= NK; ++jj) kk[jj] = kv[jj][k];
@@ -832,14 +834,15 @@ __device__ __forceinline__ void sstep_tile(const AdrGeom& A, int ti, int tj, con
     }
 }
 
-__device__ __forceinline__ void tile_index(int per_side, int& ti, int& tj) {
+// Tile row ti and column tj of this block; per_row tiles along a row of the level.
+__device__ __forceinline__ void tile_index(int per_row, int& ti, int& tj) {
     const int t = xcd_remap(blockIdx.x, gridDim.x);
-    ti = t / per_side;
-    tj = t - ti * per_side;
+    ti = t / per_row;
+    tj = t - ti * per_row;
 }
 
 // Pass 1 in tile form: per-block Gram sums to partials[v * gridDim.x + blockIdx.x]
-// (layout of k_sstep_gram); Tile<M, X0, true, TT>::tiles(n) blocks.
+// (layout of k_sstep_gram); Tile<M, X0, true, TT>::tiles(nx, ny) blocks.
 template <typename T, int M, bool X0, int TT>
 __global__ __launch_bounds__(BLOCK) void k_sstep_gram_tile(AdrGeom A, const T* __restrict__ px,
                                                            const T* __restrict__ py,
@@ -857,7 +860,7 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_gram_tile(AdrGeom A, const T* _
 #pragma unroll
     for (int q = 0; q < NG; ++q) acc[q] = 0.0;
     int ti, tj;
-    tile_index(Tg::per_side(A.n), ti, tj);
+    tile_index(Tg::per_side(A.nx), ti, tj);
     sstep_tile<T, M, X0, true, TT>(A, ti, tj, px, py, c0, b, x0, buf,
                                    [&](int, int, int, bool own, cplx<T>, const cplx<T>(&k)[M + 1]) {
                                        if (own) gram_add<T, M>(acc, k);
@@ -867,7 +870,7 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_gram_tile(AdrGeom A, const T* _
 }
 
 // Pass 2 in tile form with the EPI_X epilogue: xout = x0 + sum c_j K_{j-1} on the own
-// nodes, and the zero ring (row 0, column 0); Tile<M, X0, false, TT>::tiles(n) blocks.
+// nodes, and the zero ring (row 0, column 0); Tile<M, X0, false, TT>::tiles(nx, ny) blocks.
 template <typename T, int M, bool X0, int TT>
 __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile(AdrGeom A, const T* __restrict__ px,
                                                               const T* __restrict__ py,
@@ -879,17 +882,17 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile(AdrGeom A, const T
     bshift(bi.off(), px, py, c0, b, x0, K, xout);
     using Tg = Tile<M, X0, false, TT>;
     __shared__ cplx<T> buf[2 * Tg::NR];
-    const int n = A.n;
+    const int nx = A.nx, ny = A.ny;
     cplx<T> c[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
     int ti, tj;
-    tile_index(Tg::per_side(n), ti, tj);
+    tile_index(Tg::per_side(nx), ti, tj);
     const int tid = threadIdx.x;
     if (tid < TT) {
         const int jr = 1 + tj * TT + tid, ir = 1 + ti * TT + tid;
-        if (ti == 0 && jr <= n - 1) xout[jr] = cplx<T>{};
-        if (tj == 0 && ir <= n - 1) xout[(size_t)ir * n] = cplx<T>{};
+        if (ti == 0 && jr <= nx - 1) xout[jr] = cplx<T>{};
+        if (tj == 0 && ir <= ny - 1) xout[(size_t)ir * nx] = cplx<T>{};
         if (ti == 0 && tj == 0 && tid == 0) xout[0] = cplx<T>{};
     }
     sstep_tile<T, M, X0, false, TT>(A, ti, tj, px, py, c0, b, x0, buf,
@@ -898,7 +901,7 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile(AdrGeom A, const T
                                         cplx<T> v = X0 ? xo : cplx<T>{};
 #pragma unroll
                                         for (int q = 0; q < M; ++q) v = v + c[q] * k[q];
-                                        st_off(xout, (unsigned)(gi * n + gj), v);
+                                        st_off(xout, (unsigned)(gi * nx + gj), v);
                                     });
 }
 
@@ -918,23 +921,23 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_rr(AdrGeom A, cons
     constexpr int RW = Tg::RW, H = Tg::H, TC = TT / 2;
     static_assert(TT % 2 == 0 && TC * TC <= BLOCK, "one coarse node per thread");
     __shared__ cplx<T> buf[2 * Tg::NR];
-    const int n = A.n, nc = n / 2;
+    const int nx = A.nx, ny = A.ny, ncx = nx / 2, ncy = ny / 2;
     cplx<T> c[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
     int ti, tj;
-    tile_index(Tg::per_side(n), ti, tj);
+    tile_index(Tg::per_side(nx), ti, tj);
     const int tid = threadIdx.x;
     if (tid < TT) {
         const int jr = 1 + tj * TT + tid, ir = 1 + ti * TT + tid;
-        if (ti == 0 && jr <= n - 1) xout[jr] = cplx<T>{};
-        if (tj == 0 && ir <= n - 1) xout[(size_t)ir * n] = cplx<T>{};
+        if (ti == 0 && jr <= nx - 1) xout[jr] = cplx<T>{};
+        if (tj == 0 && ir <= ny - 1) xout[(size_t)ir * nx] = cplx<T>{};
         if (ti == 0 && tj == 0 && tid == 0) xout[0] = cplx<T>{};
     }
     if (tid < TC) {
         const int Jr = 1 + tj * TC + tid, Ir = 1 + ti * TC + tid;
-        if (ti == 0 && Jr <= nc - 1) rc[Jr] = cplx<T>{};
-        if (tj == 0 && Ir <= nc - 1) rc[(size_t)Ir * nc] = cplx<T>{};
+        if (ti == 0 && Jr <= ncx - 1) rc[Jr] = cplx<T>{};
+        if (tj == 0 && Ir <= ncy - 1) rc[(size_t)Ir * ncx] = cplx<T>{};
         if (ti == 0 && tj == 0 && tid == 0) rc[0] = cplx<T>{};
     }
     cplx<T>* res = buf + ((Tg::NK + Tg::D) % 2) * Tg::NR;
@@ -947,7 +950,7 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_rr(AdrGeom A, cons
                                                  xv = xv + c[qq] * k[qq];
                                                  rv = rv - c[qq] * k[qq + 1];
                                              }
-                                             if (own) st_off(xout, (unsigned)(gi * n + gj), xv);
+                                             if (own) st_off(xout, (unsigned)(gi * nx + gj), xv);
                                              res[q] = rv;
                                          });
     __syncthreads();
@@ -956,12 +959,12 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_rr(AdrGeom A, cons
     if (tid < TC * TC) {
         const int ci = tid / TC, cj = tid - ci * TC;
         const int I = 1 + ti * TC + ci, J = 1 + tj * TC + cj;
-        if (I <= nc - 1 && J <= nc - 1) {
+        if (I <= ncy - 1 && J <= ncx - 1) {
             const int l = (1 + 2 * ci + H) * RW + 1 + 2 * cj + H;
             const cplx<T> cc = res[l];
             const cplx<T> ud = ((res[l - RW] + res[l + RW]) + res[l - 1]) + res[l + 1];
             const cplx<T> dg = ((res[l - RW - 1] + res[l - RW + 1]) + res[l + RW - 1]) + res[l + RW + 1];
-            st_off(rc, (unsigned)(I * nc + J), T(1.0 / 16.0) * ((T(4) * cc + T(2) * ud) + dg));
+            st_off(rc, (unsigned)(I * ncx + J), T(1.0 / 16.0) * ((T(4) * cc + T(2) * ud) + dg));
         }
     }
 }
@@ -969,7 +972,7 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_rr(AdrGeom A, cons
 // Tile form of pass 2 with the prolongation epilogue: x = x0 + sum_j c_j K_{j-1} on the
 // tile and a ring of one node (LDS), then xf += P x (bilinear) on the fine nodes of the
 // tile: fine rows and columns 2I and 2I + 1 of its coarse nodes, and row / column 1 on
-// the first tiles (xf has 2 n nodes per side; its zero ring is left alone).  x itself is
+// the first tiles (xf has 2 nx x 2 ny nodes; its zero ring is left alone).  x itself is
 // not stored: its only use is this prolongation.
 template <typename T, int M, bool X0, int TT>
 __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, const T* __restrict__ px,
@@ -983,12 +986,12 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, cons
     using Tg = Tile<M, X0, false, TT, 1>;
     constexpr int RW = Tg::RW, H = Tg::H;
     __shared__ cplx<T> buf[2 * Tg::NR];
-    const int n = A.n, nf = 2 * n;
+    const int nx = A.nx, ny = A.ny, nfx = 2 * nx;
     cplx<T> c[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) c[q] = mk<T>(T(K->y[2 * q]), T(K->y[2 * q + 1]));
     int ti, tj;
-    tile_index(Tg::per_side(n), ti, tj);
+    tile_index(Tg::per_side(nx), ti, tj);
     cplx<T>* xs = buf + ((Tg::NK + Tg::D) % 2) * Tg::NR;
     sstep_tile<T, M, X0, false, TT, 1>(A, ti, tj, px, py, c0, b, x0, buf,
                                        [&](int q, int, int, bool, cplx<T> xo, const cplx<T>(&k)[M]) {
@@ -998,8 +1001,8 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, cons
                                            xs[q] = v;
                                        });
     __syncthreads();
-    const int Ia = 1 + ti * TT, Ib = Ia + TT - 1 < n - 1 ? Ia + TT - 1 : n - 1;
-    const int Ja = 1 + tj * TT, Jb = Ja + TT - 1 < n - 1 ? Ja + TT - 1 : n - 1;
+    const int Ia = 1 + ti * TT, Ib = Ia + TT - 1 < ny - 1 ? Ia + TT - 1 : ny - 1;
+    const int Ja = 1 + tj * TT, Jb = Ja + TT - 1 < nx - 1 ? Ja + TT - 1 : nx - 1;
     const int f0 = ti == 0 ? 1 : 2 * Ia, f1 = 2 * Ib + 1;
     const int i0 = Ia - H, j0 = Ja - H;  // coarse node of region (0, 0)
     // fine columns in pairs (2J, 2J + 1) over the tile's coarse columns J, one read-modify-
@@ -1018,7 +1021,7 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, cons
             ve = T(0.5) * (xs[l] + xs[l + RW]);
             vo = T(0.25) * (((xs[l] + xs[l + RW]) + xs[l + 1]) + xs[l + RW + 1]);
         }
-        const unsigned p = (unsigned)(f * nf + 2 * J);
+        const unsigned p = (unsigned)(f * nfx + 2 * J);
         if constexpr (sizeof(T) == 4) {
             float4* a = reinterpret_cast<float4*>(reinterpret_cast<char*>(xf) + p * (unsigned)sizeof(cplx<T>));
             float4 w4 = *a;
@@ -1038,7 +1041,7 @@ __global__ __launch_bounds__(BLOCK) void k_sstep_combine_tile_pa(AdrGeom A, cons
             const int l = (I - i0) * RW + (0 - j0);
             const cplx<T> v = (f & 1) ? T(0.25) * (((xs[l] + xs[l + RW]) + xs[l + 1]) + xs[l + RW + 1])
                                       : T(0.5) * (xs[l] + xs[l + 1]);
-            const unsigned p = (unsigned)(f * nf + 1);
+            const unsigned p = (unsigned)(f * nfx + 1);
             st_off(xf, p, ld_off((const cplx<T>*)xf, p) + v);
         }
     }

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(TB) void k_gmres_block(BlockLevel<T> L, int x0_zero
     using C = cplx<T>;
     constexpr int TW = TB / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n = L.A.n, N = n * n, m = L.m;
+    const int n = L.A.nx, N = L.A.nx * L.A.ny, m = L.m;  // n: nodes per row
     const C* V0 = x0_zero ? L.b : L.V;
     auto vget = [&](int q, int p) -> C { return q == 0 ? V0[p] : L.V[(size_t)q * N + p]; };
     // r0 and beta

@@ -17,11 +17,11 @@ constexpr int TWY = 4;   // wavefronts per block
 constexpr int RPT = 4;   // rows per thread
 constexpr int TY = TWY * RPT;
 
-__host__ __device__ inline int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
+__host__ __device__ inline int tiles_of(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
 
-// Column j and first row i0 of this thread's strip.
-__device__ __forceinline__ void tile_origin(int n, int& j, int& i0) {
-    const int ntx = (n + TX - 1) / TX;
+// Column j and first row i0 of this thread's strip (nx nodes per row).
+__device__ __forceinline__ void tile_origin(int nx, int& j, int& i0) {
+    const int ntx = (nx + TX - 1) / TX;
     const int nb = gridDim.x;
     int b = blockIdx.x;
     b = xcd_remap(b, nb);
@@ -32,10 +32,12 @@ __device__ __forceinline__ void tile_origin(int n, int& j, int& i0) {
 
 // Reduction kernels run at most MAXRED blocks; each block owns a contiguous chunk
 // of tiles [t0, t1) (XCD-aware block order as above).
-__host__ __device__ inline int red_blocks(int n) { return tiles_of(n) < MAXRED ? tiles_of(n) : MAXRED; }
+__host__ __device__ inline int red_blocks(int nx, int ny) {
+    return tiles_of(nx, ny) < MAXRED ? tiles_of(nx, ny) : MAXRED;
+}
 
-__device__ __forceinline__ void tile_chunk(int n, int& t0, int& t1) {
-    const int nt = tiles_of(n);
+__device__ __forceinline__ void tile_chunk(int nx, int ny, int& t0, int& t1) {
+    const int nt = tiles_of(nx, ny);
     const int nb = gridDim.x;
     int b = blockIdx.x;
     b = xcd_remap(b, nb);
@@ -44,8 +46,8 @@ __device__ __forceinline__ void tile_chunk(int n, int& t0, int& t1) {
     t1 = t0 + per < nt ? t0 + per : nt;
 }
 
-__device__ __forceinline__ void tile_xy(int n, int t, int& j, int& i0) {
-    const int ntx = (n + TX - 1) / TX;
+__device__ __forceinline__ void tile_xy(int nx, int t, int& j, int& i0) {
+    const int ntx = (nx + TX - 1) / TX;
     j = (t % ntx) * TX + threadIdx.x;
     i0 = (t / ntx) * TY + threadIdx.y * RPT;
 }
@@ -59,7 +61,7 @@ struct TileRing {
     static constexpr int W = TX + 2 * R, NR = (TY + 2 * R) * W, NQ = (NR + BLOCK - 1) / BLOCK;
 };
 template <int R, typename V>
-__device__ __forceinline__ void tile_fetch(const V* __restrict__ a, int n, int it, int jt,
+__device__ __forceinline__ void tile_fetch(const V* __restrict__ a, int nx, int ny, int it, int jt,
                                            V (&v)[TileRing<R>::NQ]) {
     using TR = TileRing<R>;
     const int tid = threadIdx.x + threadIdx.y * TX;
@@ -69,7 +71,7 @@ __device__ __forceinline__ void tile_fetch(const V* __restrict__ a, int n, int i
         const int ri = q / TR::W, rj = q - ri * TR::W;
         const int gi = it - R + ri, gj = jt - R + rj;
         v[k] = V{};
-        if (q < TR::NR && gi >= 1 && gj >= 1 && gi < n && gj < n) v[k] = a[(size_t)gi * n + gj];
+        if (q < TR::NR && gi >= 1 && gj >= 1 && gi < ny && gj < nx) v[k] = a[(size_t)gi * nx + gj];
     }
 }
 template <int R, typename V>
@@ -84,9 +86,10 @@ __device__ __forceinline__ void tile_store(const V (&v)[TileRing<R>::NQ], V* s) 
 }
 
 template <typename T>
-__device__ __forceinline__ cplx<T> lap_at(const cplx<T>* __restrict__ u, int i, int j, int n, T inv_h2) {
-    cplx<T> c = u[(size_t)i * n + j];
-    cplx<T> nb = ldz(u, i - 1, j, n) + ldz(u, i + 1, j, n) + ldz(u, i, j - 1, n) + ldz(u, i, j + 1, n);
+__device__ __forceinline__ cplx<T> lap_at(const cplx<T>* __restrict__ u, int i, int j, int nx, int ny, T inv_h2) {
+    cplx<T> c = u[(size_t)i * nx + j];
+    cplx<T> nb = ldz(u, i - 1, j, nx, ny) + ldz(u, i + 1, j, nx, ny) + ldz(u, i, j - 1, nx, ny) +
+                 ldz(u, i, j + 1, nx, ny);
     return inv_h2 * (T(4) * c - nb);
 }
 
@@ -94,16 +97,16 @@ __device__ __forceinline__ cplx<T> lap_at(const cplx<T>* __restrict__ u, int i, 
 template <typename T>
 __device__ __forceinline__ cplx<T> applyA_at(const Geom& G, const T* __restrict__ n2, const cplx<T>* __restrict__ u,
                                              int i, int j, bool conj_k) {
-    const int n = G.n;
-    cplx<T> kap = kappa_at<T>(G, n2[(size_t)i * n + j], i, j);
+    const int nx = G.nx;
+    cplx<T> kap = kappa_at<T>(G, n2[(size_t)i * nx + j], i, j);
     if (conj_k) kap.im = -kap.im;
-    return lap_at(u, i, j, n, T(G.inv_h2)) - kap * u[(size_t)i * n + j];
+    return lap_at(u, i, j, nx, G.ny, T(G.inv_h2)) - kap * u[(size_t)i * nx + j];
 }
 
 template <typename T>
 __device__ __forceinline__ cplx<T> resid_at(const Geom& G, const T* __restrict__ n2, const cplx<T>* __restrict__ g,
                                             const cplx<T>* __restrict__ u, int i, int j) {
-    cplx<T> gv = g[(size_t)i * G.n + j];
+    cplx<T> gv = g[(size_t)i * G.nx + j];
     if (u == nullptr) return gv;
     return gv - applyA_at(G, n2, u, i, j, false);
 }
@@ -114,14 +117,14 @@ __global__ __launch_bounds__(BLOCK) void k_apply_A(Geom G, const T* __restrict__
                                                    cplx<T>* __restrict__ y, int conj_k, BatchIdx bi) {
     bshift(bi.off(), n2, x, y);
     int j, i0;
-    tile_origin(G.n, j, i0);
-    if (j >= G.n) return;
+    tile_origin(G.nx, j, i0);
+    if (j >= G.nx) return;
     for (int r = 0; r < RPT; ++r) {
         const int i = i0 + r;
-        if (i >= G.n) break;
+        if (i >= G.ny) break;
         cplx<T> v{};
         if (i > 0 && j > 0) v = applyA_at(G, n2, x, i, j, conj_k != 0);
-        y[(size_t)i * G.n + j] = v;
+        y[(size_t)i * G.nx + j] = v;
     }
 }
 
@@ -131,14 +134,14 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom G, const T* __restrict_
                                                     const cplx<T>* __restrict__ u, cplx<T>* __restrict__ r, BatchIdx bi) {
     bshift(bi.off(), n2, g, u, r);
     int j, i0;
-    tile_origin(G.n, j, i0);
-    if (j >= G.n) return;
+    tile_origin(G.nx, j, i0);
+    if (j >= G.nx) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        if (i >= G.n) break;
+        if (i >= G.ny) break;
         cplx<T> v{};
         if (i > 0 && j > 0) v = resid_at(G, n2, g, u, i, j);
-        r[(size_t)i * G.n + j] = v;
+        r[(size_t)i * G.nx + j] = v;
     }
 }
 
@@ -152,22 +155,22 @@ __global__ __launch_bounds__(BLOCK) void k_residual_norms(Geom G, const double* 
     __shared__ double sums[2];
     double acc[2] = {0.0, 0.0};
     int t0, t1;
-    tile_chunk(G.n, t0, t1);
+    tile_chunk(G.nx, G.ny, t0, t1);
     for (int t = t0; t < t1; ++t) {
         int j, i0;
-        tile_xy(G.n, t, j, i0);
-        if (j >= G.n) continue;
+        tile_xy(G.nx, t, j, i0);
+        if (j >= G.nx) continue;
         for (int rr = 0; rr < RPT; ++rr) {
             const int i = i0 + rr;
-            if (i >= G.n) break;
+            if (i >= G.ny) break;
             c128 v{};
             if (i > 0 && j > 0) {
                 v = resid_at(G, n2, g, u, i, j);
-                c128 gv = g[(size_t)i * G.n + j];
+                c128 gv = g[(size_t)i * G.nx + j];
                 acc[0] += v.re * v.re + v.im * v.im;
                 acc[1] += gv.re * gv.re + gv.im * gv.im;
             }
-            if (r) r[(size_t)i * G.n + j] = v;
+            if (r) r[(size_t)i * G.nx + j] = v;
         }
     }
     block_sum<2, 4>(acc, 2, red, sums);
@@ -192,17 +195,17 @@ __global__ __launch_bounds__(FBLOCK) void k_finalize_sums(const double* __restri
 // instead of 2.25 times).  Coarse tiles are assigned XCD-aware as in tile_origin.
 constexpr int RCX = 32, RCY = 16;
 
-__host__ __device__ inline int rr_blocks(int n) {
-    const int nc = n / 2;
-    return ((nc + RCX - 1) / RCX) * ((nc + RCY - 1) / RCY);
+__host__ __device__ inline int rr_blocks(int nx, int ny) {
+    const int ncx = nx / 2, ncy = ny / 2;
+    return ((ncx + RCX - 1) / RCX) * ((ncy + RCY - 1) / RCY);
 }
 
 template <typename Tf, typename Tc, typename Res>
-__device__ __forceinline__ void restrict_tile(int n, const Res& res, cplx<Tc>* __restrict__ rc) {
+__device__ __forceinline__ void restrict_tile(int nx, int ny, const Res& res, cplx<Tc>* __restrict__ rc) {
     constexpr int FW = 2 * RCX + 1, FH = 2 * RCY + 1;
     __shared__ cplx<Tf> r[FH * FW];
-    const int nc = n / 2;
-    const int ntx = (nc + RCX - 1) / RCX;
+    const int ncx = nx / 2, ncy = ny / 2;
+    const int ntx = (ncx + RCX - 1) / RCX;
     const int nb = gridDim.x;
     int b = blockIdx.x;
     b = xcd_remap(b, nb);
@@ -212,14 +215,14 @@ __device__ __forceinline__ void restrict_tile(int n, const Res& res, cplx<Tc>* _
         const int ri = q / FW, rj = q - ri * FW;
         const int fi = fi0 + ri, fj = fj0 + rj;
         cplx<Tf> v{};
-        if (fi >= 1 && fj >= 1 && fi < n && fj < n) v = res(fi, fj);
+        if (fi >= 1 && fj >= 1 && fi < ny && fj < nx) v = res(fi, fj);
         r[q] = v;
     }
     __syncthreads();
     for (int q = threadIdx.x; q < RCX * RCY; q += BLOCK) {
         const int ci = q / RCX, cj = q - ci * RCX;
         const int I = I0 + ci, J = J0 + cj;
-        if (I >= nc || J >= nc) continue;
+        if (I >= ncy || J >= ncx) continue;
         cplx<Tf> v{};
         if (I > 0 && J > 0) {
             const int l = (2 * ci + 1) * FW + 2 * cj + 1;
@@ -228,7 +231,7 @@ __device__ __forceinline__ void restrict_tile(int n, const Res& res, cplx<Tc>* _
             const cplx<Tf> dg = ((r[l - FW - 1] + r[l - FW + 1]) + r[l + FW - 1]) + r[l + FW + 1];
             v = Tf(1.0 / 16.0) * ((Tf(4) * c + Tf(2) * ud) + dg);
         }
-        rc[(size_t)I * nc + J] = ccast<Tc>(v);
+        rc[(size_t)I * ncx + J] = ccast<Tc>(v);
     }
 }
 
@@ -241,22 +244,24 @@ struct HelmRes {
     __device__ cplx<Tf> operator()(int i, int j) const { return resid_at(G, n2, g, u, i, j); }
 };
 
-// rc = R (g - A u) on the coarse grid of size G.n/2 (u == nullptr: u = 0); rr_blocks(G.n) blocks.
+// rc = R (g - A u) on the coarse grid of G.nx/2 x G.ny/2 nodes (u == nullptr: u = 0);
+// rr_blocks(G.nx, G.ny) blocks.
 template <typename Tf, typename Tc>
 __global__ __launch_bounds__(BLOCK) void k_resid_restrict(Geom G, const Tf* __restrict__ n2,
                                                           const cplx<Tf>* __restrict__ g,
                                                           const cplx<Tf>* __restrict__ u, cplx<Tc>* __restrict__ rc, BatchIdx bi) {
     bshift(bi.off(), n2, g, u, rc);
-    restrict_tile<Tf, Tc>(G.n, HelmRes<Tf>{G, n2, g, u}, rc);
+    restrict_tile<Tf, Tc>(G.nx, G.ny, HelmRes<Tf>{G, n2, g, u}, rc);
 }
 
-// u += P ec (bilinear interpolation, P = 4 R^T); ec has nc = n/2 nodes per side.
+// u += P ec (bilinear interpolation, P = 4 R^T); ec has ncx = nx/2 nodes per row and
+// ncy = ny/2 rows.
 template <typename Tc, typename Tf>
-__device__ __forceinline__ cplx<Tf> prolong_at(const cplx<Tc>* __restrict__ ec, int nc, int i, int j) {
+__device__ __forceinline__ cplx<Tf> prolong_at(const cplx<Tc>* __restrict__ ec, int ncx, int ncy, int i, int j) {
     const int I = i >> 1, J = j >> 1;
     auto e = [&](int a, int b) -> cplx<Tc> {
-        if (a <= 0 || b <= 0 || a >= nc || b >= nc) return cplx<Tc>{};
-        return ec[(size_t)a * nc + b];
+        if (a <= 0 || b <= 0 || a >= ncy || b >= ncx) return cplx<Tc>{};
+        return ec[(size_t)a * ncx + b];
     };
     cplx<Tc> v;
     if (!(i & 1) && !(j & 1)) {
@@ -272,38 +277,39 @@ __device__ __forceinline__ cplx<Tf> prolong_at(const cplx<Tc>* __restrict__ ec, 
 }
 
 template <typename Tc, typename Tf>
-__global__ __launch_bounds__(BLOCK) void k_prolong_add(int n, const cplx<Tc>* __restrict__ ec, cplx<Tf>* __restrict__ u, BatchIdx bi) {
+__global__ __launch_bounds__(BLOCK) void k_prolong_add(int nx, int ny, const cplx<Tc>* __restrict__ ec,
+                                                       cplx<Tf>* __restrict__ u, BatchIdx bi) {
     bshift(bi.off(), ec, u);
     int j, i0;
-    tile_origin(n, j, i0);
-    if (j >= n) return;
-    const int nc = n / 2;
+    tile_origin(nx, j, i0);
+    if (j >= nx) return;
     for (int r = 0; r < RPT; ++r) {
         const int i = i0 + r;
-        if (i >= n) break;
+        if (i >= ny) break;
         if (i == 0 || j == 0) continue;
-        cplx<Tf>* p = u + (size_t)i * n + j;
-        *p = *p + prolong_at<Tc, Tf>(ec, nc, i, j);
+        cplx<Tf>* p = u + (size_t)i * nx + j;
+        *p = *p + prolong_at<Tc, Tf>(ec, nx / 2, ny / 2, i, j);
     }
 }
 
 // u += P ec (assign: u = P ec) over pairs of fine columns (2J, 2J + 1): one coarse column
 // pair and one row parity per thread, one 16-byte read-modify-write per pair in FP32.
-// (n - 1) (n/2) pairs of rows 1..n-1 (assign also writes row 0); coarse values off the
+// (ny - 1) (nx/2) pairs of rows 1..ny-1 (assign also writes row 0); coarse values off the
 // unknowns read index 0 (the zero ring), so column 0 receives 0.
 template <typename Tc, typename Tf>
-__global__ __launch_bounds__(BLOCK) void k_prolong_pairs(int n, const cplx<Tc>* __restrict__ ec,
+__global__ __launch_bounds__(BLOCK) void k_prolong_pairs(int nx, int ny, const cplx<Tc>* __restrict__ ec,
                                                          cplx<Tf>* __restrict__ u, int assign, BatchIdx bi) {
     bshift(bi.off(), ec, u);
-    const int nc = n / 2;
-    const size_t NP = (size_t)n * nc;
+    const int ncx = nx / 2, ncy = ny / 2;
+    const size_t NP = (size_t)ny * ncx;
     auto e = [&](int a, int b) -> cplx<Tc> {
-        const bool in = a >= 1 && b >= 1 && a < nc && b < nc;
-        return ec[in ? (size_t)a * nc + b : 0];
+        const bool in = a >= 1 && b >= 1 && a < ncy && b < ncx;
+        return ec[in ? (size_t)a * ncx + b : 0];
     };
     for (size_t q = (size_t)blockIdx.x * BLOCK + threadIdx.x; q < NP; q += (size_t)gridDim.x * BLOCK) {
-        const int f = (int)(q / nc), J = (int)(q - (size_t)f * nc);
-        const size_t p = (size_t)f * n + 2 * J;
+        int f, J;
+        rowcol(q, ncx, f, J);
+        const size_t p = (size_t)f * nx + 2 * J;
         cplx<Tf> ve{}, vo{};
         if (f > 0) {
             const int I = f >> 1;
@@ -345,21 +351,21 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(Geom G, const T* __restrict__ 
     bshift(bi.off(), n2, g, uin, uout, wp);
     const T w = T(wp[0]);
     int j, i0;
-    tile_origin(G.n, j, i0);
-    if (j >= G.n) return;
+    tile_origin(G.nx, j, i0);
+    if (j >= G.nx) return;
     for (int r = 0; r < RPT; ++r) {
         const int i = i0 + r;
-        if (i >= G.n) break;
+        if (i >= G.ny) break;
         cplx<T> v{};
         if (i > 0 && j > 0) {
-            const size_t p = (size_t)i * G.n + j;
+            const size_t p = (size_t)i * G.nx + j;
             cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
             cplx<T> d = mk<T>(T(4) * T(G.inv_h2) - kap.re, -kap.im);
             cplx<T> res = resid_at(G, n2, g, uin, i, j);
             cplx<T> u0 = uin ? uin[p] : cplx<T>{};
             v = u0 + w * cdiv(res, d);
         }
-        uout[(size_t)i * G.n + j] = v;
+        uout[(size_t)i * G.nx + j] = v;
     }
 }
 
@@ -372,14 +378,14 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start(Geom G, const T* __restric
     bshift(bi.off(), n2, t, r, d, cc);
     const T inv_theta = T(cc[0]);
     int j, i0;
-    tile_origin(G.n, j, i0);
-    if (j >= G.n) return;
+    tile_origin(G.nx, j, i0);
+    if (j >= G.nx) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        if (i >= G.n) break;
+        if (i >= G.ny) break;
         cplx<T> v{};
         if (i > 0 && j > 0) v = applyA_at(G, n2, t, i, j, true);
-        const size_t p = (size_t)i * G.n + j;
+        const size_t p = (size_t)i * G.nx + j;
         r[p] = v;
         d[p] = inv_theta * v;
     }
@@ -400,17 +406,17 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __res
     __shared__ cplx<T> sg[HH * HW];
     __shared__ T sn[HH * HW];
     __shared__ cplx<T> ts[HH * HW];
-    const int n = G.n;
+    const int nx = G.nx, ny = G.ny;
     const T ih2 = T(G.inv_h2);
     int j, i0;
-    tile_origin(n, j, i0);
+    tile_origin(nx, j, i0);
     const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
     const int tid = threadIdx.x + threadIdx.y * TX;
     cplx<T> fu[TileRing<2>::NQ], fg[TileRing<1>::NQ];
     T fn[TileRing<1>::NQ];
-    tile_fetch<2>(u, n, it, jt, fu);
-    tile_fetch<1>(g, n, it, jt, fg);
-    tile_fetch<1>(n2, n, it, jt, fn);
+    tile_fetch<2>(u, nx, ny, it, jt, fu);
+    tile_fetch<1>(g, nx, ny, it, jt, fg);
+    tile_fetch<1>(n2, nx, ny, it, jt, fn);
     tile_store<2>(fu, su);
     tile_store<1>(fg, sg);
     tile_store<1>(fn, sn);
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __res
         const int ri = q / HW, rj = q - ri * HW;
         const int gi = it - 1 + ri, gj = jt - 1 + rj;
         cplx<T> v{};
-        if (gi >= 1 && gj >= 1 && gi < n && gj < n) {
+        if (gi >= 1 && gj >= 1 && gi < ny && gj < nx) {
             const int l = (ri + 1) * UW + rj + 1;
             const cplx<T> c = su[l];
             const cplx<T> lap = ih2 * (T(4) * c - (((su[l - UW] + su[l + UW]) + su[l - 1]) + su[l + 1]));
@@ -428,11 +434,11 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_start_res(Geom G, const T* __res
         ts[q] = v;
     }
     __syncthreads();
-    if (j >= n) return;
+    if (j >= nx) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        if (i >= n) break;
-        const size_t p = (size_t)i * n + j;
+        if (i >= ny) break;
+        const size_t p = (size_t)i * nx + j;
         cplx<T> v{};
         if (i > 0 && j > 0) {
             const int l = (i - it + 1) * HW + (j - jt + 1);
@@ -465,24 +471,24 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
     __shared__ cplx<T> sd[DH * DW];
     __shared__ T sn[HH * HW];
     __shared__ cplx<T> ts[HH * HW];
-    const int n = G.n;
+    const int nx = G.nx, ny = G.ny;
     const T ih2 = T(G.inv_h2);
     int j, i0;
-    tile_origin(n, j, i0);
+    tile_origin(nx, j, i0);
     const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
     const int tid = threadIdx.x + threadIdx.y * TX;
     // the tile fields and the own rows of r and u are all loaded before the first store
     cplx<T> fd[TileRing<2>::NQ];
     T fn[TileRing<1>::NQ];
-    tile_fetch<2>(d_in, n, it, jt, fd);
-    tile_fetch<1>(n2, n, it, jt, fn);
+    tile_fetch<2>(d_in, nx, ny, it, jt, fd);
+    tile_fetch<1>(n2, nx, ny, it, jt, fn);
     cplx<T> rv0[RPT], uv0[RPT];
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
         rv0[rr] = uv0[rr] = cplx<T>{};
-        if (i >= 1 && i < n && j >= 1 && j < n) {
-            const size_t p = (size_t)i * n + j;
+        if (i >= 1 && i < ny && j >= 1 && j < nx) {
+            const size_t p = (size_t)i * nx + j;
             rv0[rr] = r[p];
             if (!(mode & CHEB_UZERO)) uv0[rr] = u[p];
         }
@@ -494,7 +500,7 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
         const int ri = q / HW, rj = q - ri * HW;
         const int gi = it - 1 + ri, gj = jt - 1 + rj;
         cplx<T> v{};
-        if (gi >= 1 && gj >= 1 && gi < n && gj < n) {
+        if (gi >= 1 && gj >= 1 && gi < ny && gj < nx) {
             const int l = (ri + 1) * DW + rj + 1;
             const cplx<T> c = sd[l];
             const cplx<T> lap = ih2 * (T(4) * c - (((sd[l - DW] + sd[l + DW]) + sd[l - 1]) + sd[l + 1]));
@@ -503,11 +509,11 @@ __global__ __launch_bounds__(BLOCK) void k_cheb_fused(Geom G, const T* __restric
         ts[q] = v;
     }
     __syncthreads();
-    if (j >= n) return;
+    if (j >= nx) return;
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + rr;
-        if (i >= n) break;
-        const size_t p = (size_t)i * n + j;
+        if (i >= ny) break;
+        const size_t p = (size_t)i * nx + j;
         if (i == 0 || j == 0) {  // keep the ring of the alternate d buffer (and of u) zero
             if (!(mode & CHEB_LAST)) d_out[p] = cplx<T>{};
             if (mode & CHEB_UZERO) u[p] = cplx<T>{};
@@ -609,14 +615,16 @@ __global__ __launch_bounds__(BLOCK) void k_zero(size_t N, cplx<T>* __restrict__ 
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) y[p] = cplx<T>{};
 }
 
-// Injection of a fine real field to a level (stride s); double -> T.
+// Injection of a fine real field (nfx nodes per row) to a level of nx x ny nodes
+// (stride s); double -> T.
 template <typename T, typename Ti>
-__global__ __launch_bounds__(BLOCK) void k_inject_real(int n, int s, int nf, const Ti* __restrict__ fine, T* __restrict__ out) {
-    size_t N = (size_t)n * n;
+__global__ __launch_bounds__(BLOCK) void k_inject_real(int nx, int ny, int s, int nfx, const Ti* __restrict__ fine,
+                                                       T* __restrict__ out) {
+    size_t N = (size_t)nx * ny;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
-        rowcol(p, n, i, j);
-        out[p] = T(fine[(size_t)i * s * nf + (size_t)j * s]);
+        rowcol(p, nx, i, j);
+        out[p] = T(fine[(size_t)i * s * nfx + (size_t)j * s]);
     }
 }
 
@@ -634,12 +642,13 @@ __global__ __launch_bounds__(BLOCK) void k_slowness2(size_t N, const double* __r
     }
 }
 
-// Per-level statistics over the unknowns (1 <= i, j <= n-1): per-block max |4/h^2 - kappa|,
-// max n2 and sum n2, stored as partials[3 * block + {0,1,2}] (combined on the host).
+// Per-level statistics over the unknowns (1 <= i <= ny-1, 1 <= j <= nx-1): per-block
+// max |4/h^2 - kappa|, max n2 and sum n2, stored as partials[3 * block + {0,1,2}]
+// (combined on the host).
 __global__ __launch_bounds__(BLOCK) void k_level_stats(Geom G, const double* __restrict__ n2, double* partials) {
     __shared__ double red[4 * 3];
-    const int n = G.n;
-    const size_t N = (size_t)n * n;
+    const int n = G.nx;
+    const size_t N = (size_t)G.nx * G.ny;
     double mx = 0.0, mn2 = 0.0, sn2 = 0.0;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;

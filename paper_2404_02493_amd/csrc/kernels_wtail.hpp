@@ -41,8 +41,8 @@ struct TailWaveArgs {
 template <typename P>
 __device__ void wt_cheb(const TailWaveLevel& W, bool u_zero, int m, size_t o) {
     const Geom& G = W.G;
-    const int n = G.n;
-    const int N = n * n;
+    const int n = G.nx;  // nodes per row
+    const int N = G.nx * G.ny;
     const P* n2 = (const P*)bsh_one(o, W.n2);
     cplx<P>* g = (cplx<P>*)bsh_one(o, W.g);
     cplx<P>* u = (cplx<P>*)bsh_one(o, W.u);
@@ -105,13 +105,13 @@ __device__ void wt_cheb(const TailWaveLevel& W, bool u_zero, int m, size_t o) {
 template <typename Pf, typename Pc>
 __device__ void wt_restrict(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero, size_t o) {
     const Geom& G = F.G;
-    const int n = G.n, nc = n / 2;
+    const int ncx = G.nx / 2, ncy = G.ny / 2;
     const Pf* n2 = (const Pf*)bsh_one(o, F.n2);
     const cplx<Pf>* g = (const cplx<Pf>*)bsh_one(o, F.g);
     const cplx<Pf>* u = u_zero ? nullptr : (const cplx<Pf>*)bsh_one(o, F.u);
     cplx<Pc>* gc = (cplx<Pc>*)bsh_one(o, Cl.g);
-    for (int q = threadIdx.x; q < nc * nc; q += WT_THREADS) {
-        const int I = q / nc, J = q - I * nc;
+    for (int q = threadIdx.x; q < ncx * ncy; q += WT_THREADS) {
+        const int I = q / ncx, J = q - I * ncx;
         cplx<Pf> v{};
         if (I > 0 && J > 0) {
             const int fi = 2 * I, fj = 2 * J;
@@ -129,13 +129,13 @@ __device__ void wt_restrict(const TailWaveLevel& F, const TailWaveLevel& Cl, boo
 // u (level l, precision Pf) += P e (level l + 1, precision Pc); u_zero: u = P e.
 template <typename Pc, typename Pf>
 __device__ void wt_prolong(const TailWaveLevel& F, const TailWaveLevel& Cl, bool u_zero, size_t o) {
-    const int n = F.G.n, nc = n / 2;
+    const int n = F.G.nx, ny = F.G.ny;
     cplx<Pf>* u = (cplx<Pf>*)bsh_one(o, F.u);
     const cplx<Pc>* ec = (const cplx<Pc>*)bsh_one(o, Cl.u);
-    for (int p = threadIdx.x; p < n * n; p += WT_THREADS) {
+    for (int p = threadIdx.x; p < n * ny; p += WT_THREADS) {
         const int i = p / n, j = p - i * n;
         cplx<Pf> v{};
-        if (i > 0 && j > 0) v = prolong_at<Pc, Pf>(ec, nc, i, j);
+        if (i > 0 && j > 0) v = prolong_at<Pc, Pf>(ec, n / 2, ny / 2, i, j);
         u[p] = u_zero ? v : u[p] + v;
     }
     __syncthreads();

@@ -19,8 +19,8 @@
 
 // x = hashed values in [-1, 1] + i [-1, 1] on the unknowns, 0 on the ring.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_fill_hash(int n, uint32_t seed, cplx<T>* __restrict__ x) {
-    const size_t N = (size_t)n * n;
+__global__ __launch_bounds__(BLOCK) void k_fill_hash(int n, int ny, uint32_t seed, cplx<T>* __restrict__ x) {
+    const size_t N = (size_t)n * ny;  // n nodes per row, ny rows
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         const int i = (int)(p / n), j = (int)(p % n);
         uint64_t h = (uint64_t)p * 0x9E3779B97F4A7C15ull + seed;
@@ -60,7 +60,9 @@ static double time_ms(hipStream_t st, int reps, F&& f) {
 }
 
 static std::string tuning_json(helm_ctx c, const std::string& timings) {
-    std::string out = "{\"n\": " + std::to_string(c->d.n) + ", \"levels\": " + std::to_string(c->L) +
+    std::string out = "{\"n\": " + std::to_string(c->d.n) +
+                      (c->d.ny != c->d.n ? ", \"ny\": " + std::to_string(c->d.ny) : std::string()) +
+                      ", \"levels\": " + std::to_string(c->L) +
                       ", \"prec\": \"" + (c->f32 ? "c64" : "c128") + "\", \"sstep_rows\": {";
     bool first = true;
     for (int l = 2; l <= c->LA && l < 16; ++l) {
@@ -92,20 +94,20 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
             AdrLevel& A = c->al[l];
             const int m = l == c->LA ? c->d.gmres_coarse_m : c->d.gmres_m;
             if (m > 4) continue;
-            if (l == c->LA && A.n <= c->d.tail_n && (size_t)A.n * A.n <= 4096) continue;  // one-workgroup form
-            const int nb = flat_blocks((size_t)A.n * A.n);
-            hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.n, 17u + l, (cplx<T>*)A.b);
-            hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.n, 91u + l, (cplx<T>*)A.x);
+            if (E.block_form(l, m)) continue;  // one-workgroup form
+            const int nb = flat_blocks((size_t)A.nx * A.ny);
+            hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.nx, A.ny, 17u + l, (cplx<T>*)A.b);
+            hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, A.nx, A.ny, 91u + l, (cplx<T>*)A.x);
             if (l == 2) {
                 WaveLevel& W = c->wl[2];
-                hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, W.n, 23u, (cplx<T>*)W.g);
-                hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, W.n, 29u, (cplx<T>*)W.u);
+                hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, W.nx, W.ny, 23u, (cplx<T>*)W.g);
+                hipLaunchKernelGGL((k_fill_hash<T>), dim3(nb), dim3(BLOCK), 0, st, W.nx, W.ny, 29u, (cplx<T>*)W.u);
             }
             HIPCHK(hipGetLastError());
             int best = 0;
             double tbest = 1e30;
             for (int cand : {1, 2, 16, 24, 32, 40, 48, 64, 80, 96, 128}) {
-                if (cand > 16 && cand >= 2 * A.n) break;
+                if (cand > 16 && cand >= 2 * A.ny) break;  // segments run down the rows
                 c->tn.sstep_rows[l] = cand;
                 const double t = time_ms(st, reps, [&] {
                     if (l > 2) {
@@ -132,15 +134,16 @@ static std::string tune_ctx(helm_ctx c, hipStream_t st) {
         const int mode = c->f32 ? 1 : 0;
         ensure_solver_ws(c, mode);
         const Geom G = make_geom_sys(c);
-        const size_t NF = (size_t)G.n * G.n;
+        const size_t NF = (size_t)G.nx * G.ny;
         const int jj = std::max(0, c->d.restart / 2);
         void** Vp = c->f32 ? c->iV : c->fV;
         void** Zp = c->f32 ? c->iZ : c->fZ;
         const void* n2 = c->f32 ? c->wl[1].n2 : (const void*)c->n2f;
         for (int i = 0; i <= jj + 1; ++i)
-            hipLaunchKernelGGL((k_fill_hash<T>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, G.n, 1000u + i,
+            hipLaunchKernelGGL((k_fill_hash<T>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, G.nx, G.ny, 1000u + i,
                                (cplx<T>*)Vp[i]);
-        hipLaunchKernelGGL((k_fill_hash<T>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, G.n, 7u, (cplx<T>*)Zp[0]);
+        hipLaunchKernelGGL((k_fill_hash<T>), dim3(flat_blocks(NF)), dim3(BLOCK), 0, st, G.nx, G.ny, 7u,
+                           (cplx<T>*)Zp[0]);
         hipLaunchKernelGGL(k_tune_kstate, dim3(1), dim3(64), 0, st, c->Kin);
         HIPCHK(hipGetLastError());
         VecSet<T> Vs{};

@@ -43,8 +43,10 @@ def assert_close(a, b, tol, what=""):
 
 
 def rand_grid(rng, n, dtype=torch.complex128):
-    """Random complex grid, zero on the ring; values representable in ``dtype``."""
-    v = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    """Random complex grid of n x n (or of shape n = (rows, columns)), zero on the ring;
+    values representable in ``dtype``."""
+    shape = (n, n) if isinstance(n, int) else tuple(n)
+    v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     v[0, :] = 0
     v[:, 0] = 0
     return torch.as_tensor(v).to(dtype).to(torch.complex128)
@@ -90,8 +92,13 @@ def operator_report(c, P, H, prec, rng):
     cd = H.cdtype
     L = c.levels
     report = {}
+
+    def shape(l, half=False):  # (rows, columns) of level l (half: of level l + 1)
+        s = l if not half else l + 1
+        return (c.rows >> (s - 1), c.n >> (s - 1))
+
     for l in range(1, L + 1):
-        nl = c.n >> (l - 1)
+        nl = shape(l)
         dt = H.level_dtype(l)
         x = rounded(_rand(rng, nl), dt)
         out = H.debug_op(1, l, to_dev(x, dt), out_dtype=dt)
@@ -100,7 +107,7 @@ def operator_report(c, P, H, prec, rng):
             dtc = H.level_dtype(l + 1)
             out = H.debug_op(2, l, to_dev(x, dt), out_shape_level=l + 1, out_dtype=dtc)
             report[f"R{l}"] = measure(out, restrict_fw(x))
-            e = rounded(_rand(rng, nl // 2), dtc)
+            e = rounded(_rand(rng, shape(l, True)), dtc)
             base = rounded(_rand(rng, nl), dt)
             outp = to_dev(base, dt)
             H.debug_op(3, l, to_dev(e, dtc), out=outp)
@@ -109,24 +116,24 @@ def operator_report(c, P, H, prec, rng):
             out = H.debug_op(11, l, to_dev(x, dt), to_dev(g, dt), out_shape_level=l + 1, out_dtype=dtc)
             report[f"RR{l}"] = measure(out, restrict_fw(g - apply_A(x, P.kappa[l], P.h[l])))
     # Jacobi (level 1)
-    x, g = rounded(_rand(rng, c.n), cd), rounded(_rand(rng, c.n), cd)
+    x, g = rounded(_rand(rng, shape(1)), cd), rounded(_rand(rng, shape(1)), cd)
     out = H.debug_op(4, 1, to_dev(x, cd), to_dev(g, cd))
     report["J1"] = measure(out, jacobi(x, g, P.kappa[1], P.h[1], P.weights[0]))
     # Chebyshev on level 2 (pre count) and the coarsest level
     for l, m in [(2, P.cheb_pre), (L, P.cheb_coarse)]:
-        nl = c.n >> (l - 1)
+        nl = shape(l)
         dt = H.level_dtype(l)
         x, g = rounded(_rand(rng, nl), dt), rounded(_rand(rng, nl), dt)
         out = H.debug_op(5, l, to_dev(x, dt), to_dev(g, dt), out_dtype=dt)
         report[f"C{l}"] = measure(out, chebyshev(x, g, P.kappa[l], P.h[l], P.weights[l - 1], m, P.lam[l]))
     # ADR operator on every ADR level
     for l in range(2, P.LA + 1):
-        nl = c.n >> (l - 1)
+        nl = shape(l)
         x = rounded(_rand(rng, nl), cd)
         out = H.debug_op(6, l, to_dev(x, cd))
         report[f"M{l}"] = measure(out, apply_M(x, P.adr[l]))
     # GMRES(3) from a nonzero x0 on level 2
-    n2 = c.n // 2
+    n2 = shape(2)
     x0, b = rounded(_rand(rng, n2), cd), rounded(_rand(rng, n2), cd)
     out = H.debug_op(7, 2, to_dev(x0, cd), to_dev(b, cd))
     report["G2"] = measure(out, gmres(lambda v: apply_M(v, P.adr[2]), b, x0, P.gmres_m))
@@ -141,7 +148,7 @@ def operator_report(c, P, H, prec, rng):
     out = H.debug_op(10, 2, None, to_dev(g2, cd))
     report["W2"] = measure(out, wave_adr_cycle(P, 2, g2, torch.zeros_like(g2)))
     # fine cycle from a random iterate
-    u, g = rounded(_rand(rng, c.n), cd), rounded(_rand(rng, c.n), cd)
+    u, g = rounded(_rand(rng, shape(1)), cd), rounded(_rand(rng, shape(1)), cd)
     out = H.debug_op(10, 1, to_dev(u, cd), to_dev(g, cd))
     report["W1"] = measure(out, cycle(P, g, u))
     # fine cycle from a zero iterate (the preconditioner application inside FGMRES)
