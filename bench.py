@@ -287,6 +287,41 @@ def bench_eikonal(case, g, maxit: int = 1000):
             "solve_iterations": its, "solve_relres": rr, "solve_seconds": round(solve_s, 3), "maxit": maxit}
 
 
+def bench_rect(seed: int, maxit: int = 3000):
+    """A non-square domain (Section 4.3.2): the layered medium on 4096 columns x 1024 rows
+    at the headline spacing and frequency, FP32+refinement to 1e-6 with tuned launch
+    shapes, in both orientations (the tall one is the transposed problem: same medium,
+    phase and source turned by 90 degrees)."""
+    import numpy as np
+    import torch
+
+    import helm_inputs as hi
+    from paper_2404_02493_amd import Helmholtz
+
+    case = hi.make_case("layered4096x1024", seed=seed)
+    out = {"workload": "layered4096x1024 (4096 columns x 1024 rows, k = 2100, h = 1/4096)",
+           "damping_cells": case.damping_cells, "levels": case.levels}
+    for name, tr in (("wide", False), ("tall", True)):
+        vel, phi, g_np = case.velocity, case.phi, case.g
+        if tr:
+            vel, phi, g_np = vel.T.copy(), phi.T.copy(), g_np.T.copy()
+        H = Helmholtz(vel, case.k, levels=case.levels, precision="c64", damping_cells=case.damping_cells)
+        H.set_phase(phi)
+        H.tune(cache=os.path.join(ROOT, "paper_2404_02493_amd", "tuning.json"))
+        g = torch.as_tensor(g_np).to("cuda:0")
+        H.solve(g, tol=1e-6, maxit=5, mode=1)  # graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, its, rr, _ = H.solve(g, tol=1e-6, maxit=maxit, mode=1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        H.close()
+        out[name] = {"shape": list(vel.shape), "iterations": its, "relres": rr, "seconds": round(dt, 4),
+                     "ms_per_iteration": round(1e3 * dt / max(its, 1), 3),
+                     "node_iterations_per_s": round(float(np.prod(vel.shape)) * its / dt, 1)}
+    return out
+
+
 def copy_probe(reps: int = 5):
     """A plain device copy of 4096^2 complex64 values (128 MiB read + 128 MiB written per
     dispatch), the known-size reference for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -551,7 +586,7 @@ def main():
 
     roofline_hbm = hbm_rooflines(prof32["kernels"]) if prof32 else None
 
-    shifted = sharp = batch = comparison = eikonal = None
+    shifted = sharp = batch = comparison = eikonal = rect = None
     if not args.no_extras:
         log("shifted equation (relative shift 0.01) to 1e-7")
         shifted = bench_shifted(case, g)
@@ -568,6 +603,9 @@ def main():
         log("travel-time phase on the device (factored eikonal) and its solve")
         eikonal = bench_eikonal(case, g)
         log(f"eikonal: {eikonal}")
+        log("non-square domain 4096 x 1024, both orientations")
+        rect = bench_rect(args.seed)
+        log(f"rect: {rect}")
 
     adjoint = None
     if not args.no_adjoint:
@@ -614,6 +652,7 @@ def main():
         "batch64": batch,
         "comparison": comparison,
         "eikonal_phase": eikonal,
+        "non_square": rect,
         "profile_fp32": summary,
         "adjoint": adjoint,
         "tuning": {k: v for k, v in tuning.items() if k != "timings_ms"} if tuning else None,

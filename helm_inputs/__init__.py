@@ -210,6 +210,10 @@ CONFIGS = {
     "layered4096": dict(n=4096, k=2100.0, levels=7, medium="layered", nsrc=(1, 1), phase="fmm", smooth=0.01),
     # the same model without smoothing (sharp interfaces)
     "layered4096_sharp": dict(n=4096, k=2100.0, levels=7, medium="layered", nsrc=(1, 1), phase="fmm"),
+    # non-square domain of aspect 4 (4096 columns, 1024 rows; the paper's non-square
+    # seismic models are 3-4.5 times wider than deep), the same spacing and frequency
+    "layered4096x1024": dict(n=4096, ny=1024, k=2100.0, levels=7, medium="layered", nsrc=(1, 1), phase="fmm",
+                             smooth=0.01),
 }
 
 
