@@ -112,13 +112,19 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
                 AdrTape& T = S.adr[s][l];
                 T.b = dalloc(c, cb);
                 T.xo = dalloc(c, cb);
-                for (int q = 0; q <= m; ++q) T.kpre[q] = dalloc(c, cb);
+                for (int q = 0; q <= m; ++q) {
+                    T.kpre[q] = dalloc(c, cb);
+                    HIPCHK(hipMemsetAsync(T.kpre[q], 0, cb, st));
+                }
                 hrec[ri].m = m;
                 T.rpre = recs + ri++;
                 if (l < c->LA) {
                     T.x1 = dalloc(c, cb);
                     T.x2 = dalloc(c, cb);
-                    for (int q = 0; q <= m; ++q) T.kpost[q] = dalloc(c, cb);
+                    for (int q = 0; q <= m; ++q) {
+                        T.kpost[q] = dalloc(c, cb);
+                        HIPCHK(hipMemsetAsync(T.kpost[q], 0, cb, st));
+                    }
                     hrec[ri].m = m;
                     T.rpost = recs + ri++;
                 }
@@ -226,12 +232,55 @@ struct AdjEngine {
         rec_gmres(l, Tp.b, Tp.x2, m, Tp.kpost, Tp.rpost, Tp.xo);
     }
 
+    // The basis and Gram partials of a recorded GMRES(MM) call in one tile pass; returns
+    // the number of blocks (whose partials k_gr_solve sums).
+    template <int MM>
+    int rec_tile(int l, const void* b, const void* x0, void* const* kv) {
+        AdrLevel& A = c->al[l];
+        KvOut<T> ko{};
+        for (int q = 0; q <= MM; ++q) ko.v[q] = (C*)kv[q];
+        const int tt = E.sstep_tile_edge(l) == 16 ? 16 : 32;
+        int nb = 0;
+        const double bytes = ((x0 ? 3.0 : 2.0) * sizeof(C) + 2 * sizeof(T)) * double(N(l)) +
+                             (MM + 1.0) * sizeof(C) * double(N(l));
+        auto go = [&](auto ttc, auto x0c) {
+            constexpr int TT = decltype(ttc)::value;
+            constexpr bool X0 = decltype(x0c)::value;
+            nb = Tile<MM, X0, true, TT>::tiles(A.nx, A.ny);
+            REQUIRE((size_t)(MM + 1) * (MM + 2) * nb <= c->partials_cap, "adjoint: reduction scratch too small");
+            LAUNCH_NB(c, bytes, (k_gr_tile<T, MM, X0, TT>), dim3(nb), dim3(BLOCK), st, A.A, (const T*)A.px,
+                      (const T*)A.py, (const C*)A.c0, (const C*)b, (const C*)x0, ko, 1.0 / tau(l), c->partials);
+        };
+        if (tt == 16) {
+            if (x0) go(std::integral_constant<int, 16>{}, std::true_type{});
+            else go(std::integral_constant<int, 16>{}, std::false_type{});
+        } else {
+            if (x0) go(std::integral_constant<int, 32>{}, std::true_type{});
+            else go(std::integral_constant<int, 32>{}, std::false_type{});
+        }
+        return nb;
+    }
+
     void rec_gmres(int l, const void* b, const void* x0, int m, void* const* kv, GRec* R, void* xout) {
         AdrLevel& A = c->al[l];
         const size_t n = N(l);
         const int nb = fb(n);
         VecSet<T> K{};
         for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
+        if (m <= 4) {
+            int nt = 0;
+            switch (m) {
+                case 1: nt = rec_tile<1>(l, b, x0, kv); break;
+                case 2: nt = rec_tile<2>(l, b, x0, kv); break;
+                case 3: nt = rec_tile<3>(l, b, x0, kv); break;
+                default: nt = rec_tile<4>(l, b, x0, kv); break;
+            }
+            LAUNCH_NB(c, 8.0 * (m + 1) * (m + 2) * nt, k_gr_solve, dim3(1), dim3(FBLOCK), st,
+                      (const double*)c->partials, nt, R, tau(l));
+            LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n,
+                      K, m, (const GRec*)R, (const C*)x0, (C*)xout);
+            return;
+        }
         // the partials of k_{j+1} go to entries j (j + 1) .. (j + 1)(j + 2) - 1, the layout of
         // the record's Gram matrix, summed once by the solve
         REQUIRE((size_t)(m + 1) * (m + 2) * nb <= c->partials_cap, "adjoint: reduction scratch too small");

@@ -14,7 +14,7 @@
 // Every kernel keeps the ring i = 0 or j = 0 at zero, as the forward kernels do.
 #pragma once
 
-#include "kernels_krylov.hpp"
+#include "kernels_sstep.hpp"
 
 namespace helm {
 
@@ -414,6 +414,64 @@ __global__ __launch_bounds__(BLOCK) void k_gr_chain(AdrGeom A, const T* __restri
         kout[p] = v;
     }
     reduce_store<2 * (GMAX + 1)>(acc, 2 * (jj + 1), partials);
+}
+
+// Output vectors k_1..k_{m+1} of a recorded GMRES call.
+template <typename T>
+struct KvOut {
+    cplx<T>* v[GMAX + 1];
+};
+
+// The record of one GMRES(M) call in one pass on overlapped tiles (the s-step tile
+// machinery): k_1 = b - M x0 (X0; else b) and k_{j+1} = M k_j / tau, built on the tile and
+// a ring of M (+1 with x0) nodes in LDS, stored at the tile's nodes, with this block's
+// Gram partials of k_1..k_{M+1} in the layout k_gr_solve sums (entry e at
+// partials[e * nblk + block]; the imaginary part of a diagonal entry is 0).  tau is a
+// power of two, so scaling the unscaled powers by tau^-j is exact.  Ring nodes are not
+// written (the tape keeps them 0).  Tile<M, X0, true, TT>::tiles(nx, ny) blocks.
+template <typename T, int M, bool X0, int TT>
+__global__ __launch_bounds__(BLOCK) void k_gr_tile(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                   const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ b,
+                                                   const cplx<T>* __restrict__ x0, KvOut<T> kout, double inv_tau,
+                                                   double* __restrict__ partials) {
+    using Tg = Tile<M, X0, true, TT>;
+    constexpr int NE = (M + 1) * (M + 2);
+    __shared__ cplx<T> buf[2 * Tg::NR];
+    __shared__ double red[(BLOCK / 64) * NE];
+    __shared__ double sums[NE];
+    double acc[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) acc[q] = 0.0;
+    T sc[M + 1];
+    sc[0] = T(1);
+#pragma unroll
+    for (int j = 1; j <= M; ++j) sc[j] = sc[j - 1] * T(inv_tau);
+    int ti, tj;
+    tile_index(Tg::per_side(A.nx), ti, tj);
+    sstep_tile<T, M, X0, true, TT>(A, ti, tj, px, py, c0, b, x0, buf,
+                                   [&](int, int gi, int gj, bool own, cplx<T>, const cplx<T>(&k)[M + 1]) {
+        if (!own) return;
+        const unsigned p = (unsigned)(gi * A.nx + gj);
+        double kr[M + 1], ki[M + 1];
+#pragma unroll
+        for (int j = 0; j <= M; ++j) {
+            const cplx<T> v = sc[j] * k[j];
+            st_off(kout.v[j], p, v);
+            kr[j] = double(v.re);
+            ki[j] = double(v.im);
+        }
+#pragma unroll
+        for (int c = 0; c <= M; ++c) {
+#pragma unroll
+            for (int q = 0; q < c; ++q) {
+                acc[c * (c + 1) + 2 * q] += kr[q] * kr[c] + ki[q] * ki[c];
+                acc[c * (c + 1) + 2 * q + 1] += kr[q] * ki[c] - ki[q] * kr[c];
+            }
+            acc[c * (c + 1) + 2 * c] += kr[c] * kr[c] + ki[c] * ki[c];
+        }
+    });
+    block_sum<NE, BLOCK / 64>(acc, NE, red, sums);
+    store_partials(sums, NE, partials);
 }
 
 // sum over blocks b < nblk of row[b] in one wavefront: each lane issues its loads in
