@@ -109,7 +109,7 @@ def single_thread_oracle():
 def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):
     """The adjoint of K unrolled FP32 cycles on the 1024^2, k = 640 random medium
     (7 levels, fast-marching phase in float32): wall time of one helm_cycle_backward
-    (which re-runs the K forward cycles for its checkpoints) against K forward cycles."""
+    (which re-runs the K cycles with their tapes) against K forward cycles."""
     import numpy as np
     import torch
 
@@ -145,8 +145,7 @@ def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):
     f, b = float(np.median(tf)), float(np.median(tb))
     return {"workload": "grf1024 (n=1024, k=640, L=7), K=10 FP32 cycles from zero", "forward_ms": round(1e3 * f, 3),
             "backward_ms": round(1e3 * b, 3), "backward_over_forward": round(b / f, 2),
-            "note": "backward includes re-running the K forward cycles for the checkpoints and the per-cycle "
-                    "re-recording of the tape"}
+            "note": "backward re-runs the K cycles recording one tape per cycle, then reverses them"}
 
 
 HBM_CLEAN = ("k_jac0_restrict", "k_jac0_prolong_jacobi", "k_fg_arnoldi", "k_fg_orth")

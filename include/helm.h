@@ -214,9 +214,13 @@ helm_status helm_residual_noalloc(helm_ctx ctx, const void* g, const void* u, vo
  *            helm_set_weights (w[0] Jacobi, w[l-1] Chebyshev alpha of level l).
  *   ckpt_ws  device workspace of K*ny*n complex elements in cycle_prec for the
  *            per-cycle checkpoints, or NULL for a library-owned buffer.
- * The call re-runs the K cycles (checkpointing u_0..u_{K-1}), then reverses them
- * one at a time, re-recording each cycle's intermediates on a library-owned tape
- * (allocated on the first call, about 4 + 4*adr_steps fine-grid vectors).
+ * The call re-runs the K cycles recording each cycle's intermediates on a library-owned
+ * tape of its own (about 4 + 4*adr_steps fine-grid vectors per cycle, allocated by the
+ * first call that needs them) and keeping u_0..u_{K-1} in the checkpoints, then reverses
+ * them.  When the tapes still to be allocated would take more than a quarter of the
+ * free device memory or 32 GiB (or the environment variable HELM_ADJ_TAPE_MB, in MiB,
+ * when set), one tape is reused: the K cycles run first for the checkpoints and each
+ * cycle is recorded again just before its reverse.
  * Requires gmres_m, gmres_coarse_m <= 6 (HELM_EINVAL otherwise) and the phase
  * (HELM_ESTATE otherwise).  Asynchronous on `stream`. */
 helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const void* u0,

@@ -1,14 +1,15 @@
 // Host side of the adjoint of K unrolled cycles (Section 3.3: the loss after K
 // cycles and its back-propagation to the phase and to the smoother weights).
 //
-// Strategy: the K forward cycles are re-run from u_0 and every iterate u_k is
-// kept (one checkpoint per cycle).  Then, for k = K-1 .. 0, cycle k is run once
-// more from u_k while a tape records what its reverse needs (the inputs of the
-// smoothers, the ADR right-hand sides and iterates, and for every GMRES call the
-// monomial Krylov basis and its least-squares coefficients), and the cycle is
-// reversed from the tape: u_k's cotangent from u_{k+1}'s, with the cotangents of
-// the weights, of the ADR coefficients phi_x, phi_y, c0 and of the carrier phase
-// accumulated on the way.  At the end those are pulled back to the fine phase.
+// Strategy: the K cycles are run forward from u_0 while a tape per cycle records what
+// its reverse needs (the inputs of the smoothers, the ADR right-hand sides and
+// iterates, and for every GMRES call the monomial Krylov basis and its least-squares
+// record); u_{k+1} comes from that recording.  Then, for k = K-1 .. 0, cycle k is
+// reversed from its tape: u_k's cotangent from u_{k+1}'s, with the cotangents of the
+// weights, of the ADR coefficients phi_x, phi_y, c0 and of the carrier phase
+// accumulated on the way.  At the end those are pulled back to the fine phase.  When K
+// tapes do not fit, one tape is reused: the K forward cycles are run first for the
+// checkpoints u_k, and each cycle is recorded again from u_k just before its reverse.
 //
 // Included from helm.hip inside namespace helm (uses its context, LAUNCH, Engine).
 #pragma once
@@ -24,16 +25,23 @@ struct AdrTape {  // one GMRES-smoothed ADR level inside one ADR step
     GRec* rpost = nullptr;
 };
 
+// What the reverse of one cycle reads: the tape of its recording.
+struct CycleTape {
+    void* uB = nullptr;                      // level 1: input of the post-Jacobi sweep
+    std::vector<void*> g, ub;                // wave levels: right-hand side, input of the post-smoother
+    std::vector<std::vector<AdrTape>> adr;   // [step][level]
+};
+
 struct AdjState {
     bool ready = false;
     int M = 0;
-    void* ubuf = nullptr;                    // u_k of the cycle being reversed (graph input)
-    void* uB = nullptr;                      // level 1: input of the post-Jacobi sweep
+    size_t tape_bytes = 0;                   // device bytes of one cycle's tape
+    std::vector<CycleTape> tapes;            // one per cycle when they fit, else one reused per cycle
+    int cur = 0;                             // the tape being recorded or reversed
+    void* ubuf = nullptr;                    // u_k of the cycle being reversed (graph input, one tape)
     void* fb[2] = {};                        // level-1 cotangents
-    std::vector<void*> g, ub;                // wave levels: right-hand side, input of the post-smoother
     std::vector<void*> lub, lgb;             // cotangent of the level's output / of its right-hand side
     std::vector<std::array<void*, 9>> cs;    // Chebyshev reverse scratch
-    std::vector<std::vector<AdrTape>> adr;   // [step][level]
     std::vector<void*> axb, axb2, abb, acc0, acc1;  // ADR cotangents per level
     std::vector<double*> pxb, pyb;
     std::vector<c128*> c0b;
@@ -54,6 +62,57 @@ static void dfree(helm_ctx c, void* p) {
 
 static int gm_of(helm_ctx c, int l) { return l == c->LA ? c->d.gmres_coarse_m : c->d.gmres_m; }
 
+// One cycle's tape: the wave-level inputs, and per ADR step and level the right-hand
+// side, iterates, Krylov bases (zeroed here: the tile record leaves their ring unwritten)
+// and GMRES records.
+static void alloc_tape(helm_ctx c, CycleTape& T, int M, hipStream_t st) {
+    const int L = c->L;
+    const bool f64c = !c->f32;
+    const size_t NF = (size_t)c->d.n * c->d.ny;
+    T.uB = dalloc(c, NF * csize(f64c));
+    T.g.assign(L + 1, nullptr);
+    T.ub.assign(L + 1, nullptr);
+    for (int l = 2; l <= L; ++l) {
+        const size_t cb = (size_t)lnx(c, l) * lny(c, l) * csize(c->wl[l].f64);
+        T.g[l] = dalloc(c, cb);
+        if (l < L) T.ub[l] = dalloc(c, cb);
+    }
+    if (M == 0) return;
+    T.adr.assign(M, std::vector<AdrTape>(c->LA + 1));
+    const int nrec = M * c->LA * 2;
+    GRec* recs = (GRec*)dalloc(c, (size_t)nrec * sizeof(GRec));
+    std::vector<GRec> hrec(nrec);
+    std::memset(hrec.data(), 0, hrec.size() * sizeof(GRec));
+    int ri = 0;
+    for (int l = 2; l <= c->LA; ++l) {
+        const size_t cb = (size_t)lnx(c, l) * lny(c, l) * csize(f64c);
+        const int m = gm_of(c, l);
+        for (int s = 0; s < M; ++s) {
+            AdrTape& A = T.adr[s][l];
+            A.b = dalloc(c, cb);
+            A.xo = dalloc(c, cb);
+            for (int q = 0; q <= m; ++q) {
+                A.kpre[q] = dalloc(c, cb);
+                HIPCHK(hipMemsetAsync(A.kpre[q], 0, cb, st));
+            }
+            hrec[ri].m = m;
+            A.rpre = recs + ri++;
+            if (l < c->LA) {
+                A.x1 = dalloc(c, cb);
+                A.x2 = dalloc(c, cb);
+                for (int q = 0; q <= m; ++q) {
+                    A.kpost[q] = dalloc(c, cb);
+                    HIPCHK(hipMemsetAsync(A.kpost[q], 0, cb, st));
+                }
+                hrec[ri].m = m;
+                A.rpost = recs + ri++;
+            }
+        }
+    }
+    HIPCHK(hipMemcpyAsync(recs, hrec.data(), hrec.size() * sizeof(GRec), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+}
+
 static void adj_alloc(helm_ctx c, hipStream_t st) {
     AdjState& S = *c->adj;
     if (S.ready) return;
@@ -63,26 +122,19 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
     const bool adr_on = c->d.adr_steps > 0 && L >= 3;
     S.M = adr_on ? c->d.adr_steps : 0;
     S.ubuf = dalloc(c, NF * csize(f64c));
-    S.uB = dalloc(c, NF * csize(f64c));
     S.fb[0] = dalloc(c, NF * csize(f64c));
     S.fb[1] = dalloc(c, NF * csize(f64c));
-    S.g.assign(L + 1, nullptr);
-    S.ub.assign(L + 1, nullptr);
     S.lub.assign(L + 1, nullptr);
     S.lgb.assign(L + 1, nullptr);
     S.cs.assign(L + 1, {});
     for (int l = 2; l <= L; ++l) {
-        const size_t Nl = (size_t)lnx(c, l) * lny(c, l);
-        const size_t cb = Nl * csize(c->wl[l].f64);
-        S.g[l] = dalloc(c, cb);
-        if (l < L) S.ub[l] = dalloc(c, cb);
+        const size_t cb = (size_t)lnx(c, l) * lny(c, l) * csize(c->wl[l].f64);
         S.lub[l] = dalloc(c, cb);
         S.lgb[l] = dalloc(c, cb);
         for (int q = 0; q < 9; ++q) S.cs[l][q] = dalloc(c, cb);
     }
     S.wacc = (double*)dalloc(c, 64 * sizeof(double));
     if (adr_on) {
-        S.adr.assign(S.M, std::vector<AdrTape>(c->LA + 1));
         S.axb.assign(c->LA + 1, nullptr);
         S.axb2.assign(c->LA + 1, nullptr);
         S.abb.assign(c->LA + 1, nullptr);
@@ -91,11 +143,6 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
         S.pxb.assign(c->LA + 1, nullptr);
         S.pyb.assign(c->LA + 1, nullptr);
         S.c0b.assign(c->LA + 1, nullptr);
-        const int nrec = S.M * c->LA * 2;
-        GRec* recs = (GRec*)dalloc(c, (size_t)nrec * sizeof(GRec));
-        std::vector<GRec> hrec(nrec);
-        std::memset(hrec.data(), 0, hrec.size() * sizeof(GRec));
-        int ri = 0;
         for (int l = 2; l <= c->LA; ++l) {
             const size_t Nl = (size_t)lnx(c, l) * lny(c, l);
             const size_t cb = Nl * csize(f64c);
@@ -107,37 +154,38 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
             S.pxb[l] = (double*)dalloc(c, Nl * sizeof(double));
             S.pyb[l] = (double*)dalloc(c, Nl * sizeof(double));
             S.c0b[l] = (c128*)dalloc(c, Nl * sizeof(c128));
-            const int m = gm_of(c, l);
-            for (int s = 0; s < S.M; ++s) {
-                AdrTape& T = S.adr[s][l];
-                T.b = dalloc(c, cb);
-                T.xo = dalloc(c, cb);
-                for (int q = 0; q <= m; ++q) {
-                    T.kpre[q] = dalloc(c, cb);
-                    HIPCHK(hipMemsetAsync(T.kpre[q], 0, cb, st));
-                }
-                hrec[ri].m = m;
-                T.rpre = recs + ri++;
-                if (l < c->LA) {
-                    T.x1 = dalloc(c, cb);
-                    T.x2 = dalloc(c, cb);
-                    for (int q = 0; q <= m; ++q) {
-                        T.kpost[q] = dalloc(c, cb);
-                        HIPCHK(hipMemsetAsync(T.kpost[q], 0, cb, st));
-                    }
-                    hrec[ri].m = m;
-                    T.rpost = recs + ri++;
-                }
-            }
         }
-        HIPCHK(hipMemcpyAsync(recs, hrec.data(), hrec.size() * sizeof(GRec), hipMemcpyHostToDevice, st));
         const size_t N2 = (size_t)lnx(c, 2) * lny(c, 2);
         S.thb = (double*)dalloc(c, N2 * sizeof(double));
         S.phib2 = (double*)dalloc(c, N2 * sizeof(double));
         S.rbar2 = dalloc(c, N2 * csize(f64c));
     }
+    const size_t before = c->count_bytes;
+    S.tapes.assign(1, CycleTape{});
+    alloc_tape(c, S.tapes[0], S.M, st);
+    S.tape_bytes = c->count_bytes - before;
     HIPCHK(hipStreamSynchronize(st));
     S.ready = true;
+}
+
+// One tape per cycle when K of them fit (at most a quarter of the free device memory and
+// 32 GiB, or HELM_ADJ_TAPE_MB MiB when that variable is set): the forward pass then
+// records every cycle once and the checkpoint pass is not needed.  Returns whether K
+// tapes are available.
+static bool adj_tapes_for(helm_ctx c, int K, hipStream_t st) {
+    AdjState& S = *c->adj;
+    if ((int)S.tapes.size() >= K) return true;
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    size_t cap = (size_t)32 << 30;
+    if (const char* e = std::getenv("HELM_ADJ_TAPE_MB")) cap = (size_t)std::strtoull(e, nullptr, 10) << 20;
+    const size_t need = (size_t)(K - (int)S.tapes.size()) * S.tape_bytes;
+    if (need > fr / 4 || need > cap) return false;
+    while ((int)S.tapes.size() < K) {
+        S.tapes.emplace_back();
+        alloc_tape(c, S.tapes.back(), S.M, st);
+    }
+    return true;
 }
 
 template <typename T>
@@ -149,6 +197,8 @@ struct AdjEngine {
     using C = cplx<T>;
 
     AdjEngine(helm_ctx ctx, hipStream_t s) : c(ctx), st(s), E(ctx, s), S(*ctx->adj) {}
+
+    CycleTape& tp() { return S.tapes[S.cur]; }
 
     size_t N(int l) const { return E.N(l); }
     int fb(size_t n) const { return flat_blocks(n); }
@@ -172,10 +222,19 @@ struct AdjEngine {
         WaveLevel& W = c->wl[1];
         const Geom& G = W.G;
         LAUNCH(c, ((u0 ? 3 : 2) * sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny), (k_jacobi<T>), dim3(tiles_of(G.nx, G.ny)), tile_block(),
-               st, G, (const T*)W.n2, (const C*)g, (const C*)u0, (C*)S.uB, (const double*)c->cdev->la);
-        E.restrict_down(1, g, S.uB, S.g[2]);
+               st, G, (const T*)W.n2, (const C*)g, (const C*)u0, (C*)tp().uB, (const double*)c->cdev->la);
+        E.restrict_down(1, g, tp().uB, tp().g[2]);
         rec_level(2);
-        E.prolong_up(1, c->wl[2].u, S.uB);
+        E.prolong_up(1, c->wl[2].u, tp().uB);
+    }
+
+    // u_{k+1} = the post-Jacobi sweep of the recorded cycle (from the tape's uB).
+    void post_jacobi(const void* g, void* out) {
+        WaveLevel& W = c->wl[1];
+        const Geom& G = W.G;
+        LAUNCH(c, (3 * sizeof(C) + sizeof(T)) * NN2(G.nx, G.ny), (k_jacobi<T>), dim3(tiles_of(G.nx, G.ny)),
+               tile_block(), st, G, (const T*)W.n2, (const C*)g, (const C*)tp().uB, (C*)out,
+               (const double*)c->cdev->la);
     }
 
     void rec_level(int l) {
@@ -183,21 +242,21 @@ struct AdjEngine {
         const int L = c->L;
         const size_t cb = N(l) * csize(W.f64);
         if (l == L) {
-            E.template chebyshev<double>(l, S.g[l], W.u, true, c->w[l - 1], c->d.cheb_coarse);
+            E.template chebyshev<double>(l, tp().g[l], W.u, true, c->w[l - 1], c->d.cheb_coarse);
             return;
         }
         if (l == 3) {
-            E.restrict_down(l, S.g[l], nullptr, S.g[l + 1]);
+            E.restrict_down(l, tp().g[l], nullptr, tp().g[l + 1]);
         } else {
-            E.template chebyshev<T>(l, S.g[l], W.u, true, c->w[l - 1], c->d.cheb_pre);
-            E.restrict_down(l, S.g[l], W.u, S.g[l + 1]);
+            E.template chebyshev<T>(l, tp().g[l], W.u, true, c->w[l - 1], c->d.cheb_pre);
+            E.restrict_down(l, tp().g[l], W.u, tp().g[l + 1]);
         }
         rec_level(l + 1);
         if (l == 3) E.template zero<T>(W.u, N(l));
         E.prolong_up(l, c->wl[l + 1].u, W.u);
         if (l != 3 || c->d.level3_literal) {
-            copy(S.ub[l], W.u, cb);
-            E.template chebyshev<T>(l, S.g[l], W.u, false, c->w[l - 1], c->d.cheb_post);
+            copy(tp().ub[l], W.u, cb);
+            E.template chebyshev<T>(l, tp().g[l], W.u, false, c->w[l - 1], c->d.cheb_post);
         }
         if (l == 2)
             for (int s = 0; s < S.M; ++s) rec_adr_step(s);
@@ -205,16 +264,16 @@ struct AdjEngine {
 
     void rec_adr_step(int s) {
         WaveLevel& W = c->wl[2];
-        AdrTape& Tp = S.adr[s][2];
+        AdrTape& Tp = tp().adr[s][2];
         LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN2(W.nx, W.ny), (k_adr_demod<T>), dim3(tiles_of(W.nx, W.ny)), tile_block(), st,
-               W.G, (const T*)W.n2, (const C*)S.g[2], (const C*)W.u, (const C*)c->car2, (C*)Tp.b);
+               W.G, (const T*)W.n2, (const C*)tp().g[2], (const C*)W.u, (const C*)c->car2, (C*)Tp.b);
         rec_adrv(s, 2);
         LAUNCH(c, 4 * sizeof(C) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
                (const C*)Tp.xo, (const C*)c->car2, (C*)W.u);
     }
 
     void rec_adrv(int s, int l) {
-        AdrTape& Tp = S.adr[s][l];
+        AdrTape& Tp = tp().adr[s][l];
         AdrLevel& A = c->al[l];
         if (l == c->LA) {
             rec_gmres(l, Tp.b, nullptr, gm_of(c, l), Tp.kpre, Tp.rpre, Tp.xo);
@@ -224,11 +283,11 @@ struct AdjEngine {
         rec_gmres(l, Tp.b, nullptr, m, Tp.kpre, Tp.rpre, Tp.x1);
         LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.nx, A.ny)),
                dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)Tp.b,
-               (const C*)Tp.x1, (C*)S.adr[s][l + 1].b);
+               (const C*)Tp.x1, (C*)tp().adr[s][l + 1].b);
         rec_adrv(s, l + 1);
         copy(Tp.x2, Tp.x1, N(l) * sizeof(C));
         LAUNCH(c, 3 * sizeof(C) * NN2(A.nx, A.ny), (k_prolong_add<T, T>), dim3(tiles_of(A.nx, A.ny)), tile_block(), st,
-               A.nx, A.ny, (const C*)S.adr[s][l + 1].xo, (C*)Tp.x2);
+               A.nx, A.ny, (const C*)tp().adr[s][l + 1].xo, (C*)Tp.x2);
         rec_gmres(l, Tp.b, Tp.x2, m, Tp.kpost, Tp.rpost, Tp.xo);
     }
 
@@ -304,7 +363,7 @@ struct AdjEngine {
         const size_t NF = N(1);
         const int nb = fb(NF);
         LAUNCH_NB(c, (5.0 * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G, (const T*)W.n2,
-               (const C*)g, (const C*)S.uB, (const C*)S.fb[0], (C*)S.fb[1], T(c->w[0]), c->partials);
+               (const C*)g, (const C*)tp().uB, (const C*)S.fb[0], (C*)S.fb[1], T(c->w[0]), c->partials);
         fin_add(nb, 0);
         restrict_adj(1, S.fb[1], S.lub[2]);
         rev_level(2);
@@ -395,23 +454,23 @@ struct AdjEngine {
             E.template zero<P>(S.lgb[l], n);
         });
         if (l == L) {
-            cheb_adj<double>(l, S.g[l], nullptr, S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_coarse);
+            cheb_adj<double>(l, tp().g[l], nullptr, S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_coarse);
             return;
         }
         if (l == 2)
             for (int s = S.M - 1; s >= 0; --s) rev_adr_step(s);
         if (l != 3 || c->d.level3_literal)
-            cheb_adj<T>(l, S.g[l], S.ub[l], S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_post);
+            cheb_adj<T>(l, tp().g[l], tp().ub[l], S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_post);
         restrict_adj(l, S.lub[l], S.lub[l + 1]);
         rev_level(l + 1);
         prolong_adj(l, S.lgb[l + 1], l == 3 ? nullptr : S.lub[l], S.lgb[l]);
-        if (l != 3) cheb_adj<T>(l, S.g[l], nullptr, S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_pre);
+        if (l != 3) cheb_adj<T>(l, tp().g[l], nullptr, S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_pre);
         (void)W;
     }
 
     void rev_adr_step(int s) {
         WaveLevel& W = c->wl[2];
-        AdrTape& Tp = S.adr[s][2];
+        AdrTape& Tp = tp().adr[s][2];
         const size_t n = N(2);
         LAUNCH_NB(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_modadd_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
                (const C*)S.lub[2], (const C*)Tp.xo, (const C*)c->car2, (C*)S.axb[2], S.thb);
@@ -423,7 +482,7 @@ struct AdjEngine {
     }
 
     void rev_adrv(int s, int l) {
-        AdrTape& Tp = S.adr[s][l];
+        AdrTape& Tp = tp().adr[s][l];
         AdrLevel& A = c->al[l];
         const int m = gm_of(c, l);
         if (l == c->LA) {
@@ -535,24 +594,14 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
         HIPCHK(hipMemsetAsync(S.thb, 0, N2 * sizeof(double), st));
         HIPCHK(hipMemsetAsync(S.phib2, 0, N2 * sizeof(double), st));
     }
-    // u_0 .. u_{K-1}
     if (u0) HIPCHK(hipMemcpyAsync(ck, u0, vb, hipMemcpyDeviceToDevice, st));
     else HIPCHK(hipMemsetAsync(ck, 0, vb, st));
-    for (int k = 0; k + 1 < K; ++k) cycle_any(c, g, ck + (size_t)k * vb, ck + (size_t)(k + 1) * vb, st);
-    // reverse sweep: per cycle, u_k into a fixed buffer, then the recording and the
-    // reverse of that cycle, replayed from one captured graph (about 1100 launches a cycle)
-    AdjEngine<T> R(c, st);
     HIPCHK(hipMemcpyAsync(S.fb[0], grad_uK, vb, hipMemcpyDeviceToDevice, st));
+    AdjEngine<T> R(c, st);
     const bool graphs = c->d.use_graphs && !c->prof.on;
-    for (int k = K - 1; k >= 0; --k) {
-        const void* uk = ck + (size_t)k * vb;
-        if (!graphs) {
-            R.rec_cycle(g, uk);
-            R.rev_cycle(g, uk);
-            continue;
-        }
-        HIPCHK(hipMemcpyAsync(S.ubuf, uk, vb, hipMemcpyDeviceToDevice, st));
-        if (!c->adj_exec || c->adj_g != g) {
+    // Captures body on the capture stream and keeps the graph for (g, ck, K).
+    auto replay = [&](int key_K, auto&& body) {
+        if (!c->adj_exec || c->adj_g != g || c->adj_ck != ck || c->adj_K != key_K) {
             if (c->adj_exec) (void)hipGraphExecDestroy(c->adj_exec);
             c->adj_exec = nullptr;
             if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -560,8 +609,7 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
             HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
             try {
                 AdjEngine<T> Rc(c, c->cap_stream);
-                Rc.rec_cycle(g, S.ubuf);
-                Rc.rev_cycle(g, S.ubuf);
+                body(Rc);
             } catch (...) {
                 (void)hipStreamEndCapture(c->cap_stream, &graph);
                 if (graph) (void)hipGraphDestroy(graph);
@@ -574,8 +622,47 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
             HIPCHK(e);
             c->adj_exec = exec;
             c->adj_g = g;
+            c->adj_ck = ck;
+            c->adj_K = key_K;
         }
         HIPCHK(hipGraphLaunch(c->adj_exec, st));
+    };
+    if (adj_tapes_for(c, K, st)) {
+        // every cycle recorded once on its own tape, u_{k+1} from the recording, then the
+        // reverse sweep over the tapes (about 1000 launches a cycle, one graph for all)
+        auto body = [&](AdjEngine<T>& E) {
+            for (int k = 0; k < K; ++k) {
+                S.cur = k;
+                E.rec_cycle(g, ck + (size_t)k * vb);
+                if (k + 1 < K) E.post_jacobi(g, ck + (size_t)(k + 1) * vb);
+            }
+            for (int k = K - 1; k >= 0; --k) {
+                S.cur = k;
+                E.rev_cycle(g, ck + (size_t)k * vb);
+            }
+            S.cur = 0;
+        };
+        if (graphs) replay(K, body);
+        else body(R);
+    } else {
+        // one tape: the K forward cycles for the checkpoints u_0 .. u_{K-1}, then per cycle
+        // u_k into a fixed buffer, the recording and the reverse of that cycle, replayed
+        // from one captured graph
+        S.cur = 0;
+        for (int k = 0; k + 1 < K; ++k) cycle_any(c, g, ck + (size_t)k * vb, ck + (size_t)(k + 1) * vb, st);
+        for (int k = K - 1; k >= 0; --k) {
+            const void* uk = ck + (size_t)k * vb;
+            if (!graphs) {
+                R.rec_cycle(g, uk);
+                R.rev_cycle(g, uk);
+                continue;
+            }
+            HIPCHK(hipMemcpyAsync(S.ubuf, uk, vb, hipMemcpyDeviceToDevice, st));
+            replay(0, [&](AdjEngine<T>& E) {
+                E.rec_cycle(g, S.ubuf);
+                E.rev_cycle(g, S.ubuf);
+            });
+        }
     }
     if (c->f32) R.template phase_out<float>(grad_phi);
     else R.template phase_out<double>(grad_phi);

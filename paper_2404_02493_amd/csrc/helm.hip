@@ -11,6 +11,7 @@
 #include <atomic>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <stdexcept>
@@ -140,8 +141,12 @@ struct helm_ctx_s {
     hipEvent_t col_ev[helm::MAXM] = {};
     void* dbuf = nullptr;    // inner correction (mode 1)
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
-    hipGraphExec_t adj_exec = nullptr;  // one cycle of the adjoint (record + reverse), for adj_g
+    hipGraphExec_t adj_exec = nullptr;  // the adjoint's captured work for (adj_g, adj_ck, adj_K): all K
+                                        // cycles with one tape each (adj_K = K), or the recording and
+                                        // reverse of one cycle (adj_K = 0)
     const void* adj_g = nullptr;
+    const void* adj_ck = nullptr;
+    int adj_K = -1;
     // launch shapes chosen by the autotuner (0 = built-in default)
     struct Tuning {
         int sstep_rows[16] = {};    // s-step form on ADR level l: steps per marching unit, 1/2 tiles, 0 default
@@ -1375,6 +1380,8 @@ static void drop_graphs(helm_ctx c) {
     if (c->adj_exec) (void)hipGraphExecDestroy(c->adj_exec);
     c->adj_exec = nullptr;
     c->adj_g = nullptr;
+    c->adj_ck = nullptr;
+    c->adj_K = -1;
 }
 
 // One cycle: replays the graph captured for these pointers (capturing it on first
