@@ -151,6 +151,8 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
             S.abb[l] = dalloc(c, cb);
             S.acc0[l] = dalloc(c, cb);
             S.acc1[l] = dalloc(c, cb);
+            // the tile reverse writes the unknowns only: rings stay at this 0
+            for (void* z : {S.axb[l], S.axb2[l], S.abb[l], S.acc0[l], S.acc1[l]}) HIPCHK(hipMemsetAsync(z, 0, cb, st));
             S.pxb[l] = (double*)dalloc(c, Nl * sizeof(double));
             S.pyb[l] = (double*)dalloc(c, Nl * sizeof(double));
             S.c0b[l] = (c128*)dalloc(c, Nl * sizeof(c128));
@@ -502,6 +504,24 @@ struct AdjEngine {
 
     // Reverse of x = GMRES(M_l; b, x0, m) from the recorded basis kv and record R:
     // bbar (=|+=) the cotangent of b; xbar0 (if x0) = that of x0.
+    // The reverse of a recorded GMRES(MM) call's basis chain in one tile pass (k_ga_tile).
+    template <int MM>
+    void rev_tile(int l, const void* x0, const VecSet<T>& V, const GRec* R, void* bbar, bool bset, void* xbar0) {
+        AdrLevel& A = c->al[l];
+        constexpr int TT = 16;
+        const int nt = ((A.nx - 2) / TT + 1) * ((A.ny - 2) / TT + 1);
+        const double bytes = ((MM + 3.0 + (x0 ? 2.0 : 0.0) + (bset ? 0.0 : 1.0)) * sizeof(C) + 2 * sizeof(T) + 64.0) *
+                             double(N(l));
+        if (x0)
+            LAUNCH_NB(c, bytes, (k_ga_tile<T, MM, true, TT>), dim3(nt), dim3(BLOCK), st, A.A, (const T*)A.px,
+                      (const T*)A.py, (const C*)A.c0, V, (const double*)R->coef, 1.0 / tau(l), (const C*)x0, (C*)bbar,
+                      bset ? 0 : 1, (C*)xbar0, S.pxb[l], S.pyb[l], S.c0b[l]);
+        else
+            LAUNCH_NB(c, bytes, (k_ga_tile<T, MM, false, TT>), dim3(nt), dim3(BLOCK), st, A.A, (const T*)A.px,
+                      (const T*)A.py, (const C*)A.c0, V, (const double*)R->coef, 1.0 / tau(l), (const C*)nullptr,
+                      (C*)bbar, bset ? 0 : 1, (C*)nullptr, S.pxb[l], S.pyb[l], S.c0b[l]);
+    }
+
     void rev_gmres(int l, const void* x0, int m, void* const* kv, GRec* R, const void* xbar, void* bbar, bool bset,
                    void* xbar0) {
         AdrLevel& A = c->al[l];
@@ -515,6 +535,15 @@ struct AdjEngine {
         VecSet<T> V{};
         V.v[0] = (const C*)xbar;
         for (int q = 0; q <= m; ++q) V.v[q + 1] = (const C*)kv[q];
+        if (m <= 4) {
+            switch (m) {
+                case 1: rev_tile<1>(l, x0, V, R, bbar, bset, xbar0); break;
+                case 2: rev_tile<2>(l, x0, V, R, bbar, bset, xbar0); break;
+                case 3: rev_tile<3>(l, x0, V, R, bbar, bset, xbar0); break;
+                default: rev_tile<4>(l, x0, V, R, bbar, bset, xbar0); break;
+            }
+            return;
+        }
         const int nv = m + 2;
         C* acc = (C*)S.acc0[l];
         C* nxt = (C*)S.acc1[l];

@@ -772,6 +772,179 @@ __global__ __launch_bounds__(BLOCK) void k_ga_step(AdrGeom A, const T* __restric
     }
 }
 
+// The reverse of one recorded GMRES(M) call (the k_ga_step sequence of one call) in one
+// pass on overlapped tiles.  V_0 = xbar, V_{q+1} = k_q (q = 0..M); coef: the rows of
+// k_ga_prep.  On the tile and a ring of H = M (+1 with x0) nodes, with the cotangent y
+// and the vector a of each step in LDS:
+//   y = kbar_{M+1} = sum_q coef[M][q] V_q,
+//   y <- sum_q coef[j-2][q] V_q + (1/tau) M^H y   for j = M+1 .. 2   (then y = kbar_1),
+// with the coefficient cotangents of k_j = M k_{j-1} / tau (a = k_{j-1}, ybar = y / tau)
+// summed per node in registers; bbar = y (add: bbar += y) at the tile's nodes; with x0,
+// xbar0 = xbar - M^H y and the cotangents of M x0 (ybar = -y); finally one
+// read-modify-write of pxb, pyb, c0b per node.  Values off the unknowns are 0, so each
+// application spoils one more ring of the region and the tile's own values are exact.
+// The ring of bbar and xbar0 is not written.  Tiles of TT x TT unknowns, one per block.
+template <typename T, int M, bool X0, int TT>
+__global__ __launch_bounds__(BLOCK) void k_ga_tile(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
+                                                   const cplx<T>* __restrict__ c0, VecSet<T> V,
+                                                   const double* __restrict__ coef, double inv_tau,
+                                                   const cplx<T>* __restrict__ x0, cplx<T>* __restrict__ bbar, int add,
+                                                   cplx<T>* __restrict__ xbar0, double* __restrict__ pxb,
+                                                   double* __restrict__ pyb, c128* __restrict__ c0b) {
+    constexpr int NV = M + 2;
+    constexpr int H = M + (X0 ? 1 : 0);
+    constexpr int RW = TT + 2 * H, NR = RW * RW, NPT = (NR + BLOCK - 1) / BLOCK;
+    __shared__ cplx<T> ys[2 * NR];  // cotangent of the step (double buffer)
+    __shared__ cplx<T> as[2 * NR];  // a of the step (double buffer)
+    __shared__ T fxs[NR], fys[NR];
+    __shared__ T cf[2 * NV * (M + 1)];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 2 * NV * (M + 1); q += BLOCK) {
+        const int r = q / (2 * NV), e = q - r * (2 * NV);
+        cf[q] = T(coef[r * GCOEF_STRIDE + e]);
+    }
+    const int nx = A.nx, ny = A.ny;
+    int ti, tj;
+    tile_index((nx - 2) / TT + 1, ti, tj);
+    const int i0 = 1 + ti * TT - H, j0 = 1 + tj * TT - H;  // region node (0, 0)
+    const T g = T(A.inv_2h) * T(A.two_sk), ih2 = T(A.inv_h2);
+    cplx<T> v[NV][NPT], cc[NPT], xo[NPT];
+    T fx[NPT], fy[NPT];
+    bool ok[NPT], inner[NPT], own[NPT];
+    unsigned gp[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = tid + k * BLOCK;
+        const int ri = q / RW, rj = q - ri * RW;
+        const int gi = i0 + ri, gj = j0 + rj;
+        ok[k] = q < NR && gi >= 1 && gi <= ny - 1 && gj >= 1 && gj <= nx - 1;
+        inner[k] = ok[k] && ri >= 1 && ri <= RW - 2 && rj >= 1 && rj <= RW - 2;
+        own[k] = ok[k] && ri >= H && ri < H + TT && rj >= H && rj < H + TT;
+        gp[k] = ok[k] ? (unsigned)(gi * nx + gj) : 0u;
+#pragma unroll
+        for (int iv = 0; iv < NV; ++iv) v[iv][k] = cplx<T>{};
+        cc[k] = xo[k] = cplx<T>{};
+        fx[k] = fy[k] = T(0);
+        if (ok[k]) {
+#pragma unroll
+            for (int iv = 0; iv < NV; ++iv) v[iv][k] = ld_off(V.v[iv], gp[k]);
+            fx[k] = ld_off(px, gp[k]);
+            fy[k] = ld_off(py, gp[k]);
+            cc[k] = ld_off(c0, gp[k]);
+            if constexpr (X0) xo[k] = ld_off(x0, gp[k]);
+        }
+        if (q < NR) {
+            fxs[q] = fx[k];
+            fys[q] = fy[k];
+        }
+    }
+    __syncthreads();
+    auto lincomb = [&](int row, int k) {
+        cplx<T> r{};
+#pragma unroll
+        for (int iv = 0; iv < NV; ++iv) r = r + mk<T>(cf[row * 2 * NV + 2 * iv], cf[row * 2 * NV + 2 * iv + 1]) * v[iv][k];
+        return r;
+    };
+    // M^H y at region node q (thread slot k): the conjugated centre of the node and the
+    // conjugated coefficients of its neighbours' rows towards it (0 off the unknowns).
+    auto mh = [&](const cplx<T>* y, int k) {
+        const int q = tid + k * BLOCK;
+        const T ax = fabs(fx[k]), ay = fabs(fy[k]);
+        const cplx<T> c = y[q], e = y[q + 1], w = y[q - 1], n = y[q + RW], sth = y[q - RW];
+        const T fe = fxs[q + 1], fw = fxs[q - 1], fn = fys[q + RW], fs = fys[q - RW];
+        const T gwe = -g * (fe + fabs(fe)), gew = g * (fw - fabs(fw));    // west coefficient of e, east of w
+        const T gsn = -g * (fn + fabs(fn)), gns = g * (fs - fabs(fs));    // south coefficient of n, north of s
+        const T cr = cc[k].re + T(4) * ih2, ci = -(cc[k].im - g * (T(2) * (ax + ay)));
+        T re = cr * c.re - ci * c.im, im = cr * c.im + ci * c.re;
+        re -= ih2 * (((e.re + w.re) + n.re) + sth.re);
+        im -= ih2 * (((e.im + w.im) + n.im) + sth.im);
+        re -= ((gwe * e.im + gew * w.im) + gsn * n.im) + gns * sth.im;
+        im += ((gwe * e.re + gew * w.re) + gsn * n.re) + gns * sth.re;
+        return mk<T>(re, im);
+    };
+    double gx[NPT], gy[NPT];
+    c128 g0[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        gx[k] = gy[k] = 0.0;
+        g0[k] = c128{0.0, 0.0};
+    }
+    // coefficient cotangents of y = M a at own node slot k (a in LDS buffer ab), ybar yb
+    auto grad = [&](const cplx<T>* ab, int k, cplx<T> yb) {
+        const int q = tid + k * BLOCK;
+        const T sx = fx[k] > T(0) ? T(1) : (fx[k] < T(0) ? T(-1) : T(0));
+        const T sy = fy[k] > T(0) ? T(1) : (fy[k] < T(0) ? T(-1) : T(0));
+        const cplx<T> ac = ab[q], aw = ab[q - 1], ae = ab[q + 1], asd = ab[q - RW], an = ab[q + RW];
+        const cplx<T> dux = T(A.inv_2h) * (((T(2) * sx) * ac - (T(1) + sx) * aw) + (T(1) - sx) * ae);
+        const cplx<T> duy = T(A.inv_2h) * (((T(2) * sy) * ac - (T(1) + sy) * asd) + (T(1) - sy) * an);
+        const double ybr = double(yb.re), ybi = double(yb.im);
+        gx[k] += A.two_sk * (ybr * double(dux.im) - ybi * double(dux.re));
+        gy[k] += A.two_sk * (ybr * double(duy.im) - ybi * double(duy.re));
+        g0[k].re += double(ac.re) * ybr + double(ac.im) * ybi;
+        g0[k].im += double(ac.re) * ybi - double(ac.im) * ybr;
+    };
+    cplx<T> y[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) y[k] = ok[k] ? lincomb(M, k) : cplx<T>{};
+    const T mu = T(inv_tau);
+#pragma unroll
+    for (int s = 0; s < M; ++s) {  // kbar_{j-1} from kbar_j, j = M + 1 - s; a = k_{j-1} = V_{M-s}
+        cplx<T>* yb = ys + (s & 1) * NR;
+        cplx<T>* ab = as + (s & 1) * NR;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int q = tid + k * BLOCK;
+            if (q < NR) {
+                yb[q] = y[k];
+                ab[q] = v[M - s][k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            cplx<T> nv{};
+            if (inner[k]) {
+                nv = lincomb(M - 1 - s, k) + mu * mh(yb, k);
+                if (own[k]) grad(ab, k, mu * y[k]);
+            }
+            y[k] = nv;
+        }
+    }
+    // bbar (= or +=) kbar_1 at the tile's nodes
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+        if (own[k]) st_off(bbar, gp[k], add ? ld_off((const cplx<T>*)bbar, gp[k]) + y[k] : y[k]);
+    if constexpr (X0) {  // xbar0 = xbar - M^H kbar_1, cotangents of M x0 with ybar = -kbar_1
+        cplx<T>* yb = ys + (M & 1) * NR;
+        cplx<T>* ab = as + (M & 1) * NR;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int q = tid + k * BLOCK;
+            if (q < NR) {
+                yb[q] = y[k];
+                ab[q] = xo[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (!own[k]) continue;
+            st_off(xbar0, gp[k], v[0][k] - mh(yb, k));
+            grad(ab, k, T(-1) * y[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        if (!own[k]) continue;
+        pxb[gp[k]] += gx[k];
+        pyb[gp[k]] += gy[k];
+        c128 b0 = c0b[gp[k]];
+        b0.re += g0[k].re;
+        b0.im += g0[k].im;
+        c0b[gp[k]] = b0;
+    }
+}
+
 // Reverse of bc = R (b - M x1) given bcbar (coarse): with t = P bcbar / 4,
 //   bbar += t, xbar -= M^H t, coefficient cotangents with ybar = -t, a = x1.  In place.
 template <typename T>
