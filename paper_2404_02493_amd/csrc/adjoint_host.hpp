@@ -336,8 +336,13 @@ struct AdjEngine {
                 case 3: nt = rec_tile<3>(l, b, x0, kv); break;
                 default: nt = rec_tile<4>(l, b, x0, kv); break;
             }
-            LAUNCH_NB(c, 8.0 * (m + 1) * (m + 2) * nt, k_gr_solve, dim3(1), dim3(FBLOCK), st,
-                      (const double*)c->partials, nt, R, tau(l));
+            const double sb = 8.0 * (m + 1) * (m + 2) * nt;
+            switch (m) {
+                case 1: LAUNCH_NB(c, sb, k_gr_solve_m<1>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nt, R, tau(l)); break;
+                case 2: LAUNCH_NB(c, sb, k_gr_solve_m<2>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nt, R, tau(l)); break;
+                case 3: LAUNCH_NB(c, sb, k_gr_solve_m<3>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nt, R, tau(l)); break;
+                default: LAUNCH_NB(c, sb, k_gr_solve_m<4>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nt, R, tau(l)); break;
+            }
             LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n,
                       K, m, (const GRec*)R, (const C*)x0, (C*)xout);
             return;
@@ -531,7 +536,14 @@ struct AdjEngine {
         for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
         LAUNCH_NB(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
                c->partials);
-        LAUNCH_NB(c, 16.0 * nb * m, k_ga_prep, dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, R, tau(l));
+        const double pb = 16.0 * nb * m;
+        switch (m) {
+            case 1: LAUNCH_NB(c, pb, k_ga_prep_m<1>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nb, R, tau(l)); break;
+            case 2: LAUNCH_NB(c, pb, k_ga_prep_m<2>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nb, R, tau(l)); break;
+            case 3: LAUNCH_NB(c, pb, k_ga_prep_m<3>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nb, R, tau(l)); break;
+            case 4: LAUNCH_NB(c, pb, k_ga_prep_m<4>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nb, R, tau(l)); break;
+            default: LAUNCH_NB(c, pb, k_ga_prep, dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nb, R, tau(l)); break;
+        }
         VecSet<T> V{};
         V.v[0] = (const C*)xbar;
         for (int q = 0; q <= m; ++q) V.v[q + 1] = (const C*)kv[q];

@@ -607,6 +607,162 @@ __global__ __launch_bounds__(FBLOCK) void k_gr_solve(const double* __restrict__ 
     }
 }
 
+// Sums rows e = wv, wv + NW, ... (e < ne) of partials (nblk entries each) with one
+// wavefront per row, the loads of a wavefront's rows issued together; row sums to out[e].
+template <int NEMAX, int THREADS>
+__device__ __forceinline__ void rows_sum(const double* __restrict__ partials, int nblk, int ne, double* out) {
+    constexpr int NW = THREADS / 64, R = (NEMAX + NW - 1) / NW, SB = 32 / R > 0 ? 32 / R : 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int b0 = 0; b0 < nblk; b0 += 64 * SB) {
+        double t[R][SB];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = wv + r * NW;
+#pragma unroll
+            for (int k = 0; k < SB; ++k) {
+                const int b = b0 + k * 64 + lane;
+                t[r][k] = (e < ne && b < nblk) ? partials[(size_t)e * nblk + b] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < SB; ++k) acc[r] += t[r][k];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = wv + r * NW;
+        const double v = wave_sum(acc[r]);
+        if (lane == 0 && e < ne) out[e] = v;
+    }
+}
+
+// k_gr_solve for a compile-time dimension MM: the same sums and the same least squares,
+// with the serial part on registers (fully unrolled loops; the rank as a flag).  One
+// block of SBLOCK threads (fewer than FBLOCK, so that the serial thread has the
+// registers it needs).
+constexpr int SBLOCK = 512;
+template <int MM>
+__global__ __launch_bounds__(SBLOCK) void k_gr_solve_m(const double* __restrict__ partials, int nblk,
+                                                       GRec* __restrict__ R, double tau) {
+    constexpr int NE = (MM + 1) * (MM + 2);
+    __shared__ double gs[NE];
+    rows_sum<NE, SBLOCK>(partials, nblk, NE, gs);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double G[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        G[e] = gs[e];
+        R->gram[e] = G[e];
+    }
+    auto Gc = [&](int i, int j) -> c128 {  // <k_i, k_j>, 1-based
+        if (i <= j) return c128{G[2 * (j * (j - 1) / 2 + i - 1)], G[2 * (j * (j - 1) / 2 + i - 1) + 1]};
+        return c128{G[2 * (i * (i - 1) / 2 + j - 1)], -G[2 * (i * (i - 1) / 2 + j - 1) + 1]};
+    };
+    double Lr[MM][MM], Li[MM][MM], sc[MM], cr[MM], ci[MM];
+#pragma unroll
+    for (int a = 0; a < MM; ++a) {
+        sc[a] = cr[a] = ci[a] = 0.0;
+#pragma unroll
+        for (int b = 0; b < MM; ++b) Lr[a][b] = Li[a][b] = 0.0;
+    }
+    const double b2 = Gc(1, 1).re;
+    const int zero = !(b2 > 0.0) || !isfinite(b2);
+    int rank = 0;
+    if (!zero) {
+#pragma unroll
+        for (int a = 0; a < MM; ++a) {
+            const double dg = tau * tau * Gc(a + 2, a + 2).re;
+            sc[a] = dg > 0.0 ? 1.0 / sqrt(dg) : 0.0;
+        }
+        bool live = true;
+#pragma unroll
+        for (int a = 0; a < MM; ++a) {
+            if (live && sc[a] == 0.0) live = false;
+            bool ok = live;
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                if (!ok) continue;
+                const c128 gv = Gc(a + 2, b + 2);
+                double gr = sc[a] * sc[b] * tau * tau * gv.re, gi = sc[a] * sc[b] * tau * tau * gv.im;
+#pragma unroll
+                for (int q = 0; q < b; ++q) {  // - L_aq conj(L_bq)
+                    gr -= Lr[a][q] * Lr[b][q] + Li[a][q] * Li[b][q];
+                    gi -= Li[a][q] * Lr[b][q] - Lr[a][q] * Li[b][q];
+                }
+                if (b < a) {
+                    Lr[a][b] = gr / Lr[b][b];
+                    Li[a][b] = gi / Lr[b][b];
+                } else if (!(gr > 1e-14)) {
+                    ok = false;
+                } else {
+                    Lr[a][a] = sqrt(gr);
+                    Li[a][a] = 0.0;
+                }
+            }
+            if (live && !ok) {
+                live = false;
+#pragma unroll
+                for (int b = 0; b < MM; ++b) Lr[a][b] = Li[a][b] = 0.0;
+            }
+            if (live) rank = a + 1;
+        }
+        // rhs_a = s_a tau <k_{a+2}, k_1>;  L L^H y = rhs;  c_a = s_a y_a
+        double yr[MM], yi[MM];
+#pragma unroll
+        for (int a = 0; a < MM; ++a) {
+            yr[a] = yi[a] = 0.0;
+            if (a >= rank) continue;
+            const c128 gv = Gc(a + 2, 1);
+            double rr = sc[a] * tau * gv.re, ri = sc[a] * tau * gv.im;
+#pragma unroll
+            for (int q = 0; q < a; ++q) {
+                rr -= Lr[a][q] * yr[q] - Li[a][q] * yi[q];
+                ri -= Lr[a][q] * yi[q] + Li[a][q] * yr[q];
+            }
+            yr[a] = rr / Lr[a][a];
+            yi[a] = ri / Lr[a][a];
+        }
+#pragma unroll
+        for (int a = MM - 1; a >= 0; --a) {
+            if (a >= rank) continue;
+            double rr = yr[a], ri = yi[a];
+#pragma unroll
+            for (int q = a + 1; q < MM; ++q) {  // - conj(L_qa) y_q
+                if (q >= rank) continue;
+                rr -= Lr[q][a] * yr[q] + Li[q][a] * yi[q];
+                ri -= Lr[q][a] * yi[q] - Li[q][a] * yr[q];
+            }
+            yr[a] = rr / Lr[a][a];
+            yi[a] = ri / Lr[a][a];
+        }
+#pragma unroll
+        for (int a = 0; a < MM; ++a) {
+            if (a >= rank) continue;
+            cr[a] = sc[a] * yr[a];
+            ci[a] = sc[a] * yi[a];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < MM; ++a) {
+#pragma unroll
+        for (int b = 0; b < MM; ++b) {
+            R->Lf[2 * (a * GMAX + b)] = Lr[a][b];
+            R->Lf[2 * (a * GMAX + b) + 1] = Li[a][b];
+        }
+        R->c[2 * a] = cr[a];
+        R->c[2 * a + 1] = ci[a];
+        R->z[2 * a] = R->z[2 * a + 1] = 0.0;
+        R->dsc[a] = sc[a];
+    }
+    R->rank = rank;
+    R->zero = zero;
+}
+
 // x = x0 + sum_{j=1..m} c_j k_j  (x0 may be null; may alias x).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gr_combine(size_t N, VecSet<T> Kv, int m, const GRec* __restrict__ R,
@@ -741,6 +897,117 @@ __global__ __launch_bounds__(FBLOCK) void k_ga_prep(const double* __restrict__ p
         R->one[0] = 1.0;
         R->one[1] = 0.0;
     }
+}
+
+// k_ga_prep for a compile-time dimension MM: the same sums and coefficient rows, with
+// the serial part on registers; writes rows 0..MM of R->coef over (xbar, k_1..k_{MM+1}).
+// One block of SBLOCK threads.
+template <int MM>
+__global__ __launch_bounds__(SBLOCK) void k_ga_prep_m(const double* __restrict__ partials, int nblk,
+                                                      GRec* __restrict__ R, double tau) {
+    constexpr int NV = MM + 2;
+    __shared__ double cb[2 * MM];
+    rows_sum<2 * MM, SBLOCK>(partials, nblk, 2 * MM, cb);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int rank = R->rank, zero = R->zero;
+    double Lr[MM][MM], Li[MM][MM], ds[MM], cs[2 * MM], zs[2 * MM], cbr[2 * MM];
+#pragma unroll
+    for (int a = 0; a < MM; ++a) {
+#pragma unroll
+        for (int b = 0; b < MM; ++b) {
+            Lr[a][b] = R->Lf[2 * (a * GMAX + b)];
+            Li[a][b] = R->Lf[2 * (a * GMAX + b) + 1];
+        }
+        ds[a] = R->dsc[a];
+        cs[2 * a] = R->c[2 * a];
+        cs[2 * a + 1] = R->c[2 * a + 1];
+        cbr[2 * a] = cb[2 * a];
+        cbr[2 * a + 1] = cb[2 * a + 1];
+        zs[2 * a] = zs[2 * a + 1] = 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 2 * MM; ++e) R->cbar[e] = cbr[e];
+    double co[MM + 1][2 * NV];
+#pragma unroll
+    for (int r = 0; r <= MM; ++r)
+#pragma unroll
+        for (int e = 0; e < 2 * NV; ++e) co[r][e] = 0.0;
+    if (!zero) {
+        double yr[MM], yi[MM];
+#pragma unroll
+        for (int a = 0; a < MM; ++a) {
+            yr[a] = yi[a] = 0.0;
+            if (a >= rank) continue;
+            double rr = ds[a] * cbr[2 * a], ri = ds[a] * cbr[2 * a + 1];
+#pragma unroll
+            for (int q = 0; q < a; ++q) {
+                rr -= Lr[a][q] * yr[q] - Li[a][q] * yi[q];
+                ri -= Lr[a][q] * yi[q] + Li[a][q] * yr[q];
+            }
+            yr[a] = rr / Lr[a][a];
+            yi[a] = ri / Lr[a][a];
+        }
+#pragma unroll
+        for (int a = MM - 1; a >= 0; --a) {
+            if (a >= rank) continue;
+            double rr = yr[a], ri = yi[a];
+#pragma unroll
+            for (int q = a + 1; q < MM; ++q) {
+                if (q >= rank) continue;
+                rr -= Lr[q][a] * yr[q] + Li[q][a] * yi[q];
+                ri -= Lr[q][a] * yi[q] - Li[q][a] * yr[q];
+            }
+            yr[a] = rr / Lr[a][a];
+            yi[a] = ri / Lr[a][a];
+        }
+#pragma unroll
+        for (int a = 0; a < MM; ++a) {
+            if (a >= rank) continue;
+            zs[2 * a] = ds[a] * yr[a];
+            zs[2 * a + 1] = ds[a] * yi[a];
+        }
+        // vectors over (xbar, k_1, ..., k_{MM+1}) as complex coefficient lists
+        c128 rho[NV], wz[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) rho[q] = wz[q] = c128{0.0, 0.0};
+        rho[1] = c128{1.0, 0.0};
+#pragma unroll
+        for (int j = 1; j <= MM; ++j) {
+            rho[j + 1] = c128{-tau * cs[2 * (j - 1)], -tau * cs[2 * (j - 1) + 1]};
+            wz[j + 1] = c128{tau * zs[2 * (j - 1)], tau * zs[2 * (j - 1) + 1]};
+        }
+        co[0][0] = cs[0];  // kbar_1
+        co[0][1] = -cs[1];
+#pragma unroll
+        for (int q = 1; q < NV; ++q) {
+            co[0][2 * q] += wz[q].re;
+            co[0][2 * q + 1] += wz[q].im;
+        }
+#pragma unroll
+        for (int j = 1; j <= MM; ++j) {
+            if (j < MM) {
+                co[j][0] = cs[2 * j];
+                co[j][1] = -cs[2 * j + 1];
+            }
+            const c128 zc = c128{tau * zs[2 * (j - 1)], -tau * zs[2 * (j - 1) + 1]};  // tau conj(z_j)
+            const c128 cc = c128{tau * cs[2 * (j - 1)], -tau * cs[2 * (j - 1) + 1]};  // tau conj(c_j)
+#pragma unroll
+            for (int q = 1; q < NV; ++q) {
+                const c128 a = zc * rho[q], b = cc * wz[q];
+                co[j][2 * q] += a.re - b.re;
+                co[j][2 * q + 1] += a.im - b.im;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r <= MM; ++r)
+#pragma unroll
+        for (int e = 0; e < 2 * NV; ++e) R->coef[r * GCOEF_STRIDE + e] = co[r][e];
+#pragma unroll
+    for (int e = 0; e < 2 * MM; ++e) R->z[e] = zs[e];
+    R->one[0] = 1.0;
+    R->one[1] = 0.0;
 }
 
 // out = sum_q coef_q V_q + mu M^H accin   (accin may be null), and, when a is given,
