@@ -430,16 +430,18 @@ struct AdjEngine {
         double rho = dc / th, rho_t = (dc_t * th - dc * th_t) / (th * th);
         LAUNCH_NB(c, 7.0 * sizeof(Cp) * n, (k_chebadj_start<P>), dim3(nb), dim3(BLOCK), st, n, (const Cp*)ubar, r, rt, d,
                dt, s, stt, P(1.0 / th), P(-th_t / (th * th)));
+        // one fused pass per step; d, dt alternate with the buffers t1, t2
         for (int t = 1; t < m; ++t) {
-            LAUNCH_NB(c, (4.0 * sizeof(Cp) + sizeof(P)) * n, (k_apply_A2<P>), dim3(nb), dim3(BLOCK), st, G,
-                   (const P*)W.n2, (const Cp*)d, (const Cp*)dt, t1, t2);
             const double den = 2.0 * th - dc * rho;
             const double den_t = 2.0 * th_t - dc_t * rho - dc * rho_t;
             const double rn = dc / den, rn_t = (dc_t * den - dc * den_t) / (den * den);
             const double c1 = rn * rho, c1t = rn_t * rho + rn * rho_t;
             const double c2 = 2.0 / den, c2t = -2.0 * den_t / (den * den);
-            LAUNCH_NB(c, (14.0 * sizeof(Cp) + sizeof(P)) * n, (k_chebadj_step<P>), dim3(nb), dim3(BLOCK), st, G,
-                   (const P*)W.n2, (const Cp*)t1, (const Cp*)t2, r, rt, d, dt, s, stt, P(c1), P(c2), P(c1t), P(c2t));
+            LAUNCH_NB(c, (14.0 * sizeof(Cp) + sizeof(P)) * n, (k_chebadj_fused<P>), dim3(tiles_of(G.nx, G.ny)),
+                      tile_block(), st, G, (const P*)W.n2, (const Cp*)d, (const Cp*)dt, t1, t2, r, rt, s, stt, P(c1),
+                      P(c2), P(c1t), P(c2t));
+            std::swap(d, t1);
+            std::swap(dt, t2);
             rho = rn;
             rho_t = rn_t;
         }

@@ -239,6 +239,109 @@ __global__ __launch_bounds__(BLOCK) void k_chebadj_step(Geom G, const T* __restr
     }
 }
 
+// One step of both recurrences in one pass on a 64 x 16 tile (the k_apply_A2 and
+// k_chebadj_step pair): t1 = A d_in and t2 = A dt_in on the tile and a ring of one node in
+// LDS (from d_in, dt_in on a ring of two), then at the tile's nodes
+//   r -= A^H t1; rt -= A^H t2; d_out = c1 d + c2 r; dt_out = c1t d + c1 dt + c2t r + c2 rt;
+//   s += d_out; st += dt_out.
+// d_out, dt_out must not alias d_in, dt_in (neighbouring tiles still read them); their
+// ring is written 0.  The LDS of d_in, dt_in is reused for t1, t2.  tiles_of(nx, ny)
+// blocks of 64 x 4 threads.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_chebadj_fused(Geom G, const T* __restrict__ n2,
+                                                         const cplx<T>* __restrict__ d_in,
+                                                         const cplx<T>* __restrict__ dt_in, cplx<T>* __restrict__ d_out,
+                                                         cplx<T>* __restrict__ dt_out, cplx<T>* __restrict__ r,
+                                                         cplx<T>* __restrict__ rt, cplx<T>* __restrict__ s,
+                                                         cplx<T>* __restrict__ st, T c1, T c2, T c1t, T c2t) {
+    constexpr int DW = TX + 4, DH = TY + 4, HW = TX + 2, HH = TY + 2;
+    constexpr int NQ1 = (HH * HW + BLOCK - 1) / BLOCK;
+    __shared__ cplx<T> sa[DH * DW];  // d_in (ring 2), then t1 (ring 1, width HW)
+    __shared__ cplx<T> sb[DH * DW];  // dt_in (ring 2), then t2
+    __shared__ T sn[HH * HW];
+    const int nx = G.nx, ny = G.ny;
+    const T ih2 = T(G.inv_h2);
+    int j, i0;
+    tile_origin(nx, j, i0);
+    const int jt = j - (int)threadIdx.x, it = i0 - (int)threadIdx.y * RPT;  // tile origin
+    const int tid = threadIdx.x + threadIdx.y * TX;
+    cplx<T> fa[TileRing<2>::NQ], fb[TileRing<2>::NQ];
+    T fn[TileRing<1>::NQ];
+    tile_fetch<2>(d_in, nx, ny, it, jt, fa);
+    tile_fetch<2>(dt_in, nx, ny, it, jt, fb);
+    tile_fetch<1>(n2, nx, ny, it, jt, fn);
+    cplx<T> rv0[RPT], rtv0[RPT], dv0[RPT], dtv0[RPT];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int i = i0 + rr;
+        rv0[rr] = rtv0[rr] = dv0[rr] = dtv0[rr] = cplx<T>{};
+        if (i >= 1 && i < ny && j >= 1 && j < nx) {
+            const size_t p = (size_t)i * nx + j;
+            rv0[rr] = r[p];
+            rtv0[rr] = rt[p];
+            dv0[rr] = d_in[p];
+            dtv0[rr] = dt_in[p];
+        }
+    }
+    tile_store<2>(fa, sa);
+    tile_store<2>(fb, sb);
+    tile_store<1>(fn, sn);
+    __syncthreads();
+    cplx<T> t1r[NQ1], t2r[NQ1];
+#pragma unroll
+    for (int k = 0; k < NQ1; ++k) {  // t = A d on the tile and a ring of one
+        const int q = tid + k * BLOCK;
+        t1r[k] = t2r[k] = cplx<T>{};
+        if (q >= HH * HW) continue;
+        const int ri = q / HW, rj = q - ri * HW;
+        const int gi = it - 1 + ri, gj = jt - 1 + rj;
+        if (gi >= 1 && gj >= 1 && gi < ny && gj < nx) {
+            const int l = (ri + 1) * DW + rj + 1;
+            const cplx<T> kap = kappa_at<T>(G, sn[q], gi, gj);
+            const cplx<T> ca = sa[l], cb = sb[l];
+            t1r[k] = ih2 * (T(4) * ca - (((sa[l - DW] + sa[l + DW]) + sa[l - 1]) + sa[l + 1])) - kap * ca;
+            t2r[k] = ih2 * (T(4) * cb - (((sb[l - DW] + sb[l + DW]) + sb[l - 1]) + sb[l + 1])) - kap * cb;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NQ1; ++k) {
+        const int q = tid + k * BLOCK;
+        if (q < HH * HW) {
+            sa[q] = t1r[k];
+            sb[q] = t2r[k];
+        }
+    }
+    __syncthreads();
+    if (j >= nx) return;
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int i = i0 + rr;
+        if (i >= ny) break;
+        const size_t p = (size_t)i * nx + j;
+        if (i == 0 || j == 0) {  // the ring of the alternate buffers
+            d_out[p] = cplx<T>{};
+            dt_out[p] = cplx<T>{};
+            continue;
+        }
+        const int l = (i - it + 1) * HW + (j - jt + 1);
+        cplx<T> kap = kappa_at<T>(G, sn[l], i, j);
+        kap.im = -kap.im;
+        const cplx<T> a1 = sa[l], a2 = sb[l];
+        const cplx<T> h1 = ih2 * (T(4) * a1 - (((sa[l - HW] + sa[l + HW]) + sa[l - 1]) + sa[l + 1])) - kap * a1;
+        const cplx<T> h2 = ih2 * (T(4) * a2 - (((sb[l - HW] + sb[l + HW]) + sb[l - 1]) + sb[l + 1])) - kap * a2;
+        const cplx<T> rv = rv0[rr] - h1, rtv = rtv0[rr] - h2;
+        const cplx<T> dn = c1 * dv0[rr] + c2 * rv;
+        const cplx<T> dtn = ((c1t * dv0[rr] + c1 * dtv0[rr]) + c2t * rv) + c2 * rtv;
+        r[p] = rv;
+        rt[p] = rtv;
+        d_out[p] = dn;
+        dt_out[p] = dtn;
+        s[p] = s[p] + dn;
+        st[p] = st[p] + dtn;
+    }
+}
+
 // partial Re <a, A^H b>
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_dot_ah(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ a,
