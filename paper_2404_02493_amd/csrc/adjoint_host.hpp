@@ -282,14 +282,10 @@ struct AdjEngine {
             return;
         }
         const int m = gm_of(c, l);
-        rec_gmres(l, Tp.b, nullptr, m, Tp.kpre, Tp.rpre, Tp.x1);
-        LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_adr_resid_restrict<T>), dim3(rr_blocks(A.nx, A.ny)),
-               dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)Tp.b,
-               (const C*)Tp.x1, (C*)tp().adr[s][l + 1].b);
+        rec_gmres(l, Tp.b, nullptr, m, Tp.kpre, Tp.rpre, Tp.x1, tp().adr[s][l + 1].b);
         rec_adrv(s, l + 1);
-        copy(Tp.x2, Tp.x1, N(l) * sizeof(C));
-        LAUNCH(c, 3 * sizeof(C) * NN2(A.nx, A.ny), (k_prolong_add<T, T>), dim3(tiles_of(A.nx, A.ny)), tile_block(), st,
-               A.nx, A.ny, (const C*)tp().adr[s][l + 1].xo, (C*)Tp.x2);
+        LAUNCH_NB(c, 2.25 * sizeof(C) * NN2(A.nx, A.ny), (k_prolong_copy<T>), dim3(tiles_of(A.nx, A.ny)),
+                  tile_block(), st, A.nx, A.ny, (const C*)tp().adr[s][l + 1].xo, (const C*)Tp.x1, (C*)Tp.x2);
         rec_gmres(l, Tp.b, Tp.x2, m, Tp.kpost, Tp.rpost, Tp.xo);
     }
 
@@ -322,7 +318,10 @@ struct AdjEngine {
         return nb;
     }
 
-    void rec_gmres(int l, const void* b, const void* x0, int m, void* const* kv, GRec* R, void* xout) {
+    // rc (x0 = 0 only): also the restriction of the call's residual to the next level, from
+    // the Krylov identity in the same pass as the combination.
+    void rec_gmres(int l, const void* b, const void* x0, int m, void* const* kv, GRec* R, void* xout,
+                   void* rc = nullptr) {
         AdrLevel& A = c->al[l];
         const size_t n = N(l);
         const int nb = fb(n);
@@ -343,8 +342,18 @@ struct AdjEngine {
                 case 3: LAUNCH_NB(c, sb, k_gr_solve_m<3>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nt, R, tau(l)); break;
                 default: LAUNCH_NB(c, sb, k_gr_solve_m<4>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nt, R, tau(l)); break;
             }
+            if (rc && !x0) {
+                LAUNCH_NB(c, (m + 2.0) * sizeof(C) * n + sizeof(C) * n / 4.0, (k_gr_combine_rr<T>),
+                          dim3(gr_rr_blocks(A.nx, A.ny)), dim3(BLOCK), st, A.nx, A.ny, K, m, (const GRec*)R, tau(l),
+                          (C*)xout, (C*)rc);
+                return;
+            }
             LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n,
                       K, m, (const GRec*)R, (const C*)x0, (C*)xout);
+            if (rc)
+                LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_adr_resid_restrict<T>),
+                       dim3(rr_blocks(A.nx, A.ny)), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py,
+                       (const C*)A.c0, (const C*)b, (const C*)xout, (C*)rc);
             return;
         }
         // the partials of k_{j+1} go to entries j (j + 1) .. (j + 1)(j + 2) - 1, the layout of
@@ -360,6 +369,10 @@ struct AdjEngine {
                nb, R, tau(l));
         LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n, K, m,
                (const GRec*)R, (const C*)x0, (C*)xout);
+        if (rc)
+            LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_adr_resid_restrict<T>),
+                   dim3(rr_blocks(A.nx, A.ny)), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py,
+                   (const C*)A.c0, (const C*)b, (const C*)xout, (C*)rc);
     }
 
     // ------------------------------------------------------------ reverse
@@ -503,10 +516,14 @@ struct AdjEngine {
         LAUNCH_NB(c, sizeof(C) * (double(N(l)) + nc), (k_restrict_scale<T, T>), dim3(fb(nc)), dim3(BLOCK), st, A.nx,
                A.ny, (const C*)S.axb2[l], (C*)S.axb[l + 1], 4.0);
         rev_adrv(s, l + 1);
-        LAUNCH_NB(c, (6.0 * sizeof(C) + 2 * sizeof(T) + 32.0 * 2) * NN2(A.nx, A.ny), (k_adr_rr_adj<T>), dim3(fb(N(l))),
-               dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0, (const C*)S.abb[l + 1],
-               (const C*)Tp.x1, (C*)S.axb2[l], (C*)S.abb[l], S.pxb[l], S.pyb[l], S.c0b[l]);
-        rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb2[l], S.abb[l], false, nullptr);
+        // the dots of the pre-smoother's reverse, <k_j, xbar>, come with this pass
+        VecSet<T> Kd{};
+        for (int q = 0; q < m; ++q) Kd.v[q] = (const C*)Tp.kpre[q];
+        LAUNCH_NB(c, (6.0 * sizeof(C) + 2 * sizeof(T) + 32.0 * 2 + m * sizeof(C)) * NN2(A.nx, A.ny), (k_adr_rr_adj<T>),
+                  dim3(fb(N(l))), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0,
+                  (const C*)S.abb[l + 1], (const C*)Tp.x1, (C*)S.axb2[l], (C*)S.abb[l], S.pxb[l], S.pyb[l], S.c0b[l],
+                  Kd, m, c->partials);
+        rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb2[l], S.abb[l], false, nullptr, true);
     }
 
     // Reverse of x = GMRES(M_l; b, x0, m) from the recorded basis kv and record R:
@@ -529,15 +546,17 @@ struct AdjEngine {
                       (C*)bbar, bset ? 0 : 1, (C*)nullptr, S.pxb[l], S.pyb[l], S.c0b[l]);
     }
 
+    // dots_done: the partials of <k_j, xbar> (fb(N(l)) blocks) are already in place.
     void rev_gmres(int l, const void* x0, int m, void* const* kv, GRec* R, const void* xbar, void* bbar, bool bset,
-                   void* xbar0) {
+                   void* xbar0, bool dots_done = false) {
         AdrLevel& A = c->al[l];
         const size_t n = N(l);
         const int nb = fb(n);
         VecSet<T> K{};
         for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
-        LAUNCH_NB(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
-               c->partials);
+        if (!dots_done)
+            LAUNCH_NB(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
+                      c->partials);
         const double pb = 16.0 * nb * m;
         switch (m) {
             case 1: LAUNCH_NB(c, pb, k_ga_prep_m<1>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nb, R, tau(l)); break;

@@ -880,6 +880,68 @@ __global__ __launch_bounds__(BLOCK) void k_gr_combine(size_t N, VecSet<T> Kv, in
     }
 }
 
+// The combination of a recorded pre-smoother call (x0 = 0) fused with the restriction of
+// its residual: x = sum_{j=1..m} c_j k_j on every fine node and rc = R (b - M x) on the
+// coarse grid, where b - M x = k_1 - tau sum_j c_j k_{j+1} (M k_j = tau k_{j+1}), so no
+// stencil of M is needed.  A block owns a coarse tile of GRC x GRC nodes (small, so that
+// the small ADR levels still give hundreds of blocks) and the fine nodes
+// 2I0 .. 2I0 + 2 GRC - 1 in both directions (it writes x there, 0 on the ring);
+// gr_rr_blocks(nx, ny) blocks.
+constexpr int GRC = 8;
+__host__ __device__ inline int gr_rr_blocks(int nx, int ny) {
+    return ((nx / 2 + GRC - 1) / GRC) * ((ny / 2 + GRC - 1) / GRC);
+}
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gr_combine_rr(int nx, int ny, VecSet<T> Kv, int m,
+                                                         const GRec* __restrict__ R, double tau,
+                                                         cplx<T>* __restrict__ x, cplx<T>* __restrict__ rc) {
+    constexpr int FW = 2 * GRC + 1, FH = 2 * GRC + 1;
+    __shared__ cplx<T> r[FH * FW];
+    __shared__ T cf[4 * GMAX];  // c_j, then tau c_j
+    if (threadIdx.x < 2 * GMAX) {
+        const T cv = T(R->c[threadIdx.x]);
+        cf[threadIdx.x] = cv;
+        cf[2 * GMAX + threadIdx.x] = T(tau) * cv;
+    }
+    __syncthreads();
+    const int ncx = nx / 2, ncy = ny / 2;
+    const int ntx = (ncx + GRC - 1) / GRC;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int I0 = (b / ntx) * GRC, J0 = (b % ntx) * GRC;
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;
+    for (int q = threadIdx.x; q < FH * FW; q += BLOCK) {
+        const int ri = q / FW, rj = q - ri * FW;
+        const int fi = fi0 + ri, fj = fj0 + rj;
+        cplx<T> v{}, xv{};
+        if (fi >= 1 && fj >= 1 && fi < ny && fj < nx) {
+            const size_t p = (size_t)fi * nx + fj;
+            v = Kv.v[0][p];
+            for (int jv = 0; jv < m; ++jv) {
+                const cplx<T> kj = Kv.v[jv][p], kn = Kv.v[jv + 1][p];
+                xv = xv + mk<T>(cf[2 * jv], cf[2 * jv + 1]) * kj;
+                v = v - mk<T>(cf[2 * GMAX + 2 * jv], cf[2 * GMAX + 2 * jv + 1]) * kn;
+            }
+        }
+        r[q] = v;
+        if (ri >= 1 && rj >= 1 && fi < ny && fj < nx) x[(size_t)fi * nx + fj] = xv;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < GRC * GRC; q += BLOCK) {
+        const int ci = q / GRC, cj = q - ci * GRC;
+        const int I = I0 + ci, J = J0 + cj;
+        if (I >= ncy || J >= ncx) continue;
+        cplx<T> v{};
+        if (I > 0 && J > 0) {
+            const int l = (2 * ci + 1) * FW + 2 * cj + 1;
+            const cplx<T> c = r[l];
+            const cplx<T> ud = ((r[l - FW] + r[l + FW]) + r[l - 1]) + r[l + 1];
+            const cplx<T> dg = ((r[l - FW - 1] + r[l - FW + 1]) + r[l + FW - 1]) + r[l + FW + 1];
+            v = T(1.0 / 16.0) * ((T(4) * c + T(2) * ud) + dg);
+        }
+        rc[(size_t)I * ncx + J] = v;
+    }
+}
+
 // ------------------------------------------------------------------ GMRES reverse
 
 // partial <k_j, xbar>, j = 1..m
@@ -1317,12 +1379,15 @@ __global__ __launch_bounds__(BLOCK) void k_ga_tile(AdrGeom A, const T* __restric
 
 // Reverse of bc = R (b - M x1) given bcbar (coarse): with t = P bcbar / 4,
 //   bbar += t, xbar -= M^H t, coefficient cotangents with ybar = -t, a = x1.  In place.
+// With md > 0 also the per-block partials of <k_q, xbar>, q < md (Kd: k_1..k_md), the
+// sums k_ga_dots would form for the reverse call that reads xbar next.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                       const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ bcbar,
                                                       const cplx<T>* __restrict__ x1, cplx<T>* __restrict__ xbar,
                                                       cplx<T>* __restrict__ bbar, double* __restrict__ pxb,
-                                                      double* __restrict__ pyb, c128* __restrict__ c0b) {
+                                                      double* __restrict__ pyb, c128* __restrict__ c0b, VecSet<T> Kd,
+                                                      int md, double* __restrict__ partials) {
     const int n = A.nx, ny = A.ny;  // n: nodes per row
     const size_t N = (size_t)n * ny;
     const T g = T(A.two_sk * A.inv_2h), ih2 = T(A.inv_h2);
@@ -1330,6 +1395,9 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
         if (a <= 0 || b <= 0 || a >= ny || b >= n) return cplx<T>{};
         return T(0.25) * prolong_at<T, T>(bcbar, n / 2, ny / 2, a, b);
     };
+    double acc[2 * GMAX];
+#pragma unroll
+    for (int v = 0; v < 2 * GMAX; ++v) acc[v] = 0.0;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         int i, j;
         rowcol(p, n, i, j);
@@ -1357,9 +1425,19 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
             const T f = py[p - n], af = f < T(0) ? -f : f;
             mh = mh + mk<T>(-ih2, g * (f - af)) * tq(i - 1, j);
         }
-        xbar[p] = xbar[p] - mh;
+        const cplx<T> xb = xbar[p] - mh;
+        xbar[p] = xb;
         coef_grad_at(A, px, py, x1, T(-1) * t, i, j, pxb, pyb, c0b);
+#pragma unroll
+        for (int q = 0; q < GMAX; ++q) {  // the dots of k_ga_dots for the next reverse call
+            if (q < md) {
+                const cplx<T> k = Kd.v[q][p];
+                acc[2 * q] += double(k.re) * double(xb.re) + double(k.im) * double(xb.im);
+                acc[2 * q + 1] += double(k.re) * double(xb.im) - double(k.im) * double(xb.re);
+            }
+        }
     }
+    if (md > 0) reduce_store<2 * GMAX>(acc, 2 * md, partials);
 }
 
 // ------------------------------------------------------------------ phase cotangent

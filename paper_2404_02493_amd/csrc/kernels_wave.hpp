@@ -292,6 +292,23 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(int nx, int ny, const cpl
     }
 }
 
+// out = base + P ec out of place on every node (the ring copies base, which is 0 there).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_prolong_copy(int nx, int ny, const cplx<T>* __restrict__ ec,
+                                                        const cplx<T>* __restrict__ base, cplx<T>* __restrict__ out) {
+    int j, i0;
+    tile_origin(nx, j, i0);
+    if (j >= nx) return;
+    for (int r = 0; r < RPT; ++r) {
+        const int i = i0 + r;
+        if (i >= ny) break;
+        const size_t p = (size_t)i * nx + j;
+        cplx<T> v = base[p];
+        if (i > 0 && j > 0) v = v + prolong_at<T, T>(ec, nx / 2, ny / 2, i, j);
+        out[p] = v;
+    }
+}
+
 // u += P ec (assign: u = P ec) over pairs of fine columns (2J, 2J + 1): one coarse column
 // pair and one row parity per thread, one 16-byte read-modify-write per pair in FP32.
 // (ny - 1) (nx/2) pairs of rows 1..ny-1 (assign also writes row 0); coarse values off the
