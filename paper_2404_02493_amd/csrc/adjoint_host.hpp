@@ -261,17 +261,35 @@ struct AdjEngine {
             E.template chebyshev<T>(l, tp().g[l], W.u, false, c->w[l - 1], c->d.cheb_post);
         }
         if (l == 2)
-            for (int s = 0; s < S.M; ++s) rec_adr_step(s);
+            if (S.M > 0) rec_adr_steps();
     }
 
-    void rec_adr_step(int s) {
+    // The ADR steps of level 2: the first demodulation, then per step the ADR V-cycle and
+    // the re-modulation fused with the next step's demodulation; the iterate alternates
+    // between W.u and W.ualt and ends in W.u.
+    void rec_adr_steps() {
         WaveLevel& W = c->wl[2];
-        AdrTape& Tp = tp().adr[s][2];
-        LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN2(W.nx, W.ny), (k_adr_demod<T>), dim3(tiles_of(W.nx, W.ny)), tile_block(), st,
-               W.G, (const T*)W.n2, (const C*)tp().g[2], (const C*)W.u, (const C*)c->car2, (C*)Tp.b);
-        rec_adrv(s, 2);
-        LAUNCH(c, 4 * sizeof(C) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
-               (const C*)Tp.xo, (const C*)c->car2, (C*)W.u);
+        const int M = S.M;
+        LAUNCH(c, (4 * sizeof(C) + sizeof(T)) * NN2(W.nx, W.ny), (k_adr_demod<T>), dim3(tiles_of(W.nx, W.ny)),
+               tile_block(), st, W.G, (const T*)W.n2, (const C*)tp().g[2], (const C*)W.u, (const C*)c->car2,
+               (C*)tp().adr[0][2].b);
+        void* ucur = W.u;
+        void* unext = W.ualt;
+        for (int s = 0; s < M; ++s) {
+            rec_adrv(s, 2);
+            const bool last = s + 1 == M;
+            void* out = last ? W.u : unext;  // the last step lands in W.u (in place when it is current)
+            if (last && ucur == W.u) {
+                LAUNCH(c, 4 * sizeof(C) * double(N(2)), (k_adr_modadd<T>), dim3(fb(N(2))), dim3(BLOCK), st, N(2),
+                       (const C*)tp().adr[s][2].xo, (const C*)c->car2, (C*)W.u);
+                break;
+            }
+            LAUNCH_NB(c, (last ? 4.0 : 7.0) * sizeof(C) * double(N(2)), (k_adr_modadd_demod<T>), dim3(fb(N(2))),
+                      dim3(BLOCK), st, W.G, (const T*)W.n2, (const C*)tp().g[2], (const C*)ucur,
+                      (const C*)tp().adr[s][2].xo, (const C*)c->car2, (C*)out,
+                      (C*)(last ? nullptr : tp().adr[s + 1][2].b));
+            std::swap(ucur, unext);
+        }
     }
 
     void rec_adrv(int s, int l) {

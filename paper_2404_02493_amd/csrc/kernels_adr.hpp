@@ -205,6 +205,41 @@ __global__ __launch_bounds__(BLOCK) void k_adr_demod(Geom G, const T* __restrict
     }
 }
 
+// Two consecutive ADR steps' joint: uout = uin + a e^{i theta} (the re-modulation of one
+// step, out of place) and, when bout is given, bout = (g - A uout) e^{-i theta} (the
+// demodulated residual of the next), with uout at the four neighbours formed on the fly.
+// Every node is written (0 on the ring).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_modadd_demod(Geom G, const T* __restrict__ n2,
+                                                            const cplx<T>* __restrict__ g,
+                                                            const cplx<T>* __restrict__ uin,
+                                                            const cplx<T>* __restrict__ a,
+                                                            const cplx<T>* __restrict__ car, cplx<T>* __restrict__ uout,
+                                                            cplx<T>* __restrict__ bout) {
+    const int nx = G.nx, ny = G.ny;
+    const size_t N = (size_t)nx * ny;
+    auto U = [&](int i, int j) -> cplx<T> {
+        if (i <= 0 || j <= 0 || i >= ny || j >= nx) return cplx<T>{};
+        const size_t q = (size_t)i * nx + j;
+        return uin[q] + a[q] * car[q];
+    };
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        int i, j;
+        rowcol(p, nx, i, j);
+        const cplx<T> uc = U(i, j);
+        uout[p] = uc;
+        if (!bout) continue;
+        cplx<T> v{};
+        if (i > 0 && j > 0) {
+            const cplx<T> nb = ((U(i - 1, j) + U(i + 1, j)) + U(i, j - 1)) + U(i, j + 1);
+            const cplx<T> lap = T(G.inv_h2) * (T(4) * uc - nb);
+            const cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
+            v = (g[p] - (lap - kap * uc)) * conjg(car[p]);
+        }
+        bout[p] = v;
+    }
+}
+
 // u += a e^{+i theta}   (car = e^{i theta})
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_modadd(size_t N, const cplx<T>* __restrict__ a,
