@@ -497,8 +497,7 @@ struct AdjEngine {
             cheb_adj<double>(l, tp().g[l], nullptr, S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_coarse);
             return;
         }
-        if (l == 2)
-            for (int s = S.M - 1; s >= 0; --s) rev_adr_step(s);
+        if (l == 2 && S.M > 0) rev_adr_steps();
         if (l != 3 || c->d.level3_literal)
             cheb_adj<T>(l, tp().g[l], tp().ub[l], S.lub[l], S.lgb[l], c->w[l - 1], c->d.cheb_post);
         restrict_adj(l, S.lub[l], S.lub[l + 1]);
@@ -508,17 +507,22 @@ struct AdjEngine {
         (void)W;
     }
 
-    void rev_adr_step(int s) {
+    // The ADR steps of level 2 in reverse: the last step's re-modulation, then per step the
+    // reverse ADR V-cycle and one pass for its demodulation with the re-modulation of the
+    // step before it.
+    void rev_adr_steps() {
         WaveLevel& W = c->wl[2];
-        AdrTape& Tp = tp().adr[s][2];
         const size_t n = N(2);
+        const int M = S.M;
         LAUNCH_NB(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_modadd_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
-               (const C*)S.lub[2], (const C*)Tp.xo, (const C*)c->car2, (C*)S.axb[2], S.thb);
-        rev_adrv(s, 2);
-        LAUNCH_NB(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_demod_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
-               (const C*)S.abb[2], (const C*)Tp.b, (const C*)c->car2, (C*)S.rbar2, S.thb);
-        LAUNCH_NB(c, (5.0 * sizeof(C) + sizeof(T)) * n, (k_adj_ahsub<T>), dim3(fb(n)), dim3(BLOCK), st, W.G,
-               (const T*)W.n2, (const C*)S.rbar2, (C*)S.lub[2], (C*)S.lgb[2]);
+                  (const C*)S.lub[2], (const C*)tp().adr[M - 1][2].xo, (const C*)c->car2, (C*)S.axb[2], S.thb);
+        for (int s = M - 1; s >= 0; --s) {
+            rev_adrv(s, 2);
+            const C* an = s > 0 ? (const C*)tp().adr[s - 1][2].xo : nullptr;
+            LAUNCH_NB(c, (8.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_adr_step_adj<T>), dim3(fb(n)), dim3(BLOCK), st,
+                      W.G, (const T*)W.n2, (const C*)S.abb[2], (const C*)tp().adr[s][2].b, (const C*)c->car2,
+                      (C*)S.lub[2], (C*)S.lgb[2], S.thb, an, (C*)(an ? S.axb[2] : nullptr));
+        }
     }
 
     void rev_adrv(int s, int l) {

@@ -392,6 +392,52 @@ __global__ __launch_bounds__(BLOCK) void k_demod_adj(size_t N, const cplx<T>* __
     }
 }
 
+// The reverse of one level-2 ADR step's demodulation b = (g - A u) e^{-i theta} and of the
+// previous step's re-modulation, in one pass (k_demod_adj, k_adj_ahsub and k_modadd_adj):
+// with rbar = e^{i theta} bbar (formed at the neighbours on the fly)
+//   thbar += Im(conj(bbar) b),  gbar += rbar,  ubar -= A^H rbar,
+// and, when an (the earlier step's ADR result) is given, for the updated ubar
+//   abar = e^{-i theta} ubar,  thbar -= Im(conj(ubar) an e^{i theta}).
+// Interior nodes only, except that abar is written everywhere (0 on the ring).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_adr_step_adj(Geom G, const T* __restrict__ n2,
+                                                        const cplx<T>* __restrict__ bbar, const cplx<T>* __restrict__ b,
+                                                        const cplx<T>* __restrict__ car, cplx<T>* __restrict__ ubar,
+                                                        cplx<T>* __restrict__ gbar, double* __restrict__ thbar,
+                                                        const cplx<T>* __restrict__ an, cplx<T>* __restrict__ abar) {
+    const int nx = G.nx, ny = G.ny;
+    const size_t N = (size_t)nx * ny;
+    auto RB = [&](int i, int j) -> cplx<T> {
+        if (i <= 0 || j <= 0 || i >= ny || j >= nx) return cplx<T>{};
+        const size_t q = (size_t)i * nx + j;
+        return car[q] * bbar[q];
+    };
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        int i, j;
+        rowcol(p, nx, i, j);
+        if (i == 0 || j == 0) {
+            if (an) abar[p] = cplx<T>{};
+            continue;
+        }
+        const cplx<T> y = bbar[p], bv = b[p], e = car[p];
+        double th = thbar[p] + (double(y.re) * double(bv.im) - double(y.im) * double(bv.re));
+        const cplx<T> rc = e * y;
+        gbar[p] = gbar[p] + rc;
+        cplx<T> kap = kappa_at<T>(G, n2[p], i, j);
+        kap.im = -kap.im;
+        const cplx<T> nb = ((RB(i - 1, j) + RB(i + 1, j)) + RB(i, j - 1)) + RB(i, j + 1);
+        const cplx<T> ah = T(G.inv_h2) * (T(4) * rc - nb) - kap * rc;
+        const cplx<T> ub = ubar[p] - ah;
+        ubar[p] = ub;
+        if (an) {
+            abar[p] = conjg(e) * ub;
+            const cplx<T> ae = an[p] * e;
+            th -= double(ub.re) * double(ae.im) - double(ub.im) * double(ae.re);
+        }
+        thbar[p] = th;
+    }
+}
+
 // ------------------------------------------------------------------ ADR operator adjoint
 
 // Row coefficients of M at an unknown (fx = phi_x, fy = phi_y): with g = 2 sigma k / (2h),
