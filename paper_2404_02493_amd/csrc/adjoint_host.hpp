@@ -47,7 +47,6 @@ struct AdjState {
     std::vector<c128*> c0b;
     double* thb = nullptr;                   // carrier phase cotangent (level 2)
     double* phib2 = nullptr;                 // phase cotangent on the level-2 lattice
-    void* rbar2 = nullptr;
     double* wacc = nullptr;                  // weight cotangents (FP64, device)
     void* ckpt = nullptr;                    // library-owned checkpoints
     size_t ckpt_bytes = 0;
@@ -160,7 +159,6 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
         const size_t N2 = (size_t)lnx(c, 2) * lny(c, 2);
         S.thb = (double*)dalloc(c, N2 * sizeof(double));
         S.phib2 = (double*)dalloc(c, N2 * sizeof(double));
-        S.rbar2 = dalloc(c, N2 * csize(f64c));
     }
     const size_t before = c->count_bytes;
     S.tapes.assign(1, CycleTape{});

@@ -190,57 +190,8 @@ __global__ __launch_bounds__(BLOCK) void k_chebadj_start(size_t N, const cplx<T>
     }
 }
 
-// t1 = A d, t2 = A dt
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_apply_A2(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ d,
-                                                    const cplx<T>* __restrict__ dt, cplx<T>* __restrict__ t1,
-                                                    cplx<T>* __restrict__ t2) {
-    const int n = G.nx;  // nodes per row
-    const size_t N = (size_t)n * G.ny;
-    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        int i, j;
-        rowcol(p, n, i, j);
-        cplx<T> a{}, b{};
-        if (i > 0 && j > 0) {
-            a = applyA_at(G, n2, d, i, j, false);
-            b = applyA_at(G, n2, dt, i, j, false);
-        }
-        t1[p] = a;
-        t2[p] = b;
-    }
-}
-
-// One step of both recurrences (t1 = A d, t2 = A dt):
-//   r -= A^H t1; rt -= A^H t2; d' = c1 d + c2 r; dt' = c1t d + c1 dt + c2t r + c2 rt;
-//   s += d'; st += dt'.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_chebadj_step(Geom G, const T* __restrict__ n2, const cplx<T>* __restrict__ t1,
-                                                        const cplx<T>* __restrict__ t2, cplx<T>* __restrict__ r,
-                                                        cplx<T>* __restrict__ rt, cplx<T>* __restrict__ d,
-                                                        cplx<T>* __restrict__ dt, cplx<T>* __restrict__ s,
-                                                        cplx<T>* __restrict__ st, T c1, T c2, T c1t, T c2t) {
-    const int n = G.nx;  // nodes per row
-    const size_t N = (size_t)n * G.ny;
-    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        int i, j;
-        rowcol(p, n, i, j);
-        if (i == 0 || j == 0) continue;
-        const cplx<T> rv = r[p] - applyA_at(G, n2, t1, i, j, true);
-        const cplx<T> rtv = rt[p] - applyA_at(G, n2, t2, i, j, true);
-        const cplx<T> dv = d[p], dtv = dt[p];
-        const cplx<T> dn = c1 * dv + c2 * rv;
-        const cplx<T> dtn = ((c1t * dv + c1 * dtv) + c2t * rv) + c2 * rtv;
-        r[p] = rv;
-        rt[p] = rtv;
-        d[p] = dn;
-        dt[p] = dtn;
-        s[p] = s[p] + dn;
-        st[p] = st[p] + dtn;
-    }
-}
-
-// One step of both recurrences in one pass on a 64 x 16 tile (the k_apply_A2 and
-// k_chebadj_step pair): t1 = A d_in and t2 = A dt_in on the tile and a ring of one node in
+// One step of both recurrences of the Chebyshev adjoint in one pass on a 64 x 16 tile:
+// t1 = A d_in and t2 = A dt_in on the tile and a ring of one node in
 // LDS (from d_in, dt_in on a ring of two), then at the tile's nodes
 //   r -= A^H t1; rt -= A^H t2; d_out = c1 d + c2 r; dt_out = c1t d + c1 dt + c2t r + c2 rt;
 //   s += d_out; st += dt_out.
@@ -378,22 +329,8 @@ __global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* _
     }
 }
 
-// Reverse of b = r e^{-i theta} (car = e^{i theta}):  rbar = e^{i theta} bbar,
-// thbar += Im(conj(bbar) b).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_demod_adj(size_t N, const cplx<T>* __restrict__ bbar, const cplx<T>* __restrict__ b,
-                                                     const cplx<T>* __restrict__ car, cplx<T>* __restrict__ rbar,
-                                                     double* __restrict__ thbar) {
-    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const cplx<T> e = car[p];
-        const cplx<T> y = bbar[p], bv = b[p];
-        rbar[p] = e * y;
-        thbar[p] += double(y.re) * double(bv.im) - double(y.im) * double(bv.re);
-    }
-}
-
 // The reverse of one level-2 ADR step's demodulation b = (g - A u) e^{-i theta} and of the
-// previous step's re-modulation, in one pass (k_demod_adj, k_adj_ahsub and k_modadd_adj):
+// previous step's re-modulation (k_modadd_adj), in one pass:
 // with rbar = e^{i theta} bbar (formed at the neighbours on the fly)
 //   thbar += Im(conj(bbar) b),  gbar += rbar,  ubar -= A^H rbar,
 // and, when an (the earlier step's ADR result) is given, for the updated ubar
