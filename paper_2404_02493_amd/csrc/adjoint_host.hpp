@@ -507,34 +507,56 @@ struct AdjEngine {
 
     // The ADR steps of level 2 in reverse: the last step's re-modulation, then per step the
     // reverse ADR V-cycle and one pass for its demodulation with the re-modulation of the
-    // step before it.
+    // step before it.  The passes that produce a reverse call's xbar also form its dots
+    // <k_j, xbar> (k_ga_dots' partials).
     void rev_adr_steps() {
         WaveLevel& W = c->wl[2];
         const size_t n = N(2);
         const int M = S.M;
-        LAUNCH_NB(c, (3.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_modadd_adj<T>), dim3(fb(n)), dim3(BLOCK), st, n,
-                  (const C*)S.lub[2], (const C*)tp().adr[M - 1][2].xo, (const C*)c->car2, (C*)S.axb[2], S.thb);
+        int md = 0;
+        VecSet<T> Kd = first_rev_basis(M - 1, 2, md);
+        LAUNCH_NB(c, (3.0 * sizeof(C) + sizeof(T) + 16.0 + md * sizeof(C)) * n, (k_modadd_adj<T>), dim3(fb(n)),
+                  dim3(BLOCK), st, n, (const C*)S.lub[2], (const C*)tp().adr[M - 1][2].xo, (const C*)c->car2,
+                  (C*)S.axb[2], S.thb, Kd, md, c->partials);
         for (int s = M - 1; s >= 0; --s) {
             rev_adrv(s, 2);
             const C* an = s > 0 ? (const C*)tp().adr[s - 1][2].xo : nullptr;
-            LAUNCH_NB(c, (8.0 * sizeof(C) + sizeof(T) + 16.0) * n, (k_adr_step_adj<T>), dim3(fb(n)), dim3(BLOCK), st,
-                      W.G, (const T*)W.n2, (const C*)S.abb[2], (const C*)tp().adr[s][2].b, (const C*)c->car2,
-                      (C*)S.lub[2], (C*)S.lgb[2], S.thb, an, (C*)(an ? S.axb[2] : nullptr));
+            md = 0;
+            Kd = s > 0 ? first_rev_basis(s - 1, 2, md) : VecSet<T>{};
+            LAUNCH_NB(c, (8.0 * sizeof(C) + sizeof(T) + 16.0 + md * sizeof(C)) * n, (k_adr_step_adj<T>), dim3(fb(n)),
+                      dim3(BLOCK), st, W.G, (const T*)W.n2, (const C*)S.abb[2], (const C*)tp().adr[s][2].b,
+                      (const C*)c->car2, (C*)S.lub[2], (C*)S.lgb[2], S.thb, an, (C*)(an ? S.axb[2] : nullptr), Kd, md,
+                      c->partials);
         }
     }
 
+    // k_1..k_m of the first GMRES call that rev_adrv(s, l) reverses (the post-smoother of
+    // level l, the only call on the coarsest level), m to md.
+    VecSet<T> first_rev_basis(int s, int l, int& md) {
+        AdrTape& Tp = tp().adr[s][l];
+        md = gm_of(c, l);
+        void* const* kv = l == c->LA ? Tp.kpre : Tp.kpost;
+        VecSet<T> K{};
+        for (int q = 0; q < md; ++q) K.v[q] = (const C*)kv[q];
+        return K;
+    }
+
+    // Reverse of ADR V-cycle s from level l; its first reverse call finds the dots of its
+    // xbar already in c->partials.
     void rev_adrv(int s, int l) {
         AdrTape& Tp = tp().adr[s][l];
         AdrLevel& A = c->al[l];
         const int m = gm_of(c, l);
         if (l == c->LA) {
-            rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb[l], S.abb[l], true, nullptr);
+            rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb[l], S.abb[l], true, nullptr, true);
             return;
         }
-        rev_gmres(l, Tp.x2, m, Tp.kpost, Tp.rpost, S.axb[l], S.abb[l], true, S.axb2[l]);
+        rev_gmres(l, Tp.x2, m, Tp.kpost, Tp.rpost, S.axb[l], S.abb[l], true, S.axb2[l], true);
         const size_t nc = N(l + 1);
-        LAUNCH_NB(c, sizeof(C) * (double(N(l)) + nc), (k_restrict_scale<T, T>), dim3(fb(nc)), dim3(BLOCK), st, A.nx,
-               A.ny, (const C*)S.axb2[l], (C*)S.axb[l + 1], 4.0);
+        int mc = 0;
+        const VecSet<T> Kc = first_rev_basis(s, l + 1, mc);
+        LAUNCH_NB(c, sizeof(C) * (double(N(l)) + nc * (1.0 + mc)), (k_restrict_scale_dots<T>), dim3(fb(nc)),
+                  dim3(BLOCK), st, A.nx, A.ny, (const C*)S.axb2[l], (C*)S.axb[l + 1], 4.0, Kc, mc, c->partials);
         rev_adrv(s, l + 1);
         // the dots of the pre-smoother's reverse, <k_j, xbar>, come with this pass
         VecSet<T> Kd{};

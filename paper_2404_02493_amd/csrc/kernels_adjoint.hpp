@@ -57,6 +57,21 @@ __device__ __forceinline__ void reduce_store(const double (&acc)[K], int kcount,
     store_partials(sums, kcount, partials);
 }
 
+// acc[2q] + i acc[2q+1] += <k_q, y> = conj(k_q) y at one node, q < md (FP64 products; the
+// sums k_ga_dots forms, so a pass that produces y can form them on the way).
+template <typename T>
+__device__ __forceinline__ void dots_add(double (&acc)[2 * GMAX], const VecSet<T>& Kd, int md, size_t p,
+                                         cplx<T> y) {
+#pragma unroll
+    for (int q = 0; q < GMAX; ++q) {
+        if (q < md) {
+            const cplx<T> k = Kd.v[q][p];
+            acc[2 * q] += double(k.re) * double(y.re) + double(k.im) * double(y.im);
+            acc[2 * q + 1] += double(k.re) * double(y.im) - double(k.im) * double(y.re);
+        }
+    }
+}
+
 // out[v] += sum over blocks (one block of FBLOCK threads), v < kcount; scale s.
 template <int K>
 __global__ __launch_bounds__(FBLOCK) void k_finalize_add(const double* __restrict__ partials, int nblk, int kcount,
@@ -127,6 +142,37 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_scale(int nx, int ny, const 
         }
         xc[p] = out;
     }
+}
+
+// k_restrict_scale on one precision with the per-block partials of <k_q, xc>, q < md
+// (Kd: k_1..k_md on the coarse level), the sums of k_ga_dots for the reverse call that
+// reads xc next.  fb(coarse nodes) blocks, as k_ga_dots.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_restrict_scale_dots(int nx, int ny, const cplx<T>* __restrict__ x,
+                                                               cplx<T>* __restrict__ xc, double s, VecSet<T> Kd,
+                                                               int md, double* __restrict__ partials) {
+    const int ncx = nx / 2;
+    const size_t N = (size_t)ncx * (ny / 2);
+    double acc[2 * GMAX];
+#pragma unroll
+    for (int v = 0; v < 2 * GMAX; ++v) acc[v] = 0.0;
+    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
+        int I, J;
+        rowcol(p, ncx, I, J);
+        cplx<T> out{};
+        if (I > 0 && J > 0) {
+            const int fi = 2 * I, fj = 2 * J;
+            auto X = [&](int a, int b) { return ccast<double>(ldc(x, a, b, nx, ny)); };
+            c128 c = X(fi, fj);
+            c128 e = ((X(fi - 1, fj) + X(fi + 1, fj)) + X(fi, fj - 1)) + X(fi, fj + 1);
+            c128 dg = ((X(fi - 1, fj - 1) + X(fi - 1, fj + 1)) + X(fi + 1, fj - 1)) + X(fi + 1, fj + 1);
+            c128 v = (s / 16.0) * ((4.0 * c + 2.0 * e) + dg);
+            out = ccast<T>(v);
+            dots_add(acc, Kd, md, p, out);
+        }
+        xc[p] = out;
+    }
+    if (md > 0) reduce_store<2 * GMAX>(acc, 2 * md, partials);
 }
 
 // Reverse of rc = R (g - A u) given rcbar on the coarse level: with t = P rcbar / 4,
@@ -314,19 +360,28 @@ __global__ __launch_bounds__(BLOCK) void k_dot_ah(Geom G, const T* __restrict__ 
 // ------------------------------------------------------------------ ADR correction (level 2)
 
 // Reverse of u' = u + a e^{i theta} (car = e^{i theta}):  abar = e^{-i theta} ubar',
-// thbar += Re <ubar', i a e^{i theta}> = -Im(conj(ubar') a e^{i theta}).
+// thbar += Re <ubar', i a e^{i theta}> = -Im(conj(ubar') a e^{i theta}); with md > 0 also
+// the per-block partials of <k_q, abar>, q < md (Kd: k_1..k_md), for the reverse call that
+// reads abar next (fb(N) blocks, as k_ga_dots).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* __restrict__ ub, const cplx<T>* __restrict__ a,
                                                       const cplx<T>* __restrict__ car, cplx<T>* __restrict__ abar,
-                                                      double* __restrict__ thbar) {
+                                                      double* __restrict__ thbar, VecSet<T> Kd, int md,
+                                                      double* __restrict__ partials) {
+    double acc[2 * GMAX];
+#pragma unroll
+    for (int v = 0; v < 2 * GMAX; ++v) acc[v] = 0.0;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
         const cplx<T> e = car[p];
         const cplx<T> y = ub[p];
-        abar[p] = conjg(e) * y;
+        const cplx<T> ab = conjg(e) * y;
+        abar[p] = ab;
+        dots_add(acc, Kd, md, p, ab);
         const cplx<T> ae = a[p] * e;
         // Im(conj(y) * ae)
         thbar[p] -= double(y.re) * double(ae.im) - double(y.im) * double(ae.re);
     }
+    if (md > 0) reduce_store<2 * GMAX>(acc, 2 * md, partials);
 }
 
 // The reverse of one level-2 ADR step's demodulation b = (g - A u) e^{-i theta} and of the
@@ -334,16 +389,22 @@ __global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* _
 // with rbar = e^{i theta} bbar (formed at the neighbours on the fly)
 //   thbar += Im(conj(bbar) b),  gbar += rbar,  ubar -= A^H rbar,
 // and, when an (the earlier step's ADR result) is given, for the updated ubar
-//   abar = e^{-i theta} ubar,  thbar -= Im(conj(ubar) an e^{i theta}).
+//   abar = e^{-i theta} ubar,  thbar -= Im(conj(ubar) an e^{i theta}),
+// with md > 0 the per-block partials of <k_q, abar>, q < md (Kd: k_1..k_md), for the
+// reverse call that reads abar next (fb(N) blocks, as k_ga_dots).
 // Interior nodes only, except that abar is written everywhere (0 on the ring).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_step_adj(Geom G, const T* __restrict__ n2,
                                                         const cplx<T>* __restrict__ bbar, const cplx<T>* __restrict__ b,
                                                         const cplx<T>* __restrict__ car, cplx<T>* __restrict__ ubar,
                                                         cplx<T>* __restrict__ gbar, double* __restrict__ thbar,
-                                                        const cplx<T>* __restrict__ an, cplx<T>* __restrict__ abar) {
+                                                        const cplx<T>* __restrict__ an, cplx<T>* __restrict__ abar,
+                                                        VecSet<T> Kd, int md, double* __restrict__ partials) {
     const int nx = G.nx, ny = G.ny;
     const size_t N = (size_t)nx * ny;
+    double acc[2 * GMAX];
+#pragma unroll
+    for (int v = 0; v < 2 * GMAX; ++v) acc[v] = 0.0;
     auto RB = [&](int i, int j) -> cplx<T> {
         if (i <= 0 || j <= 0 || i >= ny || j >= nx) return cplx<T>{};
         const size_t q = (size_t)i * nx + j;
@@ -367,12 +428,15 @@ __global__ __launch_bounds__(BLOCK) void k_adr_step_adj(Geom G, const T* __restr
         const cplx<T> ub = ubar[p] - ah;
         ubar[p] = ub;
         if (an) {
-            abar[p] = conjg(e) * ub;
+            const cplx<T> ab = conjg(e) * ub;
+            abar[p] = ab;
+            dots_add(acc, Kd, md, p, ab);
             const cplx<T> ae = an[p] * e;
             th -= double(ub.re) * double(ae.im) - double(ub.im) * double(ae.re);
         }
         thbar[p] = th;
     }
+    if (md > 0) reduce_store<2 * GMAX>(acc, 2 * md, partials);
 }
 
 // ------------------------------------------------------------------ ADR operator adjoint
@@ -697,7 +761,7 @@ __global__ __launch_bounds__(FBLOCK) void k_gr_solve(const double* __restrict__ 
 // wavefront per row, the loads of a wavefront's rows issued together; row sums to out[e].
 template <int NEMAX, int THREADS>
 __device__ __forceinline__ void rows_sum(const double* __restrict__ partials, int nblk, int ne, double* out) {
-    constexpr int NW = THREADS / 64, R = (NEMAX + NW - 1) / NW, SB = 32 / R > 0 ? 32 / R : 1;
+    constexpr int NW = THREADS / 64, R = (NEMAX + NW - 1) / NW, SB = 48 / R > 0 ? 48 / R : 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double acc[R];
 #pragma unroll
@@ -935,15 +999,7 @@ __global__ __launch_bounds__(BLOCK) void k_ga_dots(size_t N, VecSet<T> Kv, int m
 #pragma unroll
     for (int v = 0; v < 2 * GMAX; ++v) acc[v] = 0.0;
     for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        const cplx<T> y = xb[p];
-#pragma unroll
-        for (int q = 0; q < GMAX; ++q) {
-            if (q < m) {
-                const cplx<T> k = Kv.v[q][p];
-                acc[2 * q] += double(k.re) * double(y.re) + double(k.im) * double(y.im);
-                acc[2 * q + 1] += double(k.re) * double(y.im) - double(k.im) * double(y.re);
-            }
-        }
+        dots_add(acc, Kv, m, p, xb[p]);
     }
     reduce_store<2 * GMAX>(acc, 2 * m, partials);
 }
@@ -1411,14 +1467,7 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
         const cplx<T> xb = xbar[p] - mh;
         xbar[p] = xb;
         coef_grad_at(A, px, py, x1, T(-1) * t, i, j, pxb, pyb, c0b);
-#pragma unroll
-        for (int q = 0; q < GMAX; ++q) {  // the dots of k_ga_dots for the next reverse call
-            if (q < md) {
-                const cplx<T> k = Kd.v[q][p];
-                acc[2 * q] += double(k.re) * double(xb.re) + double(k.im) * double(xb.im);
-                acc[2 * q + 1] += double(k.re) * double(xb.im) - double(k.im) * double(xb.re);
-            }
-        }
+        dots_add(acc, Kd, md, p, xb);  // the dots of k_ga_dots for the next reverse call
     }
     if (md > 0) reduce_store<2 * GMAX>(acc, 2 * md, partials);
 }
