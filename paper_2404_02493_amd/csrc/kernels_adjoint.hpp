@@ -76,9 +76,8 @@ __device__ __forceinline__ void dots_add(double (&acc)[2 * GMAX], const VecSet<T
 template <int K>
 __global__ __launch_bounds__(FBLOCK) void k_finalize_add(const double* __restrict__ partials, int nblk, int kcount,
                                                          double s, double* out) {
-    __shared__ double red[(FBLOCK / 64) * K];
     __shared__ double sums[K];
-    final_sum<K>(partials, nblk, kcount, red, sums);
+    final_sum<K>(partials, nblk, kcount, sums);
     if ((int)threadIdx.x < kcount) out[threadIdx.x] += s * sums[threadIdx.x];
 }
 

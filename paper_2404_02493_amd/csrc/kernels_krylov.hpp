@@ -523,13 +523,15 @@ template <int KV>
 __global__ __launch_bounds__(FBLOCK) void k_krylov_finalize(const double* __restrict__ partials, int nblk, int op,
                                                             int jj, int m, KrylovScal* K, double tol, BatchIdx bi) {
     bshift(bi.off(), partials, K);
-    __shared__ double red[(FBLOCK / 64) * KV];
     __shared__ double sums[KV];
-    if (op != FIN_INIT && K->done) return;
+    // the state flag is read alongside the partials (when it is set they are stale but
+    // in bounds, and unused)
+    const int done = op != FIN_INIT ? K->done : 0;
     const int kcount = (op == FIN_MV || op == FIN_ORTH1)     ? 2 * (jj + 1)
                        : (op == FIN_LMV || op == FIN_LORTH) ? 2 * (jj + 1) + 1
                                                             : 1;
-    final_sum<KV>(partials, nblk, kcount, red, sums);
+    final_sum<KV>(partials, nblk, kcount, sums);
+    if (done) return;
     if (op == FIN_LMV || op == FIN_LORTH) {
         // one lane per basis vector: the K fields of every i are read at once
         if (threadIdx.x < 64) fin_lagged(op, jj, sums, K, tol);

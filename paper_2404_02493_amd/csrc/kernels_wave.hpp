@@ -182,9 +182,8 @@ template <int K>
 __global__ __launch_bounds__(FBLOCK) void k_finalize_sums(const double* __restrict__ partials, int nblk, int kcount,
                                                           double* out, BatchIdx bi) {
     bshift(bi.off(), partials, out);
-    __shared__ double red[(FBLOCK / 64) * K];
     __shared__ double sums[K];
-    final_sum<K>(partials, nblk, kcount, red, sums);
+    final_sum<K>(partials, nblk, kcount, sums);
     if ((int)threadIdx.x < kcount) out[threadIdx.x] = sums[threadIdx.x];
 }
 
