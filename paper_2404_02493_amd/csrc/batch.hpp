@@ -413,7 +413,7 @@ static void class_solve(helm_batch b, helm_batch_s::Class& K, const void* const*
         std::vector<double> target(P, 0.0);
         std::vector<int> left(P, 0);
         for (int q : active) {
-            target[q] = std::max(eta, 0.5 * tol * gn[q] / rn[q]);
+            target[q] = std::max(eta, REFINE_MARGIN * tol * gn[q] / rn[q]);
             left[q] = maxit - its[q];
         }
         class_fgmres(K, c0, active, target, left, used, bd, st);
