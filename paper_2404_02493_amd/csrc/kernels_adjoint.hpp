@@ -757,10 +757,11 @@ __global__ __launch_bounds__(FBLOCK) void k_gr_solve(const double* __restrict__ 
 }
 
 // Sums rows e = wv, wv + NW, ... (e < ne) of partials (nblk entries each) with one
-// wavefront per row, the loads of a wavefront's rows issued together; row sums to out[e].
-template <int NEMAX, int THREADS>
-__device__ __forceinline__ void rows_sum(const double* __restrict__ partials, int nblk, int ne, double* out) {
-    constexpr int NW = THREADS / 64, R = (NEMAX + NW - 1) / NW, SB = 48 / R > 0 ? 48 / R : 1;
+// wavefront per row, the loads of a wavefront's rows issued together (SB per lane and row
+// at a time); row sums to out[e].
+template <int NEMAX, int THREADS, int SB>
+__device__ __forceinline__ void rows_sum_sb(const double* __restrict__ partials, int nblk, int ne, double* out) {
+    constexpr int NW = THREADS / 64, R = (NEMAX + NW - 1) / NW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double acc[R];
 #pragma unroll
@@ -789,6 +790,21 @@ __device__ __forceinline__ void rows_sum(const double* __restrict__ partials, in
     }
 }
 
+// rows_sum_sb with a batch that fits the row length: one round of loads up to 1024
+// blocks, without issuing loads for blocks beyond the rows on the small levels.
+template <int NEMAX, int THREADS>
+__device__ __forceinline__ void rows_sum(const double* __restrict__ partials, int nblk, int ne, double* out) {
+    constexpr int NW = THREADS / 64, R = (NEMAX + NW - 1) / NW, SB = 32 / R > 0 ? 32 / R : 1;
+    if (nblk <= 64)
+        rows_sum_sb<NEMAX, THREADS, 1>(partials, nblk, ne, out);
+    else if (nblk <= 256 && SB > 4)
+        rows_sum_sb<NEMAX, THREADS, 4>(partials, nblk, ne, out);
+    else if (nblk > 64 * SB && nblk <= 1024)
+        rows_sum_sb<NEMAX, THREADS, 16>(partials, nblk, ne, out);
+    else
+        rows_sum_sb<NEMAX, THREADS, SB>(partials, nblk, ne, out);
+}
+
 // k_gr_solve for a compile-time dimension MM: the same sums and the same least squares,
 // with the serial part on registers (fully unrolled loops; the rank as a flag).  One
 // block of SBLOCK threads (fewer than FBLOCK, so that the serial thread has the
@@ -799,7 +815,9 @@ __global__ __launch_bounds__(SBLOCK) void k_gr_solve_m(const double* __restrict_
                                                        GRec* __restrict__ R, double tau) {
     constexpr int NE = (MM + 1) * (MM + 2);
     __shared__ double gs[NE];
-    rows_sum<NE, SBLOCK>(partials, nblk, NE, gs);
+    // one wavefront for up to three rows: a fixed batch measured faster here than the
+    // row-length dispatch of rows_sum
+    rows_sum_sb<NE, SBLOCK, 32 / ((NE + SBLOCK / 64 - 1) / (SBLOCK / 64))>(partials, nblk, NE, gs);
     __syncthreads();
     if (threadIdx.x != 0) return;
     double G[NE];
