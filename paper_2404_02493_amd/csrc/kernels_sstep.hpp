@@ -457,10 +457,28 @@ __device__ __forceinline__ void sstep_small_solve(const double* __restrict__ sum
 
 // Reduction of the Gram partials and the coefficient solve in one block of SOLVE_THREADS
 // threads: wavefront v sums partials[v * nblk + b] over b (fixed order; the loads of a
-// lane are issued in batches of SOLVE_BATCH before the adds), then thread 0 solves the
+// lane are issued in batches of up to SOLVE_BATCH before the adds), then thread 0 solves the
 // normal equations and writes K->y (c_j of K_{j-1}, zero for dropped columns), K->cols,
 // K->beta = ||K_0|| and K->done (1; 2 if the norm is not finite).
 constexpr int SOLVE_THREADS = 1024, SOLVE_BATCH = 32;
+
+// Lane's share of a row of nblk partials: row[lane], row[lane + 64], ... added in order,
+// the loads issued SB at a time before the adds.
+template <int SB>
+__device__ __forceinline__ double lane_row_sum(const double* __restrict__ row, int nblk, int lane) {
+    double acc = 0.0;
+    for (int b0 = 0; b0 < nblk; b0 += 64 * SB) {
+        double t[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const int bb = b0 + k * 64 + lane;
+            t[k] = bb < nblk ? row[bb] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) acc += t[k];
+    }
+    return acc;
+}
 
 template <int M>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_sstep_solve(const double* __restrict__ partials, int nblk,
@@ -471,17 +489,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_sstep_solve(const double* __r
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int v = wv; v < NG; v += NW) {
         const double* __restrict__ row = partials + (size_t)v * nblk;
-        double acc = 0.0;
-        for (int b0 = 0; b0 < nblk; b0 += 64 * SOLVE_BATCH) {
-            double t[SOLVE_BATCH];
-#pragma unroll
-            for (int k = 0; k < SOLVE_BATCH; ++k) {
-                const int bb = b0 + k * 64 + lane;
-                t[k] = bb < nblk ? row[bb] : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < SOLVE_BATCH; ++k) acc += t[k];
-        }
+        // a batch no longer than the row (the same sums: the loads left out read zeros)
+        double acc = nblk <= 64     ? lane_row_sum<1>(row, nblk, lane)
+                     : nblk <= 256  ? lane_row_sum<4>(row, nblk, lane)
+                     : nblk <= 1024 ? lane_row_sum<16>(row, nblk, lane)
+                                    : lane_row_sum<SOLVE_BATCH>(row, nblk, lane);
         acc = wave_sum(acc);
         if (lane == 0) sums[v] = acc;
     }
