@@ -51,7 +51,16 @@ CASES = {
                          dict(sign=-1, level3_literal=1, gmres_m=2, gmres_coarse_m=4, adr_steps=3)),
     # heterogeneous 256^2 medium, three cycles, the default sponge of one wavelength
     "grf256": (256, 160.0, 5, 7, "grf", "fmm", None, 3, {}),
+    # GMRES deeper than the single-pass tile record and reverse take (m <= 4): the
+    # per-vector passes and the general least-squares kernels
+    "grf64_deep_gmres": (64, 40.0, 4, 11, "grf", "fmm", 8, 2, dict(gmres_m=5, gmres_coarse_m=6)),
 }
+# The taped GMRES calls keep their monomial Krylov basis k_{j+1} = M k_j / tau, whose
+# conditioning grows with the depth: in FP64 the phase gradient of the deep case is off by
+# 4.8e-11 against about 2e-12 for depths up to 4.  FP32 scales that by 1.5e8 to 5e8 (the
+# ratio of the FP32 and FP64 errors at depths up to 4), which puts the deep case between
+# 7e-3 and 2.4e-2; 3.3e-3 measured.
+FP32_PHI_TOL = {"grf64_deep_gmres": 1e-2}
 
 
 @pytest.fixture(scope="module")
@@ -80,6 +89,8 @@ def test_adjoint_matches_oracle_autograd(oracle_grads, name, prec):
     H = _helm(case, prec, **kw)
     L, gphi, gw, _ = gpu_grad(H, case.g, case.phi, w, K)
     tol_phi, tol_w, tol_L = (1e-8, 1e-8, 1e-11) if prec == "c128" else (2e-3, 2e-3, 1e-4)
+    if prec == "c64" and name in FP32_PHI_TOL:
+        tol_phi = FP32_PHI_TOL[name]
     print(f"{name} {prec}: L {L:.6e} vs {Lo:.6e}; phi rel {relerr(gphi, dphi):.2e}; "
           f"w {np.abs(gw - dw).max() / np.abs(dw).max():.2e}", flush=True)
     assert abs(L - Lo) <= tol_L * abs(Lo)
@@ -187,6 +198,8 @@ def test_full_size_1024_one_cycle_matches_oracle_autograd(oracle_1024, prec):
     H = _helm(case, prec)
     L, gphi, gw, _ = gpu_grad(H, case.g, phi if prec == "c128" else case.phi, w, 1)
     tol_phi, tol_w, tol_L = (1e-8, 1e-8, 1e-11) if prec == "c128" else (2e-3, 2e-3, 1e-4)
+    if prec == "c64" and name in FP32_PHI_TOL:
+        tol_phi = FP32_PHI_TOL[name]
     print(f"grf1024 K=1 {prec}: L {L:.6e} vs {Lo:.6e}; phi rel {relerr(gphi, dphi):.2e}; "
           f"w {np.abs(gw - dw).max() / np.abs(dw).max():.2e}", flush=True)
     assert abs(L - Lo) <= tol_L * abs(Lo)
