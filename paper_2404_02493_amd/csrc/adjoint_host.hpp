@@ -508,7 +508,7 @@ struct AdjEngine {
     // The ADR steps of level 2 in reverse: the last step's re-modulation, then per step the
     // reverse ADR V-cycle and one pass for its demodulation with the re-modulation of the
     // step before it.  The passes that produce a reverse call's xbar also form its dots
-    // <k_j, xbar> (k_ga_dots' partials).
+    // <k_j, xbar>.
     void rev_adr_steps() {
         WaveLevel& W = c->wl[2];
         const size_t n = N(2);
@@ -548,10 +548,10 @@ struct AdjEngine {
         AdrLevel& A = c->al[l];
         const int m = gm_of(c, l);
         if (l == c->LA) {
-            rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb[l], S.abb[l], true, nullptr, true);
+            rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb[l], S.abb[l], true, nullptr);
             return;
         }
-        rev_gmres(l, Tp.x2, m, Tp.kpost, Tp.rpost, S.axb[l], S.abb[l], true, S.axb2[l], true);
+        rev_gmres(l, Tp.x2, m, Tp.kpost, Tp.rpost, S.axb[l], S.abb[l], true, S.axb2[l]);
         const size_t nc = N(l + 1);
         int mc = 0;
         const VecSet<T> Kc = first_rev_basis(s, l + 1, mc);
@@ -565,7 +565,7 @@ struct AdjEngine {
                   dim3(fb(N(l))), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py, (const C*)A.c0,
                   (const C*)S.abb[l + 1], (const C*)Tp.x1, (C*)S.axb2[l], (C*)S.abb[l], S.pxb[l], S.pyb[l], S.c0b[l],
                   Kd, m, c->partials);
-        rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb2[l], S.abb[l], false, nullptr, true);
+        rev_gmres(l, nullptr, m, Tp.kpre, Tp.rpre, S.axb2[l], S.abb[l], false, nullptr);
     }
 
     // Reverse of x = GMRES(M_l; b, x0, m) from the recorded basis kv and record R:
@@ -588,17 +588,13 @@ struct AdjEngine {
                       (C*)bbar, bset ? 0 : 1, (C*)nullptr, S.pxb[l], S.pyb[l], S.c0b[l]);
     }
 
-    // dots_done: the partials of <k_j, xbar> (fb(N(l)) blocks) are already in place.
+    // The partials of <k_j, xbar> (fb(N(l)) blocks) are already in c->partials: the pass
+    // that produced xbar formed them.
     void rev_gmres(int l, const void* x0, int m, void* const* kv, GRec* R, const void* xbar, void* bbar, bool bset,
-                   void* xbar0, bool dots_done = false) {
+                   void* xbar0) {
         AdrLevel& A = c->al[l];
         const size_t n = N(l);
         const int nb = fb(n);
-        VecSet<T> K{};
-        for (int q = 0; q <= m; ++q) K.v[q] = (const C*)kv[q];
-        if (!dots_done)
-            LAUNCH_NB(c, (m + 1.0) * sizeof(C) * n, (k_ga_dots<T>), dim3(nb), dim3(BLOCK), st, n, K, m, (const C*)xbar,
-                      c->partials);
         const double pb = 16.0 * nb * m;
         switch (m) {
             case 1: LAUNCH_NB(c, pb, k_ga_prep_m<1>, dim3(1), dim3(SBLOCK), st, (const double*)c->partials, nb, R, tau(l)); break;

@@ -57,8 +57,10 @@ __device__ __forceinline__ void reduce_store(const double (&acc)[K], int kcount,
     store_partials(sums, kcount, partials);
 }
 
-// acc[2q] + i acc[2q+1] += <k_q, y> = conj(k_q) y at one node, q < md (FP64 products; the
-// sums k_ga_dots forms, so a pass that produces y can form them on the way).
+// acc[2q] + i acc[2q+1] += <k_q, y> = conj(k_q) y at one node, q < md (FP64 products).
+// The reverse of a taped GMRES call needs <k_j, xbar> for its output cotangent xbar; the
+// pass that produces xbar forms their per-block partials on the way (grid-stride over
+// fb(nodes) blocks, the layout k_ga_prep reads).
 template <typename T>
 __device__ __forceinline__ void dots_add(double (&acc)[2 * GMAX], const VecSet<T>& Kd, int md, size_t p,
                                          cplx<T> y) {
@@ -144,8 +146,8 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_scale(int nx, int ny, const 
 }
 
 // k_restrict_scale on one precision with the per-block partials of <k_q, xc>, q < md
-// (Kd: k_1..k_md on the coarse level), the sums of k_ga_dots for the reverse call that
-// reads xc next.  fb(coarse nodes) blocks, as k_ga_dots.
+// (Kd: k_1..k_md on the coarse level), the dots of the reverse call that reads xc next.
+// fb(coarse nodes) blocks.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_restrict_scale_dots(int nx, int ny, const cplx<T>* __restrict__ x,
                                                                cplx<T>* __restrict__ xc, double s, VecSet<T> Kd,
@@ -361,7 +363,7 @@ __global__ __launch_bounds__(BLOCK) void k_dot_ah(Geom G, const T* __restrict__ 
 // Reverse of u' = u + a e^{i theta} (car = e^{i theta}):  abar = e^{-i theta} ubar',
 // thbar += Re <ubar', i a e^{i theta}> = -Im(conj(ubar') a e^{i theta}); with md > 0 also
 // the per-block partials of <k_q, abar>, q < md (Kd: k_1..k_md), for the reverse call that
-// reads abar next (fb(N) blocks, as k_ga_dots).
+// reads abar next (fb(N) blocks).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* __restrict__ ub, const cplx<T>* __restrict__ a,
                                                       const cplx<T>* __restrict__ car, cplx<T>* __restrict__ abar,
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(BLOCK) void k_modadd_adj(size_t N, const cplx<T>* _
 // and, when an (the earlier step's ADR result) is given, for the updated ubar
 //   abar = e^{-i theta} ubar,  thbar -= Im(conj(ubar) an e^{i theta}),
 // with md > 0 the per-block partials of <k_q, abar>, q < md (Kd: k_1..k_md), for the
-// reverse call that reads abar next (fb(N) blocks, as k_ga_dots).
+// reverse call that reads abar next (fb(N) blocks).
 // Interior nodes only, except that abar is written everywhere (0 on the ring).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_step_adj(Geom G, const T* __restrict__ n2,
@@ -1008,20 +1010,7 @@ __global__ __launch_bounds__(BLOCK) void k_gr_combine_rr(int nx, int ny, VecSet<
 
 // ------------------------------------------------------------------ GMRES reverse
 
-// partial <k_j, xbar>, j = 1..m
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_ga_dots(size_t N, VecSet<T> Kv, int m, const cplx<T>* __restrict__ xb,
-                                                   double* partials) {
-    double acc[2 * GMAX];
-#pragma unroll
-    for (int v = 0; v < 2 * GMAX; ++v) acc[v] = 0.0;
-    for (size_t p = blockIdx.x * (size_t)BLOCK + threadIdx.x; p < N; p += (size_t)gridDim.x * BLOCK) {
-        dots_add(acc, Kv, m, p, xb[p]);
-    }
-    reduce_store<2 * GMAX>(acc, 2 * m, partials);
-}
-
-// cbar = <k_j, xbar> summed from the per-block partials of k_ga_dots (one wavefront per
+// cbar = <k_j, xbar> summed from the per-block partials (dots_add; one wavefront per
 // entry, fixed order) into R->cbar, then (one thread, on LDS copies of the record)
 // z = (W^H W)^{-1} cbar and the coefficients of kbar_1..kbar_{m+1} over (xbar, k_1..k_{m+1}):
 //   rho = r0 - W c = k_1 - tau sum c_j k_{j+1},   Wz = tau sum z_j k_{j+1},
@@ -1436,7 +1425,7 @@ __global__ __launch_bounds__(BLOCK) void k_ga_tile(AdrGeom A, const T* __restric
 // Reverse of bc = R (b - M x1) given bcbar (coarse): with t = P bcbar / 4,
 //   bbar += t, xbar -= M^H t, coefficient cotangents with ybar = -t, a = x1.  In place.
 // With md > 0 also the per-block partials of <k_q, xbar>, q < md (Kd: k_1..k_md), the
-// sums k_ga_dots would form for the reverse call that reads xbar next.
+// dots of the reverse call that reads xbar next.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __restrict__ px, const T* __restrict__ py,
                                                       const cplx<T>* __restrict__ c0, const cplx<T>* __restrict__ bcbar,
@@ -1484,7 +1473,7 @@ __global__ __launch_bounds__(BLOCK) void k_adr_rr_adj(AdrGeom A, const T* __rest
         const cplx<T> xb = xbar[p] - mh;
         xbar[p] = xb;
         coef_grad_at(A, px, py, x1, T(-1) * t, i, j, pxb, pyb, c0b);
-        dots_add(acc, Kd, md, p, xb);  // the dots of k_ga_dots for the next reverse call
+        dots_add(acc, Kd, md, p, xb);  // the dots of the next reverse call
     }
     if (md > 0) reduce_store<2 * GMAX>(acc, 2 * md, partials);
 }
