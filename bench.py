@@ -321,6 +321,30 @@ def bench_rect(seed: int, maxit: int = 3000):
     return out
 
 
+def copy_rate(reps: int = 10) -> dict:
+    """Rate of a plain device copy of 2 GiB (complex64, far above the 256 MB last-level
+    cache), read plus written bytes per second: what a streaming kernel reaches on this
+    HBM, beside the published peak the rooflines use."""
+    import torch
+
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.complex64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    nbytes = 2 * n * x.element_size()
+    del x, y
+    return {"GBs": round(nbytes / s / 1e9, 1), "bytes_per_copy": nbytes, "us_per_copy": round(1e6 * s, 1),
+            "note": "torch device copy of 2 GiB complex64; read plus written bytes"}
+
+
 def copy_probe(reps: int = 5):
     """A plain device copy of 4096^2 complex64 values (128 MiB read + 128 MiB written per
     dispatch), the known-size reference for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -584,6 +608,8 @@ def main():
                                     "GBs": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)} for k in ks[:8]]}
 
     roofline_hbm = hbm_rooflines(prof32["kernels"]) if prof32 else None
+    copy_ref = copy_rate()
+    log(f"plain copy: {copy_ref['GBs']} GB/s")
 
     shifted = sharp = batch = comparison = eikonal = rect = None
     if not args.no_extras:
@@ -645,6 +671,7 @@ def main():
         "fp64": fp64,
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
+        "hbm_copy": copy_ref,
         "cpu_baseline": cpu,
         "shifted": shifted,
         "sharp": sharp,
