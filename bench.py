@@ -109,7 +109,8 @@ def single_thread_oracle():
 def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):
     """The adjoint of K unrolled FP32 cycles on the 1024^2, k = 640 random medium
     (7 levels, fast-marching phase in float32): wall time of one helm_cycle_backward
-    (which re-runs the K cycles with their tapes) against K forward cycles."""
+    (which re-runs the K cycles with their tapes) against K forward cycles, and of the
+    split path (a recording forward pass, then only the reverse)."""
     import numpy as np
     import torch
 
@@ -130,22 +131,34 @@ def bench_adjoint(seed: int = 0, K: int = 10, reps: int = 3):
     u = forward()
     _, gu = H.loss(g, u, grad=True)
     H.cycle_backward(K, g, gu)  # first call allocates the tape
+    ur = torch.empty_like(g)
+    H.cycle_record(K, g, ur)  # and the split path's graphs
+    H.cycle_reverse(K, g, gu)
     torch.cuda.synchronize()
-    tf, tb = [], []
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    tf, tb, trec, trev = [], [], [], []
     for _ in range(reps):
-        t0 = time.perf_counter()
-        u = forward()
-        torch.cuda.synchronize()
-        tf.append(time.perf_counter() - t0)
-        t0 = time.perf_counter()
-        H.cycle_backward(K, g, gu)
-        torch.cuda.synchronize()
-        tb.append(time.perf_counter() - t0)
+        tf.append(timed(forward))
+        tb.append(timed(lambda: H.cycle_backward(K, g, gu)))
+        trec.append(timed(lambda: H.cycle_record(K, g, ur)))
+        trev.append(timed(lambda: H.cycle_reverse(K, g, gu)))
     H.close()
     f, b = float(np.median(tf)), float(np.median(tb))
+    rec, rev = float(np.median(trec)), float(np.median(trev))
     return {"workload": "grf1024 (n=1024, k=640, L=7), K=10 FP32 cycles from zero", "forward_ms": round(1e3 * f, 3),
             "backward_ms": round(1e3 * b, 3), "backward_over_forward": round(b / f, 2),
-            "note": "backward re-runs the K cycles recording one tape per cycle, then reverses them"}
+            "note": "backward re-runs the K cycles recording one tape per cycle, then reverses them",
+            "split": {"record_ms": round(1e3 * rec, 3), "reverse_ms": round(1e3 * rev, 3),
+                      "reverse_over_forward": round(rev / f, 2),
+                      "step_ms": round(1e3 * (rec + rev), 3), "unsplit_step_ms": round(1e3 * (f + b), 3),
+                      "note": "the forward pass records its cycles (helm_cycle_record), the backward "
+                              "pass only reverses them (helm_cycle_reverse); step = both"}}
 
 
 HBM_CLEAN = ("k_jac0_restrict", "k_jac0_prolong_jacobi", "k_fg_arnoldi", "k_fg_orth")

@@ -227,6 +227,27 @@ helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const vo
                                 const void* grad_uK, void* grad_phi, double* grad_w, void* ckpt_ws,
                                 void* stream);
 
+/* The same adjoint split at the loss (Section 3.3, eq. loss, and Algorithm 1 reversed), for
+ * callers that run the K cycles anyway (training: the forward pass records, the backward
+ * pass only reverses).
+ * helm_cycle_record: u_{k+1} = C(u_k, g), k = 0..K-1, from u_0 (device, cycle_prec, NULL =
+ *   zero), each cycle recorded on its own tape; u_K (device, ny*n complex in cycle_prec) to
+ *   u_out.  ckpt_ws as for helm_cycle_backward (it must stay untouched until the reverse).
+ *   u_out equals the u_K of K helm_cycle calls up to rounding.  Returns HELM_ENOMEM (nothing
+ *   run, no tape kept) when the K tapes would exceed the limit of helm_cycle_backward's
+ *   one-tape-per-cycle mode; helm_cycle_backward still applies then.
+ * helm_cycle_reverse: grad_phi, grad_w from grad_uK exactly as helm_cycle_backward would
+ *   give them for the same K, g and u_0, using the tapes of the last helm_cycle_record.
+ *   Returns HELM_ESTATE when there are none, when K or g differ from that call's, when the
+ *   phase or the weights changed since, or when a helm_cycle_backward rewrote the tapes.
+ *   Other calls (helm_cycle, helm_loss, helm_solve) may run in between.  The tapes stay
+ *   valid, so one recording can be reversed for several cotangents.
+ * Same requirements as helm_cycle_backward.  Both asynchronous on `stream`. */
+helm_status helm_cycle_record(helm_ctx ctx, int32_t K, const void* g, const void* u0, void* u_out, void* ckpt_ws,
+                              void* stream);
+helm_status helm_cycle_reverse(helm_ctx ctx, int32_t K, const void* g, const void* grad_uK, void* grad_phi,
+                               double* grad_w, void* stream);
+
 /* Loss of the unrolled cycles (Section 3.3, eq. loss, without the normalisation by
  * ||g||^2): *loss = ||g - A u||^2 accumulated in FP64 from g, u (device, cycle_prec);
  * if grad_u (device, cycle_prec) is not NULL it receives the cotangent

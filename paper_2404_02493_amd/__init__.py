@@ -209,10 +209,32 @@ class Helmholtz:
                                         _ptr(ckpt), _stream_ptr(stream)))
         return gphi, gw
 
+    def cycle_record(self, K: int, g, u_out, u0=None, ckpt=None, stream=None):
+        """u_out <- u_K = C^K(u_0, g) with every cycle recorded on its own tape for
+        cycle_reverse (helm_cycle_record).  Raises HelmError (HELM_ENOMEM) when the K tapes
+        do not fit; cycle_backward still applies then."""
+        check(lib().helm_cycle_record(self._ctx, int(K), _ptr(g), _ptr(u0), _ptr(u_out), _ptr(ckpt),
+                                      _stream_ptr(stream)))
+        return u_out
+
+    def cycle_reverse(self, K: int, g, grad_uK, stream=None):
+        """The cotangents of cycle_backward from the tapes of the last cycle_record (same K
+        and g, phase and weights unchanged since).  Returns (grad_phi, grad_w)."""
+        torch = _torch()
+        pdt = torch.float32 if self.cdtype == torch.complex64 else torch.float64
+        gphi = torch.empty(self.shape, dtype=pdt, device=self.device)
+        gw = torch.empty((self.levels,), dtype=torch.float64, device=self.device)
+        check(lib().helm_cycle_reverse(self._ctx, int(K), _ptr(g), _ptr(grad_uK), _ptr(gphi), _ptr(gw),
+                                       _stream_ptr(stream)))
+        return gphi, gw
+
     def unrolled(self, phi, w, g, K: int):
         """u_K after K cycles from u_0 = 0 as a differentiable function of the phase phi
         (tensor of the grid's shape) and the weights w (levels float64 tensor); g is a cycle-dtype
-        device grid.  Gradients come from the hand-written adjoint (helm_cycle_backward)."""
+        device grid.  The forward pass records the cycles (helm_cycle_record) and the
+        backward pass reverses them (helm_cycle_reverse); when the tapes do not fit, the
+        forward runs plain cycles and the backward is helm_cycle_backward.  The phase and
+        the weights must stay as the forward pass set them until its backward pass."""
         return _Unrolled.apply(phi, w, g, self, int(K))
 
     def residual_loss(self, g, u):
@@ -399,9 +421,17 @@ def _autograd_function():
         def forward(ctx, phi, w, g, helm, K):
             helm.set_phase(phi.detach())
             helm.set_weights([float(x) for x in w.detach().cpu().tolist()])
-            u = torch.zeros_like(g)
-            for _ in range(K):
-                helm.cycle(g, u)
+            u = torch.empty_like(g)
+            try:
+                helm.cycle_record(K, g, u)
+                ctx.recorded = True
+            except HelmError as e:
+                if e.status != 2:  # HELM_ENOMEM: the tapes do not fit
+                    raise
+                u.zero_()
+                for _ in range(K):
+                    helm.cycle(g, u)
+                ctx.recorded = False
             ctx.helm, ctx.K = helm, K
             ctx.phi_meta = (phi.dtype, phi.device)
             ctx.w_meta = (w.dtype, w.device)
@@ -412,7 +442,11 @@ def _autograd_function():
         def backward(ctx, grad_u):
             (g,) = ctx.saved_tensors
             helm = ctx.helm
-            gphi, gw = helm.cycle_backward(ctx.K, g, grad_u.contiguous().to(g.dtype))
+            gu = grad_u.contiguous().to(g.dtype)
+            if ctx.recorded:
+                gphi, gw = helm.cycle_reverse(ctx.K, g, gu)
+            else:
+                gphi, gw = helm.cycle_backward(ctx.K, g, gu)
             return (gphi.to(dtype=ctx.phi_meta[0], device=ctx.phi_meta[1]),
                     gw.to(dtype=ctx.w_meta[0], device=ctx.w_meta[1]), None, None, None)
 

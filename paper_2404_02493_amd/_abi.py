@@ -16,7 +16,7 @@ STATUS = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP", 4: "
 # every symbol declared in include/helm.h
 EXPORTS = ["helm_desc_default", "helm_setup", "helm_set_phase", "helm_set_rays", "helm_eikonal", "helm_set_weights", "helm_get_weights",
            "helm_get_lambdas", "helm_cycle", "helm_solve", "helm_residual", "helm_residual_noalloc",
-           "helm_cycle_backward", "helm_loss",
+           "helm_cycle_backward", "helm_cycle_record", "helm_cycle_reverse", "helm_loss",
            "helm_batch_setup", "helm_batch_get", "helm_batch_solve", "helm_batch_classes", "helm_batch_destroy",
            "helm_tune", "helm_set_tuning", "helm_get_tuning",
            "helm_debug_op", "helm_profile_begin", "helm_profile_end", "helm_destroy", "helm_status_string", "helm_last_error", "helm_version"]
@@ -100,6 +100,10 @@ def lib():
     L.helm_residual_noalloc.argtypes = [vp, vp, vp, vp, P(dbl), P(dbl), vp]
     L.helm_cycle_backward.restype = i32
     L.helm_cycle_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.helm_cycle_record.restype = i32
+    L.helm_cycle_record.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.helm_cycle_reverse.restype = i32
+    L.helm_cycle_reverse.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.helm_loss.restype = i32
     L.helm_batch_setup.restype = i32
     L.helm_batch_setup.argtypes = [i32, vp, P(vp), P(vp), i32, i32, P(vp), vp]

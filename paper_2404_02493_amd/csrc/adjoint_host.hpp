@@ -50,6 +50,12 @@ struct AdjState {
     double* wacc = nullptr;                  // weight cotangents (FP64, device)
     void* ckpt = nullptr;                    // library-owned checkpoints
     size_t ckpt_bytes = 0;
+    // the tapes of helm_cycle_record, reversible by helm_cycle_reverse while valid
+    bool rec_valid = false;
+    int rec_K = 0;
+    const void* rec_g = nullptr;
+    char* rec_ck = nullptr;
+    uint64_t rec_gen = 0;
 };
 
 static void dfree(helm_ctx c, void* p) {
@@ -661,15 +667,14 @@ struct AdjEngine {
     }
 };
 
-// Checkpointed forward, then the reverse sweep over the K cycles.
+// The checkpoint buffer of K cycles (library-owned unless ckpt_ws), u_0 (zero if NULL) in
+// its first slot.
 template <typename T>
-static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, const void* grad_uK, void* grad_phi,
-                           double* grad_w, void* ckpt_ws, hipStream_t st) {
+static char* adj_checkpoints(helm_ctx c, int K, const void* u0, void* ckpt_ws, hipStream_t st) {
     if (!c->adj) c->adj = new AdjState();
     adj_alloc(c, st);
     AdjState& S = *c->adj;
-    const size_t NF = (size_t)c->d.n * c->d.ny;
-    const size_t vb = NF * sizeof(cplx<T>);
+    const size_t vb = (size_t)c->d.n * c->d.ny * sizeof(cplx<T>);
     char* ck = (char*)ckpt_ws;
     if (!ck) {
         if (S.ckpt_bytes < (size_t)K * vb) {
@@ -681,7 +686,16 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
         }
         ck = (char*)S.ckpt;
     }
-    // zero the accumulators
+    if (u0) HIPCHK(hipMemcpyAsync(ck, u0, vb, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(hipMemsetAsync(ck, 0, vb, st));
+    return ck;
+}
+
+// Zero accumulators of the coefficient, carrier, phase and weight cotangents, and the
+// cotangent of u_K as the reverse sweep's start.
+template <typename T>
+static void adj_seed(helm_ctx c, const void* grad_uK, hipStream_t st) {
+    AdjState& S = *c->adj;
     HIPCHK(hipMemsetAsync(S.wacc, 0, 64 * sizeof(double), st));
     if (S.M > 0) {
         for (int l = 2; l <= c->LA; ++l) {
@@ -694,55 +708,98 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
         HIPCHK(hipMemsetAsync(S.thb, 0, N2 * sizeof(double), st));
         HIPCHK(hipMemsetAsync(S.phib2, 0, N2 * sizeof(double), st));
     }
-    if (u0) HIPCHK(hipMemcpyAsync(ck, u0, vb, hipMemcpyDeviceToDevice, st));
-    else HIPCHK(hipMemsetAsync(ck, 0, vb, st));
-    HIPCHK(hipMemcpyAsync(S.fb[0], grad_uK, vb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(S.fb[0], grad_uK, (size_t)c->d.n * c->d.ny * sizeof(cplx<T>), hipMemcpyDeviceToDevice,
+                          st));
+}
+
+// Captures body on the capture stream into graph slot a (unless it holds a graph for the
+// same key and K), then launches it on st.
+template <typename T, typename Body>
+static void adj_replay(helm_ctx c, AdjGraph& a, const void* k0, const void* k1, const void* k2, int K, hipStream_t st,
+                       Body&& body) {
+    if (!a.exec || a.key[0] != k0 || a.key[1] != k1 || a.key[2] != k2 || a.K != K) {
+        if (a.exec) (void)hipGraphExecDestroy(a.exec);
+        a = AdjGraph{};
+        if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            AdjEngine<T> Rc(c, c->cap_stream);
+            body(Rc);
+        } catch (...) {
+            (void)hipStreamEndCapture(c->cap_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(e);
+        a.exec = exec;
+        a.key[0] = k0;
+        a.key[1] = k1;
+        a.key[2] = k2;
+        a.K = K;
+    }
+    HIPCHK(hipGraphLaunch(a.exec, st));
+}
+
+// The recording of K cycles from the checkpoint ck[0], one tape each; u_{k+1} from the
+// recording into ck[k+1], and u_K into u_out when given.
+template <typename T>
+static void adj_record_all(AdjEngine<T>& E, const void* g, char* ck, int K, void* u_out) {
+    AdjState& S = *E.c->adj;
+    const size_t vb = (size_t)E.c->d.n * E.c->d.ny * sizeof(cplx<T>);
+    for (int k = 0; k < K; ++k) {
+        S.cur = k;
+        E.rec_cycle(g, ck + (size_t)k * vb);
+        if (k + 1 < K) E.post_jacobi(g, ck + (size_t)(k + 1) * vb);
+        else if (u_out) E.post_jacobi(g, u_out);
+    }
+    S.cur = 0;
+}
+
+// The reverse sweep over K recorded tapes (u_k from the checkpoints).
+template <typename T>
+static void adj_reverse_all(AdjEngine<T>& E, const void* g, char* ck, int K) {
+    AdjState& S = *E.c->adj;
+    const size_t vb = (size_t)E.c->d.n * E.c->d.ny * sizeof(cplx<T>);
+    for (int k = K - 1; k >= 0; --k) {
+        S.cur = k;
+        E.rev_cycle(g, ck + (size_t)k * vb);
+    }
+    S.cur = 0;
+}
+
+// The phase and weight cotangents from the accumulators.
+template <typename T>
+static void adj_finish(helm_ctx c, void* grad_phi, double* grad_w, hipStream_t st) {
+    AdjEngine<T> R(c, st);
+    if (c->f32) R.template phase_out<float>(grad_phi);
+    else R.template phase_out<double>(grad_phi);
+    HIPCHK(hipMemcpyAsync(grad_w, c->adj->wacc, c->L * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
+// Checkpointed forward, then the reverse sweep over the K cycles.
+template <typename T>
+static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, const void* grad_uK, void* grad_phi,
+                           double* grad_w, void* ckpt_ws, hipStream_t st) {
+    char* ck = adj_checkpoints<T>(c, K, u0, ckpt_ws, st);
+    AdjState& S = *c->adj;
+    S.rec_valid = false;  // the tapes are rewritten here
+    const size_t vb = (size_t)c->d.n * c->d.ny * sizeof(cplx<T>);
+    adj_seed<T>(c, grad_uK, st);
     AdjEngine<T> R(c, st);
     const bool graphs = c->d.use_graphs && !c->prof.on;
-    // Captures body on the capture stream and keeps the graph for (g, ck, K).
-    auto replay = [&](int key_K, auto&& body) {
-        if (!c->adj_exec || c->adj_g != g || c->adj_ck != ck || c->adj_K != key_K) {
-            if (c->adj_exec) (void)hipGraphExecDestroy(c->adj_exec);
-            c->adj_exec = nullptr;
-            if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-            hipGraph_t graph = nullptr;
-            HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            try {
-                AdjEngine<T> Rc(c, c->cap_stream);
-                body(Rc);
-            } catch (...) {
-                (void)hipStreamEndCapture(c->cap_stream, &graph);
-                if (graph) (void)hipGraphDestroy(graph);
-                throw;
-            }
-            HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
-            hipGraphExec_t exec = nullptr;
-            const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            HIPCHK(e);
-            c->adj_exec = exec;
-            c->adj_g = g;
-            c->adj_ck = ck;
-            c->adj_K = key_K;
-        }
-        HIPCHK(hipGraphLaunch(c->adj_exec, st));
-    };
     if (adj_tapes_for(c, K, st)) {
         // every cycle recorded once on its own tape, u_{k+1} from the recording, then the
         // reverse sweep over the tapes (about 1000 launches a cycle, one graph for all)
         auto body = [&](AdjEngine<T>& E) {
-            for (int k = 0; k < K; ++k) {
-                S.cur = k;
-                E.rec_cycle(g, ck + (size_t)k * vb);
-                if (k + 1 < K) E.post_jacobi(g, ck + (size_t)(k + 1) * vb);
-            }
-            for (int k = K - 1; k >= 0; --k) {
-                S.cur = k;
-                E.rev_cycle(g, ck + (size_t)k * vb);
-            }
-            S.cur = 0;
+            adj_record_all<T>(E, g, ck, K, nullptr);
+            adj_reverse_all<T>(E, g, ck, K);
         };
-        if (graphs) replay(K, body);
+        if (graphs) adj_replay<T>(c, c->adj_graph[ADJ_FULL], g, ck, nullptr, K, st, body);
         else body(R);
     } else {
         // one tape: the K forward cycles for the checkpoints u_0 .. u_{K-1}, then per cycle
@@ -758,15 +815,54 @@ static void cycle_backward(helm_ctx c, int K, const void* g, const void* u0, con
                 continue;
             }
             HIPCHK(hipMemcpyAsync(S.ubuf, uk, vb, hipMemcpyDeviceToDevice, st));
-            replay(0, [&](AdjEngine<T>& E) {
+            adj_replay<T>(c, c->adj_graph[ADJ_FULL], g, ck, nullptr, 0, st, [&](AdjEngine<T>& E) {
                 E.rec_cycle(g, S.ubuf);
                 E.rev_cycle(g, S.ubuf);
             });
         }
     }
-    if (c->f32) R.template phase_out<float>(grad_phi);
-    else R.template phase_out<double>(grad_phi);
-    HIPCHK(hipMemcpyAsync(grad_w, S.wacc, c->L * sizeof(double), hipMemcpyDeviceToDevice, st));
+    adj_finish<T>(c, grad_phi, grad_w, st);
+    HIPCHK(hipGetLastError());
+}
+
+// The forward half of a split adjoint: K cycles from u_0, each recorded on its own tape,
+// u_K to u_out; false (nothing run) when the K tapes do not fit.
+template <typename T>
+static bool cycle_record(helm_ctx c, int K, const void* g, const void* u0, void* u_out, void* ckpt_ws,
+                         hipStream_t st) {
+    char* ck = adj_checkpoints<T>(c, K, u0, ckpt_ws, st);
+    AdjState& S = *c->adj;
+    S.rec_valid = false;
+    if (!adj_tapes_for(c, K, st)) return false;
+    auto body = [&](AdjEngine<T>& E) { adj_record_all<T>(E, g, ck, K, u_out); };
+    if (c->d.use_graphs && !c->prof.on) {
+        adj_replay<T>(c, c->adj_graph[ADJ_REC], g, ck, u_out, K, st, body);
+    } else {
+        AdjEngine<T> R(c, st);
+        body(R);
+    }
+    HIPCHK(hipGetLastError());
+    S.rec_valid = true;
+    S.rec_K = K;
+    S.rec_g = g;
+    S.rec_ck = ck;
+    S.rec_gen = c->data_gen;
+    return true;
+}
+
+// The reverse half: the tapes of the last cycle_record, for the cotangent of its u_K.
+template <typename T>
+static void cycle_reverse(helm_ctx c, const void* grad_uK, void* grad_phi, double* grad_w, hipStream_t st) {
+    AdjState& S = *c->adj;
+    adj_seed<T>(c, grad_uK, st);
+    auto body = [&](AdjEngine<T>& E) { adj_reverse_all<T>(E, S.rec_g, S.rec_ck, S.rec_K); };
+    if (c->d.use_graphs && !c->prof.on) {
+        adj_replay<T>(c, c->adj_graph[ADJ_REV], S.rec_g, S.rec_ck, nullptr, S.rec_K, st, body);
+    } else {
+        AdjEngine<T> R(c, st);
+        body(R);
+    }
+    adj_finish<T>(c, grad_phi, grad_w, st);
     HIPCHK(hipGetLastError());
 }
 

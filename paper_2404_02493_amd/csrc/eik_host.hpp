@@ -142,6 +142,7 @@ static helm_status eikonal(helm_ctx c, const double* src, int nsrc, int max_roun
     drop_graphs(c);
     c->phase_set = true;
     c->phase_factored = nsrc == 1 && c->L >= 3;
+    ++c->data_gen;
     if (rounds_out) *rounds_out = rounds_max;
     if (change_out) *change_out = change_max;
     return HELM_OK;

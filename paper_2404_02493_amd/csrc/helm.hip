@@ -79,6 +79,14 @@ struct AdrLevel {
 
 struct AdjState;
 
+// A captured adjoint graph and the pointers and cycle count it was captured for.
+struct AdjGraph {
+    hipGraphExec_t exec = nullptr;
+    const void* key[3] = {};
+    int K = -1;
+};
+enum { ADJ_FULL = 0, ADJ_REC = 1, ADJ_REV = 2 };  // slots: record + reverse, record, reverse
+
 // Chebyshev coefficient tables and per-level (lambda, alpha) in device memory (one copy per
 // problem): la[0] = the Jacobi weight of level 1, la[2 l], la[2 l + 1] = (lambda_l, alpha_l);
 // cheb[l][kind] rows of 3 doubles, row 0 = {1/theta, 0, 0},
@@ -104,6 +112,8 @@ struct helm_ctx_s {
     void* car2 = nullptr;    // carrier e^{i sigma k phi} on level 2 (cycle precision)
     bool phase_set = false;
     bool phase_factored = false;  // ADR coefficients from the product rule (helm_eikonal)
+    uint64_t data_gen = 0;  // counts changes of the phase and the weights (a recorded tape is
+                            // reversible only while it is unchanged)
     // phase sets of the ADR correction: set 0 is the phase of helm_set_phase; helm_set_rays
     // fills nsets plane-wave sets and the m-th ADR step of a cycle uses set m mod nsets
     struct PhaseSet {
@@ -141,12 +151,10 @@ struct helm_ctx_s {
     hipEvent_t col_ev[helm::MAXM] = {};
     void* dbuf = nullptr;    // inner correction (mode 1)
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
-    hipGraphExec_t adj_exec = nullptr;  // the adjoint's captured work for (adj_g, adj_ck, adj_K): all K
-                                        // cycles with one tape each (adj_K = K), or the recording and
-                                        // reverse of one cycle (adj_K = 0)
-    const void* adj_g = nullptr;
-    const void* adj_ck = nullptr;
-    int adj_K = -1;
+    // the adjoint's captured work: ADJ_FULL all K cycles with one tape each (K) or the
+    // recording and reverse of one cycle (K = 0), keyed by (g, checkpoints); ADJ_REC the
+    // recording of K cycles, keyed by (g, checkpoints, u_K out); ADJ_REV their reverse
+    helm::AdjGraph adj_graph[3];
     // launch shapes chosen by the autotuner (0 = built-in default)
     struct Tuning {
         int sstep_rows[16] = {};    // s-step form on ADR level l: steps per marching unit, 1/2 tiles, 0 default
@@ -1308,6 +1316,7 @@ static void build_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
 static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
     if (c->L < 3) {
         c->phase_set = true;
+        ++c->data_gen;
         return;
     }
     use_set(c, 0);
@@ -1317,6 +1326,7 @@ static void set_phase(helm_ctx c, const void* phi, int is64, hipStream_t st) {
     drop_graphs(c);
     c->phase_set = true;
     c->phase_factored = false;
+    ++c->data_gen;
 }
 
 // Wave-Ray phases: count plane waves phi_m = nbar (cos theta_m x + sin theta_m y),
@@ -1325,6 +1335,7 @@ static void set_rays(helm_ctx c, int count, hipStream_t st) {
     REQUIRE(count >= 1 && count <= 64, "helm_set_rays: count must be in 1..64");
     if (c->L < 3) {
         c->phase_set = true;
+        ++c->data_gen;
         return;
     }
     const bool f64c = !c->f32;
@@ -1366,6 +1377,7 @@ static void set_rays(helm_ctx c, int count, hipStream_t st) {
     drop_graphs(c);
     c->phase_set = true;
     c->phase_factored = false;
+    ++c->data_gen;
 }
 
 template <typename T>
@@ -1384,11 +1396,10 @@ static void cycle_eager(helm_ctx c, const void* g, const void* u_in, void* u_out
 static void drop_graphs(helm_ctx c) {
     for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
     c->graphs.clear();
-    if (c->adj_exec) (void)hipGraphExecDestroy(c->adj_exec);
-    c->adj_exec = nullptr;
-    c->adj_g = nullptr;
-    c->adj_ck = nullptr;
-    c->adj_K = -1;
+    for (auto& a : c->adj_graph) {
+        if (a.exec) (void)hipGraphExecDestroy(a.exec);
+        a = helm::AdjGraph{};
+    }
 }
 
 // One cycle: replays the graph captured for these pointers (capturing it on first
@@ -1713,6 +1724,7 @@ helm_status helm_set_weights(helm_ctx ctx, const double* w) {
         ctx->w.assign(w, w + ctx->L);
         write_cycle_tables(ctx);
         drop_graphs(ctx);
+        ++ctx->data_gen;
         return HELM_OK;
     })
 }
@@ -1783,23 +1795,66 @@ helm_status helm_residual_noalloc(helm_ctx ctx, const void* g, const void* u, vo
     })
 }
 
+// Checks shared by the adjoint entry points.
+static void adj_require(helm_ctx ctx, const char* who) {
+    REQUIRE(ctx->nsets == 1, std::string(who) + " needs a single phase (helm_set_phase), not Wave-Ray phases");
+    if (ctx->d.adr_steps > 0 && ctx->L >= 3 && !ctx->phase_set)
+        throw Error(HELM_ESTATE, std::string("helm_set_phase must be called before ") + who);
+    if (ctx->phase_factored)
+        throw Error(HELM_ESTATE, std::string(who) + " needs a phase from helm_set_phase (the product-rule "
+                                                    "coefficients of helm_eikonal have no adjoint)");
+    REQUIRE(ctx->d.gmres_m <= GMAX && ctx->d.gmres_coarse_m <= GMAX, "the adjoint supports GMRES dimensions up to 6");
+}
+
 helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const void* u0, const void* grad_uK,
                                 void* grad_phi, double* grad_w, void* ckpt_ws, void* stream) {
     ABI_GUARD({
-        REQUIRE(ctx == nullptr || ctx->nsets == 1, "helm_cycle_backward needs a single phase (helm_set_phase), not Wave-Ray phases");
         REQUIRE(ctx != nullptr && g != nullptr && grad_uK != nullptr && grad_phi != nullptr && grad_w != nullptr,
                 "NULL argument");
         REQUIRE(K >= 1 && K <= 100000, "K must be in [1, 100000]");
-        if (ctx->d.adr_steps > 0 && ctx->L >= 3 && !ctx->phase_set)
-            throw Error(HELM_ESTATE, "helm_set_phase must be called before helm_cycle_backward");
-        if (ctx->phase_factored)
-            throw Error(HELM_ESTATE, "helm_cycle_backward needs a phase from helm_set_phase (the product-rule "
-                                     "coefficients of helm_eikonal have no adjoint)");
-        REQUIRE(ctx->d.gmres_m <= GMAX && ctx->d.gmres_coarse_m <= GMAX,
-                "the adjoint supports GMRES dimensions up to 6");
+        adj_require(ctx, "helm_cycle_backward");
         hipStream_t st = (hipStream_t)stream;
         if (ctx->f32) cycle_backward<float>(ctx, K, g, u0, grad_uK, grad_phi, grad_w, ckpt_ws, st);
         else cycle_backward<double>(ctx, K, g, u0, grad_uK, grad_phi, grad_w, ckpt_ws, st);
+        HIPCHK(hipGetLastError());
+        return HELM_OK;
+    })
+}
+
+helm_status helm_cycle_record(helm_ctx ctx, int32_t K, const void* g, const void* u0, void* u_out, void* ckpt_ws,
+                              void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && u_out != nullptr, "NULL argument");
+        REQUIRE(K >= 1 && K <= 100000, "K must be in [1, 100000]");
+        adj_require(ctx, "helm_cycle_record");
+        hipStream_t st = (hipStream_t)stream;
+        const bool ok = ctx->f32 ? cycle_record<float>(ctx, K, g, u0, u_out, ckpt_ws, st)
+                                 : cycle_record<double>(ctx, K, g, u0, u_out, ckpt_ws, st);
+        if (!ok)
+            throw Error(HELM_ENOMEM, "helm_cycle_record: the K tapes do not fit (helm_cycle_backward records "
+                                     "one cycle at a time)");
+        HIPCHK(hipGetLastError());
+        return HELM_OK;
+    })
+}
+
+helm_status helm_cycle_reverse(helm_ctx ctx, int32_t K, const void* g, const void* grad_uK, void* grad_phi,
+                               double* grad_w, void* stream) {
+    ABI_GUARD({
+        REQUIRE(ctx != nullptr && g != nullptr && grad_uK != nullptr && grad_phi != nullptr && grad_w != nullptr,
+                "NULL argument");
+        adj_require(ctx, "helm_cycle_reverse");
+        const helm::AdjState* S = ctx->adj;
+        if (!S || !S->rec_valid)
+            throw Error(HELM_ESTATE, "helm_cycle_reverse needs the tapes of a helm_cycle_record (none, or "
+                                     "rewritten by helm_cycle_backward)");
+        if (S->rec_K != K || S->rec_g != g)
+            throw Error(HELM_ESTATE, "helm_cycle_reverse: K and g must be those of the last helm_cycle_record");
+        if (S->rec_gen != ctx->data_gen)
+            throw Error(HELM_ESTATE, "helm_cycle_reverse: the phase or the weights changed since helm_cycle_record");
+        hipStream_t st = (hipStream_t)stream;
+        if (ctx->f32) cycle_reverse<float>(ctx, grad_uK, grad_phi, grad_w, st);
+        else cycle_reverse<double>(ctx, grad_uK, grad_phi, grad_w, st);
         HIPCHK(hipGetLastError());
         return HELM_OK;
     })

@@ -101,20 +101,89 @@ def test_adjoint_matches_oracle_autograd(oracle_grads, name, prec):
     H.close()
 
 
+def split_grad(H, g_np, phi, w, K):
+    """(loss, grad_phi, grad_w, u_K) through helm_cycle_record and helm_cycle_reverse."""
+    H.set_phase(phi)
+    H.set_weights(w)
+    g = torch.as_tensor(g_np).to(H.cdtype).to("cuda:0").contiguous()
+    u = torch.empty_like(g)
+    H.cycle_record(K, g, u)
+    L, gu = H.loss(g, u, grad=True)
+    gphi, gw = H.cycle_reverse(K, g, gu)
+    torch.cuda.synchronize()
+    return L, gphi.double().cpu().numpy(), gw.cpu().numpy(), u
+
+
 def test_autograd_function_uses_the_adjoint(oracle_grads):
-    """torch.autograd through Helmholtz.unrolled / residual_loss gives the same
-    gradients as the direct helm_cycle_backward call."""
+    """torch.autograd through Helmholtz.unrolled / residual_loss gives the gradients of
+    the direct helm_cycle_record / helm_cycle_reverse calls, and those of
+    helm_cycle_backward up to the rounding of u_K."""
     case, w, K, kw, Lo, dphi, dw = oracle_grads("grf64")
     H = _helm(case, "c128", **kw)
-    L, gphi, gw, _ = gpu_grad(H, case.g, case.phi, w, K)
+    L, gphi, gw, _ = split_grad(H, case.g, case.phi, w, K)
+    Lb, gphib, gwb, _ = gpu_grad(H, case.g, case.phi, w, K)
     phi_t = torch.tensor(case.phi, dtype=torch.float64, requires_grad=True)
     w_t = torch.tensor(w, dtype=torch.float64, requires_grad=True)
     g = torch.as_tensor(case.g).to("cuda:0")
     loss = H.residual_loss(g, H.unrolled(phi_t, w_t, g, K))
     loss.backward()
-    assert abs(loss.item() - L) <= 1e-14 * abs(L)
+    assert loss.item() == L
     assert np.array_equal(phi_t.grad.numpy(), gphi)
     assert np.array_equal(w_t.grad.numpy(), gw)
+    assert abs(Lb - L) <= 1e-12 * abs(L)
+    assert relerr(gphi, gphib) <= 1e-10 and np.abs(gw - gwb).max() <= 1e-10 * np.abs(gwb).max()
+    H.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_record_reverse_split(oracle_grads, prec):
+    """helm_cycle_record gives u_K of K plain cycles up to rounding; with the same
+    cotangent, helm_cycle_reverse gives exactly what helm_cycle_backward gives (the same
+    recording, reversed by the same kernels); the tapes stay valid for a second reverse;
+    changing the weights, a different K or g, or a helm_cycle_backward in between makes
+    the reverse a state error."""
+    from paper_2404_02493_amd import HelmError
+
+    case, w, K, kw, Lo, dphi, dw = oracle_grads("grf64")
+    H = _helm(case, prec, **kw)
+    H.set_phase(case.phi)
+    H.set_weights(w)
+    g = torch.as_tensor(case.g).to(H.cdtype).to("cuda:0").contiguous()
+    u_plain = torch.zeros_like(g)
+    for _ in range(K):
+        H.cycle(g, u_plain)
+    u = torch.empty_like(g)
+    H.cycle_record(K, g, u)
+    du = relerr(u.cpu().numpy(), u_plain.cpu().numpy())
+    print(f"{prec}: record u_K vs plain cycles {du:.2e}", flush=True)
+    assert du <= (1e-12 if prec == "c128" else 1e-5)
+    _, gu = H.loss(g, u, grad=True)
+    gphi1, gw1 = H.cycle_reverse(K, g, gu)
+    gphi2, gw2 = H.cycle_reverse(K, g, gu)
+    # a plain cycle and a loss in between leave the tapes alone
+    u2 = torch.zeros_like(g)
+    H.cycle(g, u2)
+    H.loss(g, u2)
+    gphi3, gw3 = H.cycle_reverse(K, g, gu)
+    assert torch.equal(gphi1, gphi2) and torch.equal(gw1, gw2)
+    assert torch.equal(gphi1, gphi3) and torch.equal(gw1, gw3)
+    with pytest.raises(HelmError) as e:
+        H.cycle_reverse(K + 1, g, gu)
+    assert e.value.status == 6
+    g2 = g.clone()
+    with pytest.raises(HelmError) as e:
+        H.cycle_reverse(K, g2, gu)
+    assert e.value.status == 6
+    gphib, gwb = H.cycle_backward(K, g, gu)
+    assert torch.equal(gphi1, gphib) and torch.equal(gw1, gwb)
+    with pytest.raises(HelmError) as e:  # the tapes were rewritten
+        H.cycle_reverse(K, g, gu)
+    assert e.value.status == 6
+    H.cycle_record(K, g, u)
+    H.set_weights(w)
+    with pytest.raises(HelmError) as e:
+        H.cycle_reverse(K, g, gu)
+    assert e.value.status == 6
     H.close()
 
 
