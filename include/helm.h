@@ -232,7 +232,8 @@ helm_status helm_cycle_backward(helm_ctx ctx, int32_t K, const void* g, const vo
  * pass only reverses).
  * helm_cycle_record: u_{k+1} = C(u_k, g), k = 0..K-1, from u_0 (device, cycle_prec, NULL =
  *   zero), each cycle recorded on its own tape; u_K (device, ny*n complex in cycle_prec) to
- *   u_out.  ckpt_ws as for helm_cycle_backward (it must stay untouched until the reverse).
+ *   u_out, which must not overlap g (the reverse reads g again).  ckpt_ws as for
+ *   helm_cycle_backward (it must stay untouched until the reverse).
  *   u_out equals the u_K of K helm_cycle calls up to rounding.  Returns HELM_ENOMEM (nothing
  *   run, no tape kept) when the K tapes would exceed the limit of helm_cycle_backward's
  *   one-tape-per-cycle mode; helm_cycle_backward still applies then.

@@ -51,6 +51,7 @@ struct AdjState {
     void* ckpt = nullptr;                    // library-owned checkpoints
     size_t ckpt_bytes = 0;
     // the tapes of helm_cycle_record, reversible by helm_cycle_reverse while valid
+    void* uK = nullptr;                      // u_K of the recording (graph output, copied out)
     bool rec_valid = false;
     int rec_K = 0;
     const void* rec_g = nullptr;
@@ -834,13 +835,17 @@ static bool cycle_record(helm_ctx c, int K, const void* g, const void* u0, void*
     AdjState& S = *c->adj;
     S.rec_valid = false;
     if (!adj_tapes_for(c, K, st)) return false;
-    auto body = [&](AdjEngine<T>& E) { adj_record_all<T>(E, g, ck, K, u_out); };
+    const size_t vb = (size_t)c->d.n * c->d.ny * sizeof(cplx<T>);
+    if (!S.uK) S.uK = dalloc(c, vb);
+    // u_K goes to a buffer of the state, so that the graph does not depend on u_out
+    auto body = [&](AdjEngine<T>& E) { adj_record_all<T>(E, g, ck, K, S.uK); };
     if (c->d.use_graphs && !c->prof.on) {
-        adj_replay<T>(c, c->adj_graph[ADJ_REC], g, ck, u_out, K, st, body);
+        adj_replay<T>(c, c->adj_graph[ADJ_REC], g, ck, nullptr, K, st, body);
     } else {
         AdjEngine<T> R(c, st);
         body(R);
     }
+    HIPCHK(hipMemcpyAsync(u_out, S.uK, vb, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipGetLastError());
     S.rec_valid = true;
     S.rec_K = K;

@@ -152,8 +152,8 @@ struct helm_ctx_s {
     void* dbuf = nullptr;    // inner correction (mode 1)
     helm::AdjState* adj = nullptr;  // adjoint tape (allocated on first use)
     // the adjoint's captured work: ADJ_FULL all K cycles with one tape each (K) or the
-    // recording and reverse of one cycle (K = 0), keyed by (g, checkpoints); ADJ_REC the
-    // recording of K cycles, keyed by (g, checkpoints, u_K out); ADJ_REV their reverse
+    // recording and reverse of one cycle (K = 0); ADJ_REC the recording of K cycles;
+    // ADJ_REV their reverse; each keyed by (g, checkpoints) and K
     helm::AdjGraph adj_graph[3];
     // launch shapes chosen by the autotuner (0 = built-in default)
     struct Tuning {
