@@ -138,14 +138,14 @@ __device__ __forceinline__ cplx<T> up_apply(const UpCoef<T>& k, cplx<T> c, cplx<
 
 // Strip/segment geometry of the marching passes.  GRAM: the pass builds K_0..K_M
 // (else K_0..K_{M-1}).
-template <int M, bool X0, bool GRAM, int XH = 0, int EP = -1>
+template <int M, bool X0, bool GRAM, int XH = 0, int EP = -1, int WR = 8>
 struct March {
     static constexpr int D = X0 ? 1 : 0;
     static constexpr int NK = GRAM ? M : M - 1;  // last Krylov vector built
     static constexpr int H = NK + D + XH;        // halo of the loaded fields (XH: rows and
                                                  // columns beyond its own that a unit emits)
     static constexpr int TXW = 64 - 2 * H;       // columns owned by one strip
-    static constexpr int W = 8;                  // rows kept per field (ring of registers)
+    static constexpr int W = WR;                 // rows kept per field (ring of registers, <= 8)
     // Steps after its own step that a loaded row is still read: x0 by K_0 of the next
     // row (and by the combination NK + D rows later), b by K_0, and the fields an
     // epilogue loads with the row by the emit of that row (EP = 0) or of the next one
@@ -176,13 +176,13 @@ struct NoExtra {
 // r = q - DIR (NK + D) is handed to emit(r, slot, k, dir) (k[j] = K_j on row r; slot: the
 // std::integral_constant ring position of row r; dir: std::integral_constant DIR) for
 // the unit's rows and XH rows beyond them on either side.
-template <typename T, int M, bool X0, bool GRAM, int XH, int EP, int DIR, typename Extra, typename Emit>
+template <typename T, int M, bool X0, bool GRAM, int XH, int EP, int DIR, int WR, typename Extra, typename Emit>
 __device__ __forceinline__ void sstep_march_dir(const AdrGeom& A, int S, const T* __restrict__ px,
                                                 const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                                 const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
                                                 int j, bool colok, int rb, int re, cplx<T> (&xr)[8], Extra& ex,
                                                 Emit& emit) {
-    using Mc = March<M, X0, GRAM, XH, EP>;
+    using Mc = March<M, X0, GRAM, XH, EP, WR>;
     constexpr int H = Mc::H, D = Mc::D, NK = Mc::NK, W = Mc::W, P = Mc::P;
     const int nx = A.nx, ny = A.ny;
     // first row loaded: the segment's rows plus H warm-up rows on the side it starts from
@@ -266,7 +266,7 @@ __device__ __forceinline__ void sstep_march_dir(const AdrGeom& A, int S, const T
 
 // The unit of this wavefront (column j of lane, rows [rb, re]) and its march, down on even
 // segments and up on odd ones.
-template <typename T, int M, bool X0, bool GRAM, int XH, int EP, typename Extra, typename Emit>
+template <typename T, int M, bool X0, bool GRAM, int XH, int EP, int WR = 8, typename Extra, typename Emit>
 __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __restrict__ px,
                                             const T* __restrict__ py, const cplx<T>* __restrict__ c0,
                                             const cplx<T>* __restrict__ b, const cplx<T>* __restrict__ x0,
@@ -287,9 +287,9 @@ __device__ __forceinline__ void sstep_march(const AdrGeom& A, int S, const T* __
     re = rb + R - 1 < ny - 1 ? rb + R - 1 : ny - 1;
     ex.init(j, colok, nx, ny);
     if (sg & 1)
-        sstep_march_dir<T, M, X0, GRAM, XH, EP, -1>(A, S, px, py, c0, b, x0, j, colok, rb, re, xr, ex, emit);
+        sstep_march_dir<T, M, X0, GRAM, XH, EP, -1, WR>(A, S, px, py, c0, b, x0, j, colok, rb, re, xr, ex, emit);
     else
-        sstep_march_dir<T, M, X0, GRAM, XH, EP, 1>(A, S, px, py, c0, b, x0, j, colok, rb, re, xr, ex, emit);
+        sstep_march_dir<T, M, X0, GRAM, XH, EP, 1, WR>(A, S, px, py, c0, b, x0, j, colok, rb, re, xr, ex, emit);
 }
 
 // acc += the Gram entries of one node's K_0..K_M (layout of k_sstep_gram), in FP64.
@@ -592,7 +592,10 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
     static_assert(EPI == EPI_X || X0, "the modulated epilogues follow the post-smoother");
     constexpr int XH = EPI == EPI_MODRD ? 1 : 0;
     constexpr int EP = EPI == EPI_X ? -1 : EPI == EPI_MOD ? 0 : 1;
-    using Mc = March<M, X0, false, XH, EP>;
+    // FP64 with the modulated epilogue: a ring of six rows (one row of prefetch), so that
+    // the registers allow two wavefronts per SIMD
+    constexpr int WR = (sizeof(T) == 8 && EPI == EPI_MODRD) ? 6 : 8;
+    using Mc = March<M, X0, false, XH, EP, WR>;
     constexpr int W = Mc::W;
     const int lane = threadIdx.x;
     const int nx = A.nx, ny = A.ny;
@@ -652,7 +655,7 @@ __global__ __launch_bounds__(64) void k_sstep_combine(AdrGeom A, int S, const T*
         cplx<T> un[W];  // updated iterate of the emitted rows
         const Geom& G = mod.G;
         const T ih2 = T(G.inv_h2);
-        sstep_march<T, M, X0, false, 1, EP>(
+        sstep_march<T, M, X0, false, 1, EP, WR>(
             A, S, px, py, c0, b, x0, j, rb, re, xr, ex, [&](int r, auto slot, const cplx<T>(&k)[M], auto dirc) {
                 constexpr int sr = decltype(slot)::value;
                 constexpr int s1 = (sr + W - 1) % W, s2 = (sr + W - 2) % W;
