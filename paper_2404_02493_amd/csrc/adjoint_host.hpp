@@ -297,19 +297,18 @@ struct AdjEngine {
         }
     }
 
-    void rec_adrv(int s, int l) {
+    // pa_base, pa_out (level l - 1, may be null): the last call's result also goes to
+    // pa_out = pa_base + P x (the finer level's post-smoother start).
+    void rec_adrv(int s, int l, const void* pa_base = nullptr, void* pa_out = nullptr) {
         AdrTape& Tp = tp().adr[s][l];
-        AdrLevel& A = c->al[l];
         if (l == c->LA) {
-            rec_gmres(l, Tp.b, nullptr, gm_of(c, l), Tp.kpre, Tp.rpre, Tp.xo);
+            rec_gmres(l, Tp.b, nullptr, gm_of(c, l), Tp.kpre, Tp.rpre, Tp.xo, nullptr, pa_base, pa_out);
             return;
         }
         const int m = gm_of(c, l);
         rec_gmres(l, Tp.b, nullptr, m, Tp.kpre, Tp.rpre, Tp.x1, tp().adr[s][l + 1].b);
-        rec_adrv(s, l + 1);
-        LAUNCH_NB(c, 2.25 * sizeof(C) * NN2(A.nx, A.ny), (k_prolong_copy<T>), dim3(tiles_of(A.nx, A.ny)),
-                  tile_block(), st, A.nx, A.ny, (const C*)tp().adr[s][l + 1].xo, (const C*)Tp.x1, (C*)Tp.x2);
-        rec_gmres(l, Tp.b, Tp.x2, m, Tp.kpost, Tp.rpost, Tp.xo);
+        rec_adrv(s, l + 1, Tp.x1, Tp.x2);
+        rec_gmres(l, Tp.b, Tp.x2, m, Tp.kpost, Tp.rpost, Tp.xo, nullptr, pa_base, pa_out);
     }
 
     // The basis and Gram partials of a recorded GMRES(MM) call in one tile pass; returns
@@ -343,8 +342,10 @@ struct AdjEngine {
 
     // rc (x0 = 0 only): also the restriction of the call's residual to the next level, from
     // the Krylov identity in the same pass as the combination.
+    // rc: also rc = R (b - M x) (pre-smoother); pa_base, pa_out: also pa_out = pa_base + P x
+    // on the finer level l - 1.
     void rec_gmres(int l, const void* b, const void* x0, int m, void* const* kv, GRec* R, void* xout,
-                   void* rc = nullptr) {
+                   void* rc = nullptr, const void* pa_base = nullptr, void* pa_out = nullptr) {
         AdrLevel& A = c->al[l];
         const size_t n = N(l);
         const int nb = fb(n);
@@ -369,6 +370,12 @@ struct AdjEngine {
                 LAUNCH_NB(c, (m + 2.0) * sizeof(C) * n + sizeof(C) * n / 4.0, (k_gr_combine_rr<T>),
                           dim3(gr_rr_blocks(A.nx, A.ny)), dim3(BLOCK), st, A.nx, A.ny, K, m, (const GRec*)R, tau(l),
                           (C*)xout, (C*)rc);
+                return;
+            }
+            if (pa_out) {
+                LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n + 2.0 * sizeof(C) * 4.0 * n,
+                          (k_gr_combine_pa<T>), dim3(gr_rr_blocks(2 * A.nx, 2 * A.ny)), dim3(BLOCK), st, A.nx, A.ny,
+                          K, m, (const GRec*)R, (const C*)x0, (C*)xout, (const C*)pa_base, (C*)pa_out);
                 return;
             }
             LAUNCH_NB(c, (m + 1.0 + (x0 ? 1.0 : 0.0)) * sizeof(C) * n, (k_gr_combine<T>), dim3(nb), dim3(BLOCK), st, n,
@@ -396,6 +403,11 @@ struct AdjEngine {
             LAUNCH(c, (3 * sizeof(C) + 2 * sizeof(T)) * NN2(A.nx, A.ny), (k_adr_resid_restrict<T>),
                    dim3(rr_blocks(A.nx, A.ny)), dim3(BLOCK), st, A.A, (const T*)A.px, (const T*)A.py,
                    (const C*)A.c0, (const C*)b, (const C*)xout, (C*)rc);
+        if (pa_out) {
+            AdrLevel& F = c->al[l - 1];
+            LAUNCH_NB(c, 2.25 * sizeof(C) * NN2(F.nx, F.ny), (k_prolong_copy<T>), dim3(tiles_of(F.nx, F.ny)),
+                      tile_block(), st, F.nx, F.ny, (const C*)xout, (const C*)pa_base, (C*)pa_out);
+        }
     }
 
     // ------------------------------------------------------------ reverse

@@ -946,6 +946,70 @@ __global__ __launch_bounds__(BLOCK) void k_gr_combine(size_t N, VecSet<T> Kv, in
     }
 }
 
+// Coarse tiles of the fused combination passes below (small, so that the small ADR levels
+// still give hundreds of blocks).
+constexpr int GRC = 8;
+__host__ __device__ inline int gr_rr_blocks(int nx, int ny) {
+    return ((nx / 2 + GRC - 1) / GRC) * ((ny / 2 + GRC - 1) / GRC);
+}
+
+// The combination of a recorded call, x = x0 + sum_{j=1..m} c_j k_j on the level of nx x ny
+// nodes (as k_gr_combine, x0 may be null), fused with its bilinear prolongation into the
+// finer level: out = base + P x out of place on the 2 nx x 2 ny fine nodes (the ring copies
+// base, as k_prolong_copy).  A block owns a coarse tile of GRC x GRC nodes: it forms x there
+// and on one more row and column in LDS (0 off the unknowns, the prolongation's rule),
+// writes x at its own nodes, then the fine nodes 2 I0 .. 2 I0 + 2 GRC - 1 in both directions.
+// gr_rr_blocks(2 nx, 2 ny) blocks.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gr_combine_pa(int nx, int ny, VecSet<T> Kv, int m,
+                                                         const GRec* __restrict__ R, const cplx<T>* x0,
+                                                         cplx<T>* __restrict__ x, const cplx<T>* __restrict__ base,
+                                                         cplx<T>* __restrict__ out) {
+    constexpr int XW = GRC + 1;
+    __shared__ cplx<T> xs[XW * XW];
+    __shared__ T cf[2 * GMAX];
+    if (threadIdx.x < 2 * GMAX) cf[threadIdx.x] = T(R->c[threadIdx.x]);
+    __syncthreads();
+    const int ntx = (nx + GRC - 1) / GRC;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int I0 = (b / ntx) * GRC, J0 = (b % ntx) * GRC;
+    for (int q = threadIdx.x; q < XW * XW; q += BLOCK) {
+        const int I = I0 + q / XW, J = J0 + q % XW;
+        cplx<T> v{};
+        if (I < ny && J < nx) {
+            const size_t p = (size_t)I * nx + J;
+            v = x0 ? x0[p] : cplx<T>{};
+            for (int jv = 0; jv < m; ++jv) v = v + mk<T>(cf[2 * jv], cf[2 * jv + 1]) * Kv.v[jv][p];
+            if (q / XW < GRC && q % XW < GRC) x[p] = v;
+        }
+        xs[q] = (I <= 0 || J <= 0 || I >= ny || J >= nx) ? cplx<T>{} : v;
+    }
+    __syncthreads();
+    const int fnx = 2 * nx, fny = 2 * ny;
+    for (int q = threadIdx.x; q < 4 * GRC * GRC; q += BLOCK) {
+        const int i = 2 * I0 + q / (2 * GRC), j = 2 * J0 + q % (2 * GRC);
+        if (i >= fny || j >= fnx) continue;
+        const size_t p = (size_t)i * fnx + j;
+        cplx<T> v = base[p];
+        if (i > 0 && j > 0) {
+            const int a = (i >> 1) - I0, c = (j >> 1) - J0;
+            auto e = [&](int da, int dc) { return xs[(a + da) * XW + c + dc]; };
+            cplx<T> w;
+            if (!(i & 1) && !(j & 1)) {
+                w = e(0, 0);
+            } else if ((i & 1) && !(j & 1)) {
+                w = T(0.5) * (e(0, 0) + e(1, 0));
+            } else if (!(i & 1) && (j & 1)) {
+                w = T(0.5) * (e(0, 0) + e(0, 1));
+            } else {
+                w = T(0.25) * (((e(0, 0) + e(1, 0)) + e(0, 1)) + e(1, 1));
+            }
+            v = v + w;
+        }
+        out[p] = v;
+    }
+}
+
 // The combination of a recorded pre-smoother call (x0 = 0) fused with the restriction of
 // its residual: x = sum_{j=1..m} c_j k_j on every fine node and rc = R (b - M x) on the
 // coarse grid, where b - M x = k_1 - tau sum_j c_j k_{j+1} (M k_j = tau k_{j+1}), so no
@@ -953,10 +1017,6 @@ __global__ __launch_bounds__(BLOCK) void k_gr_combine(size_t N, VecSet<T> Kv, in
 // the small ADR levels still give hundreds of blocks) and the fine nodes
 // 2I0 .. 2I0 + 2 GRC - 1 in both directions (it writes x there, 0 on the ring);
 // gr_rr_blocks(nx, ny) blocks.
-constexpr int GRC = 8;
-__host__ __device__ inline int gr_rr_blocks(int nx, int ny) {
-    return ((nx / 2 + GRC - 1) / GRC) * ((ny / 2 + GRC - 1) / GRC);
-}
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gr_combine_rr(int nx, int ny, VecSet<T> Kv, int m,
                                                          const GRec* __restrict__ R, double tau,
