@@ -48,6 +48,7 @@ struct AdjState {
     double* thb = nullptr;                   // carrier phase cotangent (level 2)
     double* phib2 = nullptr;                 // phase cotangent on the level-2 lattice
     double* wacc = nullptr;                  // weight cotangents (FP64, device)
+    double* wpart = nullptr;                 // WSLOTS x MAXRED partials of weight cotangents
     void* ckpt = nullptr;                    // library-owned checkpoints
     size_t ckpt_bytes = 0;
     // the tapes of helm_cycle_record, reversible by helm_cycle_reverse while valid
@@ -140,6 +141,7 @@ static void adj_alloc(helm_ctx c, hipStream_t st) {
         for (int q = 0; q < 9; ++q) S.cs[l][q] = dalloc(c, cb);
     }
     S.wacc = (double*)dalloc(c, 64 * sizeof(double));
+    S.wpart = (double*)dalloc(c, (size_t)WSLOTS * MAXRED * sizeof(double));
     if (adr_on) {
         S.axb.assign(c->LA + 1, nullptr);
         S.axb2.assign(c->LA + 1, nullptr);
@@ -219,9 +221,21 @@ struct AdjEngine {
     void copy(void* dst, const void* src, size_t bytes) {
         HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
     }
-    void fin_add(int nblk, int slot) {
-        LAUNCH_NB(c, 8.0 * nblk, (k_finalize_add<1>), dim3(1), dim3(FBLOCK), st, (const double*)c->partials, nblk, 1, 1.0,
-               S.wacc + slot);
+    // Weight-cotangent partials: the passes that form them write to the next slot of S.wpart
+    // (wslot()); fin_add(nblk, level) queues that slot, and wflush() sums the queued slots
+    // into wacc in one launch (when WSLOTS are queued, and at the end of every reversed cycle).
+    WSlots wq{};
+    double* wslot() { return S.wpart + (size_t)wq.n * MAXRED; }
+    void fin_add(int nblk, int level) {
+        wq.nblk[wq.n] = nblk;
+        wq.level[wq.n] = level;
+        if (++wq.n == WSLOTS) wflush();
+    }
+    void wflush() {
+        if (wq.n == 0) return;
+        LAUNCH_NB(c, 8.0 * MAXRED * wq.n, k_wsum, dim3(1), dim3(FBLOCK), st, (const double*)S.wpart, MAXRED, wq,
+                  S.wacc);
+        wq = WSlots{};
     }
 
     // ------------------------------------------------------------ record (forward with tape)
@@ -418,14 +432,15 @@ struct AdjEngine {
         const size_t NF = N(1);
         const int nb = fb(NF);
         LAUNCH_NB(c, (5.0 * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G, (const T*)W.n2,
-               (const C*)g, (const C*)tp().uB, (const C*)S.fb[0], (C*)S.fb[1], T(c->w[0]), c->partials);
+               (const C*)g, (const C*)tp().uB, (const C*)S.fb[0], (C*)S.fb[1], T(c->w[0]), wslot());
         fin_add(nb, 0);
         restrict_adj(1, S.fb[1], S.lub[2]);
         rev_level(2);
         prolong_adj(1, S.lgb[2], S.fb[1], nullptr);
         LAUNCH_NB(c, ((u0 ? 5.0 : 4.0) * sizeof(C) + sizeof(T)) * NF, (k_jacobi_adj<T>), dim3(nb), dim3(BLOCK), st, G,
-               (const T*)W.n2, (const C*)g, (const C*)u0, (const C*)S.fb[1], (C*)S.fb[0], T(c->w[0]), c->partials);
+               (const T*)W.n2, (const C*)g, (const C*)u0, (const C*)S.fb[1], (C*)S.fb[0], T(c->w[0]), wslot());
         fin_add(nb, 0);
+        wflush();
     }
 
     // out (level l+1) = 4 R x (level l): the cotangent of a coarse correction.
@@ -495,7 +510,7 @@ struct AdjEngine {
         }
         E.template residual<P>(G, W.n2, g, u, res);
         LAUNCH_NB(c, (2.0 * sizeof(Cp) + sizeof(P)) * n, (k_dot_ah<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,
-               (const Cp*)stt, (const Cp*)res, c->partials);
+               (const Cp*)stt, (const Cp*)res, wslot());
         fin_add(nb, l - 1);
         E.template applyA<P>(G, W.n2, s, t1, 0);
         LAUNCH_NB(c, (5.0 * sizeof(Cp) + sizeof(P)) * n, (k_adj_ahsub<P>), dim3(nb), dim3(BLOCK), st, G, (const P*)W.n2,

@@ -74,13 +74,27 @@ __device__ __forceinline__ void dots_add(double (&acc)[2 * GMAX], const VecSet<T
     }
 }
 
-// out[v] += sum over blocks (one block of FBLOCK threads), v < kcount; scale s.
-template <int K>
-__global__ __launch_bounds__(FBLOCK) void k_finalize_add(const double* __restrict__ partials, int nblk, int kcount,
-                                                         double s, double* out) {
-    __shared__ double sums[K];
-    final_sum<K>(partials, nblk, kcount, sums);
-    if ((int)threadIdx.x < kcount) out[threadIdx.x] += s * sums[threadIdx.x];
+// Weight cotangents of up to WSLOTS reverse passes, summed in one launch: slot q holds the
+// nblk[q] per-block partials of one pass at wpart + q * stride (the pass's reduce_store);
+// wavefront q sums slot q (group_row_sum, the order of the finalize kernels), then
+// wacc[level[q]] += that sum for q = 0, 1, ... (the order the passes ran in).
+constexpr int WSLOTS = FBLOCK / 64;
+struct WSlots {
+    int n;
+    int nblk[WSLOTS];
+    int level[WSLOTS];
+};
+__global__ __launch_bounds__(FBLOCK) void k_wsum(const double* __restrict__ wpart, int stride, WSlots t,
+                                                 double* __restrict__ wacc) {
+    __shared__ double sums[WSLOTS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (wv < t.n) {
+        const double sv = group_row_sum(wpart + (size_t)wv * stride, t.nblk[wv], lane);
+        if (lane == 0) sums[wv] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < t.n; ++q) wacc[t.level[q]] += 1.0 * sums[q];
 }
 
 // ------------------------------------------------------------------ wave levels

@@ -69,43 +69,48 @@ __device__ __forceinline__ void store_partials(const double* sums, int kcount, d
     if (tid < kcount) partials[(size_t)tid * nblk + blockIdx.x] = sums[tid];
 }
 
+// Sum of row[0 .. nblk) in a fixed order, returned to every lane of the calling wavefront:
+// lane l of group g (g = 0..15) adds blocks 64 g + l, 64 g + l + FBLOCK, ...; each group is
+// summed over its lanes (wave_sum) and the group sums are added for g = 0, 1, ...  Only the
+// groups that hold blocks are reduced; the sums are bit-identical to those of a block
+// reduction over FBLOCK threads (one group per wavefront) in the same order.
+__device__ __forceinline__ double group_row_sum(const double* __restrict__ row, int nblk, int lane) {
+    constexpr int NW = FBLOCK / 64;
+    const int ng = (nblk + 63) / 64 < NW ? (nblk + 63) / 64 : NW;  // groups holding blocks
+    double t[NW];
+#pragma unroll
+    for (int g = 0; g < NW; ++g) {  // the first FBLOCK blocks: every load issued (from
+        const int bb = g * 64 + lane;  // block 0 past the end), none under a branch
+        const double v = row[bb < nblk ? bb : 0];
+        t[g] = bb < nblk ? 0.0 + v : 0.0;
+    }
+    for (int b0 = FBLOCK; b0 < nblk; b0 += FBLOCK) {
+#pragma unroll
+        for (int g = 0; g < NW; ++g) {
+            const int bb = b0 + g * 64 + lane;
+            if (bb < nblk) t[g] += row[bb];
+        }
+    }
+    double sv = 0.0;
+#pragma unroll
+    for (int g = 0; g < NW; ++g)
+        if (g < ng) sv += wave_sum(t[g]);
+    if (ng < NW) sv += 0.0;  // the empty groups' zero sums (only the sign of a zero can change)
+    return sv;
+}
+
 // In a one-block finalize kernel of FBLOCK threads: sums[v] = sum over blocks of
-// partials[v * nblk + b], v < kcount, fixed order; result in LDS sums[] for all threads.
-// The order: lane l of group g (g = 0..15) adds blocks 64 g + l, 64 g + l + FBLOCK, ...;
-// each group is summed over its lanes (wave_sum), and the group sums are added for
-// g = 0, 1, ...  One wavefront per entry (wavefront w takes v = w, w + 16, ...) forms
-// all groups of its entries, so only the groups that hold blocks are reduced.  The sums
-// are bit-identical to those of a block reduction over FBLOCK threads (one group per
-// wavefront) in the same order.
+// partials[v * nblk + b], v < kcount, in the order of group_row_sum; result in LDS sums[]
+// for all threads.  One wavefront per entry (wavefront w takes v = w, w + 16, ...).
 template <int K>
 __device__ __forceinline__ void final_sum(const double* __restrict__ partials, int nblk, int kcount, double* sums) {
     constexpr int NW = FBLOCK / 64, R = (K + NW - 1) / NW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int ng = (nblk + 63) / 64 < NW ? (nblk + 63) / 64 : NW;  // groups holding blocks
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int e = wv + r * NW;
         if (e >= kcount) continue;  // uniform over the wavefront
-        const double* __restrict__ row = partials + (size_t)e * nblk;
-        double t[NW];
-#pragma unroll
-        for (int g = 0; g < NW; ++g) {  // the first FBLOCK blocks: every load issued (from
-            const int bb = g * 64 + lane;  // block 0 past the end), none under a branch
-            const double v = row[bb < nblk ? bb : 0];
-            t[g] = bb < nblk ? 0.0 + v : 0.0;
-        }
-        for (int b0 = FBLOCK; b0 < nblk; b0 += FBLOCK) {
-#pragma unroll
-            for (int g = 0; g < NW; ++g) {
-                const int bb = b0 + g * 64 + lane;
-                if (bb < nblk) t[g] += row[bb];
-            }
-        }
-        double sv = 0.0;
-#pragma unroll
-        for (int g = 0; g < NW; ++g)
-            if (g < ng) sv += wave_sum(t[g]);
-        if (ng < NW) sv += 0.0;  // the empty groups' zero sums (only the sign of a zero can change)
+        const double sv = group_row_sum(partials + (size_t)e * nblk, nblk, lane);
         if (lane == 0) sums[e] = sv;
     }
     __syncthreads();
